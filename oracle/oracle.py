@@ -1,0 +1,201 @@
+"""ctypes marshalling for the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fcd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = C.POINTER(C.c_double)
+
+
+class OracleParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("pad0", C.c_int32), ("pad1", C.c_int32),
+        ("rho", C.c_double * 3), ("tau", C.c_double * 3), ("chi", C.c_double * 3),
+        ("sigma12", C.c_double), ("sigma13", C.c_double), ("sigma23", C.c_double),
+        ("eta", C.c_double), ("xi", C.c_double), ("mobility", C.c_double),
+        ("H0", C.c_double), ("alpha", C.c_double), ("mu0", C.c_double),
+        ("drive_G", C.c_double), ("grav_x", C.c_double), ("grav_y", C.c_double),
+        ("eps_n", C.c_double),
+    ]
+
+
+class OracleSolver(C.Structure):
+    _fields_ = [
+        ("mode", C.c_int32), ("max_sweeps", C.c_int32), ("check_every", C.c_int32),
+        ("pad", C.c_int32), ("omega", C.c_double), ("tol", C.c_double),
+    ]
+
+    @classmethod
+    def direct(cls) -> "OracleSolver":
+        return cls(0, 0, 1, 0, 1.0, 0.0)
+
+    @classmethod
+    def sor(cls, omega: float, tol: float, max_sweeps: int = 100000, check_every: int = 1):
+        return cls(1, max_sweeps, check_every, 0, omega, tol)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no architecture-specific flags)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        P = C.POINTER(OracleParams)
+        S = C.POINTER(OracleSolver)
+        L.orc_gamma.argtypes = [_dp, _dp]
+        L.orc_feq.argtypes = [C.c_double, _dp, _dp]
+        L.orc_forcing.argtypes = [_dp, C.c_double, _dp]
+        L.orc_collide_f.argtypes = [_dp, C.c_double, _dp, _dp, C.c_double, C.c_double, _dp]
+        L.orc_mrt_matrices.argtypes = [_dp, _dp]
+        L.orc_lattice.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp]
+        L.orc_free_energy.argtypes = [P, _dp]
+        L.orc_free_energy.restype = C.c_double
+        L.orc_free_energy_grad.argtypes = [P, _dp, _dp]
+        L.orc_chem_potential.argtypes = [P, _dp, _dp, _dp]
+        L.orc_solve_potential_phi.argtypes = [P, _dp, _dp, S, _dp, _dp, _dp,
+                                              C.POINTER(C.c_int32), _dp]
+        L.orc_potential_residual_phi.argtypes = [P, _dp, _dp, _dp, _dp]
+        L.orc_potential_residual_phi.restype = C.c_double
+        L.orc_apply_L.argtypes = [P, _dp, _dp, _dp]
+        L.orc_init_fields.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_init_droplet.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       _dp, _dp, _dp, _dp, _dp]
+        L.orc_step.argtypes = [P, S, C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(C.c_int32), _dp]
+        L.orc_moments.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.orc_forces.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.orc_deformation_w.argtypes = [C.c_int32, C.c_int32, _dp]
+        L.orc_deformation_w.restype = C.c_double
+        L.orc_diagnostics.argtypes = [P, _dp, _dp, _dp]
+        L.orc_stencils.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
+        L.orc_mu_r.argtypes = [P, _dp, _dp, _dp]
+        for name in ("orc_init_fields", "orc_init_droplet", "orc_step", "orc_moments",
+                     "orc_forces", "orc_diagnostics", "orc_solve_potential_phi"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "float64 C-contiguous arrays only"
+    return a.ctypes.data_as(_dp)
+
+
+def params_from_workload(w) -> OracleParams:
+    p = OracleParams()
+    p.nx, p.ny = w.nx, w.ny
+    for k in range(3):
+        p.rho[k], p.tau[k], p.chi[k] = w.rho[k], w.tau[k], w.chi[k]
+    p.sigma12, p.sigma13, p.sigma23, p.eta = w.sigma12, w.sigma13, w.sigma23, w.eta
+    p.xi, p.mobility = w.xi, w.mobility
+    p.H0, p.alpha, p.mu0 = w.H0, w.alpha, w.mu0
+    p.drive_G, p.grav_x, p.grav_y = w.drive_G, w.grav[0], w.grav[1]
+    p.eps_n = w.eps_n
+    return p
+
+
+class OracleSim:
+    """State (f, g1, g2 as [9][ny][nx]; psi' as [ny][nx]) plus calls into the oracle."""
+
+    MOMENT_NAMES = ("pstar", "ux", "uy", "phi1", "phi2", "phi3", "rho", "psi", "Hx", "Hy")
+    FORCE_NAMES = ("Fs_x", "Fs_y", "Fm_x", "Fm_y", "Fmu_x", "Fmu_y", "Ft_x", "Ft_y")
+
+    def __init__(self, workload, solver: OracleSolver | None = None):
+        self.w = workload
+        self.p = params_from_workload(workload)
+        self.solver = solver if solver is not None else OracleSolver.direct()
+        ny, nx = workload.ny, workload.nx
+        self.f = np.zeros((9, ny, nx))
+        self.g1 = np.zeros((9, ny, nx))
+        self.g2 = np.zeros((9, ny, nx))
+        self.psi = np.zeros((ny, nx))
+        self.sweeps = 0
+        self.resid = 0.0
+
+    # --- initial state ---------------------------------------------------------
+    def init_droplet(self, solve: bool = True):
+        w = self.w
+        phi1 = np.zeros((w.ny, w.nx))
+        phi2 = np.zeros((w.ny, w.nx))
+        rc = lib().orc_init_droplet(C.byref(self.p), w.xc, w.yc, w.r_core, w.r_shell,
+                                    ptr(self.f), ptr(self.g1), ptr(self.g2), ptr(phi1), ptr(phi2))
+        assert rc == 0, rc
+        if solve:
+            self.solve_potential()
+        return phi1, phi2
+
+    def init_fields(self, phi1, phi2, ux, uy, pstar=None, solve: bool = True):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (phi1, phi2, ux, uy)]
+        ps = None if pstar is None else np.ascontiguousarray(pstar, dtype=np.float64)
+        rc = lib().orc_init_fields(C.byref(self.p), *[ptr(a) for a in arrs], ptr(ps),
+                                   ptr(self.f), ptr(self.g1), ptr(self.g2))
+        assert rc == 0, rc
+        if solve:
+            self.solve_potential()
+
+    # --- potential ---------------------------------------------------------------
+    def phases(self):
+        return self.g1.sum(axis=0), self.g2.sum(axis=0)
+
+    def solve_potential(self, solver: OracleSolver | None = None):
+        phi1, phi2 = self.phases()
+        phi1 = np.ascontiguousarray(phi1)
+        phi2 = np.ascontiguousarray(phi2)
+        sw = C.c_int32(0)
+        res = C.c_double(0.0)
+        s = solver if solver is not None else self.solver
+        rc = lib().orc_solve_potential_phi(C.byref(self.p), ptr(phi1), ptr(phi2), C.byref(s),
+                                           ptr(self.psi), None, None, C.byref(sw), C.byref(res))
+        self.sweeps, self.resid = sw.value, res.value
+        return rc
+
+    # --- stepping --------------------------------------------------------------
+    def step(self, n: int) -> int:
+        sw = C.c_int32(0)
+        res = C.c_double(0.0)
+        rc = lib().orc_step(C.byref(self.p), C.byref(self.solver), int(n), ptr(self.f),
+                            ptr(self.g1), ptr(self.g2), ptr(self.psi), C.byref(sw), C.byref(res))
+        self.sweeps, self.resid = sw.value, res.value
+        return rc
+
+    # --- outputs -----------------------------------------------------------------
+    def moments(self) -> dict:
+        out = np.zeros((10, self.w.ny, self.w.nx))
+        rc = lib().orc_moments(C.byref(self.p), ptr(self.f), ptr(self.g1), ptr(self.g2),
+                               ptr(self.psi), ptr(out))
+        assert rc == 0, rc
+        return {k: out[i] for i, k in enumerate(self.MOMENT_NAMES)}
+
+    def forces(self) -> dict:
+        out = np.zeros((8, self.w.ny, self.w.nx))
+        rc = lib().orc_forces(C.byref(self.p), ptr(self.f), ptr(self.g1), ptr(self.g2),
+                              ptr(self.psi), ptr(out))
+        assert rc == 0, rc
+        return {k: out[i] for i, k in enumerate(self.FORCE_NAMES)}
+
+    def diagnostics(self):
+        out = np.zeros(4)
+        rc = lib().orc_diagnostics(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
+        assert rc == 0, rc
+        return out
