@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled ferrofluid compound-droplet step on one MI355X.
+
+Workload: the 2048 x 512 channel (shell r = 80, core r = 40, Ca = 0.1, densities 2:1:1,
+viscosities 5:1:1, ferrofluid core mu_r = 3, field at 90 degrees, Bo_m = 2), FP64.
+A step is one full coupled update: phase moments, potential solve to
+max |L(psi0 + psi')| <= 1e-10 H0 (warm-started four-colour SOR), fused collide-and-stream.
+Inputs are resident in HBM before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "MLUPS + HBM GB/s of coupled step; batched instances/hr; adjoint/forward ratio"
+
+# Algorithmic device traffic per lattice site and launch, in values of the working
+# precision: collide-stream reads 27 distributions + phi1, phi2, psi' and writes 27;
+# one SOR sweep reads mu_r and psi' and writes psi'; the residual reads mu_r and psi';
+# the phase kernel reads 18 distributions and writes phi1, phi2, mu_r.
+VALUES_PER_SITE = {"collide_stream": 57, "sor_sweep": 3, "residual": 2, "phase": 21}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(steps: int) -> dict:
+    """The oracle (single thread, as built) on the same 2048 x 512 channel at Bo_m = 0,
+    where no potential solve is needed; `steps` coupled steps after its own set-up."""
+    from fcd_inputs import single_channel_large
+    from oracle import OracleSim
+    w = single_channel_large(bond=0.0)
+    s = OracleSim(w)
+    s.init_droplet(solve=False)
+    t0 = time.perf_counter()
+    rc = s.step(steps)
+    dt = time.perf_counter() - t0
+    assert rc == 0
+    return {"value": round(w.sites * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} coupled steps of the 2048x512 channel at Bo_m=0 (no potential solve), "
+                      f"FP64, one thread, {dt:.1f} s"}
+
+
+def copy_bandwidth_gbs(torch) -> float:
+    n = 1 << 28  # 2 GiB of float64 each way
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del a, b
+    return 2 * n * 8 / dt / 1e9
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
+    ap.add_argument("--bond", type=float, default=2.0)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not built.", file=sys.stderr)
+        return 2
+
+    import torch
+    from fcd_inputs import single_channel_large
+    from paper_2410_11129_amd import fcd
+    from paper_2410_11129_amd.sim import Channel
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = fcd.FCD_FP64 if args.precision == "fp64" else fcd.FCD_FP32
+    esz = 8 if prec == fcd.FCD_FP64 else 4
+    tol = args.tol if prec == fcd.FCD_FP64 else max(args.tol, 1e-5)
+    w = single_channel_large(bond=args.bond)
+    log(f"bench: {w.name} {w.nx}x{w.ny} {args.precision} Bo_m={args.bond} H0={w.H0:.5g} tol={tol:g}")
+    ch = Channel(w, precision=prec, sor_omega=0.0, sor_tol=tol, sor_check_every=8, sor_max_sweeps=1 << 30)
+    ch.init_droplet()
+    t0 = time.perf_counter()
+    st, sw0, res0 = ch.solve_potential(tol, 1 << 30)
+    log(f"bench: initial potential solve {sw0} sweeps, residual {res0:.3e}, {time.perf_counter() - t0:.2f} s")
+    ch.step(args.warmup)
+    torch.cuda.synchronize()
+    sweeps_before = ch.stats()[1]
+    fcd.fcd_timing(ch.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timing = fcd.fcd_timing_read(ch.h)
+    fcd.fcd_timing(ch.h, False)
+    sweeps = ch.stats()[1] - sweeps_before
+    d = ch.deformation()
+    log(f"bench: {args.steps} steps in {dt:.3f} s, {sweeps / max(args.steps, 1):.1f} sweeps/step, "
+        f"D_o={d[0]:.5f} D_i={d[1]:.5f}; timing {timing}")
+
+    sites = w.sites
+    mlups = sites * args.steps / dt / 1e6
+    per_kind = {}
+    for k, (ms, n) in timing.items():
+        if n == 0:
+            continue
+        bytes_per_launch = VALUES_PER_SITE[k] * esz * sites
+        avg_s = ms / n / 1e3
+        per_kind[k] = {"launches": n, "avg_us": round(avg_s * 1e6, 3), "ms_per_step": round(ms / args.steps, 4),
+                       "GBps": round(bytes_per_launch / avg_s / 1e9, 1)}
+    dom = max(per_kind, key=lambda k: timing[k][0])
+    step_bytes = sum(VALUES_PER_SITE[k] * esz * sites * timing[k][1] for k in per_kind) / args.steps
+    roof = {"bound": "hbm", "kernel": dom, "achieved": per_kind[dom]["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(per_kind[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": VALUES_PER_SITE[dom] * esz * sites}
+    out = {
+        "metric": METRIC, "value": round(mlups, 3), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == fcd.FCD_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}_{args.precision}_bo{args.bond:g}", "nx": w.nx, "ny": w.ny,
+                   "bond": args.bond, "potential_tol": tol, "sweeps_per_step": round(sweeps / args.steps, 2)},
+        "roofline": roof,
+        "step_GBps_algorithmic": round(step_bytes / (dt / args.steps) / 1e9, 1),
+        "kernels": per_kind,
+    }
+    try:
+        out["copy_GBps_torch"] = round(copy_bandwidth_gbs(torch), 1)
+    except Exception as e:  # noqa: BLE001
+        log(f"bench: copy bandwidth probe failed: {e}")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,197 @@
+"""Thin ctypes binding of the C ABI in include/fcd.h (argument marshalling only).
+
+Every function here forwards to the function of the same name in libfcd.so; all work
+runs in the library's HIP kernels.  Loading fails loudly when libfcd.so is missing:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfcd.so")
+
+FCD_OK, FCD_ERR_ARG, FCD_ERR_HIP, FCD_ERR_OOM = 0, -1, -2, -3
+FCD_ERR_DIVERGED, FCD_ERR_NOT_CONVERGED, FCD_ERR_UNSUPPORTED = -4, -5, -6
+FCD_FP64, FCD_FP32 = 0, 1
+
+FCD_M_PSTAR, FCD_M_UX, FCD_M_UY = 1 << 0, 1 << 1, 1 << 2
+FCD_M_PHI1, FCD_M_PHI2, FCD_M_PHI3 = 1 << 3, 1 << 4, 1 << 5
+FCD_M_RHO, FCD_M_PSI, FCD_M_HX, FCD_M_HY = 1 << 6, 1 << 7, 1 << 8, 1 << 9
+FCD_M_ALL = (1 << 10) - 1
+MOMENT_NAMES = ("pstar", "ux", "uy", "phi1", "phi2", "phi3", "rho", "psi", "Hx", "Hy")
+
+# Every symbol include/fcd.h declares.
+EXPORTS = (
+    "fcd_scratch_bytes", "fcd_create", "fcd_set_params", "fcd_init_compound_droplet",
+    "fcd_init_fields", "fcd_solve_potential", "fcd_step", "fcd_read_moments", "fcd_read_state",
+    "fcd_write_state", "fcd_read_psi", "fcd_write_psi", "fcd_deformation", "fcd_stats", "fcd_timing",
+    "fcd_timing_read", "fcd_sync", "fcd_destroy", "fcd_last_error",
+)
+TIMING_KINDS = ("collide_stream", "sor_sweep", "residual", "phase")
+
+
+class fcd_lattice(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32), ("pitch", C.c_int32)]
+
+
+class fcd_params(C.Structure):
+    _fields_ = [
+        ("rho", C.c_double * 3), ("tau", C.c_double * 3), ("chi", C.c_double * 3),
+        ("sigma12", C.c_double), ("sigma13", C.c_double), ("sigma23", C.c_double),
+        ("eta", C.c_double), ("xi", C.c_double), ("mobility", C.c_double),
+        ("H0", C.c_double), ("alpha", C.c_double), ("mu0", C.c_double),
+        ("drive_G", C.c_double), ("grav_x", C.c_double), ("grav_y", C.c_double),
+        ("eps_n", C.c_double), ("sor_omega", C.c_double), ("sor_tol", C.c_double),
+        ("sor_check_every", C.c_int32), ("sor_max_sweeps", C.c_int32),
+    ]
+
+
+class fcd_buffers(C.Structure):
+    _fields_ = [("dist", C.c_void_p * 2), ("phi", C.c_void_p), ("psi", C.c_void_p),
+                ("scratch", C.c_void_p)]
+
+
+class FcdError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where} failed with status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libfcd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2410_11129_amd/build.py "
+                              "(there is no fallback implementation)")
+        L = C.CDLL(LIB_PATH)
+        H = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        L.fcd_scratch_bytes.argtypes = [C.POINTER(fcd_lattice)]
+        L.fcd_scratch_bytes.restype = C.c_size_t
+        L.fcd_create.argtypes = [C.POINTER(fcd_lattice), C.POINTER(fcd_params), C.POINTER(fcd_buffers),
+                                 C.c_void_p, C.POINTER(C.c_void_p)]
+        L.fcd_set_params.argtypes = [H, C.POINTER(fcd_params)]
+        L.fcd_init_compound_droplet.argtypes = [H, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.fcd_init_fields.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.fcd_solve_potential.argtypes = [H, C.c_double, C.c_int32, C.POINTER(C.c_int32), dp]
+        L.fcd_step.argtypes = [H, C.c_int32]
+        L.fcd_read_moments.argtypes = [H, C.c_uint32, C.c_void_p]
+        L.fcd_read_state.argtypes = [H, C.c_void_p]
+        L.fcd_write_state.argtypes = [H, C.c_void_p]
+        L.fcd_read_psi.argtypes = [H, C.c_void_p]
+        L.fcd_write_psi.argtypes = [H, C.c_void_p]
+        L.fcd_deformation.argtypes = [H, dp]
+        L.fcd_stats.argtypes = [H, dp]
+        L.fcd_timing.argtypes = [H, C.c_int32]
+        L.fcd_timing_read.argtypes = [H, dp]
+        L.fcd_sync.argtypes = [H]
+        L.fcd_destroy.argtypes = [H]
+        L.fcd_last_error.argtypes = []
+        L.fcd_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("fcd_scratch_bytes", "fcd_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def fcd_last_error() -> str:
+    return lib().fcd_last_error().decode()
+
+
+def _check(st: int, where: str, allow=()) -> int:
+    if st != FCD_OK and st not in allow:
+        raise FcdError(st, where, fcd_last_error())
+    return st
+
+
+def fcd_scratch_bytes(lat: fcd_lattice) -> int:
+    return lib().fcd_scratch_bytes(C.byref(lat))
+
+
+def fcd_create(lat: fcd_lattice, prm: fcd_params, buf: fcd_buffers, stream: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().fcd_create(C.byref(lat), C.byref(prm), C.byref(buf), C.c_void_p(stream), C.byref(h)),
+           "fcd_create")
+    return h
+
+
+def fcd_set_params(h, prm: fcd_params):
+    _check(lib().fcd_set_params(h, C.byref(prm)), "fcd_set_params")
+
+
+def fcd_init_compound_droplet(h, xc: float, yc: float, r_core: float, r_shell: float):
+    _check(lib().fcd_init_compound_droplet(h, xc, yc, r_core, r_shell), "fcd_init_compound_droplet")
+
+
+def fcd_init_fields(h, phi1: int, phi2: int, ux: int, uy: int, pstar: int | None):
+    _check(lib().fcd_init_fields(h, phi1, phi2, ux, uy, pstar), "fcd_init_fields")
+
+
+def fcd_solve_potential(h, tol: float, max_sweeps: int, allow_not_converged: bool = False):
+    sw = C.c_int32(0)
+    res = C.c_double(0.0)
+    st = lib().fcd_solve_potential(h, tol, max_sweeps, C.byref(sw), C.byref(res))
+    _check(st, "fcd_solve_potential", (FCD_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+    return st, sw.value, res.value
+
+
+def fcd_step(h, nsteps: int):
+    _check(lib().fcd_step(h, int(nsteps)), "fcd_step")
+
+
+def fcd_read_moments(h, mask: int, out: int):
+    _check(lib().fcd_read_moments(h, mask, out), "fcd_read_moments")
+
+
+def fcd_read_state(h, out: int):
+    _check(lib().fcd_read_state(h, out), "fcd_read_state")
+
+
+def fcd_write_state(h, src: int):
+    _check(lib().fcd_write_state(h, src), "fcd_write_state")
+
+
+def fcd_read_psi(h, out: int):
+    _check(lib().fcd_read_psi(h, out), "fcd_read_psi")
+
+
+def fcd_write_psi(h, src: int):
+    _check(lib().fcd_write_psi(h, src), "fcd_write_psi")
+
+
+def fcd_deformation(h):
+    out = (C.c_double * 4)()
+    _check(lib().fcd_deformation(h, out), "fcd_deformation")
+    return list(out)
+
+
+def fcd_stats(h):
+    out = (C.c_double * 3)()
+    _check(lib().fcd_stats(h, out), "fcd_stats")
+    return list(out)
+
+
+def fcd_timing(h, enable: bool):
+    _check(lib().fcd_timing(h, 1 if enable else 0), "fcd_timing")
+
+
+def fcd_timing_read(h) -> dict:
+    """{kind: (total_ms, launches)} for the kernel classes in TIMING_KINDS."""
+    out = (C.c_double * 8)()
+    _check(lib().fcd_timing_read(h, out), "fcd_timing_read")
+    return {k: (out[2 * i], int(out[2 * i + 1])) for i, k in enumerate(TIMING_KINDS)}
+
+
+def fcd_sync(h):
+    _check(lib().fcd_sync(h), "fcd_sync")
+
+
+def fcd_destroy(h):
+    _check(lib().fcd_destroy(h), "fcd_destroy")

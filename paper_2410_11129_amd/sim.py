@@ -1,0 +1,125 @@
+"""Torch-allocated buffers around one library handle (memory and streams only)."""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import fcd
+
+
+def make_params(w, sor_omega: float = 0.0, sor_tol: float = 1e-10, sor_check_every: int = 8,
+                sor_max_sweeps: int = 200000) -> fcd.fcd_params:
+    """fcd_params from a workload description (any object with the workload fields)."""
+    p = fcd.fcd_params()
+    for k in range(3):
+        p.rho[k], p.tau[k], p.chi[k] = w.rho[k], w.tau[k], w.chi[k]
+    p.sigma12, p.sigma13, p.sigma23, p.eta = w.sigma12, w.sigma13, w.sigma23, w.eta
+    p.xi, p.mobility, p.H0, p.alpha, p.mu0 = w.xi, w.mobility, w.H0, w.alpha, w.mu0
+    p.drive_G, p.grav_x, p.grav_y, p.eps_n = w.drive_G, w.grav[0], w.grav[1], w.eps_n
+    p.sor_omega, p.sor_tol = sor_omega, sor_tol
+    p.sor_check_every, p.sor_max_sweeps = sor_check_every, sor_max_sweeps
+    return p
+
+
+def padded_pitch(nx: int, elem_bytes: int) -> int:
+    """Row pitch rounded up to a multiple of 256 bytes."""
+    per = 256 // elem_bytes
+    return ((nx + per - 1) // per) * per
+
+
+class Channel:
+    """One channel on one GPU: device planes owned here (torch), handle owned by the library."""
+
+    def __init__(self, w, precision: int = fcd.FCD_FP64, device: str = "cuda:0", pitch: int | None = None,
+                 stream: torch.cuda.Stream | None = None, **solver):
+        self.w = w
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == fcd.FCD_FP64 else torch.float32
+        esz = 8 if precision == fcd.FCD_FP64 else 4
+        self.pitch = pitch if pitch is not None else padded_pitch(w.nx, esz)
+        self.lat = fcd.fcd_lattice(w.nx, w.ny, precision, self.pitch)
+        self.prm = make_params(w, **solver)
+        ny, P = w.ny, self.pitch
+        self.dist = [torch.zeros((27, ny, P), dtype=self.dtype, device=self.device) for _ in range(2)]
+        self.phi = torch.zeros((3, ny, P), dtype=self.dtype, device=self.device)
+        self.psi = torch.zeros((ny, P), dtype=self.dtype, device=self.device)
+        nscr = (fcd.fcd_scratch_bytes(self.lat) + 7) // 8
+        self.scratch = torch.zeros(nscr, dtype=torch.float64, device=self.device)
+        self.buf = fcd.fcd_buffers()
+        self.buf.dist[0] = self.dist[0].data_ptr()
+        self.buf.dist[1] = self.dist[1].data_ptr()
+        self.buf.phi = self.phi.data_ptr()
+        self.buf.psi = self.psi.data_ptr()
+        self.buf.scratch = self.scratch.data_ptr()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = fcd.fcd_create(self.lat, self.prm, self.buf, self.stream.cuda_stream)
+
+    def close(self):
+        if self.h is not None:
+            fcd.fcd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- set-up ----------------------------------------------------------------
+    def init_droplet(self):
+        w = self.w
+        fcd.fcd_init_compound_droplet(self.h, w.xc, w.yc, w.r_core, w.r_shell)
+
+    def init_fields(self, phi1, phi2, ux, uy, pstar=None):
+        t = [torch.as_tensor(a, dtype=torch.float64).to(self.device).contiguous()
+             for a in (phi1, phi2, ux, uy)]
+        ps = None if pstar is None else torch.as_tensor(pstar, dtype=torch.float64).to(self.device).contiguous()
+        fcd.fcd_init_fields(self.h, *[a.data_ptr() for a in t], None if ps is None else ps.data_ptr())
+        self.stream.synchronize()
+
+    def set_params(self, **solver):
+        self.prm = make_params(self.w, **solver)
+        fcd.fcd_set_params(self.h, self.prm)
+
+    # --- work ------------------------------------------------------------------
+    def solve_potential(self, tol: float, max_sweeps: int = 200000):
+        return fcd.fcd_solve_potential(self.h, tol, max_sweeps)
+
+    def step(self, n: int):
+        fcd.fcd_step(self.h, n)
+
+    # --- outputs ---------------------------------------------------------------
+    def moments(self, mask: int = fcd.FCD_M_ALL) -> dict:
+        names = [n for k, n in enumerate(fcd.MOMENT_NAMES) if mask & (1 << k)]
+        out = torch.empty((len(names), self.w.ny, self.w.nx), dtype=torch.float64, device=self.device)
+        fcd.fcd_read_moments(self.h, mask, out.data_ptr())
+        self.stream.synchronize()
+        host = out.cpu().numpy()
+        return {n: host[i] for i, n in enumerate(names)}
+
+    def state(self):
+        out = torch.empty((27, self.w.ny, self.w.nx), dtype=torch.float64, device=self.device)
+        fcd.fcd_read_state(self.h, out.data_ptr())
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def write_state(self, arr):
+        t = torch.as_tensor(arr, dtype=torch.float64).to(self.device).contiguous()
+        fcd.fcd_write_state(self.h, t.data_ptr())
+        self.stream.synchronize()
+
+    def psi_dense(self):
+        out = torch.empty((self.w.ny, self.w.nx), dtype=torch.float64, device=self.device)
+        fcd.fcd_read_psi(self.h, out.data_ptr())
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def deformation(self):
+        return fcd.fcd_deformation(self.h)
+
+    def stats(self):
+        return fcd.fcd_stats(self.h)
+
+    def sync(self):
+        fcd.fcd_sync(self.h)

@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every function include/fcd.h declares; host-side
+argument checks reject bad input without touching a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2410_11129_amd import fcd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fcd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcd_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(fcd.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = fcd.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes structs equal those a C compiler gives the
+    header's structs."""
+    structs = {"fcd_lattice": fcd.fcd_lattice, "fcd_params": fcd.fcd_params, "fcd_buffers": fcd.fcd_buffers}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fcd.h"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append(f'printf("{sname} size %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{sname} {fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for sname, cls in structs.items():
+        assert got[(sname, "size")] == C.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert got[(sname, fname)] == getattr(cls, fname).offset, (sname, fname)
+
+
+def test_scratch_bytes_is_host_only():
+    lat = fcd.fcd_lattice(200, 50, fcd.FCD_FP64, 256)
+    assert fcd.fcd_scratch_bytes(lat) >= 50 * 8 * 8
+
+
+def good_params():
+    from fcd_inputs import single_channel_small
+    from paper_2410_11129_amd.sim import make_params
+    return make_params(single_channel_small())
+
+
+@pytest.mark.parametrize("nx,ny,prec,pitch", [(201, 50, 0, 256), (2, 50, 0, 256), (200, 1, 0, 256),
+                                              (200, 50, 0, 100), (200, 50, 7, 256)])
+def test_bad_lattice_rejected_before_any_device_work(nx, ny, prec, pitch):
+    lat = fcd.fcd_lattice(nx, ny, prec, pitch)
+    buf = fcd.fcd_buffers()
+    buf.dist[0], buf.dist[1], buf.phi, buf.psi, buf.scratch = 256, 512, 768, 1024, 1280
+    h = C.c_void_p()
+    st = fcd.lib().fcd_create(C.byref(lat), C.byref(good_params()), C.byref(buf), None, C.byref(h))
+    assert st == fcd.FCD_ERR_ARG
+    assert fcd.fcd_last_error()
+
+
+def test_bad_params_and_null_buffers_rejected():
+    lat = fcd.fcd_lattice(200, 50, fcd.FCD_FP64, 256)
+    buf = fcd.fcd_buffers()
+    h = C.c_void_p()
+    st = fcd.lib().fcd_create(C.byref(lat), C.byref(good_params()), C.byref(buf), None, C.byref(h))
+    assert st == fcd.FCD_ERR_ARG and "null" in fcd.fcd_last_error()
+    p = good_params()
+    p.sigma12, p.sigma13, p.sigma23 = 0.01, 0.02, 0.01  # gamma_2 = 0
+    buf.dist[0], buf.dist[1], buf.phi, buf.psi, buf.scratch = 256, 512, 768, 1024, 1280
+    st = fcd.lib().fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h))
+    assert st == fcd.FCD_ERR_ARG and "gamma" in fcd.fcd_last_error()
+    assert fcd.lib().fcd_step(None, 1) == fcd.FCD_ERR_ARG
