@@ -4,7 +4,8 @@
 Workload: the 2048 x 512 channel (shell r = 80, core r = 40, Ca = 0.1, densities 2:1:1,
 viscosities 5:1:1, ferrofluid core mu_r = 3, field at 90 degrees, Bo_m = 2), FP64.
 A step is one full coupled update: phase moments, potential solve to
-max |L(psi0 + psi')| <= 1e-10 H0 (warm-started four-colour SOR), fused collide-and-stream.
+max |L(psi0 + psi')| <= 1e-10 H0 (multigrid V-cycles warm-started from the extrapolated
+previous solutions, or four-colour SOR), fused collide-and-stream.
 Inputs are resident in HBM before timing starts.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -21,11 +22,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS + HBM GB/s of coupled step; batched instances/hr; adjoint/forward ratio"
 
-# Algorithmic device traffic per lattice site and launch, in values of the working
-# precision: collide-stream reads 27 distributions + phi1, phi2, psi' and writes 27;
-# one SOR sweep reads mu_r and psi' and writes psi'; the residual reads mu_r and psi';
-# the phase kernel reads 18 distributions and writes phi1, phi2, mu_r.
-VALUES_PER_SITE = {"collide_stream": 57, "sor_sweep": 3, "residual": 2, "phase": 21}
+
+
+def values_per_site(solver: str, smooth: int) -> dict:
+    """Algorithmic device traffic per lattice site and timed unit, in values of the working
+    precision.  collide_stream reads 27 distributions + phi1, phi2, psi' and writes 27.
+    One potential iteration is an SOR sweep (read mu_r, psi'; write psi') or a multigrid
+    V(nu, nu)-cycle: on each level 2 nu sweeps of 3 values, a residual restriction
+    (mu_r, psi' read) and a prolongation (psi' read and written), the coarser levels adding
+    1/4 + 1/16 + ... = 1/3.  The residual test reads mu_r and psi'.  phase reads 18
+    distributions and writes phi1, phi2, mu_r."""
+    it = 3.0 if solver == "sor" else (6.0 * smooth + 4.0) * 4.0 / 3.0
+    return {"collide_stream": 57.0, "potential_iter": it, "residual": 2.0, "phase": 21.0}
 
 
 def log(msg: str) -> None:
@@ -47,6 +55,50 @@ def cpu_baseline(steps: int) -> dict:
     return {"value": round(w.sites * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} coupled steps of the 2048x512 channel at Bo_m=0 (no potential solve), "
                       f"FP64, one thread, {dt:.1f} s"}
+
+
+def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
+    """The 64-channel regime sweep (ny ~ U{64..256}, nx = 4 ny) as one FP32 batch, against
+    the same channels run one after another as single FP64 channels on this GPU.  Both
+    rates are extrapolated to the sweep's 10k steps per channel from timed windows."""
+    from fcd_inputs import regime_sweep_batch
+    from paper_2410_11129_amd import fcd
+    from paper_2410_11129_amd.sim import Batch, Channel
+    ws = regime_sweep_batch()
+    nsteps_target = ws[0].steps
+    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
+    bt.init_droplets()
+    bt.step(20)
+    torch.cuda.synchronize()
+    it0 = bt.stats()[1]
+    t0 = time.perf_counter()
+    bt.step(steps)
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / steps
+    sweeps = (bt.stats()[1] - it0) / steps
+    sites = sum(w.sites for w in ws)
+    bt.close()
+    del bt
+    seq = 0.0
+    for w in ws:
+        ch = Channel(w, tol=1e-10)
+        ch.init_droplet()
+        ch.step(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(seq_steps)
+        torch.cuda.synchronize()
+        seq += (time.perf_counter() - t0) / seq_steps
+        ch.close()
+    batch_iph = len(ws) / (nsteps_target * dt_batch) * 3600.0
+    seq_iph = len(ws) / (nsteps_target * seq) * 3600.0
+    return {"channels": len(ws), "sites": sites, "steps_per_channel": nsteps_target,
+            "batch_fp32_ms_per_step": round(dt_batch * 1e3, 4), "batch_MLUPS": round(sites / dt_batch / 1e6, 1),
+            "batch_sor_sweeps_per_step": round(sweeps, 2),
+            "instances_per_hour_batch_fp32": round(batch_iph, 1),
+            "instances_per_hour_sequential_fp64": round(seq_iph, 1),
+            "speedup": round(batch_iph / seq_iph, 2),
+            "sample": f"batch: {steps} timed steps; sequential: {seq_steps} timed steps per channel"}
 
 
 def copy_bandwidth_gbs(torch) -> float:
@@ -73,8 +125,16 @@ def main() -> int:
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--bond", type=float, default=2.0)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--solver", choices=("mg", "sor"), default="mg")
+    ap.add_argument("--smooth", type=int, default=1)
+    ap.add_argument("--coarse-sweeps", type=int, default=8)
+    ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--no-extrapolate", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--sequential-steps", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -92,11 +152,14 @@ def main() -> int:
     tol = args.tol if prec == fcd.FCD_FP64 else max(args.tol, 1e-5)
     w = single_channel_large(bond=args.bond)
     log(f"bench: {w.name} {w.nx}x{w.ny} {args.precision} Bo_m={args.bond} H0={w.H0:.5g} tol={tol:g}")
-    ch = Channel(w, precision=prec, sor_omega=0.0, sor_tol=tol, sor_check_every=8, sor_max_sweeps=1 << 30)
+    solver = fcd.FCD_SOLVER_MG if args.solver == "mg" else fcd.FCD_SOLVER_SOR
+    ch = Channel(w, precision=prec, solver=solver, tol=tol, check_every=args.check_every if args.solver == "mg" else 8,
+                 max_iters=1 << 30, smooth=args.smooth, coarse_sweeps=args.coarse_sweeps,
+                 extrapolate=0 if args.no_extrapolate else 1)
     ch.init_droplet()
     t0 = time.perf_counter()
     st, sw0, res0 = ch.solve_potential(tol, 1 << 30)
-    log(f"bench: initial potential solve {sw0} sweeps, residual {res0:.3e}, {time.perf_counter() - t0:.2f} s")
+    log(f"bench: initial potential solve {sw0} iterations, residual {res0:.3e}, {time.perf_counter() - t0:.2f} s")
     ch.step(args.warmup)
     torch.cuda.synchronize()
     sweeps_before = ch.stats()[1]
@@ -110,10 +173,11 @@ def main() -> int:
     fcd.fcd_timing(ch.h, False)
     sweeps = ch.stats()[1] - sweeps_before
     d = ch.deformation()
-    log(f"bench: {args.steps} steps in {dt:.3f} s, {sweeps / max(args.steps, 1):.1f} sweeps/step, "
+    log(f"bench: {args.steps} steps in {dt:.3f} s, {sweeps / max(args.steps, 1):.2f} potential iterations/step, "
         f"D_o={d[0]:.5f} D_i={d[1]:.5f}; timing {timing}")
 
     sites = w.sites
+    VALUES_PER_SITE = values_per_site(args.solver, args.smooth)
     mlups = sites * args.steps / dt / 1e6
     per_kind = {}
     for k, (ms, n) in timing.items():
@@ -134,7 +198,8 @@ def main() -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == fcd.FCD_FP64 else "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}_{args.precision}_bo{args.bond:g}", "nx": w.nx, "ny": w.ny,
-                   "bond": args.bond, "potential_tol": tol, "sweeps_per_step": round(sweeps / args.steps, 2)},
+                   "bond": args.bond, "potential_solver": args.solver, "potential_tol": tol,
+                   "potential_iters_per_step": round(sweeps / args.steps, 2)},
         "roofline": roof,
         "step_GBps_algorithmic": round(step_bytes / (dt / args.steps) / 1e9, 1),
         "kernels": per_kind,
@@ -143,6 +208,10 @@ def main() -> int:
         out["copy_GBps_torch"] = round(copy_bandwidth_gbs(torch), 1)
     except Exception as e:  # noqa: BLE001
         log(f"bench: copy bandwidth probe failed: {e}")
+    del ch
+    if not args.no_batched:
+        out["batched"] = batched_sweep(torch, args.batched_steps, args.sequential_steps)
+        log(f"bench: batched {out['batched']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

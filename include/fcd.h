@@ -47,6 +47,7 @@ typedef enum {
 } fcd_status;
 
 enum { FCD_FP64 = 0, FCD_FP32 = 1 };
+enum { FCD_SOLVER_SOR = 0, FCD_SOLVER_MG = 1 };
 
 typedef struct {
     int32_t nx;        /* nodes along the channel; even and >= 4 (four-colour ordering) */
@@ -71,11 +72,17 @@ typedef struct {
     double drive_G;  /* uniform body-force density along x driving the channel flow */
     double grav_x, grav_y; /* gravity: F_b = rho g */
     double eps_n;    /* n = grad phi / sqrt(|grad phi|^2 + eps_n^2) */
-    double sor_omega; /* over-relaxation factor of the potential solve in (0, 2); 0 selects
-                         2 / (1 + sin(pi / (ny + 1))), optimal for the constant-mu channel */
-    double sor_tol;   /* potential solve stops when max |L(psi0 + psi')| <= sor_tol * H0 */
-    int32_t sor_check_every; /* sweeps between residual tests */
-    int32_t sor_max_sweeps;  /* sweeps allowed per solve before FCD_ERR_NOT_CONVERGED */
+    double pot_tol;  /* potential solve stops when max |L(psi0 + psi')| <= pot_tol * H0, or
+                        at the working precision's rounding floor 16 eps max |C psi'| (C: sum
+                        of the operator's coefficients at a node) if that is larger */
+    double pot_omega; /* SOR over-relaxation in (0, 2); 0 selects 2 / (1 + sin(pi / (ny + 1))),
+                         optimal for the constant-mu channel.  Unused by multigrid. */
+    int32_t pot_solver;      /* FCD_SOLVER_SOR or FCD_SOLVER_MG */
+    int32_t pot_check_every; /* SOR sweeps / multigrid V-cycles between residual tests */
+    int32_t pot_max_iters;   /* SOR sweeps / V-cycles allowed per solve */
+    int32_t pot_smooth;      /* multigrid: Gauss-Seidel sweeps before and after each coarse correction */
+    int32_t pot_coarse_sweeps; /* multigrid: SOR sweeps on the coarsest level */
+    int32_t pot_extrapolate; /* 1: start each step's solve from 2 psi'(t-1) - psi'(t-2) */
 } fcd_params;
 
 /* Caller-owned device buffers (element type = lattice precision). */
@@ -103,7 +110,9 @@ enum {
     FCD_M_ALL = (1u << 10) - 1
 };
 
-/* Bytes of device scratch the handle needs for this lattice (reductions). */
+/* Bytes of device scratch the handle needs for this lattice: reductions, the multigrid
+ * hierarchy (coarse mu, correction and right-hand side per level) and one plane of psi'
+ * history for the extrapolated warm start. */
 size_t fcd_scratch_bytes(const fcd_lattice* lat);
 
 /* Validate the lattice and buffers and build a handle bound to `hip_stream`
@@ -126,15 +135,16 @@ fcd_status fcd_init_compound_droplet(fcd_handle* h, double xc, double yc, double
 fcd_status fcd_init_fields(fcd_handle* h, const double* phi1, const double* phi2,
                            const double* ux, const double* uy, const double* pstar);
 
-/* Solve the potential for the current state (Eq. 6) by four-colour SOR, warm-started
- * from the stored psi', until max |L(psi0 + psi')| <= tol * H0 or max_sweeps.  Sync.
- * sweeps_out / resid_out (nullable) receive the sweep count and the final residual.
- * Returns FCD_ERR_NOT_CONVERGED if the tolerance was not met. */
-fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_sweeps,
-                               int32_t* sweeps_out, double* resid_out);
+/* Solve the potential for the current state (Eq. 6), warm-started from the stored psi',
+ * with the configured solver (four-colour SOR or multigrid V-cycles), until
+ * max |L(psi0 + psi')| <= tol * H0 or max_iters sweeps / cycles.  Sync.  iters_out /
+ * resid_out (nullable) receive the iteration count and the final residual.  Returns
+ * FCD_ERR_NOT_CONVERGED if the tolerance was not met. */
+fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_iters,
+                               int32_t* iters_out, double* resid_out);
 
-/* Advance nsteps coupled time steps: phases and mu_r, potential solve (sor_tol,
- * sor_max_sweeps), then the fused collide-and-stream of f, g1, g2 with all forces.
+/* Advance nsteps coupled time steps: phases and mu_r, potential solve (pot_tol,
+ * pot_max_iters), then the fused collide-and-stream of f, g1, g2 with all forces.
  * The potential solve synchronises the stream at each residual test. */
 fcd_status fcd_step(fcd_handle* h, int32_t nsteps);
 
@@ -157,15 +167,17 @@ fcd_status fcd_write_psi(fcd_handle* h, const double* in);
  * masses of phases 1 and 2.  out = {D_o, D_i, mass1, mass2}.  Sync. */
 fcd_status fcd_deformation(fcd_handle* h, double out[4]);
 
-/* Counters since creation: out = {steps, potential sweeps, last residual}.  Host only. */
+/* Counters since creation: out = {steps, potential iterations (SOR sweeps or V-cycles),
+ * last residual}.  Host only. */
 fcd_status fcd_stats(fcd_handle* h, double out[3]);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around every
  * launch of the step's kernels.  fcd_timing(h, 1) clears the totals and starts
  * recording; fcd_timing(h, 0) stops.  fcd_timing_read (sync) fills out[2*k] with the
  * total milliseconds and out[2*k+1] with the launch count of kernel class k:
- * 0 fused collide-stream, 1 one four-colour SOR sweep (four launches), 2 potential
- * residual, 3 phase moments.  out must hold 8 doubles. */
+ * 0 fused collide-stream, 1 one potential iteration (a four-colour SOR sweep, or a
+ * multigrid V-cycle including its coarse-mu restriction share), 2 potential residual,
+ * 3 phase moments.  out must hold 8 doubles. */
 fcd_status fcd_timing(fcd_handle* h, int32_t enable);
 fcd_status fcd_timing_read(fcd_handle* h, double out[8]);
 
@@ -177,6 +189,75 @@ fcd_status fcd_destroy(fcd_handle* h);
 
 /* Message of the calling thread's last error ("" if none). */
 const char* fcd_last_error(void);
+
+/* ---------------------------------------------------------------------------------
+ * Adjoint (reverse-mode gradient) of J = dJ_dD[0] D_o + dJ_dD[1] D_i after nsteps steps,
+ * where D_o, D_i are the deformations of fcd_deformation, with respect to
+ * p = (H0, alpha, drive_G, sigma12, sigma13, sigma23).  Hand-written reverse of the
+ * whole coupled step: transposed streaming, node collisions and forces, stencils, the
+ * potential solve (adjoint equation L lambda = psi'-bar, L symmetric, solved by the
+ * configured solver to pot_tol relative to max |psi'-bar|) and the mixing rules.
+ * Checkpointing: the forward keeps the state every ckpt_every steps in `work`; the
+ * backward recomputes each segment (keeping its states) and runs the adjoint steps in
+ * reverse.  When the forward starts from fcd_init_compound_droplet with no step since,
+ * the drive_G gradient includes the initial Poiseuille velocity's dependence on it.
+ * --------------------------------------------------------------------------------- */
+
+/* Device bytes of `work` for fcd_adjoint_forward / _backward.  Host only. */
+size_t fcd_adjoint_bytes(const fcd_lattice* lat, int32_t nsteps, int32_t ckpt_every);
+
+/* Run nsteps forward steps from the current state, keeping checkpoints in `work`
+ * (caller-owned device buffer of fcd_adjoint_bytes, 256-byte aligned); D_out = {D_o, D_i}
+ * of the final state.  Sync.  The potential warm start is not extrapolated here. */
+fcd_status fcd_adjoint_forward(fcd_handle* h, int32_t nsteps, int32_t ckpt_every, void* work, double D_out[2]);
+
+/* Gradient of J for the run of the last fcd_adjoint_forward (same `work`, untouched
+ * since): grad = dJ/d(H0, alpha, drive_G, sigma12, sigma13, sigma23).  Sync.  Leaves the
+ * handle on the forward's final state. */
+fcd_status fcd_adjoint_backward(fcd_handle* h, const double dJ_dD[2], double grad[6]);
+
+/* ---------------------------------------------------------------------------------
+ * Batches: n independent channels of uneven size (e.g. a regime-map sweep over Bo_m and
+ * Ca) stepped together.  Every kernel of a step is launched once for the whole batch;
+ * per-channel lattices and parameters are honoured.  The potential is solved by
+ * four-colour SOR per channel (pot_solver is ignored), each channel to its own
+ * pot_tol * H0, with channels that have converged left untouched; a batch step ends
+ * when every channel has converged.  All lattices must share one precision.
+ * Caller-owned buffers, sizes from fcd_batch_sizes: `state` (both state buffers of every
+ * channel), `aux` (phi1, phi2, mu_r, psi' and psi' history planes), `scratch`
+ * (descriptors, tile tables, reductions); each at least 256-byte aligned.
+ * --------------------------------------------------------------------------------- */
+typedef struct fcd_batch fcd_batch;
+
+/* bytes_out[0..2] = state, aux and scratch bytes for these n lattices.  Host only. */
+fcd_status fcd_batch_sizes(int32_t n, const fcd_lattice* lats, size_t bytes_out[3]);
+
+/* Carve the caller's buffers, upload the per-channel descriptors and tile tables
+ * (synchronously), and bind the batch to `hip_stream`. */
+fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params* prms, void* state,
+                            void* aux, void* scratch, void* hip_stream, fcd_batch** out);
+
+/* Initial compound droplet of every channel; geom is a host array of n rows
+ * {xc, yc, r_core, r_shell} (the same initial state as fcd_init_compound_droplet). */
+fcd_status fcd_batch_init_compound_droplet(fcd_batch* b, const double* geom);
+
+/* Advance every channel by nsteps coupled steps.  Synchronises at residual tests. */
+fcd_status fcd_batch_step(fcd_batch* b, int32_t nsteps);
+
+/* Deformation and masses of every channel: out is a host array of n rows
+ * {D_o, D_i, mass1, mass2} (as fcd_deformation).  Sync. */
+fcd_status fcd_batch_deformation(fcd_batch* b, double* out);
+
+/* State (dense [27][ny][nx] FP64) and moments (as fcd_read_moments) of channel k into
+ * device buffers.  Async. */
+fcd_status fcd_batch_read_state(fcd_batch* b, int32_t k, double* out);
+fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double* out);
+
+/* out = {steps, SOR sweeps launched, largest final residual of the last solve}. */
+fcd_status fcd_batch_stats(fcd_batch* b, double out[3]);
+
+/* Free the batch (not the caller's buffers).  Waits for the stream. */
+fcd_status fcd_batch_destroy(fcd_batch* b);
 
 #ifdef __cplusplus
 }

@@ -4,11 +4,14 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "fcd.h"
+#include "fcd_adjoint_kernels.hpp"
+#include "fcd_batch.hpp"
 #include "fcd_kernels.hpp"
 
 namespace {
@@ -26,18 +29,60 @@ fcd_status hip_check(hipError_t e, const char* what) {
 }
 
 // Scratch layout (bytes from the start of the caller's scratch buffer).
-constexpr size_t OFF_RES = 0;      // uint64: bit pattern of max |residual|
+constexpr size_t OFF_RES = 0;      // 2 x uint64: bit patterns of max |residual| and max |C psi'|
 constexpr size_t OFF_CENT = 256;   // 8 doubles: centroids and masses
 constexpr size_t OFF_RESULT = 512; // 4 doubles: D_o, D_i, mass1, mass2
 constexpr size_t OFF_ROWS = 1024;  // ny * 8 doubles: per-row partial sums
 
 size_t elem_size(int precision) { return precision == FCD_FP64 ? sizeof(double) : sizeof(float); }
 
-// Over-relaxation factor: the caller's, or the optimum 2 / (1 + sin(pi h)) of SOR for
-// the Laplacian between Dirichlet rows ny + 1 cells apart.
-double sor_omega_of(const fcd_params& p, int ny) {
-    if (p.sor_omega > 0.0) return p.sor_omega;
-    return 2.0 / (1.0 + std::sin(3.14159265358979323846 / (ny + 1)));
+// Optimum SOR factor 2 / (1 + sin(pi / (ny + 1))) for the Laplacian between Dirichlet
+// rows ny + 1 cells apart.
+double sor_omega_opt(int ny) { return 2.0 / (1.0 + std::sin(3.14159265358979323846 / (ny + 1))); }
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Multigrid hierarchy and scratch layout.  Level 0 is the lattice itself (psi', mu_r
+// planes of the caller); coarser levels halve both dimensions while nx is a multiple
+// of 4, ny is even and >= 4, and the level has more than COARSE_NODES nodes.
+constexpr int MAX_LEVELS = 16;
+constexpr long long COARSE_NODES = 1024;
+constexpr size_t COARSE_LDS_MAX = 65536;
+
+struct MgPlan {
+    int levels;
+    int nx[MAX_LEVELS], ny[MAX_LEVELS], pitch[MAX_LEVELS];
+    size_t off_mu[MAX_LEVELS], off_u[MAX_LEVELS], off_f[MAX_LEVELS];
+    size_t off_prev;  // psi' history plane
+    size_t bytes;     // total scratch
+};
+
+MgPlan make_plan(const fcd_lattice& l) {
+    const size_t esz = elem_size(l.precision);
+    MgPlan p{};
+    p.levels = 1;
+    p.nx[0] = l.nx;
+    p.ny[0] = l.ny;
+    p.pitch[0] = l.pitch;
+    size_t off = align256(OFF_ROWS + (size_t)l.ny * 8 * sizeof(double));
+    p.off_prev = off;
+    off += align256((size_t)l.ny * l.pitch * esz);
+    while (p.levels < MAX_LEVELS) {
+        const int px = p.nx[p.levels - 1], py = p.ny[p.levels - 1];
+        if (px % 4 || py % 2 || py < 4 || (long long)px * py <= COARSE_NODES) break;
+        const int L = p.levels++;
+        p.nx[L] = px / 2;
+        p.ny[L] = py / 2;
+        const int per = (int)(256 / esz);
+        p.pitch[L] = (p.nx[L] + per - 1) / per * per;
+        const size_t plane = align256((size_t)p.ny[L] * p.pitch[L] * esz);
+        p.off_mu[L] = off;
+        p.off_u[L] = off + plane;
+        p.off_f[L] = off + 2 * plane;
+        off += 3 * plane;
+    }
+    p.bytes = off;
+    return p;
 }
 
 }  // namespace
@@ -100,7 +145,7 @@ struct Timer {
     }
 };
 
-enum { TK_COLLIDE = 0, TK_SWEEP = 1, TK_RESID = 2, TK_PHASE = 3 };
+enum { TK_COLLIDE = 0, TK_ITER = 1, TK_RESID = 2, TK_PHASE = 3 };
 
 struct fcd_handle {
     fcd_lattice lat;
@@ -112,6 +157,13 @@ struct fcd_handle {
     long long steps;
     long long sweeps;
     double last_resid;
+    int hist;  // completed step solves since the last state change (psi' history validity)
+    int last_iters;  // iterations the previous solve needed (first residual test is deferred)
+    int init_fresh;  // the state is the compound-droplet initial state (no step since)
+    // checkpointed adjoint: set by fcd_adjoint_forward, used by fcd_adjoint_backward
+    char* adj_work;
+    int adj_nsteps, adj_every, adj_from_init;
+    MgPlan plan;
     Timer timer;
 };
 
@@ -129,10 +181,14 @@ fcd_status check_params(const fcd_params* p) {
     if (g0 == 0.0 || g1 == 0.0 || g2 == 0.0) return fail(FCD_ERR_ARG, "a spreading coefficient gamma_i is zero");
     if (1.0 / g0 + 1.0 / g1 + 1.0 / g2 == 0.0) return fail(FCD_ERR_ARG, "gamma_T undefined");
     if (!(p->xi > 0.0) || !(p->mobility > 0.0)) return fail(FCD_ERR_ARG, "xi and mobility must be positive");
-    if (!(p->sor_omega == 0.0 || (p->sor_omega > 0.0 && p->sor_omega < 2.0)))
-        return fail(FCD_ERR_ARG, "sor_omega must be 0 (automatic) or lie in (0, 2)");
-    if (!(p->sor_tol > 0.0)) return fail(FCD_ERR_ARG, "sor_tol must be positive");
-    if (p->sor_check_every < 1 || p->sor_max_sweeps < 0) return fail(FCD_ERR_ARG, "bad SOR sweep counts");
+    if (!(p->pot_omega == 0.0 || (p->pot_omega > 0.0 && p->pot_omega < 2.0)))
+        return fail(FCD_ERR_ARG, "pot_omega must be 0 (automatic) or lie in (0, 2)");
+    if (!(p->pot_tol > 0.0)) return fail(FCD_ERR_ARG, "pot_tol must be positive");
+    if (p->pot_solver != FCD_SOLVER_SOR && p->pot_solver != FCD_SOLVER_MG)
+        return fail(FCD_ERR_ARG, "unknown pot_solver");
+    if (p->pot_check_every < 1 || p->pot_max_iters < 0) return fail(FCD_ERR_ARG, "bad potential iteration counts");
+    if (p->pot_solver == FCD_SOLVER_MG && (p->pot_smooth < 1 || p->pot_coarse_sweeps < 1))
+        return fail(FCD_ERR_ARG, "multigrid needs pot_smooth >= 1 and pot_coarse_sweeps >= 1");
     return FCD_OK;
 }
 
@@ -201,72 +257,188 @@ unsigned long long* res_word(const fcd_handle* h) {
 }
 
 template <typename T>
-fcd_status read_residual(fcd_handle* h, const fcd::StepConst<T>& P, T* psi, const T* mur, double* r) {
+fcd::PotLevel<T> pot_level(const fcd_handle* h, int l) {
+    fcd::PotLevel<T> L{};
+    char* s = static_cast<char*>(h->buf.scratch);
+    L.nx = h->plan.nx[l];
+    L.ny = h->plan.ny[l];
+    L.pitch = h->plan.pitch[l];
+    if (l == 0) {
+        L.u = static_cast<T*>(h->buf.psi);
+        L.mu = plane_ptr<T>(h->buf.phi, h, 2);
+        L.f = nullptr;
+        L.inv_h2 = T(1);
+        L.kappa = T(0);
+        L.H0x = T(h->prm.H0 * std::cos(h->prm.alpha));
+        L.H0y = T(h->prm.H0 * std::sin(h->prm.alpha));
+    } else {
+        const double hh = double(1 << l);
+        L.u = reinterpret_cast<T*>(s + h->plan.off_u[l]);
+        L.mu = reinterpret_cast<const T*>(s + h->plan.off_mu[l]);
+        L.f = reinterpret_cast<T*>(s + h->plan.off_f[l]);
+        L.inv_h2 = T(1.0 / (hh * hh));
+        L.kappa = T((hh - 1.0) / (hh + 1.0));
+        L.H0x = L.H0y = T(0);
+    }
+    return L;
+}
+
+// Rounding floor of the residual test: a residual below 16 machine epsilons of the
+// largest diagonal term C psi' cannot be resolved in the working precision.
+template <typename T>
+constexpr double resid_floor_factor() {
+    return 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
+}
+
+template <typename T>
+fcd_status read_residual(fcd_handle* h, const fcd::PotLevel<T>& L0, double* r, double* scale) {
     hipEvent_t ev = nullptr;
     const bool timed = h->timer.begin(h->stream, &ev);
-    fcd::launch_residual<T>(psi, mur, P, res_word(h), h->stream);
+    fcd::launch_pot_residual<T>(L0, res_word(h), h->stream);
     if (timed) h->timer.end(h->stream, TK_RESID, ev);
     fcd_status st = hip_check(hipGetLastError(), "residual launch");
     if (st) return st;
-    st = hip_check(hipMemcpyAsync(h->host, res_word(h), sizeof(double), hipMemcpyDeviceToHost, h->stream),
+    st = hip_check(hipMemcpyAsync(h->host, res_word(h), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
                    "residual copy");
     if (st) return st;
     st = hip_check(hipStreamSynchronize(h->stream), "residual sync");
     if (st) return st;
     h->timer.resolve();
     std::memcpy(r, h->host, sizeof(double));
+    std::memcpy(scale, h->host + 1, sizeof(double));
     return FCD_OK;
 }
 
-// Four-colour SOR on the current mu_r plane, warm-started from the stored psi'.
+// Coarse mu on every level, from the current mu_r plane.
 template <typename T>
-fcd_status solve_impl(fcd_handle* h, double tol, int max_sweeps, int* sweeps_out, double* resid_out) {
-    const fcd::StepConst<T> P = make_const<T>(h);
+void restrict_mu_all(fcd_handle* h) {
+    for (int l = 1; l < h->plan.levels; ++l) {
+        const fcd::PotLevel<T> F = pot_level<T>(h, l - 1), C = pot_level<T>(h, l);
+        fcd::launch_mg_restrict_mu<T>(F.mu, F.pitch, const_cast<T*>(C.mu), C.nx, C.ny, C.pitch, h->stream);
+    }
+}
+
+// Solve the coarsest level: in LDS by one block when it fits, else by launched sweeps.
+template <typename T>
+void coarse_solve(fcd_handle* h, int l, const fcd::PotLevel<T>& L0) {
+    const fcd::PotLevel<T> L = l == 0 ? L0 : pot_level<T>(h, l);
+    const T om = T(sor_omega_opt(L.ny));
+    if (l > 0 && fcd::mg_coarse_lds_bytes<T>(L.nx, L.ny) <= COARSE_LDS_MAX) {
+        fcd::launch_mg_coarse_solve<T>(L, h->prm.pot_coarse_sweeps, om, h->stream);
+    } else {
+        for (int s = 0; s < h->prm.pot_coarse_sweeps; ++s) fcd::launch_pot_sweep<T>(L, om, h->stream);
+    }
+}
+
+// One V-cycle: Gauss-Seidel smoothing, residual restriction, coarsest solve,
+// bilinear prolongation and post-smoothing.
+template <typename T>
+void vcycle(fcd_handle* h, const fcd::PotLevel<T>& L0) {
+    const int L = h->plan.levels, nu = h->prm.pot_smooth;
+    if (L == 1) {
+        coarse_solve<T>(h, 0, L0);
+        return;
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        const fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
+        for (int s = 0; s < nu; ++s) fcd::launch_pot_sweep<T>(F, T(1), h->stream);
+        fcd::launch_mg_restrict_residual<T>(F, pot_level<T>(h, l + 1), h->stream);
+    }
+    coarse_solve<T>(h, L - 1, L0);
+    for (int l = L - 2; l >= 0; --l) {
+        const fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
+        fcd::launch_mg_prolong<T>(pot_level<T>(h, l + 1), F, h->stream);
+        for (int s = 0; s < nu; ++s) fcd::launch_pot_sweep<T>(F, T(1), h->stream);
+    }
+}
+
+// Iterate (SOR sweeps or V-cycles) on the finest-level problem L0 until
+// max |residual| <= max(thr0, rounding floor) or max_iters; the coarse mu hierarchy
+// must already hold the restriction of L0's mu.  defer_from: iterations of a previous
+// comparable solve (the first residual test is deferred past all but one of them).
+template <typename T>
+fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0, int max_iters, int defer_from,
+                          int* iters_out, double* resid_out) {
+    const bool mg = h->prm.pot_solver == FCD_SOLVER_MG;
+    const int every = h->prm.pot_check_every;
+    const T omega = T(h->prm.pot_omega > 0.0 ? h->prm.pot_omega : sor_omega_opt(L0.ny));
+    auto one = [&]() {
+        hipEvent_t ev = nullptr;
+        const bool timed = h->timer.begin(h->stream, &ev);
+        if (mg)
+            vcycle<T>(h, L0);
+        else
+            fcd::launch_pot_sweep<T>(L0, omega, h->stream);
+        if (timed) h->timer.end(h->stream, TK_ITER, ev);
+    };
+    // The residual is tested before iterating and then every pot_check_every
+    // iterations, except that the first test is deferred past the iterations the
+    // previous comparable solve needed minus one: consecutive steps need similar counts,
+    // and each test costs a reduction and a host round trip.
+    int it = 0;
+    const int defer = defer_from > 1 ? defer_from - 1 : 0;
+    if (defer > 0 && defer <= max_iters) {
+        for (int s = 0; s < defer; ++s) one();
+        it = defer;
+    }
+    double r = 0.0, scale = 0.0;
+    fcd_status st = read_residual<T>(h, L0, &r, &scale);
+    if (st) return st;
+    auto thr_of = [&](double sc) { return std::max(thr0, resid_floor_factor<T>() * sc); };
+    double thr = thr_of(scale);
+    while (!(r <= thr)) {
+        if (r != r) {
+            h->last_resid = r;
+            return fail(FCD_ERR_DIVERGED, "potential residual is NaN");
+        }
+        if (it >= max_iters) break;
+        const int m = every < max_iters - it ? every : max_iters - it;
+        for (int s = 0; s < m; ++s) one();
+        st = hip_check(hipGetLastError(), "potential launch");
+        if (st) return st;
+        it += m;
+        st = read_residual<T>(h, L0, &r, &scale);
+        if (st) return st;
+        thr = thr_of(scale);
+    }
+    h->sweeps += it;
+    h->last_resid = r;
+    if (iters_out) *iters_out = it;
+    if (resid_out) *resid_out = r;
+    if (!(r <= thr)) return fail(FCD_ERR_NOT_CONVERGED, "potential solve reached max_iters");
+    return FCD_OK;
+}
+
+// Potential solve on the current mu_r plane, warm-started from the stored psi'.
+template <typename T>
+fcd_status solve_impl(fcd_handle* h, double tol, int max_iters, int* iters_out, double* resid_out) {
     T* psi = static_cast<T*>(h->buf.psi);
-    const T* mur = plane_ptr<T>(h->buf.phi, h, 2);
-    if (sweeps_out) *sweeps_out = 0;
+    if (iters_out) *iters_out = 0;
     if (h->prm.H0 == 0.0) {  // no applied field: psi' = 0 exactly
         fcd::launch_fill<T>(psi, (long long)h->lat.ny * h->lat.pitch, T(0), h->stream);
         if (resid_out) *resid_out = 0.0;
         h->last_resid = 0.0;
         return hip_check(hipGetLastError(), "fill");
     }
-    const double thr = tol * std::fabs(h->prm.H0);
-    const int every = h->prm.sor_check_every;
-    double r = 0.0;
-    fcd_status st = read_residual<T>(h, P, psi, mur, &r);
-    if (st) return st;
-    int sw = 0;
-    while (!(r <= thr)) {
-        if (r != r) {
-            h->last_resid = r;
-            return fail(FCD_ERR_DIVERGED, "potential residual is NaN");
-        }
-        if (sw >= max_sweeps) break;
-        const int m = every < max_sweeps - sw ? every : max_sweeps - sw;
-        const T omega = T(sor_omega_of(h->prm, h->lat.ny));
-        for (int s = 0; s < m; ++s) {
-            hipEvent_t ev = nullptr;
-            const bool timed = h->timer.begin(h->stream, &ev);
-            fcd::launch_sor_sweep<T>(psi, mur, P, omega, h->stream);
-            if (timed) h->timer.end(h->stream, TK_SWEEP, ev);
-        }
-        sw += m;
-        st = read_residual<T>(h, P, psi, mur, &r);
-        if (st) return st;
+    if (h->prm.pot_solver == FCD_SOLVER_MG) {
+        hipEvent_t ev = nullptr;
+        const bool timed = h->timer.begin(h->stream, &ev);
+        restrict_mu_all<T>(h);
+        if (timed) h->timer.end(h->stream, TK_PHASE, ev);
     }
-    h->sweeps += sw;
-    h->last_resid = r;
-    if (sweeps_out) *sweeps_out = sw;
-    if (resid_out) *resid_out = r;
-    if (!(r <= thr)) return fail(FCD_ERR_NOT_CONVERGED, "potential solve reached max_sweeps");
-    return FCD_OK;
+    int it = 0;
+    const fcd_status st = iterate_level0<T>(h, pot_level<T>(h, 0), tol * std::fabs(h->prm.H0), max_iters,
+                                            h->last_iters, &it, resid_out);
+    h->last_iters = it;
+    if (iters_out) *iters_out = it;
+    return st;
 }
 
 template <typename T>
 fcd_status step_impl(fcd_handle* h, int nsteps) {
     const fcd::StepConst<T> P = make_const<T>(h);
     T* phi = static_cast<T*>(h->buf.phi);
+    T* prev = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev);
     for (int n = 0; n < nsteps; ++n) {
         const T* src = static_cast<const T*>(h->buf.dist[h->cur]);
         T* dst = static_cast<T*>(h->buf.dist[1 - h->cur]);
@@ -276,8 +448,12 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
         if (timed) h->timer.end(h->stream, TK_PHASE, ev);
         fcd_status st = hip_check(hipGetLastError(), "phase launch");
         if (st) return st;
-        st = solve_impl<T>(h, h->prm.sor_tol, h->prm.sor_max_sweeps, nullptr, nullptr);
+        if (h->prm.pot_extrapolate && h->prm.H0 != 0.0)
+            fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, h->lat.nx, h->lat.ny, h->lat.pitch,
+                                       h->hist >= 2 ? 1 : 0, h->stream);
+        st = solve_impl<T>(h, h->prm.pot_tol, h->prm.pot_max_iters, nullptr, nullptr);
         if (st) return st;
+        ++h->hist;
         timed = h->timer.begin(h->stream, &ev);
         fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, h->stream);
         if (timed) h->timer.end(h->stream, TK_COLLIDE, ev);
@@ -359,13 +535,521 @@ fcd_status copy_in_impl(fcd_handle* h, void* dst, int nplanes, const double* in)
     return hip_check(hipGetLastError(), "copy launch");
 }
 
+
+// ---------------------------------------------------------------------------------
+// Batches.
+// ---------------------------------------------------------------------------------
+constexpr int BT_X = 64, BT_Y = 4;  // tile of the batched kernels
+
+struct BatchLayout {
+    std::vector<int> pitch;
+    std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev;  // into state / aux
+    std::vector<int> tile0, tiles_x, ctile0, ctiles_x;
+    int ntiles = 0, nctiles = 0;
+    size_t state_bytes = 0, aux_bytes = 0, scratch_bytes = 0;
+    size_t off_inst = 0, off_tiles = 0, off_ctiles = 0, off_res = 0, off_active = 0, off_counts = 0;
+    size_t off_rows = 0, off_cent = 0, off_result = 0;
+};
+
+fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
+    if (n < 1) return fail(FCD_ERR_ARG, "a batch needs at least one channel");
+    if (!lats) return fail(FCD_ERR_ARG, "lattices are null");
+    const int prec = lats[0].precision;
+    int max_ny = 0;
+    for (int k = 0; k < n; ++k) {
+        fcd_status st = check_lattice(&lats[k]);
+        if (st) return st;
+        if (lats[k].precision != prec) return fail(FCD_ERR_ARG, "all channels of a batch share one precision");
+        if (lats[k].ny > max_ny) max_ny = lats[k].ny;
+    }
+    const size_t esz = elem_size(prec);
+    const int per = (int)(256 / esz);
+    for (int k = 0; k < n; ++k) {
+        const fcd_lattice& l = lats[k];
+        const int pitch = (l.nx + per - 1) / per * per;  // batch pitch: 256-byte rows
+        const size_t plane = align256((size_t)l.ny * pitch * esz);
+        L->pitch.push_back(pitch);
+        L->off_d0.push_back(L->state_bytes);
+        L->state_bytes += 27 * plane;
+        L->off_d1.push_back(L->state_bytes);
+        L->state_bytes += 27 * plane;
+        L->off_phi.push_back(L->aux_bytes);
+        L->aux_bytes += 3 * plane;
+        L->off_psi.push_back(L->aux_bytes);
+        L->aux_bytes += plane;
+        L->off_prev.push_back(L->aux_bytes);
+        L->aux_bytes += plane;
+        const int tx = (l.nx + BT_X - 1) / BT_X, ty = (l.ny + BT_Y - 1) / BT_Y;
+        L->tile0.push_back(L->ntiles);
+        L->tiles_x.push_back(tx);
+        L->ntiles += tx * ty;
+        const int cx = ((l.nx + 1) / 2 + BT_X - 1) / BT_X, cy = ((l.ny + 1) / 2 + BT_Y - 1) / BT_Y;
+        L->ctile0.push_back(L->nctiles);
+        L->ctiles_x.push_back(cx);
+        L->nctiles += cx * cy;
+    }
+    const size_t inst_sz = prec == FCD_FP64 ? sizeof(fcd::BatchInst<double>) : sizeof(fcd::BatchInst<float>);
+    size_t off = 0;
+    L->off_inst = off;
+    off = align256(off + (size_t)n * inst_sz);
+    L->off_tiles = off;
+    off = align256(off + (size_t)L->ntiles * sizeof(int));
+    L->off_ctiles = off;
+    off = align256(off + (size_t)L->nctiles * sizeof(int));
+    L->off_res = off;
+    off = align256(off + 2 * (size_t)n * sizeof(unsigned long long));
+    L->off_active = off;
+    off = align256(off + (size_t)n * sizeof(int));
+    L->off_counts = off;
+    off = align256(off + 2 * sizeof(int));
+    L->off_rows = off;
+    off = align256(off + (size_t)max_ny * 8 * sizeof(double));
+    L->off_cent = off;
+    off = align256(off + 8 * sizeof(double));
+    L->off_result = off;
+    off = align256(off + (size_t)n * 4 * sizeof(double));
+    L->scratch_bytes = off;
+    return FCD_OK;
+}
+
+}  // namespace
+
+struct fcd_batch {
+    int n;
+    int precision;
+    hipStream_t stream;
+    std::vector<fcd_lattice> lat;
+    std::vector<fcd_params> prm;
+    BatchLayout L;
+    char* state;
+    char* aux;
+    char* scratch;
+    int cur;
+    int hist;
+    int last_iters;
+    long long steps;
+    long long iters;
+    double last_resid;
+    double* host;  // pinned: [0] active count and NaN count (two ints), [1..] n x 4 diagnostics
+};
+
+namespace {
+
+// Single-channel view of channel k (for the per-channel utility kernels).
+template <typename T>
+fcd::StepConst<T> batch_const(const fcd_batch* b, int k) {
+    fcd_handle h{};
+    h.lat = b->lat[k];
+    h.lat.pitch = b->L.pitch[k];
+    h.prm = b->prm[k];
+    return make_const<T>(&h);
+}
+
+template <typename T>
+T* bptr(char* base, size_t off) {
+    return reinterpret_cast<T*>(base + off);
+}
+
+template <typename T>
+fcd_status batch_upload(fcd_batch* b) {
+    std::vector<fcd::BatchInst<T>> inst(b->n);
+    std::vector<int> tiles(b->L.ntiles), ctiles(b->L.nctiles);
+    for (int k = 0; k < b->n; ++k) {
+        fcd::BatchInst<T>& I = inst[k];
+        const fcd_lattice& l = b->lat[k];
+        const fcd_params& p = b->prm[k];
+        I = fcd::BatchInst<T>{};
+        I.P = batch_const<T>(b, k);
+        I.dist[0] = bptr<T>(b->state, b->L.off_d0[k]);
+        I.dist[1] = bptr<T>(b->state, b->L.off_d1[k]);
+        I.phi = bptr<T>(b->aux, b->L.off_phi[k]);
+        I.prev = bptr<T>(b->aux, b->L.off_prev[k]);
+        I.L0.u = bptr<T>(b->aux, b->L.off_psi[k]);
+        I.L0.mu = I.phi + 2 * (long long)I.P.plane;
+        I.L0.f = nullptr;
+        I.L0.nx = l.nx;
+        I.L0.ny = l.ny;
+        I.L0.pitch = b->L.pitch[k];
+        I.L0.inv_h2 = T(1);
+        I.L0.kappa = T(0);
+        I.L0.H0x = T(p.H0 * std::cos(p.alpha));
+        I.L0.H0y = T(p.H0 * std::sin(p.alpha));
+        I.omega = T(p.pot_omega > 0.0 ? p.pot_omega : sor_omega_opt(l.ny));
+        I.thr = p.pot_tol * std::fabs(p.H0);
+        I.tile0 = b->L.tile0[k];
+        I.tiles_x = b->L.tiles_x[k];
+        I.ctile0 = b->L.ctile0[k];
+        I.ctiles_x = b->L.ctiles_x[k];
+        I.has_field = p.H0 != 0.0;
+        const int nt = (l.nx + BT_X - 1) / BT_X * ((l.ny + BT_Y - 1) / BT_Y);
+        for (int t = 0; t < nt; ++t) tiles[I.tile0 + t] = k;
+        const int nc = ((l.nx + 1) / 2 + BT_X - 1) / BT_X * (((l.ny + 1) / 2 + BT_Y - 1) / BT_Y);
+        for (int t = 0; t < nc; ++t) ctiles[I.ctile0 + t] = k;
+    }
+    fcd_status st = hip_check(hipMemcpy(b->scratch + b->L.off_inst, inst.data(), inst.size() * sizeof(inst[0]),
+                                        hipMemcpyHostToDevice), "descriptor upload");
+    if (st) return st;
+    st = hip_check(hipMemcpy(b->scratch + b->L.off_tiles, tiles.data(), tiles.size() * sizeof(int),
+                             hipMemcpyHostToDevice), "tile table upload");
+    if (st) return st;
+    return hip_check(hipMemcpy(b->scratch + b->L.off_ctiles, ctiles.data(), ctiles.size() * sizeof(int),
+                               hipMemcpyHostToDevice), "tile table upload");
+}
+
+template <typename T>
+const fcd::BatchInst<T>* binst(const fcd_batch* b) {
+    return reinterpret_cast<const fcd::BatchInst<T>*>(b->scratch + b->L.off_inst);
+}
+
+// Per-channel residuals and activity flags; returns the number of channels still above
+// their threshold (and fails on a NaN residual).
+template <typename T>
+fcd_status batch_check(fcd_batch* b, int* active_count) {
+    int* counts = bptr<int>(b->scratch, b->L.off_counts);
+    fcd::launch_batch_residual<T>(binst<T>(b), bptr<int>(b->scratch, b->L.off_tiles), b->L.ntiles, b->n,
+                                  bptr<unsigned long long>(b->scratch, b->L.off_res),
+                                  bptr<int>(b->scratch, b->L.off_active), counts, b->stream);
+    fcd_status st = hip_check(hipGetLastError(), "batch residual launch");
+    if (st) return st;
+    st = hip_check(hipMemcpyAsync(b->host, counts, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream),
+                   "batch residual copy");
+    if (st) return st;
+    st = hip_check(hipMemcpyAsync(b->host + 1, bptr<unsigned long long>(b->scratch, b->L.off_res),
+                                  2 * (size_t)b->n * sizeof(double), hipMemcpyDeviceToHost, b->stream),
+                   "batch residual copy");
+    if (st) return st;
+    st = hip_check(hipStreamSynchronize(b->stream), "batch residual sync");
+    if (st) return st;
+    int c[2];
+    std::memcpy(c, b->host, sizeof(c));
+    double rmax = 0.0;
+    for (int k = 0; k < b->n; ++k) rmax = b->host[1 + 2 * k] > rmax ? b->host[1 + 2 * k] : rmax;
+    b->last_resid = rmax;
+    if (c[1] > 0) return fail(FCD_ERR_DIVERGED, "a channel's potential residual is NaN");
+    *active_count = c[0];
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status batch_solve(fcd_batch* b, int max_iters, int check_every) {
+    int* active = bptr<int>(b->scratch, b->L.off_active);
+    const int* ctiles = bptr<int>(b->scratch, b->L.off_ctiles);
+    fcd::launch_fill<int>(active, b->n, 1, b->stream);
+    int it = 0;
+    const int defer = b->last_iters > 1 ? b->last_iters - 1 : 0;
+    if (defer > 0 && defer <= max_iters) {
+        for (int s = 0; s < defer; ++s) fcd::launch_batch_sweep<T>(binst<T>(b), ctiles, b->L.nctiles, active, b->stream);
+        it = defer;
+    }
+    int left = 0;
+    fcd_status st = batch_check<T>(b, &left);
+    if (st) return st;
+    while (left > 0 && it < max_iters) {
+        const int m = check_every < max_iters - it ? check_every : max_iters - it;
+        for (int s = 0; s < m; ++s) fcd::launch_batch_sweep<T>(binst<T>(b), ctiles, b->L.nctiles, active, b->stream);
+        it += m;
+        st = batch_check<T>(b, &left);
+        if (st) return st;
+    }
+    b->iters += it;
+    b->last_iters = it;
+    if (left > 0) return fail(FCD_ERR_NOT_CONVERGED, "a channel's potential solve reached pot_max_iters");
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
+    const int* tiles = bptr<int>(b->scratch, b->L.off_tiles);
+    const fcd_params& p0 = b->prm[0];
+    for (int n = 0; n < nsteps; ++n) {
+        fcd::launch_batch_phase<T>(binst<T>(b), tiles, b->L.ntiles, b->cur, b->stream);
+        if (p0.pot_extrapolate)
+            fcd::launch_batch_psi_history<T>(binst<T>(b), tiles, b->L.ntiles, b->hist >= 2 ? 1 : 0, b->stream);
+        fcd_status st = hip_check(hipGetLastError(), "batch phase launch");
+        if (st) return st;
+        st = batch_solve<T>(b, p0.pot_max_iters, p0.pot_check_every);
+        if (st) return st;
+        ++b->hist;
+        fcd::launch_batch_collide<T>(binst<T>(b), tiles, b->L.ntiles, b->cur, b->stream);
+        st = hip_check(hipGetLastError(), "batch collide launch");
+        if (st) return st;
+        b->cur = 1 - b->cur;
+        ++b->steps;
+    }
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status batch_init_impl(fcd_batch* b, const double* geom) {
+    for (int k = 0; k < b->n; ++k) {
+        const fcd_params& p = b->prm[k];
+        const fcd_lattice& l = b->lat[k];
+        const double u_scale = p.drive_G / (2.0 * p.rho[2] * p.tau[2] / 3.0);
+        fcd::launch_init_droplet<T>(bptr<T>(b->state, b->L.off_d0[k]), l.nx, l.ny, b->L.pitch[k], geom[4 * k],
+                                    geom[4 * k + 1], geom[4 * k + 2], geom[4 * k + 3], p.xi, u_scale, b->stream);
+    }
+    fcd::launch_batch_fill_psi<T>(binst<T>(b), bptr<int>(b->scratch, b->L.off_tiles), b->L.ntiles, b->stream);
+    b->cur = 0;
+    b->hist = 0;
+    b->last_iters = 0;
+    return hip_check(hipGetLastError(), "batch init launch");
+}
+
+template <typename T>
+void batch_refresh_phase(fcd_batch* b, int k) {
+    const fcd::StepConst<T> P = batch_const<T>(b, k);
+    const size_t off = b->cur == 0 ? b->L.off_d0[k] : b->L.off_d1[k];
+    fcd::launch_phase<T>(bptr<T>(b->state, off), bptr<T>(b->aux, b->L.off_phi[k]), P, b->stream);
+}
+
+template <typename T>
+fcd_status batch_diag_impl(fcd_batch* b, double* out) {
+    double* results = bptr<double>(b->scratch, b->L.off_result);
+    for (int k = 0; k < b->n; ++k) {
+        batch_refresh_phase<T>(b, k);
+        const fcd::StepConst<T> P = batch_const<T>(b, k);
+        fcd::launch_diagnostics<T>(bptr<T>(b->aux, b->L.off_phi[k]), P, bptr<double>(b->scratch, b->L.off_rows),
+                                   bptr<double>(b->scratch, b->L.off_cent), results + 4 * k, b->stream);
+    }
+    fcd_status st = hip_check(hipGetLastError(), "batch diagnostics launch");
+    if (st) return st;
+    st = hip_check(hipMemcpyAsync(b->host + 1, results, (size_t)b->n * 4 * sizeof(double), hipMemcpyDeviceToHost,
+                                  b->stream), "batch diagnostics copy");
+    if (st) return st;
+    st = hip_check(hipStreamSynchronize(b->stream), "batch diagnostics sync");
+    if (st) return st;
+    std::memcpy(out, b->host + 1, (size_t)b->n * 4 * sizeof(double));
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status batch_state_impl(fcd_batch* b, int k, double* out) {
+    const fcd_lattice& l = b->lat[k];
+    const size_t off = b->cur == 0 ? b->L.off_d0[k] : b->L.off_d1[k];
+    fcd::launch_to_dense<T>(bptr<T>(b->state, off), out, 27, l.nx, l.ny, b->L.pitch[k], b->stream);
+    return hip_check(hipGetLastError(), "batch copy launch");
+}
+
+template <typename T>
+fcd_status batch_moments_impl(fcd_batch* b, int k, unsigned mask, double* out) {
+    batch_refresh_phase<T>(b, k);
+    const size_t off = b->cur == 0 ? b->L.off_d0[k] : b->L.off_d1[k];
+    fcd::launch_moments<T>(bptr<T>(b->state, off), bptr<T>(b->aux, b->L.off_phi[k]),
+                           bptr<T>(b->aux, b->L.off_psi[k]), batch_const<T>(b, k), mask, out, b->stream);
+    return hip_check(hipGetLastError(), "batch moments launch");
+}
+
+// ---------------------------------------------------------------------------------
+// Checkpointed adjoint.
+// ---------------------------------------------------------------------------------
+struct AdjLayout {
+    size_t plane, state, rec;  // bytes of one plane, one state (27 planes), state + psi' record
+    int nseg, nblocks;
+    size_t off_ckpt, off_final, off_seg, off_lam, off_sens, off_rhs, off_lpsi, off_part, off_acc, off_rmax, bytes;
+};
+
+AdjLayout adj_layout(const fcd_lattice& l, int nsteps, int every) {
+    AdjLayout L{};
+    L.plane = (size_t)l.ny * l.pitch * elem_size(l.precision);
+    L.state = 27 * L.plane;
+    L.rec = align256(L.state + L.plane);
+    L.nseg = (nsteps + every - 1) / every;
+    L.nblocks = fcd::adj_blocks(l.nx, l.ny);
+    size_t off = 0;
+    L.off_ckpt = off;
+    off += (size_t)L.nseg * L.rec;
+    L.off_final = off;
+    off += L.rec;
+    L.off_seg = off;
+    off += (size_t)every * L.rec;
+    L.off_lam = off;
+    off += 2 * align256(L.state);
+    L.off_sens = off;
+    off += align256(10 * L.plane);
+    L.off_rhs = off;
+    off += align256(L.plane);
+    L.off_lpsi = off;
+    off += align256(L.plane);
+    L.off_part = off;
+    off += align256(3 * (size_t)L.nblocks * fcd::ADJ_NPART * sizeof(double));
+    L.off_acc = off;
+    off += 256;
+    L.off_rmax = off;
+    off += 256;
+    L.bytes = off;
+    return L;
+}
+
+fcd_status dcopy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    return hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s), "device copy");
+}
+
+template <typename T>
+fcd_status save_record(fcd_handle* h, char* rec, size_t state_bytes) {
+    fcd_status st = dcopy(rec, h->buf.dist[h->cur], state_bytes, h->stream);
+    if (st) return st;
+    return dcopy(rec + state_bytes, h->buf.psi, state_bytes / 27, h->stream);
+}
+
+template <typename T>
+fcd_status load_record(fcd_handle* h, const char* rec, size_t state_bytes) {
+    fcd_status st = dcopy(h->buf.dist[h->cur], rec, state_bytes, h->stream);
+    if (st) return st;
+    return dcopy(h->buf.psi, rec + state_bytes, state_bytes / 27, h->stream);
+}
+
+template <typename T>
+fcd_status adj_forward_impl(fcd_handle* h, int nsteps, int every, char* work, double D_out[2]) {
+    const AdjLayout L = adj_layout(h->lat, nsteps, every);
+    h->adj_work = work;
+    h->adj_nsteps = nsteps;
+    h->adj_every = every;
+    h->adj_from_init = h->init_fresh;
+    const int saved_extrap = h->prm.pot_extrapolate;
+    h->prm.pot_extrapolate = 0;  // the recomputation must be able to replay every solve
+    fcd_status st = FCD_OK;
+    for (int t = 0; t < nsteps && !st; ++t) {
+        if (t % every == 0) st = save_record<T>(h, work + L.off_ckpt + (size_t)(t / every) * L.rec, L.state);
+        if (!st) st = step_impl<T>(h, 1);
+    }
+    h->prm.pot_extrapolate = saved_extrap;
+    if (st) return st;
+    st = save_record<T>(h, work + L.off_final, L.state);
+    if (st) return st;
+    double d[4];
+    st = diag_impl<T>(h, d);
+    if (st) return st;
+    D_out[0] = d[0];
+    D_out[1] = d[1];
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) {
+    if (!h->adj_work || h->adj_every < 1) return fail(FCD_ERR_ARG, "fcd_adjoint_forward has not run");
+    const int nsteps = h->adj_nsteps, every = h->adj_every;
+    const AdjLayout L = adj_layout(h->lat, nsteps, every);
+    char* w = h->adj_work;
+    const fcd::StepConst<T> P = make_const<T>(h);
+    const long long pl = P.plane;
+    T* lam[2] = {reinterpret_cast<T*>(w + L.off_lam), reinterpret_cast<T*>(w + L.off_lam + align256(L.state))};
+    T* sens = reinterpret_cast<T*>(w + L.off_sens);
+    T* rhs = reinterpret_cast<T*>(w + L.off_rhs);
+    T* lpsi = reinterpret_cast<T*>(w + L.off_lpsi);
+    double* partA = reinterpret_cast<double*>(w + L.off_part);
+    double* partB = partA + (size_t)L.nblocks * fcd::ADJ_NPART;
+    double* partC = partB + (size_t)L.nblocks * fcd::ADJ_NPART;
+    double* acc = reinterpret_cast<double*>(w + L.off_acc);
+    unsigned long long* rmax = reinterpret_cast<unsigned long long*>(w + L.off_rmax);
+    T* phi = static_cast<T*>(h->buf.phi);
+    char* scr = static_cast<char*>(h->buf.scratch);
+    const int saved_extrap = h->prm.pot_extrapolate;
+    h->prm.pot_extrapolate = 0;
+    fcd::launch_fill<double>(acc, 16, 0.0, h->stream);
+    fcd::launch_fill<T>(lpsi, pl, T(0), h->stream);
+    // seed: adjoint of the final state from J = dJ[0] D_o + dJ[1] D_i
+    fcd_status st = load_record<T>(h, w + L.off_final, L.state);
+    if (st) return st;
+    double d[4];
+    st = diag_impl<T>(h, d);  // phase planes and the deformation moments of the final state
+    if (st) return st;
+    fcd::launch_adj_seed<T>(phi, reinterpret_cast<const double*>(scr + OFF_CENT) + 8, dJ[0], dJ[1], lam[0], P,
+                            h->stream);
+    int A = 0, adj_iters = 0;
+    const bool field = h->prm.H0 != 0.0;
+    for (int seg = L.nseg - 1; seg >= 0 && !st; --seg) {
+        const int t0 = seg * every, t1 = std::min(nsteps, t0 + every);
+        st = load_record<T>(h, w + L.off_ckpt + (size_t)seg * L.rec, L.state);
+        if (st) break;
+        for (int t = t0; t < t1 && !st; ++t) {
+            char* rec = w + L.off_seg + (size_t)(t - t0) * L.rec;
+            st = dcopy(rec, h->buf.dist[h->cur], L.state, h->stream);
+            if (!st) st = step_impl<T>(h, 1);
+            if (!st) st = dcopy(rec + L.state, h->buf.psi, L.plane, h->stream);
+        }
+        for (int t = t1 - 1; t >= t0 && !st; --t) {
+            const char* rec = w + L.off_seg + (size_t)(t - t0) * L.rec;
+            const T* s_t = reinterpret_cast<const T*>(rec);
+            const T* psi_t = reinterpret_cast<const T*>(rec + L.state);
+            fcd::launch_phase<T>(s_t, phi, P, h->stream);
+            fcd::launch_adj_node<T>(s_t, phi, psi_t, lam[A], lam[1 - A], sens, partA, P, h->stream);
+            fcd::launch_adj_reduce(partA, L.nblocks, 13, acc, 0, h->stream);
+            st = hip_check(hipGetLastError(), "adjoint node launch");
+            if (st) break;
+            if (field) {
+                fcd::launch_adj_gather_psi<T>(sens, rhs, rmax, P, h->stream);
+                if (h->prm.pot_solver == FCD_SOLVER_MG) restrict_mu_all<T>(h);
+                st = hip_check(hipMemcpyAsync(h->host, rmax, sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                               "adjoint rhs copy");
+                if (!st) st = hip_check(hipStreamSynchronize(h->stream), "adjoint rhs sync");
+                if (st) break;
+                double rm;
+                std::memcpy(&rm, h->host, sizeof(double));
+                if (rm > 0.0) {
+                    fcd::PotLevel<T> La = pot_level<T>(h, 0);
+                    La.u = lpsi;
+                    La.f = rhs;
+                    La.H0x = La.H0y = T(0);
+                    int it = 0;
+                    st = iterate_level0<T>(h, La, h->prm.pot_tol * rm, h->prm.pot_max_iters, adj_iters, &it, nullptr);
+                    adj_iters = it;
+                    if (st) break;
+                } else {
+                    fcd::launch_fill<T>(lpsi, pl, T(0), h->stream);
+                }
+                fcd::launch_adj_finish<T>(sens, phi, psi_t, lpsi, lam[1 - A], partB, P, h->stream);
+                fcd::launch_adj_reduce(partB, L.nblocks, 2, acc, 13, h->stream);
+            } else {
+                fcd::launch_fill<T>(lpsi, pl, T(0), h->stream);
+                fcd::launch_adj_finish<T>(sens, phi, psi_t, lpsi, lam[1 - A], partB, P, h->stream);
+            }
+            st = hip_check(hipGetLastError(), "adjoint finish launch");
+            A = 1 - A;
+        }
+    }
+    h->prm.pot_extrapolate = saved_extrap;
+    if (st) return st;
+    if (h->adj_from_init) {
+        const double nu3 = h->prm.tau[2] / 3.0;
+        const double dUdG = 1.0 / (2.0 * h->prm.rho[2] * nu3);
+        fcd::launch_adj_init_drive<T>(reinterpret_cast<const T*>(w + L.off_ckpt), lam[A], dUdG,
+                                      h->prm.drive_G * dUdG, partC, P, h->stream);
+        fcd::launch_adj_reduce(partC, L.nblocks, 1, acc, 15, h->stream);
+    }
+    st = hip_check(hipMemcpyAsync(h->host, acc, 16 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                   "adjoint result copy");
+    if (!st) st = hip_check(hipStreamSynchronize(h->stream), "adjoint result sync");
+    if (st) return st;
+    double a[16];
+    std::memcpy(a, h->host, sizeof(a));
+    const fcd_params& p = h->prm;
+    const double ca = std::cos(p.alpha), sa = std::sin(p.alpha);
+    const double hx = a[0] + a[13], hy = a[1] + a[14];
+    grad[0] = hx * ca + hy * sa;
+    grad[1] = p.H0 * (-hx * sa + hy * ca);
+    grad[2] = a[2] + a[15];
+    const double g[3] = {p.sigma12 + p.sigma13 - p.sigma23, p.sigma12 + p.sigma23 - p.sigma13,
+                         p.sigma13 + p.sigma23 - p.sigma12};
+    const double gT = 3.0 / (1.0 / g[0] + 1.0 / g[1] + 1.0 / g[2]);
+    double gb[3];
+    for (int k = 0; k < 3; ++k)
+        gb[k] = a[6 + k] - a[9 + k] / (g[k] * g[k]) + a[12] * (4.0 / p.xi) * gT * gT / (3.0 * g[k] * g[k]);
+    grad[3] = a[3] + gb[0] + gb[1] - gb[2];
+    grad[4] = a[4] + gb[0] - gb[1] + gb[2];
+    grad[5] = a[5] - gb[0] + gb[1] + gb[2];
+    // leave the handle on the forward's final state
+    return load_record<T>(h, w + L.off_final, L.state);
+}
+
+#define FCD_BDISPATCH(b, call) ((b)->precision == FCD_FP64 ? call<double> : call<float>)
+
 }  // namespace
 
 extern "C" {
 
 size_t fcd_scratch_bytes(const fcd_lattice* lat) {
-    if (!lat || lat->ny < 1) return 0;
-    return OFF_ROWS + (size_t)lat->ny * 8 * sizeof(double);
+    if (check_lattice(lat) != FCD_OK) return 0;
+    return make_plan(*lat).bytes;
 }
 
 fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_buffers* buf, void* hip_stream,
@@ -393,6 +1077,12 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     h->cur = 0;
     h->steps = h->sweeps = 0;
     h->last_resid = 0.0;
+    h->hist = 0;
+    h->last_iters = 0;
+    h->init_fresh = 0;
+    h->adj_work = nullptr;
+    h->adj_nsteps = h->adj_every = h->adj_from_init = 0;
+    h->plan = make_plan(*lat);
     if (hipHostMalloc(reinterpret_cast<void**>(&h->host), 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete h;
         return fail(FCD_ERR_OOM, "pinned host allocation failed");
@@ -411,6 +1101,9 @@ fcd_status fcd_set_params(fcd_handle* h, const fcd_params* prm) {
 
 fcd_status fcd_init_compound_droplet(fcd_handle* h, double xc, double yc, double r_core, double r_shell) {
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
+    h->hist = 0;
+    h->last_iters = 0;
+    h->init_fresh = 1;
     if (!(r_core >= 0.0) || !(r_shell >= r_core)) return fail(FCD_ERR_ARG, "need 0 <= r_core <= r_shell");
     return FCD_DISPATCH(h, init_droplet_impl)(h, xc, yc, r_core, r_shell);
 }
@@ -418,25 +1111,29 @@ fcd_status fcd_init_compound_droplet(fcd_handle* h, double xc, double yc, double
 fcd_status fcd_init_fields(fcd_handle* h, const double* phi1, const double* phi2, const double* ux,
                            const double* uy, const double* pstar) {
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
+    h->init_fresh = 0;
+    h->hist = 0;
+    h->last_iters = 0;
     if (!phi1 || !phi2 || !ux || !uy) return fail(FCD_ERR_ARG, "a field pointer is null");
     return FCD_DISPATCH(h, init_fields_impl)(h, phi1, phi2, ux, uy, pstar);
 }
 
-fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_sweeps, int32_t* sweeps_out,
+fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_iters, int32_t* iters_out,
                                double* resid_out) {
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
-    if (!(tol > 0.0) || max_sweeps < 0) return fail(FCD_ERR_ARG, "bad tolerance or sweep limit");
+    if (!(tol > 0.0) || max_iters < 0) return fail(FCD_ERR_ARG, "bad tolerance or iteration limit");
     fcd_status st = FCD_DISPATCH(h, refresh_phase)(h);
     if (st) return st;
-    int sw = 0;
-    st = FCD_DISPATCH(h, solve_impl)(h, tol, max_sweeps, &sw, resid_out);
-    if (sweeps_out) *sweeps_out = sw;
+    int it = 0;
+    st = FCD_DISPATCH(h, solve_impl)(h, tol, max_iters, &it, resid_out);
+    if (iters_out) *iters_out = it;
     return st;
 }
 
 fcd_status fcd_step(fcd_handle* h, int32_t nsteps) {
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
     if (nsteps < 0) return fail(FCD_ERR_ARG, "nsteps must be >= 0");
+    if (nsteps > 0) h->init_fresh = 0;
     return FCD_DISPATCH(h, step_impl)(h, nsteps);
 }
 
@@ -453,6 +1150,9 @@ fcd_status fcd_read_state(fcd_handle* h, double* out) {
 
 fcd_status fcd_write_state(fcd_handle* h, const double* in) {
     if (!h || !in) return fail(FCD_ERR_ARG, "null argument");
+    h->init_fresh = 0;
+    h->hist = 0;
+    h->last_iters = 0;
     return FCD_DISPATCH(h, copy_in_impl)(h, h->buf.dist[h->cur], 27, in);
 }
 
@@ -463,6 +1163,8 @@ fcd_status fcd_read_psi(fcd_handle* h, double* out) {
 
 fcd_status fcd_write_psi(fcd_handle* h, const double* in) {
     if (!h || !in) return fail(FCD_ERR_ARG, "null argument");
+    h->hist = 0;
+    h->last_iters = 0;
     return FCD_DISPATCH(h, copy_in_impl)(h, h->buf.psi, 1, in);
 }
 
@@ -517,5 +1219,123 @@ fcd_status fcd_destroy(fcd_handle* h) {
 }
 
 const char* fcd_last_error(void) { return g_err.c_str(); }
+
+size_t fcd_adjoint_bytes(const fcd_lattice* lat, int32_t nsteps, int32_t ckpt_every) {
+    if (check_lattice(lat) != FCD_OK || nsteps < 1 || ckpt_every < 1) return 0;
+    return adj_layout(*lat, nsteps, ckpt_every).bytes;
+}
+
+fcd_status fcd_adjoint_forward(fcd_handle* h, int32_t nsteps, int32_t ckpt_every, void* work, double D_out[2]) {
+    if (!h || !work || !D_out) return fail(FCD_ERR_ARG, "null argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(FCD_ERR_ARG, "need nsteps >= 1 and ckpt_every >= 1");
+    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(FCD_ERR_ARG, "work must be 256-byte aligned");
+    return FCD_DISPATCH(h, adj_forward_impl)(h, nsteps, ckpt_every, static_cast<char*>(work), D_out);
+}
+
+fcd_status fcd_adjoint_backward(fcd_handle* h, const double dJ_dD[2], double grad[6]) {
+    if (!h || !dJ_dD || !grad) return fail(FCD_ERR_ARG, "null argument");
+    return FCD_DISPATCH(h, adj_backward_impl)(h, dJ_dD, grad);
+}
+
+fcd_status fcd_batch_sizes(int32_t n, const fcd_lattice* lats, size_t bytes_out[3]) {
+    if (!bytes_out) return fail(FCD_ERR_ARG, "bytes_out is null");
+    BatchLayout L;
+    fcd_status st = batch_layout(n, lats, &L);
+    if (st) return st;
+    bytes_out[0] = L.state_bytes;
+    bytes_out[1] = L.aux_bytes;
+    bytes_out[2] = L.scratch_bytes;
+    return FCD_OK;
+}
+
+fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params* prms, void* state, void* aux,
+                            void* scratch, void* hip_stream, fcd_batch** out) {
+    if (!out) return fail(FCD_ERR_ARG, "out is null");
+    *out = nullptr;
+    BatchLayout L;
+    fcd_status st = batch_layout(n, lats, &L);
+    if (st) return st;
+    if (!prms) return fail(FCD_ERR_ARG, "params are null");
+    for (int k = 0; k < n; ++k) {
+        st = check_params(&prms[k]);
+        if (st) return st;
+    }
+    if (!state || !aux || !scratch) return fail(FCD_ERR_ARG, "a device buffer is null");
+    for (const void* p : {state, aux, scratch})
+        if (reinterpret_cast<uintptr_t>(p) % 256) return fail(FCD_ERR_ARG, "batch buffers must be 256-byte aligned");
+    fcd_batch* b = new (std::nothrow) fcd_batch();
+    if (!b) return fail(FCD_ERR_OOM, "batch allocation failed");
+    b->n = n;
+    b->precision = lats[0].precision;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->lat.assign(lats, lats + n);
+    b->prm.assign(prms, prms + n);
+    b->L = L;
+    b->state = static_cast<char*>(state);
+    b->aux = static_cast<char*>(aux);
+    b->scratch = static_cast<char*>(scratch);
+    b->cur = b->hist = b->last_iters = 0;
+    b->steps = b->iters = 0;
+    b->last_resid = 0.0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->host), (1 + 4 * (size_t)n) * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return fail(FCD_ERR_OOM, "pinned host allocation failed");
+    }
+    st = FCD_BDISPATCH(b, batch_upload)(b);
+    if (st) {
+        (void)hipHostFree(b->host);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FCD_OK;
+}
+
+fcd_status fcd_batch_init_compound_droplet(fcd_batch* b, const double* geom) {
+    if (!b || !geom) return fail(FCD_ERR_ARG, "null argument");
+    for (int k = 0; k < b->n; ++k)
+        if (!(geom[4 * k + 2] >= 0.0) || !(geom[4 * k + 3] >= geom[4 * k + 2]))
+            return fail(FCD_ERR_ARG, "need 0 <= r_core <= r_shell");
+    return FCD_BDISPATCH(b, batch_init_impl)(b, geom);
+}
+
+fcd_status fcd_batch_step(fcd_batch* b, int32_t nsteps) {
+    if (!b) return fail(FCD_ERR_ARG, "batch is null");
+    if (nsteps < 0) return fail(FCD_ERR_ARG, "nsteps must be >= 0");
+    return FCD_BDISPATCH(b, batch_step_impl)(b, nsteps);
+}
+
+fcd_status fcd_batch_deformation(fcd_batch* b, double* out) {
+    if (!b || !out) return fail(FCD_ERR_ARG, "null argument");
+    return FCD_BDISPATCH(b, batch_diag_impl)(b, out);
+}
+
+fcd_status fcd_batch_read_state(fcd_batch* b, int32_t k, double* out) {
+    if (!b || !out || k < 0 || k >= b->n) return fail(FCD_ERR_ARG, "bad batch channel or null output");
+    return FCD_BDISPATCH(b, batch_state_impl)(b, k, out);
+}
+
+fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double* out) {
+    if (!b || !out || k < 0 || k >= b->n) return fail(FCD_ERR_ARG, "bad batch channel or null output");
+    if (mask == 0 || (mask & ~uint32_t(FCD_M_ALL))) return fail(FCD_ERR_ARG, "bad mask");
+    return FCD_BDISPATCH(b, batch_moments_impl)(b, k, mask, out);
+}
+
+fcd_status fcd_batch_stats(fcd_batch* b, double out[3]) {
+    if (!b || !out) return fail(FCD_ERR_ARG, "null argument");
+    out[0] = (double)b->steps;
+    out[1] = (double)b->iters;
+    out[2] = b->last_resid;
+    return FCD_OK;
+}
+
+fcd_status fcd_batch_destroy(fcd_batch* b) {
+    if (!b) return fail(FCD_ERR_ARG, "batch is null");
+    fcd_status st = hip_check(hipStreamSynchronize(b->stream), "stream sync");
+    (void)hipHostFree(b->host);
+    delete b;
+    return st;
+}
 
 }  // extern "C"

@@ -41,6 +41,25 @@ struct StepConst {
     T eps2;                   // eps_n^2
 };
 
+// One level of the potential problem (see fcd_potential.hip).  f == nullptr marks the
+// finest level, whose right-hand side H0 sum_a c_a (e_a . h) is formed on the fly.
+template <typename T>
+struct PotLevel {
+    T* u;         // unknown: psi' on the finest level, the correction on coarse levels
+    const T* mu;  // mu_r (finest) or its cell averages (coarse)
+    T* f;         // right-hand side, nullptr on the finest level
+    int nx, ny, pitch, pad;
+    T inv_h2;     // 1 / h^2, h = 2^level
+    T kappa;      // ghost rows carry -kappa times the edge rows: (h - 1) / (h + 1)
+    T H0x, H0y;   // applied field (finest level only)
+};
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ a, long long n, T v) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
 // Values of a plane on the 3x3 neighbourhood of a node.
 template <typename T>
 struct Nb9 {
@@ -98,7 +117,7 @@ __device__ __forceinline__ Nb9<T> load_nb_psi(const T* __restrict__ a, const NbI
 
 // Eq. 34: grad a = 3 sum w e a(x+e): axis weight 1/9 -> 1/3, diagonal 1/36 -> 1/12.
 template <typename T>
-__device__ __forceinline__ void iso_grad(const Nb9<T>& v, T& gx, T& gy) {
+__host__ __device__ __forceinline__ void iso_grad(const Nb9<T>& v, T& gx, T& gy) {
     const T third = T(1) / T(3), twelfth = T(1) / T(12);
     T d1 = v.ne - v.sw, d2 = v.se - v.nw;
     gx = third * (v.e - v.w) + twelfth * (d1 + d2);
@@ -107,7 +126,7 @@ __device__ __forceinline__ void iso_grad(const Nb9<T>& v, T& gx, T& gy) {
 
 // Eq. 35: lap a = 6 sum w (a(x+e) - a(x)) = 2/3 sum_axis + 1/6 sum_diag - 10/3 a.
 template <typename T>
-__device__ __forceinline__ T iso_lap(const Nb9<T>& v) {
+__host__ __device__ __forceinline__ T iso_lap(const Nb9<T>& v) {
     return T(2) / T(3) * ((v.e + v.w) + (v.n + v.s)) + T(1) / T(6) * ((v.ne + v.sw) + (v.nw + v.se)) -
            T(10) / T(3) * v.c;
 }
@@ -124,16 +143,16 @@ struct NodeOut {
 };
 
 template <typename T>
-__device__ __forceinline__ T rsqrt_t(T x);
+__host__ __device__ __forceinline__ T rsqrt_t(T x);
 template <>
-__device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+__host__ __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) { return 1.0f / sqrtf(x); }
+__host__ __device__ __forceinline__ float rsqrt_t<float>(float x) { return 1.0f / sqrtf(x); }
 
 // Stencils, forces and velocity at one node from the local f, the phi1 / phi2 and
 // psi' neighbourhoods.
 template <typename T>
-__device__ __forceinline__ NodeOut<T> node_physics(const StepConst<T>& P, const T f[9], const Nb9<T>& a1,
+__host__ __device__ __forceinline__ NodeOut<T> node_physics(const StepConst<T>& P, const T f[9], const Nb9<T>& a1,
                                                    const Nb9<T>& a2, const Nb9<T>& ps) {
     NodeOut<T> o;
     const T p1 = a1.c, p2 = a2.c, p3 = T(1) - p1 - p2;  // Eq. 24
@@ -234,7 +253,7 @@ __device__ __forceinline__ NodeOut<T> node_physics(const StepConst<T>& P, const 
 //   f* = fbar^eq + (1 - s_nu)/4 [(ex^2 - ey^2) m_xx + ex ey m_xy] + F,
 // with m the p_xx, p_xy moments of f - fbar^eq and fbar^eq = f^eq - F/2 (Eq. 15).
 template <typename T>
-__device__ __forceinline__ void collide_f(const NodeOut<T>& o, const T f[9], T out[9]) {
+__host__ __device__ __forceinline__ void collide_f(const NodeOut<T>& o, const T f[9], T out[9]) {
     const T ux = o.ux, uy = o.uy;
     const T usq = T(1.5) * (ux * ux + uy * uy);
     const T fr = T(3) / o.rho;
@@ -272,7 +291,7 @@ __device__ __forceinline__ void collide_f(const NodeOut<T>& o, const T f[9], T o
 //   g* = (1 - omega) g + omega phi Gamma(u) + (1 - omega/2) F^phi,
 // F^phi_a = w_a e_a . v.
 template <typename T>
-__device__ __forceinline__ void collide_g(const NodeOut<T>& o, T om, T phi, T vx, T vy, const T g[9], T out[9]) {
+__host__ __device__ __forceinline__ void collide_g(const NodeOut<T>& o, T om, T phi, T vx, T vy, const T g[9], T out[9]) {
     const T ux = o.ux, uy = o.uy;
     const T usq = T(1.5) * (ux * ux + uy * uy);
     const T w0 = T(4) / T(9), wa = T(1) / T(9), wd = T(1) / T(36);

@@ -11,6 +11,7 @@
 
 #include "fcd_device.hpp"
 #include "fcd_kernels.hpp"
+#include "fcd_step.hpp"
 
 namespace fcd {
 
@@ -71,93 +72,7 @@ __global__ void __launch_bounds__(BX* BY)
     k_phase(const T* __restrict__ dist, T* __restrict__ phi, StepConst<T> P) {
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= P.nx || j >= P.ny) return;
-    const long long k = (long long)j * P.pitch + i, pl = P.plane;
-    T g1[9], g2[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        g1[a] = dist[(9 + a) * pl + k];
-        g2[a] = dist[(18 + a) * pl + k];
-    }
-    const T p1 = ((g1[0] + g1[1]) + (g1[2] + g1[3])) + ((g1[4] + g1[5]) + (g1[6] + g1[7])) + g1[8];
-    const T p2 = ((g2[0] + g2[1]) + (g2[2] + g2[3])) + ((g2[4] + g2[5]) + (g2[6] + g2[7])) + g2[8];
-    const T p3 = T(1) - p1 - p2;
-    phi[k] = p1;
-    phi[pl + k] = p2;
-    phi[2 * pl + k] = T(1) / (P.ic0 * p1 + P.ic1 * p2 + P.ic2 * p3);
-}
-
-// ---------------------------------------------------------------------------------
-// Magnetic potential, Eq. 6, conservative nine-point flux form:
-//   sum_a c_a (psi'(x+e_a) - psi'(x)) = H0 sum_a c_a (e_a . h),  c_a = 3 w_a (mu + mu_a).
-// One launch relaxes one of the four colours (i mod 2) + 2 (j mod 2); nodes of a colour
-// never neighbour each other, so the update is race-free and order-independent.
-// ---------------------------------------------------------------------------------
-template <typename T>
-struct PotNode {
-    T C, acc, src;  // sum c, sum c psi'_nb, H0 sum c (e.h)
-};
-
-template <typename T>
-__device__ __forceinline__ PotNode<T> pot_node(const T* __restrict__ psi, const T* __restrict__ mur, int i, int j,
-                                               const StepConst<T>& P) {
-    const NbIdx x = nb_index(i, j, P.nx, P.ny, P.pitch);
-    const Nb9<T> m = load_nb(mur, x);
-    const Nb9<T> u = load_nb_psi(psi, x, j, P.ny);
-    const T a = T(1) / T(3), d = T(1) / T(12);
-    const T ce = a * (m.c + m.e), cw = a * (m.c + m.w), cn = a * (m.c + m.n), cs = a * (m.c + m.s);
-    const T cne = d * (m.c + m.ne), cnw = d * (m.c + m.nw), csw = d * (m.c + m.sw), cse = d * (m.c + m.se);
-    PotNode<T> r;
-    r.C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
-    r.acc = ((ce * u.e + cw * u.w) + (cn * u.n + cs * u.s)) + ((cne * u.ne + csw * u.sw) + (cnw * u.nw + cse * u.se));
-    const T sx = (ce - cw) + (cne - csw) + (cse - cnw);
-    const T sy = (cn - cs) + (cne - csw) + (cnw - cse);
-    r.src = P.H0x * sx + P.H0y * sy;
-    return r;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(BX* BY)
-    k_sor_colour(T* __restrict__ psi, const T* __restrict__ mur, StepConst<T> P, int colour, T omega) {
-    const int i = 2 * (blockIdx.x * BX + threadIdx.x) + (colour & 1);
-    const int j = 2 * (blockIdx.y * BY + threadIdx.y) + (colour >> 1);
-    if (i >= P.nx || j >= P.ny) return;
-    const PotNode<T> r = pot_node(psi, mur, i, j, P);
-    const long long k = (long long)j * P.pitch + i;
-    const T old = psi[k];
-    psi[k] = old + omega * ((r.acc - r.src) / r.C - old);
-}
-
-// Max-norm of the residual L(psi0 + psi').  Grid-stride over nodes with a capped grid;
-// wave64 shuffle max, then the block's four wave maxima through LDS, then one
-// atomicMax per block on the bit pattern (monotone for non-negative doubles; a NaN
-// propagates as the largest pattern).
-constexpr int RES_T = 256;
-constexpr int RES_MAX_BLOCKS = 1024;
-
-__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
-
-template <typename T>
-__global__ void __launch_bounds__(RES_T)
-    k_residual(const T* __restrict__ psi, const T* __restrict__ mur, StepConst<T> P,
-               unsigned long long* __restrict__ out) {
-    __shared__ double wmax[RES_T / 64];
-    double v = 0.0;
-    const long long n = (long long)P.nx * P.ny;
-    for (long long t = (long long)blockIdx.x * RES_T + threadIdx.x; t < n; t += (long long)gridDim.x * RES_T) {
-        const int j = (int)(t / P.nx), i = (int)(t - (long long)j * P.nx);
-        const PotNode<T> r = pot_node(psi, mur, i, j, P);
-        const T c = psi[(long long)j * P.pitch + i];
-        v = nan_max(v, fabs((double)(r.acc - r.C * c - r.src)));
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = wmax[0];
-        for (int w = 1; w < RES_T / 64; ++w) m = nan_max(m, wmax[w]);
-        atomicMax(out, (unsigned long long)__double_as_longlong(m));
-    }
+    phase_node(dist, phi, P, i, j);
 }
 
 // ---------------------------------------------------------------------------------
@@ -170,60 +85,7 @@ __global__ void __launch_bounds__(BX* BY)
                      const T* __restrict__ psi, StepConst<T> P) {
     const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
     if (i >= P.nx || j >= P.ny) return;
-    const long long pl = P.plane;
-    const NbIdx x = nb_index(i, j, P.nx, P.ny, P.pitch);
-    const long long k = x.c;
-    T f[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = src[a * pl + k];
-    const Nb9<T> a1 = load_nb(phi, x);
-    const Nb9<T> a2 = load_nb(phi + pl, x);
-    const Nb9<T> ps = load_nb_psi(psi, x, j, P.ny);
-    const NodeOut<T> o = node_physics(P, f, a1, a2, ps);
-
-    // Destinations of the push: (i + ex, j + ey); a population that would cross a wall
-    // returns to its own node in the opposite direction (halfway bounce-back).
-    const bool bot = j == 0, top = j == P.ny - 1;
-    const long long dE = x.e, dW = x.w, dN = x.n, dS = x.s, dNE = x.ne, dNW = x.nw, dSW = x.sw, dSE = x.se;
-    // plane and node of each direction's destination
-    const int pN = top ? 4 : 2, pNE = top ? 7 : 5, pNW = top ? 8 : 6;
-    const int pS = bot ? 2 : 4, pSW = bot ? 5 : 7, pSE = bot ? 6 : 8;
-    const long long nN = top ? k : dN, nNE = top ? k : dNE, nNW = top ? k : dNW;
-    const long long nS = bot ? k : dS, nSW = bot ? k : dSW, nSE = bot ? k : dSE;
-
-    {
-        T out[9];
-        collide_f(o, f, out);
-        T* D = dst;
-        D[k] = out[0];
-        D[1 * pl + dE] = out[1];
-        D[3 * pl + dW] = out[3];
-        D[pN * pl + nN] = out[2];
-        D[pS * pl + nS] = out[4];
-        D[pNE * pl + nNE] = out[5];
-        D[pNW * pl + nNW] = out[6];
-        D[pSW * pl + nSW] = out[7];
-        D[pSE * pl + nSE] = out[8];
-    }
-#pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-        T g[9], out[9];
-        const T* S = src + (9 + 9 * comp) * pl;
-#pragma unroll
-        for (int a = 0; a < 9; ++a) g[a] = S[a * pl + k];
-        collide_g(o, P.omega_phi, comp == 0 ? o.phi1 : o.phi2, comp == 0 ? o.v1x : o.v2x,
-                  comp == 0 ? o.v1y : o.v2y, g, out);
-        T* D = dst + (9 + 9 * comp) * pl;
-        D[k] = out[0];
-        D[1 * pl + dE] = out[1];
-        D[3 * pl + dW] = out[3];
-        D[pN * pl + nN] = out[2];
-        D[pS * pl + nS] = out[4];
-        D[pNE * pl + nNE] = out[5];
-        D[pNW * pl + nNW] = out[6];
-        D[pSW * pl + nSW] = out[7];
-        D[pSE * pl + nSE] = out[8];
-    }
+    collide_stream_node(src, dst, phi, psi, P, i, j);
 }
 
 // ---------------------------------------------------------------------------------
@@ -270,12 +132,6 @@ __global__ void __launch_bounds__(BX* BY)
     if (i >= nx || j >= ny) return;
     for (int q = 0; q < nplanes; ++q)
         dst[((long long)q * ny + j) * pitch + i] = T(in[((long long)q * ny + j) * nx + i]);
-}
-
-template <typename T>
-__global__ void k_fill(T* __restrict__ a, long long n, T v) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) a[t] = v;
 }
 
 // ---------------------------------------------------------------------------------
@@ -331,9 +187,11 @@ __global__ void __launch_bounds__(DIAG_T)
             acc[1] += wo * dyo * dyo;
             acc[2] += wi * dxi * dxi;
             acc[3] += wi * dyi * dyi;
+            acc[4] += wo * dxo;
+            acc[5] += wi * dxi;
         }
     }
-    const int nv = pass == 0 ? 8 : 4;
+    const int nv = pass == 0 ? 8 : 6;
     for (int q = 0; q < nv; ++q) {
         const double s = block_sum(acc[q], sh);
         if (threadIdx.x == 0) rows[(long long)j * 8 + q] = s;
@@ -341,12 +199,14 @@ __global__ void __launch_bounds__(DIAG_T)
 }
 
 // Sums the per-row values in row order; pass 0 writes the centroids, pass 1 the result
-// {D_o, D_i, mass1, mass2} (masses kept from pass 0 in cent[4], cent[5]).
+// {D_o, D_i, mass1, mass2} (masses kept from pass 0 in cent[4], cent[5]).  cent[8..23]
+// receive, for the shell weight (8..15) and the core weight (16..23): S, C, Sn, y_c, x_c,
+// I_xx, I_yy, sum w dx -- what the adjoint of D needs.
 __global__ void k_diag_final(const double* __restrict__ rows, int ny, int nx, int pass, double* __restrict__ cent,
                              double* __restrict__ result) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int nv = pass == 0 ? 8 : 4;
+    const int nv = pass == 0 ? 8 : 6;
     for (int j = 0; j < ny; ++j)
         for (int q = 0; q < nv; ++q) s[q] += rows[(long long)j * 8 + q];
     const double twopi = 6.283185307179586476925286766559;
@@ -359,9 +219,27 @@ __global__ void k_diag_final(const double* __restrict__ rows, int ny, int nx, in
         cent[5] = s[0] - s[4];    // mass of phase 2
         cent[6] = s[0];
         cent[7] = s[4];
+        double* dg = cent + 8;
+        dg[0] = s[0];
+        dg[1] = s[1];
+        dg[2] = s[2];
+        dg[3] = cent[1];
+        dg[4] = cent[0];
+        dg[8] = s[4];
+        dg[9] = s[5];
+        dg[10] = s[6];
+        dg[11] = cent[3];
+        dg[12] = cent[2];
     } else {
         const double ixo = s[0] / cent[6], iyo = s[1] / cent[6];
         const double ixi = s[2] / cent[7], iyi = s[3] / cent[7];
+        double* dg = cent + 8;
+        dg[5] = ixo;
+        dg[6] = iyo;
+        dg[7] = s[4];
+        dg[13] = ixi;
+        dg[14] = iyi;
+        dg[15] = s[5];
         result[0] = (sqrt(iyo) - sqrt(ixo)) / (sqrt(iyo) + sqrt(ixo));
         result[1] = (sqrt(iyi) - sqrt(ixi)) / (sqrt(iyi) + sqrt(ixi));
         result[2] = cent[4];
@@ -391,21 +269,6 @@ void launch_init_droplet(T* dist, int nx, int ny, int pitch, double xc, double y
 template <typename T>
 void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s) {
     hipLaunchKernelGGL(k_phase<T>, grid2(P.nx, P.ny), dim3(BX, BY), 0, s, dist, phi, P);
-}
-
-template <typename T>
-void launch_sor_sweep(T* psi, const T* mur, const StepConst<T>& P, T omega, hipStream_t s) {
-    const dim3 g = grid2((P.nx + 1) / 2, (P.ny + 1) / 2);
-    for (int c = 0; c < 4; ++c) hipLaunchKernelGGL(k_sor_colour<T>, g, dim3(BX, BY), 0, s, psi, mur, P, c, omega);
-}
-
-template <typename T>
-void launch_residual(const T* psi, const T* mur, const StepConst<T>& P, unsigned long long* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, out, 1LL, 0ULL);
-    const long long n = (long long)P.nx * P.ny;
-    long long blocks = (n + RES_T - 1) / RES_T;
-    if (blocks > RES_MAX_BLOCKS) blocks = RES_MAX_BLOCKS;
-    hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)blocks), dim3(RES_T), 0, s, psi, mur, P, out);
 }
 
 template <typename T>
@@ -450,8 +313,6 @@ void launch_diagnostics(const T* phi, const StepConst<T>& P, double* rows, doubl
     template void launch_init_droplet<T>(T*, int, int, int, double, double, double, double, double, double,     \
                                          hipStream_t);                                                           \
     template void launch_phase<T>(const T*, T*, const StepConst<T>&, hipStream_t);                               \
-    template void launch_sor_sweep<T>(T*, const T*, const StepConst<T>&, T, hipStream_t);                        \
-    template void launch_residual<T>(const T*, const T*, const StepConst<T>&, unsigned long long*, hipStream_t); \
     template void launch_collide_stream<T>(const T*, T*, const T*, const T*, const StepConst<T>&, hipStream_t);  \
     template void launch_moments<T>(const T*, const T*, const T*, const StepConst<T>&, unsigned, double*,        \
                                     hipStream_t);                                                                \
@@ -462,5 +323,6 @@ void launch_diagnostics(const T* phi, const StepConst<T>& P, double* rows, doubl
 
 FCD_INSTANTIATE(double)
 FCD_INSTANTIATE(float)
+template void launch_fill<int>(int*, long long, int, hipStream_t);
 
 }  // namespace fcd

@@ -15,10 +15,23 @@ void launch_init_droplet(T* dist, int nx, int ny, int pitch, double xc, double y
                          double u_scale, hipStream_t s);
 template <typename T>
 void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s);
+// Potential solve (fcd_potential.hip).
 template <typename T>
-void launch_sor_sweep(T* psi, const T* mur, const StepConst<T>& P, T omega, hipStream_t s);
+void launch_pot_sweep(const PotLevel<T>& L, T omega, hipStream_t s);
 template <typename T>
-void launch_residual(const T* psi, const T* mur, const StepConst<T>& P, unsigned long long* out, hipStream_t s);
+void launch_pot_residual(const PotLevel<T>& L, unsigned long long* out, hipStream_t s);
+template <typename T>
+void launch_mg_restrict_mu(const T* muf, int pitchf, T* muc, int nxc, int nyc, int pitchc, hipStream_t s);
+template <typename T>
+void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hipStream_t s);
+template <typename T>
+void launch_mg_prolong(const PotLevel<T>& C, const PotLevel<T>& F, hipStream_t s);
+template <typename T>
+size_t mg_coarse_lds_bytes(int nx, int ny);
+template <typename T>
+void launch_mg_coarse_solve(const PotLevel<T>& L, int iters, T omega, hipStream_t s);
+template <typename T>
+void launch_psi_history(T* psi, T* prev, int nx, int ny, int pitch, int mode, hipStream_t s);
 template <typename T>
 void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P, hipStream_t s);
 template <typename T>

@@ -1,0 +1,67 @@
+// fcd_potential.hpp -- per-node evaluation of the potential operator on one level
+// (shared by the single-channel and batched solvers).  See fcd_potential.hip for the
+// discretisation and the wall rule.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "fcd_device.hpp"
+
+namespace fcd {
+
+template <typename T>
+struct MgEval {
+    T C;      // sum of the coefficients
+    T acc;    // sum c_a u(x+e_a), ghost rows by the kappa rule
+    T cself;  // kappa * c of the ghost that mirrors this node itself (edge rows)
+    T rhs;    // right-hand side
+};
+
+template <typename T>
+__device__ __forceinline__ MgEval<T> mg_eval(const PotLevel<T>& L, int i, int j) {
+    const NbIdx x = nb_index(i, j, L.nx, L.ny, L.pitch);
+    const Nb9<T> m = load_nb(L.mu, x);
+    Nb9<T> u = load_nb(static_cast<const T*>(L.u), x);  // rows clamped to the edge rows
+    const T k = L.kappa;
+    if (j == 0) {
+        u.s = -k * u.s;
+        u.sw = -k * u.sw;
+        u.se = -k * u.se;
+    }
+    if (j == L.ny - 1) {
+        u.n = -k * u.n;
+        u.ne = -k * u.ne;
+        u.nw = -k * u.nw;
+    }
+    const T a = L.inv_h2 * (T(1) / T(3)), d = L.inv_h2 * (T(1) / T(12));
+    const T ce = a * (m.c + m.e), cw = a * (m.c + m.w), cn = a * (m.c + m.n), cs = a * (m.c + m.s);
+    const T cne = d * (m.c + m.ne), cnw = d * (m.c + m.nw), csw = d * (m.c + m.sw), cse = d * (m.c + m.se);
+    MgEval<T> r;
+    r.C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
+    r.acc = ((ce * u.e + cw * u.w) + (cn * u.n + cs * u.s)) + ((cne * u.ne + csw * u.sw) + (cnw * u.nw + cse * u.se));
+    r.cself = (j == 0 ? k * cs : T(0)) + (j == L.ny - 1 ? k * cn : T(0));
+    if (L.f) {
+        r.rhs = L.f[(long long)j * L.pitch + i];
+    } else {
+        const T sx = (ce - cw) + (cne - csw) + (cse - cnw);
+        const T sy = (cn - cs) + (cne - csw) + (cnw - cse);
+        r.rhs = L.H0x * sx + L.H0y * sy;
+    }
+    return r;
+}
+
+// One colour of a Gauss-Seidel / SOR sweep: u <- u + omega (u_GS - u), with the
+// node's own ghost image taken implicitly.
+template <typename T>
+__device__ __forceinline__ void relax_node(const PotLevel<T>& L, int i, int j, T omega) {
+    const MgEval<T> r = mg_eval(L, i, j);
+    const long long k = (long long)j * L.pitch + i;
+    const T old = L.u[k];
+    const T gs = (r.acc + r.cself * old - r.rhs) / (r.C + r.cself);
+    L.u[k] = old + omega * (gs - old);
+}
+
+__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+}  // namespace fcd

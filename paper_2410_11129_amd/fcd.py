@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libfcd.so")
 FCD_OK, FCD_ERR_ARG, FCD_ERR_HIP, FCD_ERR_OOM = 0, -1, -2, -3
 FCD_ERR_DIVERGED, FCD_ERR_NOT_CONVERGED, FCD_ERR_UNSUPPORTED = -4, -5, -6
 FCD_FP64, FCD_FP32 = 0, 1
+FCD_SOLVER_SOR, FCD_SOLVER_MG = 0, 1
 
 FCD_M_PSTAR, FCD_M_UX, FCD_M_UY = 1 << 0, 1 << 1, 1 << 2
 FCD_M_PHI1, FCD_M_PHI2, FCD_M_PHI3 = 1 << 3, 1 << 4, 1 << 5
@@ -27,9 +28,12 @@ EXPORTS = (
     "fcd_scratch_bytes", "fcd_create", "fcd_set_params", "fcd_init_compound_droplet",
     "fcd_init_fields", "fcd_solve_potential", "fcd_step", "fcd_read_moments", "fcd_read_state",
     "fcd_write_state", "fcd_read_psi", "fcd_write_psi", "fcd_deformation", "fcd_stats", "fcd_timing",
-    "fcd_timing_read", "fcd_sync", "fcd_destroy", "fcd_last_error",
+    "fcd_timing_read", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
+    "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
+    "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
+    "fcd_batch_read_moments", "fcd_batch_stats", "fcd_batch_destroy",
 )
-TIMING_KINDS = ("collide_stream", "sor_sweep", "residual", "phase")
+TIMING_KINDS = ("collide_stream", "potential_iter", "residual", "phase")
 
 
 class fcd_lattice(C.Structure):
@@ -43,8 +47,9 @@ class fcd_params(C.Structure):
         ("eta", C.c_double), ("xi", C.c_double), ("mobility", C.c_double),
         ("H0", C.c_double), ("alpha", C.c_double), ("mu0", C.c_double),
         ("drive_G", C.c_double), ("grav_x", C.c_double), ("grav_y", C.c_double),
-        ("eps_n", C.c_double), ("sor_omega", C.c_double), ("sor_tol", C.c_double),
-        ("sor_check_every", C.c_int32), ("sor_max_sweeps", C.c_int32),
+        ("eps_n", C.c_double), ("pot_tol", C.c_double), ("pot_omega", C.c_double),
+        ("pot_solver", C.c_int32), ("pot_check_every", C.c_int32), ("pot_max_iters", C.c_int32),
+        ("pot_smooth", C.c_int32), ("pot_coarse_sweeps", C.c_int32), ("pot_extrapolate", C.c_int32),
     ]
 
 
@@ -92,10 +97,24 @@ def lib():
         L.fcd_timing_read.argtypes = [H, dp]
         L.fcd_sync.argtypes = [H]
         L.fcd_destroy.argtypes = [H]
+        L.fcd_adjoint_bytes.argtypes = [C.POINTER(fcd_lattice), C.c_int32, C.c_int32]
+        L.fcd_adjoint_bytes.restype = C.c_size_t
+        L.fcd_adjoint_forward.argtypes = [H, C.c_int32, C.c_int32, C.c_void_p, dp]
+        L.fcd_adjoint_backward.argtypes = [H, dp, dp]
+        L.fcd_batch_sizes.argtypes = [C.c_int32, C.POINTER(fcd_lattice), C.POINTER(C.c_size_t)]
+        L.fcd_batch_create.argtypes = [C.c_int32, C.POINTER(fcd_lattice), C.POINTER(fcd_params), C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
+        L.fcd_batch_init_compound_droplet.argtypes = [H, dp]
+        L.fcd_batch_step.argtypes = [H, C.c_int32]
+        L.fcd_batch_deformation.argtypes = [H, dp]
+        L.fcd_batch_read_state.argtypes = [H, C.c_int32, C.c_void_p]
+        L.fcd_batch_read_moments.argtypes = [H, C.c_int32, C.c_uint32, C.c_void_p]
+        L.fcd_batch_stats.argtypes = [H, dp]
+        L.fcd_batch_destroy.argtypes = [H]
         L.fcd_last_error.argtypes = []
         L.fcd_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("fcd_scratch_bytes", "fcd_last_error"):
+            if name not in ("fcd_scratch_bytes", "fcd_last_error", "fcd_adjoint_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -134,10 +153,10 @@ def fcd_init_fields(h, phi1: int, phi2: int, ux: int, uy: int, pstar: int | None
     _check(lib().fcd_init_fields(h, phi1, phi2, ux, uy, pstar), "fcd_init_fields")
 
 
-def fcd_solve_potential(h, tol: float, max_sweeps: int, allow_not_converged: bool = False):
+def fcd_solve_potential(h, tol: float, max_iters: int, allow_not_converged: bool = False):
     sw = C.c_int32(0)
     res = C.c_double(0.0)
-    st = lib().fcd_solve_potential(h, tol, max_sweeps, C.byref(sw), C.byref(res))
+    st = lib().fcd_solve_potential(h, tol, max_iters, C.byref(sw), C.byref(res))
     _check(st, "fcd_solve_potential", (FCD_ERR_NOT_CONVERGED,) if allow_not_converged else ())
     return st, sw.value, res.value
 
@@ -195,3 +214,69 @@ def fcd_sync(h):
 
 def fcd_destroy(h):
     _check(lib().fcd_destroy(h), "fcd_destroy")
+
+
+def fcd_batch_sizes(lats) -> tuple:
+    arr = (fcd_lattice * len(lats))(*lats)
+    out = (C.c_size_t * 3)()
+    _check(lib().fcd_batch_sizes(len(lats), arr, out), "fcd_batch_sizes")
+    return tuple(out)
+
+
+def fcd_batch_create(lats, prms, state: int, aux: int, scratch: int, stream: int) -> C.c_void_p:
+    la = (fcd_lattice * len(lats))(*lats)
+    pa = (fcd_params * len(prms))(*prms)
+    b = C.c_void_p()
+    _check(lib().fcd_batch_create(len(lats), la, pa, C.c_void_p(state), C.c_void_p(aux), C.c_void_p(scratch),
+                                  C.c_void_p(stream), C.byref(b)), "fcd_batch_create")
+    return b
+
+
+def fcd_batch_init_compound_droplet(b, geom):
+    g = (C.c_double * len(geom))(*geom)
+    _check(lib().fcd_batch_init_compound_droplet(b, g), "fcd_batch_init_compound_droplet")
+
+
+def fcd_batch_step(b, nsteps: int):
+    _check(lib().fcd_batch_step(b, int(nsteps)), "fcd_batch_step")
+
+
+def fcd_batch_deformation(b, n: int):
+    out = (C.c_double * (4 * n))()
+    _check(lib().fcd_batch_deformation(b, out), "fcd_batch_deformation")
+    return [list(out[4 * k:4 * k + 4]) for k in range(n)]
+
+
+def fcd_batch_read_state(b, k: int, out: int):
+    _check(lib().fcd_batch_read_state(b, k, out), "fcd_batch_read_state")
+
+
+def fcd_batch_read_moments(b, k: int, mask: int, out: int):
+    _check(lib().fcd_batch_read_moments(b, k, mask, out), "fcd_batch_read_moments")
+
+
+def fcd_batch_stats(b):
+    out = (C.c_double * 3)()
+    _check(lib().fcd_batch_stats(b, out), "fcd_batch_stats")
+    return list(out)
+
+
+def fcd_batch_destroy(b):
+    _check(lib().fcd_batch_destroy(b), "fcd_batch_destroy")
+
+
+def fcd_adjoint_bytes(lat: fcd_lattice, nsteps: int, ckpt_every: int) -> int:
+    return lib().fcd_adjoint_bytes(C.byref(lat), nsteps, ckpt_every)
+
+
+def fcd_adjoint_forward(h, nsteps: int, ckpt_every: int, work: int):
+    out = (C.c_double * 2)()
+    _check(lib().fcd_adjoint_forward(h, nsteps, ckpt_every, C.c_void_p(work), out), "fcd_adjoint_forward")
+    return list(out)
+
+
+def fcd_adjoint_backward(h, dJ_dD):
+    d = (C.c_double * 2)(*dJ_dD)
+    out = (C.c_double * 6)()
+    _check(lib().fcd_adjoint_backward(h, d, out), "fcd_adjoint_backward")
+    return list(out)

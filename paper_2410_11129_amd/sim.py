@@ -8,8 +8,9 @@ import torch
 from . import fcd
 
 
-def make_params(w, sor_omega: float = 0.0, sor_tol: float = 1e-10, sor_check_every: int = 8,
-                sor_max_sweeps: int = 200000) -> fcd.fcd_params:
+def make_params(w, solver: int = fcd.FCD_SOLVER_MG, tol: float = 1e-10, omega: float = 0.0,
+                check_every: int = 1, max_iters: int = 100000, smooth: int = 1, coarse_sweeps: int = 8,
+                extrapolate: int = 1) -> fcd.fcd_params:
     """fcd_params from a workload description (any object with the workload fields)."""
     p = fcd.fcd_params()
     for k in range(3):
@@ -17,8 +18,9 @@ def make_params(w, sor_omega: float = 0.0, sor_tol: float = 1e-10, sor_check_eve
     p.sigma12, p.sigma13, p.sigma23, p.eta = w.sigma12, w.sigma13, w.sigma23, w.eta
     p.xi, p.mobility, p.H0, p.alpha, p.mu0 = w.xi, w.mobility, w.H0, w.alpha, w.mu0
     p.drive_G, p.grav_x, p.grav_y, p.eps_n = w.drive_G, w.grav[0], w.grav[1], w.eps_n
-    p.sor_omega, p.sor_tol = sor_omega, sor_tol
-    p.sor_check_every, p.sor_max_sweeps = sor_check_every, sor_max_sweeps
+    p.pot_tol, p.pot_omega, p.pot_solver = tol, omega, solver
+    p.pot_check_every, p.pot_max_iters = check_every, max_iters
+    p.pot_smooth, p.pot_coarse_sweeps, p.pot_extrapolate = smooth, coarse_sweeps, extrapolate
     return p
 
 
@@ -83,8 +85,8 @@ class Channel:
         fcd.fcd_set_params(self.h, self.prm)
 
     # --- work ------------------------------------------------------------------
-    def solve_potential(self, tol: float, max_sweeps: int = 200000):
-        return fcd.fcd_solve_potential(self.h, tol, max_sweeps)
+    def solve_potential(self, tol: float, max_iters: int = 200000):
+        return fcd.fcd_solve_potential(self.h, tol, max_iters)
 
     def step(self, n: int):
         fcd.fcd_step(self.h, n)
@@ -123,3 +125,65 @@ class Channel:
 
     def sync(self):
         fcd.fcd_sync(self.h)
+
+
+class Batch:
+    """Many channels stepped together; device buffers owned here (torch)."""
+
+    def __init__(self, workloads, precision: int = fcd.FCD_FP32, device: str = "cuda:0",
+                 stream: torch.cuda.Stream | None = None, **solver):
+        self.ws = list(workloads)
+        self.n = len(self.ws)
+        self.device = torch.device(device)
+        self.lats = [fcd.fcd_lattice(w.nx, w.ny, precision, w.nx) for w in self.ws]
+        solver.setdefault("solver", fcd.FCD_SOLVER_SOR)
+        solver.setdefault("check_every", 1)
+        self.prms = [make_params(w, **solver) for w in self.ws]
+        sizes = fcd.fcd_batch_sizes(self.lats)
+        self.bufs = [torch.zeros((max(int(b), 8) + 255) // 256 * 256 // 8, dtype=torch.float64, device=self.device)
+                     for b in sizes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = fcd.fcd_batch_create(self.lats, self.prms, *[b.data_ptr() for b in self.bufs],
+                                      self.stream.cuda_stream)
+
+    def close(self):
+        if self.h is not None:
+            fcd.fcd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_droplets(self):
+        geom = []
+        for w in self.ws:
+            geom += [w.xc, w.yc, w.r_core, w.r_shell]
+        fcd.fcd_batch_init_compound_droplet(self.h, geom)
+
+    def step(self, n: int):
+        fcd.fcd_batch_step(self.h, n)
+
+    def deformation(self):
+        return fcd.fcd_batch_deformation(self.h, self.n)
+
+    def state(self, k: int):
+        w = self.ws[k]
+        out = torch.empty((27, w.ny, w.nx), dtype=torch.float64, device=self.device)
+        fcd.fcd_batch_read_state(self.h, k, out.data_ptr())
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def moments(self, k: int, mask: int = fcd.FCD_M_ALL) -> dict:
+        w = self.ws[k]
+        names = [nm for q, nm in enumerate(fcd.MOMENT_NAMES) if mask & (1 << q)]
+        out = torch.empty((len(names), w.ny, w.nx), dtype=torch.float64, device=self.device)
+        fcd.fcd_batch_read_moments(self.h, k, mask, out.data_ptr())
+        self.stream.synchronize()
+        host = out.cpu().numpy()
+        return {nm: host[i] for i, nm in enumerate(names)}
+
+    def stats(self):
+        return fcd.fcd_batch_stats(self.h)

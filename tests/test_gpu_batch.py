@@ -1,0 +1,94 @@
+"""Batched channels (one launch per kernel for all channels) vs each channel run alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from fcd_inputs import Workload, channel_drive, random_phase_fields, regime_sweep_batch, single_channel_small
+from oracle import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2410_11129_amd import fcd  # noqa: E402
+from paper_2410_11129_amd.sim import Batch, Channel  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def uneven_channels():
+    """Three channels of different size, parameters and field (one without field)."""
+    a = single_channel_small().replace(name="a", nx=100, ny=22, xc=30.0, yc=10.5, r_core=3.0, r_shell=7.0,
+                                       drive_G=channel_drive(0.01, 1.0, 0.8, 22))
+    b = Workload(name="b", nx=64, ny=16, rho=(2.0, 1.0, 1.0), tau=(1.0, 0.25, 0.25), chi=(2.0, 0.0, 0.0),
+                 sigma12=0.008, sigma13=0.01, sigma23=0.012, xi=4.0, H0=0.0, alpha=0.0,
+                 drive_G=channel_drive(0.01, 1.0, 0.25, 16), xc=20.0, yc=7.5, r_core=3.0, r_shell=6.0)
+    c = single_channel_small().replace(name="c", nx=130, ny=41, xc=60.0, yc=20.0, r_core=5.0, r_shell=11.0,
+                                       alpha=1.1, drive_G=channel_drive(0.01, 1.0, 0.8, 41))
+    return [a, b, c]
+
+
+def test_batch_channels_match_oracle_fp64():
+    ws = uneven_channels()
+    say("case batch fp64 3 uneven channels vs oracle")
+    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-12)
+    bt.init_droplets()
+    bt.step(30)
+    dg = bt.deformation()
+    for k, w in enumerate(ws):
+        s = OracleSim(w)
+        s.init_droplet(solve=False)
+        assert s.step(30) == 0
+        ref = np.concatenate([s.f, s.g1, s.g2])
+        assert np.abs(bt.state(k) - ref).max() < 1e-11, w.name
+        m, om = bt.moments(k), s.moments()
+        for key in om:
+            assert np.abs(m[key] - om[key]).max() < 1e-11, (w.name, key)
+        od = s.diagnostics()
+        assert abs(dg[k][0] - od[0]) < 1e-11 and abs(dg[k][1] - od[1]) < 1e-11
+
+
+def test_batch_fp32_regime_channels_track_fp64():
+    """Six channels of the regime sweep in FP32 follow the single-channel FP64 path."""
+    ws = [w.replace(steps=200) for w in regime_sweep_batch()[::11]]
+    say(f"case batch fp32 regime subset sizes {[(w.nx, w.ny) for w in ws]}")
+    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
+    bt.init_droplets()
+    bt.step(200)
+    dg = bt.deformation()
+    for k, w in enumerate(ws):
+        g = Channel(w, tol=1e-10)
+        g.init_droplet()
+        g.step(200)
+        m32, m64 = bt.moments(k), g.moments()
+        for key in ("phi1", "phi2", "phi3"):
+            assert np.abs(m32[key] - m64[key]).max() < 1e-4, (w.name, key)
+        d64 = g.deformation()
+        assert abs(dg[k][0] - d64[0]) < 1e-3 and abs(dg[k][1] - d64[1]) < 1e-3
+        assert abs(dg[k][2] - d64[2]) < 1e-4 * d64[2]
+        g.close()
+
+
+def test_batch_deterministic_and_single_channel_batch():
+    ws = uneven_channels()
+    say("case batch determinism")
+    out = []
+    for _ in range(2):
+        bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
+        bt.init_droplets()
+        bt.step(20)
+        out.append([bt.state(k) for k in range(len(ws))])
+        bt.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    # a batch of one equals the same batch entry
+    one = Batch([ws[2]], precision=fcd.FCD_FP32, tol=1e-5)
+    one.init_droplets()
+    one.step(20)
+    assert np.abs(one.state(0) - out[0][2]).max() < 1e-5

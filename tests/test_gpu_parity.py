@@ -24,8 +24,10 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU containers
 from paper_2410_11129_amd import fcd  # noqa: E402
 from paper_2410_11129_amd.sim import Channel  # noqa: E402
 
-TIGHT = dict(sor_omega=0.0, sor_tol=1e-12, sor_check_every=8, sor_max_sweeps=500000)
-FP32_SOLVE = dict(sor_omega=0.0, sor_tol=1e-5, sor_check_every=8, sor_max_sweeps=500000)
+SOR_TIGHT = dict(solver=fcd.FCD_SOLVER_SOR, tol=1e-12, omega=0.0, check_every=8, max_iters=500000)
+MG_TIGHT = dict(solver=fcd.FCD_SOLVER_MG, tol=1e-12, check_every=1, max_iters=1000)
+TIGHT = SOR_TIGHT
+FP32_SOLVE = dict(solver=fcd.FCD_SOLVER_MG, tol=1e-5, check_every=1, max_iters=1000)
 
 
 def say(msg):
@@ -66,11 +68,12 @@ def test_init_fields_parity_ragged_pitch():
     assert np.abs(g.state() - oracle_state(s)).max() < 1e-15
 
 
-def test_potential_parity():
+@pytest.mark.parametrize("solver", ["sor", "mg"])
+def test_potential_parity(solver):
     w = ragged_workload()
-    say("case potential ragged 100x22")
+    say(f"case potential ragged 100x22 solver={solver}")
     fields = random_phase_fields(w.nx, w.ny, seed=12)
-    g = Channel(w, **TIGHT)
+    g = Channel(w, **(SOR_TIGHT if solver == "sor" else MG_TIGHT))
     g.init_fields(*fields)
     st, sweeps, res = g.solve_potential(1e-13)
     assert st == fcd.FCD_OK and res <= 1e-13 * w.H0 and sweeps > 0
@@ -109,11 +112,12 @@ def test_short_run_parity_ragged(contrast):
     assert np.abs(g.psi_dense() - s.psi).max() < 1e-11
 
 
-def test_channel_200x50_1000_steps_fp64():
+@pytest.mark.parametrize("solver", ["sor", "mg"])
+def test_channel_200x50_1000_steps_fp64(solver):
     """The 200 x 50 ferrofluid-shell channel: every field within 1e-10 after 1000 steps."""
     w = single_channel_small(steps=1000)
-    say("case channel 200x50 fp64 1000 steps")
-    g = Channel(w, **TIGHT)
+    say(f"case channel 200x50 fp64 1000 steps solver={solver}")
+    g = Channel(w, **(SOR_TIGHT if solver == "sor" else MG_TIGHT))
     g.init_droplet()
     g.step(w.steps)
     s = OracleSim(w)
@@ -168,12 +172,15 @@ def test_no_field_gives_zero_potential():
     assert np.abs(g.state() - oracle_state(s)).max() < 1e-13
 
 
-@pytest.mark.parametrize("nx,ny", [(4, 2), (6, 3), (130, 5)])
-def test_degenerate_lattices(nx, ny):
+@pytest.mark.parametrize("nx,ny,solver", [(4, 2, "sor"), (6, 3, "sor"), (130, 5, "sor"), (4, 2, "mg"),
+                                          (130, 5, "mg"), (256, 96, "mg"), (200, 97, "mg")])
+def test_degenerate_lattices(nx, ny, solver):
+    """Smallest lattices, odd ny (no coarsening possible) and a multigrid hierarchy that
+    stops on an odd coarse level (96 -> 48 -> 24 -> ... ) against the oracle."""
     w = ragged_workload(nx=nx, ny=ny, drive_G=channel_drive(0.01, 1.0, 0.8, ny))
-    say(f"case degenerate {nx}x{ny}")
+    say(f"case degenerate {nx}x{ny} solver={solver}")
     fields = random_phase_fields(nx, ny, seed=15)
-    g = Channel(w, **TIGHT)
+    g = Channel(w, **(SOR_TIGHT if solver == "sor" else MG_TIGHT))
     g.init_fields(*fields)
     g.step(10)
     s = OracleSim(w)
@@ -236,7 +243,7 @@ def test_full_size_with_field_properties():
     ~(ny/pi)^2 / 2 gives ~1e-6 H0 on psi' ~ 20 H0, i.e. ~1e-7 relative."""
     w = single_channel_large(bond=4.0)
     say("case full size 2048x512 Bo=4 properties")
-    g = Channel(w, sor_omega=0.0, sor_tol=1e-10, sor_check_every=16, sor_max_sweeps=2000000)
+    g = Channel(w, solver=fcd.FCD_SOLVER_MG, tol=1e-10, check_every=1, max_iters=1000)
     g.init_droplet()
     d0 = g.deformation()
     g.step(10)
