@@ -163,6 +163,10 @@ struct fcd_handle {
     // checkpointed adjoint: set by fcd_adjoint_forward, used by fcd_adjoint_backward
     char* adj_work;
     int adj_nsteps, adj_every, adj_from_init;
+    // last_iters at each checkpoint and at the end, so that a recomputed segment repeats
+    // the forward's solves exactly
+    std::vector<int> adj_ckpt_iters;
+    int adj_final_iters;
     MgPlan plan;
     Timer timer;
 };
@@ -905,17 +909,22 @@ fcd_status adj_forward_impl(fcd_handle* h, int nsteps, int every, char* work, do
     h->adj_nsteps = nsteps;
     h->adj_every = every;
     h->adj_from_init = h->init_fresh;
+    h->adj_ckpt_iters.assign(L.nseg, 0);
     const int saved_extrap = h->prm.pot_extrapolate;
     h->prm.pot_extrapolate = 0;  // the recomputation must be able to replay every solve
     fcd_status st = FCD_OK;
     for (int t = 0; t < nsteps && !st; ++t) {
-        if (t % every == 0) st = save_record<T>(h, work + L.off_ckpt + (size_t)(t / every) * L.rec, L.state);
+        if (t % every == 0) {
+            st = save_record<T>(h, work + L.off_ckpt + (size_t)(t / every) * L.rec, L.state);
+            h->adj_ckpt_iters[t / every] = h->last_iters;
+        }
         if (!st) st = step_impl<T>(h, 1);
     }
     h->prm.pot_extrapolate = saved_extrap;
     if (st) return st;
     st = save_record<T>(h, work + L.off_final, L.state);
     if (st) return st;
+    h->adj_final_iters = h->last_iters;
     double d[4];
     st = diag_impl<T>(h, d);
     if (st) return st;
@@ -961,6 +970,7 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
         const int t0 = seg * every, t1 = std::min(nsteps, t0 + every);
         st = load_record<T>(h, w + L.off_ckpt + (size_t)seg * L.rec, L.state);
         if (st) break;
+        h->last_iters = h->adj_ckpt_iters[seg];
         for (int t = t0; t < t1 && !st; ++t) {
             char* rec = w + L.off_seg + (size_t)(t - t0) * L.rec;
             st = dcopy(rec, h->buf.dist[h->cur], L.state, h->stream);
@@ -1038,6 +1048,7 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
     grad[4] = a[4] + gb[0] - gb[1] + gb[2];
     grad[5] = a[5] - gb[0] + gb[1] + gb[2];
     // leave the handle on the forward's final state
+    h->last_iters = h->adj_final_iters;
     return load_record<T>(h, w + L.off_final, L.state);
 }
 
@@ -1082,8 +1093,9 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     h->init_fresh = 0;
     h->adj_work = nullptr;
     h->adj_nsteps = h->adj_every = h->adj_from_init = 0;
+    h->adj_final_iters = 0;
     h->plan = make_plan(*lat);
-    if (hipHostMalloc(reinterpret_cast<void**>(&h->host), 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->host), 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete h;
         return fail(FCD_ERR_OOM, "pinned host allocation failed");
     }

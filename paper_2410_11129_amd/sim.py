@@ -41,6 +41,7 @@ class Channel:
         esz = 8 if precision == fcd.FCD_FP64 else 4
         self.pitch = pitch if pitch is not None else padded_pitch(w.nx, esz)
         self.lat = fcd.fcd_lattice(w.nx, w.ny, precision, self.pitch)
+        self.solver = dict(solver)
         self.prm = make_params(w, **solver)
         ny, P = w.ny, self.pitch
         self.dist = [torch.zeros((27, ny, P), dtype=self.dtype, device=self.device) for _ in range(2)]
@@ -81,8 +82,17 @@ class Channel:
         self.stream.synchronize()
 
     def set_params(self, **solver):
-        self.prm = make_params(self.w, **solver)
+        if solver:
+            self.solver = dict(solver)
+        self.prm = make_params(self.w, **self.solver)
         fcd.fcd_set_params(self.h, self.prm)
+
+    def set_workload(self, w):
+        """Change materials, field and drive (same lattice); keeps the solver settings."""
+        if (w.nx, w.ny) != (self.w.nx, self.w.ny):
+            raise ValueError("set_workload cannot change the lattice size")
+        self.w = w
+        self.set_params()
 
     # --- work ------------------------------------------------------------------
     def solve_potential(self, tol: float, max_iters: int = 200000):
