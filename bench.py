@@ -24,16 +24,20 @@ METRIC = "MLUPS + HBM GB/s of coupled step; batched instances/hr; adjoint/forwar
 
 
 
-def values_per_site(solver: str, smooth: int) -> dict:
-    """Algorithmic device traffic per lattice site and timed unit, in values of the working
-    precision.  collide_stream reads 27 distributions + phi1, phi2, psi' and writes 27.
-    One potential iteration is an SOR sweep (read mu_r, psi'; write psi') or a multigrid
-    V(nu, nu)-cycle: on each level 2 nu sweeps of 3 values, a residual restriction
-    (mu_r, psi' read) and a prolongation (psi' read and written), the coarser levels adding
-    1/4 + 1/16 + ... = 1/3.  The residual test reads mu_r and psi'.  phase reads 18
-    distributions and writes phi1, phi2, mu_r."""
-    it = 3.0 if solver == "sor" else (6.0 * smooth + 4.0) * 4.0 / 3.0
-    return {"collide_stream": 57.0, "potential_iter": it, "residual": 2.0, "phase": 21.0}
+def values_per_site(solver: str) -> dict:
+    """Algorithmic device traffic per lattice site of one launch of each single-kernel
+    timing class, in values of the working precision.  collide_stream reads 27
+    distributions + phi1, phi2, psi' and writes 27; phase reads 18 distributions and writes
+    phi1, phi2, mu_r; the finest-level tile smoother reads psi' and mu_r and writes psi'
+    (its right-hand side is formed from H0 and mu_r in registers); the fused prolongation +
+    post-smoothing also reads the coarse correction (a quarter plane).  An SOR sweep reads
+    mu_r and psi' and writes psi'.  Composite classes (a V-cycle, a convergence test) have
+    no single-kernel figure."""
+    v = {"collide_stream": 57.0, "phase": 21.0, "mg_smooth0": 3.0, "mg_post0": 3.25}
+    if solver == "sor":
+        v["potential_iter"] = 3.0
+        v["residual"] = 2.0
+    return v
 
 
 def log(msg: str) -> None:
@@ -101,6 +105,43 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
             "sample": f"batch: {steps} timed steps; sequential: {seq_steps} timed steps per channel"}
 
 
+def adjoint_ratio(torch, steps: int, every: int) -> dict:
+    """Cost of the checkpointed gradient on the 512 x 128 channel (shell mu_r = 2, field at
+    30 degrees, Bo_m = 1), FP64: plain forward of `steps` steps, then the checkpointing
+    forward and the reverse sweep (which recomputes every segment) of the same run."""
+    from fcd_inputs import adjoint_channel
+    from paper_2410_11129_amd import fcd
+    from paper_2410_11129_amd.adjoint import AdjointRun, theta_of
+    from paper_2410_11129_amd.sim import Channel
+    w = adjoint_channel(steps=steps)
+    ch = Channel(w, tol=1e-10)
+    ch.init_droplet()
+    ch.step(20)  # warm-up
+    ch.init_droplet()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ch.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    run = AdjointRun(ch, steps, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    D = run.forward(theta_of(w))
+    torch.cuda.synchronize()
+    t_cfwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = run.backward([1.0, 0.0])
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    nbytes = run.work.numel()
+    ch.close()
+    return {"workload": f"{w.name}_fp64", "steps": steps, "ckpt_every": every,
+            "forward_s": round(t_fwd, 4), "checkpointed_forward_s": round(t_cfwd, 4), "backward_s": round(t_bwd, 4),
+            "adjoint_forward_ratio": round((t_cfwd + t_bwd) / t_fwd, 3),
+            "backward_forward_ratio": round(t_bwd / t_fwd, 3), "work_MB": round(nbytes / 1e6, 1),
+            "D_o": D[0], "dDo_dtheta": dict(zip(("H0", "alpha", "u_ref", "sigma12", "sigma13", "sigma23"), g))}
+
+
 def copy_bandwidth_gbs(torch) -> float:
     n = 1 << 28  # 2 GiB of float64 each way
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -127,7 +168,7 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--solver", choices=("mg", "sor"), default="mg")
     ap.add_argument("--smooth", type=int, default=1)
-    ap.add_argument("--coarse-sweeps", type=int, default=8)
+    ap.add_argument("--coarse-sweeps", type=int, default=2)
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--no-extrapolate", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=16)
@@ -135,6 +176,9 @@ def main() -> int:
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--sequential-steps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-ckpt", type=int, default=100)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -177,18 +221,18 @@ def main() -> int:
         f"D_o={d[0]:.5f} D_i={d[1]:.5f}; timing {timing}")
 
     sites = w.sites
-    VALUES_PER_SITE = values_per_site(args.solver, args.smooth)
+    VALUES_PER_SITE = values_per_site(args.solver)
     mlups = sites * args.steps / dt / 1e6
     per_kind = {}
     for k, (ms, n) in timing.items():
         if n == 0:
             continue
-        bytes_per_launch = VALUES_PER_SITE[k] * esz * sites
         avg_s = ms / n / 1e3
-        per_kind[k] = {"launches": n, "avg_us": round(avg_s * 1e6, 3), "ms_per_step": round(ms / args.steps, 4),
-                       "GBps": round(bytes_per_launch / avg_s / 1e9, 1)}
-    dom = max(per_kind, key=lambda k: timing[k][0])
-    step_bytes = sum(VALUES_PER_SITE[k] * esz * sites * timing[k][1] for k in per_kind) / args.steps
+        per_kind[k] = {"launches": n, "avg_us": round(avg_s * 1e6, 3), "ms_per_step": round(ms / args.steps, 4)}
+        if k in VALUES_PER_SITE:
+            per_kind[k]["GBps"] = round(VALUES_PER_SITE[k] * esz * sites / avg_s / 1e9, 1)
+    single = [k for k in per_kind if k in VALUES_PER_SITE]
+    dom = max(single, key=lambda k: timing[k][0])
     roof = {"bound": "hbm", "kernel": dom, "achieved": per_kind[dom]["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(per_kind[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": VALUES_PER_SITE[dom] * esz * sites}
@@ -201,7 +245,6 @@ def main() -> int:
                    "bond": args.bond, "potential_solver": args.solver, "potential_tol": tol,
                    "potential_iters_per_step": round(sweeps / args.steps, 2)},
         "roofline": roof,
-        "step_GBps_algorithmic": round(step_bytes / (dt / args.steps) / 1e9, 1),
         "kernels": per_kind,
     }
     try:
@@ -212,6 +255,9 @@ def main() -> int:
     if not args.no_batched:
         out["batched"] = batched_sweep(torch, args.batched_steps, args.sequential_steps)
         log(f"bench: batched {out['batched']}")
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio(torch, args.adjoint_steps, args.adjoint_ckpt)
+        log(f"bench: adjoint {out['adjoint']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -81,7 +81,7 @@ typedef struct {
     int32_t pot_check_every; /* SOR sweeps / multigrid V-cycles between residual tests */
     int32_t pot_max_iters;   /* SOR sweeps / V-cycles allowed per solve */
     int32_t pot_smooth;      /* multigrid: Gauss-Seidel sweeps before and after each coarse correction */
-    int32_t pot_coarse_sweeps; /* multigrid: SOR sweeps on the coarsest level */
+    int32_t pot_coarse_sweeps; /* multigrid: SOR sweeps on the coarsest level, times max(1, ny_c / 2) */
     int32_t pot_extrapolate; /* 1: start each step's solve from 2 psi'(t-1) - psi'(t-2) */
 } fcd_params;
 
@@ -174,12 +174,15 @@ fcd_status fcd_stats(fcd_handle* h, double out[3]);
 /* Per-kernel timing with HIP events recorded on the handle's stream around every
  * launch of the step's kernels.  fcd_timing(h, 1) clears the totals and starts
  * recording; fcd_timing(h, 0) stops.  fcd_timing_read (sync) fills out[2*k] with the
- * total milliseconds and out[2*k+1] with the launch count of kernel class k:
- * 0 fused collide-stream, 1 one potential iteration (a four-colour SOR sweep, or a
- * multigrid V-cycle including its coarse-mu restriction share), 2 potential residual,
- * 3 phase moments.  out must hold 8 doubles. */
+ * total milliseconds and out[2*k+1] with the launch count of class k:
+ * 0 fused collide-stream kernel; 1 one potential iteration (a four-colour SOR sweep,
+ * or the part of a multigrid V-cycle that follows the convergence test);
+ * 2 convergence test (SOR: residual kernel; multigrid: the V-cycle's first smoothing
+ * kernel, which reduces the residual of its input); 3 phase moments; 4 multigrid finest-level pre-smoothing kernel; 5 multigrid finest-level
+ * prolongation + post-smoothing kernel.  Classes 4 and 5 are single kernels, also
+ * counted inside classes 1 and 2.  out must hold 12 doubles. */
 fcd_status fcd_timing(fcd_handle* h, int32_t enable);
-fcd_status fcd_timing_read(fcd_handle* h, double out[8]);
+fcd_status fcd_timing_read(fcd_handle* h, double out[12]);
 
 /* Wait for the stream and report any asynchronous HIP error.  Sync. */
 fcd_status fcd_sync(fcd_handle* h);
@@ -208,7 +211,7 @@ size_t fcd_adjoint_bytes(const fcd_lattice* lat, int32_t nsteps, int32_t ckpt_ev
 
 /* Run nsteps forward steps from the current state, keeping checkpoints in `work`
  * (caller-owned device buffer of fcd_adjoint_bytes, 256-byte aligned); D_out = {D_o, D_i}
- * of the final state.  Sync.  The potential warm start is not extrapolated here. */
+ * of the final state.  Sync. */
 fcd_status fcd_adjoint_forward(fcd_handle* h, int32_t nsteps, int32_t ckpt_every, void* work, double D_out[2]);
 
 /* Gradient of J for the run of the last fcd_adjoint_forward (same `work`, untouched

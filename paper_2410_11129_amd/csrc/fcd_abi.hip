@@ -44,15 +44,17 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Multigrid hierarchy and scratch layout.  Level 0 is the lattice itself (psi', mu_r
 // planes of the caller); coarser levels halve both dimensions while nx is a multiple
-// of 4, ny is even and >= 4, and the level has more than COARSE_NODES nodes.
+// of 4 and ny is even and >= 4.  The coarsest levels whose u, f and mu fit together in
+// TAIL_LDS_MAX bytes form the tail, solved in LDS by one block; every level above the
+// tail has a second plane for the tile smoother's ping-pong.
 constexpr int MAX_LEVELS = 16;
-constexpr long long COARSE_NODES = 1024;
-constexpr size_t COARSE_LDS_MAX = 65536;
+constexpr size_t TAIL_LDS_MAX = 65536;
 
 struct MgPlan {
     int levels;
+    int tail;  // first tail level (== levels: no tail)
     int nx[MAX_LEVELS], ny[MAX_LEVELS], pitch[MAX_LEVELS];
-    size_t off_mu[MAX_LEVELS], off_u[MAX_LEVELS], off_f[MAX_LEVELS];
+    size_t off_mu[MAX_LEVELS], off_u[MAX_LEVELS], off_f[MAX_LEVELS], off_t[MAX_LEVELS];
     size_t off_prev;  // psi' history plane
     size_t bytes;     // total scratch
 };
@@ -64,28 +66,49 @@ MgPlan make_plan(const fcd_lattice& l) {
     p.nx[0] = l.nx;
     p.ny[0] = l.ny;
     p.pitch[0] = l.pitch;
-    size_t off = align256(OFF_ROWS + (size_t)l.ny * 8 * sizeof(double));
-    p.off_prev = off;
-    off += align256((size_t)l.ny * l.pitch * esz);
     while (p.levels < MAX_LEVELS) {
         const int px = p.nx[p.levels - 1], py = p.ny[p.levels - 1];
-        if (px % 4 || py % 2 || py < 4 || (long long)px * py <= COARSE_NODES) break;
+        if (px % 4 || py % 2 || py < 4) break;
         const int L = p.levels++;
         p.nx[L] = px / 2;
         p.ny[L] = py / 2;
         const int per = (int)(256 / esz);
         p.pitch[L] = (p.nx[L] + per - 1) / per * per;
+    }
+    p.tail = p.levels;
+    size_t tail_bytes = 0;
+    for (int L = p.levels - 1; L >= 1 && p.levels - L <= fcd::MG_MAX_TAIL; --L) {
+        const size_t b = 3 * (size_t)p.nx[L] * p.ny[L] * esz;
+        if (tail_bytes + b > TAIL_LDS_MAX) break;
+        tail_bytes += b;
+        p.tail = L;
+    }
+    size_t off = align256(OFF_ROWS + (size_t)l.ny * 8 * sizeof(double));
+    p.off_prev = off;
+    off += align256((size_t)l.ny * l.pitch * esz);
+    for (int L = 0; L < p.levels; ++L) {
         const size_t plane = align256((size_t)p.ny[L] * p.pitch[L] * esz);
-        p.off_mu[L] = off;
-        p.off_u[L] = off + plane;
-        p.off_f[L] = off + 2 * plane;
-        off += 3 * plane;
+        if (L > 0) {
+            p.off_mu[L] = off;
+            p.off_u[L] = off + plane;
+            p.off_f[L] = off + 2 * plane;
+            off += 3 * plane;
+        }
+        if (L < p.tail && p.levels > 1) {
+            p.off_t[L] = off;
+            off += plane;
+        }
     }
     p.bytes = off;
     return p;
 }
 
 }  // namespace
+
+// Timed kernel classes: collide-stream, potential iteration (V-cycle or SOR sweep),
+// convergence test, phase moments, finest-level pre-smoothing and
+// finest-level prolongation + post-smoothing of the multigrid.
+enum { TK_COLLIDE = 0, TK_ITER = 1, TK_RESID = 2, TK_PHASE = 3, TK_SMOOTH0 = 4, TK_POST0 = 5, TK_KINDS = 6 };
 
 // Event pairs bracketing launches, resolved into per-class totals after a sync.
 struct Timer {
@@ -96,8 +119,8 @@ struct Timer {
     bool on = false;
     std::vector<Pair> pending;
     std::vector<hipEvent_t> pool;
-    double ms[4] = {0, 0, 0, 0};
-    double count[4] = {0, 0, 0, 0};
+    double ms[TK_KINDS] = {};
+    double count[TK_KINDS] = {};
 
     hipEvent_t take() {
         if (!pool.empty()) {
@@ -134,7 +157,7 @@ struct Timer {
         pending.clear();
     }
     void clear() {
-        for (int k = 0; k < 4; ++k) ms[k] = count[k] = 0;
+        for (int k = 0; k < TK_KINDS; ++k) ms[k] = count[k] = 0;
     }
     ~Timer() {
         for (const Pair& p : pending) {
@@ -145,7 +168,6 @@ struct Timer {
     }
 };
 
-enum { TK_COLLIDE = 0, TK_ITER = 1, TK_RESID = 2, TK_PHASE = 3 };
 
 struct fcd_handle {
     fcd_lattice lat;
@@ -163,10 +185,10 @@ struct fcd_handle {
     // checkpointed adjoint: set by fcd_adjoint_forward, used by fcd_adjoint_backward
     char* adj_work;
     int adj_nsteps, adj_every, adj_from_init;
-    // last_iters at each checkpoint and at the end, so that a recomputed segment repeats
-    // the forward's solves exactly
+    // last_iters and hist at each checkpoint (pairs) and at the end, so that a recomputed
+    // segment repeats the forward's solves exactly
     std::vector<int> adj_ckpt_iters;
-    int adj_final_iters;
+    int adj_final_iters, adj_final_hist;
     MgPlan plan;
     Timer timer;
 };
@@ -322,38 +344,105 @@ void restrict_mu_all(fcd_handle* h) {
     }
 }
 
-// Solve the coarsest level: in LDS by one block when it fits, else by launched sweeps.
+// SOR sweeps per V-cycle on a coarsest level with ny rows: a few suffice on the two-row
+// levels of a full hierarchy; a hierarchy stopped early needs more on its larger rows.
+int coarse_sweeps(const fcd_handle* h, int ny) { return std::max(1, h->prm.pot_coarse_sweeps) * std::max(1, ny / 2); }
+
+// Solve the coarsest level by launched SOR sweeps (no tail, or no coarse level at all).
 template <typename T>
 void coarse_solve(fcd_handle* h, int l, const fcd::PotLevel<T>& L0) {
     const fcd::PotLevel<T> L = l == 0 ? L0 : pot_level<T>(h, l);
     const T om = T(sor_omega_opt(L.ny));
-    if (l > 0 && fcd::mg_coarse_lds_bytes<T>(L.nx, L.ny) <= COARSE_LDS_MAX) {
-        fcd::launch_mg_coarse_solve<T>(L, h->prm.pot_coarse_sweeps, om, h->stream);
+    for (int s = 0; s < coarse_sweeps(h, L.ny); ++s) fcd::launch_pot_sweep<T>(L, om, h->stream);
+}
+
+// Multigrid V-cycle with tile smoothers.  Level l above the tail keeps its iterate in
+// the level's u plane and uses a second plane t for the smoother's ping-pong; the
+// finest level's mode decides how its right-hand side is formed.
+template <typename T>
+T* mg_temp(fcd_handle* h, int l) {
+    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_t[l]);
+}
+
+template <typename T>
+int fine_mode(const fcd::PotLevel<T>& L0) {
+    return L0.f ? 2 : 1;
+}
+
+// nu1 pre-smoothing sweeps of level l starting from F.u; returns the buffer holding the
+// result.  The first sweep reduces the input's residual into res when res != nullptr.
+template <typename T>
+T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, unsigned long long* res) {
+    T* a = F.u;
+    T* b = mg_temp<T>(h, l);
+    for (int s = 0; s < std::max(1, h->prm.pot_smooth); ++s) {
+        hipEvent_t ev = nullptr;
+        const bool timed = l == 0 && h->timer.begin(h->stream, &ev);
+        fcd::launch_mg_smooth_tile<T>(F, a, b, nullptr, mode, s == 0 ? res : nullptr, h->stream);
+        if (timed) h->timer.end(h->stream, TK_SMOOTH0, ev);
+        std::swap(a, b);
+    }
+    return a;
+}
+
+// Prolongation of level l+1's correction fused with the first of nu2 post-smoothing
+// sweeps, from the pre-smoothed iterate `cur`; the result ends in F.u.
+template <typename T>
+void mg_postsmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, T* cur, const fcd::PotLevel<T>& Cl) {
+    T* other = cur == F.u ? mg_temp<T>(h, l) : F.u;
+    const int nu = std::max(1, h->prm.pot_smooth);
+    for (int s = 0; s < nu; ++s) {
+        hipEvent_t ev = nullptr;
+        const bool timed = l == 0 && s == 0 && h->timer.begin(h->stream, &ev);
+        fcd::launch_mg_smooth_tile<T>(F, cur, other, s == 0 ? &Cl : nullptr, mode, nullptr, h->stream);
+        if (timed) h->timer.end(h->stream, TK_POST0, ev);
+        std::swap(cur, other);
+    }
+    if (cur != F.u)
+        (void)hipMemcpy2DAsync(F.u, F.pitch * sizeof(T), cur, F.pitch * sizeof(T), F.nx * sizeof(T), F.ny,
+                               hipMemcpyDeviceToDevice, h->stream);
+}
+
+// Everything of a V-cycle after the finest level's pre-smoothing, whose result is cur0.
+template <typename T>
+void vcycle_rest(fcd_handle* h, const fcd::PotLevel<T>& L0, T* cur0) {
+    const int L = h->plan.levels;
+    const bool tail = h->plan.tail < L;
+    const int gend = tail ? h->plan.tail : L - 1;  // levels [0, gend) are smoothed by tiles
+    T* cur[MAX_LEVELS];
+    cur[0] = cur0;
+    for (int l = 0; l < gend; ++l) {
+        fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
+        if (l > 0) cur[l] = mg_presmooth<T>(h, F, l, 0, nullptr);
+        F.u = cur[l];
+        fcd::launch_mg_restrict_tile<T>(F, pot_level<T>(h, l + 1), l == 0 ? fine_mode(L0) : 0, h->stream);
+    }
+    if (tail) {
+        fcd::MgTail<T> tl{};
+        tl.n = L - h->plan.tail;
+        for (int k = 0; k < tl.n; ++k) tl.lv[k] = pot_level<T>(h, h->plan.tail + k);
+        tl.nu1 = tl.nu2 = std::max(1, h->prm.pot_smooth);
+        tl.coarse_sweeps = coarse_sweeps(h, tl.lv[tl.n - 1].ny);
+        tl.omega = T(sor_omega_opt(tl.lv[tl.n - 1].ny));
+        fcd::launch_mg_tail<T>(tl, h->stream);
     } else {
-        for (int s = 0; s < h->prm.pot_coarse_sweeps; ++s) fcd::launch_pot_sweep<T>(L, om, h->stream);
+        coarse_solve<T>(h, L - 1, L0);
+    }
+    for (int l = gend - 1; l >= 0; --l) {
+        const fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
+        mg_postsmooth<T>(h, F, l, l == 0 ? fine_mode(L0) : 0, cur[l], pot_level<T>(h, l + 1));
     }
 }
 
-// One V-cycle: Gauss-Seidel smoothing, residual restriction, coarsest solve,
-// bilinear prolongation and post-smoothing.
+// One full iteration: a V-cycle, or the coarse sweeps on a single-level hierarchy.
 template <typename T>
 void vcycle(fcd_handle* h, const fcd::PotLevel<T>& L0) {
-    const int L = h->plan.levels, nu = h->prm.pot_smooth;
-    if (L == 1) {
+    if (h->plan.levels == 1) {
         coarse_solve<T>(h, 0, L0);
         return;
     }
-    for (int l = 0; l < L - 1; ++l) {
-        const fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
-        for (int s = 0; s < nu; ++s) fcd::launch_pot_sweep<T>(F, T(1), h->stream);
-        fcd::launch_mg_restrict_residual<T>(F, pot_level<T>(h, l + 1), h->stream);
-    }
-    coarse_solve<T>(h, L - 1, L0);
-    for (int l = L - 2; l >= 0; --l) {
-        const fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
-        fcd::launch_mg_prolong<T>(pot_level<T>(h, l + 1), F, h->stream);
-        for (int s = 0; s < nu; ++s) fcd::launch_pot_sweep<T>(F, T(1), h->stream);
-    }
+    T* cur0 = mg_presmooth<T>(h, L0, 0, fine_mode(L0), nullptr);
+    vcycle_rest<T>(h, L0, cur0);
 }
 
 // Iterate (SOR sweeps or V-cycles) on the finest-level problem L0 until
@@ -363,13 +452,13 @@ void vcycle(fcd_handle* h, const fcd::PotLevel<T>& L0) {
 template <typename T>
 fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0, int max_iters, int defer_from,
                           int* iters_out, double* resid_out) {
-    const bool mg = h->prm.pot_solver == FCD_SOLVER_MG;
-    const int every = h->prm.pot_check_every;
+    const bool mg = h->prm.pot_solver == FCD_SOLVER_MG && h->plan.levels > 1;
+    const int every = mg ? 1 : h->prm.pot_check_every;
     const T omega = T(h->prm.pot_omega > 0.0 ? h->prm.pot_omega : sor_omega_opt(L0.ny));
     auto one = [&]() {
         hipEvent_t ev = nullptr;
         const bool timed = h->timer.begin(h->stream, &ev);
-        if (mg)
+        if (h->prm.pot_solver == FCD_SOLVER_MG)
             vcycle<T>(h, L0);
         else
             fcd::launch_pot_sweep<T>(L0, omega, h->stream);
@@ -378,38 +467,67 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
     // The residual is tested before iterating and then every pot_check_every
     // iterations, except that the first test is deferred past the iterations the
     // previous comparable solve needed minus one: consecutive steps need similar counts,
-    // and each test costs a reduction and a host round trip.
+    // and each test costs a host round trip.  With multigrid the test is the residual of
+    // the iterate entering a V-cycle, reduced by the cycle's first smoothing kernel; the
+    // host waits for it before launching the rest of the cycle.
     int it = 0;
     const int defer = defer_from > 1 ? defer_from - 1 : 0;
     if (defer > 0 && defer <= max_iters) {
         for (int s = 0; s < defer; ++s) one();
         it = defer;
     }
-    double r = 0.0, scale = 0.0;
-    fcd_status st = read_residual<T>(h, L0, &r, &scale);
-    if (st) return st;
     auto thr_of = [&](double sc) { return std::max(thr0, resid_floor_factor<T>() * sc); };
-    double thr = thr_of(scale);
-    while (!(r <= thr)) {
-        if (r != r) {
-            h->last_resid = r;
-            return fail(FCD_ERR_DIVERGED, "potential residual is NaN");
+    double r = 0.0, scale = 0.0;
+    fcd_status st = FCD_OK;
+    if (mg) {
+        for (;;) {
+            hipEvent_t ev = nullptr;
+            bool timed = h->timer.begin(h->stream, &ev);
+            T* cur0 = mg_presmooth<T>(h, L0, 0, fine_mode(L0), res_word(h));
+            if (timed) h->timer.end(h->stream, TK_RESID, ev);
+            st = hip_check(hipMemcpyAsync(h->host, res_word(h), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                           "residual copy");
+            if (!st) st = hip_check(hipStreamSynchronize(h->stream), "residual sync");
+            if (st) return st;
+            std::memcpy(&r, h->host, sizeof(double));
+            std::memcpy(&scale, h->host + 1, sizeof(double));
+            if (r <= thr_of(scale)) break;
+            if (r != r) {
+                h->last_resid = r;
+                return fail(FCD_ERR_DIVERGED, "potential residual is NaN");
+            }
+            if (it >= max_iters) break;
+            timed = h->timer.begin(h->stream, &ev);
+            vcycle_rest<T>(h, L0, cur0);
+            if (timed) h->timer.end(h->stream, TK_ITER, ev);
+            st = hip_check(hipGetLastError(), "potential launch");
+            if (st) return st;
+            ++it;
         }
-        if (it >= max_iters) break;
-        const int m = every < max_iters - it ? every : max_iters - it;
-        for (int s = 0; s < m; ++s) one();
-        st = hip_check(hipGetLastError(), "potential launch");
-        if (st) return st;
-        it += m;
+    } else {
         st = read_residual<T>(h, L0, &r, &scale);
         if (st) return st;
-        thr = thr_of(scale);
+        while (!(r <= thr_of(scale))) {
+            if (r != r) {
+                h->last_resid = r;
+                return fail(FCD_ERR_DIVERGED, "potential residual is NaN");
+            }
+            if (it >= max_iters) break;
+            const int m = every < max_iters - it ? every : max_iters - it;
+            for (int s = 0; s < m; ++s) one();
+            st = hip_check(hipGetLastError(), "potential launch");
+            if (st) return st;
+            it += m;
+            st = read_residual<T>(h, L0, &r, &scale);
+            if (st) return st;
+        }
     }
+    h->timer.resolve();
     h->sweeps += it;
     h->last_resid = r;
     if (iters_out) *iters_out = it;
     if (resid_out) *resid_out = r;
-    if (!(r <= thr)) return fail(FCD_ERR_NOT_CONVERGED, "potential solve reached max_iters");
+    if (!(r <= thr_of(scale))) return fail(FCD_ERR_NOT_CONVERGED, "potential solve reached max_iters");
     return FCD_OK;
 }
 
@@ -424,12 +542,7 @@ fcd_status solve_impl(fcd_handle* h, double tol, int max_iters, int* iters_out, 
         h->last_resid = 0.0;
         return hip_check(hipGetLastError(), "fill");
     }
-    if (h->prm.pot_solver == FCD_SOLVER_MG) {
-        hipEvent_t ev = nullptr;
-        const bool timed = h->timer.begin(h->stream, &ev);
-        restrict_mu_all<T>(h);
-        if (timed) h->timer.end(h->stream, TK_PHASE, ev);
-    }
+    if (h->prm.pot_solver == FCD_SOLVER_MG) restrict_mu_all<T>(h);
     int it = 0;
     const fcd_status st = iterate_level0<T>(h, pot_level<T>(h, 0), tol * std::fabs(h->prm.H0), max_iters,
                                             h->last_iters, &it, resid_out);
@@ -847,25 +960,29 @@ fcd_status batch_moments_impl(fcd_batch* b, int k, unsigned mask, double* out) {
 // Checkpointed adjoint.
 // ---------------------------------------------------------------------------------
 struct AdjLayout {
-    size_t plane, state, rec;  // bytes of one plane, one state (27 planes), state + psi' record
+    size_t plane, state;
+    size_t crec;  // checkpoint record: state, psi' and the psi' history plane (warm start)
+    size_t srec;  // segment record: state and the step's psi'
     int nseg, nblocks;
-    size_t off_ckpt, off_final, off_seg, off_lam, off_sens, off_rhs, off_lpsi, off_part, off_acc, off_rmax, bytes;
+    size_t off_ckpt, off_final, off_seg, off_lam, off_sens, off_rhs, off_lpsi, off_lprev, off_part, off_acc, off_rmax,
+        bytes;
 };
 
 AdjLayout adj_layout(const fcd_lattice& l, int nsteps, int every) {
     AdjLayout L{};
     L.plane = (size_t)l.ny * l.pitch * elem_size(l.precision);
     L.state = 27 * L.plane;
-    L.rec = align256(L.state + L.plane);
+    L.crec = align256(L.state + 2 * L.plane);
+    L.srec = align256(L.state + L.plane);
     L.nseg = (nsteps + every - 1) / every;
     L.nblocks = fcd::adj_blocks(l.nx, l.ny);
     size_t off = 0;
     L.off_ckpt = off;
-    off += (size_t)L.nseg * L.rec;
+    off += (size_t)L.nseg * L.crec;
     L.off_final = off;
-    off += L.rec;
+    off += L.crec;
     L.off_seg = off;
-    off += (size_t)every * L.rec;
+    off += (size_t)every * L.srec;
     L.off_lam = off;
     off += 2 * align256(L.state);
     L.off_sens = off;
@@ -873,6 +990,8 @@ AdjLayout adj_layout(const fcd_lattice& l, int nsteps, int every) {
     L.off_rhs = off;
     off += align256(L.plane);
     L.off_lpsi = off;
+    off += align256(L.plane);
+    L.off_lprev = off;
     off += align256(L.plane);
     L.off_part = off;
     off += align256(3 * (size_t)L.nblocks * fcd::ADJ_NPART * sizeof(double));
@@ -888,18 +1007,28 @@ fcd_status dcopy(void* dst, const void* src, size_t bytes, hipStream_t s) {
     return hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s), "device copy");
 }
 
+// Checkpoint records hold everything a step reads: the state, psi' (the solver's warm
+// start) and the psi' history plane; the history count and the previous solve's
+// iteration count are kept on the host beside them.
 template <typename T>
-fcd_status save_record(fcd_handle* h, char* rec, size_t state_bytes) {
-    fcd_status st = dcopy(rec, h->buf.dist[h->cur], state_bytes, h->stream);
-    if (st) return st;
-    return dcopy(rec + state_bytes, h->buf.psi, state_bytes / 27, h->stream);
+T* psi_prev(fcd_handle* h) {
+    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev);
 }
 
 template <typename T>
-fcd_status load_record(fcd_handle* h, const char* rec, size_t state_bytes) {
-    fcd_status st = dcopy(h->buf.dist[h->cur], rec, state_bytes, h->stream);
-    if (st) return st;
-    return dcopy(h->buf.psi, rec + state_bytes, state_bytes / 27, h->stream);
+fcd_status save_record(fcd_handle* h, char* rec, const AdjLayout& L) {
+    fcd_status st = dcopy(rec, h->buf.dist[h->cur], L.state, h->stream);
+    if (!st) st = dcopy(rec + L.state, h->buf.psi, L.plane, h->stream);
+    if (!st) st = dcopy(rec + L.state + L.plane, psi_prev<T>(h), L.plane, h->stream);
+    return st;
+}
+
+template <typename T>
+fcd_status load_record(fcd_handle* h, const char* rec, const AdjLayout& L) {
+    fcd_status st = dcopy(h->buf.dist[h->cur], rec, L.state, h->stream);
+    if (!st) st = dcopy(h->buf.psi, rec + L.state, L.plane, h->stream);
+    if (!st) st = dcopy(psi_prev<T>(h), rec + L.state + L.plane, L.plane, h->stream);
+    return st;
 }
 
 template <typename T>
@@ -909,22 +1038,21 @@ fcd_status adj_forward_impl(fcd_handle* h, int nsteps, int every, char* work, do
     h->adj_nsteps = nsteps;
     h->adj_every = every;
     h->adj_from_init = h->init_fresh;
-    h->adj_ckpt_iters.assign(L.nseg, 0);
-    const int saved_extrap = h->prm.pot_extrapolate;
-    h->prm.pot_extrapolate = 0;  // the recomputation must be able to replay every solve
+    h->adj_ckpt_iters.assign(2 * (size_t)L.nseg, 0);
     fcd_status st = FCD_OK;
     for (int t = 0; t < nsteps && !st; ++t) {
         if (t % every == 0) {
-            st = save_record<T>(h, work + L.off_ckpt + (size_t)(t / every) * L.rec, L.state);
-            h->adj_ckpt_iters[t / every] = h->last_iters;
+            st = save_record<T>(h, work + L.off_ckpt + (size_t)(t / every) * L.crec, L);
+            h->adj_ckpt_iters[2 * (t / every)] = h->last_iters;
+            h->adj_ckpt_iters[2 * (t / every) + 1] = h->hist;
         }
         if (!st) st = step_impl<T>(h, 1);
     }
-    h->prm.pot_extrapolate = saved_extrap;
     if (st) return st;
-    st = save_record<T>(h, work + L.off_final, L.state);
+    st = save_record<T>(h, work + L.off_final, L);
     if (st) return st;
     h->adj_final_iters = h->last_iters;
+    h->adj_final_hist = h->hist;
     double d[4];
     st = diag_impl<T>(h, d);
     if (st) return st;
@@ -952,12 +1080,12 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
     unsigned long long* rmax = reinterpret_cast<unsigned long long*>(w + L.off_rmax);
     T* phi = static_cast<T*>(h->buf.phi);
     char* scr = static_cast<char*>(h->buf.scratch);
-    const int saved_extrap = h->prm.pot_extrapolate;
-    h->prm.pot_extrapolate = 0;
+    T* lprev = reinterpret_cast<T*>(w + L.off_lprev);
     fcd::launch_fill<double>(acc, 16, 0.0, h->stream);
     fcd::launch_fill<T>(lpsi, pl, T(0), h->stream);
+    int lhist = 0;  // adjoint potential solves so far (warm-start extrapolation validity)
     // seed: adjoint of the final state from J = dJ[0] D_o + dJ[1] D_i
-    fcd_status st = load_record<T>(h, w + L.off_final, L.state);
+    fcd_status st = load_record<T>(h, w + L.off_final, L);
     if (st) return st;
     double d[4];
     st = diag_impl<T>(h, d);  // phase planes and the deformation moments of the final state
@@ -968,17 +1096,18 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
     const bool field = h->prm.H0 != 0.0;
     for (int seg = L.nseg - 1; seg >= 0 && !st; --seg) {
         const int t0 = seg * every, t1 = std::min(nsteps, t0 + every);
-        st = load_record<T>(h, w + L.off_ckpt + (size_t)seg * L.rec, L.state);
+        st = load_record<T>(h, w + L.off_ckpt + (size_t)seg * L.crec, L);
         if (st) break;
-        h->last_iters = h->adj_ckpt_iters[seg];
+        h->last_iters = h->adj_ckpt_iters[2 * seg];
+        h->hist = h->adj_ckpt_iters[2 * seg + 1];
         for (int t = t0; t < t1 && !st; ++t) {
-            char* rec = w + L.off_seg + (size_t)(t - t0) * L.rec;
+            char* rec = w + L.off_seg + (size_t)(t - t0) * L.srec;
             st = dcopy(rec, h->buf.dist[h->cur], L.state, h->stream);
             if (!st) st = step_impl<T>(h, 1);
             if (!st) st = dcopy(rec + L.state, h->buf.psi, L.plane, h->stream);
         }
         for (int t = t1 - 1; t >= t0 && !st; --t) {
-            const char* rec = w + L.off_seg + (size_t)(t - t0) * L.rec;
+            const char* rec = w + L.off_seg + (size_t)(t - t0) * L.srec;
             const T* s_t = reinterpret_cast<const T*>(rec);
             const T* psi_t = reinterpret_cast<const T*>(rec + L.state);
             fcd::launch_phase<T>(s_t, phi, P, h->stream);
@@ -996,6 +1125,11 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
                 double rm;
                 std::memcpy(&rm, h->host, sizeof(double));
                 if (rm > 0.0) {
+                    // warm start: linear extrapolation of the last two adjoint solutions
+                    if (h->prm.pot_extrapolate)
+                        fcd::launch_psi_history<T>(lpsi, lprev, h->lat.nx, h->lat.ny, h->lat.pitch, lhist >= 2 ? 1 : 0,
+                                                   h->stream);
+                    ++lhist;
                     fcd::PotLevel<T> La = pot_level<T>(h, 0);
                     La.u = lpsi;
                     La.f = rhs;
@@ -1006,6 +1140,7 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
                     if (st) break;
                 } else {
                     fcd::launch_fill<T>(lpsi, pl, T(0), h->stream);
+                    lhist = 0;
                 }
                 fcd::launch_adj_finish<T>(sens, phi, psi_t, lpsi, lam[1 - A], partB, P, h->stream);
                 fcd::launch_adj_reduce(partB, L.nblocks, 2, acc, 13, h->stream);
@@ -1017,7 +1152,6 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
             A = 1 - A;
         }
     }
-    h->prm.pot_extrapolate = saved_extrap;
     if (st) return st;
     if (h->adj_from_init) {
         const double nu3 = h->prm.tau[2] / 3.0;
@@ -1049,7 +1183,8 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
     grad[5] = a[5] - gb[0] + gb[1] + gb[2];
     // leave the handle on the forward's final state
     h->last_iters = h->adj_final_iters;
-    return load_record<T>(h, w + L.off_final, L.state);
+    h->hist = h->adj_final_hist;
+    return load_record<T>(h, w + L.off_final, L);
 }
 
 #define FCD_BDISPATCH(b, call) ((b)->precision == FCD_FP64 ? call<double> : call<float>)
@@ -1093,7 +1228,7 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     h->init_fresh = 0;
     h->adj_work = nullptr;
     h->adj_nsteps = h->adj_every = h->adj_from_init = 0;
-    h->adj_final_iters = 0;
+    h->adj_final_iters = h->adj_final_hist = 0;
     h->plan = make_plan(*lat);
     if (hipHostMalloc(reinterpret_cast<void**>(&h->host), 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete h;
@@ -1203,12 +1338,12 @@ fcd_status fcd_timing(fcd_handle* h, int32_t enable) {
     return FCD_OK;
 }
 
-fcd_status fcd_timing_read(fcd_handle* h, double out[8]) {
+fcd_status fcd_timing_read(fcd_handle* h, double out[12]) {
     if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
     fcd_status st = hip_check(hipStreamSynchronize(h->stream), "stream sync");
     if (st) return st;
     h->timer.resolve();
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < TK_KINDS; ++k) {
         out[2 * k] = h->timer.ms[k];
         out[2 * k + 1] = h->timer.count[k];
     }

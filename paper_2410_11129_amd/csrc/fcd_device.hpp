@@ -54,6 +54,16 @@ struct PotLevel {
     T H0x, H0y;   // applied field (finest level only)
 };
 
+// The coarsest levels of a V-cycle, solved in LDS by one block (levels lv[0..n), finest
+// first; lv[0].f holds the restricted residual, lv[0].u receives the correction).
+constexpr int MG_MAX_TAIL = 8;
+template <typename T>
+struct MgTail {
+    PotLevel<T> lv[MG_MAX_TAIL];
+    int n, nu1, nu2, coarse_sweeps;
+    T omega;  // SOR factor of the coarsest-level sweeps
+};
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ a, long long n, T v) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;

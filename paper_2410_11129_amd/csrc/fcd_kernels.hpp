@@ -24,12 +24,21 @@ template <typename T>
 void launch_mg_restrict_mu(const T* muf, int pitchf, T* muc, int nxc, int nyc, int pitchc, hipStream_t s);
 template <typename T>
 void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hipStream_t s);
+// One tile-smoother sweep uin -> uout (never the same buffer); prolong_from != nullptr
+// adds the prolongation of that coarse level's correction first.  mode 0: coarse level
+// (L.f), 1: finest level with the right-hand side from H0, 2: finest level with L.f.
+// res != nullptr: max |residual| and max |C u| of uin into res[0..1] (cleared first).
 template <typename T>
-void launch_mg_prolong(const PotLevel<T>& C, const PotLevel<T>& F, hipStream_t s);
+void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
+                           unsigned long long* res, hipStream_t s);
+// Residual restriction by tiles from F (u = the smoothed iterate) into C (f, u = 0);
+// mode as for the tile smoother.
 template <typename T>
-size_t mg_coarse_lds_bytes(int nx, int ny);
+void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mode, hipStream_t s);
 template <typename T>
-void launch_mg_coarse_solve(const PotLevel<T>& L, int iters, T omega, hipStream_t s);
+size_t mg_tail_lds_bytes(const MgTail<T>& tl);
+template <typename T>
+void launch_mg_tail(const MgTail<T>& tl, hipStream_t s);
 template <typename T>
 void launch_psi_history(T* psi, T* prev, int nx, int ny, int pitch, int mode, hipStream_t s);
 template <typename T>

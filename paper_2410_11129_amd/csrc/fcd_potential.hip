@@ -97,12 +97,10 @@ __global__ void __launch_bounds__(PX* PY) k_mg_restrict_residual(PotLevel<T> F, 
     Cl.u[k] = T(0);
 }
 
-// Fine correction += bilinear interpolation of the coarse correction (weights 9/16,
-// 3/16, 3/16, 1/16 of the four nearest coarse nodes; coarse ghost rows by the kappa rule).
+// Bilinear interpolation of the coarse correction at fine node (i, j): weights 9/16,
+// 3/16, 3/16, 1/16 of the four nearest coarse nodes; coarse ghost rows by the kappa rule.
 template <typename T>
-__global__ void __launch_bounds__(PX* PY) k_mg_prolong(PotLevel<T> Cl, PotLevel<T> F) {
-    const int i = blockIdx.x * PX + threadIdx.x, j = blockIdx.y * PY + threadIdx.y;
-    if (i >= F.nx || j >= F.ny) return;
+__device__ __forceinline__ T prolong_at(const PotLevel<T>& Cl, int i, int j) {
     const int I = i >> 1, J = j >> 1;
     const int I2 = (i & 1) ? (I + 1 == Cl.nx ? 0 : I + 1) : (I == 0 ? Cl.nx - 1 : I - 1);
     int J2 = (j & 1) ? J + 1 : J - 1;
@@ -116,47 +114,380 @@ __global__ void __launch_bounds__(PX* PY) k_mg_prolong(PotLevel<T> Cl, PotLevel<
     }
     const T* e = Cl.u;
     const long long rJ = (long long)J * Cl.pitch, rJ2 = (long long)J2 * Cl.pitch;
-    const T v = T(9) / T(16) * e[rJ + I] + T(3) / T(16) * (gy * e[rJ2 + I] + e[rJ + I2]) +
-                T(1) / T(16) * gy * e[rJ2 + I2];
-    F.u[(long long)j * F.pitch + i] += v;
+    return T(9) / T(16) * e[rJ + I] + T(3) / T(16) * (gy * e[rJ2 + I] + e[rJ + I2]) +
+           T(1) / T(16) * gy * e[rJ2 + I2];
 }
 
-// Coarsest level: the whole level in LDS, `iters` four-colour SOR sweeps by one block.
-constexpr int COARSE_T = 256;
+// ---------------------------------------------------------------------------------
+// Tile smoother.  One block loads a 64 x 16 tile of u and mu with a one-node halo
+// into LDS and runs one four-colour Gauss-Seidel sweep on it (the colours of the
+// tile in the fixed order 0..3, synchronised through LDS).  Halo values are those of
+// the input iterate: between tiles the sweep is a Jacobi step, so the block reads
+// uin and writes uout (never the same buffer) and the result does not depend on
+// block scheduling.  PROLONG adds the prolongation of the coarse correction to every
+// loaded value first (prolongation fused with post-smoothing).  MODE selects the
+// right-hand side: 0 coarse level (f), 1 finest level formed from H0 and mu on the
+// fly, 2 finest level with a given f (adjoint solves).  With res != nullptr the block
+// also reduces max |residual| and max |C u| of the INPUT iterate into res[0..1].
+// ---------------------------------------------------------------------------------
+constexpr int TSX = 64, TSY = 16;
+constexpr int THX = TSX + 2, THY = TSY + 2;
+constexpr int TS_T = 256;  // 32 x 8 threads: one node of each colour per thread
 
 template <typename T>
-__global__ void __launch_bounds__(COARSE_T) k_mg_coarse_solve(PotLevel<T> L, int iters, T omega) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    T* su = reinterpret_cast<T*>(lds_raw);
-    const int n = L.nx * L.ny;
-    T* sf = su + n;
-    T* smu = sf + n;
-    for (int t = threadIdx.x; t < n; t += COARSE_T) {
-        const int j = t / L.nx, i = t - j * L.nx;
-        const long long k = (long long)j * L.pitch + i;
-        su[t] = L.u[k];
-        sf[t] = L.f[k];
-        smu[t] = L.mu[k];
+__device__ __forceinline__ MgEval<T> tile_eval(const T (*su)[THX], const T (*sm)[THX], int lx, int ly, bool bot,
+                                               bool top, const PotLevel<T>& L, T fval, bool rhs_from_field) {
+    const T mc = sm[ly][lx], me = sm[ly][lx + 1], mw = sm[ly][lx - 1];
+    const T mn = sm[ly + 1][lx], ms = sm[ly - 1][lx];
+    const T mne = sm[ly + 1][lx + 1], mnw = sm[ly + 1][lx - 1], msw = sm[ly - 1][lx - 1], mse = sm[ly - 1][lx + 1];
+    const T k = L.kappa;
+    const T ue = su[ly][lx + 1], uw = su[ly][lx - 1];
+    T un, une, unw, us, usw, use;
+    if (top) {
+        un = -k * su[ly][lx];
+        une = -k * ue;
+        unw = -k * uw;
+    } else {
+        un = su[ly + 1][lx];
+        une = su[ly + 1][lx + 1];
+        unw = su[ly + 1][lx - 1];
+    }
+    if (bot) {
+        us = -k * su[ly][lx];
+        usw = -k * uw;
+        use = -k * ue;
+    } else {
+        us = su[ly - 1][lx];
+        usw = su[ly - 1][lx - 1];
+        use = su[ly - 1][lx + 1];
+    }
+    const T a = L.inv_h2 * (T(1) / T(3)), d = L.inv_h2 * (T(1) / T(12));
+    const T ce = a * (mc + me), cw = a * (mc + mw), cn = a * (mc + mn), cs = a * (mc + ms);
+    const T cne = d * (mc + mne), cnw = d * (mc + mnw), csw = d * (mc + msw), cse = d * (mc + mse);
+    MgEval<T> r;
+    r.C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
+    r.acc = ((ce * ue + cw * uw) + (cn * un + cs * us)) + ((cne * une + csw * usw) + (cnw * unw + cse * use));
+    r.cself = (bot ? k * cs : T(0)) + (top ? k * cn : T(0));
+    if (rhs_from_field) {
+        const T sx = (ce - cw) + (cne - csw) + (cse - cnw);
+        const T sy = (cn - cs) + (cne - csw) + (cnw - cse);
+        r.rhs = L.H0x * sx + L.H0y * sy;
+    } else {
+        r.rhs = fval;
+    }
+    return r;
+}
+
+// Tile + halo loads, issued together before any LDS store (the loads of one thread
+// are independent, so their latencies overlap).  Columns wrap periodically, rows
+// beyond the walls are clamped (mu mirrored; u there is never read).
+constexpr int TH_N = THX * THY;
+constexpr int TH_PER = (TH_N + TS_T - 1) / TS_T;
+// Coarse correction tile for the fused prolongation: coarse columns I0-1 .. I0+32 and
+// rows J0-1 .. J0+8 of the tile's fine origin (i0, j0) = (2 I0, 2 J0).
+constexpr int CHX = TSX / 2 + 2, CHY = TSY / 2 + 2;
+constexpr int CH_PER = (CHX * CHY + TS_T - 1) / TS_T;
+
+__device__ __forceinline__ int wrap_col(int i, int nx) {
+    while (i < 0) i += nx;
+    while (i >= nx) i -= nx;
+    return i;
+}
+
+__device__ __forceinline__ int clamp_row(int j, int ny) { return j < 0 ? 0 : (j >= ny ? ny - 1 : j); }
+
+template <typename T>
+__device__ __forceinline__ void load_tile(const PotLevel<T>& L, const T* __restrict__ uin, int i0, int j0,
+                                          T (&uv)[TH_PER], T (&mv)[TH_PER]) {
+#pragma unroll
+    for (int r = 0; r < TH_PER; ++r) {
+        const int q = threadIdx.x + r * TS_T;
+        if (q < TH_N) {
+            const int ly = q / THX, lx = q - ly * THX;
+            const long long k = (long long)clamp_row(j0 + ly - 1, L.ny) * L.pitch + wrap_col(i0 + lx - 1, L.nx);
+            uv[r] = uin[k];
+            mv[r] = L.mu[k];
+        }
+    }
+}
+
+// Prolongation at fine tile cell (lx, ly) from the coarse tile sc (bilinear weights
+// 9/16, 3/16, 3/16, 1/16; coarse ghost rows by the kappa rule).
+template <typename T>
+__device__ __forceinline__ T prolong_tile(const T (*sc)[CHX], int i0, int j0, int lx, int ly, int nyc, T kappa) {
+    const int i = i0 + lx - 1, j = j0 + ly - 1;  // unwrapped fine coordinates
+    const int I0 = i0 >> 1, J0 = j0 >> 1;
+    const int lI = (i >> 1) - I0 + 1, lI2 = (i & 1) ? lI + 1 : lI - 1;
+    const int J = j >> 1, lJ = J - J0 + 1;
+    int J2 = (j & 1) ? J + 1 : J - 1;
+    T gy = T(1);
+    if (J2 < 0) {
+        J2 = 0;
+        gy = -kappa;
+    } else if (J2 >= nyc) {
+        J2 = nyc - 1;
+        gy = -kappa;
+    }
+    const int lJ2 = J2 - J0 + 1;
+    return T(9) / T(16) * sc[lJ][lI] + T(3) / T(16) * (gy * sc[lJ2][lI] + sc[lJ][lI2]) +
+           T(1) / T(16) * gy * sc[lJ2][lI2];
+}
+
+template <typename T, bool PROLONG, int MODE>
+__global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
+                                                         T* __restrict__ uout, PotLevel<T> Cl,
+                                                         unsigned long long* __restrict__ res) {
+    __shared__ T su[THY][THX];
+    __shared__ T sm[THY][THX];
+    __shared__ T sf[MODE == 1 ? 1 : TSY][TSX];
+    __shared__ T sc[PROLONG ? CHY : 1][CHX];
+    __shared__ double wmax[2][TS_T / 64];
+    const int i0 = blockIdx.x * TSX, j0 = blockIdx.y * TSY;
+    const int tid = threadIdx.x;
+    T uv[TH_PER], mv[TH_PER], fv[4], cv[CH_PER];
+    load_tile(L, uin, i0, j0, uv, mv);
+    if (MODE != 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = tid + r * TS_T;
+            const int ly = q / TSX, lx = q - ly * TSX;
+            const int i = i0 + lx, j = j0 + ly;
+            fv[r] = (i < L.nx && j < L.ny) ? L.f[(long long)j * L.pitch + i] : T(0);
+        }
+    }
+    if (PROLONG) {
+#pragma unroll
+        for (int r = 0; r < CH_PER; ++r) {
+            const int q = tid + r * TS_T;
+            if (q < CHX * CHY) {
+                const int ly = q / CHX, lx = q - ly * CHX;
+                const int I = wrap_col((i0 >> 1) - 1 + lx, Cl.nx), J = clamp_row((j0 >> 1) - 1 + ly, Cl.ny);
+                cv[r] = Cl.u[(long long)J * Cl.pitch + I];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < CH_PER; ++r) {
+            const int q = tid + r * TS_T;
+            if (q < CHX * CHY) sc[q / CHX][q % CHX] = cv[r];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < TH_PER; ++r) {
+        const int q = tid + r * TS_T;
+        if (q < TH_N) {
+            const int ly = q / THX, lx = q - ly * THX;
+            T u = uv[r];
+            if (PROLONG) u += prolong_tile<T>(sc, i0, j0, lx, ly, Cl.ny, Cl.kappa);
+            su[ly][lx] = u;
+            sm[ly][lx] = mv[r];
+        }
+    }
+    if (MODE != 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = tid + r * TS_T;
+            sf[MODE == 1 ? 0 : q / TSX][q % TSX] = fv[r];
+        }
     }
     __syncthreads();
-    PotLevel<T> S = L;
-    S.u = su;
-    S.f = sf;
-    S.mu = smu;
-    S.pitch = L.nx;
-    const int hx = (L.nx + 1) / 2, hy = (L.ny + 1) / 2;
-    for (int it = 0; it < iters; ++it)
+    const int tx = tid & 31, ty = tid >> 5;
+    if (res) {
+        double rm = 0.0, scl = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
+            const int i = i0 + lx - 1, j = j0 + ly - 1;
+            if (i < L.nx && j < L.ny) {
+                const MgEval<T> e = tile_eval<T>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
+                                                 MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
+                const T u = su[ly][lx];
+                rm = nan_max(rm, fabs((double)(e.acc - e.C * u - e.rhs)));
+                scl = nan_max(scl, fabs((double)(e.C * u)));
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            rm = nan_max(rm, __shfl_xor(rm, off, 64));
+            scl = nan_max(scl, __shfl_xor(scl, off, 64));
+        }
+        if ((tid & 63) == 0) {
+            wmax[0][tid >> 6] = rm;
+            wmax[1][tid >> 6] = scl;
+        }
+        __syncthreads();
+        if (tid < 2) {
+            double m = wmax[tid][0];
+            for (int w = 1; w < TS_T / 64; ++w) m = nan_max(m, wmax[tid][w]);
+            atomicMax(res + tid, (unsigned long long)__double_as_longlong(m));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
+        const int i = i0 + lx - 1, j = j0 + ly - 1;
+        if (i < L.nx && j < L.ny) {
+            const MgEval<T> e = tile_eval<T>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
+                                             MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
+            const T old = su[ly][lx];
+            su[ly][lx] = (e.acc + e.cself * old - e.rhs) / (e.C + e.cself);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = tid + r * TS_T;
+        const int ly = q / TSX, lx = q - ly * TSX;
+        const int i = i0 + lx, j = j0 + ly;
+        if (i < L.nx && j < L.ny) uout[(long long)j * L.pitch + i] = su[ly + 1][lx + 1];
+    }
+}
+
+// Residual restriction by tiles: a block loads a 64 x 16 fine tile of the smoothed
+// iterate and mu with halo, forms the residual f - L u of its nodes in LDS and writes
+// the 32 x 8 coarse right-hand sides (average of the four children) and a zero coarse
+// correction.  Requires nx = 2 nxc and ny = 2 nyc.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TS_T) k_mg_restrict_tile(PotLevel<T> F, PotLevel<T> Cl) {
+    __shared__ T su[THY][THX];
+    __shared__ T sm[THY][THX];
+    __shared__ T sr[TSY][TSX];
+    const int i0 = blockIdx.x * TSX, j0 = blockIdx.y * TSY;
+    const int tid = threadIdx.x;
+    T uv[TH_PER], mv[TH_PER], fv[4];
+    load_tile(F, F.u, i0, j0, uv, mv);
+    if (MODE != 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q = tid + r * TS_T;
+            const int ly = q / TSX, lx = q - ly * TSX;
+            const int i = i0 + lx, j = j0 + ly;
+            fv[r] = (i < F.nx && j < F.ny) ? F.f[(long long)j * F.pitch + i] : T(0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < TH_PER; ++r) {
+        const int q = tid + r * TS_T;
+        if (q < TH_N) {
+            su[q / THX][q % THX] = uv[r];
+            sm[q / THX][q % THX] = mv[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = tid + r * TS_T;
+        const int ly = q / TSX, lx = q - ly * TSX;
+        const int i = i0 + lx, j = j0 + ly;
+        T v = T(0);
+        if (i < F.nx && j < F.ny) {
+            const MgEval<T> e =
+                tile_eval<T>(su, sm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F, MODE == 1 ? T(0) : fv[r], MODE == 1);
+            v = e.rhs - (e.acc - e.C * su[ly + 1][lx + 1]);
+        }
+        sr[ly][lx] = v;
+    }
+    __syncthreads();
+    const int cx = tid & 31, cy = tid >> 5;
+    const int I = (i0 >> 1) + cx, J = (j0 >> 1) + cy;
+    if (I < Cl.nx && J < Cl.ny) {
+        const long long k = (long long)J * Cl.pitch + I;
+        Cl.f[k] = T(0.25) * ((sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) +
+                             (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1]));
+        Cl.u[k] = T(0);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Tail of the V-cycle: the coarsest levels, all in LDS, by one block.  Level 0 of the
+// tail takes its right-hand side from global memory (written by the restriction above
+// it) and starts from a zero correction; the block runs the V-cycle below it (nu1
+// pre-sweeps, residual restriction, ..., coarse_sweeps sweeps at the coarsest level,
+// prolongation, nu2 post-sweeps) and writes the tail's level-0 correction back.
+// ---------------------------------------------------------------------------------
+constexpr int TAIL_T = 256;
+
+template <typename T>
+__device__ __forceinline__ PotLevel<T> tail_view(const MgTail<T>& tl, T* base, int k) {
+    long long off = 0;
+    for (int m = 0; m < k; ++m) off += 3LL * tl.lv[m].nx * tl.lv[m].ny;
+    PotLevel<T> S = tl.lv[k];
+    const long long n = (long long)S.nx * S.ny;
+    S.u = base + off;
+    S.f = base + off + n;
+    S.mu = base + off + 2 * n;
+    S.pitch = S.nx;
+    S.H0x = S.H0y = T(0);
+    return S;
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_sweeps(const PotLevel<T>& S, int sweeps, T omega) {
+    const int hx = (S.nx + 1) / 2, hy = (S.ny + 1) / 2;
+    for (int it = 0; it < sweeps; ++it)
         for (int colour = 0; colour < 4; ++colour) {
-            for (int t = threadIdx.x; t < hx * hy; t += COARSE_T) {
+            for (int t = threadIdx.x; t < hx * hy; t += TAIL_T) {
                 const int tj = t / hx, ti = t - tj * hx;
                 const int i = 2 * ti + (colour & 1), j = 2 * tj + (colour >> 1);
-                if (i < L.nx && j < L.ny) relax_node(S, i, j, omega);
+                if (i < S.nx && j < S.ny) relax_node(S, i, j, omega);
             }
             __syncthreads();
         }
-    for (int t = threadIdx.x; t < n; t += COARSE_T) {
-        const int j = t / L.nx, i = t - j * L.nx;
-        L.u[(long long)j * L.pitch + i] = su[t];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* base = reinterpret_cast<T*>(lds_raw);
+    for (int k = 0; k < tl.n; ++k) {
+        const PotLevel<T> G = tl.lv[k];
+        const PotLevel<T> S = tail_view(tl, base, k);
+        const int n = S.nx * S.ny;
+        for (int t = threadIdx.x; t < n; t += TAIL_T) {
+            const int j = t / S.nx, i = t - j * S.nx;
+            const long long g = (long long)j * G.pitch + i;
+            const_cast<T*>(S.mu)[t] = G.mu[g];
+            if (k == 0) {
+                S.f[t] = G.f[g];
+                S.u[t] = T(0);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k + 1 < tl.n; ++k) {
+        const PotLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
+        tail_sweeps(F, tl.nu1, T(1));
+        const int n = Cc.nx * Cc.ny;
+        for (int t = threadIdx.x; t < n; t += TAIL_T) {
+            const int J = t / Cc.nx, I = t - J * Cc.nx;
+            T s = T(0);
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int i = 2 * I + di, j = 2 * J + dj;
+                    const MgEval<T> r = mg_eval(F, i, j);
+                    s += r.rhs - (r.acc - r.C * F.u[(long long)j * F.pitch + i]);
+                }
+            Cc.f[t] = T(0.25) * s;
+            Cc.u[t] = T(0);
+        }
+        __syncthreads();
+    }
+    tail_sweeps(tail_view(tl, base, tl.n - 1), tl.coarse_sweeps, tl.omega);
+    for (int k = tl.n - 2; k >= 0; --k) {
+        const PotLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
+        const int n = F.nx * F.ny;
+        for (int t = threadIdx.x; t < n; t += TAIL_T) {
+            const int j = t / F.nx, i = t - j * F.nx;
+            F.u[t] += prolong_at(Cc, i, j);
+        }
+        __syncthreads();
+        tail_sweeps(F, tl.nu2, T(1));
+    }
+    const PotLevel<T> G = tl.lv[0];
+    const PotLevel<T> S = tail_view(tl, base, 0);
+    for (int t = threadIdx.x; t < S.nx * S.ny; t += TAIL_T) {
+        const int j = t / S.nx, i = t - j * S.nx;
+        G.u[(long long)j * G.pitch + i] = S.u[t];
     }
 }
 
@@ -204,19 +535,46 @@ void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hip
 }
 
 template <typename T>
-void launch_mg_prolong(const PotLevel<T>& C, const PotLevel<T>& F, hipStream_t s) {
-    hipLaunchKernelGGL(k_mg_prolong<T>, pgrid(F.nx, F.ny), dim3(PX, PY), 0, s, C, F);
+void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
+                           unsigned long long* res, hipStream_t s) {
+    const dim3 g((L.nx + TSX - 1) / TSX, (L.ny + TSY - 1) / TSY);
+    const PotLevel<T> Cl = prolong_from ? *prolong_from : PotLevel<T>{};
+    if (res) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, res, 2LL, 0ULL);
+#define FCD_TILE_LAUNCH(P, M) \
+    hipLaunchKernelGGL((k_mg_smooth_tile<T, P, M>), g, dim3(TS_T), 0, s, L, uin, uout, Cl, res)
+    if (prolong_from) {
+        if (mode == 0) FCD_TILE_LAUNCH(true, 0);
+        else if (mode == 1) FCD_TILE_LAUNCH(true, 1);
+        else FCD_TILE_LAUNCH(true, 2);
+    } else {
+        if (mode == 0) FCD_TILE_LAUNCH(false, 0);
+        else if (mode == 1) FCD_TILE_LAUNCH(false, 1);
+        else FCD_TILE_LAUNCH(false, 2);
+    }
+#undef FCD_TILE_LAUNCH
 }
 
 template <typename T>
-size_t mg_coarse_lds_bytes(int nx, int ny) {
-    return (size_t)3 * nx * ny * sizeof(T);
+void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mode, hipStream_t s) {
+    const dim3 g((F.nx + TSX - 1) / TSX, (F.ny + TSY - 1) / TSY);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, 0>), g, dim3(TS_T), 0, s, F, C);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, 1>), g, dim3(TS_T), 0, s, F, C);
+    else
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, 2>), g, dim3(TS_T), 0, s, F, C);
 }
 
 template <typename T>
-void launch_mg_coarse_solve(const PotLevel<T>& L, int iters, T omega, hipStream_t s) {
-    hipLaunchKernelGGL(k_mg_coarse_solve<T>, dim3(1), dim3(COARSE_T), mg_coarse_lds_bytes<T>(L.nx, L.ny), s, L, iters,
-                       omega);
+size_t mg_tail_lds_bytes(const MgTail<T>& tl) {
+    size_t n = 0;
+    for (int k = 0; k < tl.n; ++k) n += 3 * (size_t)tl.lv[k].nx * tl.lv[k].ny;
+    return n * sizeof(T);
+}
+
+template <typename T>
+void launch_mg_tail(const MgTail<T>& tl, hipStream_t s) {
+    hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(TAIL_T), mg_tail_lds_bytes<T>(tl), s, tl);
 }
 
 template <typename T>
@@ -229,9 +587,11 @@ void launch_psi_history(T* psi, T* prev, int nx, int ny, int pitch, int mode, hi
     template void launch_pot_residual<T>(const PotLevel<T>&, unsigned long long*, hipStream_t);           \
     template void launch_mg_restrict_mu<T>(const T*, int, T*, int, int, int, hipStream_t);                \
     template void launch_mg_restrict_residual<T>(const PotLevel<T>&, const PotLevel<T>&, hipStream_t);    \
-    template void launch_mg_prolong<T>(const PotLevel<T>&, const PotLevel<T>&, hipStream_t);              \
-    template size_t mg_coarse_lds_bytes<T>(int, int);                                                     \
-    template void launch_mg_coarse_solve<T>(const PotLevel<T>&, int, T, hipStream_t);                     \
+    template void launch_mg_smooth_tile<T>(const PotLevel<T>&, const T*, T*, const PotLevel<T>*, int,         \
+                                           unsigned long long*, hipStream_t);                                 \
+    template void launch_mg_restrict_tile<T>(const PotLevel<T>&, const PotLevel<T>&, int, hipStream_t);       \
+    template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
+    template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \
     template void launch_psi_history<T>(T*, T*, int, int, int, int, hipStream_t);
 
 FCD_POT_INSTANTIATE(double)

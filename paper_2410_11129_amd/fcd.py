@@ -33,7 +33,7 @@ EXPORTS = (
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
     "fcd_batch_read_moments", "fcd_batch_stats", "fcd_batch_destroy",
 )
-TIMING_KINDS = ("collide_stream", "potential_iter", "residual", "phase")
+TIMING_KINDS = ("collide_stream", "potential_iter", "residual", "phase", "mg_smooth0", "mg_post0")
 
 
 class fcd_lattice(C.Structure):
@@ -203,7 +203,7 @@ def fcd_timing(h, enable: bool):
 
 def fcd_timing_read(h) -> dict:
     """{kind: (total_ms, launches)} for the kernel classes in TIMING_KINDS."""
-    out = (C.c_double * 8)()
+    out = (C.c_double * (2 * len(TIMING_KINDS)))()
     _check(lib().fcd_timing_read(h, out), "fcd_timing_read")
     return {k: (out[2 * i], int(out[2 * i + 1])) for i, k in enumerate(TIMING_KINDS)}
 
