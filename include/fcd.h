@@ -184,6 +184,13 @@ fcd_status fcd_stats(fcd_handle* h, double out[3]);
 fcd_status fcd_timing(fcd_handle* h, int32_t enable);
 fcd_status fcd_timing_read(fcd_handle* h, double out[12]);
 
+/* Repeated launch sequences of the potential solve (a multigrid V-cycle and the part of
+ * it after the convergence test) run as HIP graphs captured on first use and replayed
+ * on the handle's stream (default: enabled).  enable = 0 launches every kernel
+ * eagerly; the results are bitwise the same.  Graphs are also bypassed while
+ * fcd_timing is on.  Sync. */
+fcd_status fcd_use_graphs(fcd_handle* h, int32_t enable);
+
 /* Wait for the stream and report any asynchronous HIP error.  Sync. */
 fcd_status fcd_sync(fcd_handle* h);
 

@@ -44,11 +44,14 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Multigrid hierarchy and scratch layout.  Level 0 is the lattice itself (psi', mu_r
 // planes of the caller); coarser levels halve both dimensions while nx is a multiple
-// of 4 and ny is even and >= 4.  The coarsest levels whose u, f and mu fit together in
-// TAIL_LDS_MAX bytes form the tail, solved in LDS by one block; every level above the
-// tail has a second plane for the tile smoother's ping-pong.
+// of 4 and ny is even and >= 4.  The coarsest levels whose u, f, mu and a Jacobi
+// ping-pong array fit together in TAIL_LDS_MAX bytes form the tail, solved in LDS by one
+// block; every level above the tail has a second plane for the tile smoother's
+// ping-pong.
 constexpr int MAX_LEVELS = 16;
 constexpr size_t TAIL_LDS_MAX = 65536;
+// Tile sweeps per smoothing launch on the levels between the finest and the tail.
+constexpr int MG_COARSE_INNER = 2;
 
 struct MgPlan {
     int levels;
@@ -78,7 +81,7 @@ MgPlan make_plan(const fcd_lattice& l) {
     p.tail = p.levels;
     size_t tail_bytes = 0;
     for (int L = p.levels - 1; L >= 1 && p.levels - L <= fcd::MG_MAX_TAIL; --L) {
-        const size_t b = 3 * (size_t)p.nx[L] * p.ny[L] * esz;
+        const size_t b = 4 * (size_t)p.nx[L] * p.ny[L] * esz;
         if (tail_bytes + b > TAIL_LDS_MAX) break;
         tail_bytes += b;
         p.tail = L;
@@ -169,6 +172,36 @@ struct Timer {
 };
 
 
+// Instantiated HIP graphs of recurring launch sequences, keyed by the buffers they
+// touch and a kind.  Captured on a private non-blocking stream (default priority) and
+// launched on the caller's stream; cleared whenever the parameters baked into the
+// kernel arguments change.
+struct GraphCache {
+    struct Entry {
+        const void* k1;
+        const void* k2;
+        int kind;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> entries;
+    hipStream_t cap = nullptr;
+    bool enabled = true;
+
+    hipGraphExec_t find(const void* k1, const void* k2, int kind) const {
+        for (const Entry& e : entries)
+            if (e.k1 == k1 && e.k2 == k2 && e.kind == kind) return e.exec;
+        return nullptr;
+    }
+    void clear() {
+        for (const Entry& e : entries) (void)hipGraphExecDestroy(e.exec);
+        entries.clear();
+    }
+    ~GraphCache() {
+        clear();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 struct fcd_handle {
     fcd_lattice lat;
     fcd_params prm;
@@ -189,6 +222,7 @@ struct fcd_handle {
     // segment repeats the forward's solves exactly
     std::vector<int> adj_ckpt_iters;
     int adj_final_iters, adj_final_hist;
+    GraphCache graphs;
     MgPlan plan;
     Timer timer;
 };
@@ -344,6 +378,38 @@ void restrict_mu_all(fcd_handle* h) {
     }
 }
 
+// Run the launch sequence `record` (which launches on h->stream) through a cached HIP
+// graph, capturing it on first use; eagerly while per-kernel timing is on or graphs
+// are disabled.
+template <typename F>
+fcd_status run_graph(fcd_handle* h, const void* k1, const void* k2, int kind, F&& record) {
+    GraphCache& G = h->graphs;
+    if (!G.enabled || h->timer.on) {
+        record();
+        return hip_check(hipGetLastError(), "launch");
+    }
+    hipGraphExec_t exec = G.find(k1, k2, kind);
+    if (!exec) {
+        fcd_status st = FCD_OK;
+        if (!G.cap) st = hip_check(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking), "capture stream");
+        if (st) return st;
+        hipStream_t saved = h->stream;
+        st = hip_check(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (st) return st;
+        h->stream = G.cap;
+        record();
+        h->stream = saved;
+        hipGraph_t graph = nullptr;
+        st = hip_check(hipStreamEndCapture(G.cap, &graph), "end capture");
+        if (st) return st;
+        st = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+        (void)hipGraphDestroy(graph);
+        if (st) return st;
+        G.entries.push_back({k1, k2, kind, exec});
+    }
+    return hip_check(hipGraphLaunch(exec, h->stream), "graph launch");
+}
+
 // SOR sweeps per V-cycle on a coarsest level with ny rows: a few suffice on the two-row
 // levels of a full hierarchy; a hierarchy stopped early needs more on its larger rows.
 int coarse_sweeps(const fcd_handle* h, int ny) { return std::max(1, h->prm.pot_coarse_sweeps) * std::max(1, ny / 2); }
@@ -378,7 +444,8 @@ T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, unsig
     for (int s = 0; s < std::max(1, h->prm.pot_smooth); ++s) {
         hipEvent_t ev = nullptr;
         const bool timed = l == 0 && h->timer.begin(h->stream, &ev);
-        fcd::launch_mg_smooth_tile<T>(F, a, b, nullptr, mode, s == 0 ? res : nullptr, h->stream);
+        fcd::launch_mg_smooth_tile<T>(F, a, b, nullptr, mode, s == 0 ? res : nullptr, l == 0 ? 1 : MG_COARSE_INNER,
+                                      h->stream);
         if (timed) h->timer.end(h->stream, TK_SMOOTH0, ev);
         std::swap(a, b);
     }
@@ -394,7 +461,8 @@ void mg_postsmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, T*
     for (int s = 0; s < nu; ++s) {
         hipEvent_t ev = nullptr;
         const bool timed = l == 0 && s == 0 && h->timer.begin(h->stream, &ev);
-        fcd::launch_mg_smooth_tile<T>(F, cur, other, s == 0 ? &Cl : nullptr, mode, nullptr, h->stream);
+        fcd::launch_mg_smooth_tile<T>(F, cur, other, s == 0 ? &Cl : nullptr, mode, nullptr, l == 0 ? 1 : MG_COARSE_INNER,
+                                      h->stream);
         if (timed) h->timer.end(h->stream, TK_POST0, ev);
         std::swap(cur, other);
     }
@@ -455,10 +523,13 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
     const bool mg = h->prm.pot_solver == FCD_SOLVER_MG && h->plan.levels > 1;
     const int every = mg ? 1 : h->prm.pot_check_every;
     const T omega = T(h->prm.pot_omega > 0.0 ? h->prm.pot_omega : sor_omega_opt(L0.ny));
+    enum { G_CYCLE = 1, G_REST = 2 };
     auto one = [&]() {
         hipEvent_t ev = nullptr;
         const bool timed = h->timer.begin(h->stream, &ev);
-        if (h->prm.pot_solver == FCD_SOLVER_MG)
+        if (mg)
+            (void)run_graph(h, L0.u, L0.f, G_CYCLE, [&]() { vcycle<T>(h, L0); });
+        else if (h->prm.pot_solver == FCD_SOLVER_MG)
             vcycle<T>(h, L0);
         else
             fcd::launch_pot_sweep<T>(L0, omega, h->stream);
@@ -498,9 +569,8 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
             }
             if (it >= max_iters) break;
             timed = h->timer.begin(h->stream, &ev);
-            vcycle_rest<T>(h, L0, cur0);
+            st = run_graph(h, L0.u, L0.f, G_REST, [&]() { vcycle_rest<T>(h, L0, cur0); });
             if (timed) h->timer.end(h->stream, TK_ITER, ev);
-            st = hip_check(hipGetLastError(), "potential launch");
             if (st) return st;
             ++it;
         }
@@ -1243,7 +1313,16 @@ fcd_status fcd_set_params(fcd_handle* h, const fcd_params* prm) {
     fcd_status st = check_params(prm);
     if (st) return st;
     h->prm = *prm;
+    h->graphs.clear();
     return FCD_OK;
+}
+
+fcd_status fcd_use_graphs(fcd_handle* h, int32_t enable) {
+    if (!h) return fail(FCD_ERR_ARG, "handle is null");
+    fcd_status st = hip_check(hipStreamSynchronize(h->stream), "stream sync");
+    h->graphs.clear();
+    h->graphs.enabled = enable != 0;
+    return st;
 }
 
 fcd_status fcd_init_compound_droplet(fcd_handle* h, double xc, double yc, double r_core, double r_shell) {

@@ -28,9 +28,10 @@ void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hip
 // adds the prolongation of that coarse level's correction first.  mode 0: coarse level
 // (L.f), 1: finest level with the right-hand side from H0, 2: finest level with L.f.
 // res != nullptr: max |residual| and max |C u| of uin into res[0..1] (cleared first).
+// inner: sweeps on the tile before it is written back.
 template <typename T>
 void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
-                           unsigned long long* res, hipStream_t s);
+                           unsigned long long* res, int inner, hipStream_t s);
 // Residual restriction by tiles from F (u = the smoothed iterate) into C (f, u = 0);
 // mode as for the tile smoother.
 template <typename T>

@@ -124,7 +124,8 @@ __device__ __forceinline__ T prolong_at(const PotLevel<T>& Cl, int i, int j) {
 // tile in the fixed order 0..3, synchronised through LDS).  Halo values are those of
 // the input iterate: between tiles the sweep is a Jacobi step, so the block reads
 // uin and writes uout (never the same buffer) and the result does not depend on
-// block scheduling.  PROLONG adds the prolongation of the coarse correction to every
+// block scheduling.  `inner` sweeps run on the tile before it is written back (the halo
+// stays that of the input).  PROLONG adds the prolongation of the coarse correction to every
 // loaded value first (prolongation fused with post-smoothing).  MODE selects the
 // right-hand side: 0 coarse level (f), 1 finest level formed from H0 and mu on the
 // fly, 2 finest level with a given f (adjoint solves).  With res != nullptr the block
@@ -236,7 +237,7 @@ __device__ __forceinline__ T prolong_tile(const T (*sc)[CHX], int i0, int j0, in
 template <typename T, bool PROLONG, int MODE>
 __global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
                                                          T* __restrict__ uout, PotLevel<T> Cl,
-                                                         unsigned long long* __restrict__ res) {
+                                                         unsigned long long* __restrict__ res, int inner) {
     __shared__ T su[THY][THX];
     __shared__ T sm[THY][THX];
     __shared__ T sf[MODE == 1 ? 1 : TSY][TSX];
@@ -322,17 +323,19 @@ __global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T*
             atomicMax(res + tid, (unsigned long long)__double_as_longlong(m));
         }
     }
+    for (int sweep = 0; sweep < inner; ++sweep) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
-        const int i = i0 + lx - 1, j = j0 + ly - 1;
-        if (i < L.nx && j < L.ny) {
-            const MgEval<T> e = tile_eval<T>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
-                                             MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
-            const T old = su[ly][lx];
-            su[ly][lx] = (e.acc + e.cself * old - e.rhs) / (e.C + e.cself);
+        for (int c = 0; c < 4; ++c) {
+            const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
+            const int i = i0 + lx - 1, j = j0 + ly - 1;
+            if (i < L.nx && j < L.ny) {
+                const MgEval<T> e = tile_eval<T>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
+                                                 MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
+                const T old = su[ly][lx];
+                su[ly][lx] = (e.acc + e.cself * old - e.rhs) / (e.C + e.cself);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -401,28 +404,33 @@ __global__ void __launch_bounds__(TS_T) k_mg_restrict_tile(PotLevel<T> F, PotLev
 // ---------------------------------------------------------------------------------
 // Tail of the V-cycle: the coarsest levels, all in LDS, by one block.  Level 0 of the
 // tail takes its right-hand side from global memory (written by the restriction above
-// it) and starts from a zero correction; the block runs the V-cycle below it (nu1
-// pre-sweeps, residual restriction, ..., coarse_sweeps sweeps at the coarsest level,
-// prolongation, nu2 post-sweeps) and writes the tail's level-0 correction back.
+// it) and starts from a zero correction; the block runs the V-cycle below it and
+// writes the tail's level-0 correction back.  On these small levels the smoother is
+// damped Jacobi (weight 4/5, `sweeps` sweeps before and after the coarse correction,
+// ping-pong between two LDS arrays): one barrier per sweep instead of four, and two
+// Jacobi sweeps smooth at least as well as one four-colour Gauss-Seidel sweep here.
+// The coarsest level gets 2 coarse_sweeps Jacobi sweeps when it has at most four rows,
+// otherwise that many four-colour SOR sweeps with the factor `omega`.
 // ---------------------------------------------------------------------------------
-constexpr int TAIL_T = 256;
+constexpr int TAIL_T = 512;
 
 template <typename T>
-__device__ __forceinline__ PotLevel<T> tail_view(const MgTail<T>& tl, T* base, int k) {
+__device__ __forceinline__ PotLevel<T> tail_view(const MgTail<T>& tl, T* base, int k, T** alt) {
     long long off = 0;
-    for (int m = 0; m < k; ++m) off += 3LL * tl.lv[m].nx * tl.lv[m].ny;
+    for (int m = 0; m < k; ++m) off += 4LL * tl.lv[m].nx * tl.lv[m].ny;
     PotLevel<T> S = tl.lv[k];
     const long long n = (long long)S.nx * S.ny;
     S.u = base + off;
     S.f = base + off + n;
     S.mu = base + off + 2 * n;
+    *alt = base + off + 3 * n;
     S.pitch = S.nx;
     S.H0x = S.H0y = T(0);
     return S;
 }
 
 template <typename T>
-__device__ __forceinline__ void tail_sweeps(const PotLevel<T>& S, int sweeps, T omega) {
+__device__ __forceinline__ void tail_sor(const PotLevel<T>& S, int sweeps, T omega) {
     const int hx = (S.nx + 1) / 2, hy = (S.ny + 1) / 2;
     for (int it = 0; it < sweeps; ++it)
         for (int colour = 0; colour < 4; ++colour) {
@@ -435,13 +443,36 @@ __device__ __forceinline__ void tail_sweeps(const PotLevel<T>& S, int sweeps, T 
         }
 }
 
+// Damped Jacobi, an even number of sweeps: u -> alt -> u -> ...
+template <typename T>
+__device__ __forceinline__ void tail_jacobi(PotLevel<T> S, T* alt, int sweeps) {
+    const T w = T(0.8);
+    T* a = S.u;
+    T* b = alt;
+    const int n = S.nx * S.ny;
+    for (int it = 0; it < sweeps; ++it) {
+        S.u = a;
+        for (int t = threadIdx.x; t < n; t += TAIL_T) {
+            const int j = t / S.nx, i = t - j * S.nx;
+            const MgEval<T> r = mg_eval(S, i, j);
+            const T old = a[t];
+            b[t] = old + w * ((r.acc + r.cself * old - r.rhs) / (r.C + r.cself) - old);
+        }
+        __syncthreads();
+        T* c = a;
+        a = b;
+        b = c;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* base = reinterpret_cast<T*>(lds_raw);
+    T* alt;
     for (int k = 0; k < tl.n; ++k) {
         const PotLevel<T> G = tl.lv[k];
-        const PotLevel<T> S = tail_view(tl, base, k);
+        const PotLevel<T> S = tail_view(tl, base, k, &alt);
         const int n = S.nx * S.ny;
         for (int t = threadIdx.x; t < n; t += TAIL_T) {
             const int j = t / S.nx, i = t - j * S.nx;
@@ -454,9 +485,11 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         }
     }
     __syncthreads();
+    const int sw = 2 * ((tl.nu1 + 1) / 2);  // even
     for (int k = 0; k + 1 < tl.n; ++k) {
-        const PotLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
-        tail_sweeps(F, tl.nu1, T(1));
+        T* altc;
+        const PotLevel<T> F = tail_view(tl, base, k, &alt), Cc = tail_view(tl, base, k + 1, &altc);
+        tail_jacobi(F, alt, sw);
         const int n = Cc.nx * Cc.ny;
         for (int t = threadIdx.x; t < n; t += TAIL_T) {
             const int J = t / Cc.nx, I = t - J * Cc.nx;
@@ -472,19 +505,26 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         }
         __syncthreads();
     }
-    tail_sweeps(tail_view(tl, base, tl.n - 1), tl.coarse_sweeps, tl.omega);
+    {
+        const PotLevel<T> S = tail_view(tl, base, tl.n - 1, &alt);
+        if (S.ny <= 4)
+            tail_jacobi(S, alt, 2 * tl.coarse_sweeps);
+        else
+            tail_sor(S, tl.coarse_sweeps, tl.omega);
+    }
     for (int k = tl.n - 2; k >= 0; --k) {
-        const PotLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
+        T* altc;
+        const PotLevel<T> F = tail_view(tl, base, k, &alt), Cc = tail_view(tl, base, k + 1, &altc);
         const int n = F.nx * F.ny;
         for (int t = threadIdx.x; t < n; t += TAIL_T) {
             const int j = t / F.nx, i = t - j * F.nx;
             F.u[t] += prolong_at(Cc, i, j);
         }
         __syncthreads();
-        tail_sweeps(F, tl.nu2, T(1));
+        tail_jacobi(F, alt, sw);
     }
     const PotLevel<T> G = tl.lv[0];
-    const PotLevel<T> S = tail_view(tl, base, 0);
+    const PotLevel<T> S = tail_view(tl, base, 0, &alt);
     for (int t = threadIdx.x; t < S.nx * S.ny; t += TAIL_T) {
         const int j = t / S.nx, i = t - j * S.nx;
         G.u[(long long)j * G.pitch + i] = S.u[t];
@@ -536,12 +576,12 @@ void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hip
 
 template <typename T>
 void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
-                           unsigned long long* res, hipStream_t s) {
+                           unsigned long long* res, int inner, hipStream_t s) {
     const dim3 g((L.nx + TSX - 1) / TSX, (L.ny + TSY - 1) / TSY);
     const PotLevel<T> Cl = prolong_from ? *prolong_from : PotLevel<T>{};
     if (res) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, res, 2LL, 0ULL);
 #define FCD_TILE_LAUNCH(P, M) \
-    hipLaunchKernelGGL((k_mg_smooth_tile<T, P, M>), g, dim3(TS_T), 0, s, L, uin, uout, Cl, res)
+    hipLaunchKernelGGL((k_mg_smooth_tile<T, P, M>), g, dim3(TS_T), 0, s, L, uin, uout, Cl, res, inner)
     if (prolong_from) {
         if (mode == 0) FCD_TILE_LAUNCH(true, 0);
         else if (mode == 1) FCD_TILE_LAUNCH(true, 1);
@@ -568,7 +608,7 @@ void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mod
 template <typename T>
 size_t mg_tail_lds_bytes(const MgTail<T>& tl) {
     size_t n = 0;
-    for (int k = 0; k < tl.n; ++k) n += 3 * (size_t)tl.lv[k].nx * tl.lv[k].ny;
+    for (int k = 0; k < tl.n; ++k) n += 4 * (size_t)tl.lv[k].nx * tl.lv[k].ny;
     return n * sizeof(T);
 }
 
@@ -588,7 +628,7 @@ void launch_psi_history(T* psi, T* prev, int nx, int ny, int pitch, int mode, hi
     template void launch_mg_restrict_mu<T>(const T*, int, T*, int, int, int, hipStream_t);                \
     template void launch_mg_restrict_residual<T>(const PotLevel<T>&, const PotLevel<T>&, hipStream_t);    \
     template void launch_mg_smooth_tile<T>(const PotLevel<T>&, const T*, T*, const PotLevel<T>*, int,         \
-                                           unsigned long long*, hipStream_t);                                 \
+                                           unsigned long long*, int, hipStream_t);                            \
     template void launch_mg_restrict_tile<T>(const PotLevel<T>&, const PotLevel<T>&, int, hipStream_t);       \
     template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
     template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \

@@ -28,7 +28,7 @@ EXPORTS = (
     "fcd_scratch_bytes", "fcd_create", "fcd_set_params", "fcd_init_compound_droplet",
     "fcd_init_fields", "fcd_solve_potential", "fcd_step", "fcd_read_moments", "fcd_read_state",
     "fcd_write_state", "fcd_read_psi", "fcd_write_psi", "fcd_deformation", "fcd_stats", "fcd_timing",
-    "fcd_timing_read", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
+    "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
     "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
     "fcd_batch_read_moments", "fcd_batch_stats", "fcd_batch_destroy",
@@ -95,6 +95,7 @@ def lib():
         L.fcd_stats.argtypes = [H, dp]
         L.fcd_timing.argtypes = [H, C.c_int32]
         L.fcd_timing_read.argtypes = [H, dp]
+        L.fcd_use_graphs.argtypes = [H, C.c_int32]
         L.fcd_sync.argtypes = [H]
         L.fcd_destroy.argtypes = [H]
         L.fcd_adjoint_bytes.argtypes = [C.POINTER(fcd_lattice), C.c_int32, C.c_int32]
@@ -199,6 +200,10 @@ def fcd_stats(h):
 
 def fcd_timing(h, enable: bool):
     _check(lib().fcd_timing(h, 1 if enable else 0), "fcd_timing")
+
+
+def fcd_use_graphs(h, enable: bool):
+    _check(lib().fcd_use_graphs(h, 1 if enable else 0), "fcd_use_graphs")
 
 
 def fcd_timing_read(h) -> dict:

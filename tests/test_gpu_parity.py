@@ -11,7 +11,7 @@ import sys
 import numpy as np
 import pytest
 
-from fcd_inputs import (Workload, channel_drive, random_phase_fields, single_channel_large,
+from fcd_inputs import (Workload, adjoint_channel, channel_drive, random_phase_fields, single_channel_large,
                         single_channel_small)
 from oracle import OracleSim, OracleSolver
 
@@ -219,6 +219,29 @@ def test_bitwise_deterministic():
         runs.append(g.state())
         g.close()
     assert np.array_equal(runs[0], runs[1])
+
+
+@pytest.mark.parametrize("precision", [fcd.FCD_FP64, fcd.FCD_FP32])
+def test_graph_replays_equal_eager_launches(precision):
+    """The multigrid V-cycle replayed as HIP graphs gives bitwise the eager results, step
+    after step (each step replays the graphs several times, with the convergence tests'
+    eager kernels and copies in between)."""
+    w = adjoint_channel()
+    say(f"case graphs vs eager 512x128 precision {precision}")
+    solve = MG_TIGHT if precision == fcd.FCD_FP64 else FP32_SOLVE
+    a = Channel(w, precision=precision, **solve)
+    b = Channel(w, precision=precision, **solve)
+    fcd.fcd_use_graphs(b.h, False)
+    for ch in (a, b):
+        ch.init_droplet()
+    for _ in range(4):
+        a.step(3)
+        b.step(3)
+        assert np.array_equal(a.state(), b.state())
+        assert np.array_equal(a.psi_dense(), b.psi_dense())
+    assert a.stats()[1] == b.stats()[1]
+    a.close()
+    b.close()
 
 
 def test_full_size_init_and_fieldless_steps():
