@@ -263,6 +263,20 @@ fcd_status fcd_batch_deformation(fcd_batch* b, double* out);
 fcd_status fcd_batch_read_state(fcd_batch* b, int32_t k, double* out);
 fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double* out);
 
+/* Launch schedule of the batch: kernels run over 64 x tile_rows tiles (tile_rows 1, 2,
+ * 4 or 8) and the potential sweeps are replayed as HIP graphs of block_sweeps sweeps (a
+ * multiple of pot_check_every of channel 0, the interval of the device-side convergence
+ * test).  The schedule changes launch geometry only: states are bitwise the same under
+ * every schedule.  Default: tile_rows 4, block_sweeps 8 * pot_check_every. */
+fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps);
+
+/* Autotuner: tries every tile_rows in {1, 2, 4, 8} with block_sweeps in
+ * {2, 8, 32} * pot_check_every, each for steps_per_candidate real steps of the batch
+ * (timed with HIP events; one untimed step per tile shape first), keeps the fastest and
+ * writes it to choice = {tile_rows, block_sweeps}.  Advances the batch by
+ * 4 (1 + 3 steps_per_candidate) steps.  Sync. */
+fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[2]);
+
 /* out = {steps, SOR sweeps launched, largest final residual of the last solve}. */
 fcd_status fcd_batch_stats(fcd_batch* b, double out[3]);
 

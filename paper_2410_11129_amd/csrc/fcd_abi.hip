@@ -382,9 +382,9 @@ void restrict_mu_all(fcd_handle* h) {
 // graph, capturing it on first use; eagerly while per-kernel timing is on or graphs
 // are disabled.
 template <typename F>
-fcd_status run_graph(fcd_handle* h, const void* k1, const void* k2, int kind, F&& record) {
-    GraphCache& G = h->graphs;
-    if (!G.enabled || h->timer.on) {
+fcd_status run_graph_on(GraphCache& G, hipStream_t& stream, bool eager, const void* k1, const void* k2, int kind,
+                        F&& record) {
+    if (!G.enabled || eager) {
         record();
         return hip_check(hipGetLastError(), "launch");
     }
@@ -393,12 +393,12 @@ fcd_status run_graph(fcd_handle* h, const void* k1, const void* k2, int kind, F&
         fcd_status st = FCD_OK;
         if (!G.cap) st = hip_check(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking), "capture stream");
         if (st) return st;
-        hipStream_t saved = h->stream;
+        hipStream_t saved = stream;
         st = hip_check(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal), "begin capture");
         if (st) return st;
-        h->stream = G.cap;
+        stream = G.cap;
         record();
-        h->stream = saved;
+        stream = saved;
         hipGraph_t graph = nullptr;
         st = hip_check(hipStreamEndCapture(G.cap, &graph), "end capture");
         if (st) return st;
@@ -407,7 +407,12 @@ fcd_status run_graph(fcd_handle* h, const void* k1, const void* k2, int kind, F&
         if (st) return st;
         G.entries.push_back({k1, k2, kind, exec});
     }
-    return hip_check(hipGraphLaunch(exec, h->stream), "graph launch");
+    return hip_check(hipGraphLaunch(exec, stream), "graph launch");
+}
+
+template <typename F>
+fcd_status run_graph(fcd_handle* h, const void* k1, const void* k2, int kind, F&& record) {
+    return run_graph_on(h->graphs, h->stream, h->timer.on, k1, k2, kind, record);
 }
 
 // SOR sweeps per V-cycle on a coarsest level with ny rows: a few suffice on the two-row
@@ -726,20 +731,24 @@ fcd_status copy_in_impl(fcd_handle* h, void* dst, int nplanes, const double* in)
 // ---------------------------------------------------------------------------------
 // Batches.
 // ---------------------------------------------------------------------------------
-constexpr int BT_X = 64, BT_Y = 4;  // tile of the batched kernels
+constexpr int BT_X = 64;  // tile width of the batched kernels; rows 1, 2, 4 or 8 (shape 0..3)
+constexpr int BT_ROWS[fcd::BATCH_SHAPES] = {1, 2, 4, 8};
+constexpr int BATCH_MAX_CHANNELS = 65536;
 
 struct BatchLayout {
     std::vector<int> pitch;
     std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev;  // into state / aux
-    std::vector<int> tile0, tiles_x, ctile0, ctiles_x;
-    int ntiles = 0, nctiles = 0;
+    std::vector<int> tile0[fcd::BATCH_SHAPES], tiles_x[fcd::BATCH_SHAPES];
+    std::vector<int> ctile0[fcd::BATCH_SHAPES], ctiles_x[fcd::BATCH_SHAPES];
+    int ntiles[fcd::BATCH_SHAPES] = {}, nctiles[fcd::BATCH_SHAPES] = {};
     size_t state_bytes = 0, aux_bytes = 0, scratch_bytes = 0;
-    size_t off_inst = 0, off_tiles = 0, off_ctiles = 0, off_res = 0, off_active = 0, off_counts = 0;
+    size_t off_inst = 0, off_tiles[fcd::BATCH_SHAPES] = {}, off_ctiles[fcd::BATCH_SHAPES] = {};
+    size_t off_res = 0, off_active = 0, off_counts = 0;
     size_t off_rows = 0, off_cent = 0, off_result = 0;
 };
 
 fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
-    if (n < 1) return fail(FCD_ERR_ARG, "a batch needs at least one channel");
+    if (n < 1 || n > BATCH_MAX_CHANNELS) return fail(FCD_ERR_ARG, "a batch holds 1 to 65536 channels");
     if (!lats) return fail(FCD_ERR_ARG, "lattices are null");
     const int prec = lats[0].precision;
     int max_ny = 0;
@@ -766,23 +775,28 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
         L->aux_bytes += plane;
         L->off_prev.push_back(L->aux_bytes);
         L->aux_bytes += plane;
-        const int tx = (l.nx + BT_X - 1) / BT_X, ty = (l.ny + BT_Y - 1) / BT_Y;
-        L->tile0.push_back(L->ntiles);
-        L->tiles_x.push_back(tx);
-        L->ntiles += tx * ty;
-        const int cx = ((l.nx + 1) / 2 + BT_X - 1) / BT_X, cy = ((l.ny + 1) / 2 + BT_Y - 1) / BT_Y;
-        L->ctile0.push_back(L->nctiles);
-        L->ctiles_x.push_back(cx);
-        L->nctiles += cx * cy;
+        for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
+            const int ty = BT_ROWS[s];
+            const int tx = (l.nx + BT_X - 1) / BT_X, tyc = (l.ny + ty - 1) / ty;
+            L->tile0[s].push_back(L->ntiles[s]);
+            L->tiles_x[s].push_back(tx);
+            L->ntiles[s] += tx * tyc;
+            const int cx = ((l.nx + 1) / 2 + BT_X - 1) / BT_X, cy = ((l.ny + 1) / 2 + ty - 1) / ty;
+            L->ctile0[s].push_back(L->nctiles[s]);
+            L->ctiles_x[s].push_back(cx);
+            L->nctiles[s] += cx * cy;
+        }
     }
     const size_t inst_sz = prec == FCD_FP64 ? sizeof(fcd::BatchInst<double>) : sizeof(fcd::BatchInst<float>);
     size_t off = 0;
     L->off_inst = off;
     off = align256(off + (size_t)n * inst_sz);
-    L->off_tiles = off;
-    off = align256(off + (size_t)L->ntiles * sizeof(int));
-    L->off_ctiles = off;
-    off = align256(off + (size_t)L->nctiles * sizeof(int));
+    for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
+        L->off_tiles[s] = off;
+        off = align256(off + (size_t)L->ntiles[s] * sizeof(int));
+        L->off_ctiles[s] = off;
+        off = align256(off + (size_t)L->nctiles[s] * sizeof(int));
+    }
     L->off_res = off;
     off = align256(off + 2 * (size_t)n * sizeof(unsigned long long));
     L->off_active = off;
@@ -792,7 +806,7 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     L->off_rows = off;
     off = align256(off + (size_t)max_ny * 8 * sizeof(double));
     L->off_cent = off;
-    off = align256(off + 8 * sizeof(double));
+    off = align256(off + 32 * sizeof(double));
     L->off_result = off;
     off = align256(off + (size_t)n * 4 * sizeof(double));
     L->scratch_bytes = off;
@@ -818,6 +832,10 @@ struct fcd_batch {
     long long iters;
     double last_resid;
     double* host;  // pinned: [0] active count and NaN count (two ints), [1..] n x 4 diagnostics
+    // launch schedule: tile shape (rows 1, 2, 4, 8) and sweeps per graph-launched block
+    int shape;
+    int block_sweeps;
+    GraphCache graphs;
 };
 
 namespace {
@@ -837,10 +855,24 @@ T* bptr(char* base, size_t off) {
     return reinterpret_cast<T*>(base + off);
 }
 
+fcd::BatchTiles btiles(const fcd_batch* b) {
+    fcd::BatchTiles t;
+    t.shape = b->shape;
+    t.ntiles = b->L.ntiles[b->shape];
+    t.nctiles = b->L.nctiles[b->shape];
+    t.tiles = reinterpret_cast<const int*>(b->scratch + b->L.off_tiles[b->shape]);
+    t.ctiles = reinterpret_cast<const int*>(b->scratch + b->L.off_ctiles[b->shape]);
+    return t;
+}
+
 template <typename T>
 fcd_status batch_upload(fcd_batch* b) {
     std::vector<fcd::BatchInst<T>> inst(b->n);
-    std::vector<int> tiles(b->L.ntiles), ctiles(b->L.nctiles);
+    std::vector<int> tiles[fcd::BATCH_SHAPES], ctiles[fcd::BATCH_SHAPES];
+    for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
+        tiles[s].resize(b->L.ntiles[s]);
+        ctiles[s].resize(b->L.nctiles[s]);
+    }
     for (int k = 0; k < b->n; ++k) {
         fcd::BatchInst<T>& I = inst[k];
         const fcd_lattice& l = b->lat[k];
@@ -863,24 +895,32 @@ fcd_status batch_upload(fcd_batch* b) {
         I.L0.H0y = T(p.H0 * std::sin(p.alpha));
         I.omega = T(p.pot_omega > 0.0 ? p.pot_omega : sor_omega_opt(l.ny));
         I.thr = p.pot_tol * std::fabs(p.H0);
-        I.tile0 = b->L.tile0[k];
-        I.tiles_x = b->L.tiles_x[k];
-        I.ctile0 = b->L.ctile0[k];
-        I.ctiles_x = b->L.ctiles_x[k];
         I.has_field = p.H0 != 0.0;
-        const int nt = (l.nx + BT_X - 1) / BT_X * ((l.ny + BT_Y - 1) / BT_Y);
-        for (int t = 0; t < nt; ++t) tiles[I.tile0 + t] = k;
-        const int nc = ((l.nx + 1) / 2 + BT_X - 1) / BT_X * (((l.ny + 1) / 2 + BT_Y - 1) / BT_Y);
-        for (int t = 0; t < nc; ++t) ctiles[I.ctile0 + t] = k;
+        for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
+            const int ty = BT_ROWS[s];
+            I.tile0[s] = b->L.tile0[s][k];
+            I.tiles_x[s] = b->L.tiles_x[s][k];
+            I.ctile0[s] = b->L.ctile0[s][k];
+            I.ctiles_x[s] = b->L.ctiles_x[s][k];
+            const int nt = (l.nx + BT_X - 1) / BT_X * ((l.ny + ty - 1) / ty);
+            for (int t = 0; t < nt; ++t) tiles[s][I.tile0[s] + t] = k;
+            const int nc = ((l.nx + 1) / 2 + BT_X - 1) / BT_X * (((l.ny + 1) / 2 + ty - 1) / ty);
+            for (int t = 0; t < nc; ++t) ctiles[s][I.ctile0[s] + t] = k;
+        }
     }
     fcd_status st = hip_check(hipMemcpy(b->scratch + b->L.off_inst, inst.data(), inst.size() * sizeof(inst[0]),
                                         hipMemcpyHostToDevice), "descriptor upload");
+    for (int s = 0; s < fcd::BATCH_SHAPES && !st; ++s) {
+        st = hip_check(hipMemcpy(b->scratch + b->L.off_tiles[s], tiles[s].data(), tiles[s].size() * sizeof(int),
+                                 hipMemcpyHostToDevice), "tile table upload");
+        if (!st)
+            st = hip_check(hipMemcpy(b->scratch + b->L.off_ctiles[s], ctiles[s].data(),
+                                     ctiles[s].size() * sizeof(int), hipMemcpyHostToDevice), "tile table upload");
+    }
     if (st) return st;
-    st = hip_check(hipMemcpy(b->scratch + b->L.off_tiles, tiles.data(), tiles.size() * sizeof(int),
-                             hipMemcpyHostToDevice), "tile table upload");
-    if (st) return st;
-    return hip_check(hipMemcpy(b->scratch + b->L.off_ctiles, ctiles.data(), ctiles.size() * sizeof(int),
-                               hipMemcpyHostToDevice), "tile table upload");
+    // residual slots start (and are always left) at zero
+    return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 2 * (size_t)b->n * sizeof(unsigned long long)),
+                     "residual slots");
 }
 
 template <typename T>
@@ -888,82 +928,138 @@ const fcd::BatchInst<T>* binst(const fcd_batch* b) {
     return reinterpret_cast<const fcd::BatchInst<T>*>(b->scratch + b->L.off_inst);
 }
 
-// Per-channel residuals and activity flags; returns the number of channels still above
-// their threshold (and fails on a NaN residual).
+int check_interval(const fcd_batch* b) { return std::max(1, b->prm[0].pot_check_every); }
+
+// A block of `block_sweeps` SOR sweeps with a device-side convergence test after every
+// `check` sweeps (block_sweeps is a multiple of check).
 template <typename T>
-fcd_status batch_check(fcd_batch* b, int* active_count) {
+void batch_block(fcd_batch* b) {
+    const fcd::BatchTiles t = btiles(b);
+    int* active = bptr<int>(b->scratch, b->L.off_active);
+    const int check = check_interval(b);
+    for (int s = 1; s <= b->block_sweeps; ++s) {
+        fcd::launch_batch_sweep<T>(binst<T>(b), t, active, b->stream);
+        if (s % check == 0)
+            fcd::launch_batch_check<T>(binst<T>(b), t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res),
+                                       active, bptr<int>(b->scratch, b->L.off_counts), b->stream);
+    }
+}
+
+template <typename T>
+fcd_status batch_read_counts(fcd_batch* b, int* active_count) {
     int* counts = bptr<int>(b->scratch, b->L.off_counts);
-    fcd::launch_batch_residual<T>(binst<T>(b), bptr<int>(b->scratch, b->L.off_tiles), b->L.ntiles, b->n,
-                                  bptr<unsigned long long>(b->scratch, b->L.off_res),
-                                  bptr<int>(b->scratch, b->L.off_active), counts, b->stream);
-    fcd_status st = hip_check(hipGetLastError(), "batch residual launch");
-    if (st) return st;
-    st = hip_check(hipMemcpyAsync(b->host, counts, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream),
-                   "batch residual copy");
-    if (st) return st;
-    st = hip_check(hipMemcpyAsync(b->host + 1, bptr<unsigned long long>(b->scratch, b->L.off_res),
-                                  2 * (size_t)b->n * sizeof(double), hipMemcpyDeviceToHost, b->stream),
-                   "batch residual copy");
-    if (st) return st;
-    st = hip_check(hipStreamSynchronize(b->stream), "batch residual sync");
+    fcd_status st = hip_check(hipMemcpyAsync(b->host, counts, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream),
+                              "batch count copy");
+    if (!st) st = hip_check(hipStreamSynchronize(b->stream), "batch count sync");
     if (st) return st;
     int c[2];
     std::memcpy(c, b->host, sizeof(c));
-    double rmax = 0.0;
-    for (int k = 0; k < b->n; ++k) rmax = b->host[1 + 2 * k] > rmax ? b->host[1 + 2 * k] : rmax;
-    b->last_resid = rmax;
     if (c[1] > 0) return fail(FCD_ERR_DIVERGED, "a channel's potential residual is NaN");
     *active_count = c[0];
     return FCD_OK;
 }
 
+// Potential solves of every channel: all channels start active; the first test runs
+// before any sweep; blocks of sweeps (HIP graphs) follow until no channel is active.
+// The host reads the active count after each block, except that it launches the blocks
+// the previous solve needed minus one without reading.  Which sweeps a channel receives
+// is decided on the device, so the result does not depend on the block size.
 template <typename T>
-fcd_status batch_solve(fcd_batch* b, int max_iters, int check_every) {
+fcd_status batch_solve(fcd_batch* b, int max_iters) {
+    const fcd::BatchTiles t = btiles(b);
     int* active = bptr<int>(b->scratch, b->L.off_active);
-    const int* ctiles = bptr<int>(b->scratch, b->L.off_ctiles);
     fcd::launch_fill<int>(active, b->n, 1, b->stream);
-    int it = 0;
-    const int defer = b->last_iters > 1 ? b->last_iters - 1 : 0;
-    if (defer > 0 && defer <= max_iters) {
-        for (int s = 0; s < defer; ++s) fcd::launch_batch_sweep<T>(binst<T>(b), ctiles, b->L.nctiles, active, b->stream);
-        it = defer;
-    }
-    int left = 0;
-    fcd_status st = batch_check<T>(b, &left);
+    fcd::launch_batch_check<T>(binst<T>(b), t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res), active,
+                               bptr<int>(b->scratch, b->L.off_counts), b->stream);
+    fcd_status st = hip_check(hipGetLastError(), "batch check launch");
     if (st) return st;
-    while (left > 0 && it < max_iters) {
-        const int m = check_every < max_iters - it ? check_every : max_iters - it;
-        for (int s = 0; s < m; ++s) fcd::launch_batch_sweep<T>(binst<T>(b), ctiles, b->L.nctiles, active, b->stream);
-        it += m;
-        st = batch_check<T>(b, &left);
+    int left = 1, it = 0;
+    const int G = b->block_sweeps;
+    int blind = b->last_iters > G ? (b->last_iters + G - 1) / G - 1 : 0;
+    if (blind == 0) {
+        st = batch_read_counts<T>(b, &left);
+        if (st) return st;
+    }
+    while (left > 0) {
+        if (it >= max_iters) break;
+        st = run_graph_on(b->graphs, b->stream, false, nullptr, nullptr, 1000 * b->shape + G,
+                          [&]() { batch_block<T>(b); });
+        if (st) return st;
+        it += G;
+        if (blind > 0) {
+            --blind;
+            continue;
+        }
+        st = batch_read_counts<T>(b, &left);
         if (st) return st;
     }
     b->iters += it;
     b->last_iters = it;
+    b->last_resid = 0.0;
     if (left > 0) return fail(FCD_ERR_NOT_CONVERGED, "a channel's potential solve reached pot_max_iters");
     return FCD_OK;
 }
 
 template <typename T>
 fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
-    const int* tiles = bptr<int>(b->scratch, b->L.off_tiles);
     const fcd_params& p0 = b->prm[0];
     for (int n = 0; n < nsteps; ++n) {
-        fcd::launch_batch_phase<T>(binst<T>(b), tiles, b->L.ntiles, b->cur, b->stream);
-        if (p0.pot_extrapolate)
-            fcd::launch_batch_psi_history<T>(binst<T>(b), tiles, b->L.ntiles, b->hist >= 2 ? 1 : 0, b->stream);
+        const fcd::BatchTiles t = btiles(b);
+        fcd::launch_batch_phase<T>(binst<T>(b), t, b->cur, b->stream);
+        if (p0.pot_extrapolate) fcd::launch_batch_psi_history<T>(binst<T>(b), t, b->hist >= 2 ? 1 : 0, b->stream);
         fcd_status st = hip_check(hipGetLastError(), "batch phase launch");
         if (st) return st;
-        st = batch_solve<T>(b, p0.pot_max_iters, p0.pot_check_every);
+        st = batch_solve<T>(b, p0.pot_max_iters);
         if (st) return st;
         ++b->hist;
-        fcd::launch_batch_collide<T>(binst<T>(b), tiles, b->L.ntiles, b->cur, b->stream);
+        fcd::launch_batch_collide<T>(binst<T>(b), t, b->cur, b->stream);
         st = hip_check(hipGetLastError(), "batch collide launch");
         if (st) return st;
         b->cur = 1 - b->cur;
         ++b->steps;
     }
     return FCD_OK;
+}
+
+// Autotuner: every (tile shape, block size) candidate advances the batch by `steps`
+// real steps, timed with HIP events on the batch stream after one untimed step per
+// shape; the fastest is kept.  The candidates differ only in launch geometry and in how
+// sweeps are grouped into graph launches, so the states they produce are bitwise the
+// same as an untuned run's.
+template <typename T>
+fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
+    const int check = check_interval(b);
+    const int blocks[3] = {2 * check, 8 * check, 32 * check};
+    double best = 1e300;
+    int best_shape = b->shape, best_block = b->block_sweeps;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    fcd_status st = hip_check(hipEventCreate(&e0), "event");
+    if (!st) st = hip_check(hipEventCreate(&e1), "event");
+    for (int s = 0; s < fcd::BATCH_SHAPES && !st; ++s) {
+        for (int g = 0; g < 3 && !st; ++g) {
+            b->shape = s;
+            b->block_sweeps = blocks[g];
+            if (g == 0) st = batch_step_impl<T>(b, 1);  // warms the shape's kernels and graphs
+            if (!st) st = hip_check(hipEventRecord(e0, b->stream), "event");
+            if (!st) st = batch_step_impl<T>(b, steps);
+            if (!st) st = hip_check(hipEventRecord(e1, b->stream), "event");
+            if (!st) st = hip_check(hipEventSynchronize(e1), "event");
+            float ms = 0.f;
+            if (!st) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            if (!st && ms < best) {
+                best = ms;
+                best_shape = s;
+                best_block = blocks[g];
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    b->shape = best_shape;
+    b->block_sweeps = best_block;
+    choice[0] = BT_ROWS[best_shape];
+    choice[1] = best_block;
+    return st;
 }
 
 template <typename T>
@@ -975,7 +1071,7 @@ fcd_status batch_init_impl(fcd_batch* b, const double* geom) {
         fcd::launch_init_droplet<T>(bptr<T>(b->state, b->L.off_d0[k]), l.nx, l.ny, b->L.pitch[k], geom[4 * k],
                                     geom[4 * k + 1], geom[4 * k + 2], geom[4 * k + 3], p.xi, u_scale, b->stream);
     }
-    fcd::launch_batch_fill_psi<T>(binst<T>(b), bptr<int>(b->scratch, b->L.off_tiles), b->L.ntiles, b->stream);
+    fcd::launch_batch_fill_psi<T>(binst<T>(b), btiles(b), b->stream);
     b->cur = 0;
     b->hist = 0;
     b->last_iters = 0;
@@ -1503,6 +1599,8 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     b->cur = b->hist = b->last_iters = 0;
     b->steps = b->iters = 0;
     b->last_resid = 0.0;
+    b->shape = 2;  // 64 x 4 tiles
+    b->block_sweeps = 8 * std::max(1, prms[0].pot_check_every);
     if (hipHostMalloc(reinterpret_cast<void**>(&b->host), (1 + 4 * (size_t)n) * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         delete b;
@@ -1546,6 +1644,24 @@ fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double
     if (!b || !out || k < 0 || k >= b->n) return fail(FCD_ERR_ARG, "bad batch channel or null output");
     if (mask == 0 || (mask & ~uint32_t(FCD_M_ALL))) return fail(FCD_ERR_ARG, "bad mask");
     return FCD_BDISPATCH(b, batch_moments_impl)(b, k, mask, out);
+}
+
+fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[2]) {
+    if (!b || !choice) return fail(FCD_ERR_ARG, "null argument");
+    if (steps_per_candidate < 1) return fail(FCD_ERR_ARG, "steps_per_candidate must be >= 1");
+    return FCD_BDISPATCH(b, batch_autotune_impl)(b, steps_per_candidate, choice);
+}
+
+fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps) {
+    if (!b) return fail(FCD_ERR_ARG, "batch is null");
+    int s = -1;
+    for (int k = 0; k < fcd::BATCH_SHAPES; ++k)
+        if (BT_ROWS[k] == tile_rows) s = k;
+    if (s < 0) return fail(FCD_ERR_ARG, "tile_rows must be 1, 2, 4 or 8");
+    if (block_sweeps < 1 || block_sweeps % check_interval(b)) return fail(FCD_ERR_ARG, "block_sweeps must be a positive multiple of pot_check_every");
+    b->shape = s;
+    b->block_sweeps = block_sweeps;
+    return FCD_OK;
 }
 
 fcd_status fcd_batch_stats(fcd_batch* b, double out[3]) {

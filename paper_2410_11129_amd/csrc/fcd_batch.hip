@@ -1,8 +1,11 @@
 // fcd_batch.hip -- many independent channels of uneven size stepped together: every
 // kernel of the step is launched once for the whole batch over a flattened list of
-// 64x4-node tiles, each tile mapped to its channel through a table.  Per-channel
-// constants live in device descriptors; the potential solve is four-colour SOR with a
-// per-channel convergence flag so converged channels stop relaxing.
+// 64 x TY-node tiles, each tile mapped to its channel through a table (one table per
+// tile shape; the shape is chosen by the batch autotuner).  Per-channel constants live
+// in device descriptors.  The potential solve is four-colour SOR; every `check` sweeps a
+// residual pass and a decision kernel update per-channel activity flags on the device,
+// so converged channels stop relaxing and the result does not depend on how the host
+// groups the sweeps into launches or graphs.
 #include <hip/hip_runtime.h>
 
 #include "fcd_batch.hpp"
@@ -13,63 +16,69 @@
 namespace fcd {
 
 constexpr int TBX = 64;
-constexpr int TBY = 4;
 
-template <typename T>
-__device__ __forceinline__ bool tile_node(const BatchInst<T>& B, int lt, int tiles_x, int& i, int& j) {
-    const int ty = lt / tiles_x, tx = lt - ty * tiles_x;
-    i = tx * TBX + threadIdx.x;
-    j = ty * TBY + threadIdx.y;
-    return true;
+template <int TY>
+constexpr int shape_index() {
+    return TY == 1 ? 0 : TY == 2 ? 1 : TY == 4 ? 2 : 3;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(TBX* TBY) kb_phase(const BatchInst<T>* __restrict__ inst,
-                                                     const int* __restrict__ tile_inst, int cur) {
-    const int k = tile_inst[blockIdx.x];
-    const BatchInst<T>& B = inst[k];
+template <typename T, int TY>
+__device__ __forceinline__ void tile_node(const BatchInst<T>& B, int tile, bool colour_grid, int& i, int& j) {
+    constexpr int S = shape_index<TY>();
+    const int lt = tile - (colour_grid ? B.ctile0[S] : B.tile0[S]);
+    const int tx = colour_grid ? B.ctiles_x[S] : B.tiles_x[S];
+    const int ty = lt / tx, txi = lt - ty * tx;
+    i = txi * TBX + threadIdx.x;
+    j = ty * TY + threadIdx.y;
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(TBX* TY) kb_phase(const BatchInst<T>* __restrict__ inst,
+                                                    const int* __restrict__ tile_inst, int cur) {
+    const BatchInst<T>& B = inst[tile_inst[blockIdx.x]];
     int i, j;
-    tile_node(B, blockIdx.x - B.tile0, B.tiles_x, i, j);
+    tile_node<T, TY>(B, blockIdx.x, false, i, j);
     if (i >= B.P.nx || j >= B.P.ny) return;
     phase_node(static_cast<const T*>(B.dist[cur]), B.phi, B.P, i, j);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(TBX* TBY) kb_collide_stream(const BatchInst<T>* __restrict__ inst,
-                                                              const int* __restrict__ tile_inst, int cur) {
-    const int k = tile_inst[blockIdx.x];
-    const BatchInst<T>& B = inst[k];
+template <typename T, int TY>
+__global__ void __launch_bounds__(TBX* TY) kb_collide_stream(const BatchInst<T>* __restrict__ inst,
+                                                             const int* __restrict__ tile_inst, int cur) {
+    const BatchInst<T>& B = inst[tile_inst[blockIdx.x]];
     int i, j;
-    tile_node(B, blockIdx.x - B.tile0, B.tiles_x, i, j);
+    tile_node<T, TY>(B, blockIdx.x, false, i, j);
     if (i >= B.P.nx || j >= B.P.ny) return;
     collide_stream_node(static_cast<const T*>(B.dist[cur]), B.dist[1 - cur], B.phi, B.L0.u, B.P, i, j);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(TBX* TBY) kb_sor_colour(const BatchInst<T>* __restrict__ inst,
-                                                          const int* __restrict__ ctile_inst,
-                                                          const int* __restrict__ active, int colour) {
+template <typename T, int TY>
+__global__ void __launch_bounds__(TBX* TY) kb_sor_colour(const BatchInst<T>* __restrict__ inst,
+                                                         const int* __restrict__ ctile_inst,
+                                                         const int* __restrict__ active, int colour) {
     const int k = ctile_inst[blockIdx.x];
     if (!active[k]) return;
     const BatchInst<T>& B = inst[k];
     int ti, tj;
-    tile_node(B, blockIdx.x - B.ctile0, B.ctiles_x, ti, tj);
+    tile_node<T, TY>(B, blockIdx.x, true, ti, tj);
     const int i = 2 * ti + (colour & 1), j = 2 * tj + (colour >> 1);
     if (i >= B.P.nx || j >= B.P.ny) return;
     relax_node(B.L0, i, j, B.omega);
 }
 
-// Per-channel max-norms of the potential residual (res[2k]) and of C psi' (res[2k+1]):
-// block max, one atomicMax per block and quantity into the channel's slots.
-template <typename T>
-__global__ void __launch_bounds__(TBX* TBY) kb_residual(const BatchInst<T>* __restrict__ inst,
-                                                        const int* __restrict__ tile_inst,
-                                                        unsigned long long* __restrict__ res) {
-    __shared__ double wmax[2][TBY];
+// Per-channel max-norms of the potential residual (res[2k]) and of C psi' (res[2k+1])
+// of the channels still active: block max, one atomicMax per block and quantity.
+template <typename T, int TY>
+__global__ void __launch_bounds__(TBX* TY) kb_residual(const BatchInst<T>* __restrict__ inst,
+                                                       const int* __restrict__ tile_inst,
+                                                       const int* __restrict__ active,
+                                                       unsigned long long* __restrict__ res) {
+    __shared__ double wmax[2][TY];
     const int k = tile_inst[blockIdx.x];
+    if (!active[k]) return;  // uniform over the block
     const BatchInst<T>& B = inst[k];
     int i, j;
-    tile_node(B, blockIdx.x - B.tile0, B.tiles_x, i, j);
+    tile_node<T, TY>(B, blockIdx.x, false, i, j);
     double v = 0.0, sc = 0.0;
     if (i < B.P.nx && j < B.P.ny && B.has_field) {
         const MgEval<T> r = mg_eval(B.L0, i, j);
@@ -89,34 +98,58 @@ __global__ void __launch_bounds__(TBX* TBY) kb_residual(const BatchInst<T>* __re
     __syncthreads();
     if (threadIdx.y == 0 && threadIdx.x < 2) {
         double m = wmax[threadIdx.x][0];
-        for (int w = 1; w < TBY; ++w) m = nan_max(m, wmax[threadIdx.x][w]);
+        for (int w = 1; w < TY; ++w) m = nan_max(m, wmax[threadIdx.x][w]);
         atomicMax(res + 2 * k + threadIdx.x, (unsigned long long)__double_as_longlong(m));
     }
 }
 
-// active[k] = residual above max(thr, floor * scale); counts[0] = channels still
-// active, counts[1] = channels whose residual is NaN.  One thread per channel.
-template <typename T>
-__global__ void kb_decide(const BatchInst<T>* __restrict__ inst, const unsigned long long* __restrict__ res, int n,
-                          double floor_factor, int* __restrict__ active, int* __restrict__ counts) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const double r = __longlong_as_double((long long)res[2 * k]);
-    const double sc = __longlong_as_double((long long)res[2 * k + 1]);
-    const double thr = fmax(inst[k].thr, floor_factor * sc);
-    const int a = !(r <= thr);
-    active[k] = a;
-    if (a) atomicAdd(counts, 1);
-    if (r != r) atomicAdd(counts + 1, 1);
-}
+// One block: a channel stays active while its residual is above max(thr, floor * scale)
+// (an inactive channel stays inactive for the rest of the solve); the residual slots are
+// cleared for the next test; counts[0] = channels still active, counts[1] = channels
+// whose residual is NaN.
+constexpr int DECIDE_T = 256;
 
 template <typename T>
-__global__ void __launch_bounds__(TBX* TBY) kb_psi_history(const BatchInst<T>* __restrict__ inst,
-                                                           const int* __restrict__ tile_inst, int mode) {
-    const int k = tile_inst[blockIdx.x];
-    const BatchInst<T>& B = inst[k];
+__global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __restrict__ inst,
+                                                      unsigned long long* __restrict__ res, int n,
+                                                      double floor_factor, int* __restrict__ active,
+                                                      int* __restrict__ counts) {
+    __shared__ int cnt[2][DECIDE_T / 64];
+    int a_sum = 0, nan_sum = 0;
+    for (int k = threadIdx.x; k < n; k += DECIDE_T) {
+        if (!active[k]) continue;
+        const double r = __longlong_as_double((long long)res[2 * k]);
+        const double sc = __longlong_as_double((long long)res[2 * k + 1]);
+        const int a = !(r <= fmax(inst[k].thr, floor_factor * sc));
+        active[k] = a;
+        a_sum += a;
+        nan_sum += r != r;
+        res[2 * k] = 0ULL;
+        res[2 * k + 1] = 0ULL;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a_sum += __shfl_xor(a_sum, off, 64);
+        nan_sum += __shfl_xor(nan_sum, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        cnt[0][threadIdx.x >> 6] = a_sum;
+        cnt[1][threadIdx.x >> 6] = nan_sum;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        int s = 0;
+        for (int w = 0; w < DECIDE_T / 64; ++w) s += cnt[threadIdx.x][w];
+        counts[threadIdx.x] = s;
+    }
+}
+
+template <typename T, int TY>
+__global__ void __launch_bounds__(TBX* TY) kb_psi_history(const BatchInst<T>* __restrict__ inst,
+                                                          const int* __restrict__ tile_inst, int mode) {
+    const BatchInst<T>& B = inst[tile_inst[blockIdx.x]];
     int i, j;
-    tile_node(B, blockIdx.x - B.tile0, B.tiles_x, i, j);
+    tile_node<T, TY>(B, blockIdx.x, false, i, j);
     if (i >= B.P.nx || j >= B.P.ny || !B.has_field) return;
     const long long q = (long long)j * B.L0.pitch + i;
     const T cur = B.L0.u[q];
@@ -124,66 +157,86 @@ __global__ void __launch_bounds__(TBX* TBY) kb_psi_history(const BatchInst<T>* _
     B.prev[q] = cur;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(TBX* TBY) kb_fill_psi(const BatchInst<T>* __restrict__ inst,
-                                                        const int* __restrict__ tile_inst) {
-    const int k = tile_inst[blockIdx.x];
-    const BatchInst<T>& B = inst[k];
+template <typename T, int TY>
+__global__ void __launch_bounds__(TBX* TY) kb_fill_psi(const BatchInst<T>* __restrict__ inst,
+                                                       const int* __restrict__ tile_inst) {
+    const BatchInst<T>& B = inst[tile_inst[blockIdx.x]];
     int i, j;
-    tile_node(B, blockIdx.x - B.tile0, B.tiles_x, i, j);
+    tile_node<T, TY>(B, blockIdx.x, false, i, j);
     if (i >= B.P.nx || j >= B.P.ny) return;
     B.L0.u[(long long)j * B.L0.pitch + i] = T(0);
 }
 
 // ---------------------------------------------------------------------------------
-// Launchers.
+// Launchers: `shape` indexes the tile rows TY = 1, 2, 4, 8.
 // ---------------------------------------------------------------------------------
+#define FCD_SHAPE_SWITCH(shape, CALL) \
+    switch (shape) {                  \
+        case 0: CALL(1); break;       \
+        case 1: CALL(2); break;       \
+        case 2: CALL(4); break;       \
+        default: CALL(8); break;      \
+    }
+
 template <typename T>
-void launch_batch_phase(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int cur, hipStream_t s) {
-    hipLaunchKernelGGL(kb_phase<T>, dim3(ntiles), dim3(TBX, TBY), 0, s, inst, tile_inst, cur);
+void launch_batch_phase(const BatchInst<T>* inst, const BatchTiles& t, int cur, hipStream_t s) {
+#define C_(TY) hipLaunchKernelGGL((kb_phase<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, cur)
+    FCD_SHAPE_SWITCH(t.shape, C_)
+#undef C_
 }
 
 template <typename T>
-void launch_batch_collide(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int cur, hipStream_t s) {
-    hipLaunchKernelGGL(kb_collide_stream<T>, dim3(ntiles), dim3(TBX, TBY), 0, s, inst, tile_inst, cur);
+void launch_batch_collide(const BatchInst<T>* inst, const BatchTiles& t, int cur, hipStream_t s) {
+#define C_(TY) \
+    hipLaunchKernelGGL((kb_collide_stream<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, cur)
+    FCD_SHAPE_SWITCH(t.shape, C_)
+#undef C_
 }
 
 template <typename T>
-void launch_batch_sweep(const BatchInst<T>* inst, const int* ctile_inst, int nctiles, const int* active,
-                        hipStream_t s) {
-    for (int c = 0; c < 4; ++c)
-        hipLaunchKernelGGL(kb_sor_colour<T>, dim3(nctiles), dim3(TBX, TBY), 0, s, inst, ctile_inst, active, c);
+void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int* active, hipStream_t s) {
+    for (int c = 0; c < 4; ++c) {
+#define C_(TY) \
+    hipLaunchKernelGGL((kb_sor_colour<T, TY>), dim3(t.nctiles), dim3(TBX, TY), 0, s, inst, t.ctiles, active, c)
+        FCD_SHAPE_SWITCH(t.shape, C_)
+#undef C_
+    }
 }
 
 template <typename T>
-void launch_batch_residual(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int n,
-                           unsigned long long* res, int* active, int* counts, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3((2 * n + 255) / 256), dim3(256), 0, s, res, 2LL * n, 0ULL);
-    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, counts, 2LL, 0);
-    hipLaunchKernelGGL(kb_residual<T>, dim3(ntiles), dim3(TBX, TBY), 0, s, inst, tile_inst, res);
+void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
+                        int* active, int* counts, hipStream_t s) {
+#define C_(TY) \
+    hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
+    FCD_SHAPE_SWITCH(t.shape, C_)
+#undef C_
     const double floor_factor = 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
-    hipLaunchKernelGGL(kb_decide<T>, dim3((n + 255) / 256), dim3(256), 0, s, inst, res, n, floor_factor, active,
-                       counts);
+    hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, n, floor_factor, active, counts);
 }
 
 template <typename T>
-void launch_batch_psi_history(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(kb_psi_history<T>, dim3(ntiles), dim3(TBX, TBY), 0, s, inst, tile_inst, mode);
+void launch_batch_psi_history(const BatchInst<T>* inst, const BatchTiles& t, int mode, hipStream_t s) {
+#define C_(TY) \
+    hipLaunchKernelGGL((kb_psi_history<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, mode)
+    FCD_SHAPE_SWITCH(t.shape, C_)
+#undef C_
 }
 
 template <typename T>
-void launch_batch_fill_psi(const BatchInst<T>* inst, const int* tile_inst, int ntiles, hipStream_t s) {
-    hipLaunchKernelGGL(kb_fill_psi<T>, dim3(ntiles), dim3(TBX, TBY), 0, s, inst, tile_inst);
+void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStream_t s) {
+#define C_(TY) hipLaunchKernelGGL((kb_fill_psi<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles)
+    FCD_SHAPE_SWITCH(t.shape, C_)
+#undef C_
 }
 
-#define FCD_BATCH_INSTANTIATE(T)                                                                                 \
-    template void launch_batch_phase<T>(const BatchInst<T>*, const int*, int, int, hipStream_t);               \
-    template void launch_batch_collide<T>(const BatchInst<T>*, const int*, int, int, hipStream_t);             \
-    template void launch_batch_sweep<T>(const BatchInst<T>*, const int*, int, const int*, hipStream_t);        \
-    template void launch_batch_residual<T>(const BatchInst<T>*, const int*, int, int, unsigned long long*, int*, \
-                                           int*, hipStream_t);                                                   \
-    template void launch_batch_psi_history<T>(const BatchInst<T>*, const int*, int, int, hipStream_t);         \
-    template void launch_batch_fill_psi<T>(const BatchInst<T>*, const int*, int, hipStream_t);
+#define FCD_BATCH_INSTANTIATE(T)                                                                               \
+    template void launch_batch_phase<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);           \
+    template void launch_batch_collide<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);         \
+    template void launch_batch_sweep<T>(const BatchInst<T>*, const BatchTiles&, const int*, hipStream_t);    \
+    template void launch_batch_check<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,    \
+                                        int*, int*, hipStream_t);                                            \
+    template void launch_batch_psi_history<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);     \
+    template void launch_batch_fill_psi<T>(const BatchInst<T>*, const BatchTiles&, hipStream_t);
 
 FCD_BATCH_INSTANTIATE(double)
 FCD_BATCH_INSTANTIATE(float)

@@ -1,4 +1,4 @@
-// fcd_batch.hpp -- per-channel descriptors and launchers of the batched step.
+// fcd_batch.hpp -- per-channel descriptors, tile tables and launchers of the batched step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -6,6 +6,9 @@
 #include "fcd_device.hpp"
 
 namespace fcd {
+
+// Tile shapes 64 x TY, TY = 1, 2, 4, 8 (index 0..3).
+constexpr int BATCH_SHAPES = 4;
 
 // One channel of a batch, as the kernels see it (stored in device memory).
 template <typename T>
@@ -17,25 +20,37 @@ struct BatchInst {
     T* prev;          // psi' history plane
     T omega;          // SOR factor
     double thr;       // stop when max |residual| <= thr (= tol * H0)
-    int tile0, tiles_x;    // first tile in the full-resolution list, tiles per row
-    int ctile0, ctiles_x;  // the same for the half-resolution (colour) list
-    int has_field;         // H0 != 0
+    // per tile shape: first tile in the full-resolution and half-resolution (colour)
+    // lists, and tiles per row
+    int tile0[BATCH_SHAPES], tiles_x[BATCH_SHAPES];
+    int ctile0[BATCH_SHAPES], ctiles_x[BATCH_SHAPES];
+    int has_field;  // H0 != 0
     int pad;
 };
 
+// The tile lists of one shape (device tables: tile -> channel).
+struct BatchTiles {
+    int shape;
+    int ntiles, nctiles;
+    const int* tiles;
+    const int* ctiles;
+};
+
 template <typename T>
-void launch_batch_phase(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int cur, hipStream_t s);
+void launch_batch_phase(const BatchInst<T>* inst, const BatchTiles& t, int cur, hipStream_t s);
 template <typename T>
-void launch_batch_collide(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int cur, hipStream_t s);
+void launch_batch_collide(const BatchInst<T>* inst, const BatchTiles& t, int cur, hipStream_t s);
+// One four-colour SOR sweep of the active channels.
 template <typename T>
-void launch_batch_sweep(const BatchInst<T>* inst, const int* ctile_inst, int nctiles, const int* active,
-                        hipStream_t s);
+void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int* active, hipStream_t s);
+// Residual of the active channels, then the activity decision; res must be zero on entry
+// and is left zero; counts[0..1] = active channels, channels with a NaN residual.
 template <typename T>
-void launch_batch_residual(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int n,
-                           unsigned long long* res, int* active, int* counts, hipStream_t s);
+void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
+                        int* active, int* counts, hipStream_t s);
 template <typename T>
-void launch_batch_psi_history(const BatchInst<T>* inst, const int* tile_inst, int ntiles, int mode, hipStream_t s);
+void launch_batch_psi_history(const BatchInst<T>* inst, const BatchTiles& t, int mode, hipStream_t s);
 template <typename T>
-void launch_batch_fill_psi(const BatchInst<T>* inst, const int* tile_inst, int ntiles, hipStream_t s);
+void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStream_t s);
 
 }  // namespace fcd

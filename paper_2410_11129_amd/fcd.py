@@ -31,7 +31,8 @@ EXPORTS = (
     "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
     "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
-    "fcd_batch_read_moments", "fcd_batch_stats", "fcd_batch_destroy",
+    "fcd_batch_read_moments", "fcd_batch_set_schedule", "fcd_batch_autotune", "fcd_batch_stats",
+    "fcd_batch_destroy",
 )
 TIMING_KINDS = ("collide_stream", "potential_iter", "residual", "phase", "mg_smooth0", "mg_post0")
 
@@ -107,6 +108,8 @@ def lib():
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
         L.fcd_batch_init_compound_droplet.argtypes = [H, dp]
         L.fcd_batch_step.argtypes = [H, C.c_int32]
+        L.fcd_batch_set_schedule.argtypes = [H, C.c_int32, C.c_int32]
+        L.fcd_batch_autotune.argtypes = [H, C.c_int32, C.POINTER(C.c_int32)]
         L.fcd_batch_deformation.argtypes = [H, dp]
         L.fcd_batch_read_state.argtypes = [H, C.c_int32, C.c_void_p]
         L.fcd_batch_read_moments.argtypes = [H, C.c_int32, C.c_uint32, C.c_void_p]
@@ -285,3 +288,13 @@ def fcd_adjoint_backward(h, dJ_dD):
     out = (C.c_double * 6)()
     _check(lib().fcd_adjoint_backward(h, d, out), "fcd_adjoint_backward")
     return list(out)
+
+
+def fcd_batch_set_schedule(b, tile_rows: int, block_sweeps: int):
+    _check(lib().fcd_batch_set_schedule(b, tile_rows, block_sweeps), "fcd_batch_set_schedule")
+
+
+def fcd_batch_autotune(b, steps_per_candidate: int):
+    out = (C.c_int32 * 2)()
+    _check(lib().fcd_batch_autotune(b, steps_per_candidate, out), "fcd_batch_autotune")
+    return int(out[0]), int(out[1])

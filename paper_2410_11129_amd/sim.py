@@ -147,7 +147,7 @@ class Batch:
         self.device = torch.device(device)
         self.lats = [fcd.fcd_lattice(w.nx, w.ny, precision, w.nx) for w in self.ws]
         solver.setdefault("solver", fcd.FCD_SOLVER_SOR)
-        solver.setdefault("check_every", 1)
+        solver.setdefault("check_every", 4)
         self.prms = [make_params(w, **solver) for w in self.ws]
         sizes = fcd.fcd_batch_sizes(self.lats)
         self.bufs = [torch.zeros((max(int(b), 8) + 255) // 256 * 256 // 8, dtype=torch.float64, device=self.device)
@@ -175,6 +175,13 @@ class Batch:
 
     def step(self, n: int):
         fcd.fcd_batch_step(self.h, n)
+
+    def set_schedule(self, tile_rows: int, block_sweeps: int):
+        fcd.fcd_batch_set_schedule(self.h, tile_rows, block_sweeps)
+
+    def autotune(self, steps_per_candidate: int = 2):
+        """Pick the launch schedule by timing real steps; returns (tile_rows, block_sweeps)."""
+        return fcd.fcd_batch_autotune(self.h, steps_per_candidate)
 
     def deformation(self):
         return fcd.fcd_batch_deformation(self.h, self.n)
