@@ -144,6 +144,47 @@ def adjoint_ratio(torch, steps: int, every: int) -> dict:
             "D_o": D[0], "dDo_dtheta": dict(zip(("H0", "alpha", "u_ref", "sigma12", "sigma13", "sigma23"), g))}
 
 
+def batched_adjoint(torch, steps: int, every: int) -> dict:
+    """The 32 adjoint channels (256 x 64, Bo_m ~ U(0, 6), Ca ~ U(0.05, 0.2), random field
+    angle) as one FP32 batch: checkpointed forward + batched reverse sweep of `steps` steps,
+    against the single-channel FP64 adjoint of the first two channels run one after another
+    (per-instance rates; the full sweep is 3000 steps per channel, the rates scale with it)."""
+    from fcd_inputs import adjoint_batch
+    from paper_2410_11129_amd import fcd
+    from paper_2410_11129_amd.adjoint import AdjointRun, BatchAdjointRun, theta_of
+    from paper_2410_11129_amd.sim import Batch, Channel
+    ws = adjoint_batch(steps=steps)
+    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
+    bt.init_droplets()
+    run = BatchAdjointRun(bt, steps, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.forward()
+    g = run.backward([(1.0, 0.0)] * len(ws))
+    torch.cuda.synchronize()
+    dt_batch = time.perf_counter() - t0
+    bt.close()
+    seq = 0.0
+    gs = []
+    for w in ws[:2]:
+        ch = Channel(w, tol=1e-10)
+        r1 = AdjointRun(ch, steps, every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r1.forward(theta_of(w))
+        gs.append(r1.backward((1.0, 0.0)))
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+        ch.close()
+    per_batch = dt_batch / len(ws)
+    per_seq = seq / 2
+    rel = [abs(g[k][q] - gs[k][q]) / abs(gs[k][q]) for k in range(2) for q in (0, 1)]
+    return {"channels": len(ws), "steps": steps, "ckpt_every": every,
+            "batch_fp32_s": round(dt_batch, 3), "s_per_gradient_batch_fp32": round(per_batch, 4),
+            "s_per_gradient_sequential_fp64": round(per_seq, 4), "speedup": round(per_seq / per_batch, 2),
+            "max_rel_diff_dDo_dH0_dalpha_vs_fp64": float(f"{max(rel):.3e}")}
+
+
 def copy_bandwidth_gbs(torch) -> float:
     n = 1 << 28  # 2 GiB of float64 each way
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -181,6 +222,7 @@ def main() -> int:
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-ckpt", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--batch-adjoint-steps", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -263,6 +305,8 @@ def main() -> int:
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, args.adjoint_steps, args.adjoint_ckpt)
         log(f"bench: adjoint {out['adjoint']}")
+        out["batched_adjoint"] = batched_adjoint(torch, args.batch_adjoint_steps, 30)
+        log(f"bench: batched adjoint {out['batched_adjoint']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -277,6 +277,20 @@ fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block
  * 4 (1 + 3 steps_per_candidate) steps.  Sync. */
 fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[2]);
 
+/* Batched adjoint: the adjoint of fcd_adjoint_forward / _backward for every channel of
+ * the batch at once (one launch per kernel for all channels, the adjoint potential
+ * solves by the batch's SOR with per-channel thresholds pot_tol * max |psi'-bar|).
+ * fcd_batch_adjoint_bytes: device bytes of `work` (host only).
+ * fcd_batch_adjoint_forward: nsteps steps from the current state, checkpoints every
+ * ckpt_every steps in `work` (caller-owned, 256-byte aligned); D_out[2k..2k+1] =
+ * {D_o, D_i} of channel k after the run.  Sync.
+ * fcd_batch_adjoint_backward: grad[6k..6k+5] = dJ_k/d(H0, alpha, drive_G, sigma12,
+ * sigma13, sigma23) of channel k for J_k = dJ_dD[2k] D_o + dJ_dD[2k+1] D_i.  Sync; leaves
+ * the batch on the forward's final state. */
+size_t fcd_batch_adjoint_bytes(fcd_batch* b, int32_t nsteps, int32_t ckpt_every);
+fcd_status fcd_batch_adjoint_forward(fcd_batch* b, int32_t nsteps, int32_t ckpt_every, void* work, double* D_out);
+fcd_status fcd_batch_adjoint_backward(fcd_batch* b, const double* dJ_dD, double* grad);
+
 /* out = {steps, SOR sweeps launched, largest final residual of the last solve}. */
 fcd_status fcd_batch_stats(fcd_batch* b, double out[3]);
 

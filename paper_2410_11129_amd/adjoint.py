@@ -16,7 +16,7 @@ from __future__ import annotations
 import torch
 
 from . import fcd
-from .sim import Channel
+from .sim import Batch, Channel
 
 CS2 = 1.0 / 3.0
 PARAM_NAMES = ("H0", "alpha", "u_ref", "sigma12", "sigma13", "sigma23")
@@ -90,3 +90,33 @@ class DeformationFunction(torch.autograd.Function):
 
 def deformation(theta: torch.Tensor, run: AdjointRun) -> torch.Tensor:
     return DeformationFunction.apply(theta, run)
+
+
+class BatchAdjointRun:
+    """The checkpointed forward and reverse sweep of every channel of a batch at once."""
+
+    def __init__(self, bt: Batch, nsteps: int, ckpt_every: int):
+        if nsteps < 1 or ckpt_every < 1:
+            raise ValueError("need nsteps >= 1 and ckpt_every >= 1")
+        self.bt, self.nsteps, self.every = bt, nsteps, ckpt_every
+        nbytes = fcd.fcd_batch_adjoint_bytes(bt.h, nsteps, ckpt_every)
+        if nbytes == 0:
+            raise ValueError("fcd_batch_adjoint_bytes rejected the sizes")
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=bt.device)
+        self.D = None
+
+    def forward(self) -> list:
+        """Run nsteps from the batch's current state; [(D_o, D_i)] per channel."""
+        self.D = fcd.fcd_batch_adjoint_forward(self.bt.h, self.bt.n, self.nsteps, self.every, self.work.data_ptr())
+        return self.D
+
+    def backward(self, dJ_dD) -> list:
+        """Per channel dJ/d(H0, alpha, u_ref, sigma12, sigma13, sigma23)."""
+        if self.D is None:
+            raise RuntimeError("forward has not run")
+        g = fcd.fcd_batch_adjoint_backward(self.bt.h, [(float(a), float(b)) for a, b in dJ_dD])
+        out = []
+        for gk, w in zip(g, self.bt.ws):
+            dG_du = drive_from_u_ref(1.0, w.rho[2], w.tau[2], w.ny)
+            out.append([gk[0], gk[1], gk[2] * dG_du, gk[3], gk[4], gk[5]])
+        return out

@@ -836,6 +836,13 @@ struct fcd_batch {
     int shape;
     int block_sweeps;
     GraphCache graphs;
+    // batched adjoint
+    int init_fresh;
+    char* adj_work;
+    int adj_nsteps, adj_every, adj_from_init;
+    std::vector<int> adj_ckpt;  // (last_iters, hist) per checkpoint
+    int adj_final_iters, adj_final_hist;
+    int adj_solve_iters;        // sweeps of the previous adjoint potential solve
 };
 
 namespace {
@@ -866,6 +873,38 @@ fcd::BatchTiles btiles(const fcd_batch* b) {
 }
 
 template <typename T>
+fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
+    fcd::BatchInst<T> I{};
+    const fcd_lattice& l = b->lat[k];
+    const fcd_params& p = b->prm[k];
+    I.P = batch_const<T>(b, k);
+    I.dist[0] = bptr<T>(b->state, b->L.off_d0[k]);
+    I.dist[1] = bptr<T>(b->state, b->L.off_d1[k]);
+    I.phi = bptr<T>(b->aux, b->L.off_phi[k]);
+    I.prev = bptr<T>(b->aux, b->L.off_prev[k]);
+    I.L0.u = bptr<T>(b->aux, b->L.off_psi[k]);
+    I.L0.mu = I.phi + 2 * (long long)I.P.plane;
+    I.L0.f = nullptr;
+    I.L0.nx = l.nx;
+    I.L0.ny = l.ny;
+    I.L0.pitch = b->L.pitch[k];
+    I.L0.inv_h2 = T(1);
+    I.L0.kappa = T(0);
+    I.L0.H0x = T(p.H0 * std::cos(p.alpha));
+    I.L0.H0y = T(p.H0 * std::sin(p.alpha));
+    I.omega = T(p.pot_omega > 0.0 ? p.pot_omega : sor_omega_opt(l.ny));
+    I.thr = p.pot_tol * std::fabs(p.H0);
+    I.has_field = p.H0 != 0.0;
+    for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
+        I.tile0[s] = b->L.tile0[s][k];
+        I.tiles_x[s] = b->L.tiles_x[s][k];
+        I.ctile0[s] = b->L.ctile0[s][k];
+        I.ctiles_x[s] = b->L.ctiles_x[s][k];
+    }
+    return I;
+}
+
+template <typename T>
 fcd_status batch_upload(fcd_batch* b) {
     std::vector<fcd::BatchInst<T>> inst(b->n);
     std::vector<int> tiles[fcd::BATCH_SHAPES], ctiles[fcd::BATCH_SHAPES];
@@ -876,32 +915,9 @@ fcd_status batch_upload(fcd_batch* b) {
     for (int k = 0; k < b->n; ++k) {
         fcd::BatchInst<T>& I = inst[k];
         const fcd_lattice& l = b->lat[k];
-        const fcd_params& p = b->prm[k];
-        I = fcd::BatchInst<T>{};
-        I.P = batch_const<T>(b, k);
-        I.dist[0] = bptr<T>(b->state, b->L.off_d0[k]);
-        I.dist[1] = bptr<T>(b->state, b->L.off_d1[k]);
-        I.phi = bptr<T>(b->aux, b->L.off_phi[k]);
-        I.prev = bptr<T>(b->aux, b->L.off_prev[k]);
-        I.L0.u = bptr<T>(b->aux, b->L.off_psi[k]);
-        I.L0.mu = I.phi + 2 * (long long)I.P.plane;
-        I.L0.f = nullptr;
-        I.L0.nx = l.nx;
-        I.L0.ny = l.ny;
-        I.L0.pitch = b->L.pitch[k];
-        I.L0.inv_h2 = T(1);
-        I.L0.kappa = T(0);
-        I.L0.H0x = T(p.H0 * std::cos(p.alpha));
-        I.L0.H0y = T(p.H0 * std::sin(p.alpha));
-        I.omega = T(p.pot_omega > 0.0 ? p.pot_omega : sor_omega_opt(l.ny));
-        I.thr = p.pot_tol * std::fabs(p.H0);
-        I.has_field = p.H0 != 0.0;
+        I = make_batch_inst<T>(b, k);
         for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
             const int ty = BT_ROWS[s];
-            I.tile0[s] = b->L.tile0[s][k];
-            I.tiles_x[s] = b->L.tiles_x[s][k];
-            I.ctile0[s] = b->L.ctile0[s][k];
-            I.ctiles_x[s] = b->L.ctiles_x[s][k];
             const int nt = (l.nx + BT_X - 1) / BT_X * ((l.ny + ty - 1) / ty);
             for (int t = 0; t < nt; ++t) tiles[s][I.tile0[s] + t] = k;
             const int nc = ((l.nx + 1) / 2 + BT_X - 1) / BT_X * (((l.ny + 1) / 2 + ty - 1) / ty);
@@ -930,18 +946,33 @@ const fcd::BatchInst<T>* binst(const fcd_batch* b) {
 
 int check_interval(const fcd_batch* b) { return std::max(1, b->prm[0].pot_check_every); }
 
+// The problem a batched potential solve works on: the descriptors (u, f, mu, thresholds)
+// and, for relative thresholds, per-channel scales on the device.
+template <typename T>
+struct BatchProblem {
+    const fcd::BatchInst<T>* inst;
+    const unsigned long long* scale;  // nullptr: absolute thresholds of the descriptors
+    double rel_tol;
+    int* last_iters;                  // sweeps the previous solve of this problem needed
+};
+
+template <typename T>
+BatchProblem<T> forward_problem(fcd_batch* b) {
+    return {binst<T>(b), nullptr, 0.0, &b->last_iters};
+}
+
 // A block of `block_sweeps` SOR sweeps with a device-side convergence test after every
 // `check` sweeps (block_sweeps is a multiple of check).
 template <typename T>
-void batch_block(fcd_batch* b) {
+void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
     const fcd::BatchTiles t = btiles(b);
     int* active = bptr<int>(b->scratch, b->L.off_active);
     const int check = check_interval(b);
     for (int s = 1; s <= b->block_sweeps; ++s) {
-        fcd::launch_batch_sweep<T>(binst<T>(b), t, active, b->stream);
+        fcd::launch_batch_sweep<T>(P.inst, t, active, b->stream);
         if (s % check == 0)
-            fcd::launch_batch_check<T>(binst<T>(b), t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res),
-                                       active, bptr<int>(b->scratch, b->L.off_counts), b->stream);
+            fcd::launch_batch_check<T>(P.inst, t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res), active,
+                                       bptr<int>(b->scratch, b->L.off_counts), P.scale, P.rel_tol, b->stream);
     }
 }
 
@@ -965,25 +996,25 @@ fcd_status batch_read_counts(fcd_batch* b, int* active_count) {
 // the previous solve needed minus one without reading.  Which sweeps a channel receives
 // is decided on the device, so the result does not depend on the block size.
 template <typename T>
-fcd_status batch_solve(fcd_batch* b, int max_iters) {
+fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
     const fcd::BatchTiles t = btiles(b);
     int* active = bptr<int>(b->scratch, b->L.off_active);
     fcd::launch_fill<int>(active, b->n, 1, b->stream);
-    fcd::launch_batch_check<T>(binst<T>(b), t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res), active,
-                               bptr<int>(b->scratch, b->L.off_counts), b->stream);
+    fcd::launch_batch_check<T>(P.inst, t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res), active,
+                               bptr<int>(b->scratch, b->L.off_counts), P.scale, P.rel_tol, b->stream);
     fcd_status st = hip_check(hipGetLastError(), "batch check launch");
     if (st) return st;
     int left = 1, it = 0;
     const int G = b->block_sweeps;
-    int blind = b->last_iters > G ? (b->last_iters + G - 1) / G - 1 : 0;
+    int blind = *P.last_iters > G ? (*P.last_iters + G - 1) / G - 1 : 0;
     if (blind == 0) {
         st = batch_read_counts<T>(b, &left);
         if (st) return st;
     }
     while (left > 0) {
         if (it >= max_iters) break;
-        st = run_graph_on(b->graphs, b->stream, false, nullptr, nullptr, 1000 * b->shape + G,
-                          [&]() { batch_block<T>(b); });
+        st = run_graph_on(b->graphs, b->stream, false, P.inst, nullptr, 1000 * b->shape + G,
+                          [&]() { batch_block<T>(b, P); });
         if (st) return st;
         it += G;
         if (blind > 0) {
@@ -994,7 +1025,7 @@ fcd_status batch_solve(fcd_batch* b, int max_iters) {
         if (st) return st;
     }
     b->iters += it;
-    b->last_iters = it;
+    *P.last_iters = it;
     b->last_resid = 0.0;
     if (left > 0) return fail(FCD_ERR_NOT_CONVERGED, "a channel's potential solve reached pot_max_iters");
     return FCD_OK;
@@ -1009,7 +1040,7 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
         if (p0.pot_extrapolate) fcd::launch_batch_psi_history<T>(binst<T>(b), t, b->hist >= 2 ? 1 : 0, b->stream);
         fcd_status st = hip_check(hipGetLastError(), "batch phase launch");
         if (st) return st;
-        st = batch_solve<T>(b, p0.pot_max_iters);
+        st = batch_solve<T>(b, forward_problem<T>(b), p0.pot_max_iters);
         if (st) return st;
         ++b->hist;
         fcd::launch_batch_collide<T>(binst<T>(b), t, b->cur, b->stream);
@@ -1075,6 +1106,7 @@ fcd_status batch_init_impl(fcd_batch* b, const double* geom) {
     b->cur = 0;
     b->hist = 0;
     b->last_iters = 0;
+    b->init_fresh = 1;
     return hip_check(hipGetLastError(), "batch init launch");
 }
 
@@ -1353,6 +1385,263 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
     return load_record<T>(h, w + L.off_final, L);
 }
 
+// ---------------------------------------------------------------------------------
+// Batched checkpointed adjoint.  Per channel the work buffer holds the checkpoint
+// records (state, psi', psi' history), the final record, the segment records (state,
+// psi'), two adjoint states, the ten sensitivity planes and the adjoint potential's
+// right-hand side, solution and history; shared: the adjoint-potential descriptors,
+// the per-channel adjoint descriptors, per-tile partials, per-channel accumulators
+// and scales.
+// ---------------------------------------------------------------------------------
+struct BatchAdjLayout {
+    int nseg = 0;
+    std::vector<size_t> plane, crec, srec, off_ckpt, off_final, off_seg, off_lam0, off_lam1, off_sens, off_rhs,
+        off_lpsi, off_lprev;
+    size_t off_ainst = 0, off_adj = 0, off_part = 0, off_partC = 0, off_acc = 0, off_scale = 0, bytes = 0;
+};
+
+BatchAdjLayout batch_adj_layout(const fcd_batch* b, int nsteps, int every) {
+    BatchAdjLayout A;
+    A.nseg = (nsteps + every - 1) / every;
+    const size_t esz = elem_size(b->precision);
+    size_t off = 0;
+    int max_blocks = 0;
+    for (int k = 0; k < b->n; ++k) {
+        const size_t pl = align256((size_t)b->lat[k].ny * b->L.pitch[k] * esz);
+        A.plane.push_back(pl);
+        A.crec.push_back(29 * pl);
+        A.srec.push_back(28 * pl);
+        A.off_ckpt.push_back(off);
+        off += (size_t)A.nseg * 29 * pl;
+        A.off_final.push_back(off);
+        off += 29 * pl;
+        A.off_seg.push_back(off);
+        off += (size_t)every * 28 * pl;
+        A.off_lam0.push_back(off);
+        off += 27 * pl;
+        A.off_lam1.push_back(off);
+        off += 27 * pl;
+        A.off_sens.push_back(off);
+        off += 10 * pl;
+        A.off_rhs.push_back(off);
+        off += pl;
+        A.off_lpsi.push_back(off);
+        off += pl;
+        A.off_lprev.push_back(off);
+        off += pl;
+        max_blocks = std::max(max_blocks, fcd::adj_blocks(b->lat[k].nx, b->lat[k].ny));
+    }
+    const size_t inst_sz = b->precision == FCD_FP64 ? sizeof(fcd::BatchInst<double>) : sizeof(fcd::BatchInst<float>);
+    const size_t adj_sz = b->precision == FCD_FP64 ? sizeof(fcd::BatchAdj<double>) : sizeof(fcd::BatchAdj<float>);
+    A.off_ainst = off;
+    off = align256(off + (size_t)b->n * inst_sz);
+    A.off_adj = off;
+    off = align256(off + (size_t)b->n * adj_sz);
+    A.off_part = off;
+    off = align256(off + (size_t)b->L.ntiles[2] * fcd::ADJ_NPART * sizeof(double));
+    A.off_partC = off;
+    off = align256(off + (size_t)max_blocks * fcd::ADJ_NPART * sizeof(double));
+    A.off_acc = off;
+    off = align256(off + (size_t)b->n * 16 * sizeof(double));
+    A.off_scale = off;
+    off = align256(off + (size_t)b->n * sizeof(unsigned long long));
+    A.bytes = off;
+    return A;
+}
+
+char* bstate(fcd_batch* b, int k) { return b->state + (b->cur == 0 ? b->L.off_d0[k] : b->L.off_d1[k]); }
+
+// Whole-batch records: the current state, psi' and psi' history of every channel.
+fcd_status batch_save_records(fcd_batch* b, const BatchAdjLayout& A, const std::vector<size_t>& off, int idx) {
+    fcd_status st = FCD_OK;
+    for (int k = 0; k < b->n && !st; ++k) {
+        char* rec = b->adj_work + off[k] + (size_t)idx * A.crec[k];
+        const size_t pl = A.plane[k];
+        st = dcopy(rec, bstate(b, k), 27 * pl, b->stream);
+        if (!st) st = dcopy(rec + 27 * pl, b->aux + b->L.off_psi[k], pl, b->stream);
+        if (!st) st = dcopy(rec + 28 * pl, b->aux + b->L.off_prev[k], pl, b->stream);
+    }
+    return st;
+}
+
+fcd_status batch_load_records(fcd_batch* b, const BatchAdjLayout& A, const std::vector<size_t>& off, int idx) {
+    fcd_status st = FCD_OK;
+    for (int k = 0; k < b->n && !st; ++k) {
+        const char* rec = b->adj_work + off[k] + (size_t)idx * A.crec[k];
+        const size_t pl = A.plane[k];
+        st = dcopy(bstate(b, k), rec, 27 * pl, b->stream);
+        if (!st) st = dcopy(b->aux + b->L.off_psi[k], rec + 27 * pl, pl, b->stream);
+        if (!st) st = dcopy(b->aux + b->L.off_prev[k], rec + 28 * pl, pl, b->stream);
+    }
+    return st;
+}
+
+template <typename T>
+fcd_status batch_adj_forward_impl(fcd_batch* b, int nsteps, int every, char* work, double* D_out) {
+    const BatchAdjLayout A = batch_adj_layout(b, nsteps, every);
+    // descriptors of the adjoint potential problems and of the per-channel work planes
+    std::vector<fcd::BatchInst<T>> ainst(b->n);
+    std::vector<fcd::BatchAdj<T>> adj(b->n);
+    for (int k = 0; k < b->n; ++k) {
+        fcd::BatchInst<T>& I = ainst[k];
+        I = make_batch_inst<T>(b, k);
+        I.L0.u = reinterpret_cast<T*>(work + A.off_lpsi[k]);
+        I.L0.f = reinterpret_cast<T*>(work + A.off_rhs[k]);
+        I.L0.H0x = I.L0.H0y = T(0);
+        I.prev = reinterpret_cast<T*>(work + A.off_lprev[k]);
+        fcd::BatchAdj<T>& D = adj[k];
+        D.seg = reinterpret_cast<T*>(work + A.off_seg[k]);
+        D.srec = (long long)(A.srec[k] / sizeof(T));
+        D.lam[0] = reinterpret_cast<T*>(work + A.off_lam0[k]);
+        D.lam[1] = reinterpret_cast<T*>(work + A.off_lam1[k]);
+        D.sens = reinterpret_cast<T*>(work + A.off_sens[k]);
+        D.rhs = reinterpret_cast<T*>(work + A.off_rhs[k]);
+        D.tile_first = b->L.tile0[2][k];
+        D.tile_count = b->L.tiles_x[2][k] * ((b->lat[k].ny + BT_ROWS[2] - 1) / BT_ROWS[2]);
+    }
+    fcd_status st = hip_check(hipMemcpy(work + A.off_ainst, ainst.data(), ainst.size() * sizeof(ainst[0]),
+                                        hipMemcpyHostToDevice), "adjoint descriptor upload");
+    if (!st) st = hip_check(hipMemcpy(work + A.off_adj, adj.data(), adj.size() * sizeof(adj[0]),
+                                      hipMemcpyHostToDevice), "adjoint descriptor upload");
+    if (st) return st;
+    b->adj_work = work;
+    b->adj_nsteps = nsteps;
+    b->adj_every = every;
+    b->adj_from_init = b->init_fresh;
+    b->adj_ckpt.assign(2 * (size_t)A.nseg, 0);
+    for (int t = 0; t < nsteps && !st; ++t) {
+        if (t % every == 0) {
+            st = batch_save_records(b, A, A.off_ckpt, t / every);
+            b->adj_ckpt[2 * (t / every)] = b->last_iters;
+            b->adj_ckpt[2 * (t / every) + 1] = b->hist;
+        }
+        if (!st) st = batch_step_impl<T>(b, 1);
+    }
+    if (!st) st = batch_save_records(b, A, A.off_final, 0);
+    if (st) return st;
+    b->init_fresh = 0;
+    b->adj_final_iters = b->last_iters;
+    b->adj_final_hist = b->hist;
+    std::vector<double> d(4 * (size_t)b->n);
+    st = batch_diag_impl<T>(b, d.data());
+    if (st) return st;
+    for (int k = 0; k < b->n; ++k) {
+        D_out[2 * k] = d[4 * k];
+        D_out[2 * k + 1] = d[4 * k + 1];
+    }
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status batch_adj_backward_impl(fcd_batch* b, const double* dJ, double* grad) {
+    if (!b->adj_work || b->adj_every < 1) return fail(FCD_ERR_ARG, "fcd_batch_adjoint_forward has not run");
+    const int nsteps = b->adj_nsteps, every = b->adj_every;
+    const BatchAdjLayout A = batch_adj_layout(b, nsteps, every);
+    char* w = b->adj_work;
+    const fcd::BatchInst<T>* inst = binst<T>(b);
+    const fcd::BatchInst<T>* ainst = reinterpret_cast<const fcd::BatchInst<T>*>(w + A.off_ainst);
+    const fcd::BatchAdj<T>* adj = reinterpret_cast<const fcd::BatchAdj<T>*>(w + A.off_adj);
+    double* part = reinterpret_cast<double*>(w + A.off_part);
+    double* partC = reinterpret_cast<double*>(w + A.off_partC);
+    double* acc = reinterpret_cast<double*>(w + A.off_acc);
+    unsigned long long* scale = reinterpret_cast<unsigned long long*>(w + A.off_scale);
+    fcd::BatchTiles t2;
+    t2.shape = 2;
+    t2.ntiles = b->L.ntiles[2];
+    t2.nctiles = b->L.nctiles[2];
+    t2.tiles = reinterpret_cast<const int*>(b->scratch + b->L.off_tiles[2]);
+    t2.ctiles = reinterpret_cast<const int*>(b->scratch + b->L.off_ctiles[2]);
+    fcd::launch_fill<double>(acc, 16LL * b->n, 0.0, b->stream);
+    fcd::launch_batch_fill_psi<T>(ainst, btiles(b), b->stream);  // adjoint potentials start at zero
+    fcd_status st = batch_load_records(b, A, A.off_final, 0);
+    if (st) return st;
+    // seed: adjoint of every channel's final state from J_k = dJ[2k] D_o + dJ[2k+1] D_i
+    double* cent = bptr<double>(b->scratch, b->L.off_cent);
+    double* results = bptr<double>(b->scratch, b->L.off_result);
+    for (int k = 0; k < b->n; ++k) {
+        batch_refresh_phase<T>(b, k);
+        const fcd::StepConst<T> P = batch_const<T>(b, k);
+        T* phi = bptr<T>(b->aux, b->L.off_phi[k]);
+        fcd::launch_diagnostics<T>(phi, P, bptr<double>(b->scratch, b->L.off_rows), cent, results + 4 * k, b->stream);
+        fcd::launch_adj_seed<T>(phi, cent + 8, dJ[2 * k], dJ[2 * k + 1], reinterpret_cast<T*>(w + A.off_lam0[k]), P,
+                                b->stream);
+    }
+    st = hip_check(hipGetLastError(), "batch adjoint seed");
+    if (st) return st;
+    int Aidx = 0, lhist = 0;
+    b->adj_solve_iters = 0;
+    const fcd_params& p0 = b->prm[0];
+    const BatchProblem<T> adjP{ainst, scale, p0.pot_tol, &b->adj_solve_iters};
+    for (int seg = A.nseg - 1; seg >= 0 && !st; --seg) {
+        const int t0 = seg * every, t1 = std::min(nsteps, t0 + every);
+        st = batch_load_records(b, A, A.off_ckpt, seg);
+        if (st) break;
+        b->last_iters = b->adj_ckpt[2 * seg];
+        b->hist = b->adj_ckpt[2 * seg + 1];
+        for (int t = t0; t < t1 && !st; ++t) {
+            fcd::launch_batch_adj_save<T>(inst, adj, t2, b->cur, t - t0, 0, b->stream);
+            st = batch_step_impl<T>(b, 1);
+            fcd::launch_batch_adj_save<T>(inst, adj, t2, b->cur, t - t0, 1, b->stream);
+        }
+        for (int t = t1 - 1; t >= t0 && !st; --t) {
+            const int r = t - t0;
+            fcd::launch_batch_adj_phase<T>(inst, adj, t2, r, b->stream);
+            fcd::launch_batch_adj_node<T>(inst, adj, t2, r, Aidx, part, b->stream);
+            fcd::launch_batch_adj_reduce<T>(adj, b->n, part, 13, acc, 0, b->stream);
+            fcd::launch_batch_adj_gather<T>(inst, adj, t2, scale, b->n, b->stream);
+            // warm start: linear extrapolation of the last two adjoint solutions
+            if (p0.pot_extrapolate) fcd::launch_batch_psi_history<T>(ainst, btiles(b), lhist >= 2 ? 1 : 0, b->stream);
+            ++lhist;
+            st = hip_check(hipGetLastError(), "batch adjoint launch");
+            if (!st) st = batch_solve<T>(b, adjP, p0.pot_max_iters);
+            if (st) break;
+            fcd::launch_batch_adj_finish<T>(inst, ainst, adj, t2, r, Aidx, part, b->stream);
+            fcd::launch_batch_adj_reduce<T>(adj, b->n, part, 2, acc, 13, b->stream);
+            st = hip_check(hipGetLastError(), "batch adjoint launch");
+            Aidx = 1 - Aidx;
+        }
+    }
+    if (st) return st;
+    if (b->adj_from_init) {
+        for (int k = 0; k < b->n; ++k) {
+            const fcd_params& p = b->prm[k];
+            const fcd::StepConst<T> P = batch_const<T>(b, k);
+            const double dUdG = 1.0 / (2.0 * p.rho[2] * p.tau[2] / 3.0);
+            const T* s0 = reinterpret_cast<const T*>(w + A.off_ckpt[k]);
+            const T* lam0 = reinterpret_cast<const T*>(w + (Aidx == 0 ? A.off_lam0[k] : A.off_lam1[k]));
+            fcd::launch_adj_init_drive<T>(s0, lam0, dUdG, p.drive_G * dUdG, partC, P, b->stream);
+            fcd::launch_adj_reduce(partC, fcd::adj_blocks(b->lat[k].nx, b->lat[k].ny), 1, acc + 16 * k, 15, b->stream);
+        }
+    }
+    std::vector<double> a(16 * (size_t)b->n);
+    st = hip_check(hipStreamSynchronize(b->stream), "batch adjoint sync");
+    if (!st) st = hip_check(hipMemcpy(a.data(), acc, a.size() * sizeof(double), hipMemcpyDeviceToHost), "copy");
+    if (st) return st;
+    for (int k = 0; k < b->n; ++k) {
+        const double* ak = a.data() + 16 * k;
+        const fcd_params& p = b->prm[k];
+        double* g = grad + 6 * k;
+        const double ca = std::cos(p.alpha), sa = std::sin(p.alpha);
+        const double hx = ak[0] + ak[13], hy = ak[1] + ak[14];
+        g[0] = hx * ca + hy * sa;
+        g[1] = p.H0 * (-hx * sa + hy * ca);
+        g[2] = ak[2] + ak[15];
+        const double gm[3] = {p.sigma12 + p.sigma13 - p.sigma23, p.sigma12 + p.sigma23 - p.sigma13,
+                              p.sigma13 + p.sigma23 - p.sigma12};
+        const double gT = 3.0 / (1.0 / gm[0] + 1.0 / gm[1] + 1.0 / gm[2]);
+        double gb[3];
+        for (int q = 0; q < 3; ++q)
+            gb[q] = ak[6 + q] - ak[9 + q] / (gm[q] * gm[q]) + ak[12] * (4.0 / p.xi) * gT * gT / (3.0 * gm[q] * gm[q]);
+        g[3] = ak[3] + gb[0] + gb[1] - gb[2];
+        g[4] = ak[4] + gb[0] - gb[1] + gb[2];
+        g[5] = ak[5] - gb[0] + gb[1] + gb[2];
+    }
+    b->last_iters = b->adj_final_iters;
+    b->hist = b->adj_final_hist;
+    return batch_load_records(b, A, A.off_final, 0);
+}
+
+
 #define FCD_BDISPATCH(b, call) ((b)->precision == FCD_FP64 ? call<double> : call<float>)
 
 }  // namespace
@@ -1600,6 +1889,10 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     b->steps = b->iters = 0;
     b->last_resid = 0.0;
     b->shape = 2;  // 64 x 4 tiles
+    b->init_fresh = 0;
+    b->adj_work = nullptr;
+    b->adj_nsteps = b->adj_every = b->adj_from_init = 0;
+    b->adj_final_iters = b->adj_final_hist = b->adj_solve_iters = 0;
     b->block_sweeps = 8 * std::max(1, prms[0].pot_check_every);
     if (hipHostMalloc(reinterpret_cast<void**>(&b->host), (1 + 4 * (size_t)n) * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
@@ -1627,6 +1920,7 @@ fcd_status fcd_batch_init_compound_droplet(fcd_batch* b, const double* geom) {
 fcd_status fcd_batch_step(fcd_batch* b, int32_t nsteps) {
     if (!b) return fail(FCD_ERR_ARG, "batch is null");
     if (nsteps < 0) return fail(FCD_ERR_ARG, "nsteps must be >= 0");
+    if (nsteps > 0) b->init_fresh = 0;
     return FCD_BDISPATCH(b, batch_step_impl)(b, nsteps);
 }
 
@@ -1662,6 +1956,23 @@ fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block
     b->shape = s;
     b->block_sweeps = block_sweeps;
     return FCD_OK;
+}
+
+size_t fcd_batch_adjoint_bytes(fcd_batch* b, int32_t nsteps, int32_t ckpt_every) {
+    if (!b || nsteps < 1 || ckpt_every < 1) return 0;
+    return batch_adj_layout(b, nsteps, ckpt_every).bytes;
+}
+
+fcd_status fcd_batch_adjoint_forward(fcd_batch* b, int32_t nsteps, int32_t ckpt_every, void* work, double* D_out) {
+    if (!b || !work || !D_out) return fail(FCD_ERR_ARG, "null argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(FCD_ERR_ARG, "need nsteps >= 1 and ckpt_every >= 1");
+    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(FCD_ERR_ARG, "work must be 256-byte aligned");
+    return FCD_BDISPATCH(b, batch_adj_forward_impl)(b, nsteps, ckpt_every, static_cast<char*>(work), D_out);
+}
+
+fcd_status fcd_batch_adjoint_backward(fcd_batch* b, const double* dJ_dD, double* grad) {
+    if (!b || !dJ_dD || !grad) return fail(FCD_ERR_ARG, "null argument");
+    return FCD_BDISPATCH(b, batch_adj_backward_impl)(b, dJ_dD, grad);
 }
 
 fcd_status fcd_batch_stats(fcd_batch* b, double out[3]) {

@@ -113,14 +113,16 @@ template <typename T>
 __global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __restrict__ inst,
                                                       unsigned long long* __restrict__ res, int n,
                                                       double floor_factor, int* __restrict__ active,
-                                                      int* __restrict__ counts) {
+                                                      int* __restrict__ counts,
+                                                      const unsigned long long* __restrict__ scale, double rel_tol) {
     __shared__ int cnt[2][DECIDE_T / 64];
     int a_sum = 0, nan_sum = 0;
     for (int k = threadIdx.x; k < n; k += DECIDE_T) {
         if (!active[k]) continue;
         const double r = __longlong_as_double((long long)res[2 * k]);
         const double sc = __longlong_as_double((long long)res[2 * k + 1]);
-        const int a = !(r <= fmax(inst[k].thr, floor_factor * sc));
+        const double thr = scale ? rel_tol * __longlong_as_double((long long)scale[k]) : inst[k].thr;
+        const int a = !(r <= fmax(thr, floor_factor * sc));
         active[k] = a;
         a_sum += a;
         nan_sum += r != r;
@@ -205,13 +207,14 @@ void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int
 
 template <typename T>
 void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
-                        int* active, int* counts, hipStream_t s) {
+                        int* active, int* counts, const unsigned long long* scale, double rel_tol, hipStream_t s) {
 #define C_(TY) \
     hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
     FCD_SHAPE_SWITCH(t.shape, C_)
 #undef C_
     const double floor_factor = 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
-    hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, n, floor_factor, active, counts);
+    hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, n, floor_factor, active, counts, scale,
+                       rel_tol);
 }
 
 template <typename T>
@@ -234,7 +237,7 @@ void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStr
     template void launch_batch_collide<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);         \
     template void launch_batch_sweep<T>(const BatchInst<T>*, const BatchTiles&, const int*, hipStream_t);    \
     template void launch_batch_check<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,    \
-                                        int*, int*, hipStream_t);                                            \
+                                        int*, int*, const unsigned long long*, double, hipStream_t);         \
     template void launch_batch_psi_history<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);     \
     template void launch_batch_fill_psi<T>(const BatchInst<T>*, const BatchTiles&, hipStream_t);
 

@@ -28,6 +28,17 @@ struct BatchInst {
     int pad;
 };
 
+// Per-channel work pointers of the batched adjoint (device descriptors).
+template <typename T>
+struct BatchAdj {
+    T* seg;          // segment records: record r at seg + r * srec (27 state planes, then psi')
+    long long srec;  // elements per segment record
+    T* lam[2];       // adjoint states (27 planes each)
+    T* sens;         // ten stencil sensitivity planes
+    T* rhs;          // right-hand side of the adjoint potential equation
+    int tile_first, tile_count;  // the channel's tiles in the 64 x 4 list
+};
+
 // The tile lists of one shape (device tables: tile -> channel).
 struct BatchTiles {
     int shape;
@@ -45,12 +56,34 @@ template <typename T>
 void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int* active, hipStream_t s);
 // Residual of the active channels, then the activity decision; res must be zero on entry
 // and is left zero; counts[0..1] = active channels, channels with a NaN residual.
+// scale != nullptr: channel k's threshold is rel_tol * scale[k] (bit pattern of a
+// non-negative double) instead of its descriptor's thr.
 template <typename T>
 void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
-                        int* active, int* counts, hipStream_t s);
+                        int* active, int* counts, const unsigned long long* scale, double rel_tol, hipStream_t s);
 template <typename T>
 void launch_batch_psi_history(const BatchInst<T>* inst, const BatchTiles& t, int mode, hipStream_t s);
 template <typename T>
 void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStream_t s);
+
+// Batched adjoint (fcd_adjoint.hip); all over the 64 x 4 tile list `t` (shape 2).
+template <typename T>
+void launch_batch_adj_save(const BatchInst<T>* inst, const BatchAdj<T>* adj, const BatchTiles& t, int cur, int r,
+                           int what, hipStream_t s);
+template <typename T>
+void launch_batch_adj_phase(const BatchInst<T>* inst, const BatchAdj<T>* adj, const BatchTiles& t, int r,
+                            hipStream_t s);
+template <typename T>
+void launch_batch_adj_node(const BatchInst<T>* inst, const BatchAdj<T>* adj, const BatchTiles& t, int r, int A,
+                           double* part, hipStream_t s);
+template <typename T>
+void launch_batch_adj_gather(const BatchInst<T>* inst, const BatchAdj<T>* adj, const BatchTiles& t,
+                             unsigned long long* scale, int n, hipStream_t s);
+template <typename T>
+void launch_batch_adj_finish(const BatchInst<T>* inst, const BatchInst<T>* ainst, const BatchAdj<T>* adj,
+                             const BatchTiles& t, int r, int A, double* part, hipStream_t s);
+template <typename T>
+void launch_batch_adj_reduce(const BatchAdj<T>* adj, int n, const double* part, int nq, double* acc, int dst,
+                             hipStream_t s);
 
 }  // namespace fcd

@@ -31,7 +31,8 @@ EXPORTS = (
     "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
     "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
-    "fcd_batch_read_moments", "fcd_batch_set_schedule", "fcd_batch_autotune", "fcd_batch_stats",
+    "fcd_batch_read_moments", "fcd_batch_set_schedule", "fcd_batch_autotune", "fcd_batch_adjoint_bytes",
+    "fcd_batch_adjoint_forward", "fcd_batch_adjoint_backward", "fcd_batch_stats",
     "fcd_batch_destroy",
 )
 TIMING_KINDS = ("collide_stream", "potential_iter", "residual", "phase", "mg_smooth0", "mg_post0")
@@ -109,6 +110,10 @@ def lib():
         L.fcd_batch_init_compound_droplet.argtypes = [H, dp]
         L.fcd_batch_step.argtypes = [H, C.c_int32]
         L.fcd_batch_set_schedule.argtypes = [H, C.c_int32, C.c_int32]
+        L.fcd_batch_adjoint_bytes.argtypes = [H, C.c_int32, C.c_int32]
+        L.fcd_batch_adjoint_bytes.restype = C.c_size_t
+        L.fcd_batch_adjoint_forward.argtypes = [H, C.c_int32, C.c_int32, C.c_void_p, dp]
+        L.fcd_batch_adjoint_backward.argtypes = [H, dp, dp]
         L.fcd_batch_autotune.argtypes = [H, C.c_int32, C.POINTER(C.c_int32)]
         L.fcd_batch_deformation.argtypes = [H, dp]
         L.fcd_batch_read_state.argtypes = [H, C.c_int32, C.c_void_p]
@@ -118,7 +123,7 @@ def lib():
         L.fcd_last_error.argtypes = []
         L.fcd_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("fcd_scratch_bytes", "fcd_last_error", "fcd_adjoint_bytes"):
+            if name not in ("fcd_scratch_bytes", "fcd_last_error", "fcd_adjoint_bytes", "fcd_batch_adjoint_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -298,3 +303,21 @@ def fcd_batch_autotune(b, steps_per_candidate: int):
     out = (C.c_int32 * 2)()
     _check(lib().fcd_batch_autotune(b, steps_per_candidate, out), "fcd_batch_autotune")
     return int(out[0]), int(out[1])
+
+
+def fcd_batch_adjoint_bytes(b, nsteps: int, ckpt_every: int) -> int:
+    return lib().fcd_batch_adjoint_bytes(b, nsteps, ckpt_every)
+
+
+def fcd_batch_adjoint_forward(b, n: int, nsteps: int, ckpt_every: int, work: int):
+    out = (C.c_double * (2 * n))()
+    _check(lib().fcd_batch_adjoint_forward(b, nsteps, ckpt_every, C.c_void_p(work), out), "fcd_batch_adjoint_forward")
+    return [(out[2 * k], out[2 * k + 1]) for k in range(n)]
+
+
+def fcd_batch_adjoint_backward(b, dJ_dD):
+    n = len(dJ_dD)
+    d = (C.c_double * (2 * n))(*[v for pair in dJ_dD for v in pair])
+    out = (C.c_double * (6 * n))()
+    _check(lib().fcd_batch_adjoint_backward(b, d, out), "fcd_batch_adjoint_backward")
+    return [list(out[6 * k:6 * k + 6]) for k in range(n)]

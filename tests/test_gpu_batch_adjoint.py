@@ -1,0 +1,104 @@
+"""Batched adjoint: every channel's gradient from one batched reverse sweep against the
+single-channel adjoint of the same channel (FP64), and FP32 batches of the 256 x 64
+adjoint channels against single-channel FP64 gradients (dD_o/d(H0, alpha), 1e-3)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from fcd_inputs import Workload, adjoint_batch, channel_drive, h0_from_bond
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2410_11129_amd import fcd  # noqa: E402
+from paper_2410_11129_amd.adjoint import AdjointRun, BatchAdjointRun, theta_of  # noqa: E402
+from paper_2410_11129_amd.sim import Batch, Channel  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def field_channels():
+    """Three channels of different size, surface tensions and field angle."""
+    out = []
+    for k, (nx, ny, rc, rs, alpha, s12, s13, s23) in enumerate((
+            (96, 32, 5.0, 9.0, 30.0, 0.008, 0.012, 0.01),
+            (64, 24, 4.0, 7.0, 75.0, 0.01, 0.01, 0.01),
+            (128, 20, 3.0, 6.0, 10.0, 0.012, 0.009, 0.011))):
+        u = 0.01
+        out.append(Workload(name=f"badj_{k}", nx=nx, ny=ny, tau=(0.8, 0.8, 0.8), chi=(0.0, 1.0, 0.0),
+                            sigma12=s12, sigma13=s13, sigma23=s23, xi=4.0,
+                            H0=h0_from_bond(1.0, "shell", 1.0, rc, rs, s12, s23), alpha=math.radians(alpha),
+                            drive_G=channel_drive(u, 1.0, 0.8, ny), xc=nx / 3.0, yc=ny / 2.0 - 0.7,
+                            r_core=rc, r_shell=rs, u_ref=u))
+    return out
+
+
+def single_grad(w, nsteps, dJ, every=8, tol=1e-12):
+    ch = Channel(w, tol=tol)
+    run = AdjointRun(ch, nsteps, every)
+    D = run.forward(theta_of(w))
+    g = np.array(run.backward(dJ))
+    ch.close()
+    return D, g
+
+
+def test_batch_adjoint_equals_single_channel_adjoints_fp64():
+    ws = field_channels()
+    nsteps = 20
+    say(f"case batch adjoint fp64 {[(w.nx, w.ny) for w in ws]} {nsteps} steps")
+    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-12)
+    bt.init_droplets()
+    run = BatchAdjointRun(bt, nsteps, 6)
+    D = run.forward()
+    dJ = [(1.0, 0.5)] * len(ws)
+    g = run.backward(dJ)
+    for k, w in enumerate(ws):
+        Ds, gs = single_grad(w, nsteps, dJ[k])
+        th = np.array(theta_of(w))
+        sc = np.where(np.arange(6) == 1, 1.0, np.abs(th))
+        err = np.abs((np.array(g[k]) - gs) * sc)
+        say(f"  {w.name}: D {D[k]} vs {Ds}; max scaled gradient error {err.max():.2e} of {np.abs(gs * sc).max():.2e}")
+        assert abs(D[k][0] - Ds[0]) < 1e-11 and abs(D[k][1] - Ds[1]) < 1e-11
+        assert np.all(err <= 1e-7 * np.abs(gs * sc) + 1e-10 * np.abs(gs * sc).max()), (w.name, g[k], gs)
+    bt.close()
+
+
+def test_batch_adjoint_fp32_tracks_fp64_single():
+    ws = [w.replace(steps=60) for w in adjoint_batch()[:6]]
+    nsteps, every = 60, 15
+    say(f"case batch adjoint fp32, 6 channels 256x64, {nsteps} steps")
+    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
+    bt.init_droplets()
+    run = BatchAdjointRun(bt, nsteps, every)
+    run.forward()
+    g = run.backward([(1.0, 0.0)] * len(ws))
+    for k, w in enumerate(ws):
+        _, gs = single_grad(w, nsteps, (1.0, 0.0), tol=1e-10)
+        for q, name in ((0, "H0"), (1, "alpha")):
+            rel = abs(g[k][q] - gs[q]) / max(abs(gs[q]), 1e-300)
+            say(f"  {w.name} Bo {w.bond:.2f} dDo/d{name}: fp32 batch {g[k][q]:.6e} fp64 {gs[q]:.6e} rel {rel:.1e}")
+            # an exactly vanishing derivative (no field) is compared absolutely
+            assert rel < 1e-3 or (gs[q] == 0.0 and g[k][q] == 0.0), (w.name, name)
+    bt.close()
+
+
+def test_batch_adjoint_leaves_final_state():
+    ws = field_channels()[:2]
+    say("case batch adjoint final state")
+    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-12)
+    bt.init_droplets()
+    run = BatchAdjointRun(bt, 9, 4)
+    run.forward()
+    s_fwd = [bt.state(k) for k in range(len(ws))]
+    run.backward([(1.0, 0.0)] * len(ws))
+    for k in range(len(ws)):
+        assert np.array_equal(bt.state(k), s_fwd[k])
+    bt.close()
