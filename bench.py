@@ -198,10 +198,18 @@ def batched_adjoint(torch, steps: int, every: int) -> dict:
     per_batch = dt_batch / len(ws)
     per_seq = seq / 2
     rel = [abs(g[k][q] - gs[k][q]) / abs(gs[k][q]) for k in range(2) for q in (0, 1)]
+    # the same error relative to the instance's (H0, alpha) gradient norm, H0-scaled
+    rel_norm = []
+    for k in range(2):
+        w = ws[k]
+        sc = (w.H0, 1.0)
+        norm = max(abs(gs[k][q] * sc[q]) for q in (0, 1))
+        rel_norm += [abs(g[k][q] - gs[k][q]) * sc[q] / norm for q in (0, 1)]
     return {"channels": len(ws), "steps": steps, "ckpt_every": every,
             "batch_fp32_s": round(dt_batch, 3), "s_per_gradient_batch_fp32": round(per_batch, 4),
             "s_per_gradient_sequential_fp64": round(per_seq, 4), "speedup": round(per_seq / per_batch, 2),
-            "max_rel_diff_dDo_dH0_dalpha_vs_fp64": float(f"{max(rel):.3e}")}
+            "max_rel_diff_dDo_dH0_dalpha_vs_fp64": float(f"{max(rel):.3e}"),
+            "max_diff_rel_to_gradient_norm": float(f"{max(rel_norm):.3e}")}
 
 
 def copy_bandwidth_gbs(torch) -> float:

@@ -147,6 +147,7 @@ struct NodeOut {
     T pstar, ux, uy;       // p* (Eq. 21), u (Eq. 22)
     T Ftx, Fty;            // total force F_t
     T rho, tau;            // mixture density and relaxation time
+    T inv_rho, snu;        // 1 / rho, s_nu = 1 / (tau + 1/2)
     T phi1, phi2;          // order parameters
     T v1x, v1y, v2x, v2y;  // theta_i n_i - (1/3) sum_k theta_k n_k for i = 1, 2
     T Hx, Hy;              // magnetic field
@@ -232,7 +233,8 @@ __host__ __device__ __forceinline__ NodeOut<T> node_physics(const StepConst<T>& 
     const T cp = -pstar * (T(1) / T(3));
     const T F0x = Fsx + Fmx + cp * grx + P.drive + rho * P.grav_x;
     const T F0y = Fsy + Fmy + cp * gry + rho * P.grav_y;
-    const T ihr = T(0.5) / rho;
+    const T inv_rho = T(1) / rho;
+    const T ihr = T(0.5) * inv_rho;
     const T u0x = jx + F0x * ihr, u0y = jy + F0y * ihr;
 
     // Viscous force from the non-equilibrium stress of f - f^eq(p*, u0); the second
@@ -253,6 +255,8 @@ __host__ __device__ __forceinline__ NodeOut<T> node_physics(const StepConst<T>& 
     o.pstar = pstar;
     o.rho = rho;
     o.tau = tau;
+    o.inv_rho = inv_rho;
+    o.snu = snu;
     o.phi1 = p1;
     o.phi2 = p2;
     return o;
@@ -266,7 +270,7 @@ template <typename T>
 __host__ __device__ __forceinline__ void collide_f(const NodeOut<T>& o, const T f[9], T out[9]) {
     const T ux = o.ux, uy = o.uy;
     const T usq = T(1.5) * (ux * ux + uy * uy);
-    const T fr = T(3) / o.rho;
+    const T fr = T(3) * o.inv_rho;
     const T fx = fr * o.Ftx, fy = fr * o.Fty;  // 3 F/rho
     const T w0 = T(4) / T(9), wa = T(1) / T(9), wd = T(1) / T(36);
     T fb[9], F[9];
@@ -284,7 +288,7 @@ __host__ __device__ __forceinline__ void collide_f(const NodeOut<T>& o, const T 
     }
     const T mxx = ((f[1] + f[3]) - (f[2] + f[4])) - ((fb[1] + fb[3]) - (fb[2] + fb[4]));
     const T mxy = ((f[5] + f[7]) - (f[6] + f[8])) - ((fb[5] + fb[7]) - (fb[6] + fb[8]));
-    const T k = T(0.25) * (T(1) - T(1) / (o.tau + T(0.5)));
+    const T k = T(0.25) * (T(1) - o.snu);
     const T kx = k * mxx, ky = k * mxy;
     out[0] = fb[0];
     out[1] = fb[1] + kx + F[1];

@@ -77,15 +77,52 @@ __global__ void __launch_bounds__(BX* BY)
 
 // ---------------------------------------------------------------------------------
 // Fused step: stencils + forces + MRT collision of f + phase-field collision of g1, g2,
-// then push streaming with halfway bounce-back at the walls.
+// then push streaming with halfway bounce-back.  The phi1, phi2 and psi' neighbourhoods
+// are staged through LDS: a block loads its (64 + 2) x (CY + 2) tile of the three planes
+// once (coalesced rows; columns wrap, rows beyond the walls mirrored for phi and zero
+// for psi'), then every node reads its nine-point neighbourhoods from LDS.
 // ---------------------------------------------------------------------------------
+constexpr int CY = 4;
+
 template <typename T>
-__global__ void __launch_bounds__(BX* BY)
+__device__ __forceinline__ Nb9<T> lds_nb(const T (*t)[BX + 2], int lx, int ly) {
+    Nb9<T> v;
+    v.c = t[ly][lx];
+    v.e = t[ly][lx + 1];
+    v.w = t[ly][lx - 1];
+    v.n = t[ly + 1][lx];
+    v.s = t[ly - 1][lx];
+    v.ne = t[ly + 1][lx + 1];
+    v.nw = t[ly + 1][lx - 1];
+    v.sw = t[ly - 1][lx - 1];
+    v.se = t[ly - 1][lx + 1];
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX* CY)
     k_collide_stream(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ phi,
-                     const T* __restrict__ psi, StepConst<T> P) {
-    const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+                         const T* __restrict__ psi, StepConst<T> P) {
+    __shared__ T t1[CY + 2][BX + 2], t2[CY + 2][BX + 2], tp[CY + 2][BX + 2];
+    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * CY;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    for (int q = tid; q < (BX + 2) * (CY + 2); q += BX * CY) {
+        const int ly = q / (BX + 2), lx = q - ly * (BX + 2);
+        int i = i0 + lx - 1;
+        while (i < 0) i += P.nx;
+        while (i >= P.nx) i -= P.nx;
+        const int jr = j0 + ly - 1;
+        const int j = jr < 0 ? 0 : (jr >= P.ny ? P.ny - 1 : jr);
+        const long long k = (long long)j * P.pitch + i;
+        t1[ly][lx] = phi[k];
+        t2[ly][lx] = phi[P.plane + k];
+        tp[ly][lx] = (jr < 0 || jr >= P.ny) ? T(0) : psi[k];
+    }
+    __syncthreads();
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= P.nx || j >= P.ny) return;
-    collide_stream_node(src, dst, phi, psi, P, i, j);
+    const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
+    collide_stream_nb(src, dst, lds_nb<T>(t1, lx, ly), lds_nb<T>(t2, lx, ly), lds_nb<T>(tp, lx, ly), P, i, j);
 }
 
 // ---------------------------------------------------------------------------------
@@ -273,7 +310,8 @@ void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s) {
 
 template <typename T>
 void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_collide_stream<T>, grid2(P.nx, P.ny), dim3(BX, BY), 0, s, src, dst, phi, psi, P);
+    hipLaunchKernelGGL(k_collide_stream<T>, dim3((P.nx + BX - 1) / BX, (P.ny + CY - 1) / CY), dim3(BX, CY), 0, s, src,
+                       dst, phi, psi, P);
 }
 
 template <typename T>

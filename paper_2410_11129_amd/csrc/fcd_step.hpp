@@ -6,7 +6,20 @@
 
 #include "fcd_device.hpp"
 
+
 namespace fcd {
+
+// Load of a state value read once per step.  In FP64 the two state buffers (2 x 27
+// planes) exceed the 256 MB last-level cache of the 2048 x 512 channel, so the loads are
+// marked non-temporal (they do not displace lines that are reused); in FP32 the state
+// fits and the plain load lets the next step find it in the cache.
+template <typename T>
+__device__ __forceinline__ T ld_state(const T* p) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
 
 // Order parameters (Eq. 32, 24) and mu_r = 1 / sum phi_i/(1+chi_i) (Eq. 8) at (i, j).
 template <typename T>
@@ -28,20 +41,18 @@ __device__ __forceinline__ void phase_node(const T* __restrict__ dist, T* __rest
 }
 
 // Stencils + forces + MRT collision of f + phase-field collisions of g1, g2 at (i, j),
-// then push streaming with halfway bounce-back at the walls.
+// then push streaming with halfway bounce-back at the walls.  The phi1, phi2 and psi'
+// neighbourhoods are given (from global memory or from an LDS tile).
 template <typename T>
-__device__ __forceinline__ void collide_stream_node(const T* __restrict__ src, T* __restrict__ dst,
-                                                    const T* __restrict__ phi, const T* __restrict__ psi,
-                                                    const StepConst<T>& P, int i, int j) {
+__device__ __forceinline__ void collide_stream_nb(const T* __restrict__ src, T* __restrict__ dst,
+                                                  const Nb9<T>& a1, const Nb9<T>& a2, const Nb9<T>& ps,
+                                                  const StepConst<T>& P, int i, int j) {
     const long long pl = P.plane;
     const NbIdx x = nb_index(i, j, P.nx, P.ny, P.pitch);
     const long long k = x.c;
     T f[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) f[a] = src[a * pl + k];
-    const Nb9<T> a1 = load_nb(phi, x);
-    const Nb9<T> a2 = load_nb(phi + pl, x);
-    const Nb9<T> ps = load_nb_psi(psi, x, j, P.ny);
+    for (int a = 0; a < 9; ++a) f[a] = ld_state(src + a * pl + k);
     const NodeOut<T> o = node_physics(P, f, a1, a2, ps);
 
     // Destinations of the push: (i + ex, j + ey); a population that would cross a wall
@@ -73,7 +84,7 @@ __device__ __forceinline__ void collide_stream_node(const T* __restrict__ src, T
         T g[9], out[9];
         const T* S = src + (9 + 9 * comp) * pl;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) g[a] = S[a * pl + k];
+        for (int a = 0; a < 9; ++a) g[a] = ld_state(S + a * pl + k);
         collide_g(o, P.omega_phi, comp == 0 ? o.phi1 : o.phi2, comp == 0 ? o.v1x : o.v2x,
                   comp == 0 ? o.v1y : o.v2y, g, out);
         T* D = dst + (9 + 9 * comp) * pl;
@@ -87,6 +98,15 @@ __device__ __forceinline__ void collide_stream_node(const T* __restrict__ src, T
         D[pSW * pl + nSW] = out[7];
         D[pSE * pl + nSE] = out[8];
     }
+}
+
+// The same with the neighbourhoods read from global memory.
+template <typename T>
+__device__ __forceinline__ void collide_stream_node(const T* __restrict__ src, T* __restrict__ dst,
+                                                    const T* __restrict__ phi, const T* __restrict__ psi,
+                                                    const StepConst<T>& P, int i, int j) {
+    const NbIdx x = nb_index(i, j, P.nx, P.ny, P.pitch);
+    collide_stream_nb(src, dst, load_nb(phi, x), load_nb(phi + P.plane, x), load_nb_psi(psi, x, j, P.ny), P, i, j);
 }
 
 }  // namespace fcd
