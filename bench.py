@@ -28,10 +28,10 @@ METRIC = "MLUPS + HBM GB/s of coupled step; batched instances/hr; adjoint/forwar
 # two rocprofv3 counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors that a
 # 2 GiB device copy reads on the same counters), with the first 16 hex digits of the sha256
 # of the sources the kernel was built from; reported only while the sources are unchanged.
-TRAFFIC_BYTES = {"collide_stream": (2 * 131785 + 230388) * 1024}
-TRAFFIC_SOURCES = {"paper_2410_11129_amd/csrc/fcd_step.hpp": "c9d8c6994fc913b0",
-                   "paper_2410_11129_amd/csrc/fcd_device.hpp": "3d8b1d61f08ba1c8",
-                   "paper_2410_11129_amd/csrc/fcd_kernels.hip": "84081dda44f74502"}
+TRAFFIC_BYTES = {"collide_stream": (2 * 129978 + 230388) * 1024}
+TRAFFIC_SOURCES = {"paper_2410_11129_amd/csrc/fcd_step.hpp": "137d66caf7a347bc",
+                   "paper_2410_11129_amd/csrc/fcd_device.hpp": "610429870637d8d2",
+                   "paper_2410_11129_amd/csrc/fcd_kernels.hip": "56f5d6bde17a28c5"}
 
 
 def sources_match(table: dict) -> bool:
@@ -305,8 +305,8 @@ def main() -> int:
         per_kind[k] = {"launches": n, "avg_us": round(avg_s * 1e6, 3), "ms_per_step": round(ms / prof_steps, 4)}
         if k in VALUES_PER_SITE:
             per_kind[k]["GBps"] = round(VALUES_PER_SITE[k] * esz * sites / avg_s / 1e9, 1)
-    # Roofline of the dominant HBM-bound kernel, the fused collide-and-stream (rocprof: ~109 us of
-    # the step's ~1.15 ms; the finest smoothing kernels follow at ~10 us per launch).  The rest
+    # Roofline of the dominant HBM-bound kernel, the fused collide-and-stream (rocprof: ~82 us of
+    # the step's ~1.1 ms; the finest smoothing kernels follow at ~10 us per launch).  The rest
     # of the potential solve is a chain of small coarse-level kernels bound by launch and
     # dependency latency, not by bandwidth, so no HBM roofline applies to them.
     dom = "collide_stream"
