@@ -131,12 +131,28 @@ __device__ __forceinline__ T prolong_at(const PotLevel<T>& Cl, int i, int j) {
 // fly, 2 finest level with a given f (adjoint solves).  With res != nullptr the block
 // also reduces max |residual| and max |C u| of the INPUT iterate into res[0..1].
 // ---------------------------------------------------------------------------------
-constexpr int TSX = 64, TSY = 16;
-constexpr int THX = TSX + 2, THY = TSY + 2;
-constexpr int TS_T = 256;  // 32 x 8 threads: one node of each colour per thread
+// Tile geometry: SX x SY nodes, one node of each colour per thread (SX/2 x SY/2 threads).
+// The finest level, which is bandwidth-bound, uses 64 x 16 tiles (256 threads); the
+// coarser levels, whose kernels are bound by latency, use 32 x 8 tiles of one wavefront,
+// whose barriers are cheap and which spread a small level over more CUs.
+template <int SX_, int SY_>
+struct TileGeom {
+    static constexpr int SX = SX_, SY = SY_;
+    static constexpr int HX = SX + 2, HY = SY + 2;    // with the halo
+    static constexpr int NT = SX * SY / 4;             // threads
+    static constexpr int HN = HX * HY;
+    static constexpr int HPER = (HN + NT - 1) / NT;    // halo-tile loads per thread
+    static constexpr int FPER = SX * SY / NT;          // interior values per thread (4)
+    // coarse correction tile for the fused prolongation: coarse columns I0-1 .. I0+SX/2
+    // and rows J0-1 .. J0+SY/2 of the tile's fine origin (i0, j0) = (2 I0, 2 J0)
+    static constexpr int CX = SX / 2 + 2, CY = SY / 2 + 2;
+    static constexpr int CPER = (CX * CY + NT - 1) / NT;
+};
+using FineTile = TileGeom<64, 16>;
+using CoarseTile = TileGeom<32, 8>;
 
-template <typename T>
-__device__ __forceinline__ MgEval<T> tile_eval(const T (*su)[THX], const T (*sm)[THX], int lx, int ly, bool bot,
+template <typename T, int HX>
+__device__ __forceinline__ MgEval<T> tile_eval(const T (*su)[HX], const T (*sm)[HX], int lx, int ly, bool bot,
                                                bool top, const PotLevel<T>& L, T fval, bool rhs_from_field) {
     const T mc = sm[ly][lx], me = sm[ly][lx + 1], mw = sm[ly][lx - 1];
     const T mn = sm[ly + 1][lx], ms = sm[ly - 1][lx];
@@ -182,12 +198,6 @@ __device__ __forceinline__ MgEval<T> tile_eval(const T (*su)[THX], const T (*sm)
 // Tile + halo loads, issued together before any LDS store (the loads of one thread
 // are independent, so their latencies overlap).  Columns wrap periodically, rows
 // beyond the walls are clamped (mu mirrored; u there is never read).
-constexpr int TH_N = THX * THY;
-constexpr int TH_PER = (TH_N + TS_T - 1) / TS_T;
-// Coarse correction tile for the fused prolongation: coarse columns I0-1 .. I0+32 and
-// rows J0-1 .. J0+8 of the tile's fine origin (i0, j0) = (2 I0, 2 J0).
-constexpr int CHX = TSX / 2 + 2, CHY = TSY / 2 + 2;
-constexpr int CH_PER = (CHX * CHY + TS_T - 1) / TS_T;
 
 __device__ __forceinline__ int wrap_col(int i, int nx) {
     while (i < 0) i += nx;
@@ -197,14 +207,14 @@ __device__ __forceinline__ int wrap_col(int i, int nx) {
 
 __device__ __forceinline__ int clamp_row(int j, int ny) { return j < 0 ? 0 : (j >= ny ? ny - 1 : j); }
 
-template <typename T>
+template <typename T, typename G>
 __device__ __forceinline__ void load_tile(const PotLevel<T>& L, const T* __restrict__ uin, int i0, int j0,
-                                          T (&uv)[TH_PER], T (&mv)[TH_PER]) {
+                                          T (&uv)[G::HPER], T (&mv)[G::HPER]) {
 #pragma unroll
-    for (int r = 0; r < TH_PER; ++r) {
-        const int q = threadIdx.x + r * TS_T;
-        if (q < TH_N) {
-            const int ly = q / THX, lx = q - ly * THX;
+    for (int r = 0; r < G::HPER; ++r) {
+        const int q = threadIdx.x + r * G::NT;
+        if (q < G::HN) {
+            const int ly = q / G::HX, lx = q - ly * G::HX;
             const long long k = (long long)clamp_row(j0 + ly - 1, L.ny) * L.pitch + wrap_col(i0 + lx - 1, L.nx);
             uv[r] = uin[k];
             mv[r] = L.mu[k];
@@ -214,8 +224,8 @@ __device__ __forceinline__ void load_tile(const PotLevel<T>& L, const T* __restr
 
 // Prolongation at fine tile cell (lx, ly) from the coarse tile sc (bilinear weights
 // 9/16, 3/16, 3/16, 1/16; coarse ghost rows by the kappa rule).
-template <typename T>
-__device__ __forceinline__ T prolong_tile(const T (*sc)[CHX], int i0, int j0, int lx, int ly, int nyc, T kappa) {
+template <typename T, int CX>
+__device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int lx, int ly, int nyc, T kappa) {
     const int i = i0 + lx - 1, j = j0 + ly - 1;  // unwrapped fine coordinates
     const int I0 = i0 >> 1, J0 = j0 >> 1;
     const int lI = (i >> 1) - I0 + 1, lI2 = (i & 1) ? lI + 1 : lI - 1;
@@ -234,65 +244,66 @@ __device__ __forceinline__ T prolong_tile(const T (*sc)[CHX], int i0, int j0, in
            T(1) / T(16) * gy * sc[lJ2][lI2];
 }
 
-template <typename T, bool PROLONG, int MODE>
-__global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
-                                                         T* __restrict__ uout, PotLevel<T> Cl,
-                                                         unsigned long long* __restrict__ res, int inner) {
-    __shared__ T su[THY][THX];
-    __shared__ T sm[THY][THX];
-    __shared__ T sf[MODE == 1 ? 1 : TSY][TSX];
-    __shared__ T sc[PROLONG ? CHY : 1][CHX];
-    __shared__ double wmax[2][TS_T / 64];
-    const int i0 = blockIdx.x * TSX, j0 = blockIdx.y * TSY;
+template <typename T, typename G, bool PROLONG, int MODE>
+__global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
+                                                          T* __restrict__ uout, PotLevel<T> Cl,
+                                                          unsigned long long* __restrict__ res, int inner) {
+    constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT, CX = G::CX, CY = G::CY;
+    __shared__ T su[HY][HX];
+    __shared__ T sm[HY][HX];
+    __shared__ T sf[MODE == 1 ? 1 : SY][SX];
+    __shared__ T sc[PROLONG ? CY : 1][CX];
+    __shared__ double wmax[2][NT / 64];
+    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * SY;
     const int tid = threadIdx.x;
-    T uv[TH_PER], mv[TH_PER], fv[4], cv[CH_PER];
-    load_tile(L, uin, i0, j0, uv, mv);
+    T uv[G::HPER], mv[G::HPER], fv[G::FPER], cv[G::CPER];
+    load_tile<T, G>(L, uin, i0, j0, uv, mv);
     if (MODE != 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int q = tid + r * TS_T;
-            const int ly = q / TSX, lx = q - ly * TSX;
+        for (int r = 0; r < G::FPER; ++r) {
+            const int q = tid + r * NT;
+            const int ly = q / SX, lx = q - ly * SX;
             const int i = i0 + lx, j = j0 + ly;
             fv[r] = (i < L.nx && j < L.ny) ? L.f[(long long)j * L.pitch + i] : T(0);
         }
     }
     if (PROLONG) {
 #pragma unroll
-        for (int r = 0; r < CH_PER; ++r) {
-            const int q = tid + r * TS_T;
-            if (q < CHX * CHY) {
-                const int ly = q / CHX, lx = q - ly * CHX;
+        for (int r = 0; r < G::CPER; ++r) {
+            const int q = tid + r * NT;
+            if (q < CX * CY) {
+                const int ly = q / CX, lx = q - ly * CX;
                 const int I = wrap_col((i0 >> 1) - 1 + lx, Cl.nx), J = clamp_row((j0 >> 1) - 1 + ly, Cl.ny);
                 cv[r] = Cl.u[(long long)J * Cl.pitch + I];
             }
         }
 #pragma unroll
-        for (int r = 0; r < CH_PER; ++r) {
-            const int q = tid + r * TS_T;
-            if (q < CHX * CHY) sc[q / CHX][q % CHX] = cv[r];
+        for (int r = 0; r < G::CPER; ++r) {
+            const int q = tid + r * NT;
+            if (q < CX * CY) sc[q / CX][q % CX] = cv[r];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < TH_PER; ++r) {
-        const int q = tid + r * TS_T;
-        if (q < TH_N) {
-            const int ly = q / THX, lx = q - ly * THX;
+    for (int r = 0; r < G::HPER; ++r) {
+        const int q = tid + r * NT;
+        if (q < G::HN) {
+            const int ly = q / HX, lx = q - ly * HX;
             T u = uv[r];
-            if (PROLONG) u += prolong_tile<T>(sc, i0, j0, lx, ly, Cl.ny, Cl.kappa);
+            if (PROLONG) u += prolong_tile<T, CX>(sc, i0, j0, lx, ly, Cl.ny, Cl.kappa);
             su[ly][lx] = u;
             sm[ly][lx] = mv[r];
         }
     }
     if (MODE != 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int q = tid + r * TS_T;
-            sf[MODE == 1 ? 0 : q / TSX][q % TSX] = fv[r];
+        for (int r = 0; r < G::FPER; ++r) {
+            const int q = tid + r * NT;
+            sf[MODE == 1 ? 0 : q / SX][q % SX] = fv[r];
         }
     }
     __syncthreads();
-    const int tx = tid & 31, ty = tid >> 5;
+    const int tx = tid % (SX / 2), ty = tid / (SX / 2);
     if (res) {
         double rm = 0.0, scl = 0.0;
 #pragma unroll
@@ -300,8 +311,8 @@ __global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T*
             const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
             const int i = i0 + lx - 1, j = j0 + ly - 1;
             if (i < L.nx && j < L.ny) {
-                const MgEval<T> e = tile_eval<T>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
-                                                 MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
+                const MgEval<T> e = tile_eval<T, HX>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
+                                                     MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
                 const T u = su[ly][lx];
                 rm = nan_max(rm, fabs((double)(e.acc - e.C * u - e.rhs)));
                 scl = nan_max(scl, fabs((double)(e.C * u)));
@@ -319,7 +330,7 @@ __global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T*
         __syncthreads();
         if (tid < 2) {
             double m = wmax[tid][0];
-            for (int w = 1; w < TS_T / 64; ++w) m = nan_max(m, wmax[tid][w]);
+            for (int w = 1; w < NT / 64; ++w) m = nan_max(m, wmax[tid][w]);
             atomicMax(res + tid, (unsigned long long)__double_as_longlong(m));
         }
     }
@@ -329,8 +340,8 @@ __global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T*
             const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
             const int i = i0 + lx - 1, j = j0 + ly - 1;
             if (i < L.nx && j < L.ny) {
-                const MgEval<T> e = tile_eval<T>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
-                                                 MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
+                const MgEval<T> e = tile_eval<T, HX>(su, sm, lx, ly, j == 0, j == L.ny - 1, L,
+                                                     MODE == 1 ? T(0) : sf[MODE == 1 ? 0 : ly - 1][lx - 1], MODE == 1);
                 const T old = su[ly][lx];
                 su[ly][lx] = (e.acc + e.cself * old - e.rhs) / (e.C + e.cself);
             }
@@ -338,9 +349,9 @@ __global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T*
         }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int q = tid + r * TS_T;
-        const int ly = q / TSX, lx = q - ly * TSX;
+    for (int r = 0; r < G::FPER; ++r) {
+        const int q = tid + r * NT;
+        const int ly = q / SX, lx = q - ly * SX;
         const int i = i0 + lx, j = j0 + ly;
         if (i < L.nx && j < L.ny) uout[(long long)j * L.pitch + i] = su[ly + 1][lx + 1];
     }
@@ -350,48 +361,49 @@ __global__ void __launch_bounds__(TS_T) k_mg_smooth_tile(PotLevel<T> L, const T*
 // iterate and mu with halo, forms the residual f - L u of its nodes in LDS and writes
 // the 32 x 8 coarse right-hand sides (average of the four children) and a zero coarse
 // correction.  Requires nx = 2 nxc and ny = 2 nyc.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(TS_T) k_mg_restrict_tile(PotLevel<T> F, PotLevel<T> Cl) {
-    __shared__ T su[THY][THX];
-    __shared__ T sm[THY][THX];
-    __shared__ T sr[TSY][TSX];
-    const int i0 = blockIdx.x * TSX, j0 = blockIdx.y * TSY;
+template <typename T, typename G, int MODE>
+__global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<T> Cl) {
+    constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT;
+    __shared__ T su[HY][HX];
+    __shared__ T sm[HY][HX];
+    __shared__ T sr[SY][SX];
+    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * SY;
     const int tid = threadIdx.x;
-    T uv[TH_PER], mv[TH_PER], fv[4];
-    load_tile(F, F.u, i0, j0, uv, mv);
+    T uv[G::HPER], mv[G::HPER], fv[G::FPER];
+    load_tile<T, G>(F, F.u, i0, j0, uv, mv);
     if (MODE != 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int q = tid + r * TS_T;
-            const int ly = q / TSX, lx = q - ly * TSX;
+        for (int r = 0; r < G::FPER; ++r) {
+            const int q = tid + r * NT;
+            const int ly = q / SX, lx = q - ly * SX;
             const int i = i0 + lx, j = j0 + ly;
             fv[r] = (i < F.nx && j < F.ny) ? F.f[(long long)j * F.pitch + i] : T(0);
         }
     }
 #pragma unroll
-    for (int r = 0; r < TH_PER; ++r) {
-        const int q = tid + r * TS_T;
-        if (q < TH_N) {
-            su[q / THX][q % THX] = uv[r];
-            sm[q / THX][q % THX] = mv[r];
+    for (int r = 0; r < G::HPER; ++r) {
+        const int q = tid + r * NT;
+        if (q < G::HN) {
+            su[q / HX][q % HX] = uv[r];
+            sm[q / HX][q % HX] = mv[r];
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int q = tid + r * TS_T;
-        const int ly = q / TSX, lx = q - ly * TSX;
+    for (int r = 0; r < G::FPER; ++r) {
+        const int q = tid + r * NT;
+        const int ly = q / SX, lx = q - ly * SX;
         const int i = i0 + lx, j = j0 + ly;
         T v = T(0);
         if (i < F.nx && j < F.ny) {
-            const MgEval<T> e =
-                tile_eval<T>(su, sm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F, MODE == 1 ? T(0) : fv[r], MODE == 1);
+            const MgEval<T> e = tile_eval<T, HX>(su, sm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F,
+                                                 MODE == 1 ? T(0) : fv[r], MODE == 1);
             v = e.rhs - (e.acc - e.C * su[ly + 1][lx + 1]);
         }
         sr[ly][lx] = v;
     }
     __syncthreads();
-    const int cx = tid & 31, cy = tid >> 5;
+    const int cx = tid % (SX / 2), cy = tid / (SX / 2);
     const int I = (i0 >> 1) + cx, J = (j0 >> 1) + cy;
     if (I < Cl.nx && J < Cl.ny) {
         const long long k = (long long)J * Cl.pitch + I;
@@ -574,14 +586,13 @@ void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hip
     hipLaunchKernelGGL(k_mg_restrict_residual<T>, pgrid(C.nx, C.ny), dim3(PX, PY), 0, s, F, C);
 }
 
-template <typename T>
-void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
-                           unsigned long long* res, int inner, hipStream_t s) {
-    const dim3 g((L.nx + TSX - 1) / TSX, (L.ny + TSY - 1) / TSY);
+template <typename T, typename G>
+void launch_smooth_geom(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
+                        unsigned long long* res, int inner, hipStream_t s) {
+    const dim3 g((L.nx + G::SX - 1) / G::SX, (L.ny + G::SY - 1) / G::SY);
     const PotLevel<T> Cl = prolong_from ? *prolong_from : PotLevel<T>{};
-    if (res) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, res, 2LL, 0ULL);
 #define FCD_TILE_LAUNCH(P, M) \
-    hipLaunchKernelGGL((k_mg_smooth_tile<T, P, M>), g, dim3(TS_T), 0, s, L, uin, uout, Cl, res, inner)
+    hipLaunchKernelGGL((k_mg_smooth_tile<T, G, P, M>), g, dim3(G::NT), 0, s, L, uin, uout, Cl, res, inner)
     if (prolong_from) {
         if (mode == 0) FCD_TILE_LAUNCH(true, 0);
         else if (mode == 1) FCD_TILE_LAUNCH(true, 1);
@@ -594,15 +605,29 @@ void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const Po
 #undef FCD_TILE_LAUNCH
 }
 
+// Finest level (modes 1, 2): 64 x 16 tiles; coarser levels (mode 0): 32 x 8 tiles.
+template <typename T>
+void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
+                           unsigned long long* res, int inner, hipStream_t s) {
+    if (res) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, res, 2LL, 0ULL);
+    if (mode == 0)
+        launch_smooth_geom<T, CoarseTile>(L, uin, uout, prolong_from, mode, res, inner, s);
+    else
+        launch_smooth_geom<T, FineTile>(L, uin, uout, prolong_from, mode, res, inner, s);
+}
+
 template <typename T>
 void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mode, hipStream_t s) {
-    const dim3 g((F.nx + TSX - 1) / TSX, (F.ny + TSY - 1) / TSY);
-    if (mode == 0)
-        hipLaunchKernelGGL((k_mg_restrict_tile<T, 0>), g, dim3(TS_T), 0, s, F, C);
-    else if (mode == 1)
-        hipLaunchKernelGGL((k_mg_restrict_tile<T, 1>), g, dim3(TS_T), 0, s, F, C);
+    if (mode == 0) {
+        const dim3 g((F.nx + CoarseTile::SX - 1) / CoarseTile::SX, (F.ny + CoarseTile::SY - 1) / CoarseTile::SY);
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, CoarseTile, 0>), g, dim3(CoarseTile::NT), 0, s, F, C);
+        return;
+    }
+    const dim3 g((F.nx + FineTile::SX - 1) / FineTile::SX, (F.ny + FineTile::SY - 1) / FineTile::SY);
+    if (mode == 1)
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, FineTile, 1>), g, dim3(FineTile::NT), 0, s, F, C);
     else
-        hipLaunchKernelGGL((k_mg_restrict_tile<T, 2>), g, dim3(TS_T), 0, s, F, C);
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, FineTile, 2>), g, dim3(FineTile::NT), 0, s, F, C);
 }
 
 template <typename T>
