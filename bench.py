@@ -91,7 +91,7 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     nsteps_target = ws[0].steps
     bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
     bt.init_droplets()
-    rows, block = bt.autotune(1)
+    rows, block, fused = bt.autotune(1)
     bt.step(4)
     torch.cuda.synchronize()
     it0 = bt.stats()[1]
@@ -119,7 +119,7 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     return {"channels": len(ws), "sites": sites, "steps_per_channel": nsteps_target,
             "batch_fp32_ms_per_step": round(dt_batch * 1e3, 4), "batch_MLUPS": round(sites / dt_batch / 1e6, 1),
             "batch_sor_sweeps_per_step": round(sweeps, 2),
-            "schedule": {"tile_rows": rows, "block_sweeps": block},
+            "schedule": {"tile_rows": rows, "block_sweeps": block, "fused_sweeps": fused},
             "instances_per_hour_batch_fp32": round(batch_iph, 1),
             "instances_per_hour_sequential_fp64": round(seq_iph, 1),
             "speedup": round(batch_iph / seq_iph, 2),

@@ -75,8 +75,8 @@ typedef struct {
     double pot_tol;  /* potential solve stops when max |L(psi0 + psi')| <= pot_tol * H0, or
                         at the working precision's rounding floor 16 eps max |C psi'| (C: sum
                         of the operator's coefficients at a node) if that is larger */
-    double pot_omega; /* SOR over-relaxation in (0, 2); 0 selects 2 / (1 + sin(pi / (ny + 1))),
-                         optimal for the constant-mu channel.  Unused by multigrid. */
+    double pot_omega; /* SOR over-relaxation in (0, 2); 0 selects 2 / (1 + sin(pi / (ny + 1))).
+                         Multigrid uses the default on its coarsest level only. */
     int32_t pot_solver;      /* FCD_SOLVER_SOR or FCD_SOLVER_MG */
     int32_t pot_check_every; /* SOR sweeps / multigrid V-cycles between residual tests */
     int32_t pot_max_iters;   /* SOR sweeps / V-cycles allowed per solve */
@@ -264,18 +264,23 @@ fcd_status fcd_batch_read_state(fcd_batch* b, int32_t k, double* out);
 fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double* out);
 
 /* Launch schedule of the batch: kernels run over 64 x tile_rows tiles (tile_rows 1, 2,
- * 4 or 8) and the potential sweeps are replayed as HIP graphs of block_sweeps sweeps (a
+ * 4 or 8), the potential sweeps are replayed as HIP graphs of block_sweeps sweeps (a
  * multiple of pot_check_every of channel 0, the interval of the device-side convergence
- * test).  The schedule changes launch geometry only: states are bitwise the same under
- * every schedule.  Default: tile_rows 4, block_sweeps 8 * pot_check_every. */
-fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps);
+ * test, at most 2^20), and fused_sweeps > 0 runs that many four-colour SOR sweeps per
+ * launch on 64 x 16 tiles with their halo in LDS (1 or 2; needs pot_check_every to be a
+ * multiple of 2 fused_sweeps), 0 one launch per colour.  The schedule changes launch
+ * geometry only: states are bitwise the same under every schedule.  Default: tile_rows
+ * 4, block_sweeps 8 * pot_check_every, the largest fused_sweeps allowed.
+ * FCD_ERR_ARG for any other value. */
+fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps, int32_t fused_sweeps);
 
 /* Autotuner: tries every tile_rows in {1, 2, 4, 8} with block_sweeps in
- * {2, 8, 32} * pot_check_every, each for steps_per_candidate real steps of the batch
- * (timed with HIP events; one untimed step per tile shape first), keeps the fastest and
- * writes it to choice = {tile_rows, block_sweeps}.  Advances the batch by
- * 4 (1 + 3 steps_per_candidate) steps.  Sync. */
-fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[2]);
+ * {2, 8, 32} * pot_check_every and every allowed fused_sweeps in {0, 1, 2}, each for
+ * steps_per_candidate real steps of the batch (timed with HIP events; one untimed step
+ * per tile shape and fusion first), keeps the fastest and writes it to
+ * choice = {tile_rows, block_sweeps, fused_sweeps}.  Advances the batch by
+ * 4 F (1 + 3 steps_per_candidate) steps, F the number of allowed fusions.  Sync. */
+fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[3]);
 
 /* Batched adjoint: the adjoint of fcd_adjoint_forward / _backward for every channel of
  * the batch at once (one launch per kernel for all channels, the adjoint potential

@@ -36,8 +36,11 @@ constexpr size_t OFF_ROWS = 1024;  // ny * 8 doubles: per-row partial sums
 
 size_t elem_size(int precision) { return precision == FCD_FP64 ? sizeof(double) : sizeof(float); }
 
-// Optimum SOR factor 2 / (1 + sin(pi / (ny + 1))) for the Laplacian between Dirichlet
-// rows ny + 1 cells apart.
+// Default SOR factor 2 / (1 + sin(pi / (ny + 1))): the optimum of the five-point
+// Laplacian between Dirichlet rows ny + 1 cells apart.  For the nine-point operator the
+// asymptotic optimum is larger (2 / (1 + sqrt(1 - rho^2)), rho = 0.4 + 0.6 cos(pi /
+// (ny + 1))), but the warm-started solves of a time step are not in the asymptotic
+// regime, and which factor needs fewer sweeps there depends on the field direction.
 double sor_omega_opt(int ny) { return 2.0 / (1.0 + std::sin(3.14159265358979323846 / (ny + 1))); }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -737,12 +740,13 @@ constexpr int BATCH_MAX_CHANNELS = 65536;
 
 struct BatchLayout {
     std::vector<int> pitch;
-    std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev;  // into state / aux
+    std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev, off_alt;  // into state / aux
     std::vector<int> tile0[fcd::BATCH_SHAPES], tiles_x[fcd::BATCH_SHAPES];
     std::vector<int> ctile0[fcd::BATCH_SHAPES], ctiles_x[fcd::BATCH_SHAPES];
-    int ntiles[fcd::BATCH_SHAPES] = {}, nctiles[fcd::BATCH_SHAPES] = {};
+    std::vector<int> stile0, stiles_x;  // fused-sweep tiles
+    int ntiles[fcd::BATCH_SHAPES] = {}, nctiles[fcd::BATCH_SHAPES] = {}, nstiles = 0;
     size_t state_bytes = 0, aux_bytes = 0, scratch_bytes = 0;
-    size_t off_inst = 0, off_tiles[fcd::BATCH_SHAPES] = {}, off_ctiles[fcd::BATCH_SHAPES] = {};
+    size_t off_inst = 0, off_tiles[fcd::BATCH_SHAPES] = {}, off_ctiles[fcd::BATCH_SHAPES] = {}, off_stiles = 0;
     size_t off_res = 0, off_active = 0, off_counts = 0;
     size_t off_rows = 0, off_cent = 0, off_result = 0;
 };
@@ -775,6 +779,14 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
         L->aux_bytes += plane;
         L->off_prev.push_back(L->aux_bytes);
         L->aux_bytes += plane;
+        L->off_alt.push_back(L->aux_bytes);
+        L->aux_bytes += plane;
+        {
+            const int sx = (l.nx + fcd::FUSED_X - 1) / fcd::FUSED_X, sy = (l.ny + fcd::FUSED_Y - 1) / fcd::FUSED_Y;
+            L->stile0.push_back(L->nstiles);
+            L->stiles_x.push_back(sx);
+            L->nstiles += sx * sy;
+        }
         for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
             const int ty = BT_ROWS[s];
             const int tx = (l.nx + BT_X - 1) / BT_X, tyc = (l.ny + ty - 1) / ty;
@@ -797,6 +809,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
         L->off_ctiles[s] = off;
         off = align256(off + (size_t)L->nctiles[s] * sizeof(int));
     }
+    L->off_stiles = off;
+    off = align256(off + (size_t)L->nstiles * sizeof(int));
     L->off_res = off;
     off = align256(off + 2 * (size_t)n * sizeof(unsigned long long));
     L->off_active = off;
@@ -832,9 +846,11 @@ struct fcd_batch {
     long long iters;
     double last_resid;
     double* host;  // pinned: [0] active count and NaN count (two ints), [1..] n x 4 diagnostics
-    // launch schedule: tile shape (rows 1, 2, 4, 8) and sweeps per graph-launched block
+    // launch schedule: tile shape (rows 1, 2, 4, 8), sweeps per graph-launched block and
+    // sweeps per fused SOR launch (0: one launch per colour)
     int shape;
     int block_sweeps;
+    int fused;
     GraphCache graphs;
     // batched adjoint
     int init_fresh;
@@ -869,6 +885,9 @@ fcd::BatchTiles btiles(const fcd_batch* b) {
     t.nctiles = b->L.nctiles[b->shape];
     t.tiles = reinterpret_cast<const int*>(b->scratch + b->L.off_tiles[b->shape]);
     t.ctiles = reinterpret_cast<const int*>(b->scratch + b->L.off_ctiles[b->shape]);
+    t.fused = b->fused;
+    t.nstiles = b->L.nstiles;
+    t.stiles = reinterpret_cast<const int*>(b->scratch + b->L.off_stiles);
     return t;
 }
 
@@ -882,6 +901,7 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
     I.dist[1] = bptr<T>(b->state, b->L.off_d1[k]);
     I.phi = bptr<T>(b->aux, b->L.off_phi[k]);
     I.prev = bptr<T>(b->aux, b->L.off_prev[k]);
+    I.alt = bptr<T>(b->aux, b->L.off_alt[k]);
     I.L0.u = bptr<T>(b->aux, b->L.off_psi[k]);
     I.L0.mu = I.phi + 2 * (long long)I.P.plane;
     I.L0.f = nullptr;
@@ -901,13 +921,15 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
         I.ctile0[s] = b->L.ctile0[s][k];
         I.ctiles_x[s] = b->L.ctiles_x[s][k];
     }
+    I.stile0 = b->L.stile0[k];
+    I.stiles_x = b->L.stiles_x[k];
     return I;
 }
 
 template <typename T>
 fcd_status batch_upload(fcd_batch* b) {
     std::vector<fcd::BatchInst<T>> inst(b->n);
-    std::vector<int> tiles[fcd::BATCH_SHAPES], ctiles[fcd::BATCH_SHAPES];
+    std::vector<int> tiles[fcd::BATCH_SHAPES], ctiles[fcd::BATCH_SHAPES], stiles(b->L.nstiles);
     for (int s = 0; s < fcd::BATCH_SHAPES; ++s) {
         tiles[s].resize(b->L.ntiles[s]);
         ctiles[s].resize(b->L.nctiles[s]);
@@ -923,6 +945,8 @@ fcd_status batch_upload(fcd_batch* b) {
             const int nc = ((l.nx + 1) / 2 + BT_X - 1) / BT_X * (((l.ny + 1) / 2 + ty - 1) / ty);
             for (int t = 0; t < nc; ++t) ctiles[s][I.ctile0[s] + t] = k;
         }
+        const int ns = I.stiles_x * ((l.ny + fcd::FUSED_Y - 1) / fcd::FUSED_Y);
+        for (int t = 0; t < ns; ++t) stiles[I.stile0 + t] = k;
     }
     fcd_status st = hip_check(hipMemcpy(b->scratch + b->L.off_inst, inst.data(), inst.size() * sizeof(inst[0]),
                                         hipMemcpyHostToDevice), "descriptor upload");
@@ -933,6 +957,9 @@ fcd_status batch_upload(fcd_batch* b) {
             st = hip_check(hipMemcpy(b->scratch + b->L.off_ctiles[s], ctiles[s].data(),
                                      ctiles[s].size() * sizeof(int), hipMemcpyHostToDevice), "tile table upload");
     }
+    if (!st)
+        st = hip_check(hipMemcpy(b->scratch + b->L.off_stiles, stiles.data(), stiles.size() * sizeof(int),
+                                 hipMemcpyHostToDevice), "tile table upload");
     if (st) return st;
     // residual slots start (and are always left) at zero
     return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 2 * (size_t)b->n * sizeof(unsigned long long)),
@@ -946,6 +973,12 @@ const fcd::BatchInst<T>* binst(const fcd_batch* b) {
 
 int check_interval(const fcd_batch* b) { return std::max(1, b->prm[0].pot_check_every); }
 
+// f sweeps per fused launch need a test interval that is a multiple of 2 f (f = 0: one
+// launch per colour, always allowed).
+bool fused_allowed(const fcd_batch* b, int f) {
+    return f == 0 || (f >= 1 && f <= fcd::FUSED_MAX && check_interval(b) % (2 * f) == 0);
+}
+
 // The problem a batched potential solve works on: the descriptors (u, f, mu, thresholds)
 // and, for relative thresholds, per-channel scales on the device.
 template <typename T>
@@ -954,25 +987,40 @@ struct BatchProblem {
     const unsigned long long* scale;  // nullptr: absolute thresholds of the descriptors
     double rel_tol;
     int* last_iters;                  // sweeps the previous solve of this problem needed
+    bool rhs_plane;                   // the descriptors carry a right-hand-side plane
 };
 
 template <typename T>
 BatchProblem<T> forward_problem(fcd_batch* b) {
-    return {binst<T>(b), nullptr, 0.0, &b->last_iters};
+    return {binst<T>(b), nullptr, 0.0, &b->last_iters, false};
 }
 
 // A block of `block_sweeps` SOR sweeps with a device-side convergence test after every
-// `check` sweeps (block_sweeps is a multiple of check).
+// `check` sweeps (block_sweeps is a multiple of check).  Fused launches alternate the
+// potential between its plane and the second plane; check is a multiple of twice the
+// sweeps per fused launch, so the potential is back in its own plane at every test.
 template <typename T>
 void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
     const fcd::BatchTiles t = btiles(b);
     int* active = bptr<int>(b->scratch, b->L.off_active);
     const int check = check_interval(b);
-    for (int s = 1; s <= b->block_sweeps; ++s) {
-        fcd::launch_batch_sweep<T>(P.inst, t, active, b->stream);
-        if (s % check == 0)
-            fcd::launch_batch_check<T>(P.inst, t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res), active,
-                                       bptr<int>(b->scratch, b->L.off_counts), P.scale, P.rel_tol, b->stream);
+    unsigned long long* res = bptr<unsigned long long>(b->scratch, b->L.off_res);
+    int* counts = bptr<int>(b->scratch, b->L.off_counts);
+    const int per = t.fused > 0 ? t.fused : 1;
+    int parity = 0;
+    for (int s = per; s <= b->block_sweeps; s += per) {
+        const bool test = s % check == 0;
+        if (t.fused > 0) {
+            // the launch before a test also reduces the residual of its result
+            fcd::launch_batch_sweep_fused<T>(P.inst, t, active, parity, P.rhs_plane, test ? res : nullptr,
+                                             b->stream);
+            parity ^= 1;
+            if (test) fcd::launch_batch_decide<T>(P.inst, b->n, res, active, counts, P.scale, P.rel_tol, b->stream);
+        } else {
+            fcd::launch_batch_sweep<T>(P.inst, t, active, b->stream);
+            if (test)
+                fcd::launch_batch_check<T>(P.inst, t, b->n, res, active, counts, P.scale, P.rel_tol, b->stream);
+        }
     }
 }
 
@@ -1013,7 +1061,7 @@ fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
     }
     while (left > 0) {
         if (it >= max_iters) break;
-        st = run_graph_on(b->graphs, b->stream, false, P.inst, nullptr, 1000 * b->shape + G,
+        st = run_graph_on(b->graphs, b->stream, false, P.inst, nullptr, ((b->fused * 8 + b->shape) << 24) + G,
                           [&]() { batch_block<T>(b, P); });
         if (st) return st;
         it += G;
@@ -1062,12 +1110,15 @@ fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
     const int check = check_interval(b);
     const int blocks[3] = {2 * check, 8 * check, 32 * check};
     double best = 1e300;
-    int best_shape = b->shape, best_block = b->block_sweeps;
+    int best_shape = b->shape, best_block = b->block_sweeps, best_fused = b->fused;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     fcd_status st = hip_check(hipEventCreate(&e0), "event");
     if (!st) st = hip_check(hipEventCreate(&e1), "event");
-    for (int s = 0; s < fcd::BATCH_SHAPES && !st; ++s) {
+    for (int f = 0; f <= fcd::FUSED_MAX && !st; ++f) {
+      if (!fused_allowed(b, f)) continue;
+      for (int s = 0; s < fcd::BATCH_SHAPES && !st; ++s) {
         for (int g = 0; g < 3 && !st; ++g) {
+            b->fused = f;
             b->shape = s;
             b->block_sweeps = blocks[g];
             if (g == 0) st = batch_step_impl<T>(b, 1);  // warms the shape's kernels and graphs
@@ -1081,15 +1132,19 @@ fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
                 best = ms;
                 best_shape = s;
                 best_block = blocks[g];
+                best_fused = f;
             }
         }
+      }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     b->shape = best_shape;
     b->block_sweeps = best_block;
+    b->fused = best_fused;
     choice[0] = BT_ROWS[best_shape];
     choice[1] = best_block;
+    choice[2] = best_fused;
     return st;
 }
 
@@ -1571,7 +1626,7 @@ fcd_status batch_adj_backward_impl(fcd_batch* b, const double* dJ, double* grad)
     int Aidx = 0, lhist = 0;
     b->adj_solve_iters = 0;
     const fcd_params& p0 = b->prm[0];
-    const BatchProblem<T> adjP{ainst, scale, p0.pot_tol, &b->adj_solve_iters};
+    const BatchProblem<T> adjP{ainst, scale, p0.pot_tol, &b->adj_solve_iters, true};
     for (int seg = A.nseg - 1; seg >= 0 && !st; --seg) {
         const int t0 = seg * every, t1 = std::min(nsteps, t0 + every);
         st = batch_load_records(b, A, A.off_ckpt, seg);
@@ -1894,6 +1949,9 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     b->adj_nsteps = b->adj_every = b->adj_from_init = 0;
     b->adj_final_iters = b->adj_final_hist = b->adj_solve_iters = 0;
     b->block_sweeps = 8 * std::max(1, prms[0].pot_check_every);
+    b->fused = 0;
+    for (int f = fcd::FUSED_MAX; f >= 1 && b->fused == 0; --f)
+        if (fused_allowed(b, f)) b->fused = f;
     if (hipHostMalloc(reinterpret_cast<void**>(&b->host), (1 + 4 * (size_t)n) * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         delete b;
@@ -1940,21 +1998,25 @@ fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double
     return FCD_BDISPATCH(b, batch_moments_impl)(b, k, mask, out);
 }
 
-fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[2]) {
+fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[3]) {
     if (!b || !choice) return fail(FCD_ERR_ARG, "null argument");
     if (steps_per_candidate < 1) return fail(FCD_ERR_ARG, "steps_per_candidate must be >= 1");
     return FCD_BDISPATCH(b, batch_autotune_impl)(b, steps_per_candidate, choice);
 }
 
-fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps) {
+fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps, int32_t fused_sweeps) {
     if (!b) return fail(FCD_ERR_ARG, "batch is null");
     int s = -1;
     for (int k = 0; k < fcd::BATCH_SHAPES; ++k)
         if (BT_ROWS[k] == tile_rows) s = k;
     if (s < 0) return fail(FCD_ERR_ARG, "tile_rows must be 1, 2, 4 or 8");
-    if (block_sweeps < 1 || block_sweeps % check_interval(b)) return fail(FCD_ERR_ARG, "block_sweeps must be a positive multiple of pot_check_every");
+    if (block_sweeps < 1 || block_sweeps > (1 << 20) || block_sweeps % check_interval(b))
+        return fail(FCD_ERR_ARG, "block_sweeps must be a positive multiple of pot_check_every, at most 2^20");
+    if (!fused_allowed(b, fused_sweeps))
+        return fail(FCD_ERR_ARG, "fused_sweeps must be 0, or 1 or 2 with pot_check_every a multiple of 2 fused_sweeps");
     b->shape = s;
     b->block_sweeps = block_sweeps;
+    b->fused = fused_sweeps;
     return FCD_OK;
 }
 

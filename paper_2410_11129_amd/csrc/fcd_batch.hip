@@ -66,6 +66,133 @@ __global__ void __launch_bounds__(TBX* TY) kb_sor_colour(const BatchInst<T>* __r
     relax_node(B.L0, i, j, B.omega);
 }
 
+// Fused sweeps: NS four-colour SOR sweeps of one 64 x 16 tile in one launch.  The tile
+// and a halo of H = 4 NS + 1 nodes are staged in LDS (columns wrapped, rows clamped to
+// the channel).  Colour phase p = 0 .. 4 NS - 1 (colour p mod 4) updates the nodes of
+// its colour that lie within 4 NS - p nodes of the tile, so every value a phase reads
+// has already received all earlier phases' updates, and the tile and its first halo ring
+// end holding exactly what NS sweeps with one launch per colour produce (same per-node
+// arithmetic).  The halo work is repeated by the neighbouring tiles that own it.  Input
+// and output are separate planes, since a tile's halo is other tiles' output.  With res
+// set, the launch also reduces the tile's residual and |C psi'| max-norms into the
+// channel's slots, as the separate residual pass does.
+__device__ __forceinline__ int fs_wrap(int i, int nx) {
+    while (i < 0) i += nx;
+    while (i >= nx) i -= nx;
+    return i;
+}
+
+template <typename T, bool HF>
+__device__ __forceinline__ MgEval<T> fs_eval(const PotLevel<T>& L, const T* su, const T* sm, const T* sf, int hx,
+                                             int lx, int ly, int j) {
+    // rows beyond the walls read the edge row itself, as the clamped global loads do
+    const int c = ly * hx + lx;
+    const int s = j == 0 ? c : c - hx, n = j == L.ny - 1 ? c : c + hx;
+    Nb9<T> m, u;
+    m.c = sm[c];
+    m.e = sm[c + 1];
+    m.w = sm[c - 1];
+    m.n = sm[n];
+    m.s = sm[s];
+    m.ne = sm[n + 1];
+    m.nw = sm[n - 1];
+    m.sw = sm[s - 1];
+    m.se = sm[s + 1];
+    u.c = su[c];
+    u.e = su[c + 1];
+    u.w = su[c - 1];
+    u.n = su[n];
+    u.s = su[s];
+    u.ne = su[n + 1];
+    u.nw = su[n - 1];
+    u.sw = su[s - 1];
+    u.se = su[s + 1];
+    return mg_eval_nb(L, m, u, j, HF ? sf[c] : T(0));
+}
+
+template <typename T, int NS, bool HF>
+__global__ void __launch_bounds__(256) kb_sor_fused(const BatchInst<T>* __restrict__ inst,
+                                                    const int* __restrict__ stile_inst,
+                                                    const int* __restrict__ active, int parity,
+                                                    unsigned long long* __restrict__ res) {
+    constexpr int H = 4 * NS + 1, HX = FUSED_X + 2 * H, HY = FUSED_Y + 2 * H, HN = HX * HY, NT = 256;
+    __shared__ T su[HN];
+    __shared__ T sm[HN];
+    __shared__ T sf[HF ? HN : 1];
+    __shared__ double wmax[2][NT / 64];
+    const int k = stile_inst[blockIdx.x];
+    if (!active[k]) return;  // uniform over the block
+    const BatchInst<T>& B = inst[k];
+    const PotLevel<T> L = B.L0;
+    const T* __restrict__ uin = parity ? B.alt : L.u;
+    T* __restrict__ uout = parity ? L.u : B.alt;
+    const int lt = blockIdx.x - B.stile0, ty = lt / B.stiles_x, tx = lt - ty * B.stiles_x;
+    const int i0 = tx * FUSED_X, j0 = ty * FUSED_Y;
+    for (int q = threadIdx.x; q < HN; q += NT) {
+        const int ly = q / HX, lx = q - ly * HX;
+        const int i = fs_wrap(i0 - H + lx, L.nx);
+        int j = j0 - H + ly;
+        j = j < 0 ? 0 : (j >= L.ny ? L.ny - 1 : j);
+        const long long g = (long long)j * L.pitch + i;
+        su[q] = uin[g];
+        sm[q] = L.mu[g];
+        if (HF) sf[HF ? q : 0] = L.f[g];
+    }
+    __syncthreads();
+    const T omega = B.omega;
+    // threads as 32 columns x 8 rows of same-colour nodes
+    const int tcx = threadIdx.x & 31, tcy = threadIdx.x >> 5;
+    for (int p = 0; p < 4 * NS; ++p) {
+        // colour (cx, cy) of global parity; local column lx has the parity of lx + H
+        // (i0 and j0 are even).  Nodes with lx in [H - R, H + 64 + R), ly likewise.
+        const int R = 4 * NS - p;
+        const int px = ((p & 1) + H) & 1, py = (((p >> 1) & 1) + H) & 1;
+        const int a0 = (H - R - px + 1) >> 1, na = ((H + FUSED_X + R - px + 1) >> 1) - a0;
+        const int b0 = (H - R - py + 1) >> 1, nb = ((H + FUSED_Y + R - py + 1) >> 1) - b0;
+        for (int bq = tcy; bq < nb; bq += 8) {
+            const int ly = 2 * (b0 + bq) + py;
+            const int j = j0 - H + ly;
+            if (j < 0 || j >= L.ny) continue;
+            for (int aq = tcx; aq < na; aq += 32) {
+                const int lx = 2 * (a0 + aq) + px;
+                const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, HX, lx, ly, j);
+                su[ly * HX + lx] = sor_value(r, su[ly * HX + lx], omega);
+            }
+        }
+        __syncthreads();
+    }
+    double v = 0.0, sc = 0.0;
+    for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += NT) {
+        const int ly = q / FUSED_X, lx = q - ly * FUSED_X;
+        const int i = i0 + lx, j = j0 + ly;
+        if (i < L.nx && j < L.ny) {
+            const int c = (H + ly) * HX + H + lx;
+            uout[(long long)j * L.pitch + i] = su[c];
+            if (res && B.has_field) {
+                const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, HX, H + lx, H + ly, j);
+                v = nan_max(v, fabs((double)(r.acc - r.C * su[c] - r.rhs)));
+                sc = nan_max(sc, fabs((double)(r.C * su[c])));
+            }
+        }
+    }
+    if (!res) return;  // uniform
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        v = nan_max(v, __shfl_xor(v, off, 64));
+        sc = nan_max(sc, __shfl_xor(sc, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wmax[0][threadIdx.x >> 6] = v;
+        wmax[1][threadIdx.x >> 6] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double mx = wmax[threadIdx.x][0];
+        for (int w = 1; w < NT / 64; ++w) mx = nan_max(mx, wmax[threadIdx.x][w]);
+        atomicMax(res + 2 * k + threadIdx.x, (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
 // Per-channel max-norms of the potential residual (res[2k]) and of C psi' (res[2k+1])
 // of the channels still active: block max, one atomicMax per block and quantity.
 template <typename T, int TY>
@@ -206,12 +333,32 @@ void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int
 }
 
 template <typename T>
+void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, const int* active, int parity,
+                              bool rhs_plane, unsigned long long* res, hipStream_t s) {
+#define C_(NS, HF)                                                                                                 \
+    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF>), dim3(t.nstiles), dim3(256), 0, s, inst, t.stiles, active, parity, \
+                       res)
+    if (t.fused == 1) {
+        if (rhs_plane) C_(1, true); else C_(1, false);
+    } else {
+        if (rhs_plane) C_(2, true); else C_(2, false);
+    }
+#undef C_
+}
+
+template <typename T>
 void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
                         int* active, int* counts, const unsigned long long* scale, double rel_tol, hipStream_t s) {
 #define C_(TY) \
     hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
     FCD_SHAPE_SWITCH(t.shape, C_)
 #undef C_
+    launch_batch_decide<T>(inst, n, res, active, counts, scale, rel_tol, s);
+}
+
+template <typename T>
+void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, int* active, int* counts,
+                         const unsigned long long* scale, double rel_tol, hipStream_t s) {
     const double floor_factor = 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
     hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, n, floor_factor, active, counts, scale,
                        rel_tol);
@@ -236,6 +383,10 @@ void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStr
     template void launch_batch_phase<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);           \
     template void launch_batch_collide<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);         \
     template void launch_batch_sweep<T>(const BatchInst<T>*, const BatchTiles&, const int*, hipStream_t);    \
+    template void launch_batch_sweep_fused<T>(const BatchInst<T>*, const BatchTiles&, const int*, int, bool, \
+                                              unsigned long long*, hipStream_t);                             \
+    template void launch_batch_decide<T>(const BatchInst<T>*, int, unsigned long long*, int*, int*,          \
+                                         const unsigned long long*, double, hipStream_t);                    \
     template void launch_batch_check<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,    \
                                         int*, int*, const unsigned long long*, double, hipStream_t);         \
     template void launch_batch_psi_history<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);     \

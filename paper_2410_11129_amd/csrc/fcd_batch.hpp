@@ -18,13 +18,15 @@ struct BatchInst {
     T* dist[2];       // the two state buffers (27 planes each)
     T* phi;           // phi1, phi2, mu_r planes
     T* prev;          // psi' history plane
+    T* alt;           // second potential plane of the fused sweeps (input and output alternate)
     T omega;          // SOR factor
     double thr;       // stop when max |residual| <= thr (= tol * H0)
     // per tile shape: first tile in the full-resolution and half-resolution (colour)
     // lists, and tiles per row
     int tile0[BATCH_SHAPES], tiles_x[BATCH_SHAPES];
     int ctile0[BATCH_SHAPES], ctiles_x[BATCH_SHAPES];
-    int has_field;  // H0 != 0
+    int stile0, stiles_x;  // first tile and tiles per row in the fused-sweep (64 x 16) list
+    int has_field;         // H0 != 0
     int pad;
 };
 
@@ -39,13 +41,20 @@ struct BatchAdj {
     int tile_first, tile_count;  // the channel's tiles in the 64 x 4 list
 };
 
-// The tile lists of one shape (device tables: tile -> channel).
+// The tile lists of one shape (device tables: tile -> channel), and the 64 x 16 list of
+// the fused sweeps with their sweeps per launch (0: one launch per colour instead).
 struct BatchTiles {
     int shape;
     int ntiles, nctiles;
     const int* tiles;
     const int* ctiles;
+    int fused;
+    int nstiles;
+    const int* stiles;
 };
+
+// Fused-sweep tile: 64 x 16 nodes plus a halo of 4 nodes per sweep.
+constexpr int FUSED_X = 64, FUSED_Y = 16, FUSED_MAX = 2;
 
 template <typename T>
 void launch_batch_phase(const BatchInst<T>* inst, const BatchTiles& t, int cur, hipStream_t s);
@@ -54,6 +63,18 @@ void launch_batch_collide(const BatchInst<T>* inst, const BatchTiles& t, int cur
 // One four-colour SOR sweep of the active channels.
 template <typename T>
 void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int* active, hipStream_t s);
+// t.fused four-colour SOR sweeps of the active channels in one launch, bitwise equal to
+// as many launch_batch_sweep calls; parity 0 reads L0.u and writes alt, parity 1 the
+// reverse.  rhs_plane: the descriptors' L0.f is set (else the field gives the rhs).
+// res != nullptr: also reduce the residual of the result as launch_batch_check does
+// (the decision kernel still has to follow).
+template <typename T>
+void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, const int* active, int parity,
+                              bool rhs_plane, unsigned long long* res, hipStream_t s);
+// The activity decision of launch_batch_check alone, on residual slots already filled.
+template <typename T>
+void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, int* active, int* counts,
+                         const unsigned long long* scale, double rel_tol, hipStream_t s);
 // Residual of the active channels, then the activity decision; res must be zero on entry
 // and is left zero; counts[0..1] = active channels, channels with a NaN residual.
 // scale != nullptr: channel k's threshold is rel_tol * scale[k] (bit pattern of a

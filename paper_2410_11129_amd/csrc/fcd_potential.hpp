@@ -18,11 +18,11 @@ struct MgEval {
     T rhs;    // right-hand side
 };
 
+// The operator at node row j from its mu and u neighbourhoods (rows beyond the walls
+// clamped to the edge rows, as nb_index gives them); fval is the right-hand side when
+// the level has an f plane.
 template <typename T>
-__device__ __forceinline__ MgEval<T> mg_eval(const PotLevel<T>& L, int i, int j) {
-    const NbIdx x = nb_index(i, j, L.nx, L.ny, L.pitch);
-    const Nb9<T> m = load_nb(L.mu, x);
-    Nb9<T> u = load_nb(static_cast<const T*>(L.u), x);  // rows clamped to the edge rows
+__device__ __forceinline__ MgEval<T> mg_eval_nb(const PotLevel<T>& L, const Nb9<T>& m, Nb9<T> u, int j, T fval) {
     const T k = L.kappa;
     if (j == 0) {
         u.s = -k * u.s;
@@ -42,7 +42,7 @@ __device__ __forceinline__ MgEval<T> mg_eval(const PotLevel<T>& L, int i, int j)
     r.acc = ((ce * u.e + cw * u.w) + (cn * u.n + cs * u.s)) + ((cne * u.ne + csw * u.sw) + (cnw * u.nw + cse * u.se));
     r.cself = (j == 0 ? k * cs : T(0)) + (j == L.ny - 1 ? k * cn : T(0));
     if (L.f) {
-        r.rhs = L.f[(long long)j * L.pitch + i];
+        r.rhs = fval;
     } else {
         const T sx = (ce - cw) + (cne - csw) + (cse - cnw);
         const T sy = (cn - cs) + (cne - csw) + (cnw - cse);
@@ -51,15 +51,28 @@ __device__ __forceinline__ MgEval<T> mg_eval(const PotLevel<T>& L, int i, int j)
     return r;
 }
 
-// One colour of a Gauss-Seidel / SOR sweep: u <- u + omega (u_GS - u), with the
-// node's own ghost image taken implicitly.
+template <typename T>
+__device__ __forceinline__ MgEval<T> mg_eval(const PotLevel<T>& L, int i, int j) {
+    const NbIdx x = nb_index(i, j, L.nx, L.ny, L.pitch);
+    const Nb9<T> m = load_nb(L.mu, x);
+    const Nb9<T> u = load_nb(static_cast<const T*>(L.u), x);  // rows clamped to the edge rows
+    return mg_eval_nb(L, m, u, j, L.f ? L.f[x.c] : T(0));
+}
+
+// Gauss-Seidel / SOR value of a node: u + omega (u_GS - u), with the node's own ghost
+// image taken implicitly.
+template <typename T>
+__device__ __forceinline__ T sor_value(const MgEval<T>& r, T old, T omega) {
+    const T gs = (r.acc + r.cself * old - r.rhs) / (r.C + r.cself);
+    return old + omega * (gs - old);
+}
+
+// One node of one colour of a Gauss-Seidel / SOR sweep.
 template <typename T>
 __device__ __forceinline__ void relax_node(const PotLevel<T>& L, int i, int j, T omega) {
     const MgEval<T> r = mg_eval(L, i, j);
     const long long k = (long long)j * L.pitch + i;
-    const T old = L.u[k];
-    const T gs = (r.acc + r.cself * old - r.rhs) / (r.C + r.cself);
-    L.u[k] = old + omega * (gs - old);
+    L.u[k] = sor_value(r, L.u[k], omega);
 }
 
 __device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }

@@ -109,7 +109,7 @@ def lib():
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
         L.fcd_batch_init_compound_droplet.argtypes = [H, dp]
         L.fcd_batch_step.argtypes = [H, C.c_int32]
-        L.fcd_batch_set_schedule.argtypes = [H, C.c_int32, C.c_int32]
+        L.fcd_batch_set_schedule.argtypes = [H, C.c_int32, C.c_int32, C.c_int32]
         L.fcd_batch_adjoint_bytes.argtypes = [H, C.c_int32, C.c_int32]
         L.fcd_batch_adjoint_bytes.restype = C.c_size_t
         L.fcd_batch_adjoint_forward.argtypes = [H, C.c_int32, C.c_int32, C.c_void_p, dp]
@@ -295,14 +295,14 @@ def fcd_adjoint_backward(h, dJ_dD):
     return list(out)
 
 
-def fcd_batch_set_schedule(b, tile_rows: int, block_sweeps: int):
-    _check(lib().fcd_batch_set_schedule(b, tile_rows, block_sweeps), "fcd_batch_set_schedule")
+def fcd_batch_set_schedule(b, tile_rows: int, block_sweeps: int, fused_sweeps: int):
+    _check(lib().fcd_batch_set_schedule(b, tile_rows, block_sweeps, fused_sweeps), "fcd_batch_set_schedule")
 
 
 def fcd_batch_autotune(b, steps_per_candidate: int):
-    out = (C.c_int32 * 2)()
+    out = (C.c_int32 * 3)()
     _check(lib().fcd_batch_autotune(b, steps_per_candidate, out), "fcd_batch_autotune")
-    return int(out[0]), int(out[1])
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def fcd_batch_adjoint_bytes(b, nsteps: int, ckpt_every: int) -> int:

@@ -176,11 +176,12 @@ class Batch:
     def step(self, n: int):
         fcd.fcd_batch_step(self.h, n)
 
-    def set_schedule(self, tile_rows: int, block_sweeps: int):
-        fcd.fcd_batch_set_schedule(self.h, tile_rows, block_sweeps)
+    def set_schedule(self, tile_rows: int, block_sweeps: int, fused_sweeps: int):
+        fcd.fcd_batch_set_schedule(self.h, tile_rows, block_sweeps, fused_sweeps)
 
     def autotune(self, steps_per_candidate: int = 2):
-        """Pick the launch schedule by timing real steps; returns (tile_rows, block_sweeps)."""
+        """Pick the launch schedule by timing real steps; returns
+        (tile_rows, block_sweeps, fused_sweeps)."""
         return fcd.fcd_batch_autotune(self.h, steps_per_candidate)
 
     def deformation(self):

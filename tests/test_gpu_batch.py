@@ -31,7 +31,10 @@ def uneven_channels():
                  drive_G=channel_drive(0.01, 1.0, 0.25, 16), xc=20.0, yc=7.5, r_core=3.0, r_shell=6.0)
     c = single_channel_small().replace(name="c", nx=130, ny=41, xc=60.0, yc=20.0, r_core=5.0, r_shell=11.0,
                                        alpha=1.1, drive_G=channel_drive(0.01, 1.0, 0.8, 41))
-    return [a, b, c]
+    # narrower than a fused-sweep tile with its halo: the halo wraps onto the tile itself
+    d = single_channel_small().replace(name="d", nx=48, ny=19, xc=20.0, yc=9.0, r_core=2.5, r_shell=5.5,
+                                       alpha=0.4, drive_G=channel_drive(0.01, 1.0, 0.8, 19))
+    return [a, b, c, d]
 
 
 def test_batch_channels_match_oracle_fp64():
@@ -116,8 +119,8 @@ def test_batch_deterministic_and_single_channel_batch():
 
 @pytest.mark.parametrize("precision", [fcd.FCD_FP64, fcd.FCD_FP32])
 def test_batch_schedules_and_autotuner_do_not_change_results(precision):
-    """Tile shapes and graph block sizes change launch geometry only: every schedule, and
-    the autotuner's trial steps, give the same states bit for bit."""
+    """Tile shapes, graph block sizes and fused sweeps change launch geometry only: every
+    schedule, and the autotuner's trial steps, give the same states bit for bit."""
     ws = uneven_channels()
     say(f"case batch schedules precision {precision}")
     tol = 1e-12 if precision == fcd.FCD_FP64 else 1e-5
@@ -125,20 +128,20 @@ def test_batch_schedules_and_autotuner_do_not_change_results(precision):
     ref.init_droplets()
     ref.step(6)
     want = [ref.state(k) for k in range(len(ws))]
-    for rows, block in ((1, 4), (8, 128), (2, 32)):
+    for rows, block, fused in ((1, 4, 0), (8, 128, 1), (2, 32, 2), (4, 8, 0)):
         bt = Batch(ws, precision=precision, tol=tol)
-        bt.set_schedule(rows, block)
+        bt.set_schedule(rows, block, fused)
         bt.init_droplets()
         for _ in range(3):  # several graph replays with eager work between them
             bt.step(2)
         for k in range(len(ws)):
-            assert np.array_equal(bt.state(k), want[k]), (rows, block, k)
+            assert np.array_equal(bt.state(k), want[k]), (rows, block, fused, k)
         bt.close()
     tuned = Batch(ws, precision=precision, tol=tol)
     tuned.init_droplets()
-    rows, block = tuned.autotune(1)  # advances 4 * (1 + 3) = 16 steps
-    assert rows in (1, 2, 4, 8) and block % 4 == 0
-    ref.step(10)
+    rows, block, fused = tuned.autotune(1)  # advances 3 * 4 * (1 + 3) = 48 steps
+    assert rows in (1, 2, 4, 8) and block % 4 == 0 and fused in (0, 1, 2)
+    ref.step(42)
     for k in range(len(ws)):
         assert np.array_equal(tuned.state(k), ref.state(k)), k
     tuned.close()
