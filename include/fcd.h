@@ -76,7 +76,8 @@ typedef struct {
                         at the working precision's rounding floor 16 eps max |C psi'| (C: sum
                         of the operator's coefficients at a node) if that is larger */
     double pot_omega; /* SOR over-relaxation in (0, 2); 0 selects 2 / (1 + sin(pi / (ny + 1))).
-                         Multigrid uses the default on its coarsest level only. */
+                         Multigrid: used when the hierarchy has one level (ny odd), else
+                         the default serves its coarsest level. */
     int32_t pot_solver;      /* FCD_SOLVER_SOR or FCD_SOLVER_MG */
     int32_t pot_check_every; /* SOR sweeps / multigrid V-cycles between residual tests */
     int32_t pot_max_iters;   /* SOR sweeps / V-cycles allowed per solve */
@@ -281,6 +282,16 @@ fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block
  * choice = {tile_rows, block_sweeps, fused_sweeps}.  Advances the batch by
  * 4 F (1 + 3 steps_per_candidate) steps, F the number of allowed fusions.  Sync. */
 fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[3]);
+
+/* SOR factor tuner: for each of the ncand (1..16) candidate scales s in scale[], every
+ * channel relaxes with 2 / (1 + s sin(pi / (ny + 1))) for `steps` real steps while the
+ * device counts the sweeps each channel receives; each channel then keeps (as its
+ * pot_omega) the factor with its smallest count, the earlier candidate on ties, written
+ * to omega_out[k] (host, n values).  The choice depends on the channels' states only,
+ * not on timing.  Advances the batch by ncand * steps steps (callers that want the
+ * tuned factors from the initial state initialise again).  Sync.  FCD_ERR_ARG for a
+ * scale outside (0, 10). */
+fcd_status fcd_batch_tune_omega(fcd_batch* b, int32_t steps, int32_t ncand, const double* scale, double* omega_out);
 
 /* Batched adjoint: the adjoint of fcd_adjoint_forward / _backward for every channel of
  * the batch at once (one launch per kernel for all channels, the adjoint potential

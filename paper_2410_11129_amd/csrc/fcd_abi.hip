@@ -426,7 +426,7 @@ int coarse_sweeps(const fcd_handle* h, int ny) { return std::max(1, h->prm.pot_c
 template <typename T>
 void coarse_solve(fcd_handle* h, int l, const fcd::PotLevel<T>& L0) {
     const fcd::PotLevel<T> L = l == 0 ? L0 : pot_level<T>(h, l);
-    const T om = T(sor_omega_opt(L.ny));
+    const T om = T(l == 0 && h->prm.pot_omega > 0.0 ? h->prm.pot_omega : sor_omega_opt(L.ny));
     for (int s = 0; s < coarse_sweeps(h, L.ny); ++s) fcd::launch_pot_sweep<T>(L, om, h->stream);
 }
 
@@ -747,7 +747,7 @@ struct BatchLayout {
     int ntiles[fcd::BATCH_SHAPES] = {}, nctiles[fcd::BATCH_SHAPES] = {}, nstiles = 0;
     size_t state_bytes = 0, aux_bytes = 0, scratch_bytes = 0;
     size_t off_inst = 0, off_tiles[fcd::BATCH_SHAPES] = {}, off_ctiles[fcd::BATCH_SHAPES] = {}, off_stiles = 0;
-    size_t off_res = 0, off_active = 0, off_counts = 0;
+    size_t off_res = 0, off_active = 0, off_counts = 0, off_sweeps = 0;
     size_t off_rows = 0, off_cent = 0, off_result = 0;
 };
 
@@ -817,6 +817,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     off = align256(off + (size_t)n * sizeof(int));
     L->off_counts = off;
     off = align256(off + 2 * sizeof(int));
+    L->off_sweeps = off;
+    off = align256(off + (size_t)n * sizeof(int));
     L->off_rows = off;
     off = align256(off + (size_t)max_ny * 8 * sizeof(double));
     L->off_cent = off;
@@ -926,6 +928,19 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
     return I;
 }
 
+// Re-uploads the channel descriptors after a parameter change (after the batch's queued
+// work, which reads them, has finished).
+template <typename T>
+fcd_status batch_upload_inst(fcd_batch* b) {
+    std::vector<fcd::BatchInst<T>> inst(b->n);
+    for (int k = 0; k < b->n; ++k) inst[k] = make_batch_inst<T>(b, k);
+    fcd_status st = hip_check(hipStreamSynchronize(b->stream), "batch sync");
+    if (!st)
+        st = hip_check(hipMemcpy(b->scratch + b->L.off_inst, inst.data(), inst.size() * sizeof(inst[0]),
+                                 hipMemcpyHostToDevice), "descriptor upload");
+    return st;
+}
+
 template <typename T>
 fcd_status batch_upload(fcd_batch* b) {
     std::vector<fcd::BatchInst<T>> inst(b->n);
@@ -1006,6 +1021,7 @@ void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
     const int check = check_interval(b);
     unsigned long long* res = bptr<unsigned long long>(b->scratch, b->L.off_res);
     int* counts = bptr<int>(b->scratch, b->L.off_counts);
+    int* sweeps = bptr<int>(b->scratch, b->L.off_sweeps);
     const int per = t.fused > 0 ? t.fused : 1;
     int parity = 0;
     for (int s = per; s <= b->block_sweeps; s += per) {
@@ -1015,11 +1031,14 @@ void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
             fcd::launch_batch_sweep_fused<T>(P.inst, t, active, parity, P.rhs_plane, test ? res : nullptr,
                                              b->stream);
             parity ^= 1;
-            if (test) fcd::launch_batch_decide<T>(P.inst, b->n, res, active, counts, P.scale, P.rel_tol, b->stream);
+            if (test)
+                fcd::launch_batch_decide<T>(P.inst, b->n, res, active, counts, P.scale, P.rel_tol, sweeps, check,
+                                            b->stream);
         } else {
             fcd::launch_batch_sweep<T>(P.inst, t, active, b->stream);
             if (test)
-                fcd::launch_batch_check<T>(P.inst, t, b->n, res, active, counts, P.scale, P.rel_tol, b->stream);
+                fcd::launch_batch_check<T>(P.inst, t, b->n, res, active, counts, P.scale, P.rel_tol, sweeps, check,
+                                           b->stream);
         }
     }
 }
@@ -1049,7 +1068,8 @@ fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
     int* active = bptr<int>(b->scratch, b->L.off_active);
     fcd::launch_fill<int>(active, b->n, 1, b->stream);
     fcd::launch_batch_check<T>(P.inst, t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res), active,
-                               bptr<int>(b->scratch, b->L.off_counts), P.scale, P.rel_tol, b->stream);
+                               bptr<int>(b->scratch, b->L.off_counts), P.scale, P.rel_tol,
+                               bptr<int>(b->scratch, b->L.off_sweeps), 0, b->stream);
     fcd_status st = hip_check(hipGetLastError(), "batch check launch");
     if (st) return st;
     int left = 1, it = 0;
@@ -1146,6 +1166,42 @@ fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
     choice[1] = best_block;
     choice[2] = best_fused;
     return st;
+}
+
+// SOR factor tuner: for each candidate scale s, every channel relaxes with
+// 2 / (1 + s sin(pi / (ny + 1))) for `steps` real steps while the decision kernel counts
+// the sweeps each channel receives; each channel keeps the factor of its smallest
+// count (the first candidate on ties).  The counts depend on the channels' states only,
+// so the choice is reproducible.
+template <typename T>
+fcd_status batch_tune_omega_impl(fcd_batch* b, int steps, int ncand, const double* scale, double* omega_out) {
+    std::vector<long long> best(b->n, -1);
+    std::vector<double> pick(b->n, 0.0);
+    std::vector<int> cnt(b->n);
+    int* sweeps = bptr<int>(b->scratch, b->L.off_sweeps);
+    fcd_status st = FCD_OK;
+    for (int c = 0; c < ncand && !st; ++c) {
+        for (int k = 0; k < b->n; ++k)
+            b->prm[k].pot_omega = 2.0 / (1.0 + scale[c] * std::sin(3.14159265358979323846 / (b->lat[k].ny + 1)));
+        st = batch_upload_inst<T>(b);
+        if (!st) st = hip_check(hipMemsetAsync(sweeps, 0, (size_t)b->n * sizeof(int), b->stream), "sweep counters");
+        if (!st) st = batch_step_impl<T>(b, steps);
+        if (!st)
+            st = hip_check(hipMemcpyAsync(cnt.data(), sweeps, (size_t)b->n * sizeof(int), hipMemcpyDeviceToHost,
+                                          b->stream), "sweep counters");
+        if (!st) st = hip_check(hipStreamSynchronize(b->stream), "sweep counters");
+        for (int k = 0; k < b->n && !st; ++k)
+            if (best[k] < 0 || cnt[k] < best[k]) {
+                best[k] = cnt[k];
+                pick[k] = b->prm[k].pot_omega;
+            }
+    }
+    if (st) return st;
+    for (int k = 0; k < b->n; ++k) {
+        b->prm[k].pot_omega = pick[k];
+        omega_out[k] = pick[k];
+    }
+    return batch_upload_inst<T>(b);
 }
 
 template <typename T>
@@ -2002,6 +2058,14 @@ fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t
     if (!b || !choice) return fail(FCD_ERR_ARG, "null argument");
     if (steps_per_candidate < 1) return fail(FCD_ERR_ARG, "steps_per_candidate must be >= 1");
     return FCD_BDISPATCH(b, batch_autotune_impl)(b, steps_per_candidate, choice);
+}
+
+fcd_status fcd_batch_tune_omega(fcd_batch* b, int32_t steps, int32_t ncand, const double* scale, double* omega_out) {
+    if (!b || !scale || !omega_out) return fail(FCD_ERR_ARG, "null argument");
+    if (steps < 1 || ncand < 1 || ncand > 16) return fail(FCD_ERR_ARG, "need steps >= 1 and 1 <= ncand <= 16");
+    for (int c = 0; c < ncand; ++c)
+        if (!(scale[c] > 0.0 && scale[c] < 10.0)) return fail(FCD_ERR_ARG, "candidate scales must lie in (0, 10)");
+    return FCD_BDISPATCH(b, batch_tune_omega_impl)(b, steps, ncand, scale, omega_out);
 }
 
 fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps, int32_t fused_sweeps) {

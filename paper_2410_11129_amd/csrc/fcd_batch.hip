@@ -233,7 +233,8 @@ __global__ void __launch_bounds__(TBX* TY) kb_residual(const BatchInst<T>* __res
 // One block: a channel stays active while its residual is above max(thr, floor * scale)
 // (an inactive channel stays inactive for the rest of the solve); the residual slots are
 // cleared for the next test; counts[0] = channels still active, counts[1] = channels
-// whose residual is NaN.
+// whose residual is NaN; sweeps[k] grows by `add` (the sweeps since the previous test)
+// for every channel active on entry.
 constexpr int DECIDE_T = 256;
 
 template <typename T>
@@ -241,11 +242,13 @@ __global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __rest
                                                       unsigned long long* __restrict__ res, int n,
                                                       double floor_factor, int* __restrict__ active,
                                                       int* __restrict__ counts,
-                                                      const unsigned long long* __restrict__ scale, double rel_tol) {
+                                                      const unsigned long long* __restrict__ scale, double rel_tol,
+                                                      int* __restrict__ sweeps, int add) {
     __shared__ int cnt[2][DECIDE_T / 64];
     int a_sum = 0, nan_sum = 0;
     for (int k = threadIdx.x; k < n; k += DECIDE_T) {
         if (!active[k]) continue;
+        sweeps[k] += add;
         const double r = __longlong_as_double((long long)res[2 * k]);
         const double sc = __longlong_as_double((long long)res[2 * k + 1]);
         const double thr = scale ? rel_tol * __longlong_as_double((long long)scale[k]) : inst[k].thr;
@@ -348,20 +351,21 @@ void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, con
 
 template <typename T>
 void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
-                        int* active, int* counts, const unsigned long long* scale, double rel_tol, hipStream_t s) {
+                        int* active, int* counts, const unsigned long long* scale, double rel_tol, int* sweeps,
+                        int add, hipStream_t s) {
 #define C_(TY) \
     hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
     FCD_SHAPE_SWITCH(t.shape, C_)
 #undef C_
-    launch_batch_decide<T>(inst, n, res, active, counts, scale, rel_tol, s);
+    launch_batch_decide<T>(inst, n, res, active, counts, scale, rel_tol, sweeps, add, s);
 }
 
 template <typename T>
 void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, int* active, int* counts,
-                         const unsigned long long* scale, double rel_tol, hipStream_t s) {
+                         const unsigned long long* scale, double rel_tol, int* sweeps, int add, hipStream_t s) {
     const double floor_factor = 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
     hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, n, floor_factor, active, counts, scale,
-                       rel_tol);
+                       rel_tol, sweeps, add);
 }
 
 template <typename T>
@@ -386,9 +390,10 @@ void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStr
     template void launch_batch_sweep_fused<T>(const BatchInst<T>*, const BatchTiles&, const int*, int, bool, \
                                               unsigned long long*, hipStream_t);                             \
     template void launch_batch_decide<T>(const BatchInst<T>*, int, unsigned long long*, int*, int*,          \
-                                         const unsigned long long*, double, hipStream_t);                    \
+                                         const unsigned long long*, double, int*, int, hipStream_t);         \
     template void launch_batch_check<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,    \
-                                        int*, int*, const unsigned long long*, double, hipStream_t);         \
+                                        int*, int*, const unsigned long long*, double, int*, int,            \
+                                        hipStream_t);                                                        \
     template void launch_batch_psi_history<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);     \
     template void launch_batch_fill_psi<T>(const BatchInst<T>*, const BatchTiles&, hipStream_t);
 

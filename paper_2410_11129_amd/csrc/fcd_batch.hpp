@@ -74,14 +74,16 @@ void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, con
 // The activity decision of launch_batch_check alone, on residual slots already filled.
 template <typename T>
 void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, int* active, int* counts,
-                         const unsigned long long* scale, double rel_tol, hipStream_t s);
+                         const unsigned long long* scale, double rel_tol, int* sweeps, int add, hipStream_t s);
 // Residual of the active channels, then the activity decision; res must be zero on entry
 // and is left zero; counts[0..1] = active channels, channels with a NaN residual.
 // scale != nullptr: channel k's threshold is rel_tol * scale[k] (bit pattern of a
-// non-negative double) instead of its descriptor's thr.
+// non-negative double) instead of its descriptor's thr.  sweeps[k] += add for every
+// channel active on entry (add: sweeps since the previous test).
 template <typename T>
 void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
-                        int* active, int* counts, const unsigned long long* scale, double rel_tol, hipStream_t s);
+                        int* active, int* counts, const unsigned long long* scale, double rel_tol, int* sweeps,
+                        int add, hipStream_t s);
 template <typename T>
 void launch_batch_psi_history(const BatchInst<T>* inst, const BatchTiles& t, int mode, hipStream_t s);
 template <typename T>

@@ -31,7 +31,7 @@ EXPORTS = (
     "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
     "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
-    "fcd_batch_read_moments", "fcd_batch_set_schedule", "fcd_batch_autotune", "fcd_batch_adjoint_bytes",
+    "fcd_batch_read_moments", "fcd_batch_set_schedule", "fcd_batch_autotune", "fcd_batch_tune_omega", "fcd_batch_adjoint_bytes",
     "fcd_batch_adjoint_forward", "fcd_batch_adjoint_backward", "fcd_batch_stats",
     "fcd_batch_destroy",
 )
@@ -115,6 +115,7 @@ def lib():
         L.fcd_batch_adjoint_forward.argtypes = [H, C.c_int32, C.c_int32, C.c_void_p, dp]
         L.fcd_batch_adjoint_backward.argtypes = [H, dp, dp]
         L.fcd_batch_autotune.argtypes = [H, C.c_int32, C.POINTER(C.c_int32)]
+        L.fcd_batch_tune_omega.argtypes = [H, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.fcd_batch_deformation.argtypes = [H, dp]
         L.fcd_batch_read_state.argtypes = [H, C.c_int32, C.c_void_p]
         L.fcd_batch_read_moments.argtypes = [H, C.c_int32, C.c_uint32, C.c_void_p]
@@ -303,6 +304,13 @@ def fcd_batch_autotune(b, steps_per_candidate: int):
     out = (C.c_int32 * 3)()
     _check(lib().fcd_batch_autotune(b, steps_per_candidate, out), "fcd_batch_autotune")
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def fcd_batch_tune_omega(b, n: int, steps: int, scales):
+    sc = (C.c_double * len(scales))(*scales)
+    out = (C.c_double * n)()
+    _check(lib().fcd_batch_tune_omega(b, steps, len(scales), sc, out), "fcd_batch_tune_omega")
+    return list(out)
 
 
 def fcd_batch_adjoint_bytes(b, nsteps: int, ckpt_every: int) -> int:

@@ -184,6 +184,12 @@ class Batch:
         (tile_rows, block_sweeps, fused_sweeps)."""
         return fcd.fcd_batch_autotune(self.h, steps_per_candidate)
 
+    def tune_omega(self, steps: int = 4, scales=(1.25, 1.0, 0.9, 0.775)):
+        """Per-channel SOR factors 2 / (1 + s sin(pi / (ny + 1))), s from `scales`, chosen by
+        the fewest sweeps over `steps` steps per candidate (advances the batch); returns
+        the factors."""
+        return fcd.fcd_batch_tune_omega(self.h, self.n, steps, list(scales))
+
     def deformation(self):
         return fcd.fcd_batch_deformation(self.h, self.n)
 

@@ -146,3 +146,29 @@ def test_batch_schedules_and_autotuner_do_not_change_results(precision):
         assert np.array_equal(tuned.state(k), ref.state(k)), k
     tuned.close()
     ref.close()
+
+
+def test_sor_factor_tuner_is_reproducible():
+    """The per-channel SOR factor tuner picks from the candidates by sweep counts alone:
+    two identical batches pick the same factors, a channel without field (no sweeps)
+    keeps the first candidate, and the batch then runs and converges with them."""
+    import math
+    ws = uneven_channels()
+    scales = (1.25, 1.0, 0.775)
+    say("case batch SOR factor tuner")
+    picks = []
+    for _ in range(2):
+        bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
+        bt.init_droplets()
+        bt.step(3)
+        picks.append(bt.tune_omega(2, scales))
+        bt.init_droplets()
+        bt.step(4)
+        assert np.isfinite(np.asarray(bt.deformation())).all()
+        bt.close()
+    assert picks[0] == picks[1]
+    for w, om in zip(ws, picks[0]):
+        cands = [2.0 / (1.0 + s * math.sin(math.pi / (w.ny + 1))) for s in scales]
+        assert min(abs(om - c) for c in cands) < 1e-15, (w.name, om, cands)
+        if w.H0 == 0.0:
+            assert om == cands[0]
