@@ -460,6 +460,23 @@ T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, unsig
     return a;
 }
 
+// Coarse level l >= 1: the restriction from level l-1 (u = its pre-smoothed iterate
+// Fp.u, right-hand side by fmode) fused with the first of nu1 pre-smoothing sweeps from
+// a zero correction; returns the buffer holding the result.
+template <typename T>
+T* mg_restrict_presmooth(fcd_handle* h, const fcd::PotLevel<T>& Fp, int fmode, int l) {
+    const fcd::PotLevel<T> F = pot_level<T>(h, l);
+    T* a = F.u;
+    T* b = mg_temp<T>(h, l);
+    fcd::launch_mg_restrict_smooth<T>(Fp, F, fmode, b, MG_COARSE_INNER, h->stream);
+    std::swap(a, b);
+    for (int s = 1; s < std::max(1, h->prm.pot_smooth); ++s) {
+        fcd::launch_mg_smooth_tile<T>(F, a, b, nullptr, 0, nullptr, MG_COARSE_INNER, h->stream);
+        std::swap(a, b);
+    }
+    return a;
+}
+
 // Prolongation of level l+1's correction fused with the first of nu2 post-smoothing
 // sweeps, from the pre-smoothed iterate `cur`; the result ends in F.u.
 template <typename T>
@@ -487,11 +504,15 @@ void vcycle_rest(fcd_handle* h, const fcd::PotLevel<T>& L0, T* cur0) {
     const int gend = tail ? h->plan.tail : L - 1;  // levels [0, gend) are smoothed by tiles
     T* cur[MAX_LEVELS];
     cur[0] = cur0;
-    for (int l = 0; l < gend; ++l) {
-        fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
-        if (l > 0) cur[l] = mg_presmooth<T>(h, F, l, 0, nullptr);
-        F.u = cur[l];
-        fcd::launch_mg_restrict_tile<T>(F, pot_level<T>(h, l + 1), l == 0 ? fine_mode(L0) : 0, h->stream);
+    for (int l = 1; l < gend; ++l) {
+        fcd::PotLevel<T> Fp = l == 1 ? L0 : pot_level<T>(h, l - 1);
+        Fp.u = cur[l - 1];
+        cur[l] = mg_restrict_presmooth<T>(h, Fp, l == 1 ? fine_mode(L0) : 0, l);
+    }
+    {
+        fcd::PotLevel<T> F = gend == 1 ? L0 : pot_level<T>(h, gend - 1);
+        F.u = cur[gend - 1];
+        fcd::launch_mg_restrict_tile<T>(F, pot_level<T>(h, gend), gend == 1 ? fine_mode(L0) : 0, h->stream);
     }
     if (tail) {
         fcd::MgTail<T> tl{};

@@ -36,6 +36,12 @@ void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const Po
 // mode as for the tile smoother.
 template <typename T>
 void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mode, hipStream_t s);
+// The restriction from F fused with the first `inner`-sweep tile smoothing of the coarse
+// level C from a zero correction: C.f is written, the smoothed correction goes to uout
+// (C.u is neither read nor written); fmode is F's mode as for the tile smoother.
+template <typename T>
+void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<T>& C, int fmode, T* uout, int inner,
+                               hipStream_t s);
 template <typename T>
 size_t mg_tail_lds_bytes(const MgTail<T>& tl);
 template <typename T>

@@ -413,6 +413,105 @@ __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLe
     }
 }
 
+// Residual restriction fused with the first pre-smoothing of the coarse level below it.
+// One block owns a 32 x 8 coarse tile: it loads the matching 64 x 16 tile of the
+// smoothed fine iterate and of the fine mu with a one-node halo, forms the fine
+// residuals (FMODE: the fine level's right-hand side, as the smoother's MODE), writes
+// their four-child averages as the coarse right-hand side (to C.f and to LDS) and runs
+// `inner` tile sweeps from a zero correction (the whole coarse level starts at zero, so
+// the tile's halo is zero as well), writing the result to uout.  Same arithmetic as
+// k_mg_restrict_tile followed by k_mg_smooth_tile, one launch fewer.  Requires
+// F.nx = 2 C.nx and F.ny = 2 C.ny.
+template <typename T, int FMODE>
+__global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<T> C,
+                                                                     T* __restrict__ uout, int inner) {
+    // fine part on the fine tile's 256 threads (loads staged in registers, issued
+    // together); coarse smoothing by the first 64, one coarse node per colour each
+    using G = CoarseTile;
+    using FG = FineTile;
+    constexpr int NT = FG::NT, SX = G::SX, SY = G::SY, HX = G::HX;
+    constexpr int CPER = (G::HN + NT - 1) / NT;
+    __shared__ T fu[FG::HY][FG::HX];
+    __shared__ T fm[FG::HY][FG::HX];
+    __shared__ T su[G::HY][G::HX];
+    __shared__ T sm[G::HY][G::HX];
+    __shared__ T sf[SY][SX];
+    const int I0 = blockIdx.x * SX, J0 = blockIdx.y * SY;  // coarse tile origin
+    const int i0 = 2 * I0, j0 = 2 * J0;                    // fine tile origin
+    const int tid = threadIdx.x;
+    const int cy = tid / SX, cx = tid - cy * SX;  // this thread's coarse node
+    T uv[FG::HPER], mv[FG::HPER], fv[4], cm[CPER];
+    load_tile<T, FG>(F, F.u, i0, j0, uv, mv);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {  // fine right-hand sides of the node's four children
+        const int i = i0 + 2 * cx + (d & 1), j = j0 + 2 * cy + (d >> 1);
+        fv[d] = (FMODE != 1 && i < F.nx && j < F.ny) ? F.f[(long long)j * F.pitch + i] : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < CPER; ++r) {
+        const int q = tid + r * NT;
+        if (q < G::HN) {
+            const int ly = q / HX, lx = q - ly * HX;
+            cm[r] = C.mu[(long long)clamp_row(J0 + ly - 1, C.ny) * C.pitch + wrap_col(I0 + lx - 1, C.nx)];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < FG::HPER; ++r) {
+        const int q = tid + r * NT;
+        if (q < FG::HN) {
+            fu[q / FG::HX][q % FG::HX] = uv[r];
+            fm[q / FG::HX][q % FG::HX] = mv[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < CPER; ++r) {
+        const int q = tid + r * NT;
+        if (q < G::HN) {
+            sm[q / HX][q % HX] = cm[r];
+            su[q / HX][q % HX] = T(0);
+        }
+    }
+    __syncthreads();
+    // fine residuals of the 2 x 2 children of the thread's coarse node
+    {
+        T r[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const int lx = 2 * cx + (d & 1), ly = 2 * cy + (d >> 1);
+            const int i = i0 + lx, j = j0 + ly;
+            T v = T(0);
+            if (i < F.nx && j < F.ny) {
+                const MgEval<T> e =
+                    tile_eval<T, FG::HX>(fu, fm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F, fv[d], FMODE == 1);
+                v = e.rhs - (e.acc - e.C * fu[ly + 1][lx + 1]);
+            }
+            r[d] = v;
+        }
+        const T fc = T(0.25) * ((r[0] + r[1]) + (r[2] + r[3]));
+        sf[cy][cx] = fc;
+        const int I = I0 + cx, J = J0 + cy;
+        if (I < C.nx && J < C.ny) C.f[(long long)J * C.pitch + I] = fc;
+    }
+    __syncthreads();
+    const int tx = tid % (SX / 2), ty = tid / (SX / 2);
+    const bool smoother = tid < G::NT;
+    for (int sweep = 0; sweep < inner; ++sweep) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
+            const int i = I0 + lx - 1, j = J0 + ly - 1;
+            if (smoother && i < C.nx && j < C.ny) {
+                const MgEval<T> e =
+                    tile_eval<T, HX>(su, sm, lx, ly, j == 0, j == C.ny - 1, C, sf[ly - 1][lx - 1], false);
+                const T old = su[ly][lx];
+                su[ly][lx] = (e.acc + e.cself * old - e.rhs) / (e.C + e.cself);
+            }
+            __syncthreads();
+        }
+    }
+    if (I0 + cx < C.nx && J0 + cy < C.ny) uout[(long long)(J0 + cy) * C.pitch + I0 + cx] = su[cy + 1][cx + 1];
+}
+
 // ---------------------------------------------------------------------------------
 // Tail of the V-cycle: the coarsest levels, all in LDS, by one block.  Level 0 of the
 // tail takes its right-hand side from global memory (written by the restriction above
@@ -631,6 +730,18 @@ void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mod
 }
 
 template <typename T>
+void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<T>& C, int fmode, T* uout, int inner,
+                               hipStream_t s) {
+    const dim3 g((C.nx + CoarseTile::SX - 1) / CoarseTile::SX, (C.ny + CoarseTile::SY - 1) / CoarseTile::SY);
+    if (fmode == 0)
+        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 0>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
+    else if (fmode == 1)
+        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 1>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
+    else
+        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 2>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
+}
+
+template <typename T>
 size_t mg_tail_lds_bytes(const MgTail<T>& tl) {
     size_t n = 0;
     for (int k = 0; k < tl.n; ++k) n += 4 * (size_t)tl.lv[k].nx * tl.lv[k].ny;
@@ -655,6 +766,7 @@ void launch_psi_history(T* psi, T* prev, int nx, int ny, int pitch, int mode, hi
     template void launch_mg_smooth_tile<T>(const PotLevel<T>&, const T*, T*, const PotLevel<T>*, int,         \
                                            unsigned long long*, int, hipStream_t);                            \
     template void launch_mg_restrict_tile<T>(const PotLevel<T>&, const PotLevel<T>&, int, hipStream_t);       \
+    template void launch_mg_restrict_smooth<T>(const PotLevel<T>&, const PotLevel<T>&, int, T*, int, hipStream_t); \
     template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
     template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \
     template void launch_psi_history<T>(T*, T*, int, int, int, int, hipStream_t);
