@@ -109,7 +109,7 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     bt.close()
     del bt
     seq = 0.0
-    for w, om in zip(ws, omegas):
+    for w, om in zip(ws, omegas if seq_steps > 0 else []):
         ch = Channel(w, tol=1e-10, omega=om)
         ch.init_droplet()
         ch.step(5)
@@ -120,14 +120,14 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
         seq += (time.perf_counter() - t0) / seq_steps
         ch.close()
     batch_iph = len(ws) / (nsteps_target * dt_batch) * 3600.0
-    seq_iph = len(ws) / (nsteps_target * seq) * 3600.0
+    seq_iph = len(ws) / (nsteps_target * seq) * 3600.0 if seq_steps > 0 else None
     return {"channels": len(ws), "sites": sites, "steps_per_channel": nsteps_target,
             "batch_fp32_ms_per_step": round(dt_batch * 1e3, 4), "batch_MLUPS": round(sites / dt_batch / 1e6, 1),
             "batch_sor_sweeps_per_step": round(sweeps, 2),
             "schedule": {"tile_rows": rows, "block_sweeps": block, "fused_sweeps": fused},
             "instances_per_hour_batch_fp32": round(batch_iph, 1),
-            "instances_per_hour_sequential_fp64": round(seq_iph, 1),
-            "speedup": round(batch_iph / seq_iph, 2),
+            "instances_per_hour_sequential_fp64": round(seq_iph, 1) if seq_iph else None,
+            "speedup": round(batch_iph / seq_iph, 2) if seq_iph else None,
             "sample": f"batch: {steps} timed steps; sequential: {seq_steps} timed steps per channel"}
 
 
@@ -252,7 +252,7 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
-    ap.add_argument("--sequential-steps", type=int, default=20)
+    ap.add_argument("--sequential-steps", type=int, default=20)  # 0: no sequential comparator
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-ckpt", type=int, default=100)

@@ -282,3 +282,30 @@ def test_full_size_with_field_properties():
     for k in ("uy", "Hx", "psi"):
         a = m[k]
         assert np.abs(a + a[::-1]).max() <= 1e-6 * max(np.abs(a).max(), 1e-30), k
+
+
+def test_full_size_fp32_deformation_tracks_fp64():
+    """2048 x 512 at Bo_m = 2: the FP32 path's deformation time series stays within the
+    stated 1e-3 of the FP64 path's, and its order parameters within 1e-4, over 300 steps
+    (sampled every 50)."""
+    w = single_channel_large(bond=2.0)
+    say("case full size 2048x512 Bo=2 FP32 vs FP64 D(t)")
+    a = Channel(w, precision=fcd.FCD_FP64, tol=1e-10)
+    b = Channel(w, precision=fcd.FCD_FP32, tol=1e-5)
+    for c in (a, b):
+        c.init_droplet()
+    worst = 0.0
+    for k in range(6):
+        a.step(50)
+        b.step(50)
+        da, db = a.deformation(), b.deformation()
+        worst = max(worst, abs(da[0] - db[0]), abs(da[1] - db[1]))
+        say(f"  step {50 * (k + 1)}: D_o {da[0]:.6e} vs {db[0]:.6e}, D_i {da[1]:.6e} vs {db[1]:.6e}")
+    assert worst <= 1e-3, worst
+    ma, mb = a.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2), b.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2)
+    for key in ma:
+        err = np.abs(ma[key] - mb[key]).max()
+        say(f"  {key}: max |fp32 - fp64| = {err:.2e}")
+        assert err <= 1e-4, key
+    a.close()
+    b.close()
