@@ -278,7 +278,7 @@ def main() -> int:
     solver = fcd.FCD_SOLVER_MG if args.solver == "mg" else fcd.FCD_SOLVER_SOR
     ch = Channel(w, precision=prec, solver=solver, tol=tol, check_every=args.check_every if args.solver == "mg" else 8,
                  max_iters=1 << 30, smooth=args.smooth, coarse_sweeps=args.coarse_sweeps,
-                 extrapolate=0 if args.no_extrapolate else 1)
+                 extrapolate=0 if args.no_extrapolate else 2)
     ch.init_droplet()
     t0 = time.perf_counter()
     st, sw0, res0 = ch.solve_potential(tol, 1 << 30)

@@ -61,7 +61,8 @@ struct MgPlan {
     int tail;  // first tail level (== levels: no tail)
     int nx[MAX_LEVELS], ny[MAX_LEVELS], pitch[MAX_LEVELS];
     size_t off_mu[MAX_LEVELS], off_u[MAX_LEVELS], off_f[MAX_LEVELS], off_t[MAX_LEVELS];
-    size_t off_prev;  // psi' history plane
+    size_t off_prev;  // psi' history planes: psi'(t-1) ...
+    size_t off_prev2; // ... and psi'(t-2) (quadratic extrapolation)
     size_t bytes;     // total scratch
 };
 
@@ -91,6 +92,8 @@ MgPlan make_plan(const fcd_lattice& l) {
     }
     size_t off = align256(OFF_ROWS + (size_t)l.ny * 8 * sizeof(double));
     p.off_prev = off;
+    off += align256((size_t)l.ny * l.pitch * esz);
+    p.off_prev2 = off;
     off += align256((size_t)l.ny * l.pitch * esz);
     for (int L = 0; L < p.levels; ++L) {
         const size_t plane = align256((size_t)p.ny[L] * p.pitch[L] * esz);
@@ -252,6 +255,7 @@ fcd_status check_params(const fcd_params* p) {
     if (p->pot_check_every < 1 || p->pot_max_iters < 0) return fail(FCD_ERR_ARG, "bad potential iteration counts");
     if (p->pot_solver == FCD_SOLVER_MG && (p->pot_smooth < 1 || p->pot_coarse_sweeps < 1))
         return fail(FCD_ERR_ARG, "multigrid needs pot_smooth >= 1 and pot_coarse_sweeps >= 1");
+    if (p->pot_extrapolate < 0 || p->pot_extrapolate > 2) return fail(FCD_ERR_ARG, "pot_extrapolate must be 0, 1 or 2");
     return FCD_OK;
 }
 
@@ -655,6 +659,7 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
     const fcd::StepConst<T> P = make_const<T>(h);
     T* phi = static_cast<T*>(h->buf.phi);
     T* prev = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev);
+    T* prev2 = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev2);
     for (int n = 0; n < nsteps; ++n) {
         const T* src = static_cast<const T*>(h->buf.dist[h->cur]);
         T* dst = static_cast<T*>(h->buf.dist[1 - h->cur]);
@@ -664,9 +669,13 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
         if (timed) h->timer.end(h->stream, TK_PHASE, ev);
         fcd_status st = hip_check(hipGetLastError(), "phase launch");
         if (st) return st;
-        if (h->prm.pot_extrapolate && h->prm.H0 != 0.0)
-            fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, h->lat.nx, h->lat.ny, h->lat.pitch,
-                                       h->hist >= 2 ? 1 : 0, h->stream);
+        if (h->prm.pot_extrapolate && h->prm.H0 != 0.0) {
+            // the first solve's start (the initial solve) is not extrapolated from; linear
+            // from the third step, quadratic from the fourth
+            const int mode = h->hist >= 3 && h->prm.pot_extrapolate == 2 ? 2 : h->hist >= 2 ? 1 : 0;
+            fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, h->lat.nx, h->lat.ny, h->lat.pitch,
+                                       mode, h->stream);
+        }
         st = solve_impl<T>(h, h->prm.pot_tol, h->prm.pot_max_iters, nullptr, nullptr);
         if (st) return st;
         ++h->hist;
@@ -1291,18 +1300,18 @@ fcd_status batch_moments_impl(fcd_batch* b, int k, unsigned mask, double* out) {
 // ---------------------------------------------------------------------------------
 struct AdjLayout {
     size_t plane, state;
-    size_t crec;  // checkpoint record: state, psi' and the psi' history plane (warm start)
+    size_t crec;  // checkpoint record: state, psi' and the two psi' history planes (warm start)
     size_t srec;  // segment record: state and the step's psi'
     int nseg, nblocks;
-    size_t off_ckpt, off_final, off_seg, off_lam, off_sens, off_rhs, off_lpsi, off_lprev, off_part, off_acc, off_rmax,
-        bytes;
+    size_t off_ckpt, off_final, off_seg, off_lam, off_sens, off_rhs, off_lpsi, off_lprev, off_lprev2, off_part, off_acc,
+        off_rmax, bytes;
 };
 
 AdjLayout adj_layout(const fcd_lattice& l, int nsteps, int every) {
     AdjLayout L{};
     L.plane = (size_t)l.ny * l.pitch * elem_size(l.precision);
     L.state = 27 * L.plane;
-    L.crec = align256(L.state + 2 * L.plane);
+    L.crec = align256(L.state + 3 * L.plane);
     L.srec = align256(L.state + L.plane);
     L.nseg = (nsteps + every - 1) / every;
     L.nblocks = fcd::adj_blocks(l.nx, l.ny);
@@ -1323,6 +1332,8 @@ AdjLayout adj_layout(const fcd_lattice& l, int nsteps, int every) {
     off += align256(L.plane);
     L.off_lprev = off;
     off += align256(L.plane);
+    L.off_lprev2 = off;
+    off += align256(L.plane);
     L.off_part = off;
     off += align256(3 * (size_t)L.nblocks * fcd::ADJ_NPART * sizeof(double));
     L.off_acc = off;
@@ -1341,8 +1352,8 @@ fcd_status dcopy(void* dst, const void* src, size_t bytes, hipStream_t s) {
 // start) and the psi' history plane; the history count and the previous solve's
 // iteration count are kept on the host beside them.
 template <typename T>
-T* psi_prev(fcd_handle* h) {
-    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev);
+T* psi_prev(fcd_handle* h, int k = 1) {
+    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + (k == 1 ? h->plan.off_prev : h->plan.off_prev2));
 }
 
 template <typename T>
@@ -1350,6 +1361,7 @@ fcd_status save_record(fcd_handle* h, char* rec, const AdjLayout& L) {
     fcd_status st = dcopy(rec, h->buf.dist[h->cur], L.state, h->stream);
     if (!st) st = dcopy(rec + L.state, h->buf.psi, L.plane, h->stream);
     if (!st) st = dcopy(rec + L.state + L.plane, psi_prev<T>(h), L.plane, h->stream);
+    if (!st) st = dcopy(rec + L.state + 2 * L.plane, psi_prev<T>(h, 2), L.plane, h->stream);
     return st;
 }
 
@@ -1358,6 +1370,7 @@ fcd_status load_record(fcd_handle* h, const char* rec, const AdjLayout& L) {
     fcd_status st = dcopy(h->buf.dist[h->cur], rec, L.state, h->stream);
     if (!st) st = dcopy(h->buf.psi, rec + L.state, L.plane, h->stream);
     if (!st) st = dcopy(psi_prev<T>(h), rec + L.state + L.plane, L.plane, h->stream);
+    if (!st) st = dcopy(psi_prev<T>(h, 2), rec + L.state + 2 * L.plane, L.plane, h->stream);
     return st;
 }
 
@@ -1411,6 +1424,7 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
     T* phi = static_cast<T*>(h->buf.phi);
     char* scr = static_cast<char*>(h->buf.scratch);
     T* lprev = reinterpret_cast<T*>(w + L.off_lprev);
+    T* lprev2 = reinterpret_cast<T*>(w + L.off_lprev2);
     fcd::launch_fill<double>(acc, 16, 0.0, h->stream);
     fcd::launch_fill<T>(lpsi, pl, T(0), h->stream);
     int lhist = 0;  // adjoint potential solves so far (warm-start extrapolation validity)
@@ -1456,9 +1470,13 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
                 std::memcpy(&rm, h->host, sizeof(double));
                 if (rm > 0.0) {
                     // warm start: linear extrapolation of the last two adjoint solutions
-                    if (h->prm.pot_extrapolate)
-                        fcd::launch_psi_history<T>(lpsi, lprev, h->lat.nx, h->lat.ny, h->lat.pitch, lhist >= 2 ? 1 : 0,
+                    if (h->prm.pot_extrapolate) {
+                        // the adjoint potentials of successive (reversed) steps, extrapolated
+                        // as in the forward
+                        const int mode = lhist >= 3 && h->prm.pot_extrapolate == 2 ? 2 : lhist >= 2 ? 1 : 0;
+                        fcd::launch_psi_history<T>(lpsi, lprev, lprev2, h->lat.nx, h->lat.ny, h->lat.pitch, mode,
                                                    h->stream);
+                    }
                     ++lhist;
                     fcd::PotLevel<T> La = pot_level<T>(h, 0);
                     La.u = lpsi;

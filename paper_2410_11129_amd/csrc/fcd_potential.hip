@@ -642,16 +642,21 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
     }
 }
 
-// Warm start: mode 0 keeps psi' and records it; mode 1 replaces psi' by the linear
-// extrapolation 2 psi'(t-1) - psi'(t-2) and records psi'(t-1).
+// Warm start from the recorded solutions: mode 0 keeps psi' and records it; mode 1
+// replaces psi' by the linear extrapolation 2 psi'(t-1) - psi'(t-2), mode 2 by the
+// quadratic one 3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3); prev records psi'(t-1) and, when
+// prev2 is given, prev2 the previous prev.
 template <typename T>
-__global__ void __launch_bounds__(PX* PY) k_psi_history(T* __restrict__ psi, T* __restrict__ prev, int nx, int ny,
-                                                        int pitch, int mode) {
+__global__ void __launch_bounds__(PX* PY) k_psi_history(T* __restrict__ psi, T* __restrict__ prev,
+                                                        T* __restrict__ prev2, int nx, int ny, int pitch, int mode) {
     const int i = blockIdx.x * PX + threadIdx.x, j = blockIdx.y * PY + threadIdx.y;
     if (i >= nx || j >= ny) return;
     const long long k = (long long)j * pitch + i;
     const T cur = psi[k];
-    if (mode == 1) psi[k] = T(2) * cur - prev[k];
+    const T p1 = prev[k];
+    if (mode == 1) psi[k] = T(2) * cur - p1;
+    if (mode == 2) psi[k] = T(3) * (cur - p1) + prev2[k];
+    if (prev2) prev2[k] = p1;
     prev[k] = cur;
 }
 
@@ -754,8 +759,8 @@ void launch_mg_tail(const MgTail<T>& tl, hipStream_t s) {
 }
 
 template <typename T>
-void launch_psi_history(T* psi, T* prev, int nx, int ny, int pitch, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_psi_history<T>, pgrid(nx, ny), dim3(PX, PY), 0, s, psi, prev, nx, ny, pitch, mode);
+void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_psi_history<T>, pgrid(nx, ny), dim3(PX, PY), 0, s, psi, prev, prev2, nx, ny, pitch, mode);
 }
 
 #define FCD_POT_INSTANTIATE(T)                                                                            \
@@ -769,7 +774,7 @@ void launch_psi_history(T* psi, T* prev, int nx, int ny, int pitch, int mode, hi
     template void launch_mg_restrict_smooth<T>(const PotLevel<T>&, const PotLevel<T>&, int, T*, int, hipStream_t); \
     template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
     template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \
-    template void launch_psi_history<T>(T*, T*, int, int, int, int, hipStream_t);
+    template void launch_psi_history<T>(T*, T*, T*, int, int, int, int, hipStream_t);
 
 FCD_POT_INSTANTIATE(double)
 FCD_POT_INSTANTIATE(float)
