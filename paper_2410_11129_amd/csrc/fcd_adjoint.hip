@@ -256,13 +256,37 @@ __global__ void __launch_bounds__(AT) k_adj_finish(const T* __restrict__ sens, c
 
 // Sum of the per-block partials in a fixed order: acc[q] += sum_b part[b][q] for the
 // first nq slots, into acc slots starting at dst.
-__global__ void k_adj_reduce(const double* __restrict__ part, int nblocks, int nq, double* __restrict__ acc,
-                             int dst) {
+// One block of RED_T threads: thread t sums the partials of blocks t, t + RED_T, ... for
+// every quantity, then the threads' sums are combined by a fixed wave-shuffle and LDS
+// tree, so the result does not depend on scheduling.
+constexpr int RED_T = 256;
+
+__global__ void __launch_bounds__(RED_T) k_adj_reduce(const double* __restrict__ part, int nblocks, int nq,
+                                                      double* __restrict__ acc, int dst) {
+    __shared__ double wsum[ADJ_NPART][RED_T / 64];
+    double v[ADJ_NPART];
+#pragma unroll
+    for (int q = 0; q < ADJ_NPART; ++q) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += RED_T) {
+        const double* p = part + (long long)b * ADJ_NPART;
+#pragma unroll
+        for (int q = 0; q < ADJ_NPART; ++q)
+            if (q < nq) v[q] += p[q];
+    }
+#pragma unroll
+    for (int q = 0; q < ADJ_NPART; ++q) {
+        double s = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if ((threadIdx.x & 63) == 0) wsum[q][threadIdx.x >> 6] = s;
+    }
+    __syncthreads();
     const int q = threadIdx.x;
-    if (q >= nq) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(long long)b * ADJ_NPART + q];
-    acc[dst + q] += s;
+    if (q < nq) {
+        double s = 0.0;
+        for (int w = 0; w < RED_T / 64; ++w) s += wsum[q][w];
+        acc[dst + q] += s;
+    }
 }
 
 // Adjoint of the final state from J = dJ[0] D_o + dJ[1] D_i (second-moment deformation
@@ -461,7 +485,7 @@ void launch_adj_finish(const T* sens, const T* phi, const T* psi, const T* lpsi,
 }
 
 void launch_adj_reduce(const double* part, int nblocks, int nq, double* acc, int dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(64), 0, s, part, nblocks, nq, acc, dst);
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(RED_T), 0, s, part, nblocks, nq, acc, dst);
 }
 
 template <typename T>
