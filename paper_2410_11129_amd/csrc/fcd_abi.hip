@@ -379,9 +379,18 @@ fcd_status read_residual(fcd_handle* h, const fcd::PotLevel<T>& L0, double* r, d
 // Coarse mu on every level, from the current mu_r plane.
 template <typename T>
 void restrict_mu_all(fcd_handle* h) {
-    for (int l = 1; l < h->plan.levels; ++l) {
-        const fcd::PotLevel<T> F = pot_level<T>(h, l - 1), C = pot_level<T>(h, l);
-        fcd::launch_mg_restrict_mu<T>(F.mu, F.pitch, const_cast<T*>(C.mu), C.nx, C.ny, C.pitch, h->stream);
+    for (int l = 1; l < h->plan.levels; l += 4) {
+        const fcd::PotLevel<T> F = pot_level<T>(h, l - 1);
+        fcd::MuLevels<T> C{};
+        C.n = std::min(4, h->plan.levels - l);
+        for (int k = 0; k < C.n; ++k) {
+            const fcd::PotLevel<T> Ck = pot_level<T>(h, l + k);
+            C.mu[k] = const_cast<T*>(Ck.mu);
+            C.nx[k] = Ck.nx;
+            C.ny[k] = Ck.ny;
+            C.pitch[k] = Ck.pitch;
+        }
+        fcd::launch_mg_restrict_mu4<T>(F.mu, F.pitch, F.nx, F.ny, C, h->stream);
     }
 }
 

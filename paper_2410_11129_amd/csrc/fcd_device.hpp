@@ -57,6 +57,14 @@ struct PotLevel {
 // The coarsest levels of a V-cycle, solved in LDS by one block (levels lv[0..n), finest
 // first; lv[0].f holds the restricted residual, lv[0].u receives the correction).
 constexpr int MG_MAX_TAIL = 8;
+// Up to four successive coarse mu levels (cell averages) written by one launch.
+template <typename T>
+struct MuLevels {
+    T* mu[4];
+    int nx[4], ny[4], pitch[4];
+    int n;
+};
+
 template <typename T>
 struct MgTail {
     PotLevel<T> lv[MG_MAX_TAIL];

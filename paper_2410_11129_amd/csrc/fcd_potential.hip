@@ -78,6 +78,53 @@ __global__ void __launch_bounds__(PX* PY) k_mg_restrict_mu(const T* __restrict__
     muc[(long long)J * pitchc + I] = T(0.25) * ((muf[r0] + muf[r0 + 1]) + (muf[r1] + muf[r1 + 1]));
 }
 
+// Up to four coarse mu levels in one launch: a block owns a 64 x 16 tile of the finer
+// level, which contains the children of every coarse node of the next four levels that
+// lies over it, and averages level by level in LDS (same expression as k_mg_restrict_mu,
+// so the values are bitwise those of four separate launches).
+constexpr int MU_TX = 64, MU_TY = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* __restrict__ muf, int pitchf, int nxf,
+                                                                        int nyf, MuLevels<T> C) {
+    constexpr int NT = MU_TX * MU_TY / 4;
+    __shared__ T s0[MU_TY][MU_TX];
+    __shared__ T s1[MU_TY / 2][MU_TX / 2];
+    const int i0 = blockIdx.x * MU_TX, j0 = blockIdx.y * MU_TY, tid = threadIdx.x;
+    T v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = tid + r * NT, ly = q / MU_TX, lx = q - ly * MU_TX;
+        const int i = i0 + lx, j = j0 + ly;
+        v[r] = (i < nxf && j < nyf) ? muf[(long long)j * pitchf + i] : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int q = tid + r * NT;
+        s0[q / MU_TX][q % MU_TX] = v[r];
+    }
+    __syncthreads();
+    T* src = &s0[0][0];
+    T* dst = &s1[0][0];
+    int sx = MU_TX;  // row length of src
+    for (int k = 0; k < C.n; ++k) {
+        const int cx = sx / 2, cy = (MU_TY >> k) / 2;
+        for (int t = tid; t < cx * cy; t += NT) {
+            const int y = t / cx, x = t - y * cx;
+            const T* a = src + (2 * y) * sx + 2 * x;
+            const T m = T(0.25) * ((a[0] + a[1]) + (a[sx] + a[sx + 1]));
+            dst[y * cx + x] = m;
+            const int I = (i0 >> (k + 1)) + x, J = (j0 >> (k + 1)) + y;
+            if (I < C.nx[k] && J < C.ny[k]) C.mu[k][(long long)J * C.pitch[k] + I] = m;
+        }
+        __syncthreads();
+        T* tmp = src;
+        src = dst;
+        dst = tmp;
+        sx = cx;
+    }
+}
+
 // Coarse right-hand side = average of the four fine residuals; coarse correction = 0.
 template <typename T>
 __global__ void __launch_bounds__(PX* PY) k_mg_restrict_residual(PotLevel<T> F, PotLevel<T> Cl) {
@@ -576,22 +623,70 @@ __device__ __forceinline__ void tail_jacobi(PotLevel<T> S, T* alt, int sweeps) {
     }
 }
 
+// Largest tail level (64 KB of four arrays in FP32) and the loads per thread it takes.
+constexpr int TAIL_MAXN = 4096;
+constexpr int TAIL_LPER = TAIL_MAXN / TAIL_T;
+
 template <typename T>
 __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* base = reinterpret_cast<T*>(lds_raw);
     T* alt;
-    for (int k = 0; k < tl.n; ++k) {
-        const PotLevel<T> G = tl.lv[k];
-        const PotLevel<T> S = tail_view(tl, base, k, &alt);
+    const int tid = threadIdx.x;
+    // every tail level's mu and the top level's right-hand side, all loads issued before
+    // any LDS store (one memory latency instead of one per level)
+    T m0[TAIL_LPER], f0[TAIL_LPER], mk[MG_MAX_TAIL - 1][2];
+    {
+        const PotLevel<T> G = tl.lv[0];
+        const int n = G.nx * G.ny;
+#pragma unroll
+        for (int r = 0; r < TAIL_LPER; ++r) {
+            const int t = tid + r * TAIL_T;
+            if (t < n) {
+                const int j = t / G.nx, i = t - j * G.nx;
+                const long long g = (long long)j * G.pitch + i;
+                m0[r] = G.mu[g];
+                f0[r] = G.f[g];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 1; k < MG_MAX_TAIL; ++k) {
+        if (k < tl.n) {
+            const PotLevel<T> G = tl.lv[k];
+            const int n = G.nx * G.ny;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int t = tid + r * TAIL_T;
+                if (t < n) {
+                    const int j = t / G.nx, i = t - j * G.nx;
+                    mk[k - 1][r] = G.mu[(long long)j * G.pitch + i];
+                }
+            }
+        }
+    }
+    {
+        const PotLevel<T> S = tail_view(tl, base, 0, &alt);
         const int n = S.nx * S.ny;
-        for (int t = threadIdx.x; t < n; t += TAIL_T) {
-            const int j = t / S.nx, i = t - j * S.nx;
-            const long long g = (long long)j * G.pitch + i;
-            const_cast<T*>(S.mu)[t] = G.mu[g];
-            if (k == 0) {
-                S.f[t] = G.f[g];
+#pragma unroll
+        for (int r = 0; r < TAIL_LPER; ++r) {
+            const int t = tid + r * TAIL_T;
+            if (t < n) {
+                const_cast<T*>(S.mu)[t] = m0[r];
+                S.f[t] = f0[r];
                 S.u[t] = T(0);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 1; k < MG_MAX_TAIL; ++k) {
+        if (k < tl.n) {
+            const PotLevel<T> S = tail_view(tl, base, k, &alt);
+            const int n = S.nx * S.ny;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int t = tid + r * TAIL_T;
+                if (t < n) const_cast<T*>(S.mu)[t] = mk[k - 1][r];
             }
         }
     }
@@ -601,16 +696,24 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         T* altc;
         const PotLevel<T> F = tail_view(tl, base, k, &alt), Cc = tail_view(tl, base, k + 1, &altc);
         tail_jacobi(F, alt, sw);
+        // fine residuals into the (free) ping-pong array, then their four-child sums in
+        // the fixed order (0,0), (1,0), (0,1), (1,1)
+        const int nf = F.nx * F.ny;
+        for (int t = tid; t < nf; t += TAIL_T) {
+            const int j = t / F.nx, i = t - j * F.nx;
+            const MgEval<T> r = mg_eval(F, i, j);
+            alt[t] = r.rhs - (r.acc - r.C * F.u[t]);
+        }
+        __syncthreads();
         const int n = Cc.nx * Cc.ny;
-        for (int t = threadIdx.x; t < n; t += TAIL_T) {
+        for (int t = tid; t < n; t += TAIL_T) {
             const int J = t / Cc.nx, I = t - J * Cc.nx;
+            const T* r0 = alt + (2 * J) * F.nx + 2 * I;
             T s = T(0);
-            for (int dj = 0; dj < 2; ++dj)
-                for (int di = 0; di < 2; ++di) {
-                    const int i = 2 * I + di, j = 2 * J + dj;
-                    const MgEval<T> r = mg_eval(F, i, j);
-                    s += r.rhs - (r.acc - r.C * F.u[(long long)j * F.pitch + i]);
-                }
+            s += r0[0];
+            s += r0[1];
+            s += r0[F.nx];
+            s += r0[F.nx + 1];
             Cc.f[t] = T(0.25) * s;
             Cc.u[t] = T(0);
         }
@@ -627,7 +730,7 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         T* altc;
         const PotLevel<T> F = tail_view(tl, base, k, &alt), Cc = tail_view(tl, base, k + 1, &altc);
         const int n = F.nx * F.ny;
-        for (int t = threadIdx.x; t < n; t += TAIL_T) {
+        for (int t = tid; t < n; t += TAIL_T) {
             const int j = t / F.nx, i = t - j * F.nx;
             F.u[t] += prolong_at(Cc, i, j);
         }
@@ -636,7 +739,7 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
     }
     const PotLevel<T> G = tl.lv[0];
     const PotLevel<T> S = tail_view(tl, base, 0, &alt);
-    for (int t = threadIdx.x; t < S.nx * S.ny; t += TAIL_T) {
+    for (int t = tid; t < S.nx * S.ny; t += TAIL_T) {
         const int j = t / S.nx, i = t - j * S.nx;
         G.u[(long long)j * G.pitch + i] = S.u[t];
     }
@@ -683,6 +786,12 @@ void launch_pot_residual(const PotLevel<T>& L, unsigned long long* out, hipStrea
 template <typename T>
 void launch_mg_restrict_mu(const T* muf, int pitchf, T* muc, int nxc, int nyc, int pitchc, hipStream_t s) {
     hipLaunchKernelGGL(k_mg_restrict_mu<T>, pgrid(nxc, nyc), dim3(PX, PY), 0, s, muf, pitchf, muc, nxc, nyc, pitchc);
+}
+
+template <typename T>
+void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const MuLevels<T>& C, hipStream_t s) {
+    const dim3 g((nxf + MU_TX - 1) / MU_TX, (nyf + MU_TY - 1) / MU_TY);
+    hipLaunchKernelGGL(k_mg_restrict_mu4<T>, g, dim3(MU_TX * MU_TY / 4), 0, s, muf, pitchf, nxf, nyf, C);
 }
 
 template <typename T>
@@ -767,6 +876,7 @@ void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, in
     template void launch_pot_sweep<T>(const PotLevel<T>&, T, hipStream_t);                                \
     template void launch_pot_residual<T>(const PotLevel<T>&, unsigned long long*, hipStream_t);           \
     template void launch_mg_restrict_mu<T>(const T*, int, T*, int, int, int, hipStream_t);                \
+    template void launch_mg_restrict_mu4<T>(const T*, int, int, int, const MuLevels<T>&, hipStream_t);    \
     template void launch_mg_restrict_residual<T>(const PotLevel<T>&, const PotLevel<T>&, hipStream_t);    \
     template void launch_mg_smooth_tile<T>(const PotLevel<T>&, const T*, T*, const PotLevel<T>*, int,         \
                                            unsigned long long*, int, hipStream_t);                            \
