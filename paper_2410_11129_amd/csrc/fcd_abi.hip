@@ -46,11 +46,15 @@ double sor_omega_opt(int ny) { return 2.0 / (1.0 + std::sin(3.141592653589793238
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Multigrid hierarchy and scratch layout.  Level 0 is the lattice itself (psi', mu_r
-// planes of the caller); coarser levels halve both dimensions while nx is a multiple
-// of 4 and ny is even and >= 4.  The coarsest levels whose u, f, mu and a Jacobi
-// ping-pong array fit together in TAIL_LDS_MAX bytes form the tail, solved in LDS by one
-// block; every level above the tail has a second plane for the tile smoother's
-// ping-pong.
+// planes of the caller, in the lattice's precision); coarser levels halve both
+// dimensions while nx is a multiple of 4 and ny is even and >= 4, and are FP32 in both
+// precisions: they only compute corrections, each cycle's residual is formed on level 0
+// in the lattice's precision, so the solve still reaches that precision's tolerance
+// (mixed-precision multigrid), while the latency-bound coarse kernels run FP32 arithmetic
+// on half the bytes.  The coarsest levels whose u, f, mu and a Jacobi ping-pong array fit
+// together in TAIL_LDS_MAX bytes form the tail, solved in LDS by one block; every level
+// above the tail has a second plane for the tile smoother's ping-pong.
+using CT = float;  // element type of the coarse levels
 constexpr int MAX_LEVELS = 16;
 constexpr size_t TAIL_LDS_MAX = 65536;
 // Tile sweeps per smoothing launch on the levels between the finest and the tail.
@@ -79,13 +83,13 @@ MgPlan make_plan(const fcd_lattice& l) {
         const int L = p.levels++;
         p.nx[L] = px / 2;
         p.ny[L] = py / 2;
-        const int per = (int)(256 / esz);
+        const int per = (int)(256 / sizeof(CT));
         p.pitch[L] = (p.nx[L] + per - 1) / per * per;
     }
     p.tail = p.levels;
     size_t tail_bytes = 0;
     for (int L = p.levels - 1; L >= 1 && p.levels - L <= fcd::MG_MAX_TAIL; --L) {
-        const size_t b = 4 * (size_t)p.nx[L] * p.ny[L] * esz;
+        const size_t b = 4 * (size_t)p.nx[L] * p.ny[L] * sizeof(CT);
         if (tail_bytes + b > TAIL_LDS_MAX) break;
         tail_bytes += b;
         p.tail = L;
@@ -96,7 +100,7 @@ MgPlan make_plan(const fcd_lattice& l) {
     p.off_prev2 = off;
     off += align256((size_t)l.ny * l.pitch * esz);
     for (int L = 0; L < p.levels; ++L) {
-        const size_t plane = align256((size_t)p.ny[L] * p.pitch[L] * esz);
+        const size_t plane = align256((size_t)p.ny[L] * p.pitch[L] * (L == 0 ? esz : sizeof(CT)));
         if (L > 0) {
             p.off_mu[L] = off;
             p.off_u[L] = off + plane;
@@ -323,29 +327,38 @@ unsigned long long* res_word(const fcd_handle* h) {
     return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + OFF_RES);
 }
 
+// Level 0 (the lattice's psi' and mu_r planes).
 template <typename T>
 fcd::PotLevel<T> pot_level(const fcd_handle* h, int l) {
     fcd::PotLevel<T> L{};
+    L.nx = h->plan.nx[l];
+    L.ny = h->plan.ny[l];
+    L.pitch = h->plan.pitch[l];
+    L.u = static_cast<T*>(h->buf.psi);
+    L.mu = plane_ptr<T>(h->buf.phi, h, 2);
+    L.f = nullptr;
+    L.inv_h2 = T(1);
+    L.kappa = T(0);
+    L.H0x = T(h->prm.H0 * std::cos(h->prm.alpha));
+    L.H0y = T(h->prm.H0 * std::sin(h->prm.alpha));
+    return L;
+}
+
+// Coarse level l >= 1 (FP32 planes in the scratch).
+fcd::PotLevel<CT> coarse_level(const fcd_handle* h, int l) {
+    fcd::PotLevel<CT> L{};
     char* s = static_cast<char*>(h->buf.scratch);
     L.nx = h->plan.nx[l];
     L.ny = h->plan.ny[l];
     L.pitch = h->plan.pitch[l];
-    if (l == 0) {
-        L.u = static_cast<T*>(h->buf.psi);
-        L.mu = plane_ptr<T>(h->buf.phi, h, 2);
-        L.f = nullptr;
-        L.inv_h2 = T(1);
-        L.kappa = T(0);
-        L.H0x = T(h->prm.H0 * std::cos(h->prm.alpha));
-        L.H0y = T(h->prm.H0 * std::sin(h->prm.alpha));
-    } else {
+    {
         const double hh = double(1 << l);
-        L.u = reinterpret_cast<T*>(s + h->plan.off_u[l]);
-        L.mu = reinterpret_cast<const T*>(s + h->plan.off_mu[l]);
-        L.f = reinterpret_cast<T*>(s + h->plan.off_f[l]);
-        L.inv_h2 = T(1.0 / (hh * hh));
-        L.kappa = T((hh - 1.0) / (hh + 1.0));
-        L.H0x = L.H0y = T(0);
+        L.u = reinterpret_cast<CT*>(s + h->plan.off_u[l]);
+        L.mu = reinterpret_cast<const CT*>(s + h->plan.off_mu[l]);
+        L.f = reinterpret_cast<CT*>(s + h->plan.off_f[l]);
+        L.inv_h2 = CT(1.0 / (hh * hh));
+        L.kappa = CT((hh - 1.0) / (hh + 1.0));
+        L.H0x = L.H0y = CT(0);
     }
     return L;
 }
@@ -380,17 +393,22 @@ fcd_status read_residual(fcd_handle* h, const fcd::PotLevel<T>& L0, double* r, d
 template <typename T>
 void restrict_mu_all(fcd_handle* h) {
     for (int l = 1; l < h->plan.levels; l += 4) {
-        const fcd::PotLevel<T> F = pot_level<T>(h, l - 1);
-        fcd::MuLevels<T> C{};
+        fcd::MuLevels<CT> C{};
         C.n = std::min(4, h->plan.levels - l);
         for (int k = 0; k < C.n; ++k) {
-            const fcd::PotLevel<T> Ck = pot_level<T>(h, l + k);
-            C.mu[k] = const_cast<T*>(Ck.mu);
+            const fcd::PotLevel<CT> Ck = coarse_level(h, l + k);
+            C.mu[k] = const_cast<CT*>(Ck.mu);
             C.nx[k] = Ck.nx;
             C.ny[k] = Ck.ny;
             C.pitch[k] = Ck.pitch;
         }
-        fcd::launch_mg_restrict_mu4<T>(F.mu, F.pitch, F.nx, F.ny, C, h->stream);
+        if (l == 1) {
+            const fcd::PotLevel<T> F = pot_level<T>(h, 0);
+            fcd::launch_mg_restrict_mu4<T, CT>(F.mu, F.pitch, F.nx, F.ny, C, h->stream);
+        } else {
+            const fcd::PotLevel<CT> F = coarse_level(h, l - 1);
+            fcd::launch_mg_restrict_mu4<CT, CT>(F.mu, F.pitch, F.nx, F.ny, C, h->stream);
+        }
     }
 }
 
@@ -437,9 +455,8 @@ int coarse_sweeps(const fcd_handle* h, int ny) { return std::max(1, h->prm.pot_c
 
 // Solve the coarsest level by launched SOR sweeps (no tail, or no coarse level at all).
 template <typename T>
-void coarse_solve(fcd_handle* h, int l, const fcd::PotLevel<T>& L0) {
-    const fcd::PotLevel<T> L = l == 0 ? L0 : pot_level<T>(h, l);
-    const T om = T(l == 0 && h->prm.pot_omega > 0.0 ? h->prm.pot_omega : sor_omega_opt(L.ny));
+void coarse_solve(fcd_handle* h, const fcd::PotLevel<T>& L, bool finest) {
+    const T om = T(finest && h->prm.pot_omega > 0.0 ? h->prm.pot_omega : sor_omega_opt(L.ny));
     for (int s = 0; s < coarse_sweeps(h, L.ny); ++s) fcd::launch_pot_sweep<T>(L, om, h->stream);
 }
 
@@ -456,17 +473,18 @@ int fine_mode(const fcd::PotLevel<T>& L0) {
     return L0.f ? 2 : 1;
 }
 
-// nu1 pre-smoothing sweeps of level l starting from F.u; returns the buffer holding the
-// result.  The first sweep reduces the input's residual into res when res != nullptr.
+// nu1 pre-smoothing sweeps of the finest level starting from F.u; returns the buffer
+// holding the result.  The first sweep reduces the input's residual into res when
+// res != nullptr.
 template <typename T>
-T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, unsigned long long* res) {
+T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int mode, unsigned long long* res) {
     T* a = F.u;
-    T* b = mg_temp<T>(h, l);
+    T* b = mg_temp<T>(h, 0);
+    const fcd::PotLevel<CT>* none = nullptr;
     for (int s = 0; s < std::max(1, h->prm.pot_smooth); ++s) {
         hipEvent_t ev = nullptr;
-        const bool timed = l == 0 && h->timer.begin(h->stream, &ev);
-        fcd::launch_mg_smooth_tile<T>(F, a, b, nullptr, mode, s == 0 ? res : nullptr, l == 0 ? 1 : MG_COARSE_INNER,
-                                      h->stream);
+        const bool timed = h->timer.begin(h->stream, &ev);
+        fcd::launch_mg_smooth_tile<T, CT>(F, a, b, none, mode, s == 0 ? res : nullptr, 1, h->stream);
         if (timed) h->timer.end(h->stream, TK_SMOOTH0, ev);
         std::swap(a, b);
     }
@@ -476,15 +494,16 @@ T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, unsig
 // Coarse level l >= 1: the restriction from level l-1 (u = its pre-smoothed iterate
 // Fp.u, right-hand side by fmode) fused with the first of nu1 pre-smoothing sweeps from
 // a zero correction; returns the buffer holding the result.
-template <typename T>
-T* mg_restrict_presmooth(fcd_handle* h, const fcd::PotLevel<T>& Fp, int fmode, int l) {
-    const fcd::PotLevel<T> F = pot_level<T>(h, l);
-    T* a = F.u;
-    T* b = mg_temp<T>(h, l);
-    fcd::launch_mg_restrict_smooth<T>(Fp, F, fmode, b, MG_COARSE_INNER, h->stream);
+template <typename TF>
+CT* mg_restrict_presmooth(fcd_handle* h, const fcd::PotLevel<TF>& Fp, int fmode, int l) {
+    const fcd::PotLevel<CT> F = coarse_level(h, l);
+    const fcd::PotLevel<CT>* none = nullptr;
+    CT* a = F.u;
+    CT* b = mg_temp<CT>(h, l);
+    fcd::launch_mg_restrict_smooth<TF, CT>(Fp, F, fmode, b, MG_COARSE_INNER, h->stream);
     std::swap(a, b);
     for (int s = 1; s < std::max(1, h->prm.pot_smooth); ++s) {
-        fcd::launch_mg_smooth_tile<T>(F, a, b, nullptr, 0, nullptr, MG_COARSE_INNER, h->stream);
+        fcd::launch_mg_smooth_tile<CT, CT>(F, a, b, none, 0, nullptr, MG_COARSE_INNER, h->stream);
         std::swap(a, b);
     }
     return a;
@@ -493,14 +512,15 @@ T* mg_restrict_presmooth(fcd_handle* h, const fcd::PotLevel<T>& Fp, int fmode, i
 // Prolongation of level l+1's correction fused with the first of nu2 post-smoothing
 // sweeps, from the pre-smoothed iterate `cur`; the result ends in F.u.
 template <typename T>
-void mg_postsmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, T* cur, const fcd::PotLevel<T>& Cl) {
+void mg_postsmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, T* cur, const fcd::PotLevel<CT>& Cl) {
     T* other = cur == F.u ? mg_temp<T>(h, l) : F.u;
     const int nu = std::max(1, h->prm.pot_smooth);
+    const fcd::PotLevel<CT>* none = nullptr;
     for (int s = 0; s < nu; ++s) {
         hipEvent_t ev = nullptr;
         const bool timed = l == 0 && s == 0 && h->timer.begin(h->stream, &ev);
-        fcd::launch_mg_smooth_tile<T>(F, cur, other, s == 0 ? &Cl : nullptr, mode, nullptr, l == 0 ? 1 : MG_COARSE_INNER,
-                                      h->stream);
+        fcd::launch_mg_smooth_tile<T, CT>(F, cur, other, s == 0 ? &Cl : none, mode, nullptr,
+                                          l == 0 ? 1 : MG_COARSE_INNER, h->stream);
         if (timed) h->timer.end(h->stream, TK_POST0, ev);
         std::swap(cur, other);
     }
@@ -515,43 +535,51 @@ void vcycle_rest(fcd_handle* h, const fcd::PotLevel<T>& L0, T* cur0) {
     const int L = h->plan.levels;
     const bool tail = h->plan.tail < L;
     const int gend = tail ? h->plan.tail : L - 1;  // levels [0, gend) are smoothed by tiles
-    T* cur[MAX_LEVELS];
-    cur[0] = cur0;
+    CT* cur[MAX_LEVELS] = {};
     for (int l = 1; l < gend; ++l) {
-        fcd::PotLevel<T> Fp = l == 1 ? L0 : pot_level<T>(h, l - 1);
-        Fp.u = cur[l - 1];
-        cur[l] = mg_restrict_presmooth<T>(h, Fp, l == 1 ? fine_mode(L0) : 0, l);
+        if (l == 1) {
+            fcd::PotLevel<T> Fp = L0;
+            Fp.u = cur0;
+            cur[l] = mg_restrict_presmooth<T>(h, Fp, fine_mode(L0), l);
+        } else {
+            fcd::PotLevel<CT> Fp = coarse_level(h, l - 1);
+            Fp.u = cur[l - 1];
+            cur[l] = mg_restrict_presmooth<CT>(h, Fp, 0, l);
+        }
     }
-    {
-        fcd::PotLevel<T> F = gend == 1 ? L0 : pot_level<T>(h, gend - 1);
+    if (gend == 1) {
+        fcd::PotLevel<T> F = L0;
+        F.u = cur0;
+        fcd::launch_mg_restrict_tile<T, CT>(F, coarse_level(h, 1), fine_mode(L0), h->stream);
+    } else {
+        fcd::PotLevel<CT> F = coarse_level(h, gend - 1);
         F.u = cur[gend - 1];
-        fcd::launch_mg_restrict_tile<T>(F, pot_level<T>(h, gend), gend == 1 ? fine_mode(L0) : 0, h->stream);
+        fcd::launch_mg_restrict_tile<CT, CT>(F, coarse_level(h, gend), 0, h->stream);
     }
     if (tail) {
-        fcd::MgTail<T> tl{};
+        fcd::MgTail<CT> tl{};
         tl.n = L - h->plan.tail;
-        for (int k = 0; k < tl.n; ++k) tl.lv[k] = pot_level<T>(h, h->plan.tail + k);
+        for (int k = 0; k < tl.n; ++k) tl.lv[k] = coarse_level(h, h->plan.tail + k);
         tl.nu1 = tl.nu2 = std::max(1, h->prm.pot_smooth);
         tl.coarse_sweeps = coarse_sweeps(h, tl.lv[tl.n - 1].ny);
-        tl.omega = T(sor_omega_opt(tl.lv[tl.n - 1].ny));
-        fcd::launch_mg_tail<T>(tl, h->stream);
+        tl.omega = CT(sor_omega_opt(tl.lv[tl.n - 1].ny));
+        fcd::launch_mg_tail<CT>(tl, h->stream);
     } else {
-        coarse_solve<T>(h, L - 1, L0);
+        coarse_solve<CT>(h, coarse_level(h, L - 1), false);
     }
-    for (int l = gend - 1; l >= 0; --l) {
-        const fcd::PotLevel<T> F = l == 0 ? L0 : pot_level<T>(h, l);
-        mg_postsmooth<T>(h, F, l, l == 0 ? fine_mode(L0) : 0, cur[l], pot_level<T>(h, l + 1));
-    }
+    for (int l = gend - 1; l >= 1; --l)
+        mg_postsmooth<CT>(h, coarse_level(h, l), l, 0, cur[l], coarse_level(h, l + 1));
+    mg_postsmooth<T>(h, L0, 0, fine_mode(L0), cur0, coarse_level(h, 1));
 }
 
 // One full iteration: a V-cycle, or the coarse sweeps on a single-level hierarchy.
 template <typename T>
 void vcycle(fcd_handle* h, const fcd::PotLevel<T>& L0) {
     if (h->plan.levels == 1) {
-        coarse_solve<T>(h, 0, L0);
+        coarse_solve<T>(h, L0, true);
         return;
     }
-    T* cur0 = mg_presmooth<T>(h, L0, 0, fine_mode(L0), nullptr);
+    T* cur0 = mg_presmooth<T>(h, L0, fine_mode(L0), nullptr);
     vcycle_rest<T>(h, L0, cur0);
 }
 
@@ -596,7 +624,7 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
         for (;;) {
             hipEvent_t ev = nullptr;
             bool timed = h->timer.begin(h->stream, &ev);
-            T* cur0 = mg_presmooth<T>(h, L0, 0, fine_mode(L0), res_word(h));
+            T* cur0 = mg_presmooth<T>(h, L0, fine_mode(L0), res_word(h));
             if (timed) h->timer.end(h->stream, TK_RESID, ev);
             st = hip_check(hipMemcpyAsync(h->host, res_word(h), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
                            "residual copy");

@@ -23,27 +23,28 @@ void launch_pot_residual(const PotLevel<T>& L, unsigned long long* out, hipStrea
 template <typename T>
 void launch_mg_restrict_mu(const T* muf, int pitchf, T* muc, int nxc, int nyc, int pitchc, hipStream_t s);
 // Levels C.mu[0 .. C.n) (n <= 4, each half the previous) from the finer mu plane muf.
-template <typename T>
-void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const MuLevels<T>& C, hipStream_t s);
+template <typename T, typename TC>
+void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const MuLevels<TC>& C, hipStream_t s);
 template <typename T>
 void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hipStream_t s);
 // One tile-smoother sweep uin -> uout (never the same buffer); prolong_from != nullptr
 // adds the prolongation of that coarse level's correction first.  mode 0: coarse level
 // (L.f), 1: finest level with the right-hand side from H0, 2: finest level with L.f.
 // res != nullptr: max |residual| and max |C u| of uin into res[0..1] (cleared first).
-// inner: sweeps on the tile before it is written back.
-template <typename T>
-void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
+// inner: sweeps on the tile before it is written back.  The coarse correction may be of
+// another type (TC) than the level's.
+template <typename T, typename TC>
+void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<TC>* prolong_from, int mode,
                            unsigned long long* res, int inner, hipStream_t s);
 // Residual restriction by tiles from F (u = the smoothed iterate) into C (f, u = 0);
 // mode as for the tile smoother.
-template <typename T>
-void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mode, hipStream_t s);
+template <typename T, typename TC>
+void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<TC>& C, int mode, hipStream_t s);
 // The restriction from F fused with the first `inner`-sweep tile smoothing of the coarse
 // level C from a zero correction: C.f is written, the smoothed correction goes to uout
 // (C.u is neither read nor written); fmode is F's mode as for the tile smoother.
-template <typename T>
-void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<T>& C, int fmode, T* uout, int inner,
+template <typename T, typename TC>
+void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<TC>& C, int fmode, TC* uout, int inner,
                                hipStream_t s);
 template <typename T>
 size_t mg_tail_lds_bytes(const MgTail<T>& tl);

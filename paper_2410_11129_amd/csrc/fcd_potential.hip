@@ -84,12 +84,13 @@ __global__ void __launch_bounds__(PX* PY) k_mg_restrict_mu(const T* __restrict__
 // so the values are bitwise those of four separate launches).
 constexpr int MU_TX = 64, MU_TY = 16;
 
-template <typename T>
+template <typename T, typename TC>
 __global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* __restrict__ muf, int pitchf, int nxf,
-                                                                        int nyf, MuLevels<T> C) {
+                                                                        int nyf, MuLevels<TC> C) {
     constexpr int NT = MU_TX * MU_TY / 4;
     __shared__ T s0[MU_TY][MU_TX];
-    __shared__ T s1[MU_TY / 2][MU_TX / 2];
+    __shared__ TC sa[MU_TY / 2][MU_TX / 2];
+    __shared__ TC sb[MU_TY / 4][MU_TX / 4];
     const int i0 = blockIdx.x * MU_TX, j0 = blockIdx.y * MU_TY, tid = threadIdx.x;
     T v[4];
 #pragma unroll
@@ -104,21 +105,30 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* _
         s0[q / MU_TX][q % MU_TX] = v[r];
     }
     __syncthreads();
-    T* src = &s0[0][0];
-    T* dst = &s1[0][0];
-    int sx = MU_TX;  // row length of src
-    for (int k = 0; k < C.n; ++k) {
+    {  // first level from the finer plane's type
+        constexpr int cx = MU_TX / 2, cy = MU_TY / 2;
+        const int y = tid / cx, x = tid - y * cx;  // NT = cx * cy
+        const TC m = TC(T(0.25) * ((s0[2 * y][2 * x] + s0[2 * y][2 * x + 1]) + (s0[2 * y + 1][2 * x] + s0[2 * y + 1][2 * x + 1])));
+        sa[y][x] = m;
+        const int I = (i0 >> 1) + x, J = (j0 >> 1) + y;
+        if (I < C.nx[0] && J < C.ny[0]) C.mu[0][(long long)J * C.pitch[0] + I] = m;
+    }
+    __syncthreads();
+    TC* src = &sa[0][0];
+    TC* dst = &sb[0][0];
+    int sx = MU_TX / 2;  // row length of src
+    for (int k = 1; k < C.n; ++k) {
         const int cx = sx / 2, cy = (MU_TY >> k) / 2;
         for (int t = tid; t < cx * cy; t += NT) {
             const int y = t / cx, x = t - y * cx;
-            const T* a = src + (2 * y) * sx + 2 * x;
-            const T m = T(0.25) * ((a[0] + a[1]) + (a[sx] + a[sx + 1]));
+            const TC* a = src + (2 * y) * sx + 2 * x;
+            const TC m = TC(0.25) * ((a[0] + a[1]) + (a[sx] + a[sx + 1]));
             dst[y * cx + x] = m;
             const int I = (i0 >> (k + 1)) + x, J = (j0 >> (k + 1)) + y;
             if (I < C.nx[k] && J < C.ny[k]) C.mu[k][(long long)J * C.pitch[k] + I] = m;
         }
         __syncthreads();
-        T* tmp = src;
+        TC* tmp = src;
         src = dst;
         dst = tmp;
         sx = cx;
@@ -291,9 +301,9 @@ __device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int
            T(1) / T(16) * gy * sc[lJ2][lI2];
 }
 
-template <typename T, typename G, bool PROLONG, int MODE>
+template <typename T, typename G, bool PROLONG, int MODE, typename TC>
 __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
-                                                          T* __restrict__ uout, PotLevel<T> Cl,
+                                                          T* __restrict__ uout, PotLevel<TC> Cl,
                                                           unsigned long long* __restrict__ res, int inner) {
     constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT, CX = G::CX, CY = G::CY;
     __shared__ T su[HY][HX];
@@ -321,7 +331,7 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
             if (q < CX * CY) {
                 const int ly = q / CX, lx = q - ly * CX;
                 const int I = wrap_col((i0 >> 1) - 1 + lx, Cl.nx), J = clamp_row((j0 >> 1) - 1 + ly, Cl.ny);
-                cv[r] = Cl.u[(long long)J * Cl.pitch + I];
+                cv[r] = T(Cl.u[(long long)J * Cl.pitch + I]);
             }
         }
 #pragma unroll
@@ -337,7 +347,7 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
         if (q < G::HN) {
             const int ly = q / HX, lx = q - ly * HX;
             T u = uv[r];
-            if (PROLONG) u += prolong_tile<T, CX>(sc, i0, j0, lx, ly, Cl.ny, Cl.kappa);
+            if (PROLONG) u += prolong_tile<T, CX>(sc, i0, j0, lx, ly, Cl.ny, T(Cl.kappa));
             su[ly][lx] = u;
             sm[ly][lx] = mv[r];
         }
@@ -408,8 +418,8 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
 // iterate and mu with halo, forms the residual f - L u of its nodes in LDS and writes
 // the 32 x 8 coarse right-hand sides (average of the four children) and a zero coarse
 // correction.  Requires nx = 2 nxc and ny = 2 nyc.
-template <typename T, typename G, int MODE>
-__global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<T> Cl) {
+template <typename T, typename G, int MODE, typename TC>
+__global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
     constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT;
     __shared__ T su[HY][HX];
     __shared__ T sm[HY][HX];
@@ -454,9 +464,9 @@ __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLe
     const int I = (i0 >> 1) + cx, J = (j0 >> 1) + cy;
     if (I < Cl.nx && J < Cl.ny) {
         const long long k = (long long)J * Cl.pitch + I;
-        Cl.f[k] = T(0.25) * ((sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) +
-                             (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1]));
-        Cl.u[k] = T(0);
+        Cl.f[k] = TC(T(0.25) * ((sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) +
+                                (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1])));
+        Cl.u[k] = TC(0);
     }
 }
 
@@ -469,9 +479,9 @@ __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLe
 // the tile's halo is zero as well), writing the result to uout.  Same arithmetic as
 // k_mg_restrict_tile followed by k_mg_smooth_tile, one launch fewer.  Requires
 // F.nx = 2 C.nx and F.ny = 2 C.ny.
-template <typename T, int FMODE>
-__global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<T> C,
-                                                                     T* __restrict__ uout, int inner) {
+template <typename T, int FMODE, typename TC>
+__global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<TC> C,
+                                                                     TC* __restrict__ uout, int inner) {
     // fine part on the fine tile's 256 threads (loads staged in registers, issued
     // together); coarse smoothing by the first 64, one coarse node per colour each
     using G = CoarseTile;
@@ -480,14 +490,15 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
     constexpr int CPER = (G::HN + NT - 1) / NT;
     __shared__ T fu[FG::HY][FG::HX];
     __shared__ T fm[FG::HY][FG::HX];
-    __shared__ T su[G::HY][G::HX];
-    __shared__ T sm[G::HY][G::HX];
-    __shared__ T sf[SY][SX];
+    __shared__ TC su[G::HY][G::HX];
+    __shared__ TC sm[G::HY][G::HX];
+    __shared__ TC sf[SY][SX];
     const int I0 = blockIdx.x * SX, J0 = blockIdx.y * SY;  // coarse tile origin
     const int i0 = 2 * I0, j0 = 2 * J0;                    // fine tile origin
     const int tid = threadIdx.x;
     const int cy = tid / SX, cx = tid - cy * SX;  // this thread's coarse node
-    T uv[FG::HPER], mv[FG::HPER], fv[4], cm[CPER];
+    T uv[FG::HPER], mv[FG::HPER], fv[4];
+    TC cm[CPER];
     load_tile<T, FG>(F, F.u, i0, j0, uv, mv);
 #pragma unroll
     for (int d = 0; d < 4; ++d) {  // fine right-hand sides of the node's four children
@@ -515,7 +526,7 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
         const int q = tid + r * NT;
         if (q < G::HN) {
             sm[q / HX][q % HX] = cm[r];
-            su[q / HX][q % HX] = T(0);
+            su[q / HX][q % HX] = TC(0);
         }
     }
     __syncthreads();
@@ -534,7 +545,7 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
             }
             r[d] = v;
         }
-        const T fc = T(0.25) * ((r[0] + r[1]) + (r[2] + r[3]));
+        const TC fc = TC(T(0.25) * ((r[0] + r[1]) + (r[2] + r[3])));
         sf[cy][cx] = fc;
         const int I = I0 + cx, J = J0 + cy;
         if (I < C.nx && J < C.ny) C.f[(long long)J * C.pitch + I] = fc;
@@ -548,9 +559,9 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
             const int lx = 1 + 2 * tx + (c & 1), ly = 1 + 2 * ty + (c >> 1);
             const int i = I0 + lx - 1, j = J0 + ly - 1;
             if (smoother && i < C.nx && j < C.ny) {
-                const MgEval<T> e =
-                    tile_eval<T, HX>(su, sm, lx, ly, j == 0, j == C.ny - 1, C, sf[ly - 1][lx - 1], false);
-                const T old = su[ly][lx];
+                const MgEval<TC> e =
+                    tile_eval<TC, HX>(su, sm, lx, ly, j == 0, j == C.ny - 1, C, sf[ly - 1][lx - 1], false);
+                const TC old = su[ly][lx];
                 su[ly][lx] = (e.acc + e.cself * old - e.rhs) / (e.C + e.cself);
             }
             __syncthreads();
@@ -788,10 +799,10 @@ void launch_mg_restrict_mu(const T* muf, int pitchf, T* muc, int nxc, int nyc, i
     hipLaunchKernelGGL(k_mg_restrict_mu<T>, pgrid(nxc, nyc), dim3(PX, PY), 0, s, muf, pitchf, muc, nxc, nyc, pitchc);
 }
 
-template <typename T>
-void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const MuLevels<T>& C, hipStream_t s) {
+template <typename T, typename TC>
+void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const MuLevels<TC>& C, hipStream_t s) {
     const dim3 g((nxf + MU_TX - 1) / MU_TX, (nyf + MU_TY - 1) / MU_TY);
-    hipLaunchKernelGGL(k_mg_restrict_mu4<T>, g, dim3(MU_TX * MU_TY / 4), 0, s, muf, pitchf, nxf, nyf, C);
+    hipLaunchKernelGGL((k_mg_restrict_mu4<T, TC>), g, dim3(MU_TX * MU_TY / 4), 0, s, muf, pitchf, nxf, nyf, C);
 }
 
 template <typename T>
@@ -799,13 +810,13 @@ void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hip
     hipLaunchKernelGGL(k_mg_restrict_residual<T>, pgrid(C.nx, C.ny), dim3(PX, PY), 0, s, F, C);
 }
 
-template <typename T, typename G>
-void launch_smooth_geom(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
+template <typename T, typename G, typename TC>
+void launch_smooth_geom(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<TC>* prolong_from, int mode,
                         unsigned long long* res, int inner, hipStream_t s) {
     const dim3 g((L.nx + G::SX - 1) / G::SX, (L.ny + G::SY - 1) / G::SY);
-    const PotLevel<T> Cl = prolong_from ? *prolong_from : PotLevel<T>{};
+    const PotLevel<TC> Cl = prolong_from ? *prolong_from : PotLevel<TC>{};
 #define FCD_TILE_LAUNCH(P, M) \
-    hipLaunchKernelGGL((k_mg_smooth_tile<T, G, P, M>), g, dim3(G::NT), 0, s, L, uin, uout, Cl, res, inner)
+    hipLaunchKernelGGL((k_mg_smooth_tile<T, G, P, M, TC>), g, dim3(G::NT), 0, s, L, uin, uout, Cl, res, inner)
     if (prolong_from) {
         if (mode == 0) FCD_TILE_LAUNCH(true, 0);
         else if (mode == 1) FCD_TILE_LAUNCH(true, 1);
@@ -819,40 +830,40 @@ void launch_smooth_geom(const PotLevel<T>& L, const T* uin, T* uout, const PotLe
 }
 
 // Finest level (modes 1, 2): 64 x 16 tiles; coarser levels (mode 0): 32 x 8 tiles.
-template <typename T>
-void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<T>* prolong_from, int mode,
+template <typename T, typename TC>
+void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<TC>* prolong_from, int mode,
                            unsigned long long* res, int inner, hipStream_t s) {
     if (res) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, res, 2LL, 0ULL);
     if (mode == 0)
-        launch_smooth_geom<T, CoarseTile>(L, uin, uout, prolong_from, mode, res, inner, s);
+        launch_smooth_geom<T, CoarseTile, TC>(L, uin, uout, prolong_from, mode, res, inner, s);
     else
-        launch_smooth_geom<T, FineTile>(L, uin, uout, prolong_from, mode, res, inner, s);
+        launch_smooth_geom<T, FineTile, TC>(L, uin, uout, prolong_from, mode, res, inner, s);
 }
 
-template <typename T>
-void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<T>& C, int mode, hipStream_t s) {
+template <typename T, typename TC>
+void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<TC>& C, int mode, hipStream_t s) {
     if (mode == 0) {
         const dim3 g((F.nx + CoarseTile::SX - 1) / CoarseTile::SX, (F.ny + CoarseTile::SY - 1) / CoarseTile::SY);
-        hipLaunchKernelGGL((k_mg_restrict_tile<T, CoarseTile, 0>), g, dim3(CoarseTile::NT), 0, s, F, C);
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, CoarseTile, 0, TC>), g, dim3(CoarseTile::NT), 0, s, F, C);
         return;
     }
     const dim3 g((F.nx + FineTile::SX - 1) / FineTile::SX, (F.ny + FineTile::SY - 1) / FineTile::SY);
     if (mode == 1)
-        hipLaunchKernelGGL((k_mg_restrict_tile<T, FineTile, 1>), g, dim3(FineTile::NT), 0, s, F, C);
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, FineTile, 1, TC>), g, dim3(FineTile::NT), 0, s, F, C);
     else
-        hipLaunchKernelGGL((k_mg_restrict_tile<T, FineTile, 2>), g, dim3(FineTile::NT), 0, s, F, C);
+        hipLaunchKernelGGL((k_mg_restrict_tile<T, FineTile, 2, TC>), g, dim3(FineTile::NT), 0, s, F, C);
 }
 
-template <typename T>
-void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<T>& C, int fmode, T* uout, int inner,
+template <typename T, typename TC>
+void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<TC>& C, int fmode, TC* uout, int inner,
                                hipStream_t s) {
     const dim3 g((C.nx + CoarseTile::SX - 1) / CoarseTile::SX, (C.ny + CoarseTile::SY - 1) / CoarseTile::SY);
     if (fmode == 0)
-        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 0>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
+        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 0, TC>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
     else if (fmode == 1)
-        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 1>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
+        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 1, TC>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
     else
-        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 2>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
+        hipLaunchKernelGGL((k_mg_restrict_smooth<T, 2, TC>), g, dim3(FineTile::NT), 0, s, F, C, uout, inner);
 }
 
 template <typename T>
@@ -876,17 +887,24 @@ void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, in
     template void launch_pot_sweep<T>(const PotLevel<T>&, T, hipStream_t);                                \
     template void launch_pot_residual<T>(const PotLevel<T>&, unsigned long long*, hipStream_t);           \
     template void launch_mg_restrict_mu<T>(const T*, int, T*, int, int, int, hipStream_t);                \
-    template void launch_mg_restrict_mu4<T>(const T*, int, int, int, const MuLevels<T>&, hipStream_t);    \
     template void launch_mg_restrict_residual<T>(const PotLevel<T>&, const PotLevel<T>&, hipStream_t);    \
-    template void launch_mg_smooth_tile<T>(const PotLevel<T>&, const T*, T*, const PotLevel<T>*, int,         \
-                                           unsigned long long*, int, hipStream_t);                            \
-    template void launch_mg_restrict_tile<T>(const PotLevel<T>&, const PotLevel<T>&, int, hipStream_t);       \
-    template void launch_mg_restrict_smooth<T>(const PotLevel<T>&, const PotLevel<T>&, int, T*, int, hipStream_t); \
     template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
     template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \
     template void launch_psi_history<T>(T*, T*, T*, int, int, int, int, hipStream_t);
 
+// Multigrid transfer and smoothing kernels between a level of type T and coarse levels of
+// type TC (the coarse levels are FP32 under an FP64 finest level).
+#define FCD_MG_INSTANTIATE(T, TC)                                                                             \
+    template void launch_mg_restrict_mu4<T, TC>(const T*, int, int, int, const MuLevels<TC>&, hipStream_t);   \
+    template void launch_mg_smooth_tile<T, TC>(const PotLevel<T>&, const T*, T*, const PotLevel<TC>*, int,    \
+                                               unsigned long long*, int, hipStream_t);                        \
+    template void launch_mg_restrict_tile<T, TC>(const PotLevel<T>&, const PotLevel<TC>&, int, hipStream_t);  \
+    template void launch_mg_restrict_smooth<T, TC>(const PotLevel<T>&, const PotLevel<TC>&, int, TC*, int,    \
+                                                   hipStream_t);
+
 FCD_POT_INSTANTIATE(double)
 FCD_POT_INSTANTIATE(float)
+FCD_MG_INSTANTIATE(double, float)
+FCD_MG_INSTANTIATE(float, float)
 
 }  // namespace fcd
