@@ -128,15 +128,32 @@ __global__ void __launch_bounds__(256) kb_sor_fused(const BatchInst<T>* __restri
     T* __restrict__ uout = parity ? L.u : B.alt;
     const int lt = blockIdx.x - B.stile0, ty = lt / B.stiles_x, tx = lt - ty * B.stiles_x;
     const int i0 = tx * FUSED_X, j0 = ty * FUSED_Y;
-    for (int q = threadIdx.x; q < HN; q += NT) {
-        const int ly = q / HX, lx = q - ly * HX;
-        const int i = fs_wrap(i0 - H + lx, L.nx);
-        int j = j0 - H + ly;
-        j = j < 0 ? 0 : (j >= L.ny ? L.ny - 1 : j);
-        const long long g = (long long)j * L.pitch + i;
-        su[q] = uin[g];
-        sm[q] = L.mu[g];
-        if (HF) sf[HF ? q : 0] = L.f[g];
+    // all loads into registers first, then the LDS stores, so that the loads of a thread
+    // are in flight together
+    constexpr int LPER = (HN + NT - 1) / NT;
+    T uv[LPER], mv[LPER], fv[HF ? LPER : 1];
+#pragma unroll
+    for (int r = 0; r < LPER; ++r) {
+        const int q = threadIdx.x + r * NT;
+        if (q < HN) {
+            const int ly = q / HX, lx = q - ly * HX;
+            const int i = fs_wrap(i0 - H + lx, L.nx);
+            int j = j0 - H + ly;
+            j = j < 0 ? 0 : (j >= L.ny ? L.ny - 1 : j);
+            const long long g = (long long)j * L.pitch + i;
+            uv[r] = uin[g];
+            mv[r] = L.mu[g];
+            if (HF) fv[HF ? r : 0] = L.f[g];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < LPER; ++r) {
+        const int q = threadIdx.x + r * NT;
+        if (q < HN) {
+            su[q] = uv[r];
+            sm[q] = mv[r];
+            if (HF) sf[HF ? q : 0] = fv[HF ? r : 0];
+        }
     }
     __syncthreads();
     const T omega = B.omega;
