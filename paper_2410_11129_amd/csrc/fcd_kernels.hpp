@@ -20,13 +20,9 @@ template <typename T>
 void launch_pot_sweep(const PotLevel<T>& L, T omega, hipStream_t s);
 template <typename T>
 void launch_pot_residual(const PotLevel<T>& L, unsigned long long* out, hipStream_t s);
-template <typename T>
-void launch_mg_restrict_mu(const T* muf, int pitchf, T* muc, int nxc, int nyc, int pitchc, hipStream_t s);
 // Levels C.mu[0 .. C.n) (n <= 4, each half the previous) from the finer mu plane muf.
 template <typename T, typename TC>
 void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const MuLevels<TC>& C, hipStream_t s);
-template <typename T>
-void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hipStream_t s);
 // One tile-smoother sweep uin -> uout (never the same buffer); prolong_from != nullptr
 // adds the prolongation of that coarse level's correction first.  mode 0: coarse level
 // (L.f), 1: finest level with the right-hand side from H0, 2: finest level with L.f.

@@ -68,20 +68,11 @@ __global__ void __launch_bounds__(RES_T) k_pot_residual(PotLevel<T> L, unsigned 
     }
 }
 
-// Coarse mu: average of the four fine nodes.
-template <typename T>
-__global__ void __launch_bounds__(PX* PY) k_mg_restrict_mu(const T* __restrict__ muf, int pitchf,
-                                                           T* __restrict__ muc, int nxc, int nyc, int pitchc) {
-    const int I = blockIdx.x * PX + threadIdx.x, J = blockIdx.y * PY + threadIdx.y;
-    if (I >= nxc || J >= nyc) return;
-    const long long r0 = (long long)(2 * J) * pitchf + 2 * I, r1 = r0 + pitchf;
-    muc[(long long)J * pitchc + I] = T(0.25) * ((muf[r0] + muf[r0 + 1]) + (muf[r1] + muf[r1 + 1]));
-}
-
-// Up to four coarse mu levels in one launch: a block owns a 64 x 16 tile of the finer
-// level, which contains the children of every coarse node of the next four levels that
-// lies over it, and averages level by level in LDS (same expression as k_mg_restrict_mu,
-// so the values are bitwise those of four separate launches).
+// Coarse mu: the average of the four fine nodes under each coarse node, for up to four
+// levels in one launch.  A block owns a 64 x 16 tile of the finer level, which contains
+// the children of every coarse node of the next four levels that lies over it, and
+// averages level by level in LDS; the first level is averaged in the finer level's type
+// and stored in the coarse type.
 constexpr int MU_TX = 64, MU_TY = 16;
 
 template <typename T, typename TC>
@@ -133,25 +124,6 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* _
         dst = tmp;
         sx = cx;
     }
-}
-
-// Coarse right-hand side = average of the four fine residuals; coarse correction = 0.
-template <typename T>
-__global__ void __launch_bounds__(PX* PY) k_mg_restrict_residual(PotLevel<T> F, PotLevel<T> Cl) {
-    const int I = blockIdx.x * PX + threadIdx.x, J = blockIdx.y * PY + threadIdx.y;
-    if (I >= Cl.nx || J >= Cl.ny) return;
-    T s = T(0);
-#pragma unroll
-    for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-        for (int di = 0; di < 2; ++di) {
-            const int i = 2 * I + di, j = 2 * J + dj;
-            const MgEval<T> r = mg_eval(F, i, j);
-            s += r.rhs - (r.acc - r.C * F.u[(long long)j * F.pitch + i]);
-        }
-    const long long k = (long long)J * Cl.pitch + I;
-    Cl.f[k] = T(0.25) * s;
-    Cl.u[k] = T(0);
 }
 
 // Bilinear interpolation of the coarse correction at fine node (i, j): weights 9/16,
@@ -794,20 +766,10 @@ void launch_pot_residual(const PotLevel<T>& L, unsigned long long* out, hipStrea
     hipLaunchKernelGGL(k_pot_residual<T>, dim3((unsigned)blocks), dim3(RES_T), 0, s, L, out);
 }
 
-template <typename T>
-void launch_mg_restrict_mu(const T* muf, int pitchf, T* muc, int nxc, int nyc, int pitchc, hipStream_t s) {
-    hipLaunchKernelGGL(k_mg_restrict_mu<T>, pgrid(nxc, nyc), dim3(PX, PY), 0, s, muf, pitchf, muc, nxc, nyc, pitchc);
-}
-
 template <typename T, typename TC>
 void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const MuLevels<TC>& C, hipStream_t s) {
     const dim3 g((nxf + MU_TX - 1) / MU_TX, (nyf + MU_TY - 1) / MU_TY);
     hipLaunchKernelGGL((k_mg_restrict_mu4<T, TC>), g, dim3(MU_TX * MU_TY / 4), 0, s, muf, pitchf, nxf, nyf, C);
-}
-
-template <typename T>
-void launch_mg_restrict_residual(const PotLevel<T>& F, const PotLevel<T>& C, hipStream_t s) {
-    hipLaunchKernelGGL(k_mg_restrict_residual<T>, pgrid(C.nx, C.ny), dim3(PX, PY), 0, s, F, C);
 }
 
 template <typename T, typename G, typename TC>
@@ -886,8 +848,6 @@ void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, in
 #define FCD_POT_INSTANTIATE(T)                                                                            \
     template void launch_pot_sweep<T>(const PotLevel<T>&, T, hipStream_t);                                \
     template void launch_pot_residual<T>(const PotLevel<T>&, unsigned long long*, hipStream_t);           \
-    template void launch_mg_restrict_mu<T>(const T*, int, T*, int, int, int, hipStream_t);                \
-    template void launch_mg_restrict_residual<T>(const PotLevel<T>&, const PotLevel<T>&, hipStream_t);    \
     template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
     template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \
     template void launch_psi_history<T>(T*, T*, T*, int, int, int, int, hipStream_t);
