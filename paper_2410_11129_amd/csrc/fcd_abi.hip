@@ -51,12 +51,13 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // precisions: they only compute corrections, each cycle's residual is formed on level 0
 // in the lattice's precision, so the solve still reaches that precision's tolerance
 // (mixed-precision multigrid), while the latency-bound coarse kernels run FP32 arithmetic
-// on half the bytes.  The coarsest levels whose u, f, mu and a Jacobi ping-pong array fit
-// together in TAIL_LDS_MAX bytes form the tail, solved in LDS by one block; every level
-// above the tail has a second plane for the tile smoother's ping-pong.
+// on half the bytes.  The coarsest levels whose LDS arrays (u, f, mu, a Jacobi ping-pong
+// array and the precomputed couplings: MG_TAIL_ARRAYS per node) fit together in
+// TAIL_LDS_MAX bytes form the tail, solved in LDS by one block; every level above the tail
+// has a second plane for the tile smoother's ping-pong.
 using CT = float;  // element type of the coarse levels
 constexpr int MAX_LEVELS = 16;
-constexpr size_t TAIL_LDS_MAX = 65536;
+constexpr size_t TAIL_LDS_MAX = 98304;  // of the 160 KB of LDS a gfx950 workgroup may use
 // Tile sweeps per smoothing launch on the levels between the finest and the tail.
 constexpr int MG_COARSE_INNER = 2;
 
@@ -89,7 +90,7 @@ MgPlan make_plan(const fcd_lattice& l) {
     p.tail = p.levels;
     size_t tail_bytes = 0;
     for (int L = p.levels - 1; L >= 1 && p.levels - L <= fcd::MG_MAX_TAIL; --L) {
-        const size_t b = 4 * (size_t)p.nx[L] * p.ny[L] * sizeof(CT);
+        const size_t b = fcd::MG_TAIL_ARRAYS * (size_t)p.nx[L] * p.ny[L] * sizeof(CT);
         if (tail_bytes + b > TAIL_LDS_MAX) break;
         tail_bytes += b;
         p.tail = L;

@@ -42,6 +42,9 @@ void launch_mg_restrict_tile(const PotLevel<T>& F, const PotLevel<TC>& C, int mo
 template <typename T, typename TC>
 void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<TC>& C, int fmode, TC* uout, int inner,
                                hipStream_t s);
+// Arrays per node of a multigrid tail level in LDS: iterate, right-hand side, mu, a
+// ping-pong array, eight couplings, the diagonal and its reciprocal.
+constexpr int MG_TAIL_ARRAYS = 14;
 template <typename T>
 size_t mg_tail_lds_bytes(const MgTail<T>& tl);
 template <typename T>

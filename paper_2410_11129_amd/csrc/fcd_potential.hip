@@ -555,30 +555,101 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
 // ---------------------------------------------------------------------------------
 constexpr int TAIL_T = 512;
 
+// One tail level in LDS: iterate, right-hand side, mu, a ping-pong array and the
+// operator's couplings, set up once per launch from mu.  The couplings absorb the wall
+// ghost rule: a ghost row holds -kappa times the edge row, so the ghost image of the node
+// itself moves into the diagonal d and those of its row neighbours into their couplings,
+// and the couplings to the ghost row become zero.  Then L u = acc - d u with
+// acc = sum c_a u(x + e_a) over in-channel neighbours only (rows clamped; a clamped row
+// only ever meets a zero coupling), and a Gauss-Seidel / Jacobi value is (acc - f) / d.
 template <typename T>
-__device__ __forceinline__ PotLevel<T> tail_view(const MgTail<T>& tl, T* base, int k, T** alt) {
+struct TailLevel {
+    int nx, ny;
+    T *u, *f, *mu, *alt;
+    T* c[8];  // couplings to e, w, n, s, ne, nw, sw, se
+    T *d, *rd;
+};
+
+template <typename T>
+__device__ __forceinline__ TailLevel<T> tail_view(const MgTail<T>& tl, T* base, int k) {
     long long off = 0;
-    for (int m = 0; m < k; ++m) off += 4LL * tl.lv[m].nx * tl.lv[m].ny;
-    PotLevel<T> S = tl.lv[k];
+    for (int m = 0; m < k; ++m) off += (long long)MG_TAIL_ARRAYS * tl.lv[m].nx * tl.lv[m].ny;
+    TailLevel<T> S;
+    S.nx = tl.lv[k].nx;
+    S.ny = tl.lv[k].ny;
     const long long n = (long long)S.nx * S.ny;
-    S.u = base + off;
-    S.f = base + off + n;
-    S.mu = base + off + 2 * n;
-    *alt = base + off + 3 * n;
-    S.pitch = S.nx;
-    S.H0x = S.H0y = T(0);
+    T* p = base + off;
+    S.u = p;
+    S.f = p + n;
+    S.mu = p + 2 * n;
+    S.alt = p + 3 * n;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) S.c[a] = p + (4 + a) * n;
+    S.d = p + 12 * n;
+    S.rd = p + 13 * n;
     return S;
 }
 
+// Couplings of node t = (i, j) from mu (Eq. 35 weights of the flux form, as mg_eval_nb).
 template <typename T>
-__device__ __forceinline__ void tail_sor(const PotLevel<T>& S, int sweeps, T omega) {
+__device__ __forceinline__ void tail_setup_node(const TailLevel<T>& S, const PotLevel<T>& G, int t) {
+    const int nx = S.nx, j = t / nx, i = t - j * nx;
+    const int e = i + 1 == nx ? t + 1 - nx : t + 1, w = i == 0 ? t - 1 + nx : t - 1;
+    const int dn = j + 1 == S.ny ? 0 : nx, ds = j == 0 ? 0 : -nx;  // mirrored mu beyond the walls
+    const T* m = S.mu;
+    const T mc = m[t];
+    const T a = G.inv_h2 * (T(1) / T(3)), q = G.inv_h2 * (T(1) / T(12)), k = G.kappa;
+    T ce = a * (mc + m[e]), cw = a * (mc + m[w]), cn = a * (mc + m[t + dn]), cs = a * (mc + m[t + ds]);
+    T cne = q * (mc + m[e + dn]), cnw = q * (mc + m[w + dn]), csw = q * (mc + m[w + ds]), cse = q * (mc + m[e + ds]);
+    const T C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
+    T d = C;
+    if (j == 0) {  // ghost row below: -k times row 0
+        d += k * cs;
+        ce -= k * cse;
+        cw -= k * csw;
+        cs = csw = cse = T(0);
+    }
+    if (j + 1 == S.ny) {  // ghost row above
+        d += k * cn;
+        ce -= k * cne;
+        cw -= k * cnw;
+        cn = cne = cnw = T(0);
+    }
+    S.c[0][t] = ce;
+    S.c[1][t] = cw;
+    S.c[2][t] = cn;
+    S.c[3][t] = cs;
+    S.c[4][t] = cne;
+    S.c[5][t] = cnw;
+    S.c[6][t] = csw;
+    S.c[7][t] = cse;
+    S.d[t] = d;
+    S.rd[t] = T(1) / d;
+}
+
+template <typename T>
+__device__ __forceinline__ T tail_acc(const TailLevel<T>& S, const T* __restrict__ u, int t) {
+    const int nx = S.nx, j = t / nx, i = t - j * nx;
+    const int e = i + 1 == nx ? t + 1 - nx : t + 1, w = i == 0 ? t - 1 + nx : t - 1;
+    const int dn = j + 1 == S.ny ? 0 : nx, ds = j == 0 ? 0 : -nx;
+    return ((S.c[0][t] * u[e] + S.c[1][t] * u[w]) + (S.c[2][t] * u[t + dn] + S.c[3][t] * u[t + ds])) +
+           ((S.c[4][t] * u[e + dn] + S.c[6][t] * u[w + ds]) + (S.c[5][t] * u[w + dn] + S.c[7][t] * u[e + ds]));
+}
+
+// Coarsest level with more than four rows: four-colour SOR, factor omega.
+template <typename T>
+__device__ __forceinline__ void tail_sor(const TailLevel<T>& S, int sweeps, T omega) {
     const int hx = (S.nx + 1) / 2, hy = (S.ny + 1) / 2;
     for (int it = 0; it < sweeps; ++it)
         for (int colour = 0; colour < 4; ++colour) {
-            for (int t = threadIdx.x; t < hx * hy; t += TAIL_T) {
-                const int tj = t / hx, ti = t - tj * hx;
+            for (int q = threadIdx.x; q < hx * hy; q += TAIL_T) {
+                const int tj = q / hx, ti = q - tj * hx;
                 const int i = 2 * ti + (colour & 1), j = 2 * tj + (colour >> 1);
-                if (i < S.nx && j < S.ny) relax_node(S, i, j, omega);
+                if (i < S.nx && j < S.ny) {
+                    const int t = j * S.nx + i;
+                    const T old = S.u[t];
+                    S.u[t] = old + omega * ((tail_acc(S, S.u, t) - S.f[t]) * S.rd[t] - old);
+                }
             }
             __syncthreads();
         }
@@ -586,18 +657,15 @@ __device__ __forceinline__ void tail_sor(const PotLevel<T>& S, int sweeps, T ome
 
 // Damped Jacobi, an even number of sweeps: u -> alt -> u -> ...
 template <typename T>
-__device__ __forceinline__ void tail_jacobi(PotLevel<T> S, T* alt, int sweeps) {
+__device__ __forceinline__ void tail_jacobi(const TailLevel<T>& S, int sweeps) {
     const T w = T(0.8);
     T* a = S.u;
-    T* b = alt;
+    T* b = S.alt;
     const int n = S.nx * S.ny;
     for (int it = 0; it < sweeps; ++it) {
-        S.u = a;
         for (int t = threadIdx.x; t < n; t += TAIL_T) {
-            const int j = t / S.nx, i = t - j * S.nx;
-            const MgEval<T> r = mg_eval(S, i, j);
             const T old = a[t];
-            b[t] = old + w * ((r.acc + r.cself * old - r.rhs) / (r.C + r.cself) - old);
+            b[t] = old + w * ((tail_acc(S, a, t) - S.f[t]) * S.rd[t] - old);
         }
         __syncthreads();
         T* c = a;
@@ -606,7 +674,7 @@ __device__ __forceinline__ void tail_jacobi(PotLevel<T> S, T* alt, int sweeps) {
     }
 }
 
-// Largest tail level (64 KB of four arrays in FP32) and the loads per thread it takes.
+// Largest tail level and the loads per thread it takes.
 constexpr int TAIL_MAXN = 4096;
 constexpr int TAIL_LPER = TAIL_MAXN / TAIL_T;
 
@@ -614,7 +682,6 @@ template <typename T>
 __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* base = reinterpret_cast<T*>(lds_raw);
-    T* alt;
     const int tid = threadIdx.x;
     // every tail level's mu and the top level's right-hand side, all loads issued before
     // any LDS store (one memory latency instead of one per level)
@@ -649,13 +716,13 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         }
     }
     {
-        const PotLevel<T> S = tail_view(tl, base, 0, &alt);
+        const TailLevel<T> S = tail_view(tl, base, 0);
         const int n = S.nx * S.ny;
 #pragma unroll
         for (int r = 0; r < TAIL_LPER; ++r) {
             const int t = tid + r * TAIL_T;
             if (t < n) {
-                const_cast<T*>(S.mu)[t] = m0[r];
+                S.mu[t] = m0[r];
                 S.f[t] = f0[r];
                 S.u[t] = T(0);
             }
@@ -664,34 +731,34 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
 #pragma unroll
     for (int k = 1; k < MG_MAX_TAIL; ++k) {
         if (k < tl.n) {
-            const PotLevel<T> S = tail_view(tl, base, k, &alt);
+            const TailLevel<T> S = tail_view(tl, base, k);
             const int n = S.nx * S.ny;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int t = tid + r * TAIL_T;
-                if (t < n) const_cast<T*>(S.mu)[t] = mk[k - 1][r];
+                if (t < n) S.mu[t] = mk[k - 1][r];
             }
         }
     }
     __syncthreads();
+    for (int k = 0; k < tl.n; ++k) {
+        const TailLevel<T> S = tail_view(tl, base, k);
+        for (int t = tid; t < S.nx * S.ny; t += TAIL_T) tail_setup_node(S, tl.lv[k], t);
+    }
+    __syncthreads();
     const int sw = 2 * ((tl.nu1 + 1) / 2);  // even
     for (int k = 0; k + 1 < tl.n; ++k) {
-        T* altc;
-        const PotLevel<T> F = tail_view(tl, base, k, &alt), Cc = tail_view(tl, base, k + 1, &altc);
-        tail_jacobi(F, alt, sw);
-        // fine residuals into the (free) ping-pong array, then their four-child sums in
-        // the fixed order (0,0), (1,0), (0,1), (1,1)
+        const TailLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
+        tail_jacobi(F, sw);
+        // fine residuals f - L u into the (free) ping-pong array, then their four-child
+        // sums in the fixed order (0,0), (1,0), (0,1), (1,1)
         const int nf = F.nx * F.ny;
-        for (int t = tid; t < nf; t += TAIL_T) {
-            const int j = t / F.nx, i = t - j * F.nx;
-            const MgEval<T> r = mg_eval(F, i, j);
-            alt[t] = r.rhs - (r.acc - r.C * F.u[t]);
-        }
+        for (int t = tid; t < nf; t += TAIL_T) F.alt[t] = F.f[t] - (tail_acc(F, F.u, t) - F.d[t] * F.u[t]);
         __syncthreads();
         const int n = Cc.nx * Cc.ny;
         for (int t = tid; t < n; t += TAIL_T) {
             const int J = t / Cc.nx, I = t - J * Cc.nx;
-            const T* r0 = alt + (2 * J) * F.nx + 2 * I;
+            const T* r0 = F.alt + (2 * J) * F.nx + 2 * I;
             T s = T(0);
             s += r0[0];
             s += r0[1];
@@ -703,25 +770,27 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         __syncthreads();
     }
     {
-        const PotLevel<T> S = tail_view(tl, base, tl.n - 1, &alt);
+        const TailLevel<T> S = tail_view(tl, base, tl.n - 1);
         if (S.ny <= 4)
-            tail_jacobi(S, alt, 2 * tl.coarse_sweeps);
+            tail_jacobi(S, 2 * tl.coarse_sweeps);
         else
             tail_sor(S, tl.coarse_sweeps, tl.omega);
     }
     for (int k = tl.n - 2; k >= 0; --k) {
-        T* altc;
-        const PotLevel<T> F = tail_view(tl, base, k, &alt), Cc = tail_view(tl, base, k + 1, &altc);
+        const TailLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
+        PotLevel<T> Cp = tl.lv[k + 1];  // the coarse correction as a level (for prolong_at)
+        Cp.u = Cc.u;
+        Cp.pitch = Cc.nx;
         const int n = F.nx * F.ny;
         for (int t = tid; t < n; t += TAIL_T) {
             const int j = t / F.nx, i = t - j * F.nx;
-            F.u[t] += prolong_at(Cc, i, j);
+            F.u[t] += prolong_at(Cp, i, j);
         }
         __syncthreads();
-        tail_jacobi(F, alt, sw);
+        tail_jacobi(F, sw);
     }
     const PotLevel<T> G = tl.lv[0];
-    const PotLevel<T> S = tail_view(tl, base, 0, &alt);
+    const TailLevel<T> S = tail_view(tl, base, 0);
     for (int t = tid; t < S.nx * S.ny; t += TAIL_T) {
         const int j = t / S.nx, i = t - j * S.nx;
         G.u[(long long)j * G.pitch + i] = S.u[t];
@@ -831,7 +900,7 @@ void launch_mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<TC>& C, int 
 template <typename T>
 size_t mg_tail_lds_bytes(const MgTail<T>& tl) {
     size_t n = 0;
-    for (int k = 0; k < tl.n; ++k) n += 4 * (size_t)tl.lv[k].nx * tl.lv[k].ny;
+    for (int k = 0; k < tl.n; ++k) n += (size_t)MG_TAIL_ARRAYS * tl.lv[k].nx * tl.lv[k].ny;
     return n * sizeof(T);
 }
 
