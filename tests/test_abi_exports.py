@@ -85,3 +85,22 @@ def test_bad_params_and_null_buffers_rejected():
     st = fcd.lib().fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h))
     assert st == fcd.FCD_ERR_ARG and "gamma" in fcd.fcd_last_error()
     assert fcd.lib().fcd_step(None, 1) == fcd.FCD_ERR_ARG
+
+
+def test_batch_schedule_calls_and_warm_start_order_validated_on_host():
+    """Null batches and out-of-range settings are rejected before any device work."""
+    L = fcd.lib()
+    choice = (C.c_int32 * 3)()
+    scales = (C.c_double * 2)(1.0, 0.9)
+    out = (C.c_double * 4)()
+    assert L.fcd_batch_set_schedule(None, 4, 8, 2) == fcd.FCD_ERR_ARG
+    assert L.fcd_batch_autotune(None, 1, choice) == fcd.FCD_ERR_ARG
+    assert L.fcd_batch_tune_omega(None, 4, 2, scales, out) == fcd.FCD_ERR_ARG
+    lat = fcd.fcd_lattice(200, 50, fcd.FCD_FP64, 256)
+    buf = fcd.fcd_buffers()
+    buf.dist[0], buf.dist[1], buf.phi, buf.psi, buf.scratch = 256, 512, 768, 1024, 1280
+    p = good_params()
+    p.pot_extrapolate = 3
+    h = C.c_void_p()
+    st = L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h))
+    assert st == fcd.FCD_ERR_ARG and "pot_extrapolate" in fcd.fcd_last_error()
