@@ -173,10 +173,11 @@ def test_no_field_gives_zero_potential():
 
 
 @pytest.mark.parametrize("nx,ny,solver", [(4, 2, "sor"), (6, 3, "sor"), (130, 5, "sor"), (4, 2, "mg"),
-                                          (130, 5, "mg"), (256, 96, "mg"), (200, 97, "mg")])
+                                          (130, 5, "mg"), (256, 96, "mg"), (200, 97, "mg"), (320, 80, "mg")])
 def test_degenerate_lattices(nx, ny, solver):
-    """Smallest lattices, odd ny (no coarsening possible) and a multigrid hierarchy that
-    stops on an odd coarse level (96 -> 48 -> 24 -> ... ) against the oracle."""
+    """Smallest lattices, odd ny (no coarsening possible), a multigrid hierarchy that
+    stops on an odd coarse level (96 -> 48 -> 24 -> ... ) and one whose coarsest level has
+    five rows (80 -> ... -> 5: the LDS tail ends in SOR sweeps) against the oracle."""
     w = ragged_workload(nx=nx, ny=ny, drive_G=channel_drive(0.01, 1.0, 0.8, ny))
     say(f"case degenerate {nx}x{ny} solver={solver}")
     fields = random_phase_fields(nx, ny, seed=15)
