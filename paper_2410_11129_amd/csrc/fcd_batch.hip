@@ -82,32 +82,71 @@ __device__ __forceinline__ int fs_wrap(int i, int nx) {
     return i;
 }
 
+// LDS layout of a fused-sweep tile: the even and odd columns of every row are stored in
+// two separate planes (node (lx, ly) at plane lx & 1, row ly, word lx >> 1), so the
+// same-colour nodes of neighbouring lanes, and each of their neighbours, are consecutive
+// words; the second plane starts 16 banks after the first, so a row read across both
+// parities is conflict-free as well.
+template <int NS>
+struct FusedLds {
+    static constexpr int H = 4 * NS + 1, HX = FUSED_X + 2 * H, HY = FUSED_Y + 2 * H, HXH = HX / 2;
+    static constexpr int PS0 = HY * HXH, PS = PS0 + (48 - PS0 % 32) % 32, N = 2 * PS;
+    static_assert(HX % 2 == 0, "even halo row");
+    static __device__ __forceinline__ int at(int lx, int ly) { return (lx & 1) * PS + ly * HXH + (lx >> 1); }
+};
+
+// The operator at a staged node: c its word, o the word of its east neighbour (the west
+// one is o - 1, in the same plane), row the words per row; rows beyond the walls read
+// the edge row itself, as the clamped global loads do.
 template <typename T, bool HF>
-__device__ __forceinline__ MgEval<T> fs_eval(const PotLevel<T>& L, const T* su, const T* sm, const T* sf, int hx,
-                                             int lx, int ly, int j) {
-    // rows beyond the walls read the edge row itself, as the clamped global loads do
-    const int c = ly * hx + lx;
-    const int s = j == 0 ? c : c - hx, n = j == L.ny - 1 ? c : c + hx;
+__device__ __forceinline__ MgEval<T> fs_eval(const PotLevel<T>& L, const T* su, const T* sm, const T* sf, int c,
+                                             int o, int row, int j) {
+    const int dn = j == L.ny - 1 ? 0 : row, ds = j == 0 ? 0 : -row;
     Nb9<T> m, u;
     m.c = sm[c];
-    m.e = sm[c + 1];
-    m.w = sm[c - 1];
-    m.n = sm[n];
-    m.s = sm[s];
-    m.ne = sm[n + 1];
-    m.nw = sm[n - 1];
-    m.sw = sm[s - 1];
-    m.se = sm[s + 1];
+    m.e = sm[o];
+    m.w = sm[o - 1];
+    m.n = sm[c + dn];
+    m.s = sm[c + ds];
+    m.ne = sm[o + dn];
+    m.nw = sm[o - 1 + dn];
+    m.sw = sm[o - 1 + ds];
+    m.se = sm[o + ds];
     u.c = su[c];
-    u.e = su[c + 1];
-    u.w = su[c - 1];
-    u.n = su[n];
-    u.s = su[s];
-    u.ne = su[n + 1];
-    u.nw = su[n - 1];
-    u.sw = su[s - 1];
-    u.se = su[s + 1];
+    u.e = su[o];
+    u.w = su[o - 1];
+    u.n = su[c + dn];
+    u.s = su[c + ds];
+    u.ne = su[o + dn];
+    u.nw = su[o - 1 + dn];
+    u.sw = su[o - 1 + ds];
+    u.se = su[o + ds];
     return mg_eval_nb(L, m, u, j, HF ? sf[c] : T(0));
+}
+
+// Colour phase P of the fused sweeps: colour (cx, cy) of global parity (local column lx
+// has the parity of lx + H, since the tile origin is even), nodes with lx in
+// [H - R, H + 64 + R), ly likewise, R = 4 NS - P; the phase's nodes are dealt to the
+// block's threads row-major, so few lanes idle.
+template <typename T, int NS, bool HF, int P>
+__device__ __forceinline__ void fs_phase(const PotLevel<T>& L, T* su, const T* sm, const T* sf, int j0, T omega) {
+    using F = FusedLds<NS>;
+    constexpr int H = F::H, R = 4 * NS - P;
+    constexpr int px = ((P & 1) + H) & 1, py = (((P >> 1) & 1) + H) & 1;
+    constexpr int a0 = (H - R - px + 1) >> 1, na = ((H + FUSED_X + R - px + 1) >> 1) - a0;
+    constexpr int b0 = (H - R - py + 1) >> 1, nb = ((H + FUSED_Y + R - py + 1) >> 1) - b0;
+    for (int q = threadIdx.x; q < na * nb; q += 256) {
+        const int bq = q / na, aq = q - bq * na;
+        const int ly = 2 * (b0 + bq) + py;
+        const int j = j0 - H + ly;
+        if (j < 0 || j >= L.ny) continue;
+        const int c = px * F::PS + ly * F::HXH + a0 + aq;       // column 2 (a0 + aq) + px
+        const int o = (1 - px) * F::PS + ly * F::HXH + a0 + aq + px;  // its east neighbour
+        const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, c, o, F::HXH, j);
+        su[c] = sor_value(r, su[c], omega);
+    }
+    __syncthreads();
+    if constexpr (P + 1 < 4 * NS) fs_phase<T, NS, HF, P + 1>(L, su, sm, sf, j0, omega);
 }
 
 template <typename T, int NS, bool HF>
@@ -115,10 +154,11 @@ __global__ void __launch_bounds__(256) kb_sor_fused(const BatchInst<T>* __restri
                                                     const int* __restrict__ stile_inst,
                                                     const int* __restrict__ active, int parity,
                                                     unsigned long long* __restrict__ res) {
-    constexpr int H = 4 * NS + 1, HX = FUSED_X + 2 * H, HY = FUSED_Y + 2 * H, HN = HX * HY, NT = 256;
-    __shared__ T su[HN];
-    __shared__ T sm[HN];
-    __shared__ T sf[HF ? HN : 1];
+    using F = FusedLds<NS>;
+    constexpr int H = F::H, HX = F::HX, HN = HX * F::HY, NT = 256;
+    __shared__ T su[F::N];
+    __shared__ T sm[F::N];
+    __shared__ T sf[HF ? F::N : 1];
     __shared__ double wmax[2][NT / 64];
     const int k = stile_inst[blockIdx.x];
     if (!active[k]) return;  // uniform over the block
@@ -150,44 +190,24 @@ __global__ void __launch_bounds__(256) kb_sor_fused(const BatchInst<T>* __restri
     for (int r = 0; r < LPER; ++r) {
         const int q = threadIdx.x + r * NT;
         if (q < HN) {
-            su[q] = uv[r];
-            sm[q] = mv[r];
-            if (HF) sf[HF ? q : 0] = fv[HF ? r : 0];
+            const int ly = q / HX, lx = q - ly * HX, w = F::at(lx, ly);
+            su[w] = uv[r];
+            sm[w] = mv[r];
+            if (HF) sf[HF ? w : 0] = fv[HF ? r : 0];
         }
     }
     __syncthreads();
-    const T omega = B.omega;
-    // threads as 32 columns x 8 rows of same-colour nodes
-    const int tcx = threadIdx.x & 31, tcy = threadIdx.x >> 5;
-    for (int p = 0; p < 4 * NS; ++p) {
-        // colour (cx, cy) of global parity; local column lx has the parity of lx + H
-        // (i0 and j0 are even).  Nodes with lx in [H - R, H + 64 + R), ly likewise.
-        const int R = 4 * NS - p;
-        const int px = ((p & 1) + H) & 1, py = (((p >> 1) & 1) + H) & 1;
-        const int a0 = (H - R - px + 1) >> 1, na = ((H + FUSED_X + R - px + 1) >> 1) - a0;
-        const int b0 = (H - R - py + 1) >> 1, nb = ((H + FUSED_Y + R - py + 1) >> 1) - b0;
-        for (int bq = tcy; bq < nb; bq += 8) {
-            const int ly = 2 * (b0 + bq) + py;
-            const int j = j0 - H + ly;
-            if (j < 0 || j >= L.ny) continue;
-            for (int aq = tcx; aq < na; aq += 32) {
-                const int lx = 2 * (a0 + aq) + px;
-                const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, HX, lx, ly, j);
-                su[ly * HX + lx] = sor_value(r, su[ly * HX + lx], omega);
-            }
-        }
-        __syncthreads();
-    }
+    fs_phase<T, NS, HF, 0>(L, su, sm, sf, j0, B.omega);
     double v = 0.0, sc = 0.0;
     for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += NT) {
         const int ly = q / FUSED_X, lx = q - ly * FUSED_X;
         const int i = i0 + lx, j = j0 + ly;
         if (i < L.nx && j < L.ny) {
-            const int c = (H + ly) * HX + H + lx;
+            const int c = F::at(H + lx, H + ly);
             uout[(long long)j * L.pitch + i] = su[c];
             if (res && B.has_field) {
-                const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, HX, H + lx, H + ly, j);
-                v = nan_max(v, fabs((double)(r.acc - r.C * su[c] - r.rhs)));
+                const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, c, F::at(H + lx + 1, H + ly), F::HXH, j);
+                v = nan_max(v, residual_abs(r, su[c]));
                 sc = nan_max(sc, fabs((double)(r.C * su[c])));
             }
         }
@@ -227,7 +247,7 @@ __global__ void __launch_bounds__(TBX* TY) kb_residual(const BatchInst<T>* __res
     if (i < B.P.nx && j < B.P.ny && B.has_field) {
         const MgEval<T> r = mg_eval(B.L0, i, j);
         const T c = B.L0.u[(long long)j * B.L0.pitch + i];
-        v = fabs((double)(r.acc - r.C * c - r.rhs));
+        v = residual_abs(r, c);
         sc = fabs((double)(r.C * c));
     }
 #pragma unroll

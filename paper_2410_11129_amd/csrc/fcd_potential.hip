@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(RES_T) k_pot_residual(PotLevel<T> L, unsigned 
         const int j = (int)(t / L.nx), i = (int)(t - (long long)j * L.nx);
         const MgEval<T> r = mg_eval(L, i, j);
         const T c = L.u[(long long)j * L.pitch + i];
-        v = nan_max(v, fabs((double)(r.acc - r.C * c - r.rhs)));
+        v = nan_max(v, residual_abs(r, c));
         sc = nan_max(sc, fabs((double)(r.C * c)));
     }
 #pragma unroll

@@ -20,9 +20,13 @@ struct MgEval {
 
 // The operator at node row j from its mu and u neighbourhoods (rows beyond the walls
 // clamped to the edge rows, as nb_index gives them); fval is the right-hand side when
-// the level has an f plane.
+// the level has an f plane.  This function, sor_value and residual_abs fix every fused
+// multiply-add themselves (contraction off), so each kernel that uses them rounds the
+// same way whatever code surrounds it, and the batch's fused sweeps, per-colour sweeps
+// and residual passes agree bit for bit.
 template <typename T>
 __device__ __forceinline__ MgEval<T> mg_eval_nb(const PotLevel<T>& L, const Nb9<T>& m, Nb9<T> u, int j, T fval) {
+#pragma clang fp contract(off)
     const T k = L.kappa;
     if (j == 0) {
         u.s = -k * u.s;
@@ -39,14 +43,14 @@ __device__ __forceinline__ MgEval<T> mg_eval_nb(const PotLevel<T>& L, const Nb9<
     const T cne = d * (m.c + m.ne), cnw = d * (m.c + m.nw), csw = d * (m.c + m.sw), cse = d * (m.c + m.se);
     MgEval<T> r;
     r.C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
-    r.acc = ((ce * u.e + cw * u.w) + (cn * u.n + cs * u.s)) + ((cne * u.ne + csw * u.sw) + (cnw * u.nw + cse * u.se));
+    r.acc = (fma(ce, u.e, cw * u.w) + fma(cn, u.n, cs * u.s)) + (fma(cne, u.ne, csw * u.sw) + fma(cnw, u.nw, cse * u.se));
     r.cself = (j == 0 ? k * cs : T(0)) + (j == L.ny - 1 ? k * cn : T(0));
     if (L.f) {
         r.rhs = fval;
     } else {
         const T sx = (ce - cw) + (cne - csw) + (cse - cnw);
         const T sy = (cn - cs) + (cne - csw) + (cnw - cse);
-        r.rhs = L.H0x * sx + L.H0y * sy;
+        r.rhs = fma(L.H0x, sx, L.H0y * sy);
     }
     return r;
 }
@@ -63,8 +67,16 @@ __device__ __forceinline__ MgEval<T> mg_eval(const PotLevel<T>& L, int i, int j)
 // image taken implicitly.
 template <typename T>
 __device__ __forceinline__ T sor_value(const MgEval<T>& r, T old, T omega) {
-    const T gs = (r.acc + r.cself * old - r.rhs) / (r.C + r.cself);
-    return old + omega * (gs - old);
+#pragma clang fp contract(off)
+    const T gs = (fma(r.cself, old, r.acc) - r.rhs) / (r.C + r.cself);
+    return fma(omega, gs - old, old);
+}
+
+// |acc - C u - rhs|: the magnitude of the node's residual, in double.
+template <typename T>
+__device__ __forceinline__ double residual_abs(const MgEval<T>& r, T u) {
+#pragma clang fp contract(off)
+    return fabs((double)(fma(-r.C, u, r.acc) - r.rhs));
 }
 
 // One node of one colour of a Gauss-Seidel / SOR sweep.
