@@ -879,8 +879,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     }
     L->off_stiles = off;
     off = align256(off + (size_t)L->nstiles * sizeof(int));
-    L->off_res = off;
-    off = align256(off + 2 * (size_t)n * sizeof(unsigned long long));
+    L->off_res = off;  // two sets of residual slots (consecutive tests alternate)
+    off = align256(off + 4 * (size_t)n * sizeof(unsigned long long));
     L->off_active = off;
     off = align256(off + (size_t)n * sizeof(int));
     L->off_counts = off;
@@ -1045,7 +1045,7 @@ fcd_status batch_upload(fcd_batch* b) {
                                  hipMemcpyHostToDevice), "tile table upload");
     if (st) return st;
     // residual slots start (and are always left) at zero
-    return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 2 * (size_t)b->n * sizeof(unsigned long long)),
+    return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 4 * (size_t)b->n * sizeof(unsigned long long)),
                      "residual slots");
 }
 
@@ -1081,27 +1081,39 @@ BatchProblem<T> forward_problem(fcd_batch* b) {
 // A block of `block_sweeps` SOR sweeps with a device-side convergence test after every
 // `check` sweeps (block_sweeps is a multiple of check).  Fused launches alternate the
 // potential between its plane and the second plane; check is a multiple of twice the
-// sweeps per fused launch, so the potential is back in its own plane at every test.
+// sweeps per fused launch, so the potential is back in its own plane at every test, and
+// a test launch is never the launch right after another test.  With fused launches a
+// test's decision is taken by the next launch (consecutive tests use the two sets of
+// residual slots in turn, the deciding launch clearing the set of the next test); the
+// block's last test is decided by the decision kernel, which leaves both sets at zero
+// and sets the counts the host reads.
 template <typename T>
 void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
     const fcd::BatchTiles t = btiles(b);
     int* active = bptr<int>(b->scratch, b->L.off_active);
     const int check = check_interval(b);
     unsigned long long* res = bptr<unsigned long long>(b->scratch, b->L.off_res);
+    unsigned long long* rset[2] = {res, res + 2 * (size_t)b->n};
     int* counts = bptr<int>(b->scratch, b->L.off_counts);
     int* sweeps = bptr<int>(b->scratch, b->L.off_sweeps);
     const int per = t.fused > 0 ? t.fused : 1;
-    int parity = 0;
+    int parity = 0, tests = 0;
+    bool pending = false;  // a test whose decision has not been taken yet
     for (int s = per; s <= b->block_sweeps; s += per) {
         const bool test = s % check == 0;
         if (t.fused > 0) {
-            // the launch before a test also reduces the residual of its result
-            fcd::launch_batch_sweep_fused<T>(P.inst, t, active, parity, P.rhs_plane, test ? res : nullptr,
-                                             b->stream);
+            if (pending && test) {  // not with the allowed intervals; kept correct anyway
+                fcd::launch_batch_decide<T>(P.inst, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts,
+                                            P.scale, P.rel_tol, sweeps, check, b->stream);
+                pending = false;
+            }
+            fcd::BatchDecide dec{};
+            if (pending) dec = {rset[(tests - 1) & 1], rset[tests & 1], P.scale, P.rel_tol, sweeps, check};
+            fcd::launch_batch_sweep_fused<T>(P.inst, t, active, parity, P.rhs_plane, test ? rset[tests & 1] : nullptr,
+                                             dec, b->stream);
             parity ^= 1;
-            if (test)
-                fcd::launch_batch_decide<T>(P.inst, b->n, res, active, counts, P.scale, P.rel_tol, sweeps, check,
-                                            b->stream);
+            pending = test;
+            tests += test;
         } else {
             fcd::launch_batch_sweep<T>(P.inst, t, active, b->stream);
             if (test)
@@ -1109,6 +1121,9 @@ void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
                                            b->stream);
         }
     }
+    if (pending)
+        fcd::launch_batch_decide<T>(P.inst, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts, P.scale,
+                                    P.rel_tol, sweeps, check, b->stream);
 }
 
 template <typename T>

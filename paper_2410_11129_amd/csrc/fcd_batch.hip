@@ -149,11 +149,29 @@ __device__ __forceinline__ void fs_phase(const PotLevel<T>& L, T* su, const T* s
     if constexpr (P + 1 < 4 * NS) fs_phase<T, NS, HF, P + 1>(L, su, sm, sf, j0, omega);
 }
 
+// Whether channel k stays active after a test: its residual is above
+// max(thr, floor * |C psi'|) (NaN stays active); thr = rel_tol * scale[k] with scale
+// set, else the descriptor's.
+template <typename T>
+__device__ __forceinline__ int channel_active(const BatchInst<T>* inst, const unsigned long long* res, int k,
+                                              const unsigned long long* scale, double rel_tol,
+                                              double floor_factor) {
+    const double r = __longlong_as_double((long long)res[2 * k]);
+    const double sc = __longlong_as_double((long long)res[2 * k + 1]);
+    const double thr = scale ? rel_tol * __longlong_as_double((long long)scale[k]) : inst[k].thr;
+    return !(r <= fmax(thr, floor_factor * sc));
+}
+
+template <typename T>
+constexpr double decide_floor() {
+    return 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
+}
+
 template <typename T, int NS, bool HF>
 __global__ void __launch_bounds__(256) kb_sor_fused(const BatchInst<T>* __restrict__ inst,
-                                                    const int* __restrict__ stile_inst,
-                                                    const int* __restrict__ active, int parity,
-                                                    unsigned long long* __restrict__ res) {
+                                                    const int* __restrict__ stile_inst, int* __restrict__ active,
+                                                    int parity, unsigned long long* __restrict__ res,
+                                                    BatchDecide dec) {
     using F = FusedLds<NS>;
     constexpr int H = F::H, HX = F::HX, HN = HX * F::HY, NT = 256;
     __shared__ T su[F::N];
@@ -161,8 +179,21 @@ __global__ void __launch_bounds__(256) kb_sor_fused(const BatchInst<T>* __restri
     __shared__ T sf[HF ? F::N : 1];
     __shared__ double wmax[2][NT / 64];
     const int k = stile_inst[blockIdx.x];
-    if (!active[k]) return;  // uniform over the block
     const BatchInst<T>& B = inst[k];
+    // Another block of the channel may already have stored the decision read here; it
+    // is the same decision, so either value leads to the same one.
+    int act = active[k];
+    if (dec.res) {
+        const int was = act;
+        if (act) act = channel_active(inst, dec.res, k, dec.scale, dec.rel_tol, decide_floor<T>());
+        if (blockIdx.x == B.stile0 && threadIdx.x == 0) {
+            if (was) dec.sweeps[k] += dec.add;
+            active[k] = act;
+            dec.clear[2 * k] = 0ULL;
+            dec.clear[2 * k + 1] = 0ULL;
+        }
+    }
+    if (!act) return;  // uniform over the block
     const PotLevel<T> L = B.L0;
     const T* __restrict__ uin = parity ? B.alt : L.u;
     T* __restrict__ uout = parity ? L.u : B.alt;
@@ -269,27 +300,29 @@ __global__ void __launch_bounds__(TBX* TY) kb_residual(const BatchInst<T>* __res
 
 // One block: a channel stays active while its residual is above max(thr, floor * scale)
 // (an inactive channel stays inactive for the rest of the solve); the residual slots are
-// cleared for the next test; counts[0] = channels still active, counts[1] = channels
-// whose residual is NaN; sweeps[k] grows by `add` (the sweeps since the previous test)
-// for every channel active on entry.
+// cleared for the next test, and so are those of also_clear when set; counts[0] =
+// channels still active, counts[1] = channels whose residual is NaN; sweeps[k] grows by
+// `add` (the sweeps since the previous test) for every channel active on entry.
 constexpr int DECIDE_T = 256;
 
 template <typename T>
 __global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __restrict__ inst,
-                                                      unsigned long long* __restrict__ res, int n,
-                                                      double floor_factor, int* __restrict__ active,
-                                                      int* __restrict__ counts,
+                                                      unsigned long long* __restrict__ res,
+                                                      unsigned long long* __restrict__ also_clear, int n,
+                                                      int* __restrict__ active, int* __restrict__ counts,
                                                       const unsigned long long* __restrict__ scale, double rel_tol,
                                                       int* __restrict__ sweeps, int add) {
     __shared__ int cnt[2][DECIDE_T / 64];
     int a_sum = 0, nan_sum = 0;
     for (int k = threadIdx.x; k < n; k += DECIDE_T) {
+        if (also_clear) {
+            also_clear[2 * k] = 0ULL;
+            also_clear[2 * k + 1] = 0ULL;
+        }
         if (!active[k]) continue;
         sweeps[k] += add;
         const double r = __longlong_as_double((long long)res[2 * k]);
-        const double sc = __longlong_as_double((long long)res[2 * k + 1]);
-        const double thr = scale ? rel_tol * __longlong_as_double((long long)scale[k]) : inst[k].thr;
-        const int a = !(r <= fmax(thr, floor_factor * sc));
+        const int a = channel_active(inst, res, k, scale, rel_tol, decide_floor<T>());
         active[k] = a;
         a_sum += a;
         nan_sum += r != r;
@@ -373,11 +406,11 @@ void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int
 }
 
 template <typename T>
-void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, const int* active, int parity,
-                              bool rhs_plane, unsigned long long* res, hipStream_t s) {
+void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, int* active, int parity,
+                              bool rhs_plane, unsigned long long* res, const BatchDecide& dec, hipStream_t s) {
 #define C_(NS, HF)                                                                                                 \
     hipLaunchKernelGGL((kb_sor_fused<T, NS, HF>), dim3(t.nstiles), dim3(256), 0, s, inst, t.stiles, active, parity, \
-                       res)
+                       res, dec)
     if (t.fused == 1) {
         if (rhs_plane) C_(1, true); else C_(1, false);
     } else {
@@ -394,14 +427,14 @@ void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, un
     hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
     FCD_SHAPE_SWITCH(t.shape, C_)
 #undef C_
-    launch_batch_decide<T>(inst, n, res, active, counts, scale, rel_tol, sweeps, add, s);
+    launch_batch_decide<T>(inst, n, res, nullptr, active, counts, scale, rel_tol, sweeps, add, s);
 }
 
 template <typename T>
-void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, int* active, int* counts,
-                         const unsigned long long* scale, double rel_tol, int* sweeps, int add, hipStream_t s) {
-    const double floor_factor = 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
-    hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, n, floor_factor, active, counts, scale,
+void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, unsigned long long* also_clear,
+                         int* active, int* counts, const unsigned long long* scale, double rel_tol, int* sweeps,
+                         int add, hipStream_t s) {
+    hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, also_clear, n, active, counts, scale,
                        rel_tol, sweeps, add);
 }
 
@@ -424,10 +457,11 @@ void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStr
     template void launch_batch_phase<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);           \
     template void launch_batch_collide<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);         \
     template void launch_batch_sweep<T>(const BatchInst<T>*, const BatchTiles&, const int*, hipStream_t);    \
-    template void launch_batch_sweep_fused<T>(const BatchInst<T>*, const BatchTiles&, const int*, int, bool, \
-                                              unsigned long long*, hipStream_t);                             \
-    template void launch_batch_decide<T>(const BatchInst<T>*, int, unsigned long long*, int*, int*,          \
-                                         const unsigned long long*, double, int*, int, hipStream_t);         \
+    template void launch_batch_sweep_fused<T>(const BatchInst<T>*, const BatchTiles&, int*, int, bool,       \
+                                              unsigned long long*, const BatchDecide&, hipStream_t);         \
+    template void launch_batch_decide<T>(const BatchInst<T>*, int, unsigned long long*, unsigned long long*, \
+                                         int*, int*, const unsigned long long*, double, int*, int,           \
+                                         hipStream_t);                                                       \
     template void launch_batch_check<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,    \
                                         int*, int*, const unsigned long long*, double, int*, int,            \
                                         hipStream_t);                                                        \

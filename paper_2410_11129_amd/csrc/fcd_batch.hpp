@@ -63,18 +63,36 @@ void launch_batch_collide(const BatchInst<T>* inst, const BatchTiles& t, int cur
 // One four-colour SOR sweep of the active channels.
 template <typename T>
 void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int* active, hipStream_t s);
+// The activity decision of a test carried out at the start of the next fused sweep
+// launch instead of by a kernel of its own: every block decides its own channel from
+// the test's residual slots (the blocks of a channel all reach the same decision, the
+// one launch_batch_decide takes); the channel's first block stores it, adds `add` to
+// sweeps[k] if the channel was active, and zeroes the channel's slots in `clear` (those
+// of the following test).  res == nullptr: no decision in this launch.
+struct BatchDecide {
+    const unsigned long long* res;
+    unsigned long long* clear;
+    const unsigned long long* scale;
+    double rel_tol;
+    int* sweeps;
+    int add;
+};
 // t.fused four-colour SOR sweeps of the active channels in one launch, bitwise equal to
 // as many launch_batch_sweep calls; parity 0 reads L0.u and writes alt, parity 1 the
 // reverse.  rhs_plane: the descriptors' L0.f is set (else the field gives the rhs).
 // res != nullptr: also reduce the residual of the result as launch_batch_check does
-// (the decision kernel still has to follow).
+// (a decision has to follow, folded into the next launch or by launch_batch_decide);
+// res must not be dec.clear.
 template <typename T>
-void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, const int* active, int parity,
-                              bool rhs_plane, unsigned long long* res, hipStream_t s);
-// The activity decision of launch_batch_check alone, on residual slots already filled.
+void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, int* active, int parity,
+                              bool rhs_plane, unsigned long long* res, const BatchDecide& dec, hipStream_t s);
+// The activity decision of launch_batch_check alone, on residual slots already filled;
+// also_clear (may be null): more slots to zero, those of an earlier test decided by a
+// fused launch.
 template <typename T>
-void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, int* active, int* counts,
-                         const unsigned long long* scale, double rel_tol, int* sweeps, int add, hipStream_t s);
+void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, unsigned long long* also_clear,
+                         int* active, int* counts, const unsigned long long* scale, double rel_tol, int* sweeps,
+                         int add, hipStream_t s);
 // Residual of the active channels, then the activity decision; res must be zero on entry
 // and is left zero; counts[0..1] = active channels, channels with a NaN residual.
 // scale != nullptr: channel k's threshold is rel_tol * scale[k] (bit pattern of a
