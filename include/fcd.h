@@ -270,7 +270,7 @@ fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double
  * 4 or 8), the potential sweeps are replayed as HIP graphs of block_sweeps sweeps (a
  * multiple of pot_check_every of channel 0, the interval of the device-side convergence
  * test, at most 2^20), and fused_sweeps > 0 runs that many four-colour SOR sweeps per
- * launch on 64 x 16 tiles with their halo in LDS (1 or 2; needs pot_check_every to be a
+ * launch on 64 x 32 tiles with their halo in LDS (1 or 2; needs pot_check_every to be a
  * multiple of 2 fused_sweeps), 0 one launch per colour.  The schedule changes launch
  * geometry only: states are bitwise the same under every schedule.  Default: tile_rows
  * 4, block_sweeps 8 * pot_check_every, the largest fused_sweeps allowed.

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(TBX* TY) kb_sor_colour(const BatchInst<T>* __r
     relax_node(B.L0, i, j, B.omega);
 }
 
-// Fused sweeps: NS four-colour SOR sweeps of one 64 x 16 tile in one launch.  The tile
+// Fused sweeps: NS four-colour SOR sweeps of one 64 x 32 tile in one launch.  The tile
 // and a halo of H = 4 NS + 1 nodes are staged in LDS (columns wrapped, rows clamped to
 // the channel).  Colour phase p = 0 .. 4 NS - 1 (colour p mod 4) updates the nodes of
 // its colour that lie within 4 NS - p nodes of the tile, so every value a phase reads
@@ -126,8 +126,8 @@ __device__ __forceinline__ MgEval<T> fs_eval(const PotLevel<T>& L, const T* su, 
 
 // Colour phase P of the fused sweeps: colour (cx, cy) of global parity (local column lx
 // has the parity of lx + H, since the tile origin is even), nodes with lx in
-// [H - R, H + 64 + R), ly likewise, R = 4 NS - P; the phase's nodes are dealt to the
-// block's threads row-major, so few lanes idle.
+// [H - R, H + 64 + R), ly likewise, R = 4 NS - P, rows outside the channel left out;
+// the phase's nodes are dealt to the block's threads row-major, so few lanes idle.
 template <typename T, int NS, bool HF, int P>
 __device__ __forceinline__ void fs_phase(const PotLevel<T>& L, T* su, const T* sm, const T* sf, int j0, T omega) {
     using F = FusedLds<NS>;
@@ -135,11 +135,12 @@ __device__ __forceinline__ void fs_phase(const PotLevel<T>& L, T* su, const T* s
     constexpr int px = ((P & 1) + H) & 1, py = (((P >> 1) & 1) + H) & 1;
     constexpr int a0 = (H - R - px + 1) >> 1, na = ((H + FUSED_X + R - px + 1) >> 1) - a0;
     constexpr int b0 = (H - R - py + 1) >> 1, nb = ((H + FUSED_Y + R - py + 1) >> 1) - b0;
-    for (int q = threadIdx.x; q < na * nb; q += 256) {
+    // only the rows inside the channel: 0 <= j0 - H + ly < ny
+    const int lo = max(0, ((H - j0 - py + 1) >> 1) - b0), hi = min(nb, ((L.ny - 1 + H - j0 - py) >> 1) - b0 + 1);
+    for (int q = lo * na + threadIdx.x; q < hi * na; q += FUSED_NT) {
         const int bq = q / na, aq = q - bq * na;
         const int ly = 2 * (b0 + bq) + py;
         const int j = j0 - H + ly;
-        if (j < 0 || j >= L.ny) continue;
         const int c = px * F::PS + ly * F::HXH + a0 + aq;       // column 2 (a0 + aq) + px
         const int o = (1 - px) * F::PS + ly * F::HXH + a0 + aq + px;  // its east neighbour
         const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, c, o, F::HXH, j);
@@ -168,12 +169,12 @@ constexpr double decide_floor() {
 }
 
 template <typename T, int NS, bool HF>
-__global__ void __launch_bounds__(256) kb_sor_fused(const BatchInst<T>* __restrict__ inst,
+__global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __restrict__ inst,
                                                     const int* __restrict__ stile_inst, int* __restrict__ active,
                                                     int parity, unsigned long long* __restrict__ res,
                                                     BatchDecide dec) {
     using F = FusedLds<NS>;
-    constexpr int H = F::H, HX = F::HX, HN = HX * F::HY, NT = 256;
+    constexpr int H = F::H, HX = F::HX, HN = HX * F::HY, NT = FUSED_NT;
     __shared__ T su[F::N];
     __shared__ T sm[F::N];
     __shared__ T sf[HF ? F::N : 1];
@@ -409,7 +410,7 @@ template <typename T>
 void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, int* active, int parity,
                               bool rhs_plane, unsigned long long* res, const BatchDecide& dec, hipStream_t s) {
 #define C_(NS, HF)                                                                                                 \
-    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF>), dim3(t.nstiles), dim3(256), 0, s, inst, t.stiles, active, parity, \
+    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF>), dim3(t.nstiles), dim3(FUSED_NT), 0, s, inst, t.stiles, active, parity, \
                        res, dec)
     if (t.fused == 1) {
         if (rhs_plane) C_(1, true); else C_(1, false);

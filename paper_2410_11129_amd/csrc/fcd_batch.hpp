@@ -25,7 +25,7 @@ struct BatchInst {
     // lists, and tiles per row
     int tile0[BATCH_SHAPES], tiles_x[BATCH_SHAPES];
     int ctile0[BATCH_SHAPES], ctiles_x[BATCH_SHAPES];
-    int stile0, stiles_x;  // first tile and tiles per row in the fused-sweep (64 x 16) list
+    int stile0, stiles_x;  // first tile and tiles per row in the fused-sweep (64 x 32) list
     int has_field;         // H0 != 0
     int pad;
 };
@@ -41,7 +41,7 @@ struct BatchAdj {
     int tile_first, tile_count;  // the channel's tiles in the 64 x 4 list
 };
 
-// The tile lists of one shape (device tables: tile -> channel), and the 64 x 16 list of
+// The tile lists of one shape (device tables: tile -> channel), and the 64 x 32 list of
 // the fused sweeps with their sweeps per launch (0: one launch per colour instead).
 struct BatchTiles {
     int shape;
@@ -53,8 +53,8 @@ struct BatchTiles {
     const int* stiles;
 };
 
-// Fused-sweep tile: 64 x 16 nodes plus a halo of 4 nodes per sweep.
-constexpr int FUSED_X = 64, FUSED_Y = 16, FUSED_MAX = 2;
+// Fused-sweep tile: 64 x 32 nodes plus a halo of 4 nodes per sweep, 512 threads.
+constexpr int FUSED_X = 64, FUSED_Y = 32, FUSED_MAX = 2, FUSED_NT = 512;
 
 template <typename T>
 void launch_batch_phase(const BatchInst<T>* inst, const BatchTiles& t, int cur, hipStream_t s);
