@@ -815,6 +815,7 @@ struct BatchLayout {
     int ntiles[fcd::BATCH_SHAPES] = {}, nctiles[fcd::BATCH_SHAPES] = {}, nstiles = 0;
     size_t state_bytes = 0, aux_bytes = 0, scratch_bytes = 0;
     size_t off_inst = 0, off_tiles[fcd::BATCH_SHAPES] = {}, off_ctiles[fcd::BATCH_SHAPES] = {}, off_stiles = 0;
+    size_t off_slist = 0;
     size_t off_res = 0, off_active = 0, off_counts = 0, off_sweeps = 0;
     size_t off_rows = 0, off_cent = 0, off_result = 0;
 };
@@ -879,6 +880,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     }
     L->off_stiles = off;
     off = align256(off + (size_t)L->nstiles * sizeof(int));
+    L->off_slist = off;  // active fused tiles, then their count
+    off = align256(off + ((size_t)L->nstiles + 1) * sizeof(int));
     L->off_res = off;  // two sets of residual slots (consecutive tests alternate)
     off = align256(off + 4 * (size_t)n * sizeof(unsigned long long));
     L->off_active = off;
@@ -948,6 +951,11 @@ T* bptr(char* base, size_t off) {
     return reinterpret_cast<T*>(base + off);
 }
 
+// Blocks of a fused sweep launch (about four per compute unit); they stride over the list
+// of active tiles, so a launch late in a solve, when few channels are still active,
+// dispatches no more blocks than this.
+constexpr int FUSED_GRID = 1024;
+
 fcd::BatchTiles btiles(const fcd_batch* b) {
     fcd::BatchTiles t;
     t.shape = b->shape;
@@ -958,6 +966,9 @@ fcd::BatchTiles btiles(const fcd_batch* b) {
     t.fused = b->fused;
     t.nstiles = b->L.nstiles;
     t.stiles = reinterpret_cast<const int*>(b->scratch + b->L.off_stiles);
+    t.slist = reinterpret_cast<int*>(b->scratch + b->L.off_slist);
+    t.scount = t.slist + b->L.nstiles;
+    t.sgrid = std::max(1, std::min(b->L.nstiles, FUSED_GRID));
     return t;
 }
 
@@ -1044,6 +1055,10 @@ fcd_status batch_upload(fcd_batch* b) {
         st = hip_check(hipMemcpy(b->scratch + b->L.off_stiles, stiles.data(), stiles.size() * sizeof(int),
                                  hipMemcpyHostToDevice), "tile table upload");
     if (st) return st;
+    // an empty list of active fused tiles until the first decision kernel
+    st = hip_check(hipMemset(b->scratch + b->L.off_slist, 0, ((size_t)b->L.nstiles + 1) * sizeof(int)),
+                   "active tile list");
+    if (st) return st;
     // residual slots start (and are always left) at zero
     return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 4 * (size_t)b->n * sizeof(unsigned long long)),
                      "residual slots");
@@ -1103,7 +1118,7 @@ void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
         const bool test = s % check == 0;
         if (t.fused > 0) {
             if (pending && test) {  // not with the allowed intervals; kept correct anyway
-                fcd::launch_batch_decide<T>(P.inst, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts,
+                fcd::launch_batch_decide<T>(P.inst, t, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts,
                                             P.scale, P.rel_tol, sweeps, check, b->stream);
                 pending = false;
             }
@@ -1122,7 +1137,7 @@ void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
         }
     }
     if (pending)
-        fcd::launch_batch_decide<T>(P.inst, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts, P.scale,
+        fcd::launch_batch_decide<T>(P.inst, t, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts, P.scale,
                                     P.rel_tol, sweeps, check, b->stream);
 }
 

@@ -32,6 +32,21 @@ __device__ __forceinline__ void tile_node(const BatchInst<T>& B, int tile, bool 
     j = ty * TY + threadIdx.y;
 }
 
+template <typename T, int SX>
+__device__ __forceinline__ Nb9<T> tile_nb(const T (*t)[SX], int lx, int ly) {
+    Nb9<T> v;
+    v.c = t[ly][lx];
+    v.e = t[ly][lx + 1];
+    v.w = t[ly][lx - 1];
+    v.n = t[ly + 1][lx];
+    v.s = t[ly - 1][lx];
+    v.ne = t[ly + 1][lx + 1];
+    v.nw = t[ly + 1][lx - 1];
+    v.sw = t[ly - 1][lx - 1];
+    v.se = t[ly - 1][lx + 1];
+    return v;
+}
+
 template <typename T, int TY>
 __global__ void __launch_bounds__(TBX* TY) kb_phase(const BatchInst<T>* __restrict__ inst,
                                                     const int* __restrict__ tile_inst, int cur) {
@@ -42,14 +57,40 @@ __global__ void __launch_bounds__(TBX* TY) kb_phase(const BatchInst<T>* __restri
     phase_node(static_cast<const T*>(B.dist[cur]), B.phi, B.P, i, j);
 }
 
+// Fused collide-and-stream of one tile: the phi1, phi2 and psi' neighbourhoods are staged
+// in LDS (the tile plus a one-node ring; columns wrap, rows beyond the walls repeat the
+// edge row for phi and are zero for psi', as the global neighbourhood loads give them),
+// then each node runs the same per-node update as the single-channel kernel.
 template <typename T, int TY>
 __global__ void __launch_bounds__(TBX* TY) kb_collide_stream(const BatchInst<T>* __restrict__ inst,
                                                              const int* __restrict__ tile_inst, int cur) {
+    constexpr int SX = TBX + 2, SY = TY + 2, S = shape_index<TY>();
+    __shared__ T t1[SY][SX], t2[SY][SX], tp[SY][SX];
     const BatchInst<T>& B = inst[tile_inst[blockIdx.x]];
-    int i, j;
-    tile_node<T, TY>(B, blockIdx.x, false, i, j);
-    if (i >= B.P.nx || j >= B.P.ny) return;
-    collide_stream_node(static_cast<const T*>(B.dist[cur]), B.dist[1 - cur], B.phi, B.L0.u, B.P, i, j);
+    const int lt = blockIdx.x - B.tile0[S], tx = B.tiles_x[S];
+    const int ty = lt / tx, i0 = (lt - ty * tx) * TBX, j0 = ty * TY;
+    const int nx = B.P.nx, ny = B.P.ny;
+    const long long pitch = B.P.pitch, plane = B.P.plane;
+    const T* __restrict__ phi = B.phi;
+    const T* __restrict__ psi = B.L0.u;
+    for (int q = threadIdx.y * TBX + threadIdx.x; q < SX * SY; q += TBX * TY) {
+        const int ly = q / SX, lx = q - ly * SX;
+        int i = i0 + lx - 1;
+        while (i < 0) i += nx;
+        while (i >= nx) i -= nx;
+        const int jr = j0 + ly - 1;
+        const int j = jr < 0 ? 0 : (jr >= ny ? ny - 1 : jr);
+        const long long k = (long long)j * pitch + i;
+        t1[ly][lx] = phi[k];
+        t2[ly][lx] = phi[plane + k];
+        tp[ly][lx] = (jr < 0 || jr >= ny) ? T(0) : psi[k];
+    }
+    __syncthreads();
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
+    collide_stream_nb(static_cast<const T*>(B.dist[cur]), B.dist[1 - cur], tile_nb<T, SX>(t1, lx, ly),
+                      tile_nb<T, SX>(t2, lx, ly), tile_nb<T, SX>(tp, lx, ly), B.P, i, j);
 }
 
 template <typename T, int TY>
@@ -170,95 +211,104 @@ constexpr double decide_floor() {
 
 template <typename T, int NS, bool HF>
 __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __restrict__ inst,
-                                                    const int* __restrict__ stile_inst, int* __restrict__ active,
-                                                    int parity, unsigned long long* __restrict__ res,
-                                                    BatchDecide dec) {
+                                                         const int* __restrict__ stile_inst,
+                                                         const int* __restrict__ slist, const int* __restrict__ scount,
+                                                         int* __restrict__ active, int parity,
+                                                         unsigned long long* __restrict__ res, BatchDecide dec) {
     using F = FusedLds<NS>;
     constexpr int H = F::H, HX = F::HX, HN = HX * F::HY, NT = FUSED_NT;
     __shared__ T su[F::N];
     __shared__ T sm[F::N];
     __shared__ T sf[HF ? F::N : 1];
     __shared__ double wmax[2][NT / 64];
-    const int k = stile_inst[blockIdx.x];
-    const BatchInst<T>& B = inst[k];
-    // Another block of the channel may already have stored the decision read here; it
-    // is the same decision, so either value leads to the same one.
-    int act = active[k];
-    if (dec.res) {
-        const int was = act;
-        if (act) act = channel_active(inst, dec.res, k, dec.scale, dec.rel_tol, decide_floor<T>());
-        if (blockIdx.x == B.stile0 && threadIdx.x == 0) {
-            if (was) dec.sweeps[k] += dec.add;
-            active[k] = act;
-            dec.clear[2 * k] = 0ULL;
-            dec.clear[2 * k + 1] = 0ULL;
-        }
-    }
-    if (!act) return;  // uniform over the block
-    const PotLevel<T> L = B.L0;
-    const T* __restrict__ uin = parity ? B.alt : L.u;
-    T* __restrict__ uout = parity ? L.u : B.alt;
-    const int lt = blockIdx.x - B.stile0, ty = lt / B.stiles_x, tx = lt - ty * B.stiles_x;
-    const int i0 = tx * FUSED_X, j0 = ty * FUSED_Y;
-    // all loads into registers first, then the LDS stores, so that the loads of a thread
-    // are in flight together
-    constexpr int LPER = (HN + NT - 1) / NT;
-    T uv[LPER], mv[LPER], fv[HF ? LPER : 1];
-#pragma unroll
-    for (int r = 0; r < LPER; ++r) {
-        const int q = threadIdx.x + r * NT;
-        if (q < HN) {
-            const int ly = q / HX, lx = q - ly * HX;
-            const int i = fs_wrap(i0 - H + lx, L.nx);
-            int j = j0 - H + ly;
-            j = j < 0 ? 0 : (j >= L.ny ? L.ny - 1 : j);
-            const long long g = (long long)j * L.pitch + i;
-            uv[r] = uin[g];
-            mv[r] = L.mu[g];
-            if (HF) fv[HF ? r : 0] = L.f[g];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < LPER; ++r) {
-        const int q = threadIdx.x + r * NT;
-        if (q < HN) {
-            const int ly = q / HX, lx = q - ly * HX, w = F::at(lx, ly);
-            su[w] = uv[r];
-            sm[w] = mv[r];
-            if (HF) sf[HF ? w : 0] = fv[HF ? r : 0];
-        }
-    }
-    __syncthreads();
-    fs_phase<T, NS, HF, 0>(L, su, sm, sf, j0, B.omega);
-    double v = 0.0, sc = 0.0;
-    for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += NT) {
-        const int ly = q / FUSED_X, lx = q - ly * FUSED_X;
-        const int i = i0 + lx, j = j0 + ly;
-        if (i < L.nx && j < L.ny) {
-            const int c = F::at(H + lx, H + ly);
-            uout[(long long)j * L.pitch + i] = su[c];
-            if (res && B.has_field) {
-                const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, c, F::at(H + lx + 1, H + ly), F::HXH, j);
-                v = nan_max(v, residual_abs(r, su[c]));
-                sc = nan_max(sc, fabs((double)(r.C * su[c])));
+    // the blocks stride over the list of the tiles of the channels that were active at
+    // the last decision kernel (channels stopped since then are skipped tile by tile)
+    const int count = *scount;
+    for (int b = blockIdx.x; b < count; b += gridDim.x) {
+        const int tile = slist[b];
+        const int k = stile_inst[tile];
+        const BatchInst<T>& B = inst[k];
+        // Another block of the channel may already have stored the decision read here;
+        // it is the same decision, so either value leads to the same one.
+        int act = active[k];
+        if (dec.res) {
+            const int was = act;
+            if (act) act = channel_active(inst, dec.res, k, dec.scale, dec.rel_tol, decide_floor<T>());
+            if (tile == B.stile0 && threadIdx.x == 0) {
+                if (was) dec.sweeps[k] += dec.add;
+                active[k] = act;
+                dec.clear[2 * k] = 0ULL;
+                dec.clear[2 * k + 1] = 0ULL;
             }
         }
-    }
-    if (!res) return;  // uniform
+        if (!act) continue;  // uniform over the block
+        const PotLevel<T> L = B.L0;
+        const T* __restrict__ uin = parity ? B.alt : L.u;
+        T* __restrict__ uout = parity ? L.u : B.alt;
+        const int lt = tile - B.stile0, ty = lt / B.stiles_x, tx = lt - ty * B.stiles_x;
+        const int i0 = tx * FUSED_X, j0 = ty * FUSED_Y;
+        // all loads into registers first, then the LDS stores, so that the loads of a
+        // thread are in flight together
+        constexpr int LPER = (HN + NT - 1) / NT;
+        T uv[LPER], mv[LPER], fv[HF ? LPER : 1];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        v = nan_max(v, __shfl_xor(v, off, 64));
-        sc = nan_max(sc, __shfl_xor(sc, off, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        wmax[0][threadIdx.x >> 6] = v;
-        wmax[1][threadIdx.x >> 6] = sc;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        double mx = wmax[threadIdx.x][0];
-        for (int w = 1; w < NT / 64; ++w) mx = nan_max(mx, wmax[threadIdx.x][w]);
-        atomicMax(res + 2 * k + threadIdx.x, (unsigned long long)__double_as_longlong(mx));
+        for (int r = 0; r < LPER; ++r) {
+            const int q = threadIdx.x + r * NT;
+            if (q < HN) {
+                const int ly = q / HX, lx = q - ly * HX;
+                const int i = fs_wrap(i0 - H + lx, L.nx);
+                int j = j0 - H + ly;
+                j = j < 0 ? 0 : (j >= L.ny ? L.ny - 1 : j);
+                const long long g = (long long)j * L.pitch + i;
+                uv[r] = uin[g];
+                mv[r] = L.mu[g];
+                if (HF) fv[HF ? r : 0] = L.f[g];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < LPER; ++r) {
+            const int q = threadIdx.x + r * NT;
+            if (q < HN) {
+                const int ly = q / HX, lx = q - ly * HX, w = F::at(lx, ly);
+                su[w] = uv[r];
+                sm[w] = mv[r];
+                if (HF) sf[HF ? w : 0] = fv[HF ? r : 0];
+            }
+        }
+        __syncthreads();
+        fs_phase<T, NS, HF, 0>(L, su, sm, sf, j0, B.omega);
+        double v = 0.0, sc = 0.0;
+        for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += NT) {
+            const int ly = q / FUSED_X, lx = q - ly * FUSED_X;
+            const int i = i0 + lx, j = j0 + ly;
+            if (i < L.nx && j < L.ny) {
+                const int c = F::at(H + lx, H + ly);
+                uout[(long long)j * L.pitch + i] = su[c];
+                if (res && B.has_field) {
+                    const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, c, F::at(H + lx + 1, H + ly), F::HXH, j);
+                    v = nan_max(v, residual_abs(r, su[c]));
+                    sc = nan_max(sc, fabs((double)(r.C * su[c])));
+                }
+            }
+        }
+        if (res) {  // uniform
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                v = nan_max(v, __shfl_xor(v, off, 64));
+                sc = nan_max(sc, __shfl_xor(sc, off, 64));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                wmax[0][threadIdx.x >> 6] = v;
+                wmax[1][threadIdx.x >> 6] = sc;
+            }
+            __syncthreads();
+            if (threadIdx.x < 2) {
+                double mx = wmax[threadIdx.x][0];
+                for (int w = 1; w < NT / 64; ++w) mx = nan_max(mx, wmax[threadIdx.x][w]);
+                atomicMax(res + 2 * k + threadIdx.x, (unsigned long long)__double_as_longlong(mx));
+            }
+        }
+        __syncthreads();  // the next tile reuses the LDS arrays
     }
 }
 
@@ -312,8 +362,10 @@ __global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __rest
                                                       unsigned long long* __restrict__ also_clear, int n,
                                                       int* __restrict__ active, int* __restrict__ counts,
                                                       const unsigned long long* __restrict__ scale, double rel_tol,
-                                                      int* __restrict__ sweeps, int add) {
+                                                      int* __restrict__ sweeps, int add, int* __restrict__ slist,
+                                                      int* __restrict__ scount) {
     __shared__ int cnt[2][DECIDE_T / 64];
+    __shared__ int scan[DECIDE_T];
     int a_sum = 0, nan_sum = 0;
     for (int k = threadIdx.x; k < n; k += DECIDE_T) {
         if (also_clear) {
@@ -345,6 +397,29 @@ __global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __rest
         for (int w = 0; w < DECIDE_T / 64; ++w) s += cnt[threadIdx.x][w];
         counts[threadIdx.x] = s;
     }
+    // the fused-sweep tiles of the channels still active, in channel order (an exclusive
+    // scan of their tile counts, DECIDE_T channels at a time); the barrier makes this
+    // block's stores to active visible to all its threads
+    __syncthreads();
+    int base = 0;
+    for (int c0 = 0; c0 < n; c0 += DECIDE_T) {
+        const int k = c0 + threadIdx.x;
+        int m = 0;
+        if (k < n && active[k]) m = inst[k].stiles_x * ((inst[k].P.ny + FUSED_Y - 1) / FUSED_Y);
+        scan[threadIdx.x] = m;
+        __syncthreads();
+        for (int off = 1; off < DECIDE_T; off <<= 1) {  // inclusive scan (Hillis-Steele)
+            const int add_in = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += add_in;
+            __syncthreads();
+        }
+        const int first = base + scan[threadIdx.x] - m;
+        for (int q = 0; q < m; ++q) slist[first + q] = inst[k].stile0 + q;
+        base += scan[DECIDE_T - 1];
+        __syncthreads();  // scan[] is rewritten by the next chunk
+    }
+    if (threadIdx.x == 0) *scount = base;
 }
 
 template <typename T, int TY>
@@ -410,8 +485,8 @@ template <typename T>
 void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, int* active, int parity,
                               bool rhs_plane, unsigned long long* res, const BatchDecide& dec, hipStream_t s) {
 #define C_(NS, HF)                                                                                                 \
-    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF>), dim3(t.nstiles), dim3(FUSED_NT), 0, s, inst, t.stiles, active, parity, \
-                       res, dec)
+    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF>), dim3(t.sgrid), dim3(FUSED_NT), 0, s, inst, t.stiles, t.slist, \
+                       t.scount, active, parity, res, dec)
     if (t.fused == 1) {
         if (rhs_plane) C_(1, true); else C_(1, false);
     } else {
@@ -428,15 +503,15 @@ void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, un
     hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
     FCD_SHAPE_SWITCH(t.shape, C_)
 #undef C_
-    launch_batch_decide<T>(inst, n, res, nullptr, active, counts, scale, rel_tol, sweeps, add, s);
+    launch_batch_decide<T>(inst, t, n, res, nullptr, active, counts, scale, rel_tol, sweeps, add, s);
 }
 
 template <typename T>
-void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, unsigned long long* also_clear,
-                         int* active, int* counts, const unsigned long long* scale, double rel_tol, int* sweeps,
-                         int add, hipStream_t s) {
+void launch_batch_decide(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
+                         unsigned long long* also_clear, int* active, int* counts, const unsigned long long* scale,
+                         double rel_tol, int* sweeps, int add, hipStream_t s) {
     hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, also_clear, n, active, counts, scale,
-                       rel_tol, sweeps, add);
+                       rel_tol, sweeps, add, t.slist, t.scount);
 }
 
 template <typename T>
@@ -460,9 +535,9 @@ void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStr
     template void launch_batch_sweep<T>(const BatchInst<T>*, const BatchTiles&, const int*, hipStream_t);    \
     template void launch_batch_sweep_fused<T>(const BatchInst<T>*, const BatchTiles&, int*, int, bool,       \
                                               unsigned long long*, const BatchDecide&, hipStream_t);         \
-    template void launch_batch_decide<T>(const BatchInst<T>*, int, unsigned long long*, unsigned long long*, \
-                                         int*, int*, const unsigned long long*, double, int*, int,           \
-                                         hipStream_t);                                                       \
+    template void launch_batch_decide<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,   \
+                                         unsigned long long*, int*, int*, const unsigned long long*, double, \
+                                         int*, int, hipStream_t);                                            \
     template void launch_batch_check<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,    \
                                         int*, int*, const unsigned long long*, double, int*, int,            \
                                         hipStream_t);                                                        \

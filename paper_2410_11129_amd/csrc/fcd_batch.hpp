@@ -51,6 +51,9 @@ struct BatchTiles {
     int fused;
     int nstiles;
     const int* stiles;
+    int* slist;   // device: the fused tiles of the channels active at the last decision
+    int* scount;  // kernel (written by it) and their number
+    int sgrid;    // blocks of a fused launch, which stride over slist
 };
 
 // Fused-sweep tile: 64 x 32 nodes plus a halo of 4 nodes per sweep, 512 threads.
@@ -88,11 +91,12 @@ void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, int
                               bool rhs_plane, unsigned long long* res, const BatchDecide& dec, hipStream_t s);
 // The activity decision of launch_batch_check alone, on residual slots already filled;
 // also_clear (may be null): more slots to zero, those of an earlier test decided by a
-// fused launch.
+// fused launch.  Also lists the fused tiles of the channels left active (t.slist,
+// t.scount) for the following fused launches.
 template <typename T>
-void launch_batch_decide(const BatchInst<T>* inst, int n, unsigned long long* res, unsigned long long* also_clear,
-                         int* active, int* counts, const unsigned long long* scale, double rel_tol, int* sweeps,
-                         int add, hipStream_t s);
+void launch_batch_decide(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
+                         unsigned long long* also_clear, int* active, int* counts, const unsigned long long* scale,
+                         double rel_tol, int* sweeps, int add, hipStream_t s);
 // Residual of the active channels, then the activity decision; res must be zero on entry
 // and is left zero; counts[0..1] = active channels, channels with a NaN residual.
 // scale != nullptr: channel k's threshold is rel_tol * scale[k] (bit pattern of a

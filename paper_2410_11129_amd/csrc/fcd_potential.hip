@@ -565,18 +565,30 @@ constexpr int TAIL_T = 512;
 template <typename T>
 struct TailLevel {
     int nx, ny;
+    unsigned inv;  // ceil(2^32 / nx): row of node t = high word of t * inv
     T *u, *f, *mu, *alt;
     T* c[8];  // couplings to e, w, n, s, ne, nw, sw, se
     T *d, *rd;
 };
 
+// ceil(2^32 / nx) of every tail level (2 <= nx, as coarse levels have), from the host:
+// for t < TAIL_MAXN and nx < 2^20, t / nx is the high word of t * inv (the rounding up
+// adds less than t / 2^32 < 1 / nx to t / nx), one multiply in place of an integer
+// division in every node loop of the tail.
+struct TailDiv {
+    unsigned inv[MG_MAX_TAIL];
+};
+
+__device__ __forceinline__ int tail_div(int t, unsigned inv) { return (int)__umulhi((unsigned)t, inv); }
+
 template <typename T>
-__device__ __forceinline__ TailLevel<T> tail_view(const MgTail<T>& tl, T* base, int k) {
+__device__ __forceinline__ TailLevel<T> tail_view(const MgTail<T>& tl, const TailDiv& dv, T* base, int k) {
     long long off = 0;
     for (int m = 0; m < k; ++m) off += (long long)MG_TAIL_ARRAYS * tl.lv[m].nx * tl.lv[m].ny;
     TailLevel<T> S;
     S.nx = tl.lv[k].nx;
     S.ny = tl.lv[k].ny;
+    S.inv = dv.inv[k];
     const long long n = (long long)S.nx * S.ny;
     T* p = base + off;
     S.u = p;
@@ -593,7 +605,7 @@ __device__ __forceinline__ TailLevel<T> tail_view(const MgTail<T>& tl, T* base, 
 // Couplings of node t = (i, j) from mu (Eq. 35 weights of the flux form, as mg_eval_nb).
 template <typename T>
 __device__ __forceinline__ void tail_setup_node(const TailLevel<T>& S, const PotLevel<T>& G, int t) {
-    const int nx = S.nx, j = t / nx, i = t - j * nx;
+    const int nx = S.nx, j = tail_div(t, S.inv), i = t - j * nx;
     const int e = i + 1 == nx ? t + 1 - nx : t + 1, w = i == 0 ? t - 1 + nx : t - 1;
     const int dn = j + 1 == S.ny ? 0 : nx, ds = j == 0 ? 0 : -nx;  // mirrored mu beyond the walls
     const T* m = S.mu;
@@ -629,7 +641,7 @@ __device__ __forceinline__ void tail_setup_node(const TailLevel<T>& S, const Pot
 
 template <typename T>
 __device__ __forceinline__ T tail_acc(const TailLevel<T>& S, const T* __restrict__ u, int t) {
-    const int nx = S.nx, j = t / nx, i = t - j * nx;
+    const int nx = S.nx, j = tail_div(t, S.inv), i = t - j * nx;
     const int e = i + 1 == nx ? t + 1 - nx : t + 1, w = i == 0 ? t - 1 + nx : t - 1;
     const int dn = j + 1 == S.ny ? 0 : nx, ds = j == 0 ? 0 : -nx;
     return ((S.c[0][t] * u[e] + S.c[1][t] * u[w]) + (S.c[2][t] * u[t + dn] + S.c[3][t] * u[t + ds])) +
@@ -679,7 +691,7 @@ constexpr int TAIL_MAXN = 4096;
 constexpr int TAIL_LPER = TAIL_MAXN / TAIL_T;
 
 template <typename T>
-__global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
+__global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* base = reinterpret_cast<T*>(lds_raw);
     const int tid = threadIdx.x;
@@ -693,7 +705,7 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         for (int r = 0; r < TAIL_LPER; ++r) {
             const int t = tid + r * TAIL_T;
             if (t < n) {
-                const int j = t / G.nx, i = t - j * G.nx;
+                const int j = tail_div(t, dv.inv[0]), i = t - j * G.nx;
                 const long long g = (long long)j * G.pitch + i;
                 m0[r] = G.mu[g];
                 f0[r] = G.f[g];
@@ -709,14 +721,14 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
             for (int r = 0; r < 2; ++r) {
                 const int t = tid + r * TAIL_T;
                 if (t < n) {
-                    const int j = t / G.nx, i = t - j * G.nx;
+                    const int j = tail_div(t, dv.inv[k]), i = t - j * G.nx;
                     mk[k - 1][r] = G.mu[(long long)j * G.pitch + i];
                 }
             }
         }
     }
     {
-        const TailLevel<T> S = tail_view(tl, base, 0);
+        const TailLevel<T> S = tail_view(tl, dv, base, 0);
         const int n = S.nx * S.ny;
 #pragma unroll
         for (int r = 0; r < TAIL_LPER; ++r) {
@@ -731,7 +743,7 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
 #pragma unroll
     for (int k = 1; k < MG_MAX_TAIL; ++k) {
         if (k < tl.n) {
-            const TailLevel<T> S = tail_view(tl, base, k);
+            const TailLevel<T> S = tail_view(tl, dv, base, k);
             const int n = S.nx * S.ny;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
@@ -742,13 +754,13 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
     }
     __syncthreads();
     for (int k = 0; k < tl.n; ++k) {
-        const TailLevel<T> S = tail_view(tl, base, k);
+        const TailLevel<T> S = tail_view(tl, dv, base, k);
         for (int t = tid; t < S.nx * S.ny; t += TAIL_T) tail_setup_node(S, tl.lv[k], t);
     }
     __syncthreads();
     const int sw = 2 * ((tl.nu1 + 1) / 2);  // even
     for (int k = 0; k + 1 < tl.n; ++k) {
-        const TailLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
+        const TailLevel<T> F = tail_view(tl, dv, base, k), Cc = tail_view(tl, dv, base, k + 1);
         tail_jacobi(F, sw);
         // fine residuals f - L u into the (free) ping-pong array, then their four-child
         // sums in the fixed order (0,0), (1,0), (0,1), (1,1)
@@ -757,7 +769,7 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         __syncthreads();
         const int n = Cc.nx * Cc.ny;
         for (int t = tid; t < n; t += TAIL_T) {
-            const int J = t / Cc.nx, I = t - J * Cc.nx;
+            const int J = tail_div(t, Cc.inv), I = t - J * Cc.nx;
             const T* r0 = F.alt + (2 * J) * F.nx + 2 * I;
             T s = T(0);
             s += r0[0];
@@ -770,29 +782,29 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl) {
         __syncthreads();
     }
     {
-        const TailLevel<T> S = tail_view(tl, base, tl.n - 1);
+        const TailLevel<T> S = tail_view(tl, dv, base, tl.n - 1);
         if (S.ny <= 4)
             tail_jacobi(S, 2 * tl.coarse_sweeps);
         else
             tail_sor(S, tl.coarse_sweeps, tl.omega);
     }
     for (int k = tl.n - 2; k >= 0; --k) {
-        const TailLevel<T> F = tail_view(tl, base, k), Cc = tail_view(tl, base, k + 1);
+        const TailLevel<T> F = tail_view(tl, dv, base, k), Cc = tail_view(tl, dv, base, k + 1);
         PotLevel<T> Cp = tl.lv[k + 1];  // the coarse correction as a level (for prolong_at)
         Cp.u = Cc.u;
         Cp.pitch = Cc.nx;
         const int n = F.nx * F.ny;
         for (int t = tid; t < n; t += TAIL_T) {
-            const int j = t / F.nx, i = t - j * F.nx;
+            const int j = tail_div(t, F.inv), i = t - j * F.nx;
             F.u[t] += prolong_at(Cp, i, j);
         }
         __syncthreads();
         tail_jacobi(F, sw);
     }
     const PotLevel<T> G = tl.lv[0];
-    const TailLevel<T> S = tail_view(tl, base, 0);
+    const TailLevel<T> S = tail_view(tl, dv, base, 0);
     for (int t = tid; t < S.nx * S.ny; t += TAIL_T) {
-        const int j = t / S.nx, i = t - j * S.nx;
+        const int j = tail_div(t, S.inv), i = t - j * S.nx;
         G.u[(long long)j * G.pitch + i] = S.u[t];
     }
 }
@@ -906,7 +918,9 @@ size_t mg_tail_lds_bytes(const MgTail<T>& tl) {
 
 template <typename T>
 void launch_mg_tail(const MgTail<T>& tl, hipStream_t s) {
-    hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(TAIL_T), mg_tail_lds_bytes<T>(tl), s, tl);
+    TailDiv dv{};
+    for (int k = 0; k < tl.n; ++k) dv.inv[k] = (unsigned)(((1ull << 32) + tl.lv[k].nx - 1) / tl.lv[k].nx);
+    hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(TAIL_T), mg_tail_lds_bytes<T>(tl), s, tl, dv);
 }
 
 template <typename T>
