@@ -96,7 +96,7 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     bt.step(8)  # past the start-up transient
     omegas = bt.tune_omega(4)
     bt.init_droplets()
-    rows, block, fused = bt.autotune(1)
+    rows, block, fused, tail_fused, tail_after = bt.autotune(1)
     bt.step(4)
     torch.cuda.synchronize()
     it0 = bt.stats()[1]
@@ -124,7 +124,8 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     return {"channels": len(ws), "sites": sites, "steps_per_channel": nsteps_target,
             "batch_fp32_ms_per_step": round(dt_batch * 1e3, 4), "batch_MLUPS": round(sites / dt_batch / 1e6, 1),
             "batch_sor_sweeps_per_step": round(sweeps, 2),
-            "schedule": {"tile_rows": rows, "block_sweeps": block, "fused_sweeps": fused},
+            "schedule": {"tile_rows": rows, "block_sweeps": block, "fused_sweeps": fused,
+                         "tail_fused_sweeps": tail_fused, "tail_after_sweeps": tail_after},
             "instances_per_hour_batch_fp32": round(batch_iph, 1),
             "instances_per_hour_sequential_fp64": round(seq_iph, 1) if seq_iph else None,
             "speedup": round(batch_iph / seq_iph, 2) if seq_iph else None,

@@ -270,20 +270,35 @@ fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double
  * 4 or 8), the potential sweeps are replayed as HIP graphs of block_sweeps sweeps (a
  * multiple of pot_check_every of channel 0, the interval of the device-side convergence
  * test, at most 2^20), and fused_sweeps > 0 runs that many four-colour SOR sweeps per
- * launch on 64 x 32 tiles with their halo in LDS (1 or 2; needs pot_check_every to be a
- * multiple of 2 fused_sweeps), 0 one launch per colour.  The schedule changes launch
- * geometry only: states are bitwise the same under every schedule.  Default: tile_rows
- * 4, block_sweeps 8 * pot_check_every, the largest fused_sweeps allowed.
+ * launch on 64 x 32 tiles with their halo in LDS (1 or 2 with pot_check_every a multiple
+ * of 2 fused_sweeps, or 4 with pot_check_every a multiple of 4; block_sweeps a multiple
+ * of 2 fused_sweeps), 0 one launch per colour.  The schedule changes launch geometry
+ * only: states are bitwise the same under every schedule.  Default: tile_rows 4,
+ * block_sweeps 8 * pot_check_every, the largest of fused_sweeps 2 and 1 allowed.
  * FCD_ERR_ARG for any other value. */
 fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block_sweeps, int32_t fused_sweeps);
 
+/* Tail fusion: the graph blocks of a potential solve that start at or after
+ * after_sweeps sweeps run fused_sweeps sweeps per fused launch instead of the
+ * schedule's (deep fusion repeats halo work, which costs most while many channels are
+ * active; late in a solve, when few are, the number of launches dominates).
+ * fused_sweeps 0 turns it off; otherwise a value fcd_batch_set_schedule would accept for
+ * the test interval.  Applies only while the schedule fuses (fused_sweeps > 0) and to
+ * block sizes that are a multiple of 2 fused_sweeps.  States are bitwise unchanged.
+ * Default: 4 after 16 * pot_check_every sweeps where 4 is allowed, else off.
+ * FCD_ERR_ARG for any other value. */
+fcd_status fcd_batch_set_tail_fusion(fcd_batch* b, int32_t fused_sweeps, int32_t after_sweeps);
+
 /* Autotuner: tries every tile_rows in {1, 2, 4, 8} with block_sweeps in
- * {2, 8, 32} * pot_check_every and every allowed fused_sweeps in {0, 1, 2}, each for
+ * {2, 8, 32} * pot_check_every and every allowed fused_sweeps in {0, 1, 2, 4}, each for
  * steps_per_candidate real steps of the batch (timed with HIP events; one untimed step
- * per tile shape and fusion first), keeps the fastest and writes it to
- * choice = {tile_rows, block_sweeps, fused_sweeps}.  Advances the batch by
- * 4 F (1 + 3 steps_per_candidate) steps, F the number of allowed fusions.  Sync. */
-fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[3]);
+ * per tile shape and fusion first), keeps the fastest; then, where 4 sweeps per launch
+ * are allowed, tries the tail fusion off and 4 after {8, 16, 32} * pot_check_every
+ * sweeps the same way (one untimed step each first).  Writes choice = {tile_rows,
+ * block_sweeps, fused_sweeps, tail fused_sweeps, tail after_sweeps}.  Advances the batch
+ * by 4 F (1 + 3 steps_per_candidate) steps, F the number of allowed fusions, plus
+ * 4 (1 + steps_per_candidate) for the tail fusion when 4 is allowed.  Sync. */
+fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[5]);
 
 /* SOR factor tuner: for each of the ncand (1..16) candidate scales s in scale[], every
  * channel relaxes with 2 / (1 + s sin(pi / (ny + 1))) for `steps` real steps while the

@@ -882,10 +882,10 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     off = align256(off + (size_t)L->nstiles * sizeof(int));
     L->off_slist = off;  // active fused tiles, then their count
     off = align256(off + ((size_t)L->nstiles + 1) * sizeof(int));
-    L->off_res = off;  // two sets of residual slots (consecutive tests alternate)
-    off = align256(off + 4 * (size_t)n * sizeof(unsigned long long));
-    L->off_active = off;
-    off = align256(off + (size_t)n * sizeof(int));
+    L->off_res = off;  // three sets of residual slots (consecutive tests rotate)
+    off = align256(off + 6 * (size_t)n * sizeof(unsigned long long));
+    L->off_active = off;  // two buffers of activity flags
+    off = align256(off + 2 * (size_t)n * sizeof(int));
     L->off_counts = off;
     off = align256(off + 2 * sizeof(int));
     L->off_sweeps = off;
@@ -924,6 +924,9 @@ struct fcd_batch {
     int shape;
     int block_sweeps;
     int fused;
+    // tail fusion: blocks that start at or after tail_after sweeps of a solve use
+    // tail_fused sweeps per fused launch instead (0: off)
+    int tail_fused, tail_after;
     GraphCache graphs;
     // batched adjoint
     int init_fresh;
@@ -1060,7 +1063,7 @@ fcd_status batch_upload(fcd_batch* b) {
                    "active tile list");
     if (st) return st;
     // residual slots start (and are always left) at zero
-    return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 4 * (size_t)b->n * sizeof(unsigned long long)),
+    return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 6 * (size_t)b->n * sizeof(unsigned long long)),
                      "residual slots");
 }
 
@@ -1071,10 +1074,24 @@ const fcd::BatchInst<T>* binst(const fcd_batch* b) {
 
 int check_interval(const fcd_batch* b) { return std::max(1, b->prm[0].pot_check_every); }
 
-// f sweeps per fused launch need a test interval that is a multiple of 2 f (f = 0: one
-// launch per colour, always allowed).
+// Sweeps per fused launch: f = 1 or 2 need a test interval that is a multiple of 2 f (an
+// even number of launches per interval, so every test finds the potential in its own
+// plane); f = 4 needs a multiple of 4 (its launches copy a channel stopped on odd parity
+// back to its plane); f = 0 (one launch per colour) is always allowed.
 bool fused_allowed(const fcd_batch* b, int f) {
-    return f == 0 || (f >= 1 && f <= fcd::FUSED_MAX && check_interval(b) % (2 * f) == 0);
+    const int c = check_interval(b);
+    return f == 0 || ((f == 1 || f == 2) && c % (2 * f) == 0) || (f == 4 && c % 4 == 0);
+}
+
+// Sweeps per fused launch of the graph block that starts after `done` sweeps of a
+// solve: the tail fusion from tail_after sweeps on (when the block size allows it: an
+// even number of launches per block), else the schedule's.  Every choice gives the same
+// states, so this only trades the repeated halo work of deep fusion, which costs most
+// while many channels are active, against launches, which dominate once few are.
+int block_fusion(const fcd_batch* b, int done) {
+    if (b->fused > 0 && b->tail_fused > 0 && done >= b->tail_after && b->block_sweeps % (2 * b->tail_fused) == 0)
+        return b->tail_fused;
+    return b->fused;
 }
 
 // The problem a batched potential solve works on: the descriptors (u, f, mu, thresholds)
@@ -1094,51 +1111,51 @@ BatchProblem<T> forward_problem(fcd_batch* b) {
 }
 
 // A block of `block_sweeps` SOR sweeps with a device-side convergence test after every
-// `check` sweeps (block_sweeps is a multiple of check).  Fused launches alternate the
-// potential between its plane and the second plane; check is a multiple of twice the
-// sweeps per fused launch, so the potential is back in its own plane at every test, and
-// a test launch is never the launch right after another test.  With fused launches a
-// test's decision is taken by the next launch (consecutive tests use the two sets of
-// residual slots in turn, the deciding launch clearing the set of the next test); the
-// block's last test is decided by the decision kernel, which leaves both sets at zero
-// and sets the counts the host reads.
+// `check` sweeps (block_sweeps is a multiple of check and of twice the sweeps per fused
+// launch, so a block has an even number of fused launches and ends with the potential
+// in its own plane).  Fused launches alternate the potential between its plane and the
+// second plane.  With fused launches a test's decision is taken by the next launch,
+// which may itself be a test: consecutive tests rotate over three sets of residual slots
+// (the test's, the one being decided, and the one the deciding launch clears for the
+// next test that is not its own), and a deciding launch writes the other of the two
+// flag buffers.  The block's last test is decided by the decision kernel, which leaves
+// every set at zero, both flag buffers equal, and the counts the host reads.
 template <typename T>
-void batch_block(fcd_batch* b, const BatchProblem<T>& P) {
-    const fcd::BatchTiles t = btiles(b);
+void batch_block(fcd_batch* b, const BatchProblem<T>& P, int fused) {
+    fcd::BatchTiles t = btiles(b);
+    t.fused = fused;
+    const int n = b->n;
     int* active = bptr<int>(b->scratch, b->L.off_active);
     const int check = check_interval(b);
     unsigned long long* res = bptr<unsigned long long>(b->scratch, b->L.off_res);
-    unsigned long long* rset[2] = {res, res + 2 * (size_t)b->n};
+    unsigned long long* rset[3] = {res, res + 2 * (size_t)n, res + 4 * (size_t)n};
     int* counts = bptr<int>(b->scratch, b->L.off_counts);
     int* sweeps = bptr<int>(b->scratch, b->L.off_sweeps);
     const int per = t.fused > 0 ? t.fused : 1;
-    int parity = 0, tests = 0;
+    int parity = 0, tests = 0, cur = 0;
     bool pending = false;  // a test whose decision has not been taken yet
     for (int s = per; s <= b->block_sweeps; s += per) {
         const bool test = s % check == 0;
         if (t.fused > 0) {
-            if (pending && test) {  // not with the allowed intervals; kept correct anyway
-                fcd::launch_batch_decide<T>(P.inst, t, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts,
-                                            P.scale, P.rel_tol, sweeps, check, b->stream);
-                pending = false;
-            }
             fcd::BatchDecide dec{};
-            if (pending) dec = {rset[(tests - 1) & 1], rset[tests & 1], P.scale, P.rel_tol, sweeps, check};
-            fcd::launch_batch_sweep_fused<T>(P.inst, t, active, parity, P.rhs_plane, test ? rset[tests & 1] : nullptr,
-                                             dec, b->stream);
+            if (pending)
+                dec = {rset[(tests - 1) % 3], rset[(test ? tests + 1 : tests) % 3], P.scale, P.rel_tol, sweeps, check};
+            fcd::launch_batch_sweep_fused<T>(P.inst, t, active + cur * n, active + (1 - cur) * n, parity,
+                                             P.rhs_plane, test ? rset[tests % 3] : nullptr, dec, b->stream);
+            if (pending) cur = 1 - cur;
             parity ^= 1;
             pending = test;
             tests += test;
         } else {
             fcd::launch_batch_sweep<T>(P.inst, t, active, b->stream);
             if (test)
-                fcd::launch_batch_check<T>(P.inst, t, b->n, res, active, counts, P.scale, P.rel_tol, sweeps, check,
+                fcd::launch_batch_check<T>(P.inst, t, n, res, active, counts, P.scale, P.rel_tol, sweeps, check,
                                            b->stream);
         }
     }
     if (pending)
-        fcd::launch_batch_decide<T>(P.inst, t, b->n, rset[(tests - 1) & 1], rset[tests & 1], active, counts, P.scale,
-                                    P.rel_tol, sweeps, check, b->stream);
+        fcd::launch_batch_decide<T>(P.inst, t, n, rset[(tests - 1) % 3], rset[tests % 3], rset[(tests + 1) % 3], active,
+                                    cur, counts, P.scale, P.rel_tol, sweeps, check, b->stream);
 }
 
 template <typename T>
@@ -1164,7 +1181,7 @@ template <typename T>
 fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
     const fcd::BatchTiles t = btiles(b);
     int* active = bptr<int>(b->scratch, b->L.off_active);
-    fcd::launch_fill<int>(active, b->n, 1, b->stream);
+    fcd::launch_fill<int>(active, 2 * b->n, 1, b->stream);
     fcd::launch_batch_check<T>(P.inst, t, b->n, bptr<unsigned long long>(b->scratch, b->L.off_res), active,
                                bptr<int>(b->scratch, b->L.off_counts), P.scale, P.rel_tol,
                                bptr<int>(b->scratch, b->L.off_sweeps), 0, b->stream);
@@ -1179,8 +1196,9 @@ fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
     }
     while (left > 0) {
         if (it >= max_iters) break;
-        st = run_graph_on(b->graphs, b->stream, false, P.inst, nullptr, ((b->fused * 8 + b->shape) << 24) + G,
-                          [&]() { batch_block<T>(b, P); });
+        const int f = block_fusion(b, it);
+        st = run_graph_on(b->graphs, b->stream, false, P.inst, nullptr, ((f * 8 + b->shape) << 24) + G,
+                          [&]() { batch_block<T>(b, P, f); });
         if (st) return st;
         it += G;
         if (blind > 0) {
@@ -1218,11 +1236,13 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
     return FCD_OK;
 }
 
-// Autotuner: every (tile shape, block size) candidate advances the batch by `steps`
-// real steps, timed with HIP events on the batch stream after one untimed step per
-// shape; the fastest is kept.  The candidates differ only in launch geometry and in how
-// sweeps are grouped into graph launches, so the states they produce are bitwise the
-// same as an untuned run's.
+// Autotuner: every (fusion, tile shape, block size) candidate advances the batch by
+// `steps` real steps, timed with HIP events on the batch stream after one untimed step
+// per fusion and shape; the fastest is kept.  Then, where four sweeps per launch are
+// allowed, the tail fusion is chosen the same way among off and four sweeps per launch
+// after 8, 16 or 32 tests (one untimed step each first).  The candidates differ only in
+// launch geometry and in how sweeps are grouped into launches and graph launches, so
+// the states they produce are bitwise the same as an untuned run's.
 template <typename T>
 fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
     const int check = check_interval(b);
@@ -1232,6 +1252,13 @@ fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     fcd_status st = hip_check(hipEventCreate(&e0), "event");
     if (!st) st = hip_check(hipEventCreate(&e1), "event");
+    auto timed = [&](float* ms) {
+        if (!st) st = hip_check(hipEventRecord(e0, b->stream), "event");
+        if (!st) st = batch_step_impl<T>(b, steps);
+        if (!st) st = hip_check(hipEventRecord(e1, b->stream), "event");
+        if (!st) st = hip_check(hipEventSynchronize(e1), "event");
+        if (!st) st = hip_check(hipEventElapsedTime(ms, e0, e1), "event");
+    };
     for (int f = 0; f <= fcd::FUSED_MAX && !st; ++f) {
       if (!fused_allowed(b, f)) continue;
       for (int s = 0; s < fcd::BATCH_SHAPES && !st; ++s) {
@@ -1240,12 +1267,8 @@ fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
             b->shape = s;
             b->block_sweeps = blocks[g];
             if (g == 0) st = batch_step_impl<T>(b, 1);  // warms the shape's kernels and graphs
-            if (!st) st = hip_check(hipEventRecord(e0, b->stream), "event");
-            if (!st) st = batch_step_impl<T>(b, steps);
-            if (!st) st = hip_check(hipEventRecord(e1, b->stream), "event");
-            if (!st) st = hip_check(hipEventSynchronize(e1), "event");
             float ms = 0.f;
-            if (!st) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "event");
+            timed(&ms);
             if (!st && ms < best) {
                 best = ms;
                 best_shape = s;
@@ -1255,14 +1278,35 @@ fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
         }
       }
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     b->shape = best_shape;
     b->block_sweeps = best_block;
     b->fused = best_fused;
-    choice[0] = BT_ROWS[best_shape];
-    choice[1] = best_block;
-    choice[2] = best_fused;
+    if (fused_allowed(b, 4)) {
+        const int tails[4][2] = {{0, 0}, {4, 8 * check}, {4, 16 * check}, {4, 32 * check}};
+        double tbest = 1e300;
+        int bt = b->tail_fused, ba = b->tail_after;
+        for (int c = 0; c < 4 && !st; ++c) {
+            b->tail_fused = tails[c][0];
+            b->tail_after = tails[c][1];
+            st = batch_step_impl<T>(b, 1);
+            float ms = 0.f;
+            timed(&ms);
+            if (!st && ms < tbest) {
+                tbest = ms;
+                bt = tails[c][0];
+                ba = tails[c][1];
+            }
+        }
+        b->tail_fused = bt;
+        b->tail_after = ba;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    choice[0] = BT_ROWS[b->shape];
+    choice[1] = b->block_sweeps;
+    choice[2] = b->fused;
+    choice[3] = b->tail_fused;
+    choice[4] = b->tail_after;
     return st;
 }
 
@@ -2112,9 +2156,12 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     b->adj_nsteps = b->adj_every = b->adj_from_init = 0;
     b->adj_final_iters = b->adj_final_hist = b->adj_solve_iters = 0;
     b->block_sweeps = 8 * std::max(1, prms[0].pot_check_every);
-    b->fused = 0;
-    for (int f = fcd::FUSED_MAX; f >= 1 && b->fused == 0; --f)
+    b->fused = 0;  // default: the deepest fusion allowed up to two sweeps per launch
+    for (int f = 2; f >= 1 && b->fused == 0; --f)
         if (fused_allowed(b, f)) b->fused = f;
+    // and four sweeps per launch after 16 tests
+    b->tail_fused = fused_allowed(b, 4) ? 4 : 0;
+    b->tail_after = 16 * check_interval(b);
     if (hipHostMalloc(reinterpret_cast<void**>(&b->host), (1 + 4 * (size_t)n) * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         delete b;
@@ -2161,7 +2208,7 @@ fcd_status fcd_batch_read_moments(fcd_batch* b, int32_t k, uint32_t mask, double
     return FCD_BDISPATCH(b, batch_moments_impl)(b, k, mask, out);
 }
 
-fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[3]) {
+fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[5]) {
     if (!b || !choice) return fail(FCD_ERR_ARG, "null argument");
     if (steps_per_candidate < 1) return fail(FCD_ERR_ARG, "steps_per_candidate must be >= 1");
     return FCD_BDISPATCH(b, batch_autotune_impl)(b, steps_per_candidate, choice);
@@ -2183,11 +2230,23 @@ fcd_status fcd_batch_set_schedule(fcd_batch* b, int32_t tile_rows, int32_t block
     if (s < 0) return fail(FCD_ERR_ARG, "tile_rows must be 1, 2, 4 or 8");
     if (block_sweeps < 1 || block_sweeps > (1 << 20) || block_sweeps % check_interval(b))
         return fail(FCD_ERR_ARG, "block_sweeps must be a positive multiple of pot_check_every, at most 2^20");
-    if (!fused_allowed(b, fused_sweeps))
-        return fail(FCD_ERR_ARG, "fused_sweeps must be 0, or 1 or 2 with pot_check_every a multiple of 2 fused_sweeps");
+    if (!fused_allowed(b, fused_sweeps) || (fused_sweeps > 0 && block_sweeps % (2 * fused_sweeps)))
+        return fail(FCD_ERR_ARG,
+                    "fused_sweeps must be 0, 1 or 2 with pot_check_every a multiple of 2 fused_sweeps, or 4 with "
+                    "pot_check_every a multiple of 4; block_sweeps a multiple of 2 fused_sweeps");
     b->shape = s;
     b->block_sweeps = block_sweeps;
     b->fused = fused_sweeps;
+    return FCD_OK;
+}
+
+fcd_status fcd_batch_set_tail_fusion(fcd_batch* b, int32_t fused_sweeps, int32_t after_sweeps) {
+    if (!b) return fail(FCD_ERR_ARG, "batch is null");
+    if (after_sweeps < 0) return fail(FCD_ERR_ARG, "after_sweeps must be >= 0");
+    if (fused_sweeps != 0 && (!fused_allowed(b, fused_sweeps) || fused_sweeps == 0))
+        return fail(FCD_ERR_ARG, "tail fused_sweeps must be 0 (off) or a fusion the test interval allows");
+    b->tail_fused = fused_sweeps;
+    b->tail_after = after_sweeps;
     return FCD_OK;
 }
 

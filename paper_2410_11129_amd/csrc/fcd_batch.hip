@@ -209,12 +209,13 @@ constexpr double decide_floor() {
     return 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
 }
 
-template <typename T, int NS, bool HF>
+template <typename T, int NS, bool HF, bool CP>
 __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __restrict__ inst,
                                                          const int* __restrict__ stile_inst,
                                                          const int* __restrict__ slist, const int* __restrict__ scount,
-                                                         int* __restrict__ active, int parity,
-                                                         unsigned long long* __restrict__ res, BatchDecide dec) {
+                                                         const int* __restrict__ act_in, int* __restrict__ act_out,
+                                                         int parity, unsigned long long* __restrict__ res,
+                                                         BatchDecide dec) {
     using F = FusedLds<NS>;
     constexpr int H = F::H, HX = F::HX, HN = HX * F::HY, NT = FUSED_NT;
     __shared__ T su[F::N];
@@ -228,25 +229,34 @@ __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __r
         const int tile = slist[b];
         const int k = stile_inst[tile];
         const BatchInst<T>& B = inst[k];
-        // Another block of the channel may already have stored the decision read here;
-        // it is the same decision, so either value leads to the same one.
-        int act = active[k];
+        // the flags of a deciding launch go to the other buffer, so every block of the
+        // channel reads the flag from before the decision
+        const int was = act_in[k];
+        int act = was;
         if (dec.res) {
-            const int was = act;
             if (act) act = channel_active(inst, dec.res, k, dec.scale, dec.rel_tol, decide_floor<T>());
             if (tile == B.stile0 && threadIdx.x == 0) {
                 if (was) dec.sweeps[k] += dec.add;
-                active[k] = act;
+                act_out[k] = act;
                 dec.clear[2 * k] = 0ULL;
                 dec.clear[2 * k + 1] = 0ULL;
             }
         }
-        if (!act) continue;  // uniform over the block
         const PotLevel<T> L = B.L0;
         const T* __restrict__ uin = parity ? B.alt : L.u;
         T* __restrict__ uout = parity ? L.u : B.alt;
         const int lt = tile - B.stile0, ty = lt / B.stiles_x, tx = lt - ty * B.stiles_x;
         const int i0 = tx * FUSED_X, j0 = ty * FUSED_Y;
+        if (!act) {  // uniform over the block
+            // a channel stopped by this launch's decision whose last result is in the
+            // second plane (odd parity): its tiles move it back to the potential's plane
+            if (CP && dec.res && was && parity)
+                for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += NT) {
+                    const int i = i0 + (q & (FUSED_X - 1)), j = j0 + q / FUSED_X;
+                    if (i < L.nx && j < L.ny) uout[(long long)j * L.pitch + i] = uin[(long long)j * L.pitch + i];
+                }
+            continue;
+        }
         // all loads into registers first, then the LDS stores, so that the loads of a
         // thread are in flight together
         constexpr int LPER = (HN + NT - 1) / NT;
@@ -351,16 +361,19 @@ __global__ void __launch_bounds__(TBX* TY) kb_residual(const BatchInst<T>* __res
 
 // One block: a channel stays active while its residual is above max(thr, floor * scale)
 // (an inactive channel stays inactive for the rest of the solve); the residual slots are
-// cleared for the next test, and so are those of also_clear when set; counts[0] =
-// channels still active, counts[1] = channels whose residual is NaN; sweeps[k] grows by
-// `add` (the sweeps since the previous test) for every channel active on entry.
+// cleared for the next test, and so are those of also_clear and also_clear2 when set;
+// the flags are read from buffer `cur` of the two (active[cur * n + k]) and written to
+// both; counts[0] = channels still active, counts[1] = channels whose residual is NaN;
+// sweeps[k] grows by `add` (the sweeps since the previous test) for every channel
+// active on entry.
 constexpr int DECIDE_T = 256;
 
 template <typename T>
 __global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __restrict__ inst,
                                                       unsigned long long* __restrict__ res,
-                                                      unsigned long long* __restrict__ also_clear, int n,
-                                                      int* __restrict__ active, int* __restrict__ counts,
+                                                      unsigned long long* __restrict__ also_clear,
+                                                      unsigned long long* __restrict__ also_clear2, int n,
+                                                      int* __restrict__ active, int cur, int* __restrict__ counts,
                                                       const unsigned long long* __restrict__ scale, double rel_tol,
                                                       int* __restrict__ sweeps, int add, int* __restrict__ slist,
                                                       int* __restrict__ scount) {
@@ -372,15 +385,22 @@ __global__ void __launch_bounds__(DECIDE_T) kb_decide(const BatchInst<T>* __rest
             also_clear[2 * k] = 0ULL;
             also_clear[2 * k + 1] = 0ULL;
         }
-        if (!active[k]) continue;
-        sweeps[k] += add;
-        const double r = __longlong_as_double((long long)res[2 * k]);
-        const int a = channel_active(inst, res, k, scale, rel_tol, decide_floor<T>());
-        active[k] = a;
-        a_sum += a;
-        nan_sum += r != r;
-        res[2 * k] = 0ULL;
-        res[2 * k + 1] = 0ULL;
+        if (also_clear2) {
+            also_clear2[2 * k] = 0ULL;
+            also_clear2[2 * k + 1] = 0ULL;
+        }
+        int a = 0;
+        if (active[cur * n + k]) {
+            sweeps[k] += add;
+            const double r = __longlong_as_double((long long)res[2 * k]);
+            a = channel_active(inst, res, k, scale, rel_tol, decide_floor<T>());
+            a_sum += a;
+            nan_sum += r != r;
+            res[2 * k] = 0ULL;
+            res[2 * k + 1] = 0ULL;
+        }
+        active[k] = a;  // both flag buffers
+        active[n + k] = a;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -482,15 +502,20 @@ void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int
 }
 
 template <typename T>
-void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, int* active, int parity,
-                              bool rhs_plane, unsigned long long* res, const BatchDecide& dec, hipStream_t s) {
-#define C_(NS, HF)                                                                                                 \
-    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF>), dim3(t.sgrid), dim3(FUSED_NT), 0, s, inst, t.stiles, t.slist, \
-                       t.scount, active, parity, res, dec)
+void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, const int* act_in, int* act_out,
+                              int parity, bool rhs_plane, unsigned long long* res, const BatchDecide& dec,
+                              hipStream_t s) {
+#define C_(NS, HF, CP)                                                                                      \
+    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF, CP>), dim3(t.sgrid), dim3(FUSED_NT), 0, s, inst, t.stiles,    \
+                       t.slist, t.scount, act_in, act_out, parity, res, dec)
+    // copies on stop only where a decision can meet odd parity (an odd number of
+    // launches per test interval); the other variants carry no copy code
     if (t.fused == 1) {
-        if (rhs_plane) C_(1, true); else C_(1, false);
+        if (rhs_plane) C_(1, true, false); else C_(1, false, false);
+    } else if (t.fused == 2) {
+        if (rhs_plane) C_(2, true, false); else C_(2, false, false);
     } else {
-        if (rhs_plane) C_(2, true); else C_(2, false);
+        if (rhs_plane) C_(4, true, true); else C_(4, false, true);
     }
 #undef C_
 }
@@ -503,15 +528,16 @@ void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, un
     hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
     FCD_SHAPE_SWITCH(t.shape, C_)
 #undef C_
-    launch_batch_decide<T>(inst, t, n, res, nullptr, active, counts, scale, rel_tol, sweeps, add, s);
+    launch_batch_decide<T>(inst, t, n, res, nullptr, nullptr, active, 0, counts, scale, rel_tol, sweeps, add, s);
 }
 
 template <typename T>
 void launch_batch_decide(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
-                         unsigned long long* also_clear, int* active, int* counts, const unsigned long long* scale,
-                         double rel_tol, int* sweeps, int add, hipStream_t s) {
-    hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, also_clear, n, active, counts, scale,
-                       rel_tol, sweeps, add, t.slist, t.scount);
+                         unsigned long long* also_clear, unsigned long long* also_clear2, int* active, int cur,
+                         int* counts, const unsigned long long* scale, double rel_tol, int* sweeps, int add,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(kb_decide<T>, dim3(1), dim3(DECIDE_T), 0, s, inst, res, also_clear, also_clear2, n, active, cur,
+                       counts, scale, rel_tol, sweeps, add, t.slist, t.scount);
 }
 
 template <typename T>
@@ -533,11 +559,11 @@ void launch_batch_fill_psi(const BatchInst<T>* inst, const BatchTiles& t, hipStr
     template void launch_batch_phase<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);           \
     template void launch_batch_collide<T>(const BatchInst<T>*, const BatchTiles&, int, hipStream_t);         \
     template void launch_batch_sweep<T>(const BatchInst<T>*, const BatchTiles&, const int*, hipStream_t);    \
-    template void launch_batch_sweep_fused<T>(const BatchInst<T>*, const BatchTiles&, int*, int, bool,       \
-                                              unsigned long long*, const BatchDecide&, hipStream_t);         \
+    template void launch_batch_sweep_fused<T>(const BatchInst<T>*, const BatchTiles&, const int*, int*, int, \
+                                              bool, unsigned long long*, const BatchDecide&, hipStream_t);   \
     template void launch_batch_decide<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,   \
-                                         unsigned long long*, int*, int*, const unsigned long long*, double, \
-                                         int*, int, hipStream_t);                                            \
+                                         unsigned long long*, unsigned long long*, int*, int, int*,          \
+                                         const unsigned long long*, double, int*, int, hipStream_t);         \
     template void launch_batch_check<T>(const BatchInst<T>*, const BatchTiles&, int, unsigned long long*,    \
                                         int*, int*, const unsigned long long*, double, int*, int,            \
                                         hipStream_t);                                                        \

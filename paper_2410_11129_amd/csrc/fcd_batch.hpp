@@ -57,7 +57,7 @@ struct BatchTiles {
 };
 
 // Fused-sweep tile: 64 x 32 nodes plus a halo of 4 nodes per sweep, 512 threads.
-constexpr int FUSED_X = 64, FUSED_Y = 32, FUSED_MAX = 2, FUSED_NT = 512;
+constexpr int FUSED_X = 64, FUSED_Y = 32, FUSED_MAX = 4, FUSED_NT = 512;
 
 template <typename T>
 void launch_batch_phase(const BatchInst<T>* inst, const BatchTiles& t, int cur, hipStream_t s);
@@ -68,10 +68,13 @@ template <typename T>
 void launch_batch_sweep(const BatchInst<T>* inst, const BatchTiles& t, const int* active, hipStream_t s);
 // The activity decision of a test carried out at the start of the next fused sweep
 // launch instead of by a kernel of its own: every block decides its own channel from
-// the test's residual slots (the blocks of a channel all reach the same decision, the
-// one launch_batch_decide takes); the channel's first block stores it, adds `add` to
-// sweeps[k] if the channel was active, and zeroes the channel's slots in `clear` (those
-// of the following test).  res == nullptr: no decision in this launch.
+// the test's residual slots and the flag before the decision (the blocks of a channel
+// all reach the same decision, the one launch_batch_decide takes); the channel's first
+// block stores it in the other flag buffer, adds `add` to sweeps[k] if the channel was
+// active, and zeroes the channel's slots in `clear` (those of the next test that is not
+// this launch's).  A channel stopped by the decision whose result is in the second
+// plane (odd parity) is copied back to its own plane by its tiles.  res == nullptr: no
+// decision in this launch.
 struct BatchDecide {
     const unsigned long long* res;
     unsigned long long* clear;
@@ -80,23 +83,27 @@ struct BatchDecide {
     int* sweeps;
     int add;
 };
-// t.fused four-colour SOR sweeps of the active channels in one launch, bitwise equal to
-// as many launch_batch_sweep calls; parity 0 reads L0.u and writes alt, parity 1 the
-// reverse.  rhs_plane: the descriptors' L0.f is set (else the field gives the rhs).
+// t.fused (1, 2 or 4) four-colour SOR sweeps of the active channels in one launch,
+// bitwise equal to as many launch_batch_sweep calls; parity 0 reads L0.u and writes alt,
+// parity 1 the reverse.  rhs_plane: the descriptors' L0.f is set (else the field gives
+// the rhs).  Activity flags are read from act_in; a deciding launch writes act_out.
 // res != nullptr: also reduce the residual of the result as launch_batch_check does
 // (a decision has to follow, folded into the next launch or by launch_batch_decide);
-// res must not be dec.clear.
+// res, dec.res and dec.clear are three different slot sets.
 template <typename T>
-void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, int* active, int parity,
-                              bool rhs_plane, unsigned long long* res, const BatchDecide& dec, hipStream_t s);
+void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, const int* act_in, int* act_out,
+                              int parity, bool rhs_plane, unsigned long long* res, const BatchDecide& dec,
+                              hipStream_t s);
 // The activity decision of launch_batch_check alone, on residual slots already filled;
-// also_clear (may be null): more slots to zero, those of an earlier test decided by a
-// fused launch.  Also lists the fused tiles of the channels left active (t.slist,
-// t.scount) for the following fused launches.
+// also_clear, also_clear2 (may be null): more slot sets to zero, those of earlier tests
+// decided by fused launches.  Flags are read from buffer cur of the two at `active`
+// (2 n ints) and written to both.  Also lists the fused tiles of the channels left
+// active (t.slist, t.scount) for the following fused launches.
 template <typename T>
 void launch_batch_decide(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
-                         unsigned long long* also_clear, int* active, int* counts, const unsigned long long* scale,
-                         double rel_tol, int* sweeps, int add, hipStream_t s);
+                         unsigned long long* also_clear, unsigned long long* also_clear2, int* active, int cur,
+                         int* counts, const unsigned long long* scale, double rel_tol, int* sweeps, int add,
+                         hipStream_t s);
 // Residual of the active channels, then the activity decision; res must be zero on entry
 // and is left zero; counts[0..1] = active channels, channels with a NaN residual.
 // scale != nullptr: channel k's threshold is rel_tol * scale[k] (bit pattern of a

@@ -31,7 +31,7 @@ EXPORTS = (
     "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
     "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
-    "fcd_batch_read_moments", "fcd_batch_set_schedule", "fcd_batch_autotune", "fcd_batch_tune_omega", "fcd_batch_adjoint_bytes",
+    "fcd_batch_read_moments", "fcd_batch_set_schedule", "fcd_batch_set_tail_fusion", "fcd_batch_autotune", "fcd_batch_tune_omega", "fcd_batch_adjoint_bytes",
     "fcd_batch_adjoint_forward", "fcd_batch_adjoint_backward", "fcd_batch_stats",
     "fcd_batch_destroy",
 )
@@ -110,6 +110,7 @@ def lib():
         L.fcd_batch_init_compound_droplet.argtypes = [H, dp]
         L.fcd_batch_step.argtypes = [H, C.c_int32]
         L.fcd_batch_set_schedule.argtypes = [H, C.c_int32, C.c_int32, C.c_int32]
+        L.fcd_batch_set_tail_fusion.argtypes = [H, C.c_int32, C.c_int32]
         L.fcd_batch_adjoint_bytes.argtypes = [H, C.c_int32, C.c_int32]
         L.fcd_batch_adjoint_bytes.restype = C.c_size_t
         L.fcd_batch_adjoint_forward.argtypes = [H, C.c_int32, C.c_int32, C.c_void_p, dp]
@@ -300,10 +301,14 @@ def fcd_batch_set_schedule(b, tile_rows: int, block_sweeps: int, fused_sweeps: i
     _check(lib().fcd_batch_set_schedule(b, tile_rows, block_sweeps, fused_sweeps), "fcd_batch_set_schedule")
 
 
+def fcd_batch_set_tail_fusion(b, fused_sweeps: int, after_sweeps: int):
+    _check(lib().fcd_batch_set_tail_fusion(b, fused_sweeps, after_sweeps), "fcd_batch_set_tail_fusion")
+
+
 def fcd_batch_autotune(b, steps_per_candidate: int):
-    out = (C.c_int32 * 3)()
+    out = (C.c_int32 * 5)()
     _check(lib().fcd_batch_autotune(b, steps_per_candidate, out), "fcd_batch_autotune")
-    return int(out[0]), int(out[1]), int(out[2])
+    return tuple(int(v) for v in out)
 
 
 def fcd_batch_tune_omega(b, n: int, steps: int, scales):

@@ -179,9 +179,12 @@ class Batch:
     def set_schedule(self, tile_rows: int, block_sweeps: int, fused_sweeps: int):
         fcd.fcd_batch_set_schedule(self.h, tile_rows, block_sweeps, fused_sweeps)
 
+    def set_tail_fusion(self, fused_sweeps: int, after_sweeps: int):
+        fcd.fcd_batch_set_tail_fusion(self.h, fused_sweeps, after_sweeps)
+
     def autotune(self, steps_per_candidate: int = 2):
-        """Pick the launch schedule by timing real steps; returns
-        (tile_rows, block_sweeps, fused_sweeps)."""
+        """Pick the launch schedule by timing real steps; returns (tile_rows,
+        block_sweeps, fused_sweeps, tail fused_sweeps, tail after_sweeps)."""
         return fcd.fcd_batch_autotune(self.h, steps_per_candidate)
 
     def tune_omega(self, steps: int = 4, scales=(1.25, 1.0, 0.9, 0.775)):

@@ -90,10 +90,11 @@ def test_bad_params_and_null_buffers_rejected():
 def test_batch_schedule_calls_and_warm_start_order_validated_on_host():
     """Null batches and out-of-range settings are rejected before any device work."""
     L = fcd.lib()
-    choice = (C.c_int32 * 3)()
+    choice = (C.c_int32 * 5)()
     scales = (C.c_double * 2)(1.0, 0.9)
     out = (C.c_double * 4)()
     assert L.fcd_batch_set_schedule(None, 4, 8, 2) == fcd.FCD_ERR_ARG
+    assert L.fcd_batch_set_tail_fusion(None, 4, 64) == fcd.FCD_ERR_ARG
     assert L.fcd_batch_autotune(None, 1, choice) == fcd.FCD_ERR_ARG
     assert L.fcd_batch_tune_omega(None, 4, 2, scales, out) == fcd.FCD_ERR_ARG
     lat = fcd.fcd_lattice(200, 50, fcd.FCD_FP64, 256)

@@ -119,8 +119,9 @@ def test_batch_deterministic_and_single_channel_batch():
 
 @pytest.mark.parametrize("precision", [fcd.FCD_FP64, fcd.FCD_FP32])
 def test_batch_schedules_and_autotuner_do_not_change_results(precision):
-    """Tile shapes, graph block sizes and fused sweeps change launch geometry only: every
-    schedule, and the autotuner's trial steps, give the same states bit for bit."""
+    """Tile shapes, graph block sizes, fused sweeps and tail fusion change launch geometry
+    only: every schedule, and the autotuner's trial steps, give the same states bit for
+    bit."""
     ws = uneven_channels()
     say(f"case batch schedules precision {precision}")
     tol = 1e-12 if precision == fcd.FCD_FP64 else 1e-5
@@ -128,20 +129,24 @@ def test_batch_schedules_and_autotuner_do_not_change_results(precision):
     ref.init_droplets()
     ref.step(6)
     want = [ref.state(k) for k in range(len(ws))]
-    for rows, block, fused in ((1, 4, 0), (8, 128, 1), (2, 32, 2), (4, 8, 0)):
+    for rows, block, fused, tail in ((1, 4, 0, 0), (8, 128, 1, 4), (2, 32, 2, 0), (4, 8, 0, 4), (8, 8, 4, 0),
+                                     (2, 32, 4, 2), (4, 8, 2, 4)):
         bt = Batch(ws, precision=precision, tol=tol)
         bt.set_schedule(rows, block, fused)
+        bt.set_tail_fusion(tail, 8)  # blocks from the ninth sweep of a solve on
         bt.init_droplets()
         for _ in range(3):  # several graph replays with eager work between them
             bt.step(2)
         for k in range(len(ws)):
-            assert np.array_equal(bt.state(k), want[k]), (rows, block, fused, k)
+            assert np.array_equal(bt.state(k), want[k]), (rows, block, fused, tail, k)
         bt.close()
     tuned = Batch(ws, precision=precision, tol=tol)
     tuned.init_droplets()
-    rows, block, fused = tuned.autotune(1)  # advances 3 * 4 * (1 + 3) = 48 steps
-    assert rows in (1, 2, 4, 8) and block % 4 == 0 and fused in (0, 1, 2)
-    ref.step(42)
+    # advances 4 * 4 * (1 + 3) = 64 steps, then 4 * (1 + 1) for the tail fusion
+    rows, block, fused, tail, after = tuned.autotune(1)
+    assert rows in (1, 2, 4, 8) and block % 4 == 0 and fused in (0, 1, 2, 4)
+    assert (tail, after) in ((0, 0), (4, 32), (4, 64), (4, 128))
+    ref.step(66)
     for k in range(len(ws)):
         assert np.array_equal(tuned.state(k), ref.state(k)), k
     tuned.close()
