@@ -323,38 +323,43 @@ __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __r
 }
 
 // Per-channel max-norms of the potential residual (res[2k]) and of C psi' (res[2k+1])
-// of the channels still active: block max, one atomicMax per block and quantity.
-template <typename T, int TY>
-__global__ void __launch_bounds__(TBX* TY) kb_residual(const BatchInst<T>* __restrict__ inst,
-                                                       const int* __restrict__ tile_inst,
+// of the channels still active, over the 64 x 32 fused-sweep tiles (whatever the
+// schedule's tile shape): each of the 512 threads takes four nodes, block max, one
+// atomicMax per block and quantity (few blocks per channel, so little contention).
+template <typename T>
+__global__ void __launch_bounds__(FUSED_NT) kb_residual(const BatchInst<T>* __restrict__ inst,
+                                                       const int* __restrict__ stile_inst,
                                                        const int* __restrict__ active,
                                                        unsigned long long* __restrict__ res) {
-    __shared__ double wmax[2][TY];
-    const int k = tile_inst[blockIdx.x];
+    __shared__ double wmax[2][FUSED_NT / 64];
+    const int k = stile_inst[blockIdx.x];
     if (!active[k]) return;  // uniform over the block
     const BatchInst<T>& B = inst[k];
-    int i, j;
-    tile_node<T, TY>(B, blockIdx.x, false, i, j);
+    const int lt = blockIdx.x - B.stile0, ty = lt / B.stiles_x, tx = lt - ty * B.stiles_x;
     double v = 0.0, sc = 0.0;
-    if (i < B.P.nx && j < B.P.ny && B.has_field) {
-        const MgEval<T> r = mg_eval(B.L0, i, j);
-        const T c = B.L0.u[(long long)j * B.L0.pitch + i];
-        v = residual_abs(r, c);
-        sc = fabs((double)(r.C * c));
-    }
+    if (B.has_field)
+        for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += FUSED_NT) {
+            const int i = tx * FUSED_X + (q & (FUSED_X - 1)), j = ty * FUSED_Y + q / FUSED_X;
+            if (i < B.P.nx && j < B.P.ny) {
+                const MgEval<T> r = mg_eval(B.L0, i, j);
+                const T c = B.L0.u[(long long)j * B.L0.pitch + i];
+                v = nan_max(v, residual_abs(r, c));
+                sc = nan_max(sc, fabs((double)(r.C * c)));
+            }
+        }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         v = nan_max(v, __shfl_xor(v, off, 64));
         sc = nan_max(sc, __shfl_xor(sc, off, 64));
     }
-    if (threadIdx.x == 0) {
-        wmax[0][threadIdx.y] = v;
-        wmax[1][threadIdx.y] = sc;
+    if ((threadIdx.x & 63) == 0) {
+        wmax[0][threadIdx.x >> 6] = v;
+        wmax[1][threadIdx.x >> 6] = sc;
     }
     __syncthreads();
-    if (threadIdx.y == 0 && threadIdx.x < 2) {
+    if (threadIdx.x < 2) {
         double m = wmax[threadIdx.x][0];
-        for (int w = 1; w < TY; ++w) m = nan_max(m, wmax[threadIdx.x][w]);
+        for (int w = 1; w < FUSED_NT / 64; ++w) m = nan_max(m, wmax[threadIdx.x][w]);
         atomicMax(res + 2 * k + threadIdx.x, (unsigned long long)__double_as_longlong(m));
     }
 }
@@ -524,10 +529,8 @@ template <typename T>
 void launch_batch_check(const BatchInst<T>* inst, const BatchTiles& t, int n, unsigned long long* res,
                         int* active, int* counts, const unsigned long long* scale, double rel_tol, int* sweeps,
                         int add, hipStream_t s) {
-#define C_(TY) \
-    hipLaunchKernelGGL((kb_residual<T, TY>), dim3(t.ntiles), dim3(TBX, TY), 0, s, inst, t.tiles, active, res)
-    FCD_SHAPE_SWITCH(t.shape, C_)
-#undef C_
+    if (t.nstiles > 0)
+        hipLaunchKernelGGL(kb_residual<T>, dim3(t.nstiles), dim3(FUSED_NT), 0, s, inst, t.stiles, active, res);
     launch_batch_decide<T>(inst, t, n, res, nullptr, nullptr, active, 0, counts, scale, rel_tol, sweeps, add, s);
 }
 
