@@ -954,9 +954,9 @@ T* bptr(char* base, size_t off) {
     return reinterpret_cast<T*>(base + off);
 }
 
-// Blocks of a fused sweep launch (about four per compute unit); they stride over the list
-// of active tiles, so a launch late in a solve, when few channels are still active,
-// dispatches no more blocks than this.
+// Blocks of a four-sweep fused launch (about four per compute unit); they stride over the
+// list of active tiles, so such a launch late in a solve, when few channels are still
+// active, dispatches no more blocks than this.
 constexpr int FUSED_GRID = 1024;
 
 fcd::BatchTiles btiles(const fcd_batch* b) {

@@ -209,7 +209,12 @@ constexpr double decide_floor() {
     return 16.0 * (sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07);
 }
 
-template <typename T, int NS, bool HF, bool CP>
+// LATE: the variant for the four-sweep launches late in a solve, when few tiles are
+// active: a fixed grid strides over the list of active tiles, and a channel that stops
+// on odd parity is copied back to its plane.  The other variants take one list entry
+// per block (the grid covers every tile; blocks past the list's end return at once),
+// which holds fewer registers than the strided loop, and carry no copy code.
+template <typename T, int NS, bool HF, bool LATE>
 __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __restrict__ inst,
                                                          const int* __restrict__ stile_inst,
                                                          const int* __restrict__ slist, const int* __restrict__ scount,
@@ -222,10 +227,10 @@ __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __r
     __shared__ T sm[F::N];
     __shared__ T sf[HF ? F::N : 1];
     __shared__ double wmax[2][NT / 64];
-    // the blocks stride over the list of the tiles of the channels that were active at
-    // the last decision kernel (channels stopped since then are skipped tile by tile)
+    // list entries: the tiles of the channels that were active at the last decision
+    // kernel (channels stopped since then are skipped tile by tile)
     const int count = *scount;
-    for (int b = blockIdx.x; b < count; b += gridDim.x) {
+    for (int b = blockIdx.x; b < count; b = LATE ? b + (int)gridDim.x : count) {
         const int tile = slist[b];
         const int k = stile_inst[tile];
         const BatchInst<T>& B = inst[k];
@@ -250,7 +255,7 @@ __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __r
         if (!act) {  // uniform over the block
             // a channel stopped by this launch's decision whose last result is in the
             // second plane (odd parity): its tiles move it back to the potential's plane
-            if (CP && dec.res && was && parity)
+            if (LATE && dec.res && was && parity)
                 for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += NT) {
                     const int i = i0 + (q & (FUSED_X - 1)), j = j0 + q / FUSED_X;
                     if (i < L.nx && j < L.ny) uout[(long long)j * L.pitch + i] = uin[(long long)j * L.pitch + i];
@@ -510,11 +515,11 @@ template <typename T>
 void launch_batch_sweep_fused(const BatchInst<T>* inst, const BatchTiles& t, const int* act_in, int* act_out,
                               int parity, bool rhs_plane, unsigned long long* res, const BatchDecide& dec,
                               hipStream_t s) {
-#define C_(NS, HF, CP)                                                                                      \
-    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF, CP>), dim3(t.sgrid), dim3(FUSED_NT), 0, s, inst, t.stiles,    \
-                       t.slist, t.scount, act_in, act_out, parity, res, dec)
-    // copies on stop only where a decision can meet odd parity (an odd number of
-    // launches per test interval); the other variants carry no copy code
+#define C_(NS, HF, LATE)                                                                                    \
+    hipLaunchKernelGGL((kb_sor_fused<T, NS, HF, LATE>), dim3(LATE ? t.sgrid : std::max(1, t.nstiles)),          \
+                       dim3(FUSED_NT), 0, s, inst, t.stiles, t.slist, t.scount, act_in, act_out, parity, res, dec)
+    // a decision meets odd parity (an odd number of launches per test interval) only
+    // with four sweeps per launch
     if (t.fused == 1) {
         if (rhs_plane) C_(1, true, false); else C_(1, false, false);
     } else if (t.fused == 2) {

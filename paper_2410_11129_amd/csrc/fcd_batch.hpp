@@ -53,7 +53,7 @@ struct BatchTiles {
     const int* stiles;
     int* slist;   // device: the fused tiles of the channels active at the last decision
     int* scount;  // kernel (written by it) and their number
-    int sgrid;    // blocks of a fused launch, which stride over slist
+    int sgrid;    // blocks of a four-sweep fused launch, which stride over slist
 };
 
 // Fused-sweep tile: 64 x 32 nodes plus a halo of 4 nodes per sweep, 512 threads.
