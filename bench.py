@@ -96,7 +96,7 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     bt.step(8)  # past the start-up transient
     omegas = bt.tune_omega(4)
     bt.init_droplets()
-    rows, block, fused, tail_fused, tail_after = bt.autotune(1)
+    rows, block, fused, tail_fused, tail_after = bt.autotune(3)
     bt.step(4)
     torch.cuda.synchronize()
     it0 = bt.stats()[1]
