@@ -124,44 +124,53 @@ __device__ __forceinline__ int fs_wrap(int i, int nx) {
 }
 
 // LDS layout of a fused-sweep tile: the even and odd columns of every row are stored in
-// two separate planes (node (lx, ly) at plane lx & 1, row ly, word lx >> 1), so the
+// two separate planes (node (lx, ly) at plane lx & 1, row ly, element lx >> 1), so the
 // same-colour nodes of neighbouring lanes, and each of their neighbours, are consecutive
-// words; the second plane starts 16 banks after the first, so a row read across both
-// parities is conflict-free as well.
+// elements; an element holds a node's potential and mu_r together (one 2-value LDS read
+// per neighbour).  In FP32 the second plane starts half the banks after the first, so a
+// row read across both parities is conflict-free as well.
 template <int NS>
 struct FusedLds {
     static constexpr int H = 4 * NS + 1, HX = FUSED_X + 2 * H, HY = FUSED_Y + 2 * H, HXH = HX / 2;
-    static constexpr int PS0 = HY * HXH, PS = PS0 + (48 - PS0 % 32) % 32, N = 2 * PS;
+    static constexpr int PS0 = HY * HXH, PS = PS0 + (24 - PS0 % 16) % 16, N = 2 * PS;
     static_assert(HX % 2 == 0, "even halo row");
     static __device__ __forceinline__ int at(int lx, int ly) { return (lx & 1) * PS + ly * HXH + (lx >> 1); }
 };
 
-// The operator at a staged node: c its word, o the word of its east neighbour (the west
-// one is o - 1, in the same plane), row the words per row; rows beyond the walls read
-// the edge row itself, as the clamped global loads do.
+// A staged node: potential and mu_r.
+template <typename T>
+struct alignas(2 * sizeof(T)) UM {
+    T u, m;
+};
+
+// The operator at a staged node: c its element, o the element of its east neighbour (the
+// west one is o - 1, in the same plane), row the elements per row; rows beyond the walls
+// read the edge row itself, as the clamped global loads do.
 template <typename T, bool HF>
-__device__ __forceinline__ MgEval<T> fs_eval(const PotLevel<T>& L, const T* su, const T* sm, const T* sf, int c,
+__device__ __forceinline__ MgEval<T> fs_eval(const PotLevel<T>& L, const UM<T>* sv, const T* sf, int c,
                                              int o, int row, int j) {
     const int dn = j == L.ny - 1 ? 0 : row, ds = j == 0 ? 0 : -row;
     Nb9<T> m, u;
-    m.c = sm[c];
-    m.e = sm[o];
-    m.w = sm[o - 1];
-    m.n = sm[c + dn];
-    m.s = sm[c + ds];
-    m.ne = sm[o + dn];
-    m.nw = sm[o - 1 + dn];
-    m.sw = sm[o - 1 + ds];
-    m.se = sm[o + ds];
-    u.c = su[c];
-    u.e = su[o];
-    u.w = su[o - 1];
-    u.n = su[c + dn];
-    u.s = su[c + ds];
-    u.ne = su[o + dn];
-    u.nw = su[o - 1 + dn];
-    u.sw = su[o - 1 + ds];
-    u.se = su[o + ds];
+    const UM<T> vc = sv[c], ve = sv[o], vw = sv[o - 1], vn = sv[c + dn], vs = sv[c + ds];
+    const UM<T> vne = sv[o + dn], vnw = sv[o - 1 + dn], vsw = sv[o - 1 + ds], vse = sv[o + ds];
+    m.c = vc.m;
+    m.e = ve.m;
+    m.w = vw.m;
+    m.n = vn.m;
+    m.s = vs.m;
+    m.ne = vne.m;
+    m.nw = vnw.m;
+    m.sw = vsw.m;
+    m.se = vse.m;
+    u.c = vc.u;
+    u.e = ve.u;
+    u.w = vw.u;
+    u.n = vn.u;
+    u.s = vs.u;
+    u.ne = vne.u;
+    u.nw = vnw.u;
+    u.sw = vsw.u;
+    u.se = vse.u;
     return mg_eval_nb(L, m, u, j, HF ? sf[c] : T(0));
 }
 
@@ -170,7 +179,7 @@ __device__ __forceinline__ MgEval<T> fs_eval(const PotLevel<T>& L, const T* su, 
 // [H - R, H + 64 + R), ly likewise, R = 4 NS - P, rows outside the channel left out;
 // the phase's nodes are dealt to the block's threads row-major, so few lanes idle.
 template <typename T, int NS, bool HF, int P>
-__device__ __forceinline__ void fs_phase(const PotLevel<T>& L, T* su, const T* sm, const T* sf, int j0, T omega) {
+__device__ __forceinline__ void fs_phase(const PotLevel<T>& L, UM<T>* sv, const T* sf, int j0, T omega) {
     using F = FusedLds<NS>;
     constexpr int H = F::H, R = 4 * NS - P;
     constexpr int px = ((P & 1) + H) & 1, py = (((P >> 1) & 1) + H) & 1;
@@ -184,11 +193,11 @@ __device__ __forceinline__ void fs_phase(const PotLevel<T>& L, T* su, const T* s
         const int j = j0 - H + ly;
         const int c = px * F::PS + ly * F::HXH + a0 + aq;       // column 2 (a0 + aq) + px
         const int o = (1 - px) * F::PS + ly * F::HXH + a0 + aq + px;  // its east neighbour
-        const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, c, o, F::HXH, j);
-        su[c] = sor_value(r, su[c], omega);
+        const MgEval<T> r = fs_eval<T, HF>(L, sv, sf, c, o, F::HXH, j);
+        sv[c].u = sor_value(r, sv[c].u, omega);
     }
     __syncthreads();
-    if constexpr (P + 1 < 4 * NS) fs_phase<T, NS, HF, P + 1>(L, su, sm, sf, j0, omega);
+    if constexpr (P + 1 < 4 * NS) fs_phase<T, NS, HF, P + 1>(L, sv, sf, j0, omega);
 }
 
 // Whether channel k stays active after a test: its residual is above
@@ -223,8 +232,7 @@ __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __r
                                                          BatchDecide dec) {
     using F = FusedLds<NS>;
     constexpr int H = F::H, HX = F::HX, HN = HX * F::HY, NT = FUSED_NT;
-    __shared__ T su[F::N];
-    __shared__ T sm[F::N];
+    __shared__ UM<T> sv[F::N];
     __shared__ T sf[HF ? F::N : 1];
     __shared__ double wmax[2][NT / 64];
     // list entries: the tiles of the channels that were active at the last decision
@@ -285,24 +293,23 @@ __global__ void __launch_bounds__(FUSED_NT) kb_sor_fused(const BatchInst<T>* __r
             const int q = threadIdx.x + r * NT;
             if (q < HN) {
                 const int ly = q / HX, lx = q - ly * HX, w = F::at(lx, ly);
-                su[w] = uv[r];
-                sm[w] = mv[r];
+                sv[w] = UM<T>{uv[r], mv[r]};
                 if (HF) sf[HF ? w : 0] = fv[HF ? r : 0];
             }
         }
         __syncthreads();
-        fs_phase<T, NS, HF, 0>(L, su, sm, sf, j0, B.omega);
+        fs_phase<T, NS, HF, 0>(L, sv, sf, j0, B.omega);
         double v = 0.0, sc = 0.0;
         for (int q = threadIdx.x; q < FUSED_X * FUSED_Y; q += NT) {
             const int ly = q / FUSED_X, lx = q - ly * FUSED_X;
             const int i = i0 + lx, j = j0 + ly;
             if (i < L.nx && j < L.ny) {
                 const int c = F::at(H + lx, H + ly);
-                uout[(long long)j * L.pitch + i] = su[c];
+                uout[(long long)j * L.pitch + i] = sv[c].u;
                 if (res && B.has_field) {
-                    const MgEval<T> r = fs_eval<T, HF>(L, su, sm, sf, c, F::at(H + lx + 1, H + ly), F::HXH, j);
-                    v = nan_max(v, residual_abs(r, su[c]));
-                    sc = nan_max(sc, fabs((double)(r.C * su[c])));
+                    const MgEval<T> r = fs_eval<T, HF>(L, sv, sf, c, F::at(H + lx + 1, H + ly), F::HXH, j);
+                    v = nan_max(v, residual_abs(r, sv[c].u));
+                    sc = nan_max(sc, fabs((double)(r.C * sv[c].u)));
                 }
             }
         }
