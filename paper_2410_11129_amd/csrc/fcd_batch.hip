@@ -3,8 +3,9 @@
 // 64 x TY-node tiles, each tile mapped to its channel through a table (one table per
 // tile shape; the shape is chosen by the batch autotuner).  Per-channel constants live
 // in device descriptors.  The potential solve is four-colour SOR; every `check` sweeps a
-// residual pass and a decision kernel update per-channel activity flags on the device,
-// so converged channels stop relaxing and the result does not depend on how the host
+// residual test and a decision update per-channel activity flags on the device (in fused
+// schedules the test rides on a sweep launch and the decision on the next one), so
+// converged channels stop relaxing and the result does not depend on how the host
 // groups the sweeps into launches or graphs.
 #include <hip/hip_runtime.h>
 

@@ -97,8 +97,8 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* _
     }
     __syncthreads();
     {  // first level from the finer plane's type
-        constexpr int cx = MU_TX / 2, cy = MU_TY / 2;
-        const int y = tid / cx, x = tid - y * cx;  // NT = cx * cy
+        constexpr int cx = MU_TX / 2;
+        const int y = tid / cx, x = tid - y * cx;  // NT = cx * (MU_TY / 2)
         const TC m = TC(T(0.25) * ((s0[2 * y][2 * x] + s0[2 * y][2 * x + 1]) + (s0[2 * y + 1][2 * x] + s0[2 * y + 1][2 * x + 1])));
         sa[y][x] = m;
         const int I = (i0 >> 1) + x, J = (j0 >> 1) + y;
