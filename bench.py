@@ -171,27 +171,14 @@ def adjoint_ratio(torch, steps: int, every: int) -> dict:
 
 def batched_adjoint(torch, steps: int, every: int) -> dict:
     """The 32 adjoint channels (256 x 64, Bo_m ~ U(0, 6), Ca ~ U(0.05, 0.2), random field
-    angle) as one FP32 batch: checkpointed forward + batched reverse sweep of `steps` steps,
-    against the single-channel FP64 adjoint of the first two channels run one after another
-    (per-instance rates; the full sweep is 3000 steps per channel, the rates scale with it)."""
+    angle) as one batch: checkpointed forward + batched reverse sweep of `steps` steps, in
+    FP32 and in FP64, against the single-channel FP64 adjoint of the first two channels run
+    one after another (per-instance rates)."""
     from fcd_inputs import adjoint_batch
     from paper_2410_11129_amd import fcd
     from paper_2410_11129_amd.adjoint import AdjointRun, BatchAdjointRun, theta_of
     from paper_2410_11129_amd.sim import Batch, Channel
     ws = adjoint_batch(steps=steps)
-    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
-    bt.init_droplets()
-    bt.step(8)
-    bt.tune_omega(4)  # not timed
-    bt.init_droplets()
-    run = BatchAdjointRun(bt, steps, every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run.forward()
-    g = run.backward([(1.0, 0.0)] * len(ws))
-    torch.cuda.synchronize()
-    dt_batch = time.perf_counter() - t0
-    bt.close()
     seq = 0.0
     gs = []
     for w in ws[:2]:
@@ -204,21 +191,38 @@ def batched_adjoint(torch, steps: int, every: int) -> dict:
         torch.cuda.synchronize()
         seq += time.perf_counter() - t0
         ch.close()
-    per_batch = dt_batch / len(ws)
     per_seq = seq / 2
-    rel = [abs(g[k][q] - gs[k][q]) / abs(gs[k][q]) for k in range(2) for q in (0, 1)]
-    # the same error relative to the instance's (H0, alpha) gradient norm, H0-scaled
-    rel_norm = []
-    for k in range(2):
-        w = ws[k]
-        sc = (w.H0, 1.0)
-        norm = max(abs(gs[k][q] * sc[q]) for q in (0, 1))
-        rel_norm += [abs(g[k][q] - gs[k][q]) * sc[q] / norm for q in (0, 1)]
-    return {"channels": len(ws), "steps": steps, "ckpt_every": every,
-            "batch_fp32_s": round(dt_batch, 3), "s_per_gradient_batch_fp32": round(per_batch, 4),
-            "s_per_gradient_sequential_fp64": round(per_seq, 4), "speedup": round(per_seq / per_batch, 2),
-            "max_rel_diff_dDo_dH0_dalpha_vs_fp64": float(f"{max(rel):.3e}"),
-            "max_diff_rel_to_gradient_norm": float(f"{max(rel_norm):.3e}")}
+    out = {"channels": len(ws), "steps": steps, "ckpt_every": every,
+           "s_per_gradient_sequential_fp64": round(per_seq, 4)}
+    for name, prec, tol in (("fp32", fcd.FCD_FP32, 1e-5), ("fp64", fcd.FCD_FP64, 1e-10)):
+        bt = Batch(ws, precision=prec, tol=tol)
+        bt.init_droplets()
+        bt.step(8)
+        bt.tune_omega(4)  # not timed
+        bt.init_droplets()
+        run = BatchAdjointRun(bt, steps, every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.forward()
+        g = run.backward([(1.0, 0.0)] * len(ws))
+        torch.cuda.synchronize()
+        dt_batch = time.perf_counter() - t0
+        bt.close()
+        del run
+        per_batch = dt_batch / len(ws)
+        rel = [abs(g[k][q] - gs[k][q]) / abs(gs[k][q]) for k in range(2) for q in (0, 1)]
+        # the same error relative to the instance's (H0, alpha) gradient norm, H0-scaled
+        rel_norm = []
+        for k in range(2):
+            sc = (ws[k].H0, 1.0)
+            norm = max(abs(gs[k][q] * sc[q]) for q in (0, 1))
+            rel_norm += [abs(g[k][q] - gs[k][q]) * sc[q] / norm for q in (0, 1)]
+        out[name] = {"batch_s": round(dt_batch, 3), "s_per_gradient": round(per_batch, 4),
+                     "speedup_vs_sequential_fp64": round(per_seq / per_batch, 2),
+                     "max_rel_diff_dDo_dH0_dalpha_vs_fp64": float(f"{max(rel):.3e}"),
+                     "max_diff_rel_to_gradient_norm": float(f"{max(rel_norm):.3e}")}
+        torch.cuda.empty_cache()
+    return out
 
 
 def copy_bandwidth_gbs(torch) -> float:
@@ -258,7 +262,8 @@ def main() -> int:
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-ckpt", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--batch-adjoint-steps", type=int, default=300)
+    ap.add_argument("--batch-adjoint-steps", type=int, default=3000)
+    ap.add_argument("--batch-adjoint-ckpt", type=int, default=150)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -347,7 +352,7 @@ def main() -> int:
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, args.adjoint_steps, args.adjoint_ckpt)
         log(f"bench: adjoint {out['adjoint']}")
-        out["batched_adjoint"] = batched_adjoint(torch, args.batch_adjoint_steps, 30)
+        out["batched_adjoint"] = batched_adjoint(torch, args.batch_adjoint_steps, args.batch_adjoint_ckpt)
         log(f"bench: batched adjoint {out['batched_adjoint']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
