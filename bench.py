@@ -81,11 +81,12 @@ def cpu_baseline(steps: int) -> dict:
 
 
 def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
-    """The 64-channel regime sweep (ny ~ U{64..256}, nx = 4 ny) as one FP32 batch, against
-    the same channels run one after another as single FP64 channels on this GPU (with the
-    batch's tuned SOR factors where a channel's solve is SOR).  Both rates are
+    """The 64-channel regime sweep (ny ~ U{64..256}, nx = 4 ny) as one FP32 batch (and, for
+    the gain at equal precision, as one FP64 batch at the single channels' tolerance),
+    against the same channels run one after another as single FP64 channels on this GPU
+    (with the batch's tuned SOR factors where a channel's solve is SOR).  The rates are
     extrapolated to the sweep's 10k steps per channel from timed windows.  The tuners run
-    before the timed window and are not part of it."""
+    before the timed windows and are not part of them."""
     from fcd_inputs import regime_sweep_batch
     from paper_2410_11129_amd import fcd
     from paper_2410_11129_amd.sim import Batch, Channel
@@ -108,6 +109,22 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     sites = sum(w.sites for w in ws)
     bt.close()
     del bt
+    # the same batch in FP64 at the single channels' tolerance (the batching gain at equal
+    # precision), same SOR factors, autotuned, a shorter timed window
+    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-10)
+    bt.init_droplets()
+    bt.step(8)
+    bt.tune_omega(4)
+    bt.init_droplets()
+    bt.autotune(1)
+    bt.step(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(max(1, steps // 10))
+    torch.cuda.synchronize()
+    dt_batch64 = (time.perf_counter() - t0) / max(1, steps // 10)
+    bt.close()
+    del bt
     seq = 0.0
     for w, om in zip(ws, omegas if seq_steps > 0 else []):
         ch = Channel(w, tol=1e-10, omega=om)
@@ -127,8 +144,11 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
             "schedule": {"tile_rows": rows, "block_sweeps": block, "fused_sweeps": fused,
                          "tail_fused_sweeps": tail_fused, "tail_after_sweeps": tail_after},
             "instances_per_hour_batch_fp32": round(batch_iph, 1),
+            "batch_fp64_ms_per_step": round(dt_batch64 * 1e3, 4),
+            "instances_per_hour_batch_fp64": round(len(ws) / (nsteps_target * dt_batch64) * 3600.0, 1),
             "instances_per_hour_sequential_fp64": round(seq_iph, 1) if seq_iph else None,
             "speedup": round(batch_iph / seq_iph, 2) if seq_iph else None,
+            "speedup_fp64_batch": round(len(ws) / (nsteps_target * dt_batch64) * 3600.0 / seq_iph, 2) if seq_iph else None,
             "sample": f"batch: {steps} timed steps; sequential: {seq_steps} timed steps per channel"}
 
 
