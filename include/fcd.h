@@ -291,13 +291,13 @@ fcd_status fcd_batch_set_tail_fusion(fcd_batch* b, int32_t fused_sweeps, int32_t
 
 /* Autotuner: tries every tile_rows in {1, 2, 4, 8} with block_sweeps in
  * {2, 8, 32} * pot_check_every and every allowed fused_sweeps in {0, 1, 2, 4}, each for
- * steps_per_candidate real steps of the batch (timed with HIP events; one untimed step
- * per tile shape and fusion first), keeps the fastest; then, where 4 sweeps per launch
- * are allowed, tries the tail fusion off and 4 after {8, 16, 32} * pot_check_every
- * sweeps the same way (one untimed step each first).  Writes choice = {tile_rows,
- * block_sweeps, fused_sweeps, tail fused_sweeps, tail after_sweeps}.  Advances the batch
- * by 4 F (1 + 3 steps_per_candidate) steps, F the number of allowed fusions, plus
- * 4 (1 + steps_per_candidate) for the tail fusion when 4 is allowed.  Sync. */
+ * one untimed step (capturing its graphs) and steps_per_candidate real steps of the batch
+ * timed with HIP events, keeps the fastest; then, where 4 sweeps per launch are allowed,
+ * tries the tail fusion off and 4 after {8, 16, 32} * pot_check_every sweeps the same
+ * way.  Writes choice = {tile_rows, block_sweeps, fused_sweeps, tail fused_sweeps, tail
+ * after_sweeps}.  Advances the batch by 12 F (1 + steps_per_candidate) steps, F the
+ * number of allowed fusions, plus 4 (1 + steps_per_candidate) for the tail fusion when
+ * 4 is allowed.  Sync. */
 fcd_status fcd_batch_autotune(fcd_batch* b, int32_t steps_per_candidate, int32_t choice[5]);
 
 /* SOR factor tuner: for each of the ncand (1..16) candidate scales s in scale[], every

@@ -1236,9 +1236,9 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
     return FCD_OK;
 }
 
-// Autotuner: every (fusion, tile shape, block size) candidate advances the batch by
-// `steps` real steps, timed with HIP events on the batch stream after one untimed step
-// per fusion and shape; the fastest is kept.  Then, where four sweeps per launch are
+// Autotuner: every (fusion, tile shape, block size) candidate advances the batch by one
+// untimed step (which captures its graphs) and `steps` real steps timed with HIP events
+// on the batch stream; the fastest is kept.  Then, where four sweeps per launch are
 // allowed, the tail fusion is chosen the same way among off and four sweeps per launch
 // after 8, 16 or 32 tests (one untimed step each first).  The candidates differ only in
 // launch geometry and in how sweeps are grouped into launches and graph launches, so
@@ -1266,7 +1266,7 @@ fcd_status batch_autotune_impl(fcd_batch* b, int steps, int* choice) {
             b->fused = f;
             b->shape = s;
             b->block_sweeps = blocks[g];
-            if (g == 0) st = batch_step_impl<T>(b, 1);  // warms the shape's kernels and graphs
+            st = batch_step_impl<T>(b, 1);  // captures the candidate's graphs outside the timing
             float ms = 0.f;
             timed(&ms);
             if (!st && ms < best) {
