@@ -177,3 +177,30 @@ def test_sor_factor_tuner_is_reproducible():
         assert min(abs(om - c) for c in cands) < 1e-15, (w.name, om, cands)
         if w.H0 == 0.0:
             assert om == cands[0]
+
+
+def test_many_channels_and_a_longer_test_interval():
+    """More channels than the decision kernel's block (its channel scan and tile list run in
+    chunks), and a test interval of 8 (two- and four-sweep launches per interval): each
+    channel ends bit for bit as it does in a batch of its own."""
+    base = single_channel_small().replace(nx=48, ny=14, xc=16.0, yc=6.5, r_core=2.0, r_shell=4.5,
+                                          drive_G=channel_drive(0.01, 1.0, 0.8, 14))
+    ws = [base.replace(name=f"m{k}", H0=base.H0 * (0.5 + (k % 7) / 7.0), alpha=0.1 * (k % 5),
+                       ny=14 + (k % 3), drive_G=channel_drive(0.01, 1.0, 0.8, 14 + (k % 3)))
+          for k in range(300)]
+    say(f"case batch of {len(ws)} channels, test interval 8")
+    for fused, tail in ((2, 4), (1, 0), (4, 0)):
+        bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5, check_every=8)
+        bt.set_schedule(4, 16, fused)
+        bt.set_tail_fusion(tail, 8)
+        bt.init_droplets()
+        bt.step(3)
+        got = {k: bt.state(k) for k in (0, 1, 137, 299)}
+        bt.close()
+        for k, st in got.items():
+            one = Batch([ws[k]], precision=fcd.FCD_FP32, tol=1e-5, check_every=8)
+            one.set_schedule(4, 16, 0)
+            one.init_droplets()
+            one.step(3)
+            assert np.array_equal(one.state(0), st), (fused, tail, k)
+            one.close()
