@@ -245,6 +245,40 @@ def batched_adjoint(torch, steps: int, every: int) -> dict:
     return out
 
 
+def quasi_static(torch, steps: int) -> dict:
+    """The 2048 x 512 FP64 channel (Bo_m = 2, multigrid to 1e-10) with the potential solved
+    every K steps and held in between (an option, not the paper's every-step coupling):
+    throughput for K = 4 and 8, and how far phi1 and D_o drift from the every-step run over
+    the same `steps` steps from the same state."""
+    from fcd_inputs import single_channel_large
+    from paper_2410_11129_amd import fcd
+    from paper_2410_11129_amd.sim import Channel
+    w = single_channel_large(bond=2.0)
+    ref = None
+    out = {"workload": "channel_2048x512_fp64_bo2", "steps": steps}
+    for K in (1, 4, 8):
+        ch = Channel(w, tol=1e-10, every=K)
+        ch.init_droplet()
+        ch.solve_potential(1e-10)
+        ch.step(8)  # every K divides 8: the timed window starts on a solve step
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        phi1 = ch.moments(fcd.FCD_M_PHI1)["phi1"]
+        D = ch.deformation()[0]
+        ch.close()
+        if ref is None:
+            ref = (phi1, D)
+            out["every_1_MLUPS"] = round(w.sites / dt / 1e6, 1)
+            continue
+        out[f"every_{K}"] = {"MLUPS": round(w.sites / dt / 1e6, 1),
+                             "max_abs_dphi1_vs_every_step": float(f"{abs(phi1 - ref[0]).max():.3e}"),
+                             "dD_o_vs_every_step": float(f"{D - ref[1]:.3e}")}
+    return out
+
+
 def copy_bandwidth_gbs(torch) -> float:
     n = 1 << 28  # 2 GiB of float64 each way
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -282,6 +316,8 @@ def main() -> int:
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-ckpt", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--quasi-static-steps", type=int, default=400)
+    ap.add_argument("--no-quasi-static", action="store_true")
     ap.add_argument("--batch-adjoint-steps", type=int, default=3000)
     ap.add_argument("--batch-adjoint-ckpt", type=int, default=150)
     args = ap.parse_args()
@@ -369,6 +405,9 @@ def main() -> int:
     if not args.no_batched:
         out["batched"] = batched_sweep(torch, args.batched_steps, args.sequential_steps)
         log(f"bench: batched {out['batched']}")
+    if not args.no_quasi_static:
+        out["quasi_static"] = quasi_static(torch, args.quasi_static_steps)
+        log(f"bench: quasi-static coupling {out['quasi_static']}")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, args.adjoint_steps, args.adjoint_ckpt)
         log(f"bench: adjoint {out['adjoint']}")

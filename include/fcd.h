@@ -86,6 +86,10 @@ typedef struct {
     int32_t pot_extrapolate; /* warm start of each step's solve: 0 the previous psi', 1 the linear
                                 extrapolation 2 psi'(t-1) - psi'(t-2), 2 the quadratic one
                                 3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3) (batches: 2 acts as 1) */
+    int32_t pot_every;       /* quasi-static coupling: the potential is solved on steps 0, K, 2K, ...
+                                after the last state change and held in between (K = pot_every;
+                                0 or 1: every step, the paper's coupling; the adjoints need <= 1;
+                                batches use channel 0's value) */
 } fcd_params;
 
 /* Caller-owned device buffers (element type = lattice precision). */

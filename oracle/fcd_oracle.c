@@ -95,7 +95,7 @@ typedef struct {
     int32_t mode;        /* 0: direct banded Cholesky, 1: four-colour SOR */
     int32_t max_sweeps;  /* SOR only */
     int32_t check_every; /* SOR only: residual test every this many sweeps */
-    int32_t pad;
+    int32_t every;       /* orc_step: potential solved on steps 0, K, 2K, ... (K = every; 0, 1: all) */
     double omega; /* SOR relaxation factor */
     double tol;   /* SOR stop: max |L_mu(psi0 + psi')| <= tol * H0 */
 } orc_solver;
@@ -713,7 +713,7 @@ int orc_init_droplet(const orc_params* P, double xc, double yc, double r_core, d
 /* The coupled step.  Reading: the algorithm figure is missing; the order is   */
 /* phases -> potential -> stencils and forces -> collisions -> streaming.      */
 /* ------------------------------------------------------------------------- */
-int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, double* f, double* g1,
+int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t step0, double* f, double* g1,
              double* g2, double* psi, int32_t* total_sweeps, double* last_resid) {
     int nx = P->nx, ny = P->ny;
     if (nx < 4 || ny < 2 || (nx % 2)) return -1;
@@ -735,13 +735,17 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, double* f
         phase_from_g(nx, ny, g1, phi1);
         phase_from_g(nx, ny, g2, phi2);
         mu_r_from_phi(P, phi1, phi2, mur);
-        /* Potential from phi(t), warm start from the previous psi'. */
-        int sw = 0;
-        double res = 0.0;
-        rc = solve_mu(P, mur, S, psi, NULL, NULL, &sw, &res);
-        if (total_sweeps) *total_sweeps += sw;
-        if (last_resid) *last_resid = res;
-        if (rc != 0) goto done;
+        /* Potential from phi(t), warm start from the previous psi'.  Quasi-static option
+         * (not the paper's coupling, which solves every step): solved only on the steps
+         * step0 + step = 0, K, 2K, ... counted from the initial state, psi' held between. */
+        if ((step0 + step) % (S->every > 1 ? S->every : 1) == 0) {
+            int sw = 0;
+            double res = 0.0;
+            rc = solve_mu(P, mur, S, psi, NULL, NULL, &sw, &res);
+            if (total_sweeps) *total_sweeps += sw;
+            if (last_resid) *last_resid = res;
+            if (rc != 0) goto done;
+        }
         /* Stencils, forces and both collisions at every node. */
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {

@@ -29,16 +29,16 @@ class OracleParams(C.Structure):
 class OracleSolver(C.Structure):
     _fields_ = [
         ("mode", C.c_int32), ("max_sweeps", C.c_int32), ("check_every", C.c_int32),
-        ("pad", C.c_int32), ("omega", C.c_double), ("tol", C.c_double),
+        ("every", C.c_int32), ("omega", C.c_double), ("tol", C.c_double),
     ]
 
     @classmethod
-    def direct(cls) -> "OracleSolver":
-        return cls(0, 0, 1, 0, 1.0, 0.0)
+    def direct(cls, every: int = 1) -> "OracleSolver":
+        return cls(0, 0, 1, every, 1.0, 0.0)
 
     @classmethod
-    def sor(cls, omega: float, tol: float, max_sweeps: int = 100000, check_every: int = 1):
-        return cls(1, max_sweeps, check_every, 0, omega, tol)
+    def sor(cls, omega: float, tol: float, max_sweeps: int = 100000, check_every: int = 1, every: int = 1):
+        return cls(1, max_sweeps, check_every, every, omega, tol)
 
 
 def build(force: bool = True) -> str:
@@ -80,7 +80,7 @@ def lib():
         L.orc_init_fields.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_init_droplet.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
                                        _dp, _dp, _dp, _dp, _dp]
-        L.orc_step.argtypes = [P, S, C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(C.c_int32), _dp]
+        L.orc_step.argtypes = [P, S, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(C.c_int32), _dp]
         L.orc_moments.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
         L.orc_forces.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
         L.orc_deformation_w.argtypes = [C.c_int32, C.c_int32, _dp]
@@ -132,6 +132,7 @@ class OracleSim:
         self.psi = np.zeros((ny, nx))
         self.sweeps = 0
         self.resid = 0.0
+        self.nstep = 0  # steps since the initial state (quasi-static coupling phase)
 
     # --- initial state ---------------------------------------------------------
     def init_droplet(self, solve: bool = True):
@@ -141,6 +142,7 @@ class OracleSim:
         rc = lib().orc_init_droplet(C.byref(self.p), w.xc, w.yc, w.r_core, w.r_shell,
                                     ptr(self.f), ptr(self.g1), ptr(self.g2), ptr(phi1), ptr(phi2))
         assert rc == 0, rc
+        self.nstep = 0
         if solve:
             self.solve_potential()
         return phi1, phi2
@@ -151,6 +153,7 @@ class OracleSim:
         rc = lib().orc_init_fields(C.byref(self.p), *[ptr(a) for a in arrs], ptr(ps),
                                    ptr(self.f), ptr(self.g1), ptr(self.g2))
         assert rc == 0, rc
+        self.nstep = 0
         if solve:
             self.solve_potential()
 
@@ -174,9 +177,10 @@ class OracleSim:
     def step(self, n: int) -> int:
         sw = C.c_int32(0)
         res = C.c_double(0.0)
-        rc = lib().orc_step(C.byref(self.p), C.byref(self.solver), int(n), ptr(self.f),
+        rc = lib().orc_step(C.byref(self.p), C.byref(self.solver), int(n), int(self.nstep), ptr(self.f),
                             ptr(self.g1), ptr(self.g2), ptr(self.psi), C.byref(sw), C.byref(res))
         self.sweeps, self.resid = sw.value, res.value
+        self.nstep += int(n)
         return rc
 
     # --- outputs -----------------------------------------------------------------

@@ -224,6 +224,7 @@ struct fcd_handle {
     long long sweeps;
     double last_resid;
     int hist;  // completed step solves since the last state change (psi' history validity)
+    int qs;    // steps since the last state change (the potential is solved when qs % pot_every == 0)
     int last_iters;  // iterations the previous solve needed (first residual test is deferred)
     int init_fresh;  // the state is the compound-droplet initial state (no step since)
     // checkpointed adjoint: set by fcd_adjoint_forward, used by fcd_adjoint_backward
@@ -261,6 +262,7 @@ fcd_status check_params(const fcd_params* p) {
     if (p->pot_solver == FCD_SOLVER_MG && (p->pot_smooth < 1 || p->pot_coarse_sweeps < 1))
         return fail(FCD_ERR_ARG, "multigrid needs pot_smooth >= 1 and pot_coarse_sweeps >= 1");
     if (p->pot_extrapolate < 0 || p->pot_extrapolate > 2) return fail(FCD_ERR_ARG, "pot_extrapolate must be 0, 1 or 2");
+    if (p->pot_every < 0) return fail(FCD_ERR_ARG, "pot_every must be >= 0");
     return FCD_OK;
 }
 
@@ -707,16 +709,22 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
         if (timed) h->timer.end(h->stream, TK_PHASE, ev);
         fcd_status st = hip_check(hipGetLastError(), "phase launch");
         if (st) return st;
-        if (h->prm.pot_extrapolate && h->prm.H0 != 0.0) {
-            // the first solve's start (the initial solve) is not extrapolated from; linear
-            // from the third step, quadratic from the fourth
-            const int mode = h->hist >= 3 && h->prm.pot_extrapolate == 2 ? 2 : h->hist >= 2 ? 1 : 0;
-            fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, h->lat.nx, h->lat.ny, h->lat.pitch,
-                                       mode, h->stream);
+        // quasi-static coupling: the potential is solved on the steps qs = 0, K, 2K, ... since
+        // the last state change and held in between (K = pot_every; 0 or 1: every step)
+        const int K = std::max(1, h->prm.pot_every);
+        if (h->qs % K == 0) {
+            if (h->prm.pot_extrapolate && h->prm.H0 != 0.0) {
+                // the first solve's start (the initial solve) is not extrapolated from; linear
+                // from the third solve, quadratic from the fourth
+                const int mode = h->hist >= 3 && h->prm.pot_extrapolate == 2 ? 2 : h->hist >= 2 ? 1 : 0;
+                fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, h->lat.nx, h->lat.ny,
+                                           h->lat.pitch, mode, h->stream);
+            }
+            st = solve_impl<T>(h, h->prm.pot_tol, h->prm.pot_max_iters, nullptr, nullptr);
+            if (st) return st;
+            ++h->hist;
         }
-        st = solve_impl<T>(h, h->prm.pot_tol, h->prm.pot_max_iters, nullptr, nullptr);
-        if (st) return st;
-        ++h->hist;
+        ++h->qs;
         timed = h->timer.begin(h->stream, &ev);
         fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, h->stream);
         if (timed) h->timer.end(h->stream, TK_COLLIDE, ev);
@@ -914,6 +922,7 @@ struct fcd_batch {
     char* scratch;
     int cur;
     int hist;
+    int qs;  // steps since the initial state (the potential is solved when qs % pot_every == 0)
     int last_iters;
     long long steps;
     long long iters;
@@ -1221,12 +1230,16 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
     for (int n = 0; n < nsteps; ++n) {
         const fcd::BatchTiles t = btiles(b);
         fcd::launch_batch_phase<T>(binst<T>(b), t, b->cur, b->stream);
-        if (p0.pot_extrapolate) fcd::launch_batch_psi_history<T>(binst<T>(b), t, b->hist >= 2 ? 1 : 0, b->stream);
         fcd_status st = hip_check(hipGetLastError(), "batch phase launch");
         if (st) return st;
-        st = batch_solve<T>(b, forward_problem<T>(b), p0.pot_max_iters);
-        if (st) return st;
-        ++b->hist;
+        if (b->qs % std::max(1, p0.pot_every) == 0) {  // quasi-static coupling, as fcd_step
+            if (p0.pot_extrapolate)
+                fcd::launch_batch_psi_history<T>(binst<T>(b), t, b->hist >= 2 ? 1 : 0, b->stream);
+            st = batch_solve<T>(b, forward_problem<T>(b), p0.pot_max_iters);
+            if (st) return st;
+            ++b->hist;
+        }
+        ++b->qs;
         fcd::launch_batch_collide<T>(binst<T>(b), t, b->cur, b->stream);
         st = hip_check(hipGetLastError(), "batch collide launch");
         if (st) return st;
@@ -1358,6 +1371,7 @@ fcd_status batch_init_impl(fcd_batch* b, const double* geom) {
     fcd::launch_batch_fill_psi<T>(binst<T>(b), btiles(b), b->stream);
     b->cur = 0;
     b->hist = 0;
+    b->qs = 0;
     b->last_iters = 0;
     b->init_fresh = 1;
     return hip_check(hipGetLastError(), "batch init launch");
@@ -1941,6 +1955,7 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     h->steps = h->sweeps = 0;
     h->last_resid = 0.0;
     h->hist = 0;
+    h->qs = 0;
     h->last_iters = 0;
     h->init_fresh = 0;
     h->adj_work = nullptr;
@@ -1975,6 +1990,7 @@ fcd_status fcd_use_graphs(fcd_handle* h, int32_t enable) {
 fcd_status fcd_init_compound_droplet(fcd_handle* h, double xc, double yc, double r_core, double r_shell) {
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
     h->hist = 0;
+    h->qs = 0;
     h->last_iters = 0;
     h->init_fresh = 1;
     if (!(r_core >= 0.0) || !(r_shell >= r_core)) return fail(FCD_ERR_ARG, "need 0 <= r_core <= r_shell");
@@ -1986,6 +2002,7 @@ fcd_status fcd_init_fields(fcd_handle* h, const double* phi1, const double* phi2
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
     h->init_fresh = 0;
     h->hist = 0;
+    h->qs = 0;
     h->last_iters = 0;
     if (!phi1 || !phi2 || !ux || !uy) return fail(FCD_ERR_ARG, "a field pointer is null");
     return FCD_DISPATCH(h, init_fields_impl)(h, phi1, phi2, ux, uy, pstar);
@@ -2025,6 +2042,7 @@ fcd_status fcd_write_state(fcd_handle* h, const double* in) {
     if (!h || !in) return fail(FCD_ERR_ARG, "null argument");
     h->init_fresh = 0;
     h->hist = 0;
+    h->qs = 0;
     h->last_iters = 0;
     return FCD_DISPATCH(h, copy_in_impl)(h, h->buf.dist[h->cur], 27, in);
 }
@@ -2037,6 +2055,7 @@ fcd_status fcd_read_psi(fcd_handle* h, double* out) {
 fcd_status fcd_write_psi(fcd_handle* h, const double* in) {
     if (!h || !in) return fail(FCD_ERR_ARG, "null argument");
     h->hist = 0;
+    h->qs = 0;
     h->last_iters = 0;
     return FCD_DISPATCH(h, copy_in_impl)(h, h->buf.psi, 1, in);
 }
@@ -2102,6 +2121,7 @@ fcd_status fcd_adjoint_forward(fcd_handle* h, int32_t nsteps, int32_t ckpt_every
     if (!h || !work || !D_out) return fail(FCD_ERR_ARG, "null argument");
     if (nsteps < 1 || ckpt_every < 1) return fail(FCD_ERR_ARG, "need nsteps >= 1 and ckpt_every >= 1");
     if (reinterpret_cast<uintptr_t>(work) % 256) return fail(FCD_ERR_ARG, "work must be 256-byte aligned");
+    if (h->prm.pot_every > 1) return fail(FCD_ERR_ARG, "the adjoint needs a potential solve every step (pot_every <= 1)");
     return FCD_DISPATCH(h, adj_forward_impl)(h, nsteps, ckpt_every, static_cast<char*>(work), D_out);
 }
 
@@ -2147,7 +2167,7 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     b->state = static_cast<char*>(state);
     b->aux = static_cast<char*>(aux);
     b->scratch = static_cast<char*>(scratch);
-    b->cur = b->hist = b->last_iters = 0;
+    b->cur = b->hist = b->qs = b->last_iters = 0;
     b->steps = b->iters = 0;
     b->last_resid = 0.0;
     b->shape = 2;  // 64 x 4 tiles
@@ -2259,6 +2279,8 @@ fcd_status fcd_batch_adjoint_forward(fcd_batch* b, int32_t nsteps, int32_t ckpt_
     if (!b || !work || !D_out) return fail(FCD_ERR_ARG, "null argument");
     if (nsteps < 1 || ckpt_every < 1) return fail(FCD_ERR_ARG, "need nsteps >= 1 and ckpt_every >= 1");
     if (reinterpret_cast<uintptr_t>(work) % 256) return fail(FCD_ERR_ARG, "work must be 256-byte aligned");
+    if (b->prm[0].pot_every > 1)
+        return fail(FCD_ERR_ARG, "the adjoint needs a potential solve every step (pot_every <= 1)");
     return FCD_BDISPATCH(b, batch_adj_forward_impl)(b, nsteps, ckpt_every, static_cast<char*>(work), D_out);
 }
 

@@ -52,6 +52,7 @@ class fcd_params(C.Structure):
         ("eps_n", C.c_double), ("pot_tol", C.c_double), ("pot_omega", C.c_double),
         ("pot_solver", C.c_int32), ("pot_check_every", C.c_int32), ("pot_max_iters", C.c_int32),
         ("pot_smooth", C.c_int32), ("pot_coarse_sweeps", C.c_int32), ("pot_extrapolate", C.c_int32),
+        ("pot_every", C.c_int32),
     ]
 
 

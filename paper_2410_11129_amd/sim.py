@@ -10,7 +10,7 @@ from . import fcd
 
 def make_params(w, solver: int = fcd.FCD_SOLVER_MG, tol: float = 1e-10, omega: float = 0.0,
                 check_every: int = 1, max_iters: int = 100000, smooth: int = 1, coarse_sweeps: int = 2,
-                extrapolate: int = 2) -> fcd.fcd_params:
+                extrapolate: int = 2, every: int = 1) -> fcd.fcd_params:
     """fcd_params from a workload description (any object with the workload fields)."""
     p = fcd.fcd_params()
     for k in range(3):
@@ -21,6 +21,7 @@ def make_params(w, solver: int = fcd.FCD_SOLVER_MG, tol: float = 1e-10, omega: f
     p.pot_tol, p.pot_omega, p.pot_solver = tol, omega, solver
     p.pot_check_every, p.pot_max_iters = check_every, max_iters
     p.pot_smooth, p.pot_coarse_sweeps, p.pot_extrapolate = smooth, coarse_sweeps, extrapolate
+    p.pot_every = every
     return p
 
 

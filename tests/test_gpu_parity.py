@@ -332,3 +332,37 @@ def test_warm_start_orders_agree():
         assert np.abs(runs[order][1] - runs[0][1]).max() <= 1e-10, order
     say(f"  V-cycles over 60 steps: {[r[2] for r in runs]}")
     assert runs[2][2] < runs[1][2] < runs[0][2]
+
+
+def test_quasi_static_coupling_parity():
+    """pot_every = 4: the potential solved on steps 0, 4, 8, ... after the initial state and
+    held in between, as the oracle does it; within 1e-10 after 200 steps run in two calls
+    (the solve phase carries over), for the single channel and for a batch; the adjoint
+    refuses the option."""
+    from paper_2410_11129_amd.adjoint import AdjointRun, theta_of
+    from paper_2410_11129_amd.sim import Batch
+    w = single_channel_small(steps=200)
+    say("case quasi-static coupling every 4 steps, 200x50 fp64")
+    g = Channel(w, every=4, **MG_TIGHT)
+    g.init_droplet()
+    g.step(70)
+    g.step(130)
+    s = OracleSim(w, OracleSolver.direct(every=4))
+    s.init_droplet(solve=False)
+    assert s.step(70) == 0 and s.step(130) == 0
+    assert np.abs(g.state() - oracle_state(s)).max() < 1e-10
+    assert np.abs(g.psi_dense() - s.psi).max() < 1e-10
+    # it is not the every-step run
+    s1 = OracleSim(w)
+    s1.init_droplet(solve=False)
+    assert s1.step(200) == 0
+    assert np.abs(g.state() - oracle_state(s1)).max() > 1e-8
+    bt = Batch([w], precision=fcd.FCD_FP64, tol=1e-12, every=4)
+    bt.init_droplets()
+    bt.step(200)
+    assert np.abs(bt.state(0) - oracle_state(s)).max() < 1e-10
+    bt.close()
+    run = AdjointRun(g, 8, 4)
+    with pytest.raises(fcd.FcdError):
+        run.forward(theta_of(w))
+    g.close()
