@@ -174,6 +174,16 @@ fcd_status fcd_write_psi(fcd_handle* h, const double* in);
  * masses of phases 1 and 2.  out = {D_o, D_i, mass1, mass2}.  Sync. */
 fcd_status fcd_deformation(fcd_handle* h, double out[4]);
 
+/* Extent-based deformation index of Eq. 42, T = (l_y - l_x) / (l_y + l_x), of the outer
+ * droplet (w = phi1 + phi2) and the inner one (w = phi1), the interface at w = 1/2: l_y is
+ * the largest vertical extent over the columns (the longest run of rows with w >= 1/2
+ * between its linearly interpolated crossings; a run reaching a wall row ends at the wall),
+ * l_x the length of the longest run with w >= 1/2 along the centreline (the middle row, or
+ * the mean of the two middle rows when ny is even; periodic, nx when it closes on itself).
+ * Not smooth in the state (hence not the adjoint's objective).  out = {T_o, T_i, l_y outer,
+ * l_x outer, l_y inner, l_x inner}; T = 0 when both extents vanish.  Sync. */
+fcd_status fcd_extent_deformation(fcd_handle* h, double out[6]);
+
 /* Counters since creation: out = {steps, potential iterations (SOR sweeps or V-cycles),
  * last residual}.  Host only. */
 fcd_status fcd_stats(fcd_handle* h, double out[3]);

@@ -939,6 +939,98 @@ int orc_diagnostics(const orc_params* P, const double* g1, const double* g2, dou
     return 0;
 }
 
+/* Extent-based deformation index of Eq. 42, T = (l_y - l_x) / (l_y + l_x), of the
+ * outer droplet (w = phi1 + phi2) and the inner one (w = phi1), the interface at w = 1/2.
+ * Reading: l_y is the largest vertical extent over the columns: in each column the longest
+ * run of rows with w >= 1/2, from its linearly interpolated lower crossing to its upper one
+ * (a run reaching a wall row ends at the wall, half a node beyond the row); l_x is the
+ * length of the longest run with w >= 1/2 of the centreline profile (the middle row, or the
+ * mean of the two middle rows when ny is even), periodic in x, between its interpolated
+ * crossings (nx when the run closes on itself).  T = 0 when both extents vanish. */
+static double run_crossing(double wa, double wb) { return (0.5 - wa) / (wb - wa); }
+
+static double column_extent(int nx, int ny, const double* w, int i) {
+    double best = 0.0;
+    int j = 0;
+    while (j < ny) {
+        if (w[IDX(i, j, nx)] < 0.5) {
+            ++j;
+            continue;
+        }
+        int j0 = j;
+        while (j < ny && w[IDX(i, j, nx)] >= 0.5) ++j;
+        int j1 = j - 1; /* last row of the run */
+        double lo = j0 == 0 ? -0.5 : (j0 - 1) + run_crossing(w[IDX(i, j0 - 1, nx)], w[IDX(i, j0, nx)]);
+        double hi = j1 == ny - 1 ? ny - 0.5 : j1 + 1.0 - run_crossing(w[IDX(i, j1 + 1, nx)], w[IDX(i, j1, nx)]);
+        if (hi - lo > best) best = hi - lo;
+    }
+    return best;
+}
+
+static double centreline_extent(int nx, const double* c) {
+    int all = 1;
+    for (int i = 0; i < nx; ++i)
+        if (c[i] < 0.5) all = 0;
+    if (all) return (double)nx;
+    double best = 0.0;
+    /* start every run scan just after a node below 1/2, so runs are never cut by the seam */
+    int s = 0;
+    while (c[s] >= 0.5) ++s;
+    for (int t = 1; t <= nx; ++t) {
+        int i = (s + t) % nx;
+        if (c[i] < 0.5) continue;
+        int prev = (i - 1 + nx) % nx; /* below 1/2: a run starts at i */
+        if (c[prev] >= 0.5) continue;
+        int len = 0;
+        while (c[(i + len) % nx] >= 0.5) ++len;
+        int last = (i + len - 1) % nx, next = (i + len) % nx;
+        double left = run_crossing(c[prev], c[i]);          /* fraction of the gap before i */
+        double right = run_crossing(c[next], c[last]);      /* fraction of the gap after last */
+        double ext = (len - 1) + (1.0 - left) + (1.0 - right);
+        if (ext > best) best = ext;
+    }
+    return best;
+}
+
+int orc_extent_deformation(const orc_params* P, const double* g1, const double* g2, double out[6]) {
+    int nx = P->nx, ny = P->ny;
+    size_t n = (size_t)nx * ny;
+    double* phi1 = (double*)malloc(n * sizeof(double));
+    double* phi2 = (double*)malloc(n * sizeof(double));
+    double* wo = (double*)malloc(n * sizeof(double));
+    double* cl = (double*)malloc(2 * (size_t)nx * sizeof(double));
+    if (!phi1 || !phi2 || !wo || !cl) {
+        free(phi1);
+        free(phi2);
+        free(wo);
+        free(cl);
+        return -3;
+    }
+    phase_from_g(nx, ny, g1, phi1);
+    phase_from_g(nx, ny, g2, phi2);
+    for (size_t k = 0; k < n; ++k) wo[k] = phi1[k] + phi2[k];
+    const double* w[2] = {wo, phi1};
+    for (int d = 0; d < 2; ++d) {
+        double ly = 0.0;
+        for (int i = 0; i < nx; ++i) {
+            double e = column_extent(nx, ny, w[d], i);
+            if (e > ly) ly = e;
+        }
+        double* c = cl + (size_t)d * nx;
+        for (int i = 0; i < nx; ++i)
+            c[i] = (ny % 2) ? w[d][IDX(i, ny / 2, nx)] : 0.5 * (w[d][IDX(i, ny / 2 - 1, nx)] + w[d][IDX(i, ny / 2, nx)]);
+        double lx = centreline_extent(nx, c);
+        out[2 + 2 * d] = ly;
+        out[3 + 2 * d] = lx;
+        out[d] = (ly + lx > 0.0) ? (ly - lx) / (ly + lx) : 0.0;
+    }
+    free(phi1);
+    free(phi2);
+    free(wo);
+    free(cl);
+    return 0;
+}
+
 /* Exported for the stencil tests: Eq. 34 gradient and Eq. 35 Laplacian of a plane
  * with the mirror ghost rule. */
 void orc_stencils(int32_t nx, int32_t ny, const double* a, double* gx, double* gy, double* lap) {

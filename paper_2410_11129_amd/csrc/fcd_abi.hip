@@ -32,6 +32,7 @@ fcd_status hip_check(hipError_t e, const char* what) {
 constexpr size_t OFF_RES = 0;      // 2 x uint64: bit patterns of max |residual| and max |C psi'|
 constexpr size_t OFF_CENT = 256;   // 8 doubles: centroids and masses
 constexpr size_t OFF_RESULT = 512; // 4 doubles: D_o, D_i, mass1, mass2
+constexpr size_t OFF_EXTENT = 768; // Eq. 42 extents: 2 x uint64 (l_y bit patterns), 2 doubles (l_x)
 constexpr size_t OFF_ROWS = 1024;  // ny * 8 doubles: per-row partial sums
 
 size_t elem_size(int precision) { return precision == FCD_FP64 ? sizeof(double) : sizeof(float); }
@@ -772,6 +773,33 @@ fcd_status diag_impl(fcd_handle* h, double out[4]) {
     st = hip_check(hipStreamSynchronize(h->stream), "diagnostics sync");
     if (st) return st;
     std::memcpy(out, h->host + 1, 4 * sizeof(double));
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status extent_impl(fcd_handle* h, double out[6]) {
+    fcd_status st = refresh_phase<T>(h);
+    if (st) return st;
+    const fcd::StepConst<T> P = make_const<T>(h);
+    char* s = static_cast<char*>(h->buf.scratch);
+    unsigned long long* ly = reinterpret_cast<unsigned long long*>(s + OFF_EXTENT);
+    fcd::launch_fill<double>(reinterpret_cast<double*>(ly), 2, 0.0, h->stream);  // +0.0 has all bits zero
+    fcd::launch_extent<T>(static_cast<const T*>(h->buf.phi), P, ly, reinterpret_cast<double*>(ly + 2), h->stream);
+    st = hip_check(hipGetLastError(), "extent launch");
+    if (!st)
+        st = hip_check(hipMemcpyAsync(h->host + 8, ly, 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                       "extent copy");
+    if (!st) st = hip_check(hipStreamSynchronize(h->stream), "extent sync");
+    if (st) return st;
+    for (int d = 0; d < 2; ++d) {
+        unsigned long long bits;
+        std::memcpy(&bits, h->host + 8 + d, sizeof(bits));
+        const double lyd = __builtin_bit_cast(double, bits);
+        const double lxd = h->host[10 + d];
+        out[2 + 2 * d] = lyd;
+        out[3 + 2 * d] = lxd;
+        out[d] = lyd + lxd > 0.0 ? (lyd - lxd) / (lyd + lxd) : 0.0;
+    }
     return FCD_OK;
 }
 
@@ -2063,6 +2091,11 @@ fcd_status fcd_write_psi(fcd_handle* h, const double* in) {
 fcd_status fcd_deformation(fcd_handle* h, double out[4]) {
     if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
     return FCD_DISPATCH(h, diag_impl)(h, out);
+}
+
+fcd_status fcd_extent_deformation(fcd_handle* h, double out[6]) {
+    if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
+    return FCD_DISPATCH(h, extent_impl)(h, out);
 }
 
 fcd_status fcd_stats(fcd_handle* h, double out[3]) {

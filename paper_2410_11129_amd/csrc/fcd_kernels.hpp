@@ -65,5 +65,9 @@ void launch_fill(T* a, long long n, T v, hipStream_t s);
 template <typename T>
 void launch_diagnostics(const T* phi, const StepConst<T>& P, double* rows, double* cent, double* result,
                         hipStream_t s);
+// Eq. 42 extents (fcd_extent.hip): ly[0..1] (bit patterns, zeroed by the caller) and
+// lx[0..1] of the outer and inner droplets.
+template <typename T>
+void launch_extent(const T* phi, const StepConst<T>& P, unsigned long long* ly, double* lx, hipStream_t s);
 
 }  // namespace fcd

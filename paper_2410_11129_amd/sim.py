@@ -131,6 +131,10 @@ class Channel:
     def deformation(self):
         return fcd.fcd_deformation(self.h)
 
+    def extent_deformation(self):
+        """[T_o, T_i, l_y outer, l_x outer, l_y inner, l_x inner] (Eq. 42)."""
+        return fcd.fcd_extent_deformation(self.h)
+
     def stats(self):
         return fcd.fcd_stats(self.h)
 

@@ -366,3 +366,36 @@ def test_quasi_static_coupling_parity():
     with pytest.raises(fcd.FcdError):
         run.forward(theta_of(w))
     g.close()
+
+
+def test_extent_deformation_parity():
+    """Eq. 42 extents through the C ABI: equal to the oracle's after 300 coupled steps of the
+    200 x 50 channel, and the closed form (b - a) / (b + a) of an elliptic droplet written
+    as fields, in FP64 and FP32."""
+    w = single_channel_small(steps=300)
+    say("case extent deformation (Eq. 42) 200x50 fp64 300 steps")
+    g = Channel(w, **MG_TIGHT)
+    g.init_droplet()
+    g.step(300)
+    s = OracleSim(w)
+    s.init_droplet(solve=False)
+    assert s.step(300) == 0
+    ge, oe = np.array(g.extent_deformation()), s.extent_deformation()
+    assert np.abs(ge - oe).max() < 1e-9, (ge, oe)
+    assert ge[2] > 0 and ge[3] > 0 and ge[4] > 0 and ge[5] > 0
+    g.close()
+    nx, ny, a, b = 160, 61, 24.0, 12.0
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+
+    def ell(ax, by):
+        rho = np.sqrt(((x - 70.0) / ax) ** 2 + ((y - 30.0) / by) ** 2)
+        return 0.5 * (1.0 + np.tanh(2.0 * (1.0 - rho) * min(ax, by) / 4.0))
+
+    wo, wi = ell(a, b), ell(5.0, 9.0)
+    we = Workload(name="ell", nx=nx, ny=ny, xi=4.0)
+    for prec in (fcd.FCD_FP64, fcd.FCD_FP32):
+        c = Channel(we, precision=prec, **MG_TIGHT)
+        c.init_fields(wi, wo - wi, np.zeros_like(wo), np.zeros_like(wo))
+        T = c.extent_deformation()
+        assert abs(T[0] - (b - a) / (b + a)) < 3e-3 and abs(T[1] - 4.0 / 14.0) < 3e-3, (prec, T)
+        c.close()
