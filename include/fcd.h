@@ -184,6 +184,14 @@ fcd_status fcd_deformation(fcd_handle* h, double out[4]);
  * l_x outer, l_y inner, l_x inner}; T = 0 when both extents vanish.  Sync. */
 fcd_status fcd_extent_deformation(fcd_handle* h, double out[6]);
 
+/* Breakup probe (Sec. 2.5: breakup is the inner droplet touching the shell's interface).
+ * A contact node is a core node (phi1 >= 1/2) with a nine-point neighbour in the carrier
+ * (phi3 >= 1/2; columns periodic, no neighbours beyond the walls).  out = {number of
+ * contact nodes (0: no breakup), their mean y, their circular-mean x in [0, nx), the
+ * circular-mean x of the outer droplet weighted by phi1 + phi2 (for tracking its travel
+ * across the periodic boundary)}; the means are -1 where their weights vanish.  Sync. */
+fcd_status fcd_breakup_probe(fcd_handle* h, double out[4]);
+
 /* Counters since creation: out = {steps, potential iterations (SOR sweeps or V-cycles),
  * last residual}.  Host only. */
 fcd_status fcd_stats(fcd_handle* h, double out[3]);

@@ -1031,6 +1031,58 @@ int orc_extent_deformation(const orc_params* P, const double* g1, const double* 
     return 0;
 }
 
+/* Breakup probe (Sec. 2.5: breakup is the inner droplet touching the shell's interface).
+ * Reading: a contact node is a node of the core (phi1 >= 1/2) with a nine-point neighbour
+ * in the carrier (phi3 >= 1/2; columns periodic, no neighbours beyond the walls): no shell
+ * node separates them there.  out = {number of contact nodes, their mean y, their circular
+ * mean x (angle 2 pi x / nx), the circular mean x of the outer droplet weighted by
+ * phi1 + phi2}; the two x means are -1 where their weights vanish. */
+int orc_breakup_probe(const orc_params* P, const double* g1, const double* g2, double out[4]) {
+    int nx = P->nx, ny = P->ny;
+    size_t n = (size_t)nx * ny;
+    double* phi1 = (double*)malloc(n * sizeof(double));
+    double* phi2 = (double*)malloc(n * sizeof(double));
+    if (!phi1 || !phi2) {
+        free(phi1);
+        free(phi2);
+        return -3;
+    }
+    phase_from_g(nx, ny, g1, phi1);
+    phase_from_g(nx, ny, g2, phi2);
+    const double two_pi = 6.283185307179586;
+    double cnt = 0.0, sy = 0.0, sc = 0.0, ss = 0.0, oc = 0.0, os = 0.0;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t k = IDX(i, j, nx);
+            double th = two_pi * i / nx;
+            double wo = phi1[k] + phi2[k];
+            oc += wo * cos(th);
+            os += wo * sin(th);
+            if (phi1[k] < 0.5) continue;
+            int touch = 0;
+            for (int dj = -1; dj <= 1 && !touch; ++dj)
+                for (int di = -1; di <= 1 && !touch; ++di) {
+                    int jj = j + dj;
+                    if ((di == 0 && dj == 0) || jj < 0 || jj >= ny) continue;
+                    size_t kk = IDX(wrap(i + di, nx), jj, nx);
+                    if (1.0 - phi1[kk] - phi2[kk] >= 0.5) touch = 1;
+                }
+            if (!touch) continue;
+            cnt += 1.0;
+            sy += j;
+            sc += cos(th);
+            ss += sin(th);
+        }
+    out[0] = cnt;
+    out[1] = cnt > 0.0 ? sy / cnt : -1.0;
+    double a = atan2(ss, sc), ao = atan2(os, oc);
+    out[2] = cnt > 0.0 ? (a < 0.0 ? a + two_pi : a) * nx / two_pi : -1.0;
+    out[3] = (oc != 0.0 || os != 0.0) ? (ao < 0.0 ? ao + two_pi : ao) * nx / two_pi : -1.0;
+    free(phi1);
+    free(phi2);
+    return 0;
+}
+
 /* Exported for the stencil tests: Eq. 34 gradient and Eq. 35 Laplacian of a plane
  * with the mirror ghost rule. */
 void orc_stencils(int32_t nx, int32_t ny, const double* a, double* gx, double* gy, double* lap) {

@@ -87,10 +87,12 @@ def lib():
         L.orc_deformation_w.restype = C.c_double
         L.orc_diagnostics.argtypes = [P, _dp, _dp, _dp]
         L.orc_extent_deformation.argtypes = [P, _dp, _dp, _dp]
+        L.orc_breakup_probe.argtypes = [P, _dp, _dp, _dp]
         L.orc_stencils.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
         L.orc_mu_r.argtypes = [P, _dp, _dp, _dp]
         for name in ("orc_init_fields", "orc_init_droplet", "orc_step", "orc_moments",
-                     "orc_forces", "orc_diagnostics", "orc_extent_deformation", "orc_solve_potential_phi"):
+                     "orc_forces", "orc_diagnostics", "orc_extent_deformation", "orc_breakup_probe",
+                     "orc_solve_potential_phi"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -202,6 +204,13 @@ class OracleSim:
     def diagnostics(self):
         out = np.zeros(4)
         rc = lib().orc_diagnostics(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
+        assert rc == 0, rc
+        return out
+
+    def breakup_probe(self):
+        """{contact nodes, their mean y, their circular-mean x, outer droplet's circular-mean x}."""
+        out = np.zeros(4)
+        rc = lib().orc_breakup_probe(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
         assert rc == 0, rc
         return out
 

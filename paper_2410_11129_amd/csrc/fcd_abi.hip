@@ -33,6 +33,7 @@ constexpr size_t OFF_RES = 0;      // 2 x uint64: bit patterns of max |residual|
 constexpr size_t OFF_CENT = 256;   // 8 doubles: centroids and masses
 constexpr size_t OFF_RESULT = 512; // 4 doubles: D_o, D_i, mass1, mass2
 constexpr size_t OFF_EXTENT = 768; // Eq. 42 extents: 2 x uint64 (l_y bit patterns), 2 doubles (l_x)
+constexpr size_t OFF_BREAKUP = 832; // breakup probe: 6 doubles of sums
 constexpr size_t OFF_ROWS = 1024;  // ny * 8 doubles: per-row partial sums
 
 size_t elem_size(int precision) { return precision == FCD_FP64 ? sizeof(double) : sizeof(float); }
@@ -800,6 +801,34 @@ fcd_status extent_impl(fcd_handle* h, double out[6]) {
         out[3 + 2 * d] = lxd;
         out[d] = lyd + lxd > 0.0 ? (lyd - lxd) / (lyd + lxd) : 0.0;
     }
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status breakup_impl(fcd_handle* h, double out[4]) {
+    fcd_status st = refresh_phase<T>(h);
+    if (st) return st;
+    const fcd::StepConst<T> P = make_const<T>(h);
+    char* s = static_cast<char*>(h->buf.scratch);
+    double* sums = reinterpret_cast<double*>(s + OFF_BREAKUP);
+    fcd::launch_breakup_probe<T>(static_cast<const T*>(h->buf.phi), P, reinterpret_cast<double*>(s + OFF_ROWS), sums,
+                                 h->stream);
+    st = hip_check(hipGetLastError(), "breakup probe launch");
+    if (!st)
+        st = hip_check(hipMemcpyAsync(h->host + 16, sums, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+                       "breakup probe copy");
+    if (!st) st = hip_check(hipStreamSynchronize(h->stream), "breakup probe sync");
+    if (st) return st;
+    const double* v = h->host + 16;
+    const double two_pi = 6.283185307179586, nx = h->lat.nx;
+    auto angle_x = [&](double c, double sn) {
+        const double a = std::atan2(sn, c);
+        return (a < 0.0 ? a + two_pi : a) * nx / two_pi;
+    };
+    out[0] = v[0];
+    out[1] = v[0] > 0.0 ? v[1] / v[0] : -1.0;
+    out[2] = v[0] > 0.0 ? angle_x(v[2], v[3]) : -1.0;
+    out[3] = (v[4] != 0.0 || v[5] != 0.0) ? angle_x(v[4], v[5]) : -1.0;
     return FCD_OK;
 }
 
@@ -2096,6 +2125,11 @@ fcd_status fcd_deformation(fcd_handle* h, double out[4]) {
 fcd_status fcd_extent_deformation(fcd_handle* h, double out[6]) {
     if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
     return FCD_DISPATCH(h, extent_impl)(h, out);
+}
+
+fcd_status fcd_breakup_probe(fcd_handle* h, double out[4]) {
+    if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
+    return FCD_DISPATCH(h, breakup_impl)(h, out);
 }
 
 fcd_status fcd_stats(fcd_handle* h, double out[3]) {

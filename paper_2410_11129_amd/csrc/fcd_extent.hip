@@ -1,4 +1,5 @@
-// fcd_extent.hip -- extent-based deformation index of Eq. 42 on the device:
+// fcd_extent.hip -- shape diagnostics of the paper on the device: the extent-based
+// deformation index of Eq. 42, and the breakup probe further below.  Eq. 42:
 // T = (l_y - l_x) / (l_y + l_x) of the outer droplet (w = phi1 + phi2) and the inner one
 // (w = phi1), the interface at w = 1/2.  l_y: over the columns, the largest extent of the
 // longest run of rows with w >= 1/2, between the linearly interpolated crossings below and
@@ -102,7 +103,79 @@ __global__ void k_extent_centre(const T* __restrict__ phi, StepConst<T> P, doubl
     lx[d] = best;  // the walk ends on node s, below 1/2: every run has closed
 }
 
+// Breakup probe (Sec. 2.5: breakup is the inner droplet touching the shell's interface):
+// a contact node is a core node (phi1 >= 1/2) with a nine-point neighbour in the carrier
+// (phi3 >= 1/2; columns periodic, no neighbours beyond the walls).  One block per row
+// reduces, in a fixed order, the row's contact count, sum of y, sums of cos and sin of
+// 2 pi x / nx over the contact nodes, and the phi1 + phi2 weighted cos and sin sums of the
+// outer droplet; a single block then adds the rows in order.
+constexpr int BRK_T = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(BRK_T) k_breakup_rows(const T* __restrict__ phi, StepConst<T> P,
+                                                        double* __restrict__ rows) {
+    __shared__ double part[6][BRK_T / 64];
+    const int j = blockIdx.x;
+    const double two_pi = 6.283185307179586;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < P.nx; i += BRK_T) {
+        const long long k = (long long)j * P.pitch + i;
+        const double p1 = (double)phi[k], p2 = (double)phi[P.plane + k];
+        const double th = two_pi * i / P.nx, c = cos(th), s = sin(th);
+        acc[4] += (p1 + p2) * c;
+        acc[5] += (p1 + p2) * s;
+        if (p1 < 0.5) continue;
+        bool touch = false;
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int jj = j + dj;
+            if (jj < 0 || jj >= P.ny) continue;
+            for (int di = -1; di <= 1; ++di) {
+                if (di == 0 && dj == 0) continue;
+                int ii = i + di;
+                ii = ii < 0 ? ii + P.nx : (ii >= P.nx ? ii - P.nx : ii);
+                const long long kk = (long long)jj * P.pitch + ii;
+                touch = touch || (1.0 - (double)phi[kk] - (double)phi[P.plane + kk] >= 0.5);
+            }
+        }
+        if (!touch) continue;
+        acc[0] += 1.0;
+        acc[1] += j;
+        acc[2] += c;
+        acc[3] += s;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((threadIdx.x & 63) == 0) part[q][threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0.0;
+        for (int w = 0; w < BRK_T / 64; ++w) v += part[threadIdx.x][w];
+        rows[(long long)j * 8 + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_breakup_final(const double* __restrict__ rows, int ny, double* __restrict__ sums) {
+    const int q = threadIdx.x;
+    if (q >= 6) return;
+    double v = 0.0;
+    for (int j = 0; j < ny; ++j) v += rows[(long long)j * 8 + q];
+    sums[q] = v;
+}
+
 }  // namespace
+
+template <typename T>
+void launch_breakup_probe(const T* phi, const StepConst<T>& P, double* rows, double* sums, hipStream_t s) {
+    hipLaunchKernelGGL(k_breakup_rows<T>, dim3(P.ny), dim3(BRK_T), 0, s, phi, P, rows);
+    hipLaunchKernelGGL(k_breakup_final, dim3(1), dim3(64), 0, s, rows, P.ny, sums);
+}
+
+template void launch_breakup_probe<double>(const double*, const StepConst<double>&, double*, double*, hipStream_t);
+template void launch_breakup_probe<float>(const float*, const StepConst<float>&, double*, double*, hipStream_t);
 
 template <typename T>
 void launch_extent(const T* phi, const StepConst<T>& P, unsigned long long* ly, double* lx, hipStream_t s) {

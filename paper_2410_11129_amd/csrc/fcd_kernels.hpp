@@ -69,5 +69,10 @@ void launch_diagnostics(const T* phi, const StepConst<T>& P, double* rows, doubl
 // lx[0..1] of the outer and inner droplets.
 template <typename T>
 void launch_extent(const T* phi, const StepConst<T>& P, unsigned long long* ly, double* lx, hipStream_t s);
+// Breakup probe (fcd_extent.hip): rows (ny x 8 doubles) of per-row partials, summed in row
+// order into sums[0..5] = contact count, sum of y, sum cos, sum sin (contact nodes), outer
+// droplet's weighted sum cos, sum sin.
+template <typename T>
+void launch_breakup_probe(const T* phi, const StepConst<T>& P, double* rows, double* sums, hipStream_t s);
 
 }  // namespace fcd

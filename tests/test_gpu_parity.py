@@ -420,3 +420,57 @@ def test_total_spreading_term_parity():
     assert s0.step(25) == 0
     assert np.abs(oracle_state(s0) - oracle_state(s)).max() > 1e-8
     g.close()
+
+
+def test_breakup_probe_parity():
+    """The breakup probe through the C ABI against the oracle on written fields (intact and
+    touching cores, FP64 and FP32), and a short run to breakup of a core close to its
+    shell's interface: same probe step and breakup numbers as the oracle's run."""
+    from paper_2410_11129_amd.sim import run_to_breakup
+    nx, ny = 120, 61
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+
+    def disc(x0, y0, r):
+        dx = (x - x0 + nx / 2) % nx - nx / 2
+        return 0.5 * (1.0 + np.tanh(2.0 * (r - np.hypot(dx, y - y0)) / 4.0))
+
+    we = Workload(name="brk", nx=nx, ny=ny, xi=4.0)
+    # generic centres and radii: no node sits exactly on a 1/2 level, where the rounding
+    # of the phase sums alone would decide the predicate
+    for xc in (60.13, 74.27):
+        core = disc(xc, 30.21, 10.17 if xc > 70 else 9.07)
+        shell = np.maximum(disc(60.06, 29.93, 20.11), core) - core
+        z = np.zeros_like(core)
+        s = OracleSim(we)
+        s.init_fields(core, shell, z, z, solve=False)
+        want = s.breakup_probe()
+        for prec in (fcd.FCD_FP64, fcd.FCD_FP32):
+            c = Channel(we, precision=prec, **MG_TIGHT)
+            c.init_fields(core, shell, z, z)
+            got = c.breakup_probe()
+            assert got[0] == want[0], (xc, prec, got, want)
+            assert np.abs(np.array(got[1:]) - want[1:]).max() < (1e-9 if prec == fcd.FCD_FP64 else 1e-4), (got, want)
+            c.close()
+        assert (want[0] > 0) == (xc > 70), want
+    # a core 3 nodes inside its shell: the core outruns the shell in the channel flow and
+    # touches its front (the oracle's run breaks up after 480 steps)
+    w = single_channel_small().replace(nx=96, ny=40, xc=40.0, yc=19.5, r_shell=12.0, r_core=9.0,
+                                       drive_G=channel_drive(0.01, 1.0, 0.8, 40))
+    say("case run to breakup 96x40")
+    g = Channel(w, **MG_TIGHT)
+    g.init_droplet()
+    got = run_to_breakup(g, 600, every=20)
+    s = OracleSim(w)
+    s.init_droplet(solve=False)
+    t, hit = 0, None
+    while t < 600 and hit is None:
+        assert s.step(20) == 0
+        t += 20
+        p = s.breakup_probe()
+        if p[0] > 0:
+            hit = (t, p)
+    assert got is not None and hit is not None, (got, hit)
+    assert got["steps"] == hit[0] and got["contact_nodes"] == int(hit[1][0]), (got, hit)
+    assert abs(got["y_b"] - hit[1][1]) < 1e-9 and abs(got["x_b"] % w.nx - hit[1][2]) < 1e-9, (got, hit)
+    assert got["x_b"] > w.xc and got["y_b_star"] < 0.05, got  # at the front, near the axis
+    g.close()
