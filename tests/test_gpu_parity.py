@@ -312,6 +312,39 @@ def test_full_size_fp32_deformation_tracks_fp64():
     b.close()
 
 
+@pytest.mark.parametrize("bond", [0.0, 2.0, 4.0])
+def test_full_size_fp32_tracks_fp64_over_20k_steps(bond):
+    """2048 x 512, 20 000 steps, Bo_m in {0, 2, 4}: the FP32 path's deformation time series
+    (sampled every 1000 steps) stays within the stated 1e-3 of the FP64 path's, and the
+    mean pointwise order-parameter difference at the end within 1e-4. The pointwise maximum
+    is not bounded here: over this horizon the droplet's position in the two precisions
+    differs by a fraction of a node, which moves phi at interface nodes by up to a few 1e-2
+    while D and the field means stay put."""
+    w = single_channel_large(bond=bond)
+    say(f"case full size 2048x512 Bo={bond} FP32 vs FP64, 20000 steps")
+    a = Channel(w, precision=fcd.FCD_FP64, tol=1e-10)
+    b = Channel(w, precision=fcd.FCD_FP32, tol=1e-5)
+    for c in (a, b):
+        c.init_droplet()
+    worst = 0.0
+    for k in range(20):
+        a.step(1000)
+        b.step(1000)
+        da, db = a.deformation(), b.deformation()
+        worst = max(worst, abs(da[0] - db[0]), abs(da[1] - db[1]))
+        if k % 5 == 4:
+            say(f"  step {1000 * (k + 1)}: D_o {da[0]:.6e} vs {db[0]:.6e}, D_i {da[1]:.6e} vs {db[1]:.6e}")
+    assert worst <= 1e-3, worst
+    ma, mb = a.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2), b.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2)
+    for key in ma:
+        diff = np.abs(ma[key] - mb[key])
+        say(f"  {key}: mean |fp32 - fp64| = {diff.mean():.2e}, max {diff.max():.2e}")
+        assert diff.mean() <= 1e-4, key
+        assert np.isfinite(mb[key]).all()
+    a.close()
+    b.close()
+
+
 def test_warm_start_orders_agree():
     """The potential's warm start (previous psi', linear or quadratic extrapolation)
     changes only where each solve starts: after 60 steps of the 512 x 128 field channel
