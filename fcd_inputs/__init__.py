@@ -12,6 +12,8 @@ from .workloads import (  # noqa: F401
     sigma_from_capillary,
     single_channel_small,
     single_channel_large,
+    open_channel_small,
+    open_channel_paper,
     adjoint_channel,
     regime_sweep_batch,
     adjoint_batch,

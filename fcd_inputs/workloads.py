@@ -61,6 +61,7 @@ class Workload:
     ferro: str = "shell"
     bond: float = 0.0
     capillary: Optional[float] = None
+    u_inlet: Optional[float] = None  # open channel: u_avg of Eq. 37; None: periodic channel
 
     @property
     def sites(self) -> int:
@@ -126,6 +127,32 @@ def single_channel_large(bond: float = 2.0, steps: int = 20000) -> Workload:
         H0=h0_from_bond(bond, "core", 2.0, rc, rs, sig, sig), alpha=math.pi / 2,
         drive_G=channel_drive(u_ref, 1.0, tau3, ny), xc=4 * rs, yc=(ny - 1) / 2.0,
         r_core=rc, r_shell=rs, steps=steps, u_ref=u_ref, ferro="core", bond=bond, capillary=ca)
+
+
+def open_channel_small(xc: float = 170.0, bond: float = 1.0, u_inlet: float = 0.05,
+                       steps: int = 400) -> Workload:
+    """200 x 50 open channel (Eq. 37 inlet at x = 0, convective outlet at x = 199, no body
+    force), the 200 x 50 droplet and materials otherwise.  With the default centre
+    x = 170 and centreline inflow 0.05 the shell reaches the outlet within about 250
+    steps; a centre near x = 15 puts its rear interface against the inlet instead."""
+    return single_channel_small(bond=bond, steps=steps).replace(
+        name="open_channel_200x50", drive_G=0.0, u_inlet=u_inlet, xc=xc, u_ref=u_inlet)
+
+
+def open_channel_paper(bond: float = 2.0, steps: int = 20000) -> Workload:
+    """The paper's open-channel set-up (Sec. 2.5, Sec. 3.1): L x H = 900 x 150, core r = 20,
+    shell r = 35, the droplet centred 4 r_core from the inlet on the centre line (as
+    printed), ferrofluid shell, field along x, Ca = 0.15, equal densities, viscosities and
+    surface tensions; Eq. 37 inflow with centreline value u_ref = 0.01."""
+    nx, ny, rs, rc = 900, 150, 35.0, 20.0
+    tau3, u_ref, ca = 0.2, 0.01, 0.15
+    sig = sigma_from_capillary(ca, 1.0, tau3, u_ref)
+    return Workload(
+        name="open_channel_900x150", nx=nx, ny=ny, tau=(tau3, tau3, tau3), chi=_chi("shell", 1.0),
+        sigma12=sig, sigma13=sig, sigma23=sig, xi=5.0,
+        H0=h0_from_bond(bond, "shell", 1.0, rc, rs, sig, sig), alpha=0.0, drive_G=0.0,
+        xc=4 * rc, yc=(ny - 1) / 2.0, r_core=rc, r_shell=rs, steps=steps, u_ref=u_ref,
+        ferro="shell", bond=bond, capillary=ca, u_inlet=u_ref)
 
 
 def adjoint_channel(steps: int = 2000) -> Workload:

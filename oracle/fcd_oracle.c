@@ -12,7 +12,8 @@
  *
  * Conventions.  Node (i, j) sits at x = i, y = j, 0 <= i < nx, 0 <= j < ny.  Every
  * plane is row-major [ny][nx] (x fastest); distributions are [9][ny][nx].  The
- * channel is periodic in x; no-slip walls lie half a cell outside the first and
+ * channel is periodic in x, or open (Eq. 37 inlet at i = 0, convective outlet at
+ * i = nx - 1) when open_x is set; no-slip walls lie half a cell outside the first and
  * last rows (y = -1/2 and y = ny - 1/2).
  *
  * Parity status: every exported function below is pinned by a CPU test against
@@ -82,13 +83,15 @@ static void build_minv(void) {
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int32_t nx, ny;
-    int32_t pad0, pad1;
+    int32_t open_x; /* 0: periodic channel; 1: Eq. 37 inlet at i = 0, convective outlet at i = nx - 1 */
+    int32_t pad1;
     double rho[3], tau[3], chi[3]; /* phase 1 = core, 2 = shell, 3 = ambient   */
     double sigma12, sigma13, sigma23, eta;
     double xi, mobility;
     double H0, alpha, mu0;
     double drive_G, grav_x, grav_y;
     double eps_n; /* n = grad phi / sqrt(|grad phi|^2 + eps_n^2); the paper leaves |grad phi| = 0 open */
+    double u_inlet; /* open channel: u_avg of Eq. 37 (the centreline value of the inlet profile) */
 } orc_params;
 
 typedef struct {
@@ -104,11 +107,16 @@ typedef struct {
 
 static inline int wrap(int i, int n) { return ((i % n) + n) % n; }
 
-/* Value of a plane at (i + dx, j + dy): periodic in x; rows outside the channel
- * take the value of the nearest row (reading: zero normal gradient of phi and mu_r
- * at the walls, i.e. neutral wetting; the paper names no wetting condition). */
-static inline double nb_mirror(const double* a, int nx, int ny, int i, int j, int dx, int dy) {
-    int ii = wrap(i + dx, nx);
+/* Value of a plane at (i + dx, j + dy): periodic in x (or, with clamp_x, columns
+ * beyond the inlet and outlet take the value of the end column); rows outside the
+ * channel take the value of the nearest row (reading: zero normal gradient of phi and
+ * mu_r at the walls, i.e. neutral wetting; the paper names no wetting condition). */
+static inline double nb_mirror(const double* a, int nx, int ny, int i, int j, int dx, int dy, int clamp_x) {
+    int ii = i + dx;
+    if (clamp_x)
+        ii = ii < 0 ? 0 : (ii > nx - 1 ? nx - 1 : ii);
+    else
+        ii = wrap(ii, nx);
     int jj = j + dy;
     if (jj < 0) jj = 0;
     if (jj > ny - 1) jj = ny - 1;
@@ -285,10 +293,10 @@ static void mu_r_from_phi(const orc_params* P, const double* phi1, const double*
 }
 
 /* Isotropic gradient, Eq. 34: grad a = (1/c_s^2) sum_alpha w_alpha e_alpha a(x + e_alpha). */
-static void iso_grad(const double* a, int nx, int ny, int i, int j, double g[2]) {
+static void iso_grad(const double* a, int nx, int ny, int i, int j, int clamp_x, double g[2]) {
     double gx = 0.0, gy = 0.0;
     for (int q = 0; q < NQ; ++q) {
-        double v = nb_mirror(a, nx, ny, i, j, EX[q], EY[q]);
+        double v = nb_mirror(a, nx, ny, i, j, EX[q], EY[q], clamp_x);
         gx += WQ[q] * EX[q] * v;
         gy += WQ[q] * EY[q] * v;
     }
@@ -297,10 +305,10 @@ static void iso_grad(const double* a, int nx, int ny, int i, int j, double g[2])
 }
 
 /* Isotropic Laplacian, Eq. 35: lap a = (2/c_s^2) sum_alpha w_alpha [a(x+e_alpha) - a(x)]. */
-static double iso_lap(const double* a, int nx, int ny, int i, int j) {
+static double iso_lap(const double* a, int nx, int ny, int i, int j, int clamp_x) {
     double c = a[IDX(i, j, nx)];
     double s = 0.0;
-    for (int q = 0; q < NQ; ++q) s += WQ[q] * (nb_mirror(a, nx, ny, i, j, EX[q], EY[q]) - c);
+    for (int q = 0; q < NQ; ++q) s += WQ[q] * (nb_mirror(a, nx, ny, i, j, EX[q], EY[q], clamp_x) - c);
     return 2.0 * s / CS2;
 }
 
@@ -322,12 +330,14 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
     q->phi[0] = phi1[k];
     q->phi[1] = phi2[k];
     q->phi[2] = 1.0 - phi1[k] - phi2[k];
-    iso_grad(phi1, nx, ny, i, j, q->gphi[0]);
-    iso_grad(phi2, nx, ny, i, j, q->gphi[1]);
+    /* Open channel, reading: zero normal gradient of phi at the inlet and outlet (the
+     * paper names no phase-field condition there; as at the walls). */
+    iso_grad(phi1, nx, ny, i, j, P->open_x, q->gphi[0]);
+    iso_grad(phi2, nx, ny, i, j, P->open_x, q->gphi[1]);
     q->gphi[2][0] = -q->gphi[0][0] - q->gphi[1][0];
     q->gphi[2][1] = -q->gphi[0][1] - q->gphi[1][1];
-    q->lphi[0] = iso_lap(phi1, nx, ny, i, j);
-    q->lphi[1] = iso_lap(phi2, nx, ny, i, j);
+    q->lphi[0] = iso_lap(phi1, nx, ny, i, j, P->open_x);
+    q->lphi[1] = iso_lap(phi2, nx, ny, i, j, P->open_x);
     q->lphi[2] = -q->lphi[0] - q->lphi[1];
     for (int s = 0; s < 3; ++s) {
         double gx = q->gphi[s][0], gy = q->gphi[s][1];
@@ -454,11 +464,13 @@ static void collide_g(const orc_params* P, const nodeq* q, int comp, const doubl
  *   (L u)(x) = (1/c_s^2) sum_{a=1..8} w_a (mu(x) + mu(x+e_a)) (u(x+e_a) - u(x)),
  * which equals mu * (Eq. 35 Laplacian) when mu is constant and is symmetric.  The total potential is
  * psi = psi0 + psi', psi0 = -H0 (x cos a + y sin a); psi' is periodic in x and zero in
- * the ghost rows.  The equation L(psi0 + psi') = 0 reads
+ * the ghost rows.  In the open channel too (reading: the paper gives the potential no
+ * condition at the inlet or outlet; psi' is the droplet's perturbation of the applied
+ * field and decays away from it, so the periodic closure is kept there).  The equation L(psi0 + psi') = 0 reads
  *   sum_a c_a (psi'(x+e_a) - psi'(x)) = H0 sum_a c_a (e_a . h),   c_a = 3 w_a (mu + mu_a). */
 
 static inline double coef(const double* mur, int nx, int ny, int i, int j, int a) {
-    return (WQ[a] / CS2) * (mur[IDX(i, j, nx)] + nb_mirror(mur, nx, ny, i, j, EX[a], EY[a]));
+    return (WQ[a] / CS2) * (mur[IDX(i, j, nx)] + nb_mirror(mur, nx, ny, i, j, EX[a], EY[a], 0));
 }
 
 /* Residual r = L(psi0 + psi') at every node; returns max |r|. */
@@ -677,8 +689,17 @@ int orc_init_fields(const orc_params* P, const double* phi1, const double* phi2,
     return 0;
 }
 
-/* Concentric tanh profiles (width xi) about (xc, yc), minimum image in x; Poiseuille
- * velocity of the ambient fluid under the drive; p* = 0. Writes phi1, phi2 too. */
+/* Eq. 37: inlet velocity u_avg 4 (y/H)(1 - y/H) with the walls at y = 0 and y = H = ny,
+ * i.e. y = j + 1/2 at row j.  Reading: taken as printed, so u_avg is the centreline value
+ * and the mean over the section is (2/3) u_avg. */
+static double inlet_u(const orc_params* P, int j) {
+    double s = (j + 0.5) / P->ny;
+    return 4.0 * P->u_inlet * s * (1.0 - s);
+}
+
+/* Concentric tanh profiles (width xi) about (xc, yc), minimum image in x (plain distance
+ * in the open channel); ambient velocity: the Poiseuille profile under the drive, or the
+ * Eq. 37 profile in every column of the open channel; p* = 0. Writes phi1, phi2 too. */
 int orc_init_droplet(const orc_params* P, double xc, double yc, double r_core, double r_shell,
                      double* f, double* g1, double* g2, double* phi1, double* phi2) {
     int nx = P->nx, ny = P->ny;
@@ -694,19 +715,70 @@ int orc_init_droplet(const orc_params* P, double xc, double yc, double r_core, d
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double dx = (double)i - xc;
-            dx -= nx * floor(dx / nx + 0.5);
+            if (!P->open_x) dx -= nx * floor(dx / nx + 0.5);
             double dy = (double)j - yc;
             double d = sqrt(dx * dx + dy * dy);
             double pin = 0.5 * (1.0 + tanh(2.0 * (r_core - d) / P->xi));
             double pout = 0.5 * (1.0 + tanh(2.0 * (r_shell - d) / P->xi));
             phi1[IDX(i, j, nx)] = pin;
             phi2[IDX(i, j, nx)] = pout - pin;
-            ux[IDX(i, j, nx)] = P->drive_G / (2.0 * P->rho[2] * nu3) * (j + 0.5) * (ny - 0.5 - j);
+            ux[IDX(i, j, nx)] = P->open_x ? inlet_u(P, j)
+                                          : P->drive_G / (2.0 * P->rho[2] * nu3) * (j + 0.5) * (ny - 0.5 - j);
         }
     orc_init_fields(P, phi1, phi2, ux, uy, NULL, f, g1, g2);
     free(ux);
     free(uy);
     return 0;
+}
+
+/* Open channel: the populations that streaming cannot supply at the end columns.
+ * Inlet i = 0 (unknown directions 1, 5, 8, i.e. e_x = +1), the velocity condition of
+ * Eq. 37 in the Zou-He manner: the first moment of f is set to j = (u_in(y), 0) and the
+ * non-equilibrium part of f_1 equals that of its opposite f_3; f_eq,1 - f_eq,3 =
+ * Gamma_1 - Gamma_3 = (2/3) u_x (Eq. 16, 18).  The two first-moment equations then fix
+ * f_5 and f_8.  p* needs no closure: it is whatever the sum of the completed set gives.
+ * Reading: the prescribed velocity is the first moment of f, which equals the u of
+ * Eq. 22 where the inflowing fluid carries no force.
+ * The order parameters enter at equilibrium with the inflow's composition (reading:
+ * carrier only, phi_1 = phi_2 = 0): g^i_a = phi_in Gamma_a(u_in) (Eq. 31 without the
+ * interface term, which vanishes in a uniform phase).
+ * Outlet i = nx - 1 (unknown directions 3, 6, 7), the convective condition
+ * d f/dt + U d f/dx = 0 discretised as f(t+1, N) = [f(t, N) + U f(t+1, N-1)] / (1 + U)
+ * for f, g1 and g2.  Reading: U, which the paper does not give, is the mean inlet
+ * velocity over the section (by continuity the mean outflow velocity). */
+static void open_boundaries(const orc_params* P, const double* out_old, double* f, double* g1, double* g2) {
+    int nx = P->nx, ny = P->ny;
+    size_t n = (size_t)nx * ny;
+    double U = 0.0;
+    for (int j = 0; j < ny; ++j) U += inlet_u(P, j);
+    U /= ny;
+    const double phi_in[2] = {0.0, 0.0};
+    for (int j = 0; j < ny; ++j) {
+        /* inlet */
+        size_t k = IDX(0, j, nx);
+        double ux = inlet_u(P, j), uy = 0.0;
+        double f2 = f[2 * n + k], f3 = f[3 * n + k], f4 = f[4 * n + k], f6 = f[6 * n + k], f7 = f[7 * n + k];
+        f[1 * n + k] = f3 + (2.0 / 3.0) * ux;
+        f[5 * n + k] = f7 - 0.5 * (f2 - f4) + ux / 6.0 + 0.5 * uy;
+        f[8 * n + k] = f6 + 0.5 * (f2 - f4) + ux / 6.0 - 0.5 * uy;
+        double u[2] = {ux, uy}, G[NQ];
+        orc_gamma(u, G);
+        const int in_dirs[3] = {1, 5, 8};
+        for (int d = 0; d < 3; ++d) {
+            int a = in_dirs[d];
+            g1[a * n + k] = phi_in[0] * G[a];
+            g2[a * n + k] = phi_in[1] * G[a];
+        }
+        /* outlet */
+        size_t ko = IDX(nx - 1, j, nx), kb = IDX(nx - 2, j, nx);
+        const int out_dirs[3] = {3, 6, 7};
+        for (int d = 0; d < 3; ++d) {
+            int a = out_dirs[d];
+            f[a * n + ko] = (out_old[(0 * NQ + a) * ny + j] + U * f[a * n + kb]) / (1.0 + U);
+            g1[a * n + ko] = (out_old[(1 * NQ + a) * ny + j] + U * g1[a * n + kb]) / (1.0 + U);
+            g2[a * n + ko] = (out_old[(2 * NQ + a) * ny + j] + U * g2[a * n + kb]) / (1.0 + U);
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -724,8 +796,9 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t s
     double* fp = (double*)malloc(NQ * n * sizeof(double));
     double* g1p = (double*)malloc(NQ * n * sizeof(double));
     double* g2p = (double*)malloc(NQ * n * sizeof(double));
+    double* out_old = (double*)malloc(3 * NQ * (size_t)ny * sizeof(double));
     int rc = 0;
-    if (!phi1 || !phi2 || !mur || !fp || !g1p || !g2p) {
+    if (!phi1 || !phi2 || !mur || !fp || !g1p || !g2p || !out_old) {
         rc = -3;
         goto done;
     }
@@ -767,20 +840,32 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t s
                     g2p[a * n + k] = go2[a];
                 }
             }
+        /* Open channel: the outlet column before streaming, for the convective condition. */
+        if (P->open_x)
+            for (int j = 0; j < ny; ++j)
+                for (int a = 0; a < NQ; ++a) {
+                    size_t k = IDX(nx - 1, j, nx);
+                    out_old[(0 * NQ + a) * ny + j] = f[a * n + k];
+                    out_old[(1 * NQ + a) * ny + j] = g1[a * n + k];
+                    out_old[(2 * NQ + a) * ny + j] = g2[a * n + k];
+                }
         /* Pull streaming; halfway bounce-back when the source lies beyond a wall
-         * (reading: the paper says bounce-back without naming the variant). */
+         * (reading: the paper says bounce-back without naming the variant).  In the open
+         * channel a source beyond the inlet or outlet is unknown: set just below. */
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t k = IDX(i, j, nx);
                 for (int a = 0; a < NQ; ++a) {
-                    int js = j - EY[a];
+                    int js = j - EY[a], is = i - EX[a];
                     size_t src;
                     int as;
                     if (js < 0 || js > ny - 1) {
                         src = k;
                         as = OPP[a];
+                    } else if (P->open_x && (is < 0 || is > nx - 1)) {
+                        continue;
                     } else {
-                        src = IDX(wrap(i - EX[a], nx), js, nx);
+                        src = IDX(wrap(is, nx), js, nx);
                         as = a;
                     }
                     f[a * n + k] = fp[as * n + src];
@@ -788,6 +873,7 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t s
                     g2[a * n + k] = g2p[as * n + src];
                 }
             }
+        if (P->open_x) open_boundaries(P, out_old, f, g1, g2);
     }
 done:
     free(phi1);
@@ -796,6 +882,7 @@ done:
     free(fp);
     free(g1p);
     free(g2p);
+    free(out_old);
     return rc;
 }
 
@@ -1089,10 +1176,10 @@ void orc_stencils(int32_t nx, int32_t ny, const double* a, double* gx, double* g
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double g[2];
-            iso_grad(a, nx, ny, i, j, g);
+            iso_grad(a, nx, ny, i, j, 0, g);
             gx[IDX(i, j, nx)] = g[0];
             gy[IDX(i, j, nx)] = g[1];
-            lap[IDX(i, j, nx)] = iso_lap(a, nx, ny, i, j);
+            lap[IDX(i, j, nx)] = iso_lap(a, nx, ny, i, j, 0);
         }
 }
 

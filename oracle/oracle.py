@@ -16,13 +16,13 @@ _dp = C.POINTER(C.c_double)
 
 class OracleParams(C.Structure):
     _fields_ = [
-        ("nx", C.c_int32), ("ny", C.c_int32), ("pad0", C.c_int32), ("pad1", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("open_x", C.c_int32), ("pad1", C.c_int32),
         ("rho", C.c_double * 3), ("tau", C.c_double * 3), ("chi", C.c_double * 3),
         ("sigma12", C.c_double), ("sigma13", C.c_double), ("sigma23", C.c_double),
         ("eta", C.c_double), ("xi", C.c_double), ("mobility", C.c_double),
         ("H0", C.c_double), ("alpha", C.c_double), ("mu0", C.c_double),
         ("drive_G", C.c_double), ("grav_x", C.c_double), ("grav_y", C.c_double),
-        ("eps_n", C.c_double),
+        ("eps_n", C.c_double), ("u_inlet", C.c_double),
     ]
 
 
@@ -115,6 +115,8 @@ def params_from_workload(w) -> OracleParams:
     p.H0, p.alpha, p.mu0 = w.H0, w.alpha, w.mu0
     p.drive_G, p.grav_x, p.grav_y = w.drive_G, w.grav[0], w.grav[1]
     p.eps_n = w.eps_n
+    p.open_x = 0 if w.u_inlet is None else 1
+    p.u_inlet = 0.0 if w.u_inlet is None else w.u_inlet
     return p
 
 
