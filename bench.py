@@ -279,6 +279,32 @@ def quasi_static(torch, steps: int) -> dict:
     return out
 
 
+def open_channel(torch, steps: int) -> dict:
+    """The paper's open-channel set-up (900 x 150, Eq. 37 inlet, convective outlet; Bo_m = 2,
+    ferrofluid shell, multigrid to 1e-10), FP64: throughput with the end-column boundary
+    launches against the same lattice and droplet run as a periodic channel under the
+    equivalent body force."""
+    from fcd_inputs import channel_drive, open_channel_paper
+    from paper_2410_11129_amd.sim import Channel
+    w = open_channel_paper(bond=2.0)
+    periodic = w.replace(u_inlet=None, drive_G=channel_drive(w.u_inlet, w.rho[2], w.tau[2], w.ny))
+    out = {"workload": "open_channel_900x150_fp64_bo2", "steps": steps}
+    for name, ww in (("open", w), ("periodic", periodic)):
+        ch = Channel(ww, tol=1e-10)
+        ch.init_droplet()
+        ch.solve_potential(1e-10)
+        ch.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[f"{name}_MLUPS"] = round(ww.sites / dt / 1e6, 1)
+        out[f"{name}_ms_per_step"] = round(dt * 1e3, 4)
+        ch.close()
+    return out
+
+
 def copy_bandwidth_gbs(torch) -> float:
     n = 1 << 28  # 2 GiB of float64 each way
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -318,6 +344,8 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--quasi-static-steps", type=int, default=400)
     ap.add_argument("--no-quasi-static", action="store_true")
+    ap.add_argument("--open-channel-steps", type=int, default=1000)
+    ap.add_argument("--no-open-channel", action="store_true")
     ap.add_argument("--batch-adjoint-steps", type=int, default=3000)
     ap.add_argument("--batch-adjoint-ckpt", type=int, default=150)
     args = ap.parse_args()
@@ -408,6 +436,9 @@ def main() -> int:
     if not args.no_quasi_static:
         out["quasi_static"] = quasi_static(torch, args.quasi_static_steps)
         log(f"bench: quasi-static coupling {out['quasi_static']}")
+    if not args.no_open_channel:
+        out["open_channel"] = open_channel(torch, args.open_channel_steps)
+        log(f"bench: open channel {out['open_channel']}")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, args.adjoint_steps, args.adjoint_ckpt)
         log(f"bench: adjoint {out['adjoint']}")

@@ -130,6 +130,18 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
 /* Replace the parameters (takes effect for work enqueued afterwards). */
 fcd_status fcd_set_params(fcd_handle* h, const fcd_params* prm);
 
+/* Open channel of Sec. 2.5: from now on x = 0 is the velocity inlet of Eq. 37,
+ * u = 4 u_avg (y/H)(1 - y/H), v = 0, with y = j + 1/2 and H = ny (Zou-He closure of f;
+ * the inflow carries only the ambient phase), and x = nx - 1 is the convective outlet
+ * f(t+1, N) = [f(t, N) + U f(t+1, N-1)] / (1 + U) for f, g1 and g2, U the section mean
+ * of the inlet profile.  The phi stencils at the two end columns take zero normal
+ * gradient; psi' keeps its periodic closure in x.  The channel is usually driven by the
+ * inflow alone (drive_G = 0).  Call before fcd_init_compound_droplet, which then uses the
+ * Eq. 37 profile and no periodic image.  Waits for the handle's stream.  FCD_ERR_ARG
+ * unless 0 <= u_avg < 1.  The adjoint rejects an open-channel handle; batches are
+ * periodic. */
+fcd_status fcd_set_open_channel(fcd_handle* h, double u_avg);
+
 /* Initial state of Sec. 2.5: concentric core (radius r_core) and shell (r_shell)
  * centred at (xc, yc), tanh profiles of width xi (minimum image in x); ambient
  * Poiseuille velocity under drive_G; p* = 0; f = f^eq (Eq. 16), g^i = phi_i Gamma

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfcd.so")
-SOURCES = ["fcd_kernels.hip", "fcd_potential.hip", "fcd_batch.hip", "fcd_adjoint.hip", "fcd_extent.hip", "fcd_abi.hip"]
+SOURCES = ["fcd_kernels.hip", "fcd_potential.hip", "fcd_batch.hip", "fcd_adjoint.hip", "fcd_extent.hip", "fcd_open.hip", "fcd_abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -229,6 +229,9 @@ struct fcd_handle {
     int qs;    // steps since the last state change (the potential is solved when qs % pot_every == 0)
     int last_iters;  // iterations the previous solve needed (first residual test is deferred)
     int init_fresh;  // the state is the compound-droplet initial state (no step since)
+    int open_x;      // open channel: Eq. 37 inlet at x = 0, convective outlet at x = nx - 1
+    double u_in;     // u_avg of Eq. 37 (centreline value of the inlet profile)
+    double u_out;    // convective velocity of the outlet: the section mean of the inlet profile
     // checkpointed adjoint: set by fcd_adjoint_forward, used by fcd_adjoint_backward
     char* adj_work;
     int adj_nsteps, adj_every, adj_from_init;
@@ -729,6 +732,9 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
         ++h->qs;
         timed = h->timer.begin(h->stream, &ev);
         fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, h->stream);
+        if (h->open_x)
+            fcd::launch_open_boundaries<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, h->u_in, h->u_out,
+                                           h->stream);
         if (timed) h->timer.end(h->stream, TK_COLLIDE, ev);
         st = hip_check(hipGetLastError(), "collide-stream launch");
         if (st) return st;
@@ -754,6 +760,10 @@ fcd_status moments_impl(fcd_handle* h, unsigned mask, double* out) {
     const fcd::StepConst<T> P = make_const<T>(h);
     fcd::launch_moments<T>(static_cast<const T*>(h->buf.dist[h->cur]), static_cast<const T*>(h->buf.phi),
                            static_cast<const T*>(h->buf.psi), P, mask, out, h->stream);
+    if (h->open_x)
+        fcd::launch_open_edge_moments<T>(static_cast<const T*>(h->buf.dist[h->cur]),
+                                         static_cast<const T*>(h->buf.phi), static_cast<const T*>(h->buf.psi), P,
+                                         mask, out, h->stream);
     return hip_check(hipGetLastError(), "moments launch");
 }
 
@@ -845,8 +855,12 @@ template <typename T>
 fcd_status init_droplet_impl(fcd_handle* h, double xc, double yc, double rc, double rs) {
     const double nu3 = h->prm.tau[2] / 3.0;
     const double u_scale = h->prm.drive_G / (2.0 * h->prm.rho[2] * nu3);
-    fcd::launch_init_droplet<T>(static_cast<T*>(h->buf.dist[h->cur]), h->lat.nx, h->lat.ny, h->lat.pitch, xc, yc, rc,
-                                rs, h->prm.xi, u_scale, h->stream);
+    if (h->open_x)
+        fcd::launch_open_init_droplet<T>(static_cast<T*>(h->buf.dist[h->cur]), h->lat.nx, h->lat.ny, h->lat.pitch, xc,
+                                         yc, rc, rs, h->prm.xi, h->u_in, h->stream);
+    else
+        fcd::launch_init_droplet<T>(static_cast<T*>(h->buf.dist[h->cur]), h->lat.nx, h->lat.ny, h->lat.pitch, xc, yc,
+                                    rc, rs, h->prm.xi, u_scale, h->stream);
     fcd::launch_fill<T>(static_cast<T*>(h->buf.psi), (long long)h->lat.ny * h->lat.pitch, T(0), h->stream);
     return hip_check(hipGetLastError(), "init launch");
 }
@@ -2015,6 +2029,8 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     h->qs = 0;
     h->last_iters = 0;
     h->init_fresh = 0;
+    h->open_x = 0;
+    h->u_in = h->u_out = 0.0;
     h->adj_work = nullptr;
     h->adj_nsteps = h->adj_every = h->adj_from_init = 0;
     h->adj_final_iters = h->adj_final_hist = 0;
@@ -2041,6 +2057,22 @@ fcd_status fcd_use_graphs(fcd_handle* h, int32_t enable) {
     fcd_status st = hip_check(hipStreamSynchronize(h->stream), "stream sync");
     h->graphs.clear();
     h->graphs.enabled = enable != 0;
+    return st;
+}
+
+fcd_status fcd_set_open_channel(fcd_handle* h, double u_avg) {
+    if (!h) return fail(FCD_ERR_ARG, "handle is null");
+    if (!(u_avg >= 0.0) || !(u_avg < 1.0)) return fail(FCD_ERR_ARG, "need 0 <= u_avg < 1");
+    fcd_status st = hip_check(hipStreamSynchronize(h->stream), "stream sync");
+    h->open_x = 1;
+    h->u_in = u_avg;
+    double U = 0.0;
+    for (int j = 0; j < h->lat.ny; ++j) {
+        const double s = (j + 0.5) / h->lat.ny;
+        U += 4.0 * u_avg * s * (1.0 - s);
+    }
+    h->u_out = U / h->lat.ny;
+    h->graphs.clear();
     return st;
 }
 
@@ -2189,6 +2221,7 @@ fcd_status fcd_adjoint_forward(fcd_handle* h, int32_t nsteps, int32_t ckpt_every
     if (nsteps < 1 || ckpt_every < 1) return fail(FCD_ERR_ARG, "need nsteps >= 1 and ckpt_every >= 1");
     if (reinterpret_cast<uintptr_t>(work) % 256) return fail(FCD_ERR_ARG, "work must be 256-byte aligned");
     if (h->prm.pot_every > 1) return fail(FCD_ERR_ARG, "the adjoint needs a potential solve every step (pot_every <= 1)");
+    if (h->open_x) return fail(FCD_ERR_ARG, "the adjoint covers the periodic channel only");
     return FCD_DISPATCH(h, adj_forward_impl)(h, nsteps, ckpt_every, static_cast<char*>(work), D_out);
 }
 

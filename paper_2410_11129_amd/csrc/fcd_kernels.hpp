@@ -74,5 +74,19 @@ void launch_extent(const T* phi, const StepConst<T>& P, unsigned long long* ly, 
 // droplet's weighted sum cos, sum sin.
 template <typename T>
 void launch_breakup_probe(const T* phi, const StepConst<T>& P, double* rows, double* sums, hipStream_t s);
+// Open channel (fcd_open.hip): after the periodic collide-and-stream of src into dst, the end
+// columns re-collided with zero-gradient phi stencils, then the Eq. 37 inlet and the
+// convective outlet (u_in: centreline inflow; U: outlet convective velocity).
+template <typename T>
+void launch_open_boundaries(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P, double u_in,
+                            double U, hipStream_t s);
+// Moments of the two end columns with the open-channel stencils (after launch_moments).
+template <typename T>
+void launch_open_edge_moments(const T* src, const T* phi, const T* psi, const StepConst<T>& P, unsigned mask,
+                              double* out, hipStream_t s);
+// Compound-droplet initial state of the open channel (plain distance, Eq. 37 profile).
+template <typename T>
+void launch_open_init_droplet(T* dist, int nx, int ny, int pitch, double xc, double yc, double rc, double rs,
+                              double xi, double u_in, hipStream_t s);
 
 }  // namespace fcd

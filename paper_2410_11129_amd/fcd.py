@@ -25,7 +25,7 @@ MOMENT_NAMES = ("pstar", "ux", "uy", "phi1", "phi2", "phi3", "rho", "psi", "Hx",
 
 # Every symbol include/fcd.h declares.
 EXPORTS = (
-    "fcd_scratch_bytes", "fcd_create", "fcd_set_params", "fcd_init_compound_droplet",
+    "fcd_scratch_bytes", "fcd_create", "fcd_set_params", "fcd_set_open_channel", "fcd_init_compound_droplet",
     "fcd_init_fields", "fcd_solve_potential", "fcd_step", "fcd_read_moments", "fcd_read_state",
     "fcd_write_state", "fcd_read_psi", "fcd_write_psi", "fcd_deformation", "fcd_extent_deformation", "fcd_breakup_probe", "fcd_stats", "fcd_timing",
     "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
@@ -86,6 +86,7 @@ def lib():
                                  C.c_void_p, C.POINTER(C.c_void_p)]
         L.fcd_set_params.argtypes = [H, C.POINTER(fcd_params)]
         L.fcd_init_compound_droplet.argtypes = [H, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.fcd_set_open_channel.argtypes = [H, C.c_double]
         L.fcd_init_fields.argtypes = [H, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.fcd_solve_potential.argtypes = [H, C.c_double, C.c_int32, C.POINTER(C.c_int32), dp]
         L.fcd_step.argtypes = [H, C.c_int32]
@@ -157,6 +158,10 @@ def fcd_create(lat: fcd_lattice, prm: fcd_params, buf: fcd_buffers, stream: int)
 
 def fcd_set_params(h, prm: fcd_params):
     _check(lib().fcd_set_params(h, C.byref(prm)), "fcd_set_params")
+
+
+def fcd_set_open_channel(h, u_avg: float):
+    _check(lib().fcd_set_open_channel(h, u_avg), "fcd_set_open_channel")
 
 
 def fcd_init_compound_droplet(h, xc: float, yc: float, r_core: float, r_shell: float):

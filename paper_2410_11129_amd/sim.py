@@ -58,6 +58,8 @@ class Channel:
         self.buf.scratch = self.scratch.data_ptr()
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.h = fcd.fcd_create(self.lat, self.prm, self.buf, self.stream.cuda_stream)
+        if w.u_inlet is not None:  # open channel (Eq. 37 inlet, convective outlet)
+            fcd.fcd_set_open_channel(self.h, w.u_inlet)
 
     def close(self):
         if self.h is not None:

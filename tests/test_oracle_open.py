@@ -75,6 +75,8 @@ def test_centre_line_droplet_keeps_the_mirror_symmetry():
 
 
 def test_phase_mass_is_conserved_away_from_the_ends():
+    """Over a short run; later the ambient fluid takes up a trace of each droplet phase
+    (order 1e-6 after 2000 steps of this channel) which the outlet then carries away."""
     w = open_channel_small(xc=60.0).replace(nx=120, ny=30, yc=14.5, r_core=4.0, r_shell=8.0)
     sim = OracleSim(w)
     p1, p2 = sim.init_droplet()
