@@ -82,7 +82,8 @@ typedef struct {
     int32_t pot_check_every; /* SOR sweeps / multigrid V-cycles between residual tests */
     int32_t pot_max_iters;   /* SOR sweeps / V-cycles allowed per solve */
     int32_t pot_smooth;      /* multigrid: Gauss-Seidel sweeps before and after each coarse correction */
-    int32_t pot_coarse_sweeps; /* multigrid: SOR sweeps on the coarsest level, times max(1, ny_c / 2) */
+    int32_t pot_coarse_sweeps; /* multigrid: SOR sweeps on the coarsest level, times max(1, ny_c / 2);
+                                  a negative value -N: exactly N sweeps; 0 is rejected */
     int32_t pot_extrapolate; /* warm start of each step's solve: 0 the previous psi', 1 the linear
                                 extrapolation 2 psi'(t-1) - psi'(t-2), 2 the quadratic one
                                 3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3) (batches: 2 acts as 1) */

@@ -264,8 +264,8 @@ fcd_status check_params(const fcd_params* p) {
     if (p->pot_solver != FCD_SOLVER_SOR && p->pot_solver != FCD_SOLVER_MG)
         return fail(FCD_ERR_ARG, "unknown pot_solver");
     if (p->pot_check_every < 1 || p->pot_max_iters < 0) return fail(FCD_ERR_ARG, "bad potential iteration counts");
-    if (p->pot_solver == FCD_SOLVER_MG && (p->pot_smooth < 1 || p->pot_coarse_sweeps < 1))
-        return fail(FCD_ERR_ARG, "multigrid needs pot_smooth >= 1 and pot_coarse_sweeps >= 1");
+    if (p->pot_solver == FCD_SOLVER_MG && (p->pot_smooth < 1 || p->pot_coarse_sweeps == 0))
+        return fail(FCD_ERR_ARG, "multigrid needs pot_smooth >= 1 and pot_coarse_sweeps != 0");
     if (p->pot_extrapolate < 0 || p->pot_extrapolate > 2) return fail(FCD_ERR_ARG, "pot_extrapolate must be 0, 1 or 2");
     if (p->pot_every < 0) return fail(FCD_ERR_ARG, "pot_every must be >= 0");
     return FCD_OK;
@@ -457,9 +457,13 @@ fcd_status run_graph(fcd_handle* h, const void* k1, const void* k2, int kind, F&
     return run_graph_on(h->graphs, h->stream, h->timer.on, k1, k2, kind, record);
 }
 
-// SOR sweeps per V-cycle on a coarsest level with ny rows: a few suffice on the two-row
-// levels of a full hierarchy; a hierarchy stopped early needs more on its larger rows.
-int coarse_sweeps(const fcd_handle* h, int ny) { return std::max(1, h->prm.pot_coarse_sweeps) * std::max(1, ny / 2); }
+// SOR sweeps per V-cycle on a coarsest level with ny rows: pot_coarse_sweeps times
+// max(1, ny / 2) (a few suffice on the two-row levels of a full hierarchy; a hierarchy
+// stopped early gets more on its larger rows), or exactly -pot_coarse_sweeps when negative.
+int coarse_sweeps(const fcd_handle* h, int ny) {
+    const int c = h->prm.pot_coarse_sweeps;
+    return c < 0 ? -c : c * std::max(1, ny / 2);
+}
 
 // Solve the coarsest level by launched SOR sweeps (no tail, or no coarse level at all).
 template <typename T>

@@ -101,6 +101,10 @@ def test_batch_schedule_calls_and_warm_start_order_validated_on_host():
     buf = fcd.fcd_buffers()
     buf.dist[0], buf.dist[1], buf.phi, buf.psi, buf.scratch = 256, 512, 768, 1024, 1280
     p = good_params()
+    p.pot_coarse_sweeps = 0  # positive: times ny_c / 2; negative: an absolute count
+    st = L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h := C.c_void_p()))
+    assert st == fcd.FCD_ERR_ARG and "pot_coarse_sweeps" in fcd.fcd_last_error()
+    p = good_params()
     p.pot_extrapolate = 3
     h = C.c_void_p()
     st = L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h))

@@ -137,3 +137,21 @@ def test_open_channel_rejected_by_the_adjoint_and_checked_on_host():
     st = fcd.lib().fcd_adjoint_forward(g.h, 4, 2, fcd.C.c_void_p(work.data_ptr()), D)
     assert st == fcd.FCD_ERR_ARG and "periodic" in fcd.fcd_last_error()
     g.close()
+
+
+def test_absolute_coarse_sweep_count_reaches_the_same_solution():
+    """The 200 x 50 hierarchy also halves once (100 x 25): with an absolute coarse-sweep
+    count (pot_coarse_sweeps < 0) each solve still stops at the same residual test, so the
+    run agrees with the default schedule to the solve tolerance's level."""
+    w = open_channel_small(xc=100.0)
+    say("case open channel 200x50 coarse sweeps -16 vs default")
+    runs = []
+    for cs in (2, -16):
+        g = Channel(w, solver=fcd.FCD_SOLVER_MG, tol=1e-12, check_every=1, max_iters=1000, smooth=4,
+                    coarse_sweeps=cs)
+        g.init_droplet()
+        g.step(60)
+        runs.append((g.state(), g.psi_dense()))
+        g.close()
+    assert np.abs(runs[0][0] - runs[1][0]).max() < 1e-10
+    assert np.abs(runs[0][1] - runs[1][1]).max() < 1e-9
