@@ -155,3 +155,29 @@ def test_absolute_coarse_sweep_count_reaches_the_same_solution():
         g.close()
     assert np.abs(runs[0][0] - runs[1][0]).max() < 1e-10
     assert np.abs(runs[0][1] - runs[1][1]).max() < 1e-9
+
+
+def test_paper_open_channel_fp32_tracks_fp64():
+    """900 x 150 open channel, 2000 steps: the FP32 path's deformation time series (sampled
+    every 500 steps) within the stated 1e-3 of the FP64 path's, mean |d phi| within 1e-4."""
+    w = open_channel_paper(bond=2.0)
+    say(f"case open channel {w.nx}x{w.ny} FP32 vs FP64, 2000 steps")
+    a = Channel(w, tol=1e-10, smooth=12, coarse_sweeps=-16)
+    b = Channel(w, precision=fcd.FCD_FP32, tol=1e-5, smooth=12, coarse_sweeps=-16)
+    for c in (a, b):
+        c.init_droplet()
+    worst = 0.0
+    for k in range(4):
+        a.step(500)
+        b.step(500)
+        da, db = a.deformation(), b.deformation()
+        worst = max(worst, abs(da[0] - db[0]), abs(da[1] - db[1]))
+        say(f"  step {500 * (k + 1)}: D_o {da[0]:.6e} vs {db[0]:.6e}, D_i {da[1]:.6e} vs {db[1]:.6e}")
+    assert worst <= 1e-3, worst
+    ma, mb = a.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2), b.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2)
+    for key in ma:
+        diff = np.abs(ma[key] - mb[key])
+        say(f"  {key}: mean |fp32 - fp64| = {diff.mean():.2e}, max {diff.max():.2e}")
+        assert diff.mean() <= 1e-4, key
+    a.close()
+    b.close()
