@@ -181,3 +181,21 @@ def test_paper_open_channel_fp32_tracks_fp64():
         assert diff.mean() <= 1e-4, key
     a.close()
     b.close()
+
+
+def test_open_channel_with_quasi_static_coupling_parity():
+    """The open channel combined with the potential solved every 4 steps: FP64 state within
+    1e-10 of the oracle's after 200 steps."""
+    from oracle.oracle import OracleSolver
+    w = open_channel_small(xc=170.0)
+    say("case open channel outlet 200x50 FP64, potential every 4 steps, 200 steps")
+    s = OracleSim(w, OracleSolver.direct(every=4))
+    s.init_droplet()
+    s.step(200)
+    g = Channel(w, every=4, **TIGHT)
+    g.init_droplet()
+    g.step(200)
+    err = np.abs(g.state() - np.concatenate([s.f, s.g1, s.g2], axis=0)).max()
+    say(f"  state max |gpu - oracle| = {err:.2e}")
+    assert err < 1e-10
+    g.close()
