@@ -312,6 +312,47 @@ static double iso_lap(const double* a, int nx, int ny, int i, int j, int clamp_x
     return 2.0 * s / CS2;
 }
 
+/* Interface normals and the counter-diffusion magnitude of Eq. 23 for the three
+ * phases: n_k = grad phi_k / sqrt(|grad phi_k|^2 + eps_n^2) (reading: the paper leaves
+ * n undefined where grad phi vanishes), theta_k = (4/xi) phi_k (1 - phi_k). */
+static void interface_terms(const orc_params* P, const double* phi, const double (*gphi)[2], double* theta,
+                            double (*nrm)[2]) {
+    for (int s = 0; s < 3; ++s) {
+        double gx = gphi[s][0], gy = gphi[s][1];
+        double nn = sqrt(gx * gx + gy * gy + P->eps_n * P->eps_n);
+        nrm[s][0] = gx / nn;
+        nrm[s][1] = gy / nn;
+        theta[s] = 4.0 / P->xi * phi[s] * (1.0 - phi[s]);
+    }
+}
+
+/* Source term of the phase-field LBE of component comp (Eq. 29).  Reading: the paper
+ * only cites it; taken as the term whose first moment is c_s^2 times the
+ * counter-diffusion flux of Eq. 23 for that component,
+ *   F^{phi,i}_alpha = w_alpha e_alpha . [theta_i n_i - (1/3) sum_k theta_k n_k],
+ * the inner sum over all three phases (Eq. 23 with its reused index read as a sum over
+ * k), so that the three right-hand sides of Eq. 23 add up to zero as phi_1 + phi_2 +
+ * phi_3 = 1 requires. */
+static void phase_source(const double theta[3], const double nrm[3][2], int comp, double F[NQ]) {
+    double sx = 0.0, sy = 0.0;
+    for (int s = 0; s < 3; ++s) {
+        sx += theta[s] * nrm[s][0];
+        sy += theta[s] * nrm[s][1];
+    }
+    double vx = theta[comp] * nrm[comp][0] - sx / 3.0;
+    double vy = theta[comp] * nrm[comp][1] - sy / 3.0;
+    for (int a = 0; a < NQ; ++a) F[a] = WQ[a] * (EX[a] * vx + EY[a] * vy);
+}
+
+/* Exported for the tests: the sources of all three components at one node from phi_k and
+ * grad phi_k (k = 1..3), out[k * 9 + alpha]. */
+void orc_phase_source(const orc_params* P, const double phi[3], const double gphi[6], double out[3 * NQ]) {
+    double g[3][2] = {{gphi[0], gphi[1]}, {gphi[2], gphi[3]}, {gphi[4], gphi[5]}};
+    double theta[3], nrm[3][2];
+    interface_terms(P, phi, g, theta, nrm);
+    for (int c = 0; c < 3; ++c) phase_source(theta, nrm, c, out + c * NQ);
+}
+
 /* Everything the collision at one node needs. */
 typedef struct {
     double phi[3], gphi[3][2], lphi[3], nrm[3][2], theta[3];
@@ -339,13 +380,7 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
     q->lphi[0] = iso_lap(phi1, nx, ny, i, j, P->open_x);
     q->lphi[1] = iso_lap(phi2, nx, ny, i, j, P->open_x);
     q->lphi[2] = -q->lphi[0] - q->lphi[1];
-    for (int s = 0; s < 3; ++s) {
-        double gx = q->gphi[s][0], gy = q->gphi[s][1];
-        double nn = sqrt(gx * gx + gy * gy + P->eps_n * P->eps_n);
-        q->nrm[s][0] = gx / nn;
-        q->nrm[s][1] = gy / nn;
-        q->theta[s] = 4.0 / P->xi * q->phi[s] * (1.0 - q->phi[s]); /* Eq. 23 */
-    }
+    interface_terms(P, q->phi, q->gphi, q->theta, q->nrm);
     /* Mixture closure: Eq. 33 for rho.  Reading: the paper does not say how the
      * viscosity is mixed; tau = sum phi_i tau_i (linear). */
     q->rho = 0.0;
@@ -433,26 +468,16 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
     q->u[1] = jy + q->Ft[1] / (2.0 * q->rho);
 }
 
-/* Phase-field collision, Eq. 29-31.  Reading: the source term, which the paper only
- * cites, is the one whose first moment is c_s^2 times the counter-diffusion flux of
- * Eq. 23: F^{phi,i}_alpha = w_alpha e_alpha . [theta_i n_i - (1/3) sum_k theta_k n_k],
- * theta_k = (4/xi) phi_k (1 - phi_k).  phi in Eq. 31 is phi_i and Gamma uses the final
- * velocity of the step. */
+/* Phase-field collision, Eq. 29-31, with the source term of phase_source.  phi in
+ * Eq. 31 is phi_i and Gamma uses the final velocity of the step. */
 static void collide_g(const orc_params* P, const nodeq* q, int comp, const double g[NQ], double out[NQ]) {
-    double Gm[NQ];
+    double Gm[NQ], Fphi[NQ];
     orc_gamma(q->u, Gm);
-    double sx = 0.0, sy = 0.0;
-    for (int s = 0; s < 3; ++s) {
-        sx += q->theta[s] * q->nrm[s][0];
-        sy += q->theta[s] * q->nrm[s][1];
-    }
-    double vx = q->theta[comp] * q->nrm[comp][0] - sx / 3.0;
-    double vy = q->theta[comp] * q->nrm[comp][1] - sy / 3.0;
+    phase_source(q->theta, q->nrm, comp, Fphi);
     double tau_phi = P->mobility / CS2; /* Eq. 30, its "c_s^s" read as c_s^2 */
     for (int a = 0; a < NQ; ++a) {
-        double Fphi = WQ[a] * (EX[a] * vx + EY[a] * vy);
-        double geq = q->phi[comp] * Gm[a] - 0.5 * Fphi; /* Eq. 31 */
-        out[a] = g[a] - (g[a] - geq) / (0.5 + tau_phi) + Fphi;
+        double geq = q->phi[comp] * Gm[a] - 0.5 * Fphi[a]; /* Eq. 31 */
+        out[a] = g[a] - (g[a] - geq) / (0.5 + tau_phi) + Fphi[a];
     }
 }
 

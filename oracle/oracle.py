@@ -90,6 +90,7 @@ def lib():
         L.orc_breakup_probe.argtypes = [P, _dp, _dp, _dp]
         L.orc_stencils.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
         L.orc_mu_r.argtypes = [P, _dp, _dp, _dp]
+        L.orc_phase_source.argtypes = [P, _dp, _dp, _dp]
         for name in ("orc_init_fields", "orc_init_droplet", "orc_step", "orc_moments",
                      "orc_forces", "orc_diagnostics", "orc_extent_deformation", "orc_breakup_probe",
                      "orc_solve_potential_phi"):
