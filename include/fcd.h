@@ -78,6 +78,9 @@ typedef struct {
     double pot_omega; /* SOR over-relaxation in (0, 2); 0 selects 2 / (1 + sin(pi / (ny + 1))).
                          Multigrid: used when the hierarchy has one level (ny odd), else
                          the default serves its coarsest level. */
+    double u_limit;   /* divergence guard: a node with max(|u_x|, |u_y|) above u_limit, or a
+                         non-finite p*, phi1 or phi2, marks the state as diverged (the lattice
+                         sound speed is c_s = 1/sqrt(3); 0 selects 0.5) */
     int32_t pot_solver;      /* FCD_SOLVER_SOR or FCD_SOLVER_MG */
     int32_t pot_check_every; /* SOR sweeps / multigrid V-cycles between residual tests */
     int32_t pot_max_iters;   /* SOR sweeps / V-cycles allowed per solve */
@@ -91,6 +94,9 @@ typedef struct {
                                 after the last state change and held in between (K = pot_every;
                                 0 or 1: every step, the paper's coupling; the adjoints need <= 1;
                                 batches use channel 0's value) */
+    int32_t div_check_every; /* steps between host reads of the device divergence flag inside
+                                fcd_step / fcd_batch_step (0 selects 64); every residual test of
+                                the potential solve reads it as well */
 } fcd_params;
 
 /* Caller-owned device buffers (element type = lattice precision). */
@@ -165,7 +171,14 @@ fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_iters,
 
 /* Advance nsteps coupled time steps: phases and mu_r, potential solve (pot_tol,
  * pot_max_iters), then the fused collide-and-stream of f, g1, g2 with all forces.
- * The potential solve synchronises the stream at each residual test. */
+ * The potential solve synchronises the stream at each residual test.
+ * Divergence guard: the collide-and-stream kernel raises a device flag when a node's
+ * velocity exceeds u_limit or its p*, phi1 or phi2 is not finite; the flag stays set
+ * until the state is replaced (fcd_init_*, fcd_write_state).  It is read at every
+ * residual test, every div_check_every steps and by every sync call of the handle, and
+ * a set flag makes the call return FCD_ERR_DIVERGED (the message gives the largest
+ * |u| seen, or names a non-finite state).  Detection lags the kernel that raised it by
+ * at most one step when the potential is solved, by div_check_every steps when not. */
 fcd_status fcd_step(fcd_handle* h, int32_t nsteps);
 
 /* Write the fields selected by `mask` (FCD_M_*) for the current state into `out`,
@@ -229,7 +242,8 @@ fcd_status fcd_timing_read(fcd_handle* h, double out[12]);
  * fcd_timing is on.  Sync. */
 fcd_status fcd_use_graphs(fcd_handle* h, int32_t enable);
 
-/* Wait for the stream and report any asynchronous HIP error.  Sync. */
+/* Wait for the stream and report any asynchronous HIP error, then FCD_ERR_DIVERGED if
+ * the divergence flag is set.  Sync. */
 fcd_status fcd_sync(fcd_handle* h);
 
 /* Free the handle (not the caller's buffers).  Waits for the stream. */
@@ -289,7 +303,10 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
  * {xc, yc, r_core, r_shell} (the same initial state as fcd_init_compound_droplet). */
 fcd_status fcd_batch_init_compound_droplet(fcd_batch* b, const double* geom);
 
-/* Advance every channel by nsteps coupled steps.  Synchronises at residual tests. */
+/* Advance every channel by nsteps coupled steps.  Synchronises at residual tests.  Each
+ * channel has its own divergence flag (as fcd_step; u_limit per channel, the check
+ * interval of channel 0); a set flag makes this call, fcd_batch_deformation and the
+ * batched adjoint return FCD_ERR_DIVERGED naming the first such channel. */
 fcd_status fcd_batch_step(fcd_batch* b, int32_t nsteps);
 
 /* Deformation and masses of every channel: out is a host array of n rows

@@ -30,6 +30,7 @@ fcd_status hip_check(hipError_t e, const char* what) {
 
 // Scratch layout (bytes from the start of the caller's scratch buffer).
 constexpr size_t OFF_RES = 0;      // 2 x uint64: bit patterns of max |residual| and max |C psi'|
+constexpr size_t OFF_DIV = 16;     // uint64: divergence flag (0, or the worst node's max |u| bits / NaN)
 constexpr size_t OFF_CENT = 256;   // 8 doubles: centroids and masses
 constexpr size_t OFF_RESULT = 512; // 4 doubles: D_o, D_i, mass1, mass2
 constexpr size_t OFF_EXTENT = 768; // Eq. 42 extents: 2 x uint64 (l_y bit patterns), 2 doubles (l_x)
@@ -46,6 +47,10 @@ size_t elem_size(int precision) { return precision == FCD_FP64 ? sizeof(double) 
 double sor_omega_opt(int ny) { return 2.0 / (1.0 + std::sin(3.14159265358979323846 / (ny + 1))); }
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Divergence guard settings (0 selects the default).
+double u_limit_of(const fcd_params& p) { return p.u_limit > 0.0 ? p.u_limit : 0.5; }
+int div_every_of(const fcd_params& p) { return p.div_check_every > 0 ? p.div_check_every : 64; }
 
 // Multigrid hierarchy and scratch layout.  Level 0 is the lattice itself (psi', mu_r
 // planes of the caller, in the lattice's precision); coarser levels halve both
@@ -268,6 +273,8 @@ fcd_status check_params(const fcd_params* p) {
         return fail(FCD_ERR_ARG, "multigrid needs pot_smooth >= 1 and pot_coarse_sweeps != 0");
     if (p->pot_extrapolate < 0 || p->pot_extrapolate > 2) return fail(FCD_ERR_ARG, "pot_extrapolate must be 0, 1 or 2");
     if (p->pot_every < 0) return fail(FCD_ERR_ARG, "pot_every must be >= 0");
+    if (!(p->u_limit >= 0.0)) return fail(FCD_ERR_ARG, "u_limit must be >= 0 (0: default)");
+    if (p->div_check_every < 0) return fail(FCD_ERR_ARG, "div_check_every must be >= 0 (0: default)");
     return FCD_OK;
 }
 
@@ -323,6 +330,7 @@ fcd::StepConst<T> make_const(const fcd_handle* h) {
     c.grav_x = T(p.grav_x);
     c.grav_y = T(p.grav_y);
     c.eps2 = T(p.eps_n * p.eps_n);
+    c.u_limit = T(u_limit_of(p));
     return c;
 }
 
@@ -333,6 +341,42 @@ T* plane_ptr(void* base, const fcd_handle* h, int q) {
 
 unsigned long long* res_word(const fcd_handle* h) {
     return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + OFF_RES);
+}
+
+// The divergence flag sits right after the two residual words, so one three-word copy
+// brings a residual test's result and the flag to the host together.
+unsigned long long* div_word(const fcd_handle* h) {
+    return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + OFF_DIV);
+}
+
+
+// FCD_ERR_DIVERGED when a divergence flag word (as the collide kernel raises it) is set.
+fcd_status divergence_status(unsigned long long w, double limit, const std::string& who) {
+    if (w == 0) return FCD_OK;
+    double v;
+    std::memcpy(&v, &w, sizeof(v));
+    char msg[200];
+    if (v != v)
+        std::snprintf(msg, sizeof(msg), "%s: the state is not finite (NaN or Inf in p*, phi1 or phi2)", who.c_str());
+    else
+        std::snprintf(msg, sizeof(msg), "%s: max |u| = %.6g exceeds u_limit = %.6g", who.c_str(), v, limit);
+    return fail(FCD_ERR_DIVERGED, msg);
+}
+
+// Waits for the stream, then reports the flag.
+fcd_status read_divergence(fcd_handle* h) {
+    fcd_status st = hip_check(hipMemcpyAsync(h->host + 24, div_word(h), sizeof(unsigned long long),
+                                             hipMemcpyDeviceToHost, h->stream), "divergence flag copy");
+    if (!st) st = hip_check(hipStreamSynchronize(h->stream), "divergence flag sync");
+    if (st) return st;
+    unsigned long long w;
+    std::memcpy(&w, h->host + 24, sizeof(w));
+    return divergence_status(w, u_limit_of(h->prm), "divergence guard");
+}
+
+fcd_status clear_divergence(fcd_handle* h) {
+    hipLaunchKernelGGL(fcd::k_fill<unsigned long long>, dim3(1), dim3(64), 0, h->stream, div_word(h), 1LL, 0ULL);
+    return hip_check(hipGetLastError(), "divergence flag clear");
 }
 
 // Level 0 (the lattice's psi' and mu_r planes).
@@ -386,7 +430,7 @@ fcd_status read_residual(fcd_handle* h, const fcd::PotLevel<T>& L0, double* r, d
     if (timed) h->timer.end(h->stream, TK_RESID, ev);
     fcd_status st = hip_check(hipGetLastError(), "residual launch");
     if (st) return st;
-    st = hip_check(hipMemcpyAsync(h->host, res_word(h), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+    st = hip_check(hipMemcpyAsync(h->host, res_word(h), 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
                    "residual copy");
     if (st) return st;
     st = hip_check(hipStreamSynchronize(h->stream), "residual sync");
@@ -394,7 +438,9 @@ fcd_status read_residual(fcd_handle* h, const fcd::PotLevel<T>& L0, double* r, d
     h->timer.resolve();
     std::memcpy(r, h->host, sizeof(double));
     std::memcpy(scale, h->host + 1, sizeof(double));
-    return FCD_OK;
+    unsigned long long w;
+    std::memcpy(&w, h->host + 2, sizeof(w));
+    return divergence_status(w, u_limit_of(h->prm), "divergence guard");
 }
 
 // Coarse mu on every level, from the current mu_r plane.
@@ -638,12 +684,18 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
             bool timed = h->timer.begin(h->stream, &ev);
             T* cur0 = mg_presmooth<T>(h, L0, fine_mode(L0), res_word(h));
             if (timed) h->timer.end(h->stream, TK_RESID, ev);
-            st = hip_check(hipMemcpyAsync(h->host, res_word(h), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            st = hip_check(hipMemcpyAsync(h->host, res_word(h), 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
                            "residual copy");
             if (!st) st = hip_check(hipStreamSynchronize(h->stream), "residual sync");
             if (st) return st;
             std::memcpy(&r, h->host, sizeof(double));
             std::memcpy(&scale, h->host + 1, sizeof(double));
+            {
+                unsigned long long w;
+                std::memcpy(&w, h->host + 2, sizeof(w));
+                st = divergence_status(w, u_limit_of(h->prm), "divergence guard");
+                if (st) return st;
+            }
             if (r <= thr_of(scale)) break;
             if (r != r) {
                 h->last_resid = r;
@@ -735,7 +787,7 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
         }
         ++h->qs;
         timed = h->timer.begin(h->stream, &ev);
-        fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, h->stream);
+        fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, div_word(h), h->stream);
         if (h->open_x)
             fcd::launch_open_boundaries<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, h->u_in, h->u_out,
                                            h->stream);
@@ -744,6 +796,10 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
         if (st) return st;
         h->cur = 1 - h->cur;
         ++h->steps;
+        if (h->steps % div_every_of(h->prm) == 0) {
+            st = read_divergence(h);
+            if (st) return st;
+        }
     }
     return FCD_OK;
 }
@@ -852,7 +908,8 @@ fcd_status init_fields_impl(fcd_handle* h, const double* phi1, const double* phi
     fcd::launch_init_fields<T>(static_cast<T*>(h->buf.dist[h->cur]), phi1, phi2, ux, uy, ps, h->lat.nx, h->lat.ny,
                                h->lat.pitch, h->stream);
     fcd::launch_fill<T>(static_cast<T*>(h->buf.psi), (long long)h->lat.ny * h->lat.pitch, T(0), h->stream);
-    return hip_check(hipGetLastError(), "init launch");
+    fcd_status st = hip_check(hipGetLastError(), "init launch");
+    return st ? st : clear_divergence(h);
 }
 
 template <typename T>
@@ -866,7 +923,8 @@ fcd_status init_droplet_impl(fcd_handle* h, double xc, double yc, double rc, dou
         fcd::launch_init_droplet<T>(static_cast<T*>(h->buf.dist[h->cur]), h->lat.nx, h->lat.ny, h->lat.pitch, xc, yc,
                                     rc, rs, h->prm.xi, u_scale, h->stream);
     fcd::launch_fill<T>(static_cast<T*>(h->buf.psi), (long long)h->lat.ny * h->lat.pitch, T(0), h->stream);
-    return hip_check(hipGetLastError(), "init launch");
+    fcd_status st = hip_check(hipGetLastError(), "init launch");
+    return st ? st : clear_divergence(h);
 }
 
 template <typename T>
@@ -899,7 +957,7 @@ struct BatchLayout {
     size_t state_bytes = 0, aux_bytes = 0, scratch_bytes = 0;
     size_t off_inst = 0, off_tiles[fcd::BATCH_SHAPES] = {}, off_ctiles[fcd::BATCH_SHAPES] = {}, off_stiles = 0;
     size_t off_slist = 0;
-    size_t off_res = 0, off_active = 0, off_counts = 0, off_sweeps = 0;
+    size_t off_res = 0, off_active = 0, off_counts = 0, off_sweeps = 0, off_div = 0;
     size_t off_rows = 0, off_cent = 0, off_result = 0;
 };
 
@@ -973,6 +1031,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     off = align256(off + 2 * sizeof(int));
     L->off_sweeps = off;
     off = align256(off + (size_t)n * sizeof(int));
+    L->off_div = off;  // per-channel divergence flags
+    off = align256(off + (size_t)n * sizeof(unsigned long long));
     L->off_rows = off;
     off = align256(off + (size_t)max_ny * 8 * sizeof(double));
     L->off_cent = off;
@@ -1091,7 +1151,24 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
     }
     I.stile0 = b->L.stile0[k];
     I.stiles_x = b->L.stiles_x[k];
+    I.div = reinterpret_cast<unsigned long long*>(b->scratch + b->L.off_div) + k;
     return I;
+}
+
+// Reads every channel's divergence flag (waits for the stream); FCD_ERR_DIVERGED names the
+// first channel whose flag is set.
+fcd_status batch_read_divergence(fcd_batch* b) {
+    fcd_status st = hip_check(hipMemcpyAsync(b->host + 1, b->scratch + b->L.off_div,
+                                             (size_t)b->n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                             b->stream), "divergence flag copy");
+    if (!st) st = hip_check(hipStreamSynchronize(b->stream), "divergence flag sync");
+    if (st) return st;
+    for (int k = 0; k < b->n; ++k) {
+        unsigned long long w;
+        std::memcpy(&w, b->host + 1 + k, sizeof(w));
+        if (w) return divergence_status(w, u_limit_of(b->prm[k]), "divergence guard, channel " + std::to_string(k));
+    }
+    return FCD_OK;
 }
 
 // Re-uploads the channel descriptors after a parameter change (after the batch's queued
@@ -1320,6 +1397,10 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
         if (st) return st;
         b->cur = 1 - b->cur;
         ++b->steps;
+        if (b->steps % div_every_of(p0) == 0) {
+            st = batch_read_divergence(b);
+            if (st) return st;
+        }
     }
     return FCD_OK;
 }
@@ -1444,6 +1525,8 @@ fcd_status batch_init_impl(fcd_batch* b, const double* geom) {
                                     geom[4 * k + 1], geom[4 * k + 2], geom[4 * k + 3], p.xi, u_scale, b->stream);
     }
     fcd::launch_batch_fill_psi<T>(binst<T>(b), btiles(b), b->stream);
+    hipLaunchKernelGGL(fcd::k_fill<unsigned long long>, dim3((b->n + 255) / 256), dim3(256), 0, b->stream,
+                       reinterpret_cast<unsigned long long*>(b->scratch + b->L.off_div), (long long)b->n, 0ULL);
     b->cur = 0;
     b->hist = 0;
     b->qs = 0;
@@ -1476,7 +1559,7 @@ fcd_status batch_diag_impl(fcd_batch* b, double* out) {
     st = hip_check(hipStreamSynchronize(b->stream), "batch diagnostics sync");
     if (st) return st;
     std::memcpy(out, b->host + 1, (size_t)b->n * 4 * sizeof(double));
-    return FCD_OK;
+    return batch_read_divergence(b);
 }
 
 template <typename T>
@@ -2043,6 +2126,12 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
         delete h;
         return fail(FCD_ERR_OOM, "pinned host allocation failed");
     }
+    st = clear_divergence(h);  // the scratch arrives with the caller's contents
+    if (st) {
+        (void)hipHostFree(h->host);
+        delete h;
+        return st;
+    }
     *out = h;
     return FCD_OK;
 }
@@ -2137,7 +2226,8 @@ fcd_status fcd_write_state(fcd_handle* h, const double* in) {
     h->hist = 0;
     h->qs = 0;
     h->last_iters = 0;
-    return FCD_DISPATCH(h, copy_in_impl)(h, h->buf.dist[h->cur], 27, in);
+    fcd_status st = FCD_DISPATCH(h, copy_in_impl)(h, h->buf.dist[h->cur], 27, in);
+    return st ? st : clear_divergence(h);
 }
 
 fcd_status fcd_read_psi(fcd_handle* h, double* out) {
@@ -2155,17 +2245,20 @@ fcd_status fcd_write_psi(fcd_handle* h, const double* in) {
 
 fcd_status fcd_deformation(fcd_handle* h, double out[4]) {
     if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
-    return FCD_DISPATCH(h, diag_impl)(h, out);
+    fcd_status st = FCD_DISPATCH(h, diag_impl)(h, out);
+    return st ? st : read_divergence(h);
 }
 
 fcd_status fcd_extent_deformation(fcd_handle* h, double out[6]) {
     if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
-    return FCD_DISPATCH(h, extent_impl)(h, out);
+    fcd_status st = FCD_DISPATCH(h, extent_impl)(h, out);
+    return st ? st : read_divergence(h);
 }
 
 fcd_status fcd_breakup_probe(fcd_handle* h, double out[4]) {
     if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
-    return FCD_DISPATCH(h, breakup_impl)(h, out);
+    fcd_status st = FCD_DISPATCH(h, breakup_impl)(h, out);
+    return st ? st : read_divergence(h);
 }
 
 fcd_status fcd_stats(fcd_handle* h, double out[3]) {
@@ -2202,7 +2295,8 @@ fcd_status fcd_sync(fcd_handle* h) {
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
     fcd_status st = hip_check(hipStreamSynchronize(h->stream), "stream sync");
     if (st) return st;
-    return hip_check(hipGetLastError(), "async error");
+    st = hip_check(hipGetLastError(), "async error");
+    return st ? st : read_divergence(h);
 }
 
 fcd_status fcd_destroy(fcd_handle* h) {

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(TBX* TY) kb_collide_stream(const BatchInst<T>*
     if (i >= nx || j >= ny) return;
     const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
     collide_stream_nb(static_cast<const T*>(B.dist[cur]), B.dist[1 - cur], tile_nb<T, SX>(t1, lx, ly),
-                      tile_nb<T, SX>(t2, lx, ly), tile_nb<T, SX>(tp, lx, ly), B.P, i, j);
+                      tile_nb<T, SX>(t2, lx, ly), tile_nb<T, SX>(tp, lx, ly), B.P, i, j, B.div);
 }
 
 template <typename T, int TY>

@@ -28,6 +28,7 @@ struct BatchInst {
     int stile0, stiles_x;  // first tile and tiles per row in the fused-sweep (64 x 32) list
     int has_field;         // H0 != 0
     int pad;
+    unsigned long long* div;  // the channel's divergence flag word
 };
 
 // Per-channel work pointers of the batched adjoint (device descriptors).

@@ -39,6 +39,7 @@ struct StepConst {
     T half_mu0;
     T drive, grav_x, grav_y;
     T eps2;                   // eps_n^2
+    T u_limit;                // divergence guard: largest admissible max(|u_x|, |u_y|)
 };
 
 // One level of the potential problem (see fcd_potential.hip).  f == nullptr marks the

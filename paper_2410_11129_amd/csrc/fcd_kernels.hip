@@ -102,7 +102,7 @@ __device__ __forceinline__ Nb9<T> lds_nb(const T (*t)[BX + 2], int lx, int ly) {
 template <typename T>
 __global__ void __launch_bounds__(BX* CY)
     k_collide_stream(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ phi,
-                         const T* __restrict__ psi, StepConst<T> P) {
+                         const T* __restrict__ psi, StepConst<T> P, unsigned long long* __restrict__ div) {
     __shared__ T t1[CY + 2][BX + 2], t2[CY + 2][BX + 2], tp[CY + 2][BX + 2];
     const int i0 = blockIdx.x * BX, j0 = blockIdx.y * CY;
     const int tid = threadIdx.y * BX + threadIdx.x;
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(BX* CY)
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     if (i >= P.nx || j >= P.ny) return;
     const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
-    collide_stream_nb(src, dst, lds_nb<T>(t1, lx, ly), lds_nb<T>(t2, lx, ly), lds_nb<T>(tp, lx, ly), P, i, j);
+    collide_stream_nb(src, dst, lds_nb<T>(t1, lx, ly), lds_nb<T>(t2, lx, ly), lds_nb<T>(tp, lx, ly), P, i, j, div);
 }
 
 // ---------------------------------------------------------------------------------
@@ -309,9 +309,10 @@ void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s) {
 }
 
 template <typename T>
-void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P, hipStream_t s) {
+void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P,
+                           unsigned long long* div, hipStream_t s) {
     hipLaunchKernelGGL(k_collide_stream<T>, dim3((P.nx + BX - 1) / BX, (P.ny + CY - 1) / CY), dim3(BX, CY), 0, s, src,
-                       dst, phi, psi, P);
+                       dst, phi, psi, P, div);
 }
 
 template <typename T>
@@ -351,7 +352,8 @@ void launch_diagnostics(const T* phi, const StepConst<T>& P, double* rows, doubl
     template void launch_init_droplet<T>(T*, int, int, int, double, double, double, double, double, double,     \
                                          hipStream_t);                                                           \
     template void launch_phase<T>(const T*, T*, const StepConst<T>&, hipStream_t);                               \
-    template void launch_collide_stream<T>(const T*, T*, const T*, const T*, const StepConst<T>&, hipStream_t);  \
+    template void launch_collide_stream<T>(const T*, T*, const T*, const T*, const StepConst<T>&,                \
+                                           unsigned long long*, hipStream_t);                                    \
     template void launch_moments<T>(const T*, const T*, const T*, const StepConst<T>&, unsigned, double*,        \
                                     hipStream_t);                                                                \
     template void launch_to_dense<T>(const T*, double*, int, int, int, int, hipStream_t);                        \

@@ -52,7 +52,8 @@ void launch_mg_tail(const MgTail<T>& tl, hipStream_t s);
 template <typename T>
 void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, int mode, hipStream_t s);
 template <typename T>
-void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P, hipStream_t s);
+void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P,
+                           unsigned long long* div, hipStream_t s);
 template <typename T>
 void launch_moments(const T* src, const T* phi, const T* psi, const StepConst<T>& P, unsigned mask, double* out,
                     hipStream_t s);

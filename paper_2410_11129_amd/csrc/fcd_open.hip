@@ -56,7 +56,9 @@ __global__ void __launch_bounds__(OPEN_T)
     if (!edge_node(blockIdx.x * OPEN_T + threadIdx.x, P.nx, P.ny, i, j)) return;
     const NbIdx c = nb_index_open(i, j, P.nx, P.ny, P.pitch);
     const NbIdx x = nb_index(i, j, P.nx, P.ny, P.pitch);
-    collide_stream_nb(src, dst, load_nb(phi, c), load_nb(phi + P.plane, c), load_nb_psi(psi, x, j, P.ny), P, i, j);
+    // the end columns were collided (and checked for divergence) by the main kernel
+    collide_stream_nb(src, dst, load_nb(phi, c), load_nb(phi + P.plane, c), load_nb_psi(psi, x, j, P.ny), P, i, j,
+                      nullptr);
 }
 
 // One thread per row.  Inlet: the first moment of f is set to (u_in(y), 0) and the

@@ -40,13 +40,33 @@ __device__ __forceinline__ void phase_node(const T* __restrict__ dist, T* __rest
     phi[2 * pl + k] = T(1) / (P.ic0 * p1 + P.ic1 * p2 + P.ic2 * p3);
 }
 
+// Divergence guard: a node whose velocity exceeds the limit, or whose p*, phi1 or phi2
+// (sums over every population of f, g1, g2, so any non-finite population shows) is not
+// finite, raises the flag word `div` to the bit pattern of its max(|u_x|, |u_y|) (a
+// quiet NaN for a non-finite node).  Patterns of non-negative doubles order like their
+// values and NaN above them all, so atomicMax keeps the worst node.  The test is one
+// comparison per node; the atomic runs only on a diverged node.
+template <typename T>
+__device__ __forceinline__ void note_divergence(unsigned long long* __restrict__ div, const NodeOut<T>& o,
+                                                T limit) {
+    const T um = fmax(fabs(o.ux), fabs(o.uy));
+    const T chk = o.pstar + (o.phi1 + o.phi2);
+    const bool finite = chk - chk == T(0);  // false for NaN and +-Inf
+    if (!(um <= limit) || !finite) {
+        const double v = finite ? (double)um : __longlong_as_double(0x7ff8000000000000LL);
+        atomicMax(div, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
 // Stencils + forces + MRT collision of f + phase-field collisions of g1, g2 at (i, j),
 // then push streaming with halfway bounce-back at the walls.  The phi1, phi2 and psi'
-// neighbourhoods are given (from global memory or from an LDS tile).
+// neighbourhoods are given (from global memory or from an LDS tile).  div (nullable):
+// the divergence flag word.
 template <typename T>
 __device__ __forceinline__ void collide_stream_nb(const T* __restrict__ src, T* __restrict__ dst,
                                                   const Nb9<T>& a1, const Nb9<T>& a2, const Nb9<T>& ps,
-                                                  const StepConst<T>& P, int i, int j) {
+                                                  const StepConst<T>& P, int i, int j,
+                                                  unsigned long long* __restrict__ div) {
     const long long pl = P.plane;
     const NbIdx x = nb_index(i, j, P.nx, P.ny, P.pitch);
     const long long k = x.c;
@@ -54,6 +74,7 @@ __device__ __forceinline__ void collide_stream_nb(const T* __restrict__ src, T* 
 #pragma unroll
     for (int a = 0; a < 9; ++a) f[a] = ld_state(src + a * pl + k);
     const NodeOut<T> o = node_physics(P, f, a1, a2, ps);
+    if (div) note_divergence(div, o, P.u_limit);
 
     // Destinations of the push: (i + ex, j + ey); a population that would cross a wall
     // returns to its own node in the opposite direction (halfway bounce-back).
@@ -106,7 +127,8 @@ __device__ __forceinline__ void collide_stream_node(const T* __restrict__ src, T
                                                     const T* __restrict__ phi, const T* __restrict__ psi,
                                                     const StepConst<T>& P, int i, int j) {
     const NbIdx x = nb_index(i, j, P.nx, P.ny, P.pitch);
-    collide_stream_nb(src, dst, load_nb(phi, x), load_nb(phi + P.plane, x), load_nb_psi(psi, x, j, P.ny), P, i, j);
+    collide_stream_nb(src, dst, load_nb(phi, x), load_nb(phi + P.plane, x), load_nb_psi(psi, x, j, P.ny), P, i, j,
+                      nullptr);
 }
 
 }  // namespace fcd

@@ -49,10 +49,10 @@ class fcd_params(C.Structure):
         ("eta", C.c_double), ("xi", C.c_double), ("mobility", C.c_double),
         ("H0", C.c_double), ("alpha", C.c_double), ("mu0", C.c_double),
         ("drive_G", C.c_double), ("grav_x", C.c_double), ("grav_y", C.c_double),
-        ("eps_n", C.c_double), ("pot_tol", C.c_double), ("pot_omega", C.c_double),
+        ("eps_n", C.c_double), ("pot_tol", C.c_double), ("pot_omega", C.c_double), ("u_limit", C.c_double),
         ("pot_solver", C.c_int32), ("pot_check_every", C.c_int32), ("pot_max_iters", C.c_int32),
         ("pot_smooth", C.c_int32), ("pot_coarse_sweeps", C.c_int32), ("pot_extrapolate", C.c_int32),
-        ("pot_every", C.c_int32),
+        ("pot_every", C.c_int32), ("div_check_every", C.c_int32),
     ]
 
 

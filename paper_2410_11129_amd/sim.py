@@ -10,7 +10,8 @@ from . import fcd
 
 def make_params(w, solver: int = fcd.FCD_SOLVER_MG, tol: float = 1e-10, omega: float = 0.0,
                 check_every: int = 1, max_iters: int = 100000, smooth: int = 1, coarse_sweeps: int = 2,
-                extrapolate: int = 2, every: int = 1) -> fcd.fcd_params:
+                extrapolate: int = 2, every: int = 1, u_limit: float = 0.0,
+                div_check_every: int = 0) -> fcd.fcd_params:
     """fcd_params from a workload description (any object with the workload fields)."""
     p = fcd.fcd_params()
     for k in range(3):
@@ -22,6 +23,7 @@ def make_params(w, solver: int = fcd.FCD_SOLVER_MG, tol: float = 1e-10, omega: f
     p.pot_check_every, p.pot_max_iters = check_every, max_iters
     p.pot_smooth, p.pot_coarse_sweeps, p.pot_extrapolate = smooth, coarse_sweeps, extrapolate
     p.pot_every = every
+    p.u_limit, p.div_check_every = u_limit, div_check_every  # divergence guard (0: defaults)
     return p
 
 

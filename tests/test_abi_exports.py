@@ -109,3 +109,26 @@ def test_batch_schedule_calls_and_warm_start_order_validated_on_host():
     h = C.c_void_p()
     st = L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h))
     assert st == fcd.FCD_ERR_ARG and "pot_extrapolate" in fcd.fcd_last_error()
+
+
+def test_divergence_guard_settings_validated_on_host():
+    """The divergence guard's limit and check interval are checked before any device work;
+    0 selects the defaults."""
+    L = fcd.lib()
+    lat = fcd.fcd_lattice(200, 50, fcd.FCD_FP64, 256)
+    buf = fcd.fcd_buffers()
+    buf.dist[0], buf.dist[1], buf.phi, buf.psi, buf.scratch = 256, 512, 768, 1024, 1280
+    h = C.c_void_p()
+    p = good_params()
+    assert p.u_limit == 0.0 and p.div_check_every == 0
+    p.u_limit = -0.1
+    assert L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h)) == fcd.FCD_ERR_ARG
+    assert "u_limit" in fcd.fcd_last_error()
+    p = good_params()
+    p.u_limit = float("nan")
+    assert L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h)) == fcd.FCD_ERR_ARG
+    p = good_params()
+    p.div_check_every = -1
+    assert L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h)) == fcd.FCD_ERR_ARG
+    assert "div_check_every" in fcd.fcd_last_error()
+    assert L.fcd_sync(None) == fcd.FCD_ERR_ARG
