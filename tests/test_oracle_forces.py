@@ -143,18 +143,18 @@ def test_phase_sources_of_three_phases_sum_to_zero():
 
 
 def test_normal_regularisation_moves_the_solution_little():
-    """The normal n = grad phi / sqrt(|grad phi|^2 + eps_n^2) with eps_n = 3e-5 (the value
+    """The normal n = grad phi / sqrt(|grad phi|^2 + eps_n^2) with eps_n = 1e-4 (the value
     taken) against eps_n = 1e-7, which is within 1e-9 of the unregularised limit here,
     over 1000 steps of the 200 x 50 channel.  theta n differs only where |grad phi| is
     comparable to eps_n, i.e. in the far tails of the tanh profiles where phi itself is
     ~eps_n; D, a second moment, weights those tails by the squared distance, so it is the
-    most sensitive output (measured: 3.6e-4 on phi and D, 1.6 % of D_o and 2.7 % of D_i;
-    with eps_n = 1e-4 1.3e-3 on phi and 1.0e-3 on D).  The potential is solved every 8
-    steps in both runs to keep the CPU time down; the comparison is between two runs of
-    the same coupling."""
+    most sensitive output.  Measured: 1.3e-3 on phi and 1.0e-3 on D (4.5 % of D_o, 7.7 %
+    of D_i): the bias that buys the FP32 path its robustness at the extrema of phi.  The
+    potential is solved every 8 steps in both runs to keep the CPU time down; the
+    comparison is between two runs of the same coupling."""
     w = single_channel_small(steps=1000)
     out = []
-    for eps in (3e-5, 1e-7):
+    for eps in (1e-4, 1e-7):
         s = OracleSim(w.replace(eps_n=eps), OracleSolver.direct(every=8))
         s.init_droplet()
         assert s.step(w.steps) == 0
@@ -162,8 +162,8 @@ def test_normal_regularisation_moves_the_solution_little():
         out.append((m["phi1"], m["phi2"], s.diagnostics()))
     dphi = max(np.abs(out[0][0] - out[1][0]).max(), np.abs(out[0][1] - out[1][1]).max())
     dD = np.abs(out[0][2][:2] - out[1][2][:2]).max()
-    assert dphi < 5e-4, dphi
-    assert dD < 5e-4 and dD < 0.03 * np.abs(out[1][2][:2]).min(), dD
+    assert dphi < 2e-3, dphi
+    assert dD < 1.5e-3 and dD < 0.1 * np.abs(out[1][2][:2]).min(), dD
 
 
 def test_fp32_sized_rounding_moves_overshoot_nodes_not_the_mean():
