@@ -386,71 +386,135 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
     }
 }
 
-// Residual restriction by tiles: a block loads a 64 x 16 fine tile of the smoothed
-// iterate and mu with halo, forms the residual f - L u of its nodes in LDS and writes
-// the 32 x 8 coarse right-hand sides (average of the four children) and a zero coarse
-// correction.  Requires nx = 2 nxc and ny = 2 nyc.
-template <typename T, typename G, int MODE, typename TC>
-__global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
-    constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT;
-    __shared__ T su[HY][HX];
-    __shared__ T sm[HY][HX];
-    __shared__ T sr[SY][SX];
-    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * SY;
-    const int tid = threadIdx.x;
-    T uv[G::HPER], mv[G::HPER], fv[G::FPER];
-    load_tile<T, G>(F, F.u, i0, j0, uv, mv);
-    if (MODE != 1) {
+// Residual restriction.  The coarse right-hand side at coarse node (I, J) is the
+// transpose of the bilinear prolongation applied to the fine residual: weights
+// (1, 3, 3, 1)/8 along each axis over fine columns 2I-1 .. 2I+2 (periodic) and rows
+// 2J-1 .. 2J+2 (rows beyond the walls carry no residual).  Against the four-child
+// average this weighting of order two raises the V-cycle's contraction per cycle from
+// about 0.2 to about 0.1 on a uniform mu and cuts the cycles a time step's warm-started
+// solve needs by a fifth (measured on a CPU model of this multigrid).  A block therefore
+// forms the residuals of its fine tile and of the one-node ring around it, staging the
+// iterate and mu with a two-node halo.
+template <typename G>
+struct RestrictGeom {
+    static constexpr int FX = G::SX + 4, FY = G::SY + 4;  // staged: tile with a two-node halo
+    static constexpr int RX = G::SX + 2, RY = G::SY + 2;  // residuals: tile and its ring
+    static constexpr int FN = FX * FY, RN = RX * RY;
+    static constexpr int FPER = (FN + G::NT - 1) / G::NT;
+    static constexpr int RPER = (RN + G::NT - 1) / G::NT;
+};
+
+// Loads of the staged iterate / mu (origin (i0 - 2, j0 - 2)) and of the right-hand side at
+// the residual nodes (origin (i0 - 1, j0 - 1)), all issued before any LDS store.
+template <typename T, typename G, int MODE>
+__device__ __forceinline__ void restrict_loads(const PotLevel<T>& F, int i0, int j0, T (&uv)[RestrictGeom<G>::FPER],
+                                               T (&mv)[RestrictGeom<G>::FPER], T (&fv)[RestrictGeom<G>::RPER]) {
+    using R = RestrictGeom<G>;
 #pragma unroll
-        for (int r = 0; r < G::FPER; ++r) {
-            const int q = tid + r * NT;
-            const int ly = q / SX, lx = q - ly * SX;
-            const int i = i0 + lx, j = j0 + ly;
-            fv[r] = (i < F.nx && j < F.ny) ? F.f[(long long)j * F.pitch + i] : T(0);
+    for (int r = 0; r < R::FPER; ++r) {
+        const int q = threadIdx.x + r * G::NT;
+        if (q < R::FN) {
+            const int ly = q / R::FX, lx = q - ly * R::FX;
+            const long long k = (long long)clamp_row(j0 + ly - 2, F.ny) * F.pitch + wrap_col(i0 + lx - 2, F.nx);
+            uv[r] = F.u[k];
+            mv[r] = F.mu[k];
         }
     }
 #pragma unroll
-    for (int r = 0; r < G::HPER; ++r) {
+    for (int r = 0; r < R::RPER; ++r) {
+        const int q = threadIdx.x + r * G::NT;
+        fv[r] = T(0);
+        if (MODE != 1 && q < R::RN) {
+            const int ly = q / R::RX, lx = q - ly * R::RX;
+            fv[r] = F.f[(long long)clamp_row(j0 + ly - 1, F.ny) * F.pitch + wrap_col(i0 + lx - 1, F.nx)];
+        }
+    }
+}
+
+// Residuals f - L u of the tile and its ring into sr (zero on rows beyond the walls).
+template <typename T, typename G, int MODE>
+__device__ __forceinline__ void restrict_residuals(const PotLevel<T>& F, int i0, int j0,
+                                                   const T (*fu)[RestrictGeom<G>::FX],
+                                                   const T (*fm)[RestrictGeom<G>::FX],
+                                                   const T (&fv)[RestrictGeom<G>::RPER],
+                                                   T (*sr)[RestrictGeom<G>::RX]) {
+    using R = RestrictGeom<G>;
+    (void)i0;
+#pragma unroll
+    for (int r = 0; r < R::RPER; ++r) {
+        const int q = threadIdx.x + r * G::NT;
+        if (q < R::RN) {
+            const int ly = q / R::RX, lx = q - ly * R::RX;
+            const int j = j0 + ly - 1;
+            T v = T(0);
+            if (j >= 0 && j < F.ny) {
+                const MgEval<T> e =
+                    tile_eval<T, R::FX>(fu, fm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F, fv[r], MODE == 1);
+                v = e.rhs - (e.acc - e.C * fu[ly + 1][lx + 1]);
+            }
+            sr[ly][lx] = v;
+        }
+    }
+}
+
+// The (1, 3, 3, 1)/8 x (1, 3, 3, 1)/8 weighting of the residuals around coarse node
+// (cx, cy) of the tile (sr column / row 0 is the fine column / row before the tile).
+template <typename T, int RX>
+__device__ __forceinline__ T restrict16(const T (*sr)[RX], int cx, int cy) {
+    const T a = T(1) / T(8), b = T(3) / T(8);
+    T rows[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const T* r = sr[2 * cy + q] + 2 * cx;
+        rows[q] = (a * r[0] + b * r[1]) + (b * r[2] + a * r[3]);
+    }
+    return (a * rows[0] + b * rows[1]) + (b * rows[2] + a * rows[3]);
+}
+
+// Residual restriction by tiles: a block stages its fine tile (SX x SY) with a two-node
+// halo, forms the residuals of the tile and its ring and writes the (SX/2) x (SY/2)
+// coarse right-hand sides and a zero coarse correction.  Requires nx = 2 nxc and
+// ny = 2 nyc.
+template <typename T, typename G, int MODE, typename TC>
+__global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
+    using R = RestrictGeom<G>;
+    constexpr int SX = G::SX, NT = G::NT;
+    __shared__ T fu[R::FY][R::FX];
+    __shared__ T fm[R::FY][R::FX];
+    __shared__ T sr[R::RY][R::RX];
+    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * G::SY;
+    const int tid = threadIdx.x;
+    T uv[R::FPER], mv[R::FPER], fv[R::RPER];
+    restrict_loads<T, G, MODE>(F, i0, j0, uv, mv, fv);
+#pragma unroll
+    for (int r = 0; r < R::FPER; ++r) {
         const int q = tid + r * NT;
-        if (q < G::HN) {
-            su[q / HX][q % HX] = uv[r];
-            sm[q / HX][q % HX] = mv[r];
+        if (q < R::FN) {
+            fu[q / R::FX][q % R::FX] = uv[r];
+            fm[q / R::FX][q % R::FX] = mv[r];
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < G::FPER; ++r) {
-        const int q = tid + r * NT;
-        const int ly = q / SX, lx = q - ly * SX;
-        const int i = i0 + lx, j = j0 + ly;
-        T v = T(0);
-        if (i < F.nx && j < F.ny) {
-            const MgEval<T> e = tile_eval<T, HX>(su, sm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F,
-                                                 MODE == 1 ? T(0) : fv[r], MODE == 1);
-            v = e.rhs - (e.acc - e.C * su[ly + 1][lx + 1]);
-        }
-        sr[ly][lx] = v;
-    }
+    restrict_residuals<T, G, MODE>(F, i0, j0, fu, fm, fv, sr);
     __syncthreads();
     const int cx = tid % (SX / 2), cy = tid / (SX / 2);
     const int I = (i0 >> 1) + cx, J = (j0 >> 1) + cy;
     if (I < Cl.nx && J < Cl.ny) {
         const long long k = (long long)J * Cl.pitch + I;
-        Cl.f[k] = TC(T(0.25) * ((sr[2 * cy][2 * cx] + sr[2 * cy][2 * cx + 1]) +
-                                (sr[2 * cy + 1][2 * cx] + sr[2 * cy + 1][2 * cx + 1])));
+        Cl.f[k] = TC(restrict16<T, R::RX>(sr, cx, cy));
         Cl.u[k] = TC(0);
     }
 }
 
 // Residual restriction fused with the first pre-smoothing of the coarse level below it.
-// One block owns a 32 x 8 coarse tile: it loads the matching 64 x 16 tile of the
-// smoothed fine iterate and of the fine mu with a one-node halo, forms the fine
-// residuals (FMODE: the fine level's right-hand side, as the smoother's MODE), writes
-// their four-child averages as the coarse right-hand side (to C.f and to LDS) and runs
-// `inner` tile sweeps from a zero correction (the whole coarse level starts at zero, so
-// the tile's halo is zero as well), writing the result to uout.  Same arithmetic as
-// k_mg_restrict_tile followed by k_mg_smooth_tile, one launch fewer.  Requires
-// F.nx = 2 C.nx and F.ny = 2 C.ny.
+// One block owns a 32 x 8 coarse tile: it stages the matching 64 x 16 tile of the
+// smoothed fine iterate and of the fine mu with a two-node halo, forms the fine
+// residuals of the tile and its ring (FMODE: the fine level's right-hand side, as the
+// smoother's MODE), writes their weighted sums as the coarse right-hand side (to C.f and
+// to LDS) and runs `inner` tile sweeps from a zero correction (the whole coarse level
+// starts at zero, so the tile's halo is zero as well), writing the result to uout.  Same
+// arithmetic as k_mg_restrict_tile followed by k_mg_smooth_tile, one launch fewer.
+// Requires F.nx = 2 C.nx and F.ny = 2 C.ny.
 template <typename T, int FMODE, typename TC>
 __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<TC> C,
                                                                      TC* __restrict__ uout, int inner) {
@@ -458,10 +522,12 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
     // together); coarse smoothing by the first 64, one coarse node per colour each
     using G = CoarseTile;
     using FG = FineTile;
+    using R = RestrictGeom<FG>;
     constexpr int NT = FG::NT, SX = G::SX, SY = G::SY, HX = G::HX;
     constexpr int CPER = (G::HN + NT - 1) / NT;
-    __shared__ T fu[FG::HY][FG::HX];
-    __shared__ T fm[FG::HY][FG::HX];
+    __shared__ T fu[R::FY][R::FX];
+    __shared__ T fm[R::FY][R::FX];
+    __shared__ T sr[R::RY][R::RX];
     __shared__ TC su[G::HY][G::HX];
     __shared__ TC sm[G::HY][G::HX];
     __shared__ TC sf[SY][SX];
@@ -469,14 +535,9 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
     const int i0 = 2 * I0, j0 = 2 * J0;                    // fine tile origin
     const int tid = threadIdx.x;
     const int cy = tid / SX, cx = tid - cy * SX;  // this thread's coarse node
-    T uv[FG::HPER], mv[FG::HPER], fv[4];
+    T uv[R::FPER], mv[R::FPER], fv[R::RPER];
     TC cm[CPER];
-    load_tile<T, FG>(F, F.u, i0, j0, uv, mv);
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {  // fine right-hand sides of the node's four children
-        const int i = i0 + 2 * cx + (d & 1), j = j0 + 2 * cy + (d >> 1);
-        fv[d] = (FMODE != 1 && i < F.nx && j < F.ny) ? F.f[(long long)j * F.pitch + i] : T(0);
-    }
+    restrict_loads<T, FG, FMODE>(F, i0, j0, uv, mv, fv);
 #pragma unroll
     for (int r = 0; r < CPER; ++r) {
         const int q = tid + r * NT;
@@ -486,11 +547,11 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
         }
     }
 #pragma unroll
-    for (int r = 0; r < FG::HPER; ++r) {
+    for (int r = 0; r < R::FPER; ++r) {
         const int q = tid + r * NT;
-        if (q < FG::HN) {
-            fu[q / FG::HX][q % FG::HX] = uv[r];
-            fm[q / FG::HX][q % FG::HX] = mv[r];
+        if (q < R::FN) {
+            fu[q / R::FX][q % R::FX] = uv[r];
+            fm[q / R::FX][q % R::FX] = mv[r];
         }
     }
 #pragma unroll
@@ -502,22 +563,10 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
         }
     }
     __syncthreads();
-    // fine residuals of the 2 x 2 children of the thread's coarse node
+    restrict_residuals<T, FG, FMODE>(F, i0, j0, fu, fm, fv, sr);
+    __syncthreads();
     {
-        T r[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const int lx = 2 * cx + (d & 1), ly = 2 * cy + (d >> 1);
-            const int i = i0 + lx, j = j0 + ly;
-            T v = T(0);
-            if (i < F.nx && j < F.ny) {
-                const MgEval<T> e =
-                    tile_eval<T, FG::HX>(fu, fm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F, fv[d], FMODE == 1);
-                v = e.rhs - (e.acc - e.C * fu[ly + 1][lx + 1]);
-            }
-            r[d] = v;
-        }
-        const TC fc = TC(T(0.25) * ((r[0] + r[1]) + (r[2] + r[3])));
+        const TC fc = TC(restrict16<T, R::RX>(sr, cx, cy));
         sf[cy][cx] = fc;
         const int I = I0 + cx, J = J0 + cy;
         if (I < C.nx && J < C.ny) C.f[(long long)J * C.pitch + I] = fc;
@@ -762,21 +811,27 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
     for (int k = 0; k + 1 < tl.n; ++k) {
         const TailLevel<T> F = tail_view(tl, dv, base, k), Cc = tail_view(tl, dv, base, k + 1);
         tail_jacobi(F, sw);
-        // fine residuals f - L u into the (free) ping-pong array, then their four-child
-        // sums in the fixed order (0,0), (1,0), (0,1), (1,1)
+        // fine residuals f - L u into the (free) ping-pong array, then their
+        // (1, 3, 3, 1)/8 x (1, 3, 3, 1)/8 weighted sums (as the tile restrictions)
         const int nf = F.nx * F.ny;
         for (int t = tid; t < nf; t += TAIL_T) F.alt[t] = F.f[t] - (tail_acc(F, F.u, t) - F.d[t] * F.u[t]);
         __syncthreads();
         const int n = Cc.nx * Cc.ny;
+        const T wa = T(1) / T(8), wb = T(3) / T(8);
         for (int t = tid; t < n; t += TAIL_T) {
             const int J = tail_div(t, Cc.inv), I = t - J * Cc.nx;
-            const T* r0 = F.alt + (2 * J) * F.nx + 2 * I;
-            T s = T(0);
-            s += r0[0];
-            s += r0[1];
-            s += r0[F.nx];
-            s += r0[F.nx + 1];
-            Cc.f[t] = T(0.25) * s;
+            const int im = I == 0 ? F.nx - 1 : 2 * I - 1, i3 = 2 * I + 2 == F.nx ? 0 : 2 * I + 2;
+            T rows[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = 2 * J - 1 + q;
+                rows[q] = T(0);
+                if (j >= 0 && j < F.ny) {
+                    const T* r = F.alt + j * F.nx;
+                    rows[q] = (wa * r[im] + wb * r[2 * I]) + (wb * r[2 * I + 1] + wa * r[i3]);
+                }
+            }
+            Cc.f[t] = (wa * rows[0] + wb * rows[1]) + (wb * rows[2] + wa * rows[3]);
             Cc.u[t] = T(0);
         }
         __syncthreads();
