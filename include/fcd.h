@@ -218,6 +218,20 @@ fcd_status fcd_extent_deformation(fcd_handle* h, double out[6]);
  * across the periodic boundary)}; the means are -1 where their weights vanish.  Sync. */
 fcd_status fcd_breakup_probe(fcd_handle* h, double out[4]);
 
+/* Breakup tracking and the breakup numbers of Sec. 2.5 / Fig. 3.  Call once after the
+ * initial state is set (that call fixes the reference), then every few steps, at most
+ * half a channel period of droplet travel apart.  Each call runs fcd_breakup_probe and
+ * follows the outer droplet's circular-mean x across the periodic boundary.  out =
+ * {contact nodes (0: no breakup yet), t_b* = t_b u / (2 r_shell) (Eq. 38; t_b the steps
+ * since the initial state, u the centreline inflow of Eq. 37 in the open channel or the
+ * Poiseuille peak the drive sustains in the periodic one; -1 unless the state came from
+ * fcd_init_compound_droplet), L_b* = x_b / ny with x_b the contact point's distance along
+ * the channel from x = 0 (the inlet of the open channel; in the periodic channel followed
+ * across the boundary), y_b* = |y_b - (ny - 1)/2| / ny, x_b, y_b}; entries 1..5 are -1
+ * while there is no contact.  Replacing the state (fcd_init_*, fcd_write_state) resets the
+ * tracking.  Sync. */
+fcd_status fcd_breakup_track(fcd_handle* h, double out[6]);
+
 /* Counters since creation: out = {steps, potential iterations (SOR sweeps or V-cycles),
  * last residual}.  Host only. */
 fcd_status fcd_stats(fcd_handle* h, double out[3]);
@@ -255,14 +269,16 @@ const char* fcd_last_error(void);
 /* ---------------------------------------------------------------------------------
  * Adjoint (reverse-mode gradient) of J = dJ_dD[0] D_o + dJ_dD[1] D_i after nsteps steps,
  * where D_o, D_i are the deformations of fcd_deformation, with respect to
- * p = (H0, alpha, drive_G, sigma12, sigma13, sigma23).  Hand-written reverse of the
- * whole coupled step: transposed streaming, node collisions and forces, stencils, the
- * potential solve (adjoint equation L lambda = psi'-bar, L symmetric, solved by the
+ * p = (H0, alpha, u_ref, sigma12, sigma13, sigma23), u_ref the peak of the Poiseuille
+ * profile the drive sustains: drive_G = 8 rho_3 nu_3 u_ref / ny^2 with nu_3 = tau_3 / 3
+ * (the pressure-driven flow of Sec. 2.5 as a uniform body force).  Hand-written reverse
+ * of the whole coupled step: transposed streaming, node collisions and forces, stencils,
+ * the potential solve (adjoint equation L lambda = psi'-bar, L symmetric, solved by the
  * configured solver to pot_tol relative to max |psi'-bar|) and the mixing rules.
  * Checkpointing: the forward keeps the state every ckpt_every steps in `work`; the
  * backward recomputes each segment (keeping its states) and runs the adjoint steps in
  * reverse.  When the forward starts from fcd_init_compound_droplet with no step since,
- * the drive_G gradient includes the initial Poiseuille velocity's dependence on it.
+ * the u_ref gradient includes the initial Poiseuille velocity's dependence on it.
  * --------------------------------------------------------------------------------- */
 
 /* Device bytes of `work` for fcd_adjoint_forward / _backward.  Host only. */
@@ -274,7 +290,7 @@ size_t fcd_adjoint_bytes(const fcd_lattice* lat, int32_t nsteps, int32_t ckpt_ev
 fcd_status fcd_adjoint_forward(fcd_handle* h, int32_t nsteps, int32_t ckpt_every, void* work, double D_out[2]);
 
 /* Gradient of J for the run of the last fcd_adjoint_forward (same `work`, untouched
- * since): grad = dJ/d(H0, alpha, drive_G, sigma12, sigma13, sigma23).  Sync.  Leaves the
+ * since): grad = dJ/d(H0, alpha, u_ref, sigma12, sigma13, sigma23).  Sync.  Leaves the
  * handle on the forward's final state. */
 fcd_status fcd_adjoint_backward(fcd_handle* h, const double dJ_dD[2], double grad[6]);
 
@@ -369,7 +385,7 @@ fcd_status fcd_batch_tune_omega(fcd_batch* b, int32_t steps, int32_t ncand, cons
  * fcd_batch_adjoint_forward: nsteps steps from the current state, checkpoints every
  * ckpt_every steps in `work` (caller-owned, 256-byte aligned); D_out[2k..2k+1] =
  * {D_o, D_i} of channel k after the run.  Sync.
- * fcd_batch_adjoint_backward: grad[6k..6k+5] = dJ_k/d(H0, alpha, drive_G, sigma12,
+ * fcd_batch_adjoint_backward: grad[6k..6k+5] = dJ_k/d(H0, alpha, u_ref, sigma12,
  * sigma13, sigma23) of channel k for J_k = dJ_dD[2k] D_o + dJ_dD[2k+1] D_i.  Sync; leaves
  * the batch on the forward's final state. */
 size_t fcd_batch_adjoint_bytes(fcd_batch* b, int32_t nsteps, int32_t ckpt_every);

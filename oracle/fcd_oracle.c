@@ -25,6 +25,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------- */
 /* Lattice (Eq. 17 weights, Eq. 20 velocities; delta x = delta t = 1, c = 1). */
@@ -274,6 +277,7 @@ void orc_chem_potential(const orc_params* P, const double ph[3], const double la
 /* phi_i = sum_alpha g^i_alpha (Eq. 32). */
 static void phase_from_g(int nx, int ny, const double* g, double* phi) {
     size_t n = (size_t)nx * ny;
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
         double s = 0.0;
         for (int a = 0; a < NQ; ++a) s += g[a * n + k];
@@ -502,6 +506,7 @@ static inline double coef(const double* mur, int nx, int ny, int i, int j, int a
 static double potential_residual(int nx, int ny, const double* mur, double H0, double alpha,
                                  const double* psi, const double* lo, const double* hi, double* r) {
     double hx = cos(alpha), hy = sin(alpha), mx = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : mx)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double c0 = psi[IDX(i, j, nx)], acc = 0.0;
@@ -611,6 +616,7 @@ static int potential_sor(int nx, int ny, const double* mur, double H0, double al
     double rmax = potential_residual(nx, ny, mur, H0, alpha, psi, NULL, NULL, NULL);
     while (rmax > thr && sw < S->max_sweeps) {
         for (int colour = 0; colour < 4; ++colour)
+#pragma omp parallel for schedule(static)
             for (int j = colour / 2; j < ny; j += 2)
                 for (int i = colour % 2; i < nx; i += 2) {
                     double C = 0.0, acc = 0.0;
@@ -828,6 +834,7 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t s
         goto done;
     }
     if (total_sweeps) *total_sweeps = 0;
+    if (!minv_ready) build_minv(); /* before any threads share it */
     for (int step = 0; step < nsteps; ++step) {
         /* Order parameters (Eq. 32, 24) and mu_r (Eq. 8). */
         phase_from_g(nx, ny, g1, phi1);
@@ -844,7 +851,9 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t s
             if (last_resid) *last_resid = res;
             if (rc != 0) goto done;
         }
-        /* Stencils, forces and both collisions at every node. */
+        /* Stencils, forces and both collisions at every node (rows independent: with
+         * OpenMP they are shared out among threads, the arithmetic per node unchanged). */
+#pragma omp parallel for schedule(static)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t k = IDX(i, j, nx);
@@ -877,6 +886,7 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t s
         /* Pull streaming; halfway bounce-back when the source lies beyond a wall
          * (reading: the paper says bounce-back without naming the variant).  In the open
          * channel a source beyond the inlet or outlet is unknown: set just below. */
+#pragma omp parallel for schedule(static)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t k = IDX(i, j, nx);
@@ -1211,4 +1221,13 @@ void orc_stencils(int32_t nx, int32_t ny, const double* a, double* gx, double* g
 /* Exported: mu_r plane from phi planes (Eq. 8). */
 void orc_mu_r(const orc_params* P, const double* phi1, const double* phi2, double* mur) {
     mu_r_from_phi(P, phi1, phi2, mur);
+}
+
+/* Threads the row loops use (1 without OpenMP): reported beside CPU timings. */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,37 +1,34 @@
 """Gradients of the droplet deformation through the library's hand-written adjoint.
 
-The deformation D of the shell (D_o) and of the core (D_i), Eq. 39, taken from the
-second moments of the order parameters, after `nsteps` coupled steps from the compound
-droplet initial state, is differentiated with respect to
+The deformation D of the shell (D_o) and of the core (D_i), the second-moment stand-in
+for the deformation index of Eq. 42 taken from the order parameters, after `nsteps`
+coupled steps from the compound droplet initial state, is differentiated with respect to
 
     theta = (H0, alpha, u_ref, sigma12, sigma13, sigma23)
 
-(field strength and angle, Eq. 41 and Sec. 3; peak inlet velocity of the Poiseuille
-drive; the pairwise surface tensions of Eq. 27).  The forward keeps a checkpoint every
-`ckpt_every` steps on the device; the backward recomputes one segment at a time and runs
-the adjoint steps in reverse (all inside the HIP library).
+(field strength and angle, Eq. 41 and Sec. 3; peak velocity of the Poiseuille drive; the
+pairwise surface tensions of Eq. 27).  The forward keeps a checkpoint every `ckpt_every`
+steps on the device; the backward recomputes one segment at a time and runs the adjoint
+steps in reverse (all inside the HIP library, which also returns the u_ref component).
 """
 from __future__ import annotations
 
 import torch
 
+from fcd_inputs import channel_drive
+
 from . import fcd
 from .sim import Batch, Channel
 
-CS2 = 1.0 / 3.0
 PARAM_NAMES = ("H0", "alpha", "u_ref", "sigma12", "sigma13", "sigma23")
 
 
-def drive_from_u_ref(u_ref: float, rho3: float, tau3: float, ny: int) -> float:
-    """Body force of a Poiseuille profile peaking at u_ref between the halfway walls."""
-    return 8.0 * rho3 * CS2 * tau3 * u_ref / float(ny * ny)
-
-
 def workload_at(w, theta):
-    """The workload `w` with the six differentiated parameters replaced by `theta`."""
+    """The workload `w` with the six differentiated parameters replaced by `theta` (the
+    drive is the one whose Poiseuille peak is u_ref)."""
     H0, alpha, u_ref, s12, s13, s23 = (float(v) for v in theta)
     return w.replace(H0=H0, alpha=alpha, u_ref=u_ref, sigma12=s12, sigma13=s13, sigma23=s23,
-                     drive_G=drive_from_u_ref(u_ref, w.rho[2], w.tau[2], w.ny))
+                     drive_G=channel_drive(u_ref, w.rho[2], w.tau[2], w.ny))
 
 
 def theta_of(w):
@@ -64,10 +61,7 @@ class AdjointRun:
         """dJ/dtheta for J = dJ_dD[0] D_o + dJ_dD[1] D_i of the last forward."""
         if self.D is None:
             raise RuntimeError("forward has not run")
-        w = self.ch.w
-        g = fcd.fcd_adjoint_backward(self.ch.h, [float(dJ_dD[0]), float(dJ_dD[1])])
-        dG_du = drive_from_u_ref(1.0, w.rho[2], w.tau[2], w.ny)
-        return [g[0], g[1], g[2] * dG_du, g[3], g[4], g[5]]
+        return list(fcd.fcd_adjoint_backward(self.ch.h, [float(dJ_dD[0]), float(dJ_dD[1])]))
 
 
 class DeformationFunction(torch.autograd.Function):
@@ -115,8 +109,4 @@ class BatchAdjointRun:
         if self.D is None:
             raise RuntimeError("forward has not run")
         g = fcd.fcd_batch_adjoint_backward(self.bt.h, [(float(a), float(b)) for a, b in dJ_dD])
-        out = []
-        for gk, w in zip(g, self.bt.ws):
-            dG_du = drive_from_u_ref(1.0, w.rho[2], w.tau[2], w.ny)
-            out.append([gk[0], gk[1], gk[2] * dG_du, gk[3], gk[4], gk[5]])
-        return out
+        return [list(gk) for gk in g]

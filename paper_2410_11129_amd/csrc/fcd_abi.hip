@@ -48,6 +48,11 @@ double sor_omega_opt(int ny) { return 2.0 / (1.0 + std::sin(3.141592653589793238
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// The periodic channel's drive is the body force whose Poiseuille profile between the
+// halfway walls peaks at u_ref: drive_G = 8 rho_3 nu_3 u_ref / ny^2, nu_3 = c_s^2 tau_3
+// (the pressure-driven flow of Sec. 2.5 as a body force); d drive_G / d u_ref.
+double drive_per_u_ref(const fcd_params& p, int ny) { return 8.0 * p.rho[2] * (p.tau[2] / 3.0) / ((double)ny * ny); }
+
 // Divergence guard settings (0 selects the default).
 double u_limit_of(const fcd_params& p) { return p.u_limit > 0.0 ? p.u_limit : 0.5; }
 int div_every_of(const fcd_params& p) { return p.div_check_every > 0 ? p.div_check_every : 64; }
@@ -237,6 +242,12 @@ struct fcd_handle {
     int open_x;      // open channel: Eq. 37 inlet at x = 0, convective outlet at x = nx - 1
     double u_in;     // u_avg of Eq. 37 (centreline value of the inlet profile)
     double u_out;    // convective velocity of the outlet: the section mean of the inlet profile
+    // breakup tracking (fcd_breakup_track): the outer droplet's x followed across the periodic
+    // boundary since the last state change
+    int track_on;
+    double track_x_prev, track_x_run;
+    long long steps_at_init;  // h->steps when the state was last replaced
+    double r_shell;           // shell radius of fcd_init_compound_droplet (0: other initial state)
     // checkpointed adjoint: set by fcd_adjoint_forward, used by fcd_adjoint_backward
     char* adj_work;
     int adj_nsteps, adj_every, adj_from_init;
@@ -1803,7 +1814,7 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
     const double hx = a[0] + a[13], hy = a[1] + a[14];
     grad[0] = hx * ca + hy * sa;
     grad[1] = p.H0 * (-hx * sa + hy * ca);
-    grad[2] = a[2] + a[15];
+    grad[2] = (a[2] + a[15]) * drive_per_u_ref(p, h->lat.ny);
     const double g[3] = {p.sigma12 + p.sigma13 - p.sigma23, p.sigma12 + p.sigma23 - p.sigma13,
                          p.sigma13 + p.sigma23 - p.sigma12};
     const double gT = 3.0 / (1.0 / g[0] + 1.0 / g[1] + 1.0 / g[2]);
@@ -2059,7 +2070,7 @@ fcd_status batch_adj_backward_impl(fcd_batch* b, const double* dJ, double* grad)
         const double hx = ak[0] + ak[13], hy = ak[1] + ak[14];
         g[0] = hx * ca + hy * sa;
         g[1] = p.H0 * (-hx * sa + hy * ca);
-        g[2] = ak[2] + ak[15];
+        g[2] = (ak[2] + ak[15]) * drive_per_u_ref(p, b->lat[k].ny);
         const double gm[3] = {p.sigma12 + p.sigma13 - p.sigma23, p.sigma12 + p.sigma23 - p.sigma13,
                               p.sigma13 + p.sigma23 - p.sigma12};
         const double gT = 3.0 / (1.0 / gm[0] + 1.0 / gm[1] + 1.0 / gm[2]);
@@ -2118,6 +2129,10 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     h->init_fresh = 0;
     h->open_x = 0;
     h->u_in = h->u_out = 0.0;
+    h->track_on = 0;
+    h->track_x_prev = h->track_x_run = 0.0;
+    h->steps_at_init = 0;
+    h->r_shell = 0.0;
     h->adj_work = nullptr;
     h->adj_nsteps = h->adj_every = h->adj_from_init = 0;
     h->adj_final_iters = h->adj_final_hist = 0;
@@ -2175,6 +2190,9 @@ fcd_status fcd_init_compound_droplet(fcd_handle* h, double xc, double yc, double
     h->qs = 0;
     h->last_iters = 0;
     h->init_fresh = 1;
+    h->track_on = 0;
+    h->steps_at_init = h->steps;
+    h->r_shell = r_shell;
     if (!(r_core >= 0.0) || !(r_shell >= r_core)) return fail(FCD_ERR_ARG, "need 0 <= r_core <= r_shell");
     return FCD_DISPATCH(h, init_droplet_impl)(h, xc, yc, r_core, r_shell);
 }
@@ -2186,6 +2204,9 @@ fcd_status fcd_init_fields(fcd_handle* h, const double* phi1, const double* phi2
     h->hist = 0;
     h->qs = 0;
     h->last_iters = 0;
+    h->track_on = 0;
+    h->steps_at_init = h->steps;
+    h->r_shell = 0.0;
     if (!phi1 || !phi2 || !ux || !uy) return fail(FCD_ERR_ARG, "a field pointer is null");
     return FCD_DISPATCH(h, init_fields_impl)(h, phi1, phi2, ux, uy, pstar);
 }
@@ -2226,6 +2247,8 @@ fcd_status fcd_write_state(fcd_handle* h, const double* in) {
     h->hist = 0;
     h->qs = 0;
     h->last_iters = 0;
+    h->track_on = 0;
+    h->steps_at_init = h->steps;
     fcd_status st = FCD_DISPATCH(h, copy_in_impl)(h, h->buf.dist[h->cur], 27, in);
     return st ? st : clear_divergence(h);
 }
@@ -2259,6 +2282,43 @@ fcd_status fcd_breakup_probe(fcd_handle* h, double out[4]) {
     if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
     fcd_status st = FCD_DISPATCH(h, breakup_impl)(h, out);
     return st ? st : read_divergence(h);
+}
+
+fcd_status fcd_breakup_track(fcd_handle* h, double out[6]) {
+    if (!h || !out) return fail(FCD_ERR_ARG, "null argument");
+    double v[4];
+    fcd_status st = FCD_DISPATCH(h, breakup_impl)(h, v);
+    if (!st) st = read_divergence(h);
+    if (st) return st;
+    const double nx = h->lat.nx, ny = h->lat.ny;
+    // shortest signed displacement along the periodic channel
+    auto wrapped = [&](double d) { return d - nx * std::floor(d / nx + 0.5); };
+    const double xo = v[3];
+    if (!h->track_on) {
+        h->track_on = 1;
+        h->track_x_prev = h->track_x_run = xo;
+    } else if (!h->open_x) {
+        h->track_x_run += wrapped(xo - h->track_x_prev);
+        h->track_x_prev = xo;
+    }
+    out[0] = v[0];
+    for (int k = 1; k < 6; ++k) out[k] = -1.0;
+    if (v[0] > 0.0) {
+        // the contact point, unwrapped through the outer droplet's position (periodic), or
+        // the distance from the inlet (open channel: no seam is crossed)
+        const double x_b = h->open_x ? v[2] : h->track_x_run + wrapped(v[2] - xo);
+        // Eq. 38 with u_avg the velocity scale of the flow: the centreline inflow of Eq. 37
+        // (open channel), or the Poiseuille peak the drive sustains (periodic channel)
+        const double u_scale =
+            h->open_x ? h->u_in : h->prm.drive_G / drive_per_u_ref(h->prm, h->lat.ny);
+        const double t_b = (double)(h->steps - h->steps_at_init);
+        out[1] = h->r_shell > 0.0 ? t_b * u_scale / (2.0 * h->r_shell) : -1.0;
+        out[2] = x_b / ny;
+        out[3] = std::fabs(v[1] - (ny - 1) / 2.0) / ny;
+        out[4] = x_b;
+        out[5] = v[1];
+    }
+    return FCD_OK;
 }
 
 fcd_status fcd_stats(fcd_handle* h, double out[3]) {

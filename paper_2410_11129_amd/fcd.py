@@ -27,7 +27,8 @@ MOMENT_NAMES = ("pstar", "ux", "uy", "phi1", "phi2", "phi3", "rho", "psi", "Hx",
 EXPORTS = (
     "fcd_scratch_bytes", "fcd_create", "fcd_set_params", "fcd_set_open_channel", "fcd_init_compound_droplet",
     "fcd_init_fields", "fcd_solve_potential", "fcd_step", "fcd_read_moments", "fcd_read_state",
-    "fcd_write_state", "fcd_read_psi", "fcd_write_psi", "fcd_deformation", "fcd_extent_deformation", "fcd_breakup_probe", "fcd_stats", "fcd_timing",
+    "fcd_write_state", "fcd_read_psi", "fcd_write_psi", "fcd_deformation", "fcd_extent_deformation", "fcd_breakup_probe",
+    "fcd_breakup_track", "fcd_stats", "fcd_timing",
     "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
     "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
@@ -98,6 +99,7 @@ def lib():
         L.fcd_deformation.argtypes = [H, dp]
         L.fcd_extent_deformation.argtypes = [H, dp]
         L.fcd_breakup_probe.argtypes = [H, dp]
+        L.fcd_breakup_track.argtypes = [H, dp]
         L.fcd_stats.argtypes = [H, dp]
         L.fcd_timing.argtypes = [H, C.c_int32]
         L.fcd_timing_read.argtypes = [H, dp]
@@ -213,6 +215,12 @@ def fcd_deformation(h):
 def fcd_breakup_probe(h):
     out = (C.c_double * 4)()
     _check(lib().fcd_breakup_probe(h, out), "fcd_breakup_probe")
+    return list(out)
+
+
+def fcd_breakup_track(h):
+    out = (C.c_double * 6)()
+    _check(lib().fcd_breakup_track(h, out), "fcd_breakup_track")
     return list(out)
 
 

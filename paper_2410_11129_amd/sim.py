@@ -230,35 +230,18 @@ class Batch:
 
 
 def run_to_breakup(ch: Channel, max_steps: int, every: int = 10) -> dict | None:
-    """Step a channel from its initial state, probing every `every` steps, until the inner
-    droplet touches the shell's interface (fcd_breakup_probe); None if it has not within
-    max_steps.  The breakup numbers of Sec. 2.5 / Fig. 3: t_b* = t_b u_avg / (2 r_shell)
-    (Eq. 38, u_avg = 2/3 of the Poiseuille peak u_ref), y_b* = distance of the contact point
-    from the centreline over the channel height, L_b* = its distance along the channel from
-    x = 0 over the height, following the droplet across the periodic boundary (the outer
-    droplet's centroid is tracked between probes, which must be closer than half a period
-    of travel)."""
-    w = ch.w
-    nx, ny = w.nx, w.ny
-    half = nx / 2.0
-
-    def wrapped(d):
-        return (d + half) % nx - half
-
-    x_prev = ch.breakup_probe()[3]
-    x_run = x_prev
+    """Step a channel from its initial state, tracking the breakup probe every `every`
+    steps (fcd_breakup_track, which follows the droplet across the periodic boundary and
+    forms the breakup numbers of Sec. 2.5 / Fig. 3), until the inner droplet touches the
+    shell's interface; None if it has not within max_steps."""
+    fcd.fcd_breakup_track(ch.h)  # the reference position
     t = 0
     while t < max_steps:
         n = min(every, max_steps - t)
         ch.step(n)
         t += n
-        cnt, yb, xb, xo = ch.breakup_probe()
-        x_run += wrapped(xo - x_prev)
-        x_prev = xo
+        cnt, t_b_star, L_b_star, y_b_star, x_b, y_b = fcd.fcd_breakup_track(ch.h)
         if cnt > 0:
-            x_b = x_run + wrapped(xb - xo)
-            u_avg = 2.0 / 3.0 * w.u_ref
-            return {"steps": t, "contact_nodes": int(cnt), "x_b": x_b, "y_b": yb,
-                    "t_b_star": t * u_avg / (2.0 * w.r_shell), "L_b_star": x_b / ny,
-                    "y_b_star": abs(yb - (ny - 1) / 2.0) / ny}
+            return {"steps": t, "contact_nodes": int(cnt), "x_b": x_b, "y_b": y_b,
+                    "t_b_star": t_b_star, "L_b_star": L_b_star, "y_b_star": y_b_star}
     return None

@@ -1,7 +1,8 @@
 """Hand-written adjoint of the coupled step (checkpointed) against finite differences.
 
-The gradient of J = a D_o + b D_i (Eq. 39 deformations after n steps from the compound
-droplet) with respect to (H0, alpha, u_ref, sigma12, sigma13, sigma23) is compared with
+The gradient of J = a D_o + b D_i (the second-moment deformations that stand in for the
+index of Eq. 42, after n steps from the compound droplet) with respect to
+(H0, alpha, u_ref, sigma12, sigma13, sigma23) is compared with
 Richardson-extrapolated central differences of (1) the GPU FP64 forward and (2) the FP64
 CPU oracle (exact banded-Cholesky potential solve), to 1e-4 relative.
 """

@@ -506,4 +506,7 @@ def test_breakup_probe_parity():
     assert got["steps"] == hit[0] and got["contact_nodes"] == int(hit[1][0]), (got, hit)
     assert abs(got["y_b"] - hit[1][1]) < 1e-9 and abs(got["x_b"] % w.nx - hit[1][2]) < 1e-9, (got, hit)
     assert got["x_b"] > w.xc and got["y_b_star"] < 0.05, got  # at the front, near the axis
+    # Eq. 38 with the Poiseuille peak (0.01 here) as the velocity scale; L_b* = x_b / H
+    assert got["t_b_star"] == pytest.approx(got["steps"] * 0.01 / (2 * w.r_shell), rel=1e-12), got
+    assert got["L_b_star"] == pytest.approx(got["x_b"] / w.ny, rel=1e-15), got
     g.close()
