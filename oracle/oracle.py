@@ -67,6 +67,49 @@ def build_fast() -> str:
 
 
 _lib = None
+_lib_fast = None
+
+
+def _load(path: str):
+    L = C.CDLL(path)
+    P = C.POINTER(OracleParams)
+    S = C.POINTER(OracleSolver)
+    L.orc_gamma.argtypes = [_dp, _dp]
+    L.orc_feq.argtypes = [C.c_double, _dp, _dp]
+    L.orc_forcing.argtypes = [_dp, C.c_double, _dp]
+    L.orc_collide_f.argtypes = [_dp, C.c_double, _dp, _dp, C.c_double, C.c_double, _dp]
+    L.orc_mrt_matrices.argtypes = [_dp, _dp]
+    L.orc_lattice.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp]
+    L.orc_free_energy.argtypes = [P, _dp]
+    L.orc_free_energy.restype = C.c_double
+    L.orc_free_energy_grad.argtypes = [P, _dp, _dp]
+    L.orc_chem_potential.argtypes = [P, _dp, _dp, _dp]
+    L.orc_solve_potential_phi.argtypes = [P, _dp, _dp, S, _dp, _dp, _dp,
+                                          C.POINTER(C.c_int32), _dp]
+    L.orc_potential_residual_phi.argtypes = [P, _dp, _dp, _dp, _dp]
+    L.orc_potential_residual_phi.restype = C.c_double
+    L.orc_apply_L.argtypes = [P, _dp, _dp, _dp]
+    L.orc_init_fields.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_init_droplet.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   _dp, _dp, _dp, _dp, _dp]
+    L.orc_step.argtypes = [P, S, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(C.c_int32), _dp]
+    L.orc_moments.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+    L.orc_forces.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+    L.orc_deformation_w.argtypes = [C.c_int32, C.c_int32, _dp]
+    L.orc_deformation_w.restype = C.c_double
+    L.orc_diagnostics.argtypes = [P, _dp, _dp, _dp]
+    L.orc_extent_deformation.argtypes = [P, _dp, _dp, _dp]
+    L.orc_breakup_probe.argtypes = [P, _dp, _dp, _dp]
+    L.orc_stencils.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
+    L.orc_mu_r.argtypes = [P, _dp, _dp, _dp]
+    L.orc_phase_source.argtypes = [P, _dp, _dp, _dp]
+    L.orc_threads.argtypes = []
+    L.orc_threads.restype = C.c_int
+    for name in ("orc_init_fields", "orc_init_droplet", "orc_step", "orc_moments",
+                 "orc_forces", "orc_diagnostics", "orc_extent_deformation", "orc_breakup_probe",
+                 "orc_solve_potential_phi"):
+        getattr(L, name).restype = C.c_int
+    return L
 
 
 def use_fast_build():
@@ -82,46 +125,17 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = C.CDLL(_LIB)
-        P = C.POINTER(OracleParams)
-        S = C.POINTER(OracleSolver)
-        L.orc_gamma.argtypes = [_dp, _dp]
-        L.orc_feq.argtypes = [C.c_double, _dp, _dp]
-        L.orc_forcing.argtypes = [_dp, C.c_double, _dp]
-        L.orc_collide_f.argtypes = [_dp, C.c_double, _dp, _dp, C.c_double, C.c_double, _dp]
-        L.orc_mrt_matrices.argtypes = [_dp, _dp]
-        L.orc_lattice.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), _dp]
-        L.orc_free_energy.argtypes = [P, _dp]
-        L.orc_free_energy.restype = C.c_double
-        L.orc_free_energy_grad.argtypes = [P, _dp, _dp]
-        L.orc_chem_potential.argtypes = [P, _dp, _dp, _dp]
-        L.orc_solve_potential_phi.argtypes = [P, _dp, _dp, S, _dp, _dp, _dp,
-                                              C.POINTER(C.c_int32), _dp]
-        L.orc_potential_residual_phi.argtypes = [P, _dp, _dp, _dp, _dp]
-        L.orc_potential_residual_phi.restype = C.c_double
-        L.orc_apply_L.argtypes = [P, _dp, _dp, _dp]
-        L.orc_init_fields.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.orc_init_droplet.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double,
-                                       _dp, _dp, _dp, _dp, _dp]
-        L.orc_step.argtypes = [P, S, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp, C.POINTER(C.c_int32), _dp]
-        L.orc_moments.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
-        L.orc_forces.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
-        L.orc_deformation_w.argtypes = [C.c_int32, C.c_int32, _dp]
-        L.orc_deformation_w.restype = C.c_double
-        L.orc_diagnostics.argtypes = [P, _dp, _dp, _dp]
-        L.orc_extent_deformation.argtypes = [P, _dp, _dp, _dp]
-        L.orc_breakup_probe.argtypes = [P, _dp, _dp, _dp]
-        L.orc_stencils.argtypes = [C.c_int32, C.c_int32, _dp, _dp, _dp, _dp]
-        L.orc_mu_r.argtypes = [P, _dp, _dp, _dp]
-        L.orc_phase_source.argtypes = [P, _dp, _dp, _dp]
-        L.orc_threads.argtypes = []
-        L.orc_threads.restype = C.c_int
-        for name in ("orc_init_fields", "orc_init_droplet", "orc_step", "orc_moments",
-                     "orc_forces", "orc_diagnostics", "orc_extent_deformation", "orc_breakup_probe",
-                     "orc_solve_potential_phi"):
-            getattr(L, name).restype = C.c_int
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def lib_fast():
+    """The -O3 -march=native OpenMP build (built on first use on this machine), loaded beside
+    lib(): the same source and per-node arithmetic, for the large CPU runs."""
+    global _lib_fast
+    if _lib_fast is None:
+        _lib_fast = _load(build_fast())
+    return _lib_fast
 
 
 def ptr(a: np.ndarray | None):
@@ -152,8 +166,9 @@ class OracleSim:
     MOMENT_NAMES = ("pstar", "ux", "uy", "phi1", "phi2", "phi3", "rho", "psi", "Hx", "Hy")
     FORCE_NAMES = ("Fs_x", "Fs_y", "Fm_x", "Fm_y", "Fmu_x", "Fmu_y", "Ft_x", "Ft_y")
 
-    def __init__(self, workload, solver: OracleSolver | None = None):
+    def __init__(self, workload, solver: OracleSolver | None = None, fast: bool = False):
         self.w = workload
+        self.L = lib_fast() if fast else lib()  # fast: the -O3 -march=native OpenMP build
         self.p = params_from_workload(workload)
         self.solver = solver if solver is not None else OracleSolver.direct()
         ny, nx = workload.ny, workload.nx
@@ -170,7 +185,7 @@ class OracleSim:
         w = self.w
         phi1 = np.zeros((w.ny, w.nx))
         phi2 = np.zeros((w.ny, w.nx))
-        rc = lib().orc_init_droplet(C.byref(self.p), w.xc, w.yc, w.r_core, w.r_shell,
+        rc = self.L.orc_init_droplet(C.byref(self.p), w.xc, w.yc, w.r_core, w.r_shell,
                                     ptr(self.f), ptr(self.g1), ptr(self.g2), ptr(phi1), ptr(phi2))
         assert rc == 0, rc
         self.nstep = 0
@@ -181,7 +196,7 @@ class OracleSim:
     def init_fields(self, phi1, phi2, ux, uy, pstar=None, solve: bool = True):
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (phi1, phi2, ux, uy)]
         ps = None if pstar is None else np.ascontiguousarray(pstar, dtype=np.float64)
-        rc = lib().orc_init_fields(C.byref(self.p), *[ptr(a) for a in arrs], ptr(ps),
+        rc = self.L.orc_init_fields(C.byref(self.p), *[ptr(a) for a in arrs], ptr(ps),
                                    ptr(self.f), ptr(self.g1), ptr(self.g2))
         assert rc == 0, rc
         self.nstep = 0
@@ -199,7 +214,7 @@ class OracleSim:
         sw = C.c_int32(0)
         res = C.c_double(0.0)
         s = solver if solver is not None else self.solver
-        rc = lib().orc_solve_potential_phi(C.byref(self.p), ptr(phi1), ptr(phi2), C.byref(s),
+        rc = self.L.orc_solve_potential_phi(C.byref(self.p), ptr(phi1), ptr(phi2), C.byref(s),
                                            ptr(self.psi), None, None, C.byref(sw), C.byref(res))
         self.sweeps, self.resid = sw.value, res.value
         return rc
@@ -208,7 +223,7 @@ class OracleSim:
     def step(self, n: int) -> int:
         sw = C.c_int32(0)
         res = C.c_double(0.0)
-        rc = lib().orc_step(C.byref(self.p), C.byref(self.solver), int(n), int(self.nstep), ptr(self.f),
+        rc = self.L.orc_step(C.byref(self.p), C.byref(self.solver), int(n), int(self.nstep), ptr(self.f),
                             ptr(self.g1), ptr(self.g2), ptr(self.psi), C.byref(sw), C.byref(res))
         self.sweeps, self.resid = sw.value, res.value
         self.nstep += int(n)
@@ -217,34 +232,34 @@ class OracleSim:
     # --- outputs -----------------------------------------------------------------
     def moments(self) -> dict:
         out = np.zeros((10, self.w.ny, self.w.nx))
-        rc = lib().orc_moments(C.byref(self.p), ptr(self.f), ptr(self.g1), ptr(self.g2),
+        rc = self.L.orc_moments(C.byref(self.p), ptr(self.f), ptr(self.g1), ptr(self.g2),
                                ptr(self.psi), ptr(out))
         assert rc == 0, rc
         return {k: out[i] for i, k in enumerate(self.MOMENT_NAMES)}
 
     def forces(self) -> dict:
         out = np.zeros((8, self.w.ny, self.w.nx))
-        rc = lib().orc_forces(C.byref(self.p), ptr(self.f), ptr(self.g1), ptr(self.g2),
+        rc = self.L.orc_forces(C.byref(self.p), ptr(self.f), ptr(self.g1), ptr(self.g2),
                               ptr(self.psi), ptr(out))
         assert rc == 0, rc
         return {k: out[i] for i, k in enumerate(self.FORCE_NAMES)}
 
     def diagnostics(self):
         out = np.zeros(4)
-        rc = lib().orc_diagnostics(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
+        rc = self.L.orc_diagnostics(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
         assert rc == 0, rc
         return out
 
     def breakup_probe(self):
         """{contact nodes, their mean y, their circular-mean x, outer droplet's circular-mean x}."""
         out = np.zeros(4)
-        rc = lib().orc_breakup_probe(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
+        rc = self.L.orc_breakup_probe(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
         assert rc == 0, rc
         return out
 
     def extent_deformation(self):
         """{T_o, T_i, l_y outer, l_x outer, l_y inner, l_x inner} (Eq. 42 extents)."""
         out = np.zeros(6)
-        rc = lib().orc_extent_deformation(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
+        rc = self.L.orc_extent_deformation(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
         assert rc == 0, rc
         return out

@@ -2220,6 +2220,9 @@ fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_iters, int
     int it = 0;
     st = FCD_DISPATCH(h, solve_impl)(h, tol, max_iters, &it, resid_out);
     if (iters_out) *iters_out = it;
+    // an explicit solve (typically from a cold start) says nothing about how many cycles
+    // the next time step's warm-started solve needs: its first residual test is not deferred
+    h->last_iters = 0;
     return st;
 }
 

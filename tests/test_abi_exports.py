@@ -132,3 +132,4 @@ def test_divergence_guard_settings_validated_on_host():
     assert L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h)) == fcd.FCD_ERR_ARG
     assert "div_check_every" in fcd.fcd_last_error()
     assert L.fcd_sync(None) == fcd.FCD_ERR_ARG
+

@@ -285,6 +285,43 @@ def test_full_size_with_field_properties():
         assert np.abs(a + a[::-1]).max() <= 1e-6 * max(np.abs(a).max(), 1e-30), k
 
 
+def test_full_size_potential_with_field_against_oracle():
+    """The field path at full size (2048 x 512, Bo_m = 2, field across the channel) against
+    the oracle.  (1) The potential of the initial state, solved from zero by the GPU's
+    multigrid and, independently, by the oracle's four-colour SOR (its -O3 OpenMP build,
+    the same arithmetic), both to max |L(psi0 + psi')| <= 1e-11 H0: two solutions within
+    that residual differ by at most twice tol H0 times the inverse operator's norm,
+    ~(ny / pi)^2 / 2.  (2) After 20 GPU steps and a GPU solve for the state they reach (the
+    psi' a step stores was solved for the phases before its collision), the oracle's own
+    operator applied to the GPU's phi1, phi2 and psi' (a property any solve to tolerance
+    has): its residual is within the GPU's 1e-10 H0."""
+    w = single_channel_large(bond=2.0)
+    say("case full size 2048x512 Bo=2 potential vs oracle SOR")
+    tol = 1e-11
+    g = Channel(w, solver=fcd.FCD_SOLVER_MG, tol=1e-10, check_every=1, max_iters=1000)
+    g.init_droplet()
+    st, cycles, res = g.solve_potential(tol, 1000)
+    psi_g = g.psi_dense()
+    omega = 2.0 / (1.0 + math.sin(math.pi / (w.ny + 1)))
+    s = OracleSim(w, OracleSolver.sor(omega, tol, 1000000, 20), fast=True)
+    s.init_droplet(solve=True)
+    bound = 2 * tol * w.H0 * (w.ny / math.pi) ** 2 / 2
+    err = np.abs(psi_g - s.psi).max()
+    say(f"  initial psi': GPU {cycles} V-cycles, oracle {s.sweeps} SOR sweeps; max |d psi'| {err:.3e} "
+        f"(bound {bound:.3e}, max |psi'| {np.abs(s.psi).max():.3e})")
+    assert err <= bound
+    g.step(20)
+    g.solve_potential(1e-10, 1000)
+    m = g.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2 | fcd.FCD_M_PSI)
+    from oracle.oracle import lib as orc_lib, ptr as orc_ptr
+    r = orc_lib().orc_potential_residual_phi(s.p, orc_ptr(np.ascontiguousarray(m["phi1"])),
+                                             orc_ptr(np.ascontiguousarray(m["phi2"])),
+                                             orc_ptr(np.ascontiguousarray(m["psi"])), None)
+    say(f"  after 20 steps: oracle residual of the GPU's psi' {r:.3e} (tol {1e-10 * w.H0:.3e})")
+    assert r <= 1e-10 * w.H0 * (1 + 1e-6)
+    g.close()
+
+
 def test_full_size_fp32_deformation_tracks_fp64():
     """2048 x 512 at Bo_m = 2: the FP32 path's deformation time series stays within the
     stated 1e-3 of the FP64 path's, and its order parameters within 1e-4, over 300 steps
