@@ -232,6 +232,20 @@ fcd_status fcd_breakup_probe(fcd_handle* h, double out[4]);
  * tracking.  Sync. */
 fcd_status fcd_breakup_track(fcd_handle* h, double out[6]);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the deformation and masses of
+ * fcd_deformation for phase planes the caller holds, with no handle and no scratch
+ * buffer.  phi: device [3][ny][pitch] planes of the lattice's precision (phi1, phi2, mu_r
+ * as a handle's phase buffer holds them; phi1 and phi2 are read); out: device buffer of
+ * four doubles {D_o, D_i, mass1, mass2}, written by the last kernel.  Uses a library-owned
+ * device array of FCD_NOALLOC_MAX_NY x 8 + 32 doubles (about 512 KiB) per GPU, held until
+ * the process ends; FCD_ERR_ARG for ny > FCD_NOALLOC_MAX_NY.  All calls on one GPU share
+ * that array: calls that overlap in time on one GPU (other streams or threads) race.
+ * Allocates nothing; async on hip_stream (a hipStream_t; NULL = the null stream).  The
+ * result equals fcd_deformation's bit for bit on the same planes. */
+#define FCD_NOALLOC_MAX_NY 8192
+fcd_status fcd_deformation_noalloc(const fcd_lattice* lat, const void* phi, void* hip_stream, double* out);
+
 /* Counters since creation: out = {steps, potential iterations (SOR sweeps or V-cycles),
  * last residual}.  Host only. */
 fcd_status fcd_stats(fcd_handle* h, double out[3]);

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2567,3 +2568,79 @@ fcd_status fcd_batch_destroy(fcd_batch* b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// No-allocation deformation (fcd_deformation_noalloc).  The row partial sums and the
+// centroids of the two diagnostic passes live in this file-scope device array instead of
+// a caller's scratch buffer; each GPU holds its own copy until the process ends.  Host
+// code never passes `scratch` itself to a kernel: its device address on each GPU comes
+// from hipGetSymbolAddress, taken once per device with that device current.  Every value
+// of the array is written before it is read (rows by the first pass, centroids by its
+// final kernel), so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------------
+namespace {
+
+constexpr int NOALLOC_MAX_NY = FCD_NOALLOC_MAX_NY;
+constexpr int NOALLOC_CENT = 32;  // doubles: centroids, masses and the pass-0 sums
+constexpr size_t NOALLOC_DOUBLES = (size_t)NOALLOC_MAX_NY * 8 + NOALLOC_CENT;
+
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mutex;
+double* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's address of `scratch` (set up on the first call on that device).
+fcd_status noalloc_scratch(double** out) {
+    int dev = -1;
+    fcd_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (st) return st;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(FCD_ERR_UNSUPPORTED, "device index beyond 64");
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (st) return st;
+        if (!p) return fail(FCD_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+        g_noalloc_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return FCD_OK;
+}
+
+template <typename T>
+fcd_status deformation_noalloc_impl(const fcd_lattice* lat, const void* phi, hipStream_t stream, double* out) {
+    double* base = nullptr;
+    fcd_status st = noalloc_scratch(&base);
+    if (st) return st;
+    fcd::StepConst<T> P{};
+    P.nx = lat->nx;
+    P.ny = lat->ny;
+    P.pitch = lat->pitch;
+    P.plane = (long long)lat->ny * lat->pitch;
+    double* rows = base;
+    double* cent = base + (size_t)NOALLOC_MAX_NY * 8;
+    fcd::launch_diagnostics<T>(static_cast<const T*>(phi), P, rows, cent, out, stream);
+    return hip_check(hipGetLastError(), "diagnostics launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+fcd_status fcd_deformation_noalloc(const fcd_lattice* lat, const void* phi, void* hip_stream, double* out) {
+    fcd_status st = check_lattice(lat);
+    if (st) return st;
+    if (!phi || !out) return fail(FCD_ERR_ARG, "null argument");
+    if (lat->ny > NOALLOC_MAX_NY)
+        return fail(FCD_ERR_ARG, "fcd_deformation_noalloc: ny exceeds FCD_NOALLOC_MAX_NY (" +
+                                     std::to_string(NOALLOC_MAX_NY) + ")");
+    if (reinterpret_cast<uintptr_t>(phi) % elem_size(lat->precision) || reinterpret_cast<uintptr_t>(out) % 8)
+        return fail(FCD_ERR_ARG, "misaligned device buffer");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    return lat->precision == FCD_FP64 ? deformation_noalloc_impl<double>(lat, phi, s, out)
+                                      : deformation_noalloc_impl<float>(lat, phi, s, out);
+}
+
+}  // extern "C"
+

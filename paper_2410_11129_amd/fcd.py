@@ -22,13 +22,14 @@ FCD_M_PHI1, FCD_M_PHI2, FCD_M_PHI3 = 1 << 3, 1 << 4, 1 << 5
 FCD_M_RHO, FCD_M_PSI, FCD_M_HX, FCD_M_HY = 1 << 6, 1 << 7, 1 << 8, 1 << 9
 FCD_M_ALL = (1 << 10) - 1
 MOMENT_NAMES = ("pstar", "ux", "uy", "phi1", "phi2", "phi3", "rho", "psi", "Hx", "Hy")
+FCD_NOALLOC_MAX_NY = 8192  # rows fcd_deformation_noalloc's device array holds
 
 # Every symbol include/fcd.h declares.
 EXPORTS = (
     "fcd_scratch_bytes", "fcd_create", "fcd_set_params", "fcd_set_open_channel", "fcd_init_compound_droplet",
     "fcd_init_fields", "fcd_solve_potential", "fcd_step", "fcd_read_moments", "fcd_read_state",
     "fcd_write_state", "fcd_read_psi", "fcd_write_psi", "fcd_deformation", "fcd_extent_deformation", "fcd_breakup_probe",
-    "fcd_breakup_track", "fcd_stats", "fcd_timing",
+    "fcd_breakup_track", "fcd_deformation_noalloc", "fcd_stats", "fcd_timing",
     "fcd_timing_read", "fcd_use_graphs", "fcd_sync", "fcd_destroy", "fcd_last_error", "fcd_adjoint_bytes", "fcd_adjoint_forward",
     "fcd_adjoint_backward", "fcd_batch_sizes", "fcd_batch_create",
     "fcd_batch_init_compound_droplet", "fcd_batch_step", "fcd_batch_deformation", "fcd_batch_read_state",
@@ -100,6 +101,7 @@ def lib():
         L.fcd_extent_deformation.argtypes = [H, dp]
         L.fcd_breakup_probe.argtypes = [H, dp]
         L.fcd_breakup_track.argtypes = [H, dp]
+        L.fcd_deformation_noalloc.argtypes = [C.POINTER(fcd_lattice), C.c_void_p, C.c_void_p, C.c_void_p]
         L.fcd_stats.argtypes = [H, dp]
         L.fcd_timing.argtypes = [H, C.c_int32]
         L.fcd_timing_read.argtypes = [H, dp]
@@ -216,6 +218,12 @@ def fcd_breakup_probe(h):
     out = (C.c_double * 4)()
     _check(lib().fcd_breakup_probe(h, out), "fcd_breakup_probe")
     return list(out)
+
+
+def fcd_deformation_noalloc(lat: fcd_lattice, phi: int, stream: int, out: int):
+    """Async; out is a device pointer to four doubles."""
+    _check(lib().fcd_deformation_noalloc(C.byref(lat), C.c_void_p(phi), C.c_void_p(stream), C.c_void_p(out)),
+           "fcd_deformation_noalloc")
 
 
 def fcd_breakup_track(h):

@@ -133,3 +133,14 @@ def test_divergence_guard_settings_validated_on_host():
     assert "div_check_every" in fcd.fcd_last_error()
     assert L.fcd_sync(None) == fcd.FCD_ERR_ARG
 
+
+def test_noalloc_limit_matches_header_and_is_checked_on_host():
+    """fcd_deformation_noalloc's row limit is the header's, and a larger lattice is rejected
+    before any device work."""
+    text = open(os.path.join(ROOT, "include", "fcd.h")).read()
+    m = re.search(r"#define FCD_NOALLOC_MAX_NY (\d+)", text)
+    assert m and int(m.group(1)) == fcd.FCD_NOALLOC_MAX_NY
+    lat = fcd.fcd_lattice(8, fcd.FCD_NOALLOC_MAX_NY + 2, fcd.FCD_FP64, 8)
+    st = fcd.lib().fcd_deformation_noalloc(C.byref(lat), C.c_void_p(256), None, C.c_void_p(512))
+    assert st == fcd.FCD_ERR_ARG and "FCD_NOALLOC_MAX_NY" in fcd.fcd_last_error()
+    assert fcd.lib().fcd_deformation_noalloc(C.byref(lat), None, None, None) == fcd.FCD_ERR_ARG
