@@ -381,6 +381,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    # steps run after the initial state and before the warm-up, so that the timed window
+    # lies in the developed run rather than its start-up transient (the initial state has
+    # p* = 0 and no Laplace pressure, and its acoustic transient makes the first ~60 steps'
+    # potential solves need up to 11 V-cycles against 4-5 later); the start-up window
+    # (right after the initial state) is measured too and reported beside it
+    ap.add_argument("--preroll", type=int, default=500)
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64")
     ap.add_argument("--bond", type=float, default=2.0)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -428,14 +434,30 @@ def main() -> int:
     t0 = time.perf_counter()
     st, sw0, res0 = ch.solve_potential(tol, 1 << 30)
     log(f"bench: initial potential solve {sw0} iterations, residual {res0:.3e}, {time.perf_counter() - t0:.2f} s")
-    ch.step(args.warmup)
-    torch.cuda.synchronize()
-    sweeps_before = ch.stats()[1]
-    t0 = time.perf_counter()
-    ch.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    sweeps = ch.stats()[1] - sweeps_before
+
+    def timed_window():
+        ch.step(args.warmup)
+        torch.cuda.synchronize()
+        s0 = ch.stats()[1]
+        t1 = time.perf_counter()
+        ch.step(args.steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1, ch.stats()[1] - s0
+
+    done = 0
+    startup = None
+    if args.preroll > 0:
+        dt0, sw_0 = timed_window()
+        done = args.warmup + args.steps
+        startup = {"steps_after_init": [args.warmup + 1, done], "ms_per_step": round(dt0 / args.steps * 1e3, 4),
+                   "MLUPS": round(w.sites * args.steps / dt0 / 1e6, 3),
+                   "potential_iters_per_step": round(sw_0 / args.steps, 2)}
+        log(f"bench: start-up window {startup}")
+        if args.preroll > done:
+            ch.step(args.preroll - done)
+            done = args.preroll
+    dt, sweeps = timed_window()
+    first = done + args.warmup + 1
     # per-kernel breakdown in a separate window: HIP events around every launch add host
     # work between launches, so they stay out of the timed steps above
     prof_steps = max(1, min(args.steps, 20))
@@ -481,7 +503,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{w.name}_{args.precision}_bo{args.bond:g}", "nx": w.nx, "ny": w.ny,
                    "bond": args.bond, "potential_solver": args.solver, "potential_tol": tol,
-                   "potential_iters_per_step": round(sweeps / args.steps, 2)},
+                   "potential_iters_per_step": round(sweeps / args.steps, 2),
+                   "timed_steps_after_init": [first, first + args.steps - 1]},
         "roofline": roof,
         # the whole step against HBM: algorithmic bytes of every launch (step_bytes_per_site)
         # over the timed step; the potential's share is everything but the collide-and-stream
@@ -492,6 +515,8 @@ def main() -> int:
         "potential_share": round(max(0.0, ms_step - kernel_ms) / ms_step, 4),
         "kernels": per_kind,
     }
+    if startup is not None:
+        out["startup_window"] = startup
     try:
         out["copy_GBps_torch"] = round(copy_bandwidth_gbs(torch), 1)
     except Exception as e:  # noqa: BLE001
