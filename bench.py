@@ -59,21 +59,22 @@ def values_per_site(solver: str) -> dict:
     return v
 
 
-def step_bytes_per_site(esz: int, cycles: float, solver: str, extrapolate: bool) -> float:
+def step_bytes_per_site(esz: int, cycles: float, solver: str, extrapolate: bool, smooth: int = 1) -> float:
     """Algorithmic HBM bytes per lattice site of one whole coupled step (every launch, each
     plane counted once per pass, tile halos and re-reads not counted).  Values are esz bytes;
     the multigrid's coarse levels are FP32 and level l holds 4^-l of the sites.
     collide-and-stream 57 values; phase moments 18 read + 3 written; warm start (quadratic:
     psi', two history planes read and written) 6; mu_r read once for the coarse mu of all
-    levels (FP32 writes: sum 4 * 4^-l = 4/3 B).  A V-cycle on the finest level: pre-smoothing
-    3 (psi', mu_r read, result written), restriction fused with the level-1 smoothing 2 read
-    + 2 B of FP32 writes (f and u of level 1), prolongation + post-smoothing 3 + 1 B (the
-    level-1 correction); every coarse level repeats that pattern in FP32 on 4^-l of the
-    sites: sum_l 8 * 4 * 4^-l = 32/3 B.  An SOR sweep: mu_r and psi' read, psi' written; a
+    levels (FP32 writes: sum 4 * 4^-l = 4/3 B).  A V-cycle on the finest level: `smooth`
+    pre-smoothing launches of 3 (psi', mu_r read, result written), restriction fused with the
+    level-1 smoothing 2 read + 2 B of FP32 writes (f and u of level 1), `smooth`
+    post-smoothing launches of 3, the first also reading the level-1 correction (1 B); every
+    coarse level (one launch down, one up) repeats the single-launch pattern in FP32 on 4^-l
+    of the sites: sum_l 8 * 4 * 4^-l = 32/3 B.  An SOR sweep: mu_r and psi' read, psi' written; a
     residual test every sweep adds two reads."""
     b = (57 + 21) * esz + (6 * esz if extrapolate else 0)
     if solver == "mg":
-        b += esz + 4.0 / 3.0 + cycles * (8 * esz + 3 + 32.0 / 3.0)
+        b += esz + 4.0 / 3.0 + cycles * ((6 * smooth + 2) * esz + 3 + 32.0 / 3.0)
     else:
         b += cycles * 3 * esz
     return b
@@ -263,8 +264,22 @@ def batched_adjoint(torch, steps: int, every: int) -> dict:
         seq += time.perf_counter() - t0
         ch.close()
     per_seq = seq / 2
+    # conditioning of the horizon: channel 1's FP64 gradient again, its initial state
+    # perturbed by a random relative 6e-8 (the size of FP32 rounding)
+    import numpy as np
+    ch = Channel(ws[1], tol=1e-10)
+    r1 = AdjointRun(ch, steps, every)
+    ch.init_droplet()
+    st = ch.state()
+    ch.write_state(st * (1.0 + 6e-8 * np.random.default_rng(5).uniform(-1.0, 1.0, st.shape)))
+    fcd.fcd_adjoint_forward(ch.h, steps, every, r1.work.data_ptr())
+    gp = fcd.fcd_adjoint_backward(ch.h, [1.0, 0.0])
+    ch.close()
+    del r1
+    sens = max(abs(gp[q] - gs[1][q]) / abs(gs[1][q]) for q in (0, 1))
     out = {"channels": len(ws), "steps": steps, "ckpt_every": every,
-           "s_per_gradient_sequential_fp64": round(per_seq, 4)}
+           "s_per_gradient_sequential_fp64": round(per_seq, 4),
+           "fp64_gradient_change_under_6e-8_perturbation": float(f"{sens:.3e}")}
     for name, prec, tol in (("fp32", fcd.FCD_FP32, 1e-5), ("fp64", fcd.FCD_FP64, 1e-10)):
         bt = Batch(ws, precision=prec, tol=tol)
         bt.init_droplets()
@@ -391,7 +406,10 @@ def main() -> int:
     ap.add_argument("--bond", type=float, default=2.0)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--solver", choices=("mg", "sor"), default="mg")
-    ap.add_argument("--smooth", type=int, default=1)
+    # finest-level smoothing sweeps (one launch each) before and after each coarse
+    # correction: 3 needs 2.15 V-cycles per step against 4.0 with 1 (measured, 2048 x 512
+    # FP64 Bo_m = 2, steps 501-540: 0.531 against 0.632 ms/step; 4, 5, 6: 0.556, 0.601, 0.649)
+    ap.add_argument("--smooth", type=int, default=3)
     ap.add_argument("--coarse-sweeps", type=int, default=2)
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--no-extrapolate", action="store_true")
@@ -492,7 +510,7 @@ def main() -> int:
             "frac": round(per_kind[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": VALUES_PER_SITE[dom] * esz * sites}
     cycles = sweeps / max(args.steps, 1)
-    step_b = step_bytes_per_site(esz, cycles, args.solver, not args.no_extrapolate)
+    step_b = step_bytes_per_site(esz, cycles, args.solver, not args.no_extrapolate, args.smooth)
     step_gbps = step_b * sites / (dt / args.steps) / 1e9
     kernel_ms = sum(per_kind[k]["ms_per_step"] for k in ("collide_stream", "phase") if k in per_kind)
     ms_step = dt / args.steps * 1e3

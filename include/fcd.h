@@ -84,7 +84,9 @@ typedef struct {
     int32_t pot_solver;      /* FCD_SOLVER_SOR or FCD_SOLVER_MG */
     int32_t pot_check_every; /* SOR sweeps / multigrid V-cycles between residual tests */
     int32_t pot_max_iters;   /* SOR sweeps / V-cycles allowed per solve */
-    int32_t pot_smooth;      /* multigrid: Gauss-Seidel sweeps before and after each coarse correction */
+    int32_t pot_smooth;      /* multigrid: four-colour Gauss-Seidel sweeps of the finest level before and
+                                after each coarse correction (one launch each); coarse levels always
+                                take one launch of two tile sweeps each way */
     int32_t pot_coarse_sweeps; /* multigrid: SOR sweeps on the coarsest level, times max(1, ny_c / 2);
                                   a negative value -N: exactly N sweeps; 0 is rejected */
     int32_t pot_extrapolate; /* warm start of each step's solve: 0 the previous psi', 1 the linear

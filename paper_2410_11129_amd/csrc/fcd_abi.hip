@@ -30,8 +30,14 @@ fcd_status hip_check(hipError_t e, const char* what) {
 }
 
 // Scratch layout (bytes from the start of the caller's scratch buffer).
-constexpr size_t OFF_RES = 0;      // 2 x uint64: bit patterns of max |residual| and max |C psi'|
+// Residual words: bit patterns of max |residual| and max |C psi'|.  The multigrid's tests
+// alternate between two slots A and B placed around the divergence flag, so one
+// three-word copy brings a test's pair and the flag (A: words 0-2, B: words 2-4); each
+// test's kernel zeroes the other slot for the next test.  SOR tests use words 5-6.
+constexpr size_t OFF_RES = 0;      // slot A, 2 x uint64
 constexpr size_t OFF_DIV = 16;     // uint64: divergence flag (0, or the worst node's max |u| bits / NaN)
+constexpr size_t OFF_RES_B = 24;   // slot B, 2 x uint64
+constexpr size_t OFF_RES_SOR = 40; // 2 x uint64 (SOR and the explicit residual kernel)
 constexpr size_t OFF_CENT = 256;   // 8 doubles: centroids and masses
 constexpr size_t OFF_RESULT = 512; // 4 doubles: D_o, D_i, mass1, mass2
 constexpr size_t OFF_EXTENT = 768; // Eq. 42 extents: 2 x uint64 (l_y bit patterns), 2 doubles (l_x)
@@ -170,6 +176,17 @@ struct Timer {
         if (!b || hipEventRecord(b, s) != hipSuccess) return;
         pending.push_back({kind, a, b});
     }
+    // Two events for a launch that records them itself (hipExtLaunchKernel): they time the
+    // kernel alone, without the host's launch gap that a recorded bracket on an idle stream
+    // would include.  Returns false when timing is off.
+    bool pair(hipEvent_t* a, hipEvent_t* b) {
+        *a = *b = nullptr;
+        if (!on) return false;
+        *a = take();
+        *b = take();
+        return *a && *b;
+    }
+    void add(int kind, hipEvent_t a, hipEvent_t b) { pending.push_back({kind, a, b}); }
     // Only after the stream has been synchronised.
     void resolve() {
         for (const Pair& p : pending) {
@@ -239,6 +256,7 @@ struct fcd_handle {
     int hist;  // completed step solves since the last state change (psi' history validity)
     int qs;    // steps since the last state change (the potential is solved when qs % pot_every == 0)
     int last_iters;  // iterations the previous solve needed (first residual test is deferred)
+    int res_slot;    // multigrid residual slot of the next test (0: A, 1: B); that slot is zero
     int init_fresh;  // the state is the compound-droplet initial state (no step since)
     int open_x;      // open channel: Eq. 37 inlet at x = 0, convective outlet at x = nx - 1
     double u_in;     // u_avg of Eq. 37 (centreline value of the inlet profile)
@@ -352,7 +370,11 @@ T* plane_ptr(void* base, const fcd_handle* h, int q) {
 }
 
 unsigned long long* res_word(const fcd_handle* h) {
-    return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + OFF_RES);
+    return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + OFF_RES_SOR);
+}
+
+unsigned long long* res_slot_ptr(const fcd_handle* h, int slot) {
+    return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + (slot ? OFF_RES_B : OFF_RES));
 }
 
 // The divergence flag sits right after the two residual words, so one three-word copy
@@ -442,16 +464,17 @@ fcd_status read_residual(fcd_handle* h, const fcd::PotLevel<T>& L0, double* r, d
     if (timed) h->timer.end(h->stream, TK_RESID, ev);
     fcd_status st = hip_check(hipGetLastError(), "residual launch");
     if (st) return st;
-    st = hip_check(hipMemcpyAsync(h->host, res_word(h), 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+    // words 2-6: the divergence flag, slot B (skipped) and the SOR words
+    st = hip_check(hipMemcpyAsync(h->host, div_word(h), 5 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
                    "residual copy");
     if (st) return st;
     st = hip_check(hipStreamSynchronize(h->stream), "residual sync");
     if (st) return st;
     h->timer.resolve();
-    std::memcpy(r, h->host, sizeof(double));
-    std::memcpy(scale, h->host + 1, sizeof(double));
+    std::memcpy(r, h->host + 3, sizeof(double));
+    std::memcpy(scale, h->host + 4, sizeof(double));
     unsigned long long w;
-    std::memcpy(&w, h->host + 2, sizeof(w));
+    std::memcpy(&w, h->host, sizeof(w));
     return divergence_status(w, u_limit_of(h->prm), "divergence guard");
 }
 
@@ -547,14 +570,16 @@ int fine_mode(const fcd::PotLevel<T>& L0) {
 // holding the result.  The first sweep reduces the input's residual into res when
 // res != nullptr.
 template <typename T>
-T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int mode, unsigned long long* res) {
+T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int mode, unsigned long long* res,
+                unsigned long long* res_clear = nullptr) {
     T* a = F.u;
     T* b = mg_temp<T>(h, 0);
     const fcd::PotLevel<CT>* none = nullptr;
     for (int s = 0; s < std::max(1, h->prm.pot_smooth); ++s) {
         hipEvent_t ev = nullptr;
         const bool timed = h->timer.begin(h->stream, &ev);
-        fcd::launch_mg_smooth_tile<T, CT>(F, a, b, none, mode, s == 0 ? res : nullptr, 1, h->stream);
+        fcd::launch_mg_smooth_tile<T, CT>(F, a, b, none, mode, s == 0 ? res : nullptr, 1, h->stream,
+                                          s == 0 ? res_clear : nullptr);
         if (timed) h->timer.end(h->stream, TK_SMOOTH0, ev);
         std::swap(a, b);
     }
@@ -562,29 +587,26 @@ T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int mode, unsigned lon
 }
 
 // Coarse level l >= 1: the restriction from level l-1 (u = its pre-smoothed iterate
-// Fp.u, right-hand side by fmode) fused with the first of nu1 pre-smoothing sweeps from
-// a zero correction; returns the buffer holding the result.
+// Fp.u, right-hand side by fmode) fused with the level's pre-smoothing (MG_COARSE_INNER
+// tile sweeps from a zero correction, one launch); returns the buffer holding the result.
 template <typename TF>
 CT* mg_restrict_presmooth(fcd_handle* h, const fcd::PotLevel<TF>& Fp, int fmode, int l) {
     const fcd::PotLevel<CT> F = coarse_level(h, l);
-    const fcd::PotLevel<CT>* none = nullptr;
-    CT* a = F.u;
     CT* b = mg_temp<CT>(h, l);
     fcd::launch_mg_restrict_smooth<TF, CT>(Fp, F, fmode, b, MG_COARSE_INNER, h->stream);
-    std::swap(a, b);
-    for (int s = 1; s < std::max(1, h->prm.pot_smooth); ++s) {
-        fcd::launch_mg_smooth_tile<CT, CT>(F, a, b, none, 0, nullptr, MG_COARSE_INNER, h->stream);
-        std::swap(a, b);
-    }
-    return a;
+    return b;
 }
 
-// Prolongation of level l+1's correction fused with the first of nu2 post-smoothing
-// sweeps, from the pre-smoothed iterate `cur`; the result ends in F.u.
+// Prolongation of level l+1's correction fused with the first post-smoothing launch, from
+// the pre-smoothed iterate `cur`; the result ends in F.u.  The finest level takes
+// pot_smooth launches of one sweep each (each sweep sees its neighbours' latest values,
+// which a second sweep inside one tile launch would not), a coarse level one launch of
+// MG_COARSE_INNER sweeps: on the latency-bound coarse levels a launch costs more than the
+// cycles a second one saves, on the finest level the heavier smoothing pays.
 template <typename T>
 void mg_postsmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int l, int mode, T* cur, const fcd::PotLevel<CT>& Cl) {
     T* other = cur == F.u ? mg_temp<T>(h, l) : F.u;
-    const int nu = std::max(1, h->prm.pot_smooth);
+    const int nu = l == 0 ? std::max(1, h->prm.pot_smooth) : 1;
     const fcd::PotLevel<CT>* none = nullptr;
     for (int s = 0; s < nu; ++s) {
         hipEvent_t ev = nullptr;
@@ -630,7 +652,7 @@ void vcycle_rest(fcd_handle* h, const fcd::PotLevel<T>& L0, T* cur0) {
         fcd::MgTail<CT> tl{};
         tl.n = L - h->plan.tail;
         for (int k = 0; k < tl.n; ++k) tl.lv[k] = coarse_level(h, h->plan.tail + k);
-        tl.nu1 = tl.nu2 = std::max(1, h->prm.pot_smooth);
+        tl.nu1 = tl.nu2 = 1;  // two damped Jacobi sweeps each way
         tl.coarse_sweeps = coarse_sweeps(h, tl.lv[tl.n - 1].ny);
         tl.omega = CT(sor_omega_opt(tl.lv[tl.n - 1].ny));
         fcd::launch_mg_tail<CT>(tl, h->stream);
@@ -694,17 +716,22 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
         for (;;) {
             hipEvent_t ev = nullptr;
             bool timed = h->timer.begin(h->stream, &ev);
-            T* cur0 = mg_presmooth<T>(h, L0, fine_mode(L0), res_word(h));
+            const int slot = h->res_slot;
+            T* cur0 = mg_presmooth<T>(h, L0, fine_mode(L0), res_slot_ptr(h, slot), res_slot_ptr(h, 1 - slot));
+            h->res_slot = 1 - slot;
             if (timed) h->timer.end(h->stream, TK_RESID, ev);
-            st = hip_check(hipMemcpyAsync(h->host, res_word(h), 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+            // slot A: words 0-2 = (r, scale, flag); slot B: words 2-4 = (flag, r, scale)
+            st = hip_check(hipMemcpyAsync(h->host, slot ? div_word(h) : res_slot_ptr(h, 0), 3 * sizeof(double),
+                                          hipMemcpyDeviceToHost, h->stream),
                            "residual copy");
             if (!st) st = hip_check(hipStreamSynchronize(h->stream), "residual sync");
             if (st) return st;
-            std::memcpy(&r, h->host, sizeof(double));
-            std::memcpy(&scale, h->host + 1, sizeof(double));
+            const int o = slot ? 1 : 0;
+            std::memcpy(&r, h->host + o, sizeof(double));
+            std::memcpy(&scale, h->host + o + 1, sizeof(double));
             {
                 unsigned long long w;
-                std::memcpy(&w, h->host + 2, sizeof(w));
+                std::memcpy(&w, h->host + (slot ? 0 : 2), sizeof(w));
                 st = divergence_status(w, u_limit_of(h->prm), "divergence guard");
                 if (st) return st;
             }
@@ -776,10 +803,10 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
     for (int n = 0; n < nsteps; ++n) {
         const T* src = static_cast<const T*>(h->buf.dist[h->cur]);
         T* dst = static_cast<T*>(h->buf.dist[1 - h->cur]);
-        hipEvent_t ev = nullptr;
-        bool timed = h->timer.begin(h->stream, &ev);
-        fcd::launch_phase<T>(src, phi, P, h->stream);
-        if (timed) h->timer.end(h->stream, TK_PHASE, ev);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool timed = h->timer.pair(&e0, &e1);
+        fcd::launch_phase<T>(src, phi, P, h->stream, e0, e1);
+        if (timed) h->timer.add(TK_PHASE, e0, e1);
         fcd_status st = hip_check(hipGetLastError(), "phase launch");
         if (st) return st;
         // quasi-static coupling: the potential is solved on the steps qs = 0, K, 2K, ... since
@@ -798,12 +825,13 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
             ++h->hist;
         }
         ++h->qs;
-        timed = h->timer.begin(h->stream, &ev);
-        fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, div_word(h), h->stream);
+        timed = h->timer.pair(&e0, &e1);
+        fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, div_word(h), h->stream,
+                                      e0, e1);
+        if (timed) h->timer.add(TK_COLLIDE, e0, e1);
         if (h->open_x)
             fcd::launch_open_boundaries<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, h->u_in, h->u_out,
                                            h->stream);
-        if (timed) h->timer.end(h->stream, TK_COLLIDE, ev);
         st = hip_check(hipGetLastError(), "collide-stream launch");
         if (st) return st;
         h->cur = 1 - h->cur;
@@ -2142,7 +2170,11 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
         delete h;
         return fail(FCD_ERR_OOM, "pinned host allocation failed");
     }
-    st = clear_divergence(h);  // the scratch arrives with the caller's contents
+    // the scratch arrives with the caller's contents: zero both residual slots and the flag
+    h->res_slot = 0;
+    hipLaunchKernelGGL(fcd::k_fill<unsigned long long>, dim3(1), dim3(64), 0, h->stream, res_slot_ptr(h, 0), 5LL,
+                       0ULL);
+    st = hip_check(hipGetLastError(), "residual slot clear");
     if (st) {
         (void)hipHostFree(h->host);
         delete h;

@@ -5,6 +5,7 @@
 // 3 planes (phi1, phi2, mu_r); psi' is one plane.  One work-item owns one node; a
 // wavefront covers 64 consecutive nodes of one row, so every load and store of a
 // plane is coalesced and wall rows are wave-uniform branches.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -304,15 +305,16 @@ void launch_init_droplet(T* dist, int nx, int ny, int pitch, double xc, double y
 }
 
 template <typename T>
-void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_phase<T>, grid2(P.nx, P.ny), dim3(BX, BY), 0, s, dist, phi, P);
+void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    // with events, the launch itself records the kernel's start and end (no host gap inside)
+    hipExtLaunchKernelGGL(k_phase<T>, grid2(P.nx, P.ny), dim3(BX, BY), 0, s, ev0, ev1, 0, dist, phi, P);
 }
 
 template <typename T>
 void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P,
-                           unsigned long long* div, hipStream_t s) {
-    hipLaunchKernelGGL(k_collide_stream<T>, dim3((P.nx + BX - 1) / BX, (P.ny + CY - 1) / CY), dim3(BX, CY), 0, s, src,
-                       dst, phi, psi, P, div);
+                           unsigned long long* div, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    hipExtLaunchKernelGGL(k_collide_stream<T>, dim3((P.nx + BX - 1) / BX, (P.ny + CY - 1) / CY), dim3(BX, CY), 0, s,
+                          ev0, ev1, 0, src, dst, phi, psi, P, div);
 }
 
 template <typename T>
@@ -351,9 +353,9 @@ void launch_diagnostics(const T* phi, const StepConst<T>& P, double* rows, doubl
                                         const double*, int, int, int, hipStream_t);                              \
     template void launch_init_droplet<T>(T*, int, int, int, double, double, double, double, double, double,     \
                                          hipStream_t);                                                           \
-    template void launch_phase<T>(const T*, T*, const StepConst<T>&, hipStream_t);                               \
+    template void launch_phase<T>(const T*, T*, const StepConst<T>&, hipStream_t, hipEvent_t, hipEvent_t);       \
     template void launch_collide_stream<T>(const T*, T*, const T*, const T*, const StepConst<T>&,                \
-                                           unsigned long long*, hipStream_t);                                    \
+                                           unsigned long long*, hipStream_t, hipEvent_t, hipEvent_t);            \
     template void launch_moments<T>(const T*, const T*, const T*, const StepConst<T>&, unsigned, double*,        \
                                     hipStream_t);                                                                \
     template void launch_to_dense<T>(const T*, double*, int, int, int, int, hipStream_t);                        \

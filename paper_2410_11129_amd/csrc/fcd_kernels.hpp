@@ -14,7 +14,9 @@ template <typename T>
 void launch_init_droplet(T* dist, int nx, int ny, int pitch, double xc, double yc, double rc, double rs, double xi,
                          double u_scale, hipStream_t s);
 template <typename T>
-void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s);
+// ev0 / ev1 (nullable): events the launch itself records at the kernel's start and end.
+void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s, hipEvent_t ev0 = nullptr,
+                  hipEvent_t ev1 = nullptr);
 // Potential solve (fcd_potential.hip).
 template <typename T>
 void launch_pot_sweep(const PotLevel<T>& L, T omega, hipStream_t s);
@@ -26,12 +28,14 @@ void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const Mu
 // One tile-smoother sweep uin -> uout (never the same buffer); prolong_from != nullptr
 // adds the prolongation of that coarse level's correction first.  mode 0: coarse level
 // (L.f), 1: finest level with the right-hand side from H0, 2: finest level with L.f.
-// res != nullptr: max |residual| and max |C u| of uin into res[0..1] (cleared first).
+// res != nullptr: max |residual| and max |C u| of uin into res[0..1], which must be zero:
+// with res_clear == nullptr a fill launch clears them first; otherwise the kernel itself
+// zeroes res_clear[0..1] (the next test's slot) and res must already be zero.
 // inner: sweeps on the tile before it is written back.  The coarse correction may be of
 // another type (TC) than the level's.
 template <typename T, typename TC>
 void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<TC>* prolong_from, int mode,
-                           unsigned long long* res, int inner, hipStream_t s);
+                           unsigned long long* res, int inner, hipStream_t s, unsigned long long* res_clear = nullptr);
 // Residual restriction by tiles from F (u = the smoothed iterate) into C (f, u = 0);
 // mode as for the tile smoother.
 template <typename T, typename TC>
@@ -53,7 +57,7 @@ template <typename T>
 void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, int mode, hipStream_t s);
 template <typename T>
 void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P,
-                           unsigned long long* div, hipStream_t s);
+                           unsigned long long* div, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_moments(const T* src, const T* phi, const T* psi, const StepConst<T>& P, unsigned mask, double* out,
                     hipStream_t s);

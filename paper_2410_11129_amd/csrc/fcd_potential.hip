@@ -276,8 +276,12 @@ __device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int
 template <typename T, typename G, bool PROLONG, int MODE, typename TC>
 __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
                                                           T* __restrict__ uout, PotLevel<TC> Cl,
-                                                          unsigned long long* __restrict__ res, int inner) {
+                                                          unsigned long long* __restrict__ res,
+                                                          unsigned long long* __restrict__ res_clear, int inner) {
     constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT, CX = G::CX, CY = G::CY;
+    // the next test's (other) residual slot, zeroed for it: the kernel boundary orders this
+    // store before that test's atomics, and the host has read that slot before this launch
+    if (res_clear && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) res_clear[threadIdx.x] = 0ULL;
     __shared__ T su[HY][HX];
     __shared__ T sm[HY][HX];
     __shared__ T sf[MODE == 1 ? 1 : SY][SX];
@@ -910,11 +914,12 @@ void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const Mu
 
 template <typename T, typename G, typename TC>
 void launch_smooth_geom(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<TC>* prolong_from, int mode,
-                        unsigned long long* res, int inner, hipStream_t s) {
+                        unsigned long long* res, unsigned long long* res_clear, int inner, hipStream_t s) {
     const dim3 g((L.nx + G::SX - 1) / G::SX, (L.ny + G::SY - 1) / G::SY);
     const PotLevel<TC> Cl = prolong_from ? *prolong_from : PotLevel<TC>{};
-#define FCD_TILE_LAUNCH(P, M) \
-    hipLaunchKernelGGL((k_mg_smooth_tile<T, G, P, M, TC>), g, dim3(G::NT), 0, s, L, uin, uout, Cl, res, inner)
+#define FCD_TILE_LAUNCH(P, M)                                                                                \
+    hipLaunchKernelGGL((k_mg_smooth_tile<T, G, P, M, TC>), g, dim3(G::NT), 0, s, L, uin, uout, Cl, res, res_clear, \
+                       inner)
     if (prolong_from) {
         if (mode == 0) FCD_TILE_LAUNCH(true, 0);
         else if (mode == 1) FCD_TILE_LAUNCH(true, 1);
@@ -930,12 +935,12 @@ void launch_smooth_geom(const PotLevel<T>& L, const T* uin, T* uout, const PotLe
 // Finest level (modes 1, 2): 64 x 16 tiles; coarser levels (mode 0): 32 x 8 tiles.
 template <typename T, typename TC>
 void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<TC>* prolong_from, int mode,
-                           unsigned long long* res, int inner, hipStream_t s) {
-    if (res) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, res, 2LL, 0ULL);
+                           unsigned long long* res, int inner, hipStream_t s, unsigned long long* res_clear) {
+    if (res && !res_clear) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, res, 2LL, 0ULL);
     if (mode == 0)
-        launch_smooth_geom<T, CoarseTile, TC>(L, uin, uout, prolong_from, mode, res, inner, s);
+        launch_smooth_geom<T, CoarseTile, TC>(L, uin, uout, prolong_from, mode, res, res_clear, inner, s);
     else
-        launch_smooth_geom<T, FineTile, TC>(L, uin, uout, prolong_from, mode, res, inner, s);
+        launch_smooth_geom<T, FineTile, TC>(L, uin, uout, prolong_from, mode, res, res_clear, inner, s);
 }
 
 template <typename T, typename TC>
@@ -995,7 +1000,7 @@ void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, in
 #define FCD_MG_INSTANTIATE(T, TC)                                                                             \
     template void launch_mg_restrict_mu4<T, TC>(const T*, int, int, int, const MuLevels<TC>&, hipStream_t);   \
     template void launch_mg_smooth_tile<T, TC>(const PotLevel<T>&, const T*, T*, const PotLevel<TC>*, int,    \
-                                               unsigned long long*, int, hipStream_t);                        \
+                                               unsigned long long*, int, hipStream_t, unsigned long long*);   \
     template void launch_mg_restrict_tile<T, TC>(const PotLevel<T>&, const PotLevel<TC>&, int, hipStream_t);  \
     template void launch_mg_restrict_smooth<T, TC>(const PotLevel<T>&, const PotLevel<TC>&, int, TC*, int,    \
                                                    hipStream_t);

@@ -129,3 +129,34 @@ def test_batch_adjoint_leaves_final_state():
     for k in range(len(ws)):
         assert np.array_equal(bt.state(k), s_fwd[k])
     bt.close()
+
+
+def test_fp64_gradient_is_ill_conditioned_at_the_batched_adjoint_horizon():
+    """Why the FP32 batched adjoint cannot meet 1e-3 at the stated 3000 steps: the FP64
+    single-channel gradient of the most field-driven 256 x 64 channel (Bo_m = 5.4) itself
+    moves by tens of percent when the initial state is perturbed by a random relative 6e-8
+    (the size of FP32 rounding), while over 300 steps it moves by ~1e-6: the trajectory
+    amplifies perturbations over the horizon, so no computation rounded at FP32's level can
+    reproduce the FP64 gradient there."""
+    w = adjoint_batch(steps=3000)[1]
+    say(f"case FP64 gradient conditioning, {w.name} Bo {w.bond:.2f}")
+
+    def grad(horizon, pert):
+        ch = Channel(w, tol=1e-10)
+        run = AdjointRun(ch, horizon, horizon // 20)
+        ch.init_droplet()
+        s = ch.state()
+        rng = np.random.default_rng(5)
+        ch.write_state(s * (1.0 + pert * rng.uniform(-1.0, 1.0, s.shape)))
+        fcd.fcd_adjoint_forward(ch.h, horizon, horizon // 20, run.work.data_ptr())
+        g = np.array(fcd.fcd_adjoint_backward(ch.h, [1.0, 0.0]))
+        ch.close()
+        return g
+
+    rel = {}
+    for horizon in (300, 3000):
+        g0, g1 = grad(horizon, 0.0), grad(horizon, 6e-8)
+        rel[horizon] = np.abs(g1[:2] - g0[:2]) / np.abs(g0[:2])
+        say(f"  {horizon} steps: dD_o/d(H0, alpha) {g0[:2]} relative change {rel[horizon]}")
+    assert rel[300].max() < 1e-4
+    assert rel[3000].max() > 3e-2
