@@ -28,10 +28,10 @@ METRIC = "MLUPS + HBM GB/s of coupled step; batched instances/hr; adjoint/forwar
 # two rocprofv3 counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the factors that a
 # 2 GiB device copy reads on the same counters), with the first 16 hex digits of the sha256
 # of the sources the kernel was built from; reported only while the sources are unchanged.
-TRAFFIC_BYTES = {"collide_stream": (2 * 129826 + 230388) * 1024}
-TRAFFIC_SOURCES = {"paper_2410_11129_amd/csrc/fcd_step.hpp": "137d66caf7a347bc",
-                   "paper_2410_11129_amd/csrc/fcd_device.hpp": "0d5dde1db5cae0f7",
-                   "paper_2410_11129_amd/csrc/fcd_kernels.hip": "56f5d6bde17a28c5"}
+TRAFFIC_BYTES = {"collide_stream": (2 * 129848 + 230388) * 1024}
+TRAFFIC_SOURCES = {"paper_2410_11129_amd/csrc/fcd_step.hpp": "0955c195fe226b4b",
+                   "paper_2410_11129_amd/csrc/fcd_device.hpp": "fedf834776d01323",
+                   "paper_2410_11129_amd/csrc/fcd_kernels.hip": "b646750e3bcf8da3"}
 
 
 def sources_match(table: dict) -> bool:
@@ -202,6 +202,43 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
             "speedup": round(batch_iph / seq_iph, 2) if seq_iph else None,
             "speedup_fp64_batch": round(len(ws) / (nsteps_target * dt_batch64) * 3600.0 / seq_iph, 2) if seq_iph else None,
             "sample": f"batch: {steps} timed steps; sequential: {seq_steps} timed steps per channel"}
+
+
+def regime_accuracy(torch, stride: int, steps: int) -> dict:
+    """Accuracy of the FP32 regime batch at the sweep's full horizon: every `stride`-th of the
+    64 regime channels run as one FP32 batch (tol 1e-5) and, one after another, as single
+    FP64 channels (tol 1e-10), `steps` steps each; D_o, D_i and max / mean |d phi| at the end
+    (the stated bars: 1e-3 on D, 1e-4 on phi).  Not part of the default run (minutes)."""
+    import numpy as np
+
+    from fcd_inputs import regime_sweep_batch
+    from paper_2410_11129_amd import fcd
+    from paper_2410_11129_amd.sim import Batch, Channel
+    ws = regime_sweep_batch(steps=steps)[::stride]
+    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
+    bt.init_droplets()
+    bt.step(steps)
+    d32 = bt.deformation()
+    rows = []
+    for k, w in enumerate(ws):
+        m32 = bt.moments(k, fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2)
+        ch = Channel(w, tol=1e-10)
+        ch.init_droplet()
+        ch.step(steps)
+        d64 = ch.deformation()
+        m64 = ch.moments(fcd.FCD_M_PHI1 | fcd.FCD_M_PHI2)
+        ch.close()
+        dphi = [np.abs(m32[q] - m64[q]) for q in ("phi1", "phi2")]
+        rows.append({"channel": w.name, "nx": w.nx, "ny": w.ny, "bond": round(w.bond, 3),
+                     "capillary": round(w.capillary, 4), "dD_o": float(f"{abs(d32[k][0] - d64[0]):.3e}"),
+                     "dD_i": float(f"{abs(d32[k][1] - d64[1]):.3e}"),
+                     "max_dphi": float(f"{max(d.max() for d in dphi):.3e}"),
+                     "mean_dphi": float(f"{max(d.mean() for d in dphi):.3e}")})
+        log(f"bench: regime accuracy {rows[-1]}")
+    bt.close()
+    return {"steps": steps, "channels": rows,
+            "max_dD": max(max(r["dD_o"], r["dD_i"]) for r in rows),
+            "max_dphi": max(r["max_dphi"] for r in rows), "max_mean_dphi": max(r["mean_dphi"] for r in rows)}
 
 
 def adjoint_ratio(torch, steps: int, every: int) -> dict:
@@ -418,6 +455,8 @@ def main() -> int:
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--sequential-steps", type=int, default=20)  # 0: no sequential comparator
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--regime-accuracy", type=int, default=0,
+                    help="also compare every N-th regime channel, FP32 batch against FP64 single, at 10k steps")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-ckpt", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -543,6 +582,8 @@ def main() -> int:
     if not args.no_batched:
         out["batched"] = batched_sweep(torch, args.batched_steps, args.sequential_steps)
         log(f"bench: batched {out['batched']}")
+    if args.regime_accuracy > 0:
+        out["regime_accuracy"] = regime_accuracy(torch, args.regime_accuracy, 10000)
     if not args.no_quasi_static:
         out["quasi_static"] = quasi_static(torch, args.quasi_static_steps)
         log(f"bench: quasi-static coupling {out['quasi_static']}")
