@@ -19,7 +19,9 @@
  * Parity status: every exported function below is pinned by a CPU test against
  * closed forms, invariants or brute force.  The long-run coupled trajectory of
  * orc_step as a whole has no value printed in the paper (parity unpinned for the
- * trajectory itself; each of its parts is pinned).
+ * trajectory itself; each of its parts is pinned).  The complex-step build (see the
+ * scalar type below) is the reference gradient of the adjoint; it is pinned against
+ * central differences of this real build and the exact zeros at H0 = 0.
  */
 #include <math.h>
 #include <stdint.h>
@@ -27,6 +29,49 @@
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* Scalar type.  The method's arithmetic is written over `real`, which is      */
+/* double in the oracle proper.  Built with ORC_COMPLEX_STEP, real is          */
+/* double _Complex: a parameter given a tiny imaginary part i h then carries   */
+/* h times its first derivative through every step, and dJ/dtheta =           */
+/* Im J(theta + i h) / h holds to rounding, with no difference of nearby      */
+/* values (complex-step differentiation: Squire and Trapp, SIAM Review 40,     */
+/* 1998; Martins, Sturdza and Alonso, ACM TOMS 29, 2003).  That requires every */
+/* operation on a real to be the analytic continuation of the real one:        */
+/* sums, products, quotients, sqrt, tanh, cos, sin are; comparisons and        */
+/* floor act on the real part (they select a branch, whose derivative is that  */
+/* of the branch); |x| is x times the sign of its real part; atan2 takes its   */
+/* first-order continuation, exact for h far below the rounding of the real    */
+/* part.  Lattice constants and the solver's settings stay double.            */
+/* ------------------------------------------------------------------------- */
+#ifdef ORC_COMPLEX_STEP
+#include <complex.h>
+typedef double _Complex real;
+#define RE(x) creal(x)
+#define r_sqrt csqrt
+#define r_tanh ctanh
+#define r_cos ccos
+#define r_sin csin
+static inline real r_abs(real x) { return creal(x) < 0.0 ? -x : x; }
+/* atan2(y, x) + i (x Im y - y Im x) / (x^2 + y^2) with x, y the real parts. */
+static inline real r_atan2(real y, real x) {
+    double a = creal(x), b = creal(y);
+    return atan2(b, a) + I * ((a * cimag(y) - b * cimag(x)) / (a * a + b * b));
+}
+/* magnitude for stop tests and maxima */
+static inline double r_mag(real x) { return cabs(x); }
+#else
+typedef double real;
+#define RE(x) (x)
+#define r_sqrt sqrt
+#define r_tanh tanh
+#define r_cos cos
+#define r_sin sin
+#define r_abs fabs
+#define r_atan2 atan2
+#define r_mag fabs
 #endif
 
 /* ------------------------------------------------------------------------- */
@@ -88,13 +133,13 @@ typedef struct {
     int32_t nx, ny;
     int32_t open_x; /* 0: periodic channel; 1: Eq. 37 inlet at i = 0, convective outlet at i = nx - 1 */
     int32_t pad1;
-    double rho[3], tau[3], chi[3]; /* phase 1 = core, 2 = shell, 3 = ambient   */
-    double sigma12, sigma13, sigma23, eta;
-    double xi, mobility;
-    double H0, alpha, mu0;
-    double drive_G, grav_x, grav_y;
-    double eps_n; /* n = grad phi / sqrt(|grad phi|^2 + eps_n^2); the paper leaves |grad phi| = 0 open */
-    double u_inlet; /* open channel: u_avg of Eq. 37 (the centreline value of the inlet profile) */
+    real rho[3], tau[3], chi[3]; /* phase 1 = core, 2 = shell, 3 = ambient   */
+    real sigma12, sigma13, sigma23, eta;
+    real xi, mobility;
+    real H0, alpha, mu0;
+    real drive_G, grav_x, grav_y;
+    real eps_n; /* n = grad phi / sqrt(|grad phi|^2 + eps_n^2); the paper leaves |grad phi| = 0 open */
+    real u_inlet; /* open channel: u_avg of Eq. 37 (the centreline value of the inlet profile) */
 } orc_params;
 
 typedef struct {
@@ -114,7 +159,7 @@ static inline int wrap(int i, int n) { return ((i % n) + n) % n; }
  * beyond the inlet and outlet take the value of the end column); rows outside the
  * channel take the value of the nearest row (reading: zero normal gradient of phi and
  * mu_r at the walls, i.e. neutral wetting; the paper names no wetting condition). */
-static inline double nb_mirror(const double* a, int nx, int ny, int i, int j, int dx, int dy, int clamp_x) {
+static inline real nb_mirror(const real* a, int nx, int ny, int i, int j, int dx, int dy, int clamp_x) {
     int ii = i + dx;
     if (clamp_x)
         ii = ii < 0 ? 0 : (ii > nx - 1 ? nx - 1 : ii);
@@ -130,8 +175,8 @@ static inline double nb_mirror(const double* a, int nx, int ny, int i, int j, in
  * unless ghost data are given (used only by the potential tests).  Reading: the paper
  * gives no boundary condition for psi; the applied potential psi0 is imposed in the
  * ghost rows, i.e. psi' = 0 there. */
-static inline double nb_psi(const double* a, int nx, int ny, int i, int j, int dx, int dy,
-                            const double* lo, const double* hi) {
+static inline real nb_psi(const real* a, int nx, int ny, int i, int j, int dx, int dy,
+                            const real* lo, const real* hi) {
     int ii = wrap(i + dx, nx);
     int jj = j + dy;
     if (jj < 0) return lo ? lo[ii] : 0.0;
@@ -145,39 +190,39 @@ static inline double nb_psi(const double* a, int nx, int ny, int i, int j, int d
 
 /* Gamma_alpha(u), Eq. 18.  Reading: the last term is -u.u/(2 c_s^2) (the printed
  * -u.u/c_s^2 would break sum_alpha Gamma_alpha = 1). */
-void orc_gamma(const double u[2], double out[NQ]) {
-    double uu = u[0] * u[0] + u[1] * u[1];
+void orc_gamma(const real u[2], real out[NQ]) {
+    real uu = u[0] * u[0] + u[1] * u[1];
     for (int a = 0; a < NQ; ++a) {
-        double eu = EX[a] * u[0] + EY[a] * u[1];
+        real eu = EX[a] * u[0] + EY[a] * u[1];
         out[a] = WQ[a] * (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
     }
 }
 
 /* f^eq_alpha = p* w_alpha + (Gamma_alpha - w_alpha), Eq. 16. */
-void orc_feq(double pstar, const double u[2], double out[NQ]) {
-    double G[NQ];
+void orc_feq(real pstar, const real u[2], real out[NQ]) {
+    real G[NQ];
     orc_gamma(u, G);
     for (int a = 0; a < NQ; ++a) out[a] = pstar * WQ[a] + (G[a] - WQ[a]);
 }
 
 /* F_alpha = w_alpha e_alpha . F_t / (rho c_s^2), Eq. 19. */
-void orc_forcing(const double Ft[2], double rho, double out[NQ]) {
+void orc_forcing(const real Ft[2], real rho, real out[NQ]) {
     for (int a = 0; a < NQ; ++a) out[a] = WQ[a] * (EX[a] * Ft[0] + EY[a] * Ft[1]) / (rho * CS2);
 }
 
 /* Apply M^{-1} Lambda M to a 9-vector; Lambda = diag(1,1,1,1,1,1,1,s_nu,s_nu) (Eq. 13). */
-static void mrt_apply(const double d[NQ], double s_nu, double out[NQ]) {
+static void mrt_apply(const real d[NQ], real s_nu, real out[NQ]) {
     if (!minv_ready) build_minv();
-    double m[NQ];
+    real m[NQ];
     for (int r = 0; r < NQ; ++r) {
-        double acc = 0.0;
+        real acc = 0.0;
         for (int c = 0; c < NQ; ++c) acc += MM[r][c] * d[c];
         m[r] = acc;
     }
     m[7] *= s_nu;
     m[8] *= s_nu;
     for (int r = 0; r < NQ; ++r) {
-        double acc = 0.0;
+        real acc = 0.0;
         for (int c = 0; c < NQ; ++c) acc += MINV[r][c] * m[c];
         out[r] = acc;
     }
@@ -185,13 +230,13 @@ static void mrt_apply(const double d[NQ], double s_nu, double out[NQ]) {
 
 /* MRT collision with forcing at one node, Eq. 12 with Eq. 15:
  * f* = f - M^{-1} Lambda M (f - fbar^eq) + F,  fbar^eq = f^eq(p*, u) - F/2. */
-void orc_collide_f(const double f[NQ], double pstar, const double u[2], const double Ft[2],
-                   double rho, double tau, double out[NQ]) {
-    double feq[NQ], F[NQ], d[NQ], r[NQ];
+void orc_collide_f(const real f[NQ], real pstar, const real u[2], const real Ft[2],
+                   real rho, real tau, real out[NQ]) {
+    real feq[NQ], F[NQ], d[NQ], r[NQ];
     orc_feq(pstar, u, feq);
     orc_forcing(Ft, rho, F);
     for (int a = 0; a < NQ; ++a) d[a] = f[a] - (feq[a] - 0.5 * F[a]);
-    double s_nu = 1.0 / (0.5 + tau); /* Eq. 13 */
+    real s_nu = 1.0 / (0.5 + tau); /* Eq. 13 */
     mrt_apply(d, s_nu, r);
     for (int a = 0; a < NQ; ++a) out[a] = f[a] - r[a] + F[a];
 }
@@ -219,7 +264,7 @@ void orc_lattice(int32_t ex[NQ], int32_t ey[NQ], double w[NQ]) {
 /* ------------------------------------------------------------------------- */
 
 /* gamma_i = sigma_ij + sigma_ik - sigma_jk (Eq. 27); 3/gamma_T = sum 1/gamma_i (Eq. 26). */
-static void spreading_coeffs(const orc_params* P, double gam[3], double* gT) {
+static void spreading_coeffs(const orc_params* P, real gam[3], real* gT) {
     gam[0] = P->sigma12 + P->sigma13 - P->sigma23;
     gam[1] = P->sigma12 + P->sigma23 - P->sigma13;
     gam[2] = P->sigma13 + P->sigma23 - P->sigma12;
@@ -227,10 +272,10 @@ static void spreading_coeffs(const orc_params* P, double gam[3], double* gT) {
 }
 
 /* Bulk free energy H(phi1, phi2, phi3), Eq. 28. */
-double orc_free_energy(const orc_params* P, const double ph[3]) {
-    double gam[3], gT;
+real orc_free_energy(const orc_params* P, const real ph[3]) {
+    real gam[3], gT;
     spreading_coeffs(P, gam, &gT);
-    double p1 = ph[0], p2 = ph[1], p3 = ph[2];
+    real p1 = ph[0], p2 = ph[1], p3 = ph[2];
     return P->sigma12 * p1 * p1 * p2 * p2 + P->sigma13 * p1 * p1 * p3 * p3 +
            P->sigma23 * p2 * p2 * p3 * p3 +
            p1 * p2 * p3 * (gam[0] * p1 + gam[1] * p2 + gam[2] * p3) +
@@ -239,11 +284,11 @@ double orc_free_energy(const orc_params* P, const double ph[3]) {
 
 /* Partial derivatives dH/dphi_k of Eq. 28 with the three phi treated as
  * independent variables. */
-void orc_free_energy_grad(const orc_params* P, const double ph[3], double dH[3]) {
-    double gam[3], gT;
+void orc_free_energy_grad(const orc_params* P, const real ph[3], real dH[3]) {
+    real gam[3], gT;
     spreading_coeffs(P, gam, &gT);
-    double p1 = ph[0], p2 = ph[1], p3 = ph[2];
-    double s12 = P->sigma12, s13 = P->sigma13, s23 = P->sigma23, eta = P->eta;
+    real p1 = ph[0], p2 = ph[1], p3 = ph[2];
+    real s12 = P->sigma12, s13 = P->sigma13, s23 = P->sigma23, eta = P->eta;
     dH[0] = 2.0 * s12 * p1 * p2 * p2 + 2.0 * s13 * p1 * p3 * p3 +
             p2 * p3 * (gam[0] * p1 + gam[1] * p2 + gam[2] * p3) + p1 * p2 * p3 * gam[0] +
             2.0 * eta * p1 * p2 * p2 * p3 * p3;
@@ -258,12 +303,12 @@ void orc_free_energy_grad(const orc_params* P, const double ph[3], double dH[3])
 /* Chemical potentials, Eq. 25.  Reading: the "gamma_t" of the Laplacian term is
  * gamma_i, as in the Boyer-Lapuerta form the paper cites (equal to gamma_T when the
  * three surface tensions are equal). */
-void orc_chem_potential(const orc_params* P, const double ph[3], const double lap[3], double mu[3]) {
-    double gam[3], gT, dH[3];
+void orc_chem_potential(const orc_params* P, const real ph[3], const real lap[3], real mu[3]) {
+    real gam[3], gT, dH[3];
     spreading_coeffs(P, gam, &gT);
     orc_free_energy_grad(P, ph, dH);
     for (int k = 0; k < 3; ++k) {
-        double s = 0.0;
+        real s = 0.0;
         for (int j = 0; j < 3; ++j)
             if (j != k) s += (dH[k] - dH[j]) / gam[j];
         mu[k] = 4.0 * gT / P->xi * s - 0.75 * P->xi * gam[k] * lap[k];
@@ -275,11 +320,11 @@ void orc_chem_potential(const orc_params* P, const double ph[3], const double la
 /* ------------------------------------------------------------------------- */
 
 /* phi_i = sum_alpha g^i_alpha (Eq. 32). */
-static void phase_from_g(int nx, int ny, const double* g, double* phi) {
+static void phase_from_g(int nx, int ny, const real* g, real* phi) {
     size_t n = (size_t)nx * ny;
 #pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
-        double s = 0.0;
+        real s = 0.0;
         for (int a = 0; a < NQ; ++a) s += g[a * n + k];
         phi[k] = s;
     }
@@ -287,20 +332,20 @@ static void phase_from_g(int nx, int ny, const double* g, double* phi) {
 
 /* mu_r = 1 + chi with 1/(1+chi) = sum_i phi_i/(1+chi_i): Eq. 8 read with the index
  * on chi that the printed formula drops (harmonic mean, as the text says). */
-static void mu_r_from_phi(const orc_params* P, const double* phi1, const double* phi2, double* mur) {
+static void mu_r_from_phi(const orc_params* P, const real* phi1, const real* phi2, real* mur) {
     size_t n = (size_t)P->nx * P->ny;
     for (size_t k = 0; k < n; ++k) {
-        double p3 = 1.0 - phi1[k] - phi2[k];
-        double s = phi1[k] / (1.0 + P->chi[0]) + phi2[k] / (1.0 + P->chi[1]) + p3 / (1.0 + P->chi[2]);
+        real p3 = 1.0 - phi1[k] - phi2[k];
+        real s = phi1[k] / (1.0 + P->chi[0]) + phi2[k] / (1.0 + P->chi[1]) + p3 / (1.0 + P->chi[2]);
         mur[k] = 1.0 / s;
     }
 }
 
 /* Isotropic gradient, Eq. 34: grad a = (1/c_s^2) sum_alpha w_alpha e_alpha a(x + e_alpha). */
-static void iso_grad(const double* a, int nx, int ny, int i, int j, int clamp_x, double g[2]) {
-    double gx = 0.0, gy = 0.0;
+static void iso_grad(const real* a, int nx, int ny, int i, int j, int clamp_x, real g[2]) {
+    real gx = 0.0, gy = 0.0;
     for (int q = 0; q < NQ; ++q) {
-        double v = nb_mirror(a, nx, ny, i, j, EX[q], EY[q], clamp_x);
+        real v = nb_mirror(a, nx, ny, i, j, EX[q], EY[q], clamp_x);
         gx += WQ[q] * EX[q] * v;
         gy += WQ[q] * EY[q] * v;
     }
@@ -309,9 +354,9 @@ static void iso_grad(const double* a, int nx, int ny, int i, int j, int clamp_x,
 }
 
 /* Isotropic Laplacian, Eq. 35: lap a = (2/c_s^2) sum_alpha w_alpha [a(x+e_alpha) - a(x)]. */
-static double iso_lap(const double* a, int nx, int ny, int i, int j, int clamp_x) {
-    double c = a[IDX(i, j, nx)];
-    double s = 0.0;
+static real iso_lap(const real* a, int nx, int ny, int i, int j, int clamp_x) {
+    real c = a[IDX(i, j, nx)];
+    real s = 0.0;
     for (int q = 0; q < NQ; ++q) s += WQ[q] * (nb_mirror(a, nx, ny, i, j, EX[q], EY[q], clamp_x) - c);
     return 2.0 * s / CS2;
 }
@@ -319,11 +364,11 @@ static double iso_lap(const double* a, int nx, int ny, int i, int j, int clamp_x
 /* Interface normals and the counter-diffusion magnitude of Eq. 23 for the three
  * phases: n_k = grad phi_k / sqrt(|grad phi_k|^2 + eps_n^2) (reading: the paper leaves
  * n undefined where grad phi vanishes), theta_k = (4/xi) phi_k (1 - phi_k). */
-static void interface_terms(const orc_params* P, const double* phi, const double (*gphi)[2], double* theta,
-                            double (*nrm)[2]) {
+static void interface_terms(const orc_params* P, const real* phi, const real (*gphi)[2], real* theta,
+                            real (*nrm)[2]) {
     for (int s = 0; s < 3; ++s) {
-        double gx = gphi[s][0], gy = gphi[s][1];
-        double nn = sqrt(gx * gx + gy * gy + P->eps_n * P->eps_n);
+        real gx = gphi[s][0], gy = gphi[s][1];
+        real nn = r_sqrt(gx * gx + gy * gy + P->eps_n * P->eps_n);
         nrm[s][0] = gx / nn;
         nrm[s][1] = gy / nn;
         theta[s] = 4.0 / P->xi * phi[s] * (1.0 - phi[s]);
@@ -337,37 +382,37 @@ static void interface_terms(const orc_params* P, const double* phi, const double
  * the inner sum over all three phases (Eq. 23 with its reused index read as a sum over
  * k), so that the three right-hand sides of Eq. 23 add up to zero as phi_1 + phi_2 +
  * phi_3 = 1 requires. */
-static void phase_source(const double theta[3], const double nrm[3][2], int comp, double F[NQ]) {
-    double sx = 0.0, sy = 0.0;
+static void phase_source(const real theta[3], const real nrm[3][2], int comp, real F[NQ]) {
+    real sx = 0.0, sy = 0.0;
     for (int s = 0; s < 3; ++s) {
         sx += theta[s] * nrm[s][0];
         sy += theta[s] * nrm[s][1];
     }
-    double vx = theta[comp] * nrm[comp][0] - sx / 3.0;
-    double vy = theta[comp] * nrm[comp][1] - sy / 3.0;
+    real vx = theta[comp] * nrm[comp][0] - sx / 3.0;
+    real vy = theta[comp] * nrm[comp][1] - sy / 3.0;
     for (int a = 0; a < NQ; ++a) F[a] = WQ[a] * (EX[a] * vx + EY[a] * vy);
 }
 
 /* Exported for the tests: the sources of all three components at one node from phi_k and
  * grad phi_k (k = 1..3), out[k * 9 + alpha]. */
-void orc_phase_source(const orc_params* P, const double phi[3], const double gphi[6], double out[3 * NQ]) {
-    double g[3][2] = {{gphi[0], gphi[1]}, {gphi[2], gphi[3]}, {gphi[4], gphi[5]}};
-    double theta[3], nrm[3][2];
+void orc_phase_source(const orc_params* P, const real phi[3], const real gphi[6], real out[3 * NQ]) {
+    real g[3][2] = {{gphi[0], gphi[1]}, {gphi[2], gphi[3]}, {gphi[4], gphi[5]}};
+    real theta[3], nrm[3][2];
     interface_terms(P, phi, g, theta, nrm);
     for (int c = 0; c < 3; ++c) phase_source(theta, nrm, c, out + c * NQ);
 }
 
 /* Everything the collision at one node needs. */
 typedef struct {
-    double phi[3], gphi[3][2], lphi[3], nrm[3][2], theta[3];
-    double rho, tau, grho[2], gchi[2], mu[3];
-    double Fs[2], H[2], Fm[2], Fp[2], Fd[2], Fb[2], Fmu[2], Ft[2];
-    double pstar, u0[2], u[2];
+    real phi[3], gphi[3][2], lphi[3], nrm[3][2], theta[3];
+    real rho, tau, grho[2], gchi[2], mu[3];
+    real Fs[2], H[2], Fm[2], Fp[2], Fd[2], Fb[2], Fmu[2], Ft[2];
+    real pstar, u0[2], u[2];
 } nodeq;
 
 /* Stencils, forces and velocity at node (i, j) given phi planes, psi' and the local f. */
-static void node_quantities(const orc_params* P, const double* phi1, const double* phi2,
-                            const double* psi, const double* fnode, int i, int j, nodeq* q) {
+static void node_quantities(const orc_params* P, const real* phi1, const real* phi2,
+                            const real* psi, const real* fnode, int i, int j, nodeq* q) {
     int nx = P->nx, ny = P->ny;
     size_t k = IDX(i, j, nx);
     /* Phase fields, Eq. 24; gradients and Laplacians, Eq. 34-35; those of phi_3 follow
@@ -397,7 +442,7 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
         q->grho[1] += P->rho[s] * q->gphi[s][1];
     }
     /* Eq. 9: grad chi = -[sum grad phi_i/(1+chi_i)] / [sum phi_i/(1+chi_i)]^2. */
-    double S = 0.0, gS[2] = {0.0, 0.0};
+    real S = 0.0, gS[2] = {0.0, 0.0};
     for (int s = 0; s < 3; ++s) {
         S += q->phi[s] / (1.0 + P->chi[s]);
         gS[0] += q->gphi[s][0] / (1.0 + P->chi[s]);
@@ -414,21 +459,21 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
     }
     /* H = -grad(psi0 + psi') = H0 (cos a, sin a) - grad psi' (Eq. 5 with the Eq. 34
      * stencil); Kelvin force, Eq. 7, with mu0 in lattice units. */
-    double gpx = 0.0, gpy = 0.0;
+    real gpx = 0.0, gpy = 0.0;
     for (int a = 0; a < NQ; ++a) {
-        double v = nb_psi(psi, nx, ny, i, j, EX[a], EY[a], NULL, NULL);
+        real v = nb_psi(psi, nx, ny, i, j, EX[a], EY[a], NULL, NULL);
         gpx += WQ[a] * EX[a] * v;
         gpy += WQ[a] * EY[a] * v;
     }
-    q->H[0] = P->H0 * cos(P->alpha) - gpx / CS2;
-    q->H[1] = P->H0 * sin(P->alpha) - gpy / CS2;
-    double H2 = q->H[0] * q->H[0] + q->H[1] * q->H[1];
+    q->H[0] = P->H0 * r_cos(P->alpha) - gpx / CS2;
+    q->H[1] = P->H0 * r_sin(P->alpha) - gpy / CS2;
+    real H2 = q->H[0] * q->H[0] + q->H[1] * q->H[1];
     q->Fm[0] = -0.5 * P->mu0 * H2 * q->gchi[0];
     q->Fm[1] = -0.5 * P->mu0 * H2 * q->gchi[1];
     /* Pressure (Eq. 21), pressure force F_p = -(p/rho) grad rho = -p* c_s^2 grad rho,
      * gravity F_b = rho g.  Reading: the pressure-driven flow of the periodic channel is
      * driven by a uniform force density drive_G along x. */
-    double ps = 0.0, jx = 0.0, jy = 0.0;
+    real ps = 0.0, jx = 0.0, jy = 0.0;
     size_t n = (size_t)nx * ny;
     (void)n;
     for (int a = 0; a < NQ; ++a) {
@@ -443,7 +488,7 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
     q->Fd[1] = 0.0;
     q->Fb[0] = q->rho * P->grav_x;
     q->Fb[1] = q->rho * P->grav_y;
-    double F0[2];
+    real F0[2];
     for (int c = 0; c < 2; ++c) F0[c] = q->Fs[c] + q->Fp[c] + q->Fm[c] + q->Fd[c] + q->Fb[c];
     /* Eq. 22 without the viscous force.  Reading: F_mu needs grad u, which needs u;
      * the viscous force is taken from the local non-equilibrium stress instead, as in
@@ -453,17 +498,17 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
     /* Viscous force from the non-equilibrium stress:
      * Pi_ij = sum_b e_bi e_bj [M^-1 Lambda M (f - f^eq(p*, u0))]_b,
      * F_mu,i = -(nu / c_s^2) Pi_ij d_j rho, with nu = c_s^2 tau (Eq. 14). */
-    double feq0[NQ], d[NQ], r[NQ];
+    real feq0[NQ], d[NQ], r[NQ];
     orc_feq(ps, q->u0, feq0);
     for (int a = 0; a < NQ; ++a) d[a] = fnode[a] - feq0[a];
     mrt_apply(d, 1.0 / (0.5 + q->tau), r);
-    double Pxx = 0.0, Pxy = 0.0, Pyy = 0.0;
+    real Pxx = 0.0, Pxy = 0.0, Pyy = 0.0;
     for (int a = 0; a < NQ; ++a) {
         Pxx += EX[a] * EX[a] * r[a];
         Pxy += EX[a] * EY[a] * r[a];
         Pyy += EY[a] * EY[a] * r[a];
     }
-    double nu = CS2 * q->tau;
+    real nu = CS2 * q->tau;
     q->Fmu[0] = -(nu / CS2) * (Pxx * q->grho[0] + Pxy * q->grho[1]);
     q->Fmu[1] = -(nu / CS2) * (Pxy * q->grho[0] + Pyy * q->grho[1]);
     for (int c = 0; c < 2; ++c) q->Ft[c] = F0[c] + q->Fmu[c];
@@ -474,13 +519,13 @@ static void node_quantities(const orc_params* P, const double* phi1, const doubl
 
 /* Phase-field collision, Eq. 29-31, with the source term of phase_source.  phi in
  * Eq. 31 is phi_i and Gamma uses the final velocity of the step. */
-static void collide_g(const orc_params* P, const nodeq* q, int comp, const double g[NQ], double out[NQ]) {
-    double Gm[NQ], Fphi[NQ];
+static void collide_g(const orc_params* P, const nodeq* q, int comp, const real g[NQ], real out[NQ]) {
+    real Gm[NQ], Fphi[NQ];
     orc_gamma(q->u, Gm);
     phase_source(q->theta, q->nrm, comp, Fphi);
-    double tau_phi = P->mobility / CS2; /* Eq. 30, its "c_s^s" read as c_s^2 */
+    real tau_phi = P->mobility / CS2; /* Eq. 30, its "c_s^s" read as c_s^2 */
     for (int a = 0; a < NQ; ++a) {
-        double geq = q->phi[comp] * Gm[a] - 0.5 * Fphi[a]; /* Eq. 31 */
+        real geq = q->phi[comp] * Gm[a] - 0.5 * Fphi[a]; /* Eq. 31 */
         out[a] = g[a] - (g[a] - geq) / (0.5 + tau_phi) + Fphi[a];
     }
 }
@@ -498,25 +543,26 @@ static void collide_g(const orc_params* P, const nodeq* q, int comp, const doubl
  * field and decays away from it, so the periodic closure is kept there).  The equation L(psi0 + psi') = 0 reads
  *   sum_a c_a (psi'(x+e_a) - psi'(x)) = H0 sum_a c_a (e_a . h),   c_a = 3 w_a (mu + mu_a). */
 
-static inline double coef(const double* mur, int nx, int ny, int i, int j, int a) {
+static inline real coef(const real* mur, int nx, int ny, int i, int j, int a) {
     return (WQ[a] / CS2) * (mur[IDX(i, j, nx)] + nb_mirror(mur, nx, ny, i, j, EX[a], EY[a], 0));
 }
 
 /* Residual r = L(psi0 + psi') at every node; returns max |r|. */
-static double potential_residual(int nx, int ny, const double* mur, double H0, double alpha,
-                                 const double* psi, const double* lo, const double* hi, double* r) {
-    double hx = cos(alpha), hy = sin(alpha), mx = 0.0;
+static double potential_residual(int nx, int ny, const real* mur, real H0, real alpha,
+                                   const real* psi, const real* lo, const real* hi, real* r) {
+    real hx = r_cos(alpha), hy = r_sin(alpha);
+    double mx = 0.0;
 #pragma omp parallel for schedule(static) reduction(max : mx)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            double c0 = psi[IDX(i, j, nx)], acc = 0.0;
+            real c0 = psi[IDX(i, j, nx)], acc = 0.0;
             for (int a = 1; a < NQ; ++a) {
-                double c = coef(mur, nx, ny, i, j, a);
+                real c = coef(mur, nx, ny, i, j, a);
                 acc += c * (nb_psi(psi, nx, ny, i, j, EX[a], EY[a], lo, hi) - c0);
                 acc -= H0 * c * (EX[a] * hx + EY[a] * hy);
             }
             if (r) r[IDX(i, j, nx)] = acc;
-            if (fabs(acc) > mx) mx = fabs(acc);
+            if (r_mag(acc) > mx) mx = r_mag(acc);
         }
     return mx;
 }
@@ -525,12 +571,12 @@ static double potential_residual(int nx, int ny, const double* mur, double H0, d
 static inline int fold(int i, int nx) { return i < nx / 2 ? 2 * i : 2 * (nx - 1 - i) + 1; }
 
 /* Exact solve of -L psi' = -H0 sum c (e.h) (+ ghost data) by banded Cholesky. */
-static int potential_direct(int nx, int ny, const double* mur, double H0, double alpha, double* psi,
-                            const double* lo, const double* hi) {
+static int potential_direct(int nx, int ny, const real* mur, real H0, real alpha, real* psi,
+                            const real* lo, const real* hi) {
     size_t n = (size_t)nx * ny;
     int bw = 2 * ny + 1; /* half bandwidth under the folded ordering */
-    double* L = (double*)calloc(n * (size_t)(bw + 1), sizeof(double));
-    double* b = (double*)calloc(n, sizeof(double));
+    real* L = (real*)calloc(n * (size_t)(bw + 1), sizeof(real));
+    real* b = (real*)calloc(n, sizeof(real));
     int* inv = (int*)malloc(n * sizeof(int)); /* ordered index -> plane index */
     if (!L || !b || !inv) {
         free(L);
@@ -538,20 +584,20 @@ static int potential_direct(int nx, int ny, const double* mur, double H0, double
         free(inv);
         return -3;
     }
-    double hx = cos(alpha), hy = sin(alpha);
+    real hx = r_cos(alpha), hy = r_sin(alpha);
     /* Assemble A = -L (lower band, row-wise: L[k*(bw+1) + (k-m)] = A[k][m]) and b. */
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t k = (size_t)fold(i, nx) * ny + j;
             inv[k] = (int)IDX(i, j, nx);
-            double diag = 0.0, rhs = 0.0;
+            real diag = 0.0, rhs = 0.0;
             for (int a = 1; a < NQ; ++a) {
-                double c = coef(mur, nx, ny, i, j, a);
+                real c = coef(mur, nx, ny, i, j, a);
                 diag += c;
                 rhs -= H0 * c * (EX[a] * hx + EY[a] * hy);
                 int jj = j + EY[a];
                 if (jj < 0 || jj > ny - 1) {
-                    double gv = jj < 0 ? (lo ? lo[wrap(i + EX[a], nx)] : 0.0)
+                    real gv = jj < 0 ? (lo ? lo[wrap(i + EX[a], nx)] : 0.0)
                                        : (hi ? hi[wrap(i + EX[a], nx)] : 0.0);
                     rhs += c * gv;
                     continue;
@@ -568,16 +614,16 @@ static int potential_direct(int nx, int ny, const double* mur, double H0, double
         for (size_t m = lo_k; m <= k; ++m) {
             size_t lo_m = m > (size_t)bw ? m - bw : 0;
             size_t start = lo_k > lo_m ? lo_k : lo_m;
-            double s = L[k * (bw + 1) + (k - m)];
+            real s = L[k * (bw + 1) + (k - m)];
             for (size_t p = start; p < m; ++p) s -= L[k * (bw + 1) + (k - p)] * L[m * (bw + 1) + (m - p)];
             if (m == k) {
-                if (s <= 0.0) {
+                if (RE(s) <= 0.0) {
                     free(L);
                     free(b);
                     free(inv);
                     return -5;
                 }
-                L[k * (bw + 1)] = sqrt(s);
+                L[k * (bw + 1)] = r_sqrt(s);
             } else {
                 L[k * (bw + 1) + (k - m)] = s / L[m * (bw + 1)];
             }
@@ -586,13 +632,13 @@ static int potential_direct(int nx, int ny, const double* mur, double H0, double
     /* Forward substitution C y = b. */
     for (size_t k = 0; k < n; ++k) {
         size_t lo_k = k > (size_t)bw ? k - bw : 0;
-        double s = b[k];
+        real s = b[k];
         for (size_t p = lo_k; p < k; ++p) s -= L[k * (bw + 1) + (k - p)] * b[p];
         b[k] = s / L[k * (bw + 1)];
     }
     /* Back substitution C^T x = y. */
     for (size_t kk = n; kk-- > 0;) {
-        double s = b[kk];
+        real s = b[kk];
         size_t hi_k = kk + bw < n - 1 ? kk + bw : n - 1;
         for (size_t p = kk + 1; p <= hi_k; ++p) s -= L[p * (bw + 1) + (p - kk)] * b[p];
         b[kk] = s / L[kk * (bw + 1)];
@@ -607,10 +653,10 @@ static int potential_direct(int nx, int ny, const double* mur, double H0, double
 /* Four-colour SOR: colour (i mod 2) + 2 (j mod 2), colours in the order 0, 1, 2, 3;
  * nodes of one colour never neighbour each other (nx even), so their order within a
  * colour does not matter.  Warm-started from the psi' passed in. */
-static int potential_sor(int nx, int ny, const double* mur, double H0, double alpha, double* psi,
+static int potential_sor(int nx, int ny, const real* mur, real H0, real alpha, real* psi,
                          const orc_solver* S, int* sweeps, double* resid) {
-    double hx = cos(alpha), hy = sin(alpha);
-    double thr = S->tol * H0;
+    real hx = r_cos(alpha), hy = r_sin(alpha);
+    double thr = S->tol * RE(H0);
     int every = S->check_every > 0 ? S->check_every : 1;
     int sw = 0;
     double rmax = potential_residual(nx, ny, mur, H0, alpha, psi, NULL, NULL, NULL);
@@ -619,15 +665,15 @@ static int potential_sor(int nx, int ny, const double* mur, double H0, double al
 #pragma omp parallel for schedule(static)
             for (int j = colour / 2; j < ny; j += 2)
                 for (int i = colour % 2; i < nx; i += 2) {
-                    double C = 0.0, acc = 0.0;
+                    real C = 0.0, acc = 0.0;
                     for (int a = 1; a < NQ; ++a) {
-                        double c = coef(mur, nx, ny, i, j, a);
+                        real c = coef(mur, nx, ny, i, j, a);
                         C += c;
                         acc += c * nb_psi(psi, nx, ny, i, j, EX[a], EY[a], NULL, NULL);
                         acc -= H0 * c * (EX[a] * hx + EY[a] * hy);
                     }
-                    double gs = acc / C;
-                    double* p = &psi[IDX(i, j, nx)];
+                    real gs = acc / C;
+                    real* p = &psi[IDX(i, j, nx)];
                     *p += S->omega * (gs - *p);
                 }
         ++sw;
@@ -639,12 +685,12 @@ static int potential_sor(int nx, int ny, const double* mur, double H0, double al
     return rmax <= thr ? 0 : -5;
 }
 
-static int solve_mu(const orc_params* P, const double* mur, const orc_solver* S, double* psi,
-                    const double* lo, const double* hi, int* sweeps, double* resid) {
+static int solve_mu(const orc_params* P, const real* mur, const orc_solver* S, real* psi,
+                    const real* lo, const real* hi, int* sweeps, double* resid) {
     int nx = P->nx, ny = P->ny;
     if (sweeps) *sweeps = 0;
     if (P->H0 == 0.0 && !lo && !hi) { /* no field: psi' = 0 exactly */
-        memset(psi, 0, sizeof(double) * (size_t)nx * ny);
+        memset(psi, 0, sizeof(real) * (size_t)nx * ny);
         if (resid) *resid = 0.0;
         return 0;
     }
@@ -660,11 +706,11 @@ static int solve_mu(const orc_params* P, const double* mur, const orc_solver* S,
 }
 
 /* Exported: solve for psi' given phi1, phi2 planes (ghost data optional). */
-int orc_solve_potential_phi(const orc_params* P, const double* phi1, const double* phi2,
-                            const orc_solver* S, double* psi, const double* ghost_lo,
-                            const double* ghost_hi, int32_t* sweeps, double* resid) {
+int orc_solve_potential_phi(const orc_params* P, const real* phi1, const real* phi2,
+                            const orc_solver* S, real* psi, const real* ghost_lo,
+                            const real* ghost_hi, int32_t* sweeps, double* resid) {
     size_t n = (size_t)P->nx * P->ny;
-    double* mur = (double*)malloc(n * sizeof(double));
+    real* mur = (real*)malloc(n * sizeof(real));
     if (!mur) return -3;
     mu_r_from_phi(P, phi1, phi2, mur);
     int sw = 0;
@@ -675,10 +721,10 @@ int orc_solve_potential_phi(const orc_params* P, const double* phi1, const doubl
 }
 
 /* Exported: residual max |L(psi0+psi')| for given phi planes and psi'. */
-double orc_potential_residual_phi(const orc_params* P, const double* phi1, const double* phi2,
-                                  const double* psi, double* r_out) {
+double orc_potential_residual_phi(const orc_params* P, const real* phi1, const real* phi2,
+                                  const real* psi, real* r_out) {
     size_t n = (size_t)P->nx * P->ny;
-    double* mur = (double*)malloc(n * sizeof(double));
+    real* mur = (real*)malloc(n * sizeof(real));
     if (!mur) return -1.0;
     mu_r_from_phi(P, phi1, phi2, mur);
     double m = potential_residual(P->nx, P->ny, mur, P->H0, P->alpha, psi, NULL, NULL, r_out);
@@ -687,11 +733,11 @@ double orc_potential_residual_phi(const orc_params* P, const double* phi1, const
 }
 
 /* Exported: apply the discrete operator L_mu (without psi0) to u; ghost rows of u are 0. */
-void orc_apply_L(const orc_params* P, const double* mur, const double* u, double* out) {
+void orc_apply_L(const orc_params* P, const real* mur, const real* u, real* out) {
     int nx = P->nx, ny = P->ny;
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            double c0 = u[IDX(i, j, nx)], acc = 0.0;
+            real c0 = u[IDX(i, j, nx)], acc = 0.0;
             for (int a = 1; a < NQ; ++a)
                 acc += coef(mur, nx, ny, i, j, a) * (nb_psi(u, nx, ny, i, j, EX[a], EY[a], NULL, NULL) - c0);
             out[IDX(i, j, nx)] = acc;
@@ -704,11 +750,11 @@ void orc_apply_L(const orc_params* P, const double* mur, const double* u, double
 /* ------------------------------------------------------------------------- */
 
 /* f = f^eq(p*, u), g^i = phi_i Gamma(u). */
-int orc_init_fields(const orc_params* P, const double* phi1, const double* phi2, const double* ux,
-                    const double* uy, const double* pstar, double* f, double* g1, double* g2) {
+int orc_init_fields(const orc_params* P, const real* phi1, const real* phi2, const real* ux,
+                    const real* uy, const real* pstar, real* f, real* g1, real* g2) {
     size_t n = (size_t)P->nx * P->ny;
     for (size_t k = 0; k < n; ++k) {
-        double u[2] = {ux[k], uy[k]}, fe[NQ], G[NQ];
+        real u[2] = {ux[k], uy[k]}, fe[NQ], G[NQ];
         orc_feq(pstar ? pstar[k] : 0.0, u, fe);
         orc_gamma(u, G);
         for (int a = 0; a < NQ; ++a) {
@@ -723,8 +769,8 @@ int orc_init_fields(const orc_params* P, const double* phi1, const double* phi2,
 /* Eq. 37: inlet velocity u_avg 4 (y/H)(1 - y/H) with the walls at y = 0 and y = H = ny,
  * i.e. y = j + 1/2 at row j.  Reading: taken as printed, so u_avg is the centreline value
  * and the mean over the section is (2/3) u_avg. */
-static double inlet_u(const orc_params* P, int j) {
-    double s = (j + 0.5) / P->ny;
+static real inlet_u(const orc_params* P, int j) {
+    real s = (j + 0.5) / P->ny;
     return 4.0 * P->u_inlet * s * (1.0 - s);
 }
 
@@ -732,25 +778,25 @@ static double inlet_u(const orc_params* P, int j) {
  * in the open channel); ambient velocity: the Poiseuille profile under the drive, or the
  * Eq. 37 profile in every column of the open channel; p* = 0. Writes phi1, phi2 too. */
 int orc_init_droplet(const orc_params* P, double xc, double yc, double r_core, double r_shell,
-                     double* f, double* g1, double* g2, double* phi1, double* phi2) {
+                     real* f, real* g1, real* g2, real* phi1, real* phi2) {
     int nx = P->nx, ny = P->ny;
     size_t n = (size_t)nx * ny;
-    double* ux = (double*)malloc(n * sizeof(double));
-    double* uy = (double*)calloc(n, sizeof(double));
+    real* ux = (real*)malloc(n * sizeof(real));
+    real* uy = (real*)calloc(n, sizeof(real));
     if (!ux || !uy) {
         free(ux);
         free(uy);
         return -3;
     }
-    double nu3 = CS2 * P->tau[2];
+    real nu3 = CS2 * P->tau[2];
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             double dx = (double)i - xc;
             if (!P->open_x) dx -= nx * floor(dx / nx + 0.5);
             double dy = (double)j - yc;
             double d = sqrt(dx * dx + dy * dy);
-            double pin = 0.5 * (1.0 + tanh(2.0 * (r_core - d) / P->xi));
-            double pout = 0.5 * (1.0 + tanh(2.0 * (r_shell - d) / P->xi));
+            real pin = 0.5 * (1.0 + r_tanh(2.0 * (r_core - d) / P->xi));
+            real pout = 0.5 * (1.0 + r_tanh(2.0 * (r_shell - d) / P->xi));
             phi1[IDX(i, j, nx)] = pin;
             phi2[IDX(i, j, nx)] = pout - pin;
             ux[IDX(i, j, nx)] = P->open_x ? inlet_u(P, j)
@@ -777,22 +823,22 @@ int orc_init_droplet(const orc_params* P, double xc, double yc, double r_core, d
  * d f/dt + U d f/dx = 0 discretised as f(t+1, N) = [f(t, N) + U f(t+1, N-1)] / (1 + U)
  * for f, g1 and g2.  Reading: U, which the paper does not give, is the mean inlet
  * velocity over the section (by continuity the mean outflow velocity). */
-static void open_boundaries(const orc_params* P, const double* out_old, double* f, double* g1, double* g2) {
+static void open_boundaries(const orc_params* P, const real* out_old, real* f, real* g1, real* g2) {
     int nx = P->nx, ny = P->ny;
     size_t n = (size_t)nx * ny;
-    double U = 0.0;
+    real U = 0.0;
     for (int j = 0; j < ny; ++j) U += inlet_u(P, j);
     U /= ny;
-    const double phi_in[2] = {0.0, 0.0};
+    const real phi_in[2] = {0.0, 0.0};
     for (int j = 0; j < ny; ++j) {
         /* inlet */
         size_t k = IDX(0, j, nx);
-        double ux = inlet_u(P, j), uy = 0.0;
-        double f2 = f[2 * n + k], f3 = f[3 * n + k], f4 = f[4 * n + k], f6 = f[6 * n + k], f7 = f[7 * n + k];
+        real ux = inlet_u(P, j), uy = 0.0;
+        real f2 = f[2 * n + k], f3 = f[3 * n + k], f4 = f[4 * n + k], f6 = f[6 * n + k], f7 = f[7 * n + k];
         f[1 * n + k] = f3 + (2.0 / 3.0) * ux;
         f[5 * n + k] = f7 - 0.5 * (f2 - f4) + ux / 6.0 + 0.5 * uy;
         f[8 * n + k] = f6 + 0.5 * (f2 - f4) + ux / 6.0 - 0.5 * uy;
-        double u[2] = {ux, uy}, G[NQ];
+        real u[2] = {ux, uy}, G[NQ];
         orc_gamma(u, G);
         const int in_dirs[3] = {1, 5, 8};
         for (int d = 0; d < 3; ++d) {
@@ -816,18 +862,18 @@ static void open_boundaries(const orc_params* P, const double* out_old, double* 
 /* The coupled step.  Reading: the algorithm figure is missing; the order is   */
 /* phases -> potential -> stencils and forces -> collisions -> streaming.      */
 /* ------------------------------------------------------------------------- */
-int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t step0, double* f, double* g1,
-             double* g2, double* psi, int32_t* total_sweeps, double* last_resid) {
+int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t step0, real* f, real* g1,
+             real* g2, real* psi, int32_t* total_sweeps, double* last_resid) {
     int nx = P->nx, ny = P->ny;
     if (nx < 4 || ny < 2 || (nx % 2)) return -1;
     size_t n = (size_t)nx * ny;
-    double* phi1 = (double*)malloc(n * sizeof(double));
-    double* phi2 = (double*)malloc(n * sizeof(double));
-    double* mur = (double*)malloc(n * sizeof(double));
-    double* fp = (double*)malloc(NQ * n * sizeof(double));
-    double* g1p = (double*)malloc(NQ * n * sizeof(double));
-    double* g2p = (double*)malloc(NQ * n * sizeof(double));
-    double* out_old = (double*)malloc(3 * NQ * (size_t)ny * sizeof(double));
+    real* phi1 = (real*)malloc(n * sizeof(real));
+    real* phi2 = (real*)malloc(n * sizeof(real));
+    real* mur = (real*)malloc(n * sizeof(real));
+    real* fp = (real*)malloc(NQ * n * sizeof(real));
+    real* g1p = (real*)malloc(NQ * n * sizeof(real));
+    real* g2p = (real*)malloc(NQ * n * sizeof(real));
+    real* out_old = (real*)malloc(3 * NQ * (size_t)ny * sizeof(real));
     int rc = 0;
     if (!phi1 || !phi2 || !mur || !fp || !g1p || !g2p || !out_old) {
         rc = -3;
@@ -857,7 +903,7 @@ int orc_step(const orc_params* P, const orc_solver* S, int32_t nsteps, int32_t s
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t k = IDX(i, j, nx);
-                double fn[NQ], gn1[NQ], gn2[NQ], fo[NQ], go1[NQ], go2[NQ];
+                real fn[NQ], gn1[NQ], gn2[NQ], fo[NQ], go1[NQ], go2[NQ];
                 for (int a = 0; a < NQ; ++a) {
                     fn[a] = f[a * n + k];
                     gn1[a] = g1[a * n + k];
@@ -927,12 +973,12 @@ done:
 
 /* Planes [10][ny][nx]: p*, ux, uy, phi1, phi2, phi3, rho, psi', Hx, Hy, with u the
  * force-corrected velocity of Eq. 22 evaluated from the stored psi'. */
-int orc_moments(const orc_params* P, const double* f, const double* g1, const double* g2,
-                const double* psi, double* out) {
+int orc_moments(const orc_params* P, const real* f, const real* g1, const real* g2,
+                const real* psi, real* out) {
     int nx = P->nx, ny = P->ny;
     size_t n = (size_t)nx * ny;
-    double* phi1 = (double*)malloc(n * sizeof(double));
-    double* phi2 = (double*)malloc(n * sizeof(double));
+    real* phi1 = (real*)malloc(n * sizeof(real));
+    real* phi2 = (real*)malloc(n * sizeof(real));
     if (!phi1 || !phi2) {
         free(phi1);
         free(phi2);
@@ -943,7 +989,7 @@ int orc_moments(const orc_params* P, const double* f, const double* g1, const do
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t k = IDX(i, j, nx);
-            double fn[NQ];
+            real fn[NQ];
             for (int a = 0; a < NQ; ++a) fn[a] = f[a * n + k];
             nodeq q;
             node_quantities(P, phi1, phi2, psi, fn, i, j, &q);
@@ -965,12 +1011,12 @@ int orc_moments(const orc_params* P, const double* f, const double* g1, const do
 
 /* Forces at every node (for the force tests): planes [8][ny][nx] =
  * Fs_x, Fs_y, Fm_x, Fm_y, Fmu_x, Fmu_y, Ft_x, Ft_y. */
-int orc_forces(const orc_params* P, const double* f, const double* g1, const double* g2,
-               const double* psi, double* out) {
+int orc_forces(const orc_params* P, const real* f, const real* g1, const real* g2,
+               const real* psi, real* out) {
     int nx = P->nx, ny = P->ny;
     size_t n = (size_t)nx * ny;
-    double* phi1 = (double*)malloc(n * sizeof(double));
-    double* phi2 = (double*)malloc(n * sizeof(double));
+    real* phi1 = (real*)malloc(n * sizeof(real));
+    real* phi2 = (real*)malloc(n * sizeof(real));
     if (!phi1 || !phi2) {
         free(phi1);
         free(phi2);
@@ -981,7 +1027,7 @@ int orc_forces(const orc_params* P, const double* f, const double* g1, const dou
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t k = IDX(i, j, nx);
-            double fn[NQ];
+            real fn[NQ];
             for (int a = 0; a < NQ; ++a) fn[a] = f[a * n + k];
             nodeq q;
             node_quantities(P, phi1, phi2, psi, fn, i, j, &q);
@@ -1002,41 +1048,41 @@ int orc_forces(const orc_params* P, const double* f, const double* g1, const dou
 /* Second-moment deformation of a weight field w (a differentiable stand-in for the
  * extent-based index of Eq. 42, equal to it for an ellipse): centroid with a circular mean
  * in periodic x, I_xx and I_yy about it, D = (sqrt Iyy - sqrt Ixx)/(sqrt Iyy + sqrt Ixx). */
-double orc_deformation_w(int32_t nx, int32_t ny, const double* w) {
+real orc_deformation_w(int32_t nx, int32_t ny, const real* w) {
     const double twopi = 6.283185307179586476925286766559;
-    double sw = 0.0, sc = 0.0, ss = 0.0, sy = 0.0;
+    real sw = 0.0, sc = 0.0, ss = 0.0, sy = 0.0;
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            double v = w[IDX(i, j, nx)];
+            real v = w[IDX(i, j, nx)];
             sw += v;
             sc += v * cos(twopi * i / nx);
             ss += v * sin(twopi * i / nx);
             sy += v * j;
         }
-    double xc = nx * atan2(ss, sc) / twopi;
-    double yc = sy / sw;
-    double ixx = 0.0, iyy = 0.0;
+    real xc = nx * r_atan2(ss, sc) / twopi;
+    real yc = sy / sw;
+    real ixx = 0.0, iyy = 0.0;
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            double v = w[IDX(i, j, nx)];
-            double dx = (double)i - xc;
-            dx -= nx * floor(dx / nx + 0.5);
-            double dy = (double)j - yc;
+            real v = w[IDX(i, j, nx)];
+            real dx = (double)i - xc;
+            dx -= nx * floor(RE(dx) / nx + 0.5);
+            real dy = (double)j - yc;
             ixx += v * dx * dx;
             iyy += v * dy * dy;
         }
     ixx /= sw;
     iyy /= sw;
-    return (sqrt(iyy) - sqrt(ixx)) / (sqrt(iyy) + sqrt(ixx));
+    return (r_sqrt(iyy) - r_sqrt(ixx)) / (r_sqrt(iyy) + r_sqrt(ixx));
 }
 
 /* out = {D_o (w = 1 - phi3), D_i (w = phi1), sum phi1, sum phi2}. */
-int orc_diagnostics(const orc_params* P, const double* g1, const double* g2, double out[4]) {
+int orc_diagnostics(const orc_params* P, const real* g1, const real* g2, real out[4]) {
     int nx = P->nx, ny = P->ny;
     size_t n = (size_t)nx * ny;
-    double* phi1 = (double*)malloc(n * sizeof(double));
-    double* phi2 = (double*)malloc(n * sizeof(double));
-    double* wo = (double*)malloc(n * sizeof(double));
+    real* phi1 = (real*)malloc(n * sizeof(real));
+    real* phi2 = (real*)malloc(n * sizeof(real));
+    real* wo = (real*)malloc(n * sizeof(real));
     if (!phi1 || !phi2 || !wo) {
         free(phi1);
         free(phi2);
@@ -1045,7 +1091,7 @@ int orc_diagnostics(const orc_params* P, const double* g1, const double* g2, dou
     }
     phase_from_g(nx, ny, g1, phi1);
     phase_from_g(nx, ny, g2, phi2);
-    double m1 = 0.0, m2 = 0.0;
+    real m1 = 0.0, m2 = 0.0;
     for (size_t k = 0; k < n; ++k) {
         wo[k] = phi1[k] + phi2[k];
         m1 += phi1[k];
@@ -1061,6 +1107,7 @@ int orc_diagnostics(const orc_params* P, const double* g1, const double* g2, dou
     return 0;
 }
 
+#ifndef ORC_COMPLEX_STEP
 /* Extent-based deformation index of Eq. 42, T = (l_y - l_x) / (l_y + l_x), of the
  * outer droplet (w = phi1 + phi2) and the inner one (w = phi1), the interface at w = 1/2.
  * Reading: l_y is the largest vertical extent over the columns: in each column the longest
@@ -1205,12 +1252,14 @@ int orc_breakup_probe(const orc_params* P, const double* g1, const double* g2, d
     return 0;
 }
 
+#endif /* ORC_COMPLEX_STEP */
+
 /* Exported for the stencil tests: Eq. 34 gradient and Eq. 35 Laplacian of a plane
  * with the mirror ghost rule. */
-void orc_stencils(int32_t nx, int32_t ny, const double* a, double* gx, double* gy, double* lap) {
+void orc_stencils(int32_t nx, int32_t ny, const real* a, real* gx, real* gy, real* lap) {
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            double g[2];
+            real g[2];
             iso_grad(a, nx, ny, i, j, 0, g);
             gx[IDX(i, j, nx)] = g[0];
             gy[IDX(i, j, nx)] = g[1];
@@ -1219,7 +1268,7 @@ void orc_stencils(int32_t nx, int32_t ny, const double* a, double* gx, double* g
 }
 
 /* Exported: mu_r plane from phi planes (Eq. 8). */
-void orc_mu_r(const orc_params* P, const double* phi1, const double* phi2, double* mur) {
+void orc_mu_r(const orc_params* P, const real* phi1, const real* phi2, real* mur) {
     mu_r_from_phi(P, phi1, phi2, mur);
 }
 

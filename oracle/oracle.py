@@ -263,3 +263,133 @@ class OracleSim:
         rc = self.L.orc_extent_deformation(C.byref(self.p), ptr(self.g1), ptr(self.g2), ptr(out))
         assert rc == 0, rc
         return out
+
+
+# --- complex-step build ---------------------------------------------------------------
+# The same source compiled with real = double _Complex (ORC_COMPLEX_STEP): a parameter
+# given an imaginary part i h carries h times its first derivative through every step, so
+# dJ/dtheta = Im J(theta + i h) / h to rounding, with no difference of nearby values.
+
+_LIB_CS = os.path.join(_HERE, "liboracle_cs.so")
+_lib_cs = None
+_vp = C.c_void_p
+
+
+def build_cstep(force: bool = True) -> str:
+    """Compile the complex-step build (plain -O2; complex division by Smith's method,
+    without the library's rescaling for infinities, which these values never reach)."""
+    if force or not os.path.exists(_LIB_CS):
+        tmp = _LIB_CS + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wno-unknown-pragmas", "-DORC_COMPLEX_STEP",
+                               "-fcx-fortran-rules", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_CS)
+    return _LIB_CS
+
+
+_R2 = C.c_double * 2  # one double _Complex
+
+
+class OracleParamsCS(C.Structure):
+    """orc_params of the complex-step build: every floating field is a double _Complex."""
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("open_x", C.c_int32), ("pad1", C.c_int32),
+        ("rho", _R2 * 3), ("tau", _R2 * 3), ("chi", _R2 * 3),
+        ("sigma12", _R2), ("sigma13", _R2), ("sigma23", _R2),
+        ("eta", _R2), ("xi", _R2), ("mobility", _R2),
+        ("H0", _R2), ("alpha", _R2), ("mu0", _R2),
+        ("drive_G", _R2), ("grav_x", _R2), ("grav_y", _R2),
+        ("eps_n", _R2), ("u_inlet", _R2),
+    ]
+
+
+def _c(v) -> "_R2":
+    z = complex(v)
+    return _R2(z.real, z.imag)
+
+
+def params_cs_from_workload(w, drive_G=None) -> OracleParamsCS:
+    """Complex parameters from a workload whose fields may hold complex numbers."""
+    p = OracleParamsCS()
+    p.nx, p.ny = w.nx, w.ny
+    for k in range(3):
+        p.rho[k], p.tau[k], p.chi[k] = _c(w.rho[k]), _c(w.tau[k]), _c(w.chi[k])
+    p.sigma12, p.sigma13, p.sigma23, p.eta = _c(w.sigma12), _c(w.sigma13), _c(w.sigma23), _c(w.eta)
+    p.xi, p.mobility = _c(w.xi), _c(w.mobility)
+    p.H0, p.alpha, p.mu0 = _c(w.H0), _c(w.alpha), _c(w.mu0)
+    p.drive_G = _c(w.drive_G if drive_G is None else drive_G)
+    p.grav_x, p.grav_y = _c(w.grav[0]), _c(w.grav[1])
+    p.eps_n = _c(w.eps_n)
+    p.open_x = 0 if w.u_inlet is None else 1
+    p.u_inlet = _c(0.0 if w.u_inlet is None else w.u_inlet)
+    return p
+
+
+def lib_cstep():
+    global _lib_cs
+    if _lib_cs is None:
+        L = C.CDLL(build_cstep(force=not os.path.exists(_LIB_CS)))
+        P = C.POINTER(OracleParamsCS)
+        S = C.POINTER(OracleSolver)
+        L.orc_init_droplet.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double, _vp, _vp, _vp, _vp, _vp]
+        L.orc_step.argtypes = [P, S, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_double)]
+        L.orc_diagnostics.argtypes = [P, _vp, _vp, _vp]
+        for name in ("orc_init_droplet", "orc_step", "orc_diagnostics"):
+            getattr(L, name).restype = C.c_int
+        _lib_cs = L
+    return _lib_cs
+
+
+def _zp(a: np.ndarray):
+    assert a.dtype == np.complex128 and a.flags["C_CONTIGUOUS"], "complex128 C-contiguous arrays only"
+    return a.ctypes.data_as(_vp)
+
+
+# the parameters of the gradient, in the order the adjoint reports them
+THETA_NAMES = ("H0", "alpha", "u_ref", "sigma12", "sigma13", "sigma23")
+
+
+def complex_step_run(w, nsteps: int, k: int | None, h: float = 1e-20, solver: OracleSolver | None = None):
+    """Droplet initial state of workload w, then nsteps oracle steps with parameter k of
+    THETA_NAMES given the imaginary part h (none when k is None); returns the complex
+    diagnostics {D_o, D_i, sum phi1, sum phi2}.  u_ref enters through the channel drive
+    G = 8 rho_3 nu_3 u_ref / ny^2 (the Poiseuille peak u_ref), which is linear in it."""
+    from fcd_inputs import channel_drive
+    L = lib_cstep()
+    theta = {n: complex(getattr(w, n)) for n in THETA_NAMES}
+    if k is not None:
+        theta[THETA_NAMES[k]] += 1j * h
+    wc = w.replace(H0=theta["H0"], alpha=theta["alpha"], sigma12=theta["sigma12"], sigma13=theta["sigma13"],
+                   sigma23=theta["sigma23"])
+    p = params_cs_from_workload(wc, drive_G=channel_drive(theta["u_ref"], w.rho[2], w.tau[2], w.ny))
+    s = solver if solver is not None else OracleSolver.direct()
+    ny, nx = w.ny, w.nx
+    f = np.zeros((9, ny, nx), np.complex128)
+    g1 = np.zeros_like(f)
+    g2 = np.zeros_like(f)
+    phi1 = np.zeros((ny, nx), np.complex128)
+    phi2 = np.zeros_like(phi1)
+    psi = np.zeros_like(phi1)
+    assert L.orc_init_droplet(C.byref(p), w.xc, w.yc, w.r_core, w.r_shell, _zp(f), _zp(g1), _zp(g2), _zp(phi1),
+                              _zp(phi2)) == 0
+    sw, res = C.c_int32(0), C.c_double(0.0)
+    rc = L.orc_step(C.byref(p), C.byref(s), int(nsteps), 0, _zp(f), _zp(g1), _zp(g2), _zp(psi), C.byref(sw),
+                    C.byref(res))
+    assert rc == 0, rc
+    out = np.zeros(4, np.complex128)
+    assert L.orc_diagnostics(C.byref(p), _zp(g1), _zp(g2), _zp(out)) == 0
+    return out
+
+
+def complex_step_gradient(w, nsteps: int, weights=(1.0, 0.0), h: float = 1e-20):
+    """J = a D_o + b D_i after nsteps from the droplet state, and dJ/dtheta for the six
+    parameters of THETA_NAMES, each from one complex-step run: Im J(theta_k + i h) / h."""
+    a, b = weights
+    grad = np.zeros(6)
+    J = None
+    for k in range(6):
+        d = complex_step_run(w, nsteps, k, h)
+        Jc = a * d[0] + b * d[1]
+        grad[k] = Jc.imag / h
+        J = Jc.real if J is None else J
+    return J, grad
