@@ -386,17 +386,16 @@ def open_channel(torch, steps: int) -> dict:
     """The paper's open-channel set-up (900 x 150, Eq. 37 inlet, convective outlet; Bo_m = 2,
     ferrofluid shell, multigrid to 1e-10), FP64: throughput with the end-column boundary
     launches against the same lattice and droplet run as a periodic channel under the
-    equivalent body force.  The multigrid hierarchy of 900 x 150 stops after one halving
-    (450 x 75: nx / 2 is not a multiple of 4 and ny / 2 is odd), so its coarsest level is
-    solved by launched SOR sweeps; heavier smoothing (12 sweeps before and after) with 16
-    coarse sweeps per cycle needs 3.1 V-cycles per step of a third of the default cost."""
+    equivalent body force.  The hierarchy of 900 x 150 runs through odd levels (450 x 75,
+    225 x 37, 113 x 19, then a tail of 57 x 9, 29 x 4, 15 x 2); two finest-level sweeps each
+    way were the fastest of 1-6 measured on this lattice."""
     from fcd_inputs import channel_drive, open_channel_paper
     from paper_2410_11129_amd.sim import Channel
     w = open_channel_paper(bond=2.0)
     periodic = w.replace(u_inlet=None, drive_G=channel_drive(w.u_inlet, w.rho[2], w.tau[2], w.ny))
     out = {"workload": "open_channel_900x150_fp64_bo2", "steps": steps}
     for name, ww in (("open", w), ("periodic", periodic)):
-        ch = Channel(ww, tol=1e-10, smooth=12, coarse_sweeps=-16)
+        ch = Channel(ww, tol=1e-10, smooth=2)
         ch.init_droplet()
         ch.solve_potential(1e-10)
         ch.step(20)

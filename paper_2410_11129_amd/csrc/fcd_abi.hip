@@ -65,9 +65,10 @@ double u_limit_of(const fcd_params& p) { return p.u_limit > 0.0 ? p.u_limit : 0.
 int div_every_of(const fcd_params& p) { return p.div_check_every > 0 ? p.div_check_every : 64; }
 
 // Multigrid hierarchy and scratch layout.  Level 0 is the lattice itself (psi', mu_r
-// planes of the caller, in the lattice's precision); coarser levels halve both
-// dimensions while nx is a multiple of 4 and ny is even and >= 4, and are FP32 in both
-// precisions: they only compute corrections, each cycle's residual is formed on level 0
+// planes of the caller, in the lattice's precision); a level of nx x ny nodes with
+// nx, ny >= 4 has a coarser one of ceil(nx/2) x floor(ny/2) or ceil(ny/2) nodes (odd sizes
+// included; the row count by the wall distance below, the geometry in fcd_potential.hip),
+// and the coarse levels are FP32 in both precisions: they only compute corrections, each cycle's residual is formed on level 0
 // in the lattice's precision, so the solve still reaches that precision's tolerance
 // (mixed-precision multigrid), while the latency-bound coarse kernels run FP32 arithmetic
 // on half the bytes.  The coarsest levels whose LDS arrays (u, f, mu, a Jacobi ping-pong
@@ -84,6 +85,7 @@ struct MgPlan {
     int levels;
     int tail;  // first tail level (== levels: no tail)
     int nx[MAX_LEVELS], ny[MAX_LEVELS], pitch[MAX_LEVELS];
+    double kappa_top[MAX_LEVELS];  // upper ghost rule of each level (fcd_potential.hip)
     size_t off_mu[MAX_LEVELS], off_u[MAX_LEVELS], off_f[MAX_LEVELS], off_t[MAX_LEVELS];
     size_t off_prev;  // psi' history planes: psi'(t-1) ...
     size_t off_prev2; // ... and psi'(t-2) (quadratic extrapolation)
@@ -97,14 +99,25 @@ MgPlan make_plan(const fcd_lattice& l) {
     p.nx[0] = l.nx;
     p.ny[0] = l.ny;
     p.pitch[0] = l.pitch;
+    p.kappa_top[0] = 0.0;
     while (p.levels < MAX_LEVELS) {
         const int px = p.nx[p.levels - 1], py = p.ny[p.levels - 1];
-        if (px % 4 || py % 2 || py < 4) break;
+        if (px < 4 || py < 4) break;
         const int L = p.levels++;
-        p.nx[L] = px / 2;
-        p.ny[L] = py / 2;
+        p.nx[L] = (px + 1) / 2;
         const int per = (int)(256 / sizeof(CT));
         p.pitch[L] = (p.nx[L] + per - 1) / per * per;
+        // rows: floor(py/2), or ceil(py/2) when that puts the last row (spacing h, the first
+        // row (h-1)/2 above row 0) nearer the distance (h+1)/2 below the finest level's upper
+        // ghost row y = ny that every level of an even hierarchy has, and not closer than
+        // h/4; so the distance stays >= h/4 (kappa_top <= 3) and is finite (kappa_top > -1)
+        const double h = double(1 << L);
+        auto dist = [&](int rows) { return (double)l.ny - (h * (rows - 1) + 0.5 * (h - 1.0)); };
+        const int fl = py / 2, ce = (py + 1) / 2;
+        const double ideal = 0.5 * (h + 1.0);
+        p.ny[L] = (dist(ce) >= 0.25 * h && std::fabs(dist(ce) - ideal) < std::fabs(dist(fl) - ideal)) ? ce : fl;
+        const double d = dist(p.ny[L]);
+        p.kappa_top[L] = (h - d) / d;
     }
     p.tail = p.levels;
     size_t tail_bytes = 0;
@@ -114,6 +127,9 @@ MgPlan make_plan(const fcd_lattice& l) {
         tail_bytes += b;
         p.tail = L;
     }
+    // without a tail the coarsest level is solved by launched four-colour sweeps, which
+    // need an even width (on an odd periodic row the first and last nodes share a colour)
+    while (p.tail == p.levels && p.levels > 1 && (p.nx[p.levels - 1] & 1)) p.tail = --p.levels;
     size_t off = align256(OFF_ROWS + (size_t)l.ny * 8 * sizeof(double));
     p.off_prev = off;
     off += align256((size_t)l.ny * l.pitch * esz);
@@ -425,6 +441,7 @@ fcd::PotLevel<T> pot_level(const fcd_handle* h, int l) {
     L.f = nullptr;
     L.inv_h2 = T(1);
     L.kappa = T(0);
+    L.kappa_top = T(0);
     L.H0x = T(h->prm.H0 * std::cos(h->prm.alpha));
     L.H0y = T(h->prm.H0 * std::sin(h->prm.alpha));
     return L;
@@ -444,6 +461,7 @@ fcd::PotLevel<CT> coarse_level(const fcd_handle* h, int l) {
         L.f = reinterpret_cast<CT*>(s + h->plan.off_f[l]);
         L.inv_h2 = CT(1.0 / (hh * hh));
         L.kappa = CT((hh - 1.0) / (hh + 1.0));
+        L.kappa_top = CT(h->plan.kappa_top[l]);
         L.H0x = L.H0y = CT(0);
     }
     return L;
@@ -1178,6 +1196,7 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
     I.L0.pitch = b->L.pitch[k];
     I.L0.inv_h2 = T(1);
     I.L0.kappa = T(0);
+    I.L0.kappa_top = T(0);
     I.L0.H0x = T(p.H0 * std::cos(p.alpha));
     I.L0.H0y = T(p.H0 * std::sin(p.alpha));
     I.omega = T(p.pot_omega > 0.0 ? p.pot_omega : sor_omega_opt(l.ny));

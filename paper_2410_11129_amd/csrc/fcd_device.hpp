@@ -51,7 +51,8 @@ struct PotLevel {
     T* f;         // right-hand side, nullptr on the finest level
     int nx, ny, pitch, pad;
     T inv_h2;     // 1 / h^2, h = 2^level
-    T kappa;      // ghost rows carry -kappa times the edge rows: (h - 1) / (h + 1)
+    T kappa;      // the ghost row below the first row carries -kappa times it: (h - 1) / (h + 1)
+    T kappa_top;  // the ghost row above the last row carries -kappa_top times it (wall distance)
     T H0x, H0y;   // applied field (finest level only)
 };
 

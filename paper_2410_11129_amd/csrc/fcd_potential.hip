@@ -5,11 +5,25 @@
 //   (L u)(x) = sum_a c_a (u(x+e_a) - u(x)),  c_a = 3 w_a (mu(x) + mu(x+e_a)) / h^2.
 // On the finest level u = psi', the right-hand side is H0 sum_a c_a (e_a . h) (so that
 // L(psi0 + psi') = 0 with psi0 = -H0 (x cos a + y sin a)) and psi' = 0 on the rows beyond
-// the walls.  Coarse levels are cell-centred: coarse node (I, J) is the average of fine
-// nodes (2I..2I+1, 2J..2J+1) and sits (h-1)/2 fine cells inside the wall line, so its
-// ghost row must carry -kappa times the edge row, kappa = (h-1)/(h+1), for the
-// correction to vanish on the true wall line (linear extrapolation); kappa = 0 on the
-// finest level.  mu_r is mirrored beyond the walls on every level.
+// the walls.  Coarse levels are cell-centred: a level of nx x ny nodes coarsens to
+// ceil(nx/2) x (floor or ceil)(ny/2), coarse node (I, J) standing for fine nodes
+// (2I..2I+1, 2J..2J+1); an odd level's last column 2I+1 = nx does not exist, and its last
+// row ny - 1 lies above a coarse grid of floor(ny/2) rows (with ceil(ny/2) rows the last
+// coarse row stands for that fine row alone).  On the level of spacing h the first row
+// sits (h-1)/2 fine cells inside the lower wall line (the finest ghost row y = -1, where
+// psi' = 0), so the ghost row below it carries -kappa times it, kappa = (h-1)/(h+1), for
+// the correction to vanish on that line (linear extrapolation).  The last row sits
+// d = ny0 - (h (ny-1) + (h-1)/2) below the upper line y = ny0 of the finest level (the
+// planner keeps d >= h/4); its ghost row carries -kappa_top times it, kappa_top =
+// (h - d)/d (equal to kappa when every level above is even; otherwise between -1 and 3,
+// the diagonal dominant either way).  Both are 0 on the finest level.  A fine row above
+// the coarse grid is interpolated between the last coarse row and its ghost (3/4 of the
+// way to the ghost); its residual enters the last coarse row through the ordinary
+// weights, and a fine row missing under the last coarse row carries none.  mu_r is
+// mirrored beyond the walls on every level.  In x an odd level closes periodically over
+// its own width; its coarse level is one node more than half as wide, an approximation of
+// the geometry at the seam that the coarse corrections tolerate (the finest level's
+// residual decides convergence).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -68,11 +82,12 @@ __global__ void __launch_bounds__(RES_T) k_pot_residual(PotLevel<T> L, unsigned 
     }
 }
 
-// Coarse mu: the average of the four fine nodes under each coarse node, for up to four
+// Coarse mu: the average of the fine nodes under each coarse node, for up to four
 // levels in one launch.  A block owns a 64 x 16 tile of the finer level, which contains
 // the children of every coarse node of the next four levels that lies over it, and
 // averages level by level in LDS; the first level is averaged in the finer level's type
-// and stored in the coarse type.
+// and stored in the coarse type.  A child beyond an odd level's last column or row stands
+// in for its sibling, so a coarse node with two (or one) real children averages those.
 constexpr int MU_TX = 64, MU_TY = 16;
 
 template <typename T, typename TC>
@@ -88,7 +103,7 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* _
     for (int r = 0; r < 4; ++r) {
         const int q = tid + r * NT, ly = q / MU_TX, lx = q - ly * MU_TX;
         const int i = i0 + lx, j = j0 + ly;
-        v[r] = (i < nxf && j < nyf) ? muf[(long long)j * pitchf + i] : T(0);
+        v[r] = muf[(long long)min(j, nyf - 1) * pitchf + min(i, nxf - 1)];
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -110,10 +125,14 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* _
     int sx = MU_TX / 2;  // row length of src
     for (int k = 1; k < C.n; ++k) {
         const int cx = sx / 2, cy = (MU_TY >> k) / 2;
+        const int gx0 = i0 >> k, gy0 = j0 >> k;  // src origin on level k-1 of C
         for (int t = tid; t < cx * cy; t += NT) {
             const int y = t / cx, x = t - y * cx;
-            const TC* a = src + (2 * y) * sx + 2 * x;
-            const TC m = TC(0.25) * ((a[0] + a[1]) + (a[sx] + a[sx + 1]));
+            const int x1 = gx0 + 2 * x + 1 < C.nx[k - 1] ? 2 * x + 1 : 2 * x;
+            const int y1 = gy0 + 2 * y + 1 < C.ny[k - 1] ? 2 * y + 1 : 2 * y;
+            const TC* r0 = src + (2 * y) * sx;
+            const TC* r1 = src + y1 * sx;
+            const TC m = TC(0.25) * ((r0[2 * x] + r0[x1]) + (r1[2 * x] + r1[x1]));
             dst[y * cx + x] = m;
             const int I = (i0 >> (k + 1)) + x, J = (j0 >> (k + 1)) + y;
             if (I < C.nx[k] && J < C.ny[k]) C.mu[k][(long long)J * C.pitch[k] + I] = m;
@@ -132,6 +151,10 @@ template <typename T>
 __device__ __forceinline__ T prolong_at(const PotLevel<T>& Cl, int i, int j) {
     const int I = i >> 1, J = j >> 1;
     const int I2 = (i & 1) ? (I + 1 == Cl.nx ? 0 : I + 1) : (I == 0 ? Cl.nx - 1 : I - 1);
+    if (J >= Cl.ny) {  // the row above the coarse grid (odd fine ny)
+        const long long r = (long long)(Cl.ny - 1) * Cl.pitch;
+        return (T(1) / T(4) - T(3) / T(4) * Cl.kappa_top) * (T(3) / T(4) * Cl.u[r + I] + T(1) / T(4) * Cl.u[r + I2]);
+    }
     int J2 = (j & 1) ? J + 1 : J - 1;
     T gy = T(1);
     if (J2 < 0) {
@@ -139,7 +162,7 @@ __device__ __forceinline__ T prolong_at(const PotLevel<T>& Cl, int i, int j) {
         gy = -Cl.kappa;
     } else if (J2 >= Cl.ny) {
         J2 = Cl.ny - 1;
-        gy = -Cl.kappa;
+        gy = -Cl.kappa_top;
     }
     const T* e = Cl.u;
     const long long rJ = (long long)J * Cl.pitch, rJ2 = (long long)J2 * Cl.pitch;
@@ -186,13 +209,13 @@ __device__ __forceinline__ MgEval<T> tile_eval(const T (*su)[HX], const T (*sm)[
     const T mc = sm[ly][lx], me = sm[ly][lx + 1], mw = sm[ly][lx - 1];
     const T mn = sm[ly + 1][lx], ms = sm[ly - 1][lx];
     const T mne = sm[ly + 1][lx + 1], mnw = sm[ly + 1][lx - 1], msw = sm[ly - 1][lx - 1], mse = sm[ly - 1][lx + 1];
-    const T k = L.kappa;
+    const T k = L.kappa, kt = L.kappa_top;
     const T ue = su[ly][lx + 1], uw = su[ly][lx - 1];
     T un, une, unw, us, usw, use;
     if (top) {
-        un = -k * su[ly][lx];
-        une = -k * ue;
-        unw = -k * uw;
+        un = -kt * su[ly][lx];
+        une = -kt * ue;
+        unw = -kt * uw;
     } else {
         un = su[ly + 1][lx];
         une = su[ly + 1][lx + 1];
@@ -213,7 +236,7 @@ __device__ __forceinline__ MgEval<T> tile_eval(const T (*su)[HX], const T (*sm)[
     MgEval<T> r;
     r.C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
     r.acc = ((ce * ue + cw * uw) + (cn * un + cs * us)) + ((cne * une + csw * usw) + (cnw * unw + cse * use));
-    r.cself = (bot ? k * cs : T(0)) + (top ? k * cn : T(0));
+    r.cself = (bot ? k * cs : T(0)) + (top ? kt * cn : T(0));
     if (rhs_from_field) {
         const T sx = (ce - cw) + (cne - csw) + (cse - cnw);
         const T sy = (cn - cs) + (cne - csw) + (cnw - cse);
@@ -254,11 +277,16 @@ __device__ __forceinline__ void load_tile(const PotLevel<T>& L, const T* __restr
 // Prolongation at fine tile cell (lx, ly) from the coarse tile sc (bilinear weights
 // 9/16, 3/16, 3/16, 1/16; coarse ghost rows by the kappa rule).
 template <typename T, int CX>
-__device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int lx, int ly, int nyc, T kappa) {
+__device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int lx, int ly, int nyc, T kappa,
+                                          T kappa_top) {
     const int i = i0 + lx - 1, j = j0 + ly - 1;  // unwrapped fine coordinates
     const int I0 = i0 >> 1, J0 = j0 >> 1;
     const int lI = (i >> 1) - I0 + 1, lI2 = (i & 1) ? lI + 1 : lI - 1;
     const int J = j >> 1, lJ = J - J0 + 1;
+    if (J >= nyc) {  // the row above the coarse grid (odd fine ny), or a halo row beyond the wall
+        const int lt = nyc - 1 - J0 + 1;
+        return (T(1) / T(4) - T(3) / T(4) * kappa_top) * (T(3) / T(4) * sc[lt][lI] + T(1) / T(4) * sc[lt][lI2]);
+    }
     int J2 = (j & 1) ? J + 1 : J - 1;
     T gy = T(1);
     if (J2 < 0) {
@@ -266,7 +294,7 @@ __device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int
         gy = -kappa;
     } else if (J2 >= nyc) {
         J2 = nyc - 1;
-        gy = -kappa;
+        gy = -kappa_top;
     }
     const int lJ2 = J2 - J0 + 1;
     return T(9) / T(16) * sc[lJ][lI] + T(3) / T(16) * (gy * sc[lJ2][lI] + sc[lJ][lI2]) +
@@ -323,7 +351,7 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
         if (q < G::HN) {
             const int ly = q / HX, lx = q - ly * HX;
             T u = uv[r];
-            if (PROLONG) u += prolong_tile<T, CX>(sc, i0, j0, lx, ly, Cl.ny, T(Cl.kappa));
+            if (PROLONG) u += prolong_tile<T, CX>(sc, i0, j0, lx, ly, Cl.ny, T(Cl.kappa), T(Cl.kappa_top));
             su[ly][lx] = u;
             sm[ly][lx] = mv[r];
         }
@@ -477,8 +505,10 @@ __device__ __forceinline__ T restrict16(const T (*sr)[RX], int cx, int cy) {
 
 // Residual restriction by tiles: a block stages its fine tile (SX x SY) with a two-node
 // halo, forms the residuals of the tile and its ring and writes the (SX/2) x (SY/2)
-// coarse right-hand sides and a zero coarse correction.  Requires nx = 2 nxc and
-// ny = 2 nyc.
+// coarse right-hand sides and a zero coarse correction.  Coarse sizes as in the header
+// note; fine rows beyond the walls or missing carry no residual (an odd level's last row
+// above the coarse grid enters the last coarse row with the weight of row 2J+2), and fine
+// columns wrap over the fine width.
 template <typename T, typename G, int MODE, typename TC>
 __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
     using R = RestrictGeom<G>;
@@ -518,7 +548,7 @@ __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLe
 // to LDS) and runs `inner` tile sweeps from a zero correction (the whole coarse level
 // starts at zero, so the tile's halo is zero as well), writing the result to uout.  Same
 // arithmetic as k_mg_restrict_tile followed by k_mg_smooth_tile, one launch fewer.
-// Requires F.nx = 2 C.nx and F.ny = 2 C.ny.
+// Coarse sizes as in k_mg_restrict_tile.
 template <typename T, int FMODE, typename TC>
 __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<TC> C,
                                                                      TC* __restrict__ uout, int inner) {
@@ -663,7 +693,7 @@ __device__ __forceinline__ void tail_setup_node(const TailLevel<T>& S, const Pot
     const int dn = j + 1 == S.ny ? 0 : nx, ds = j == 0 ? 0 : -nx;  // mirrored mu beyond the walls
     const T* m = S.mu;
     const T mc = m[t];
-    const T a = G.inv_h2 * (T(1) / T(3)), q = G.inv_h2 * (T(1) / T(12)), k = G.kappa;
+    const T a = G.inv_h2 * (T(1) / T(3)), q = G.inv_h2 * (T(1) / T(12)), k = G.kappa, kt = G.kappa_top;
     T ce = a * (mc + m[e]), cw = a * (mc + m[w]), cn = a * (mc + m[t + dn]), cs = a * (mc + m[t + ds]);
     T cne = q * (mc + m[e + dn]), cnw = q * (mc + m[w + dn]), csw = q * (mc + m[w + ds]), cse = q * (mc + m[e + ds]);
     const T C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
@@ -675,9 +705,9 @@ __device__ __forceinline__ void tail_setup_node(const TailLevel<T>& S, const Pot
         cs = csw = cse = T(0);
     }
     if (j + 1 == S.ny) {  // ghost row above
-        d += k * cn;
-        ce -= k * cne;
-        cw -= k * cnw;
+        d += kt * cn;
+        ce -= kt * cne;
+        cw -= kt * cnw;
         cn = cne = cnw = T(0);
     }
     S.c[0][t] = ce;
@@ -824,15 +854,17 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
         const T wa = T(1) / T(8), wb = T(3) / T(8);
         for (int t = tid; t < n; t += TAIL_T) {
             const int J = tail_div(t, Cc.inv), I = t - J * Cc.nx;
-            const int im = I == 0 ? F.nx - 1 : 2 * I - 1, i3 = 2 * I + 2 == F.nx ? 0 : 2 * I + 2;
+            // fine columns 2I-1 .. 2I+2, periodic over the fine width (which may be odd)
+            const int i0 = wrap_col(2 * I - 1, F.nx), i1 = 2 * I, i2 = wrap_col(2 * I + 1, F.nx),
+                      i3 = wrap_col(2 * I + 2, F.nx);
             T rows[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 2 * J - 1 + q;
                 rows[q] = T(0);
-                if (j >= 0 && j < F.ny) {
+                if (j >= 0 && j < F.ny) {  // rows beyond the walls carry no residual
                     const T* r = F.alt + j * F.nx;
-                    rows[q] = (wa * r[im] + wb * r[2 * I]) + (wb * r[2 * I + 1] + wa * r[i3]);
+                    rows[q] = (wa * r[i0] + wb * r[i1]) + (wb * r[i2] + wa * r[i3]);
                 }
             }
             Cc.f[t] = (wa * rows[0] + wb * rows[1]) + (wb * rows[2] + wa * rows[3]);
@@ -842,7 +874,9 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
     }
     {
         const TailLevel<T> S = tail_view(tl, dv, base, tl.n - 1);
-        if (S.ny <= 4)
+        // four colours need an even width: on an odd periodic row the first and last
+        // nodes share a colour and neighbour each other
+        if (S.ny <= 4 || (S.nx & 1))
             tail_jacobi(S, 2 * tl.coarse_sweeps);
         else
             tail_sor(S, tl.coarse_sweeps, tl.omega);

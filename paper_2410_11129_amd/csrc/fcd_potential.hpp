@@ -27,16 +27,16 @@ struct MgEval {
 template <typename T>
 __device__ __forceinline__ MgEval<T> mg_eval_nb(const PotLevel<T>& L, const Nb9<T>& m, Nb9<T> u, int j, T fval) {
 #pragma clang fp contract(off)
-    const T k = L.kappa;
+    const T k = L.kappa, kt = L.kappa_top;
     if (j == 0) {
         u.s = -k * u.s;
         u.sw = -k * u.sw;
         u.se = -k * u.se;
     }
     if (j == L.ny - 1) {
-        u.n = -k * u.n;
-        u.ne = -k * u.ne;
-        u.nw = -k * u.nw;
+        u.n = -kt * u.n;
+        u.ne = -kt * u.ne;
+        u.nw = -kt * u.nw;
     }
     const T a = L.inv_h2 * (T(1) / T(3)), d = L.inv_h2 * (T(1) / T(12));
     const T ce = a * (m.c + m.e), cw = a * (m.c + m.w), cn = a * (m.c + m.n), cs = a * (m.c + m.s);
@@ -44,7 +44,7 @@ __device__ __forceinline__ MgEval<T> mg_eval_nb(const PotLevel<T>& L, const Nb9<
     MgEval<T> r;
     r.C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
     r.acc = (fma(ce, u.e, cw * u.w) + fma(cn, u.n, cs * u.s)) + (fma(cne, u.ne, csw * u.sw) + fma(cnw, u.nw, cse * u.se));
-    r.cself = (j == 0 ? k * cs : T(0)) + (j == L.ny - 1 ? k * cn : T(0));
+    r.cself = (j == 0 ? k * cs : T(0)) + (j == L.ny - 1 ? kt * cn : T(0));
     if (L.f) {
         r.rhs = fval;
     } else {

@@ -96,6 +96,28 @@ def test_moments_parity():
         assert np.abs(gm[k] - om[k]).max() < 1e-11, k
 
 
+@pytest.mark.parametrize("nx,ny", [(90, 15), (200, 75), (200, 97), (226, 37), (130, 19), (900, 150)])
+def test_potential_parity_odd_hierarchy(nx, ny):
+    """Multigrid on lattices whose hierarchy passes odd sizes (coarse levels of
+    ceil(nx/2) x floor or ceil(ny/2) nodes, the upper ghost rule from the wall distance, odd periodic
+    widths, a fine row above the coarse grid or alone under a coarse row; 900 x 150 is the
+    paper's open-channel lattice: seven levels, odd from the second on, the last three in the
+    LDS tail) against the oracle's direct solve, from a cold start to 1e-13 H0."""
+    w = ragged_workload(nx=nx, ny=ny, drive_G=channel_drive(0.01, 1.0, 0.8, ny))
+    say(f"case potential odd hierarchy {nx}x{ny}")
+    fields = random_phase_fields(nx, ny, seed=16)
+    g = Channel(w, **MG_TIGHT)
+    g.init_fields(*fields)
+    st, cycles, res = g.solve_potential(1e-13)
+    say(f"  {cycles} V-cycles, residual {res:.2e}")
+    assert st == fcd.FCD_OK and res <= 1e-13 * w.H0
+    # a contraction of ~0.15 per cycle reaches 1e-13 from the cold start in ~16 cycles
+    assert cycles <= 30, cycles
+    s = OracleSim(w)
+    s.init_fields(*fields)
+    assert np.abs(g.psi_dense() - s.psi).max() < 1e-11
+
+
 @pytest.mark.parametrize("contrast", [False, True])
 def test_short_run_parity_ragged(contrast):
     kw = dict(rho=(2.0, 1.0, 1.0), tau=(1.0, 0.25, 0.25)) if contrast else {}
@@ -175,9 +197,10 @@ def test_no_field_gives_zero_potential():
 @pytest.mark.parametrize("nx,ny,solver", [(4, 2, "sor"), (6, 3, "sor"), (130, 5, "sor"), (4, 2, "mg"),
                                           (130, 5, "mg"), (256, 96, "mg"), (200, 97, "mg"), (320, 80, "mg")])
 def test_degenerate_lattices(nx, ny, solver):
-    """Smallest lattices, odd ny (no coarsening possible), a multigrid hierarchy that
-    stops on an odd coarse level (96 -> 48 -> 24 -> ... ) and one whose coarsest level has
-    five rows (80 -> ... -> 5: the LDS tail ends in SOR sweeps) against the oracle."""
+    """Smallest lattices, odd ny (three rows: no coarse level; five: one coarse level of
+    two rows and odd width 65), hierarchies through odd levels (97 -> 48 -> ... -> 3,
+    with an odd finest level; 96 -> 48 -> ... -> 3) and one through five rows
+    (80 -> ... -> 5 -> 2) against the oracle."""
     w = ragged_workload(nx=nx, ny=ny, drive_G=channel_drive(0.01, 1.0, 0.8, ny))
     say(f"case degenerate {nx}x{ny} solver={solver}")
     fields = random_phase_fields(nx, ny, seed=15)
