@@ -1017,7 +1017,41 @@ struct BatchLayout {
     size_t off_slist = 0;
     size_t off_res = 0, off_active = 0, off_counts = 0, off_sweeps = 0, off_div = 0;
     size_t off_rows = 0, off_cent = 0, off_result = 0;
+    // batched multigrid: every channel's hierarchy (as a single channel's), its FP32 coarse
+    // planes from off_mgc[k] on, the descriptors, the job lists and one residual slot
+    // (two words) per channel; mg_ok: every channel has a coarse level and a tail
+    bool mg_ok = false;
+    int mg_lmax = 0;
+    std::vector<MgPlan> mg;
+    std::vector<size_t> off_mgc;
+    size_t off_mgchan = 0, off_jobs = 0, off_mgres = 0, off_mgcycles = 0;
+    std::vector<fcd::MgJob> jobs;
+    int fine0 = 0, nfine = 0;                                   // level-0 64 x 16 tiles
+    int mu0[4] = {}, nmu[4] = {};                              // mu groups 1..3 (group 0: the fine list)
+    int rs0[MAX_LEVELS] = {}, nrs[MAX_LEVELS] = {};            // restriction + pre-smoothing into level l
+    int rt00 = 0, nrt0 = 0, rtC0 = 0, nrtC = 0;                // restriction into the tail
+    int post0[MAX_LEVELS] = {}, npost[MAX_LEVELS] = {};        // prolongation + post-smoothing of level l
 };
+
+// Offsets (relative to a channel's multigrid region) of the FP32 planes mu, u, f of its
+// levels 1 .. levels-1 and the smoothers' second plane t of the tiled levels; returns
+// the region's size.
+size_t mg_region(const MgPlan& p, size_t off_mu[], size_t off_u[], size_t off_f[], size_t off_t[]) {
+    size_t off = 0;
+    for (int l = 1; l < p.levels; ++l) {
+        const size_t plane = align256((size_t)p.ny[l] * p.pitch[l] * sizeof(CT));
+        off_mu[l] = off;
+        off_u[l] = off + plane;
+        off_f[l] = off + 2 * plane;
+        off += 3 * plane;
+        off_t[l] = 0;
+        if (l < p.tail) {
+            off_t[l] = off;
+            off += plane;
+        }
+    }
+    return off;
+}
 
 fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     if (n < 1 || n > BATCH_MAX_CHANNELS) return fail(FCD_ERR_ARG, "a batch holds 1 to 65536 channels");
@@ -1097,6 +1131,72 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     off = align256(off + 32 * sizeof(double));
     L->off_result = off;
     off = align256(off + (size_t)n * 4 * sizeof(double));
+    // batched multigrid
+    L->mg_ok = true;
+    for (int k = 0; k < n; ++k) {
+        fcd_lattice lk = lats[k];
+        lk.pitch = L->pitch[k];
+        L->mg.push_back(make_plan(lk));
+        const MgPlan& p = L->mg.back();
+        if (p.levels < 2 || p.tail >= p.levels) L->mg_ok = false;
+        L->mg_lmax = std::max(L->mg_lmax, p.levels);
+    }
+    if (L->mg_ok) {
+        size_t a_mu[MAX_LEVELS], a_u[MAX_LEVELS], a_f[MAX_LEVELS], a_t[MAX_LEVELS];
+        for (int k = 0; k < n; ++k) {
+            L->off_mgc.push_back(off);
+            off = align256(off + mg_region(L->mg[k], a_mu, a_u, a_f, a_t));
+        }
+        const size_t chan_sz = prec == FCD_FP64 ? sizeof(fcd::MgChan<double, CT>) : sizeof(fcd::MgChan<float, CT>);
+        L->off_mgchan = off;
+        off = align256(off + (size_t)n * chan_sz);
+        // job lists, in launch order of a V-cycle
+        auto tiles = [&](int k, int l, int sx, int sy) {
+            const MgPlan& p = L->mg[k];
+            const int tx = (p.nx[l] + sx - 1) / sx, ty = (p.ny[l] + sy - 1) / sy;
+            for (int by = 0; by < ty; ++by)
+                for (int bx = 0; bx < tx; ++bx) L->jobs.push_back({k, l, bx, by});
+        };
+        L->fine0 = (int)L->jobs.size();
+        for (int k = 0; k < n; ++k) tiles(k, 0, 64, 16);
+        L->nfine = (int)L->jobs.size() - L->fine0;
+        for (int g = 1; g < 4; ++g) {  // mu of levels 4g+1 .. from level 4g (64 x 16 tiles)
+            L->mu0[g] = (int)L->jobs.size();
+            for (int k = 0; k < n; ++k)
+                if (L->mg[k].levels - 1 > 4 * g) {
+                    const size_t first = L->jobs.size();
+                    tiles(k, 4 * g, 64, 16);
+                    for (size_t q = first; q < L->jobs.size(); ++q) L->jobs[q].l = g;
+                }
+            L->nmu[g] = (int)L->jobs.size() - L->mu0[g];
+        }
+        for (int l = 1; l < L->mg_lmax; ++l) {  // coarse 32 x 8 tiles of the tiled levels
+            L->rs0[l] = (int)L->jobs.size();
+            for (int k = 0; k < n; ++k)
+                if (l < L->mg[k].tail) tiles(k, l, 32, 8);
+            L->nrs[l] = (int)L->jobs.size() - L->rs0[l];
+        }
+        L->rt00 = (int)L->jobs.size();
+        for (int k = 0; k < n; ++k)
+            if (L->mg[k].tail == 1) tiles(k, 0, 64, 16);
+        L->nrt0 = (int)L->jobs.size() - L->rt00;
+        L->rtC0 = (int)L->jobs.size();
+        for (int k = 0; k < n; ++k)
+            if (L->mg[k].tail >= 2) tiles(k, L->mg[k].tail - 1, 32, 8);
+        L->nrtC = (int)L->jobs.size() - L->rtC0;
+        for (int l = 1; l < L->mg_lmax; ++l) {
+            L->post0[l] = (int)L->jobs.size();
+            for (int k = 0; k < n; ++k)
+                if (l < L->mg[k].tail) tiles(k, l, 32, 8);
+            L->npost[l] = (int)L->jobs.size() - L->post0[l];
+        }
+        L->off_jobs = off;
+        off = align256(off + L->jobs.size() * sizeof(fcd::MgJob));
+        L->off_mgres = off;
+        off = align256(off + 2 * (size_t)n * sizeof(unsigned long long));
+        L->off_mgcycles = off;
+        off = align256(off + (size_t)n * sizeof(int));
+    }
     L->scratch_bytes = off;
     return FCD_OK;
 }
@@ -1137,6 +1237,11 @@ struct fcd_batch {
     std::vector<int> adj_ckpt;  // (last_iters, hist) per checkpoint
     int adj_final_iters, adj_final_hist;
     int adj_solve_iters;        // sweeps of the previous adjoint potential solve
+    // batched multigrid for the forward potential (channel 0 asks for FCD_SOLVER_MG and
+    // every channel has a hierarchy with a tail)
+    bool mg;
+    size_t mg_lds;       // dynamic LDS of the batched tail launch (largest channel's tail)
+    int mg_last_cycles;  // graph-launched cycles the previous solve needed
 };
 
 namespace {
@@ -1230,6 +1335,62 @@ fcd_status batch_read_divergence(fcd_batch* b) {
     return FCD_OK;
 }
 
+// Channel k's multigrid descriptor: the single-channel hierarchy of its lattice over the
+// batch's planes (psi', mu_r and the second potential plane as the finest level's
+// ping-pong plane) and its FP32 coarse planes.
+template <typename T>
+fcd::MgChan<T, CT> make_mgchan(const fcd_batch* b, int k) {
+    fcd::MgChan<T, CT> c{};
+    const MgPlan& p = b->L.mg[k];
+    const fcd_params& prm = b->prm[k];
+    const fcd::BatchInst<T> I = make_batch_inst<T>(b, k);
+    c.L0 = I.L0;
+    c.t0 = I.alt;
+    size_t a_mu[MAX_LEVELS], a_u[MAX_LEVELS], a_f[MAX_LEVELS], a_t[MAX_LEVELS];
+    mg_region(p, a_mu, a_u, a_f, a_t);
+    char* base = b->scratch + b->L.off_mgc[k];
+    for (int l = 1; l < p.levels; ++l) {
+        const double hh = double(1 << l);
+        fcd::PotLevel<CT>& L = c.C[l];
+        L.nx = p.nx[l];
+        L.ny = p.ny[l];
+        L.pitch = p.pitch[l];
+        L.mu = reinterpret_cast<const CT*>(base + a_mu[l]);
+        L.u = reinterpret_cast<CT*>(base + a_u[l]);
+        L.f = reinterpret_cast<CT*>(base + a_f[l]);
+        L.inv_h2 = CT(1.0 / (hh * hh));
+        L.kappa = CT((hh - 1.0) / (hh + 1.0));
+        L.kappa_top = CT(p.kappa_top[l]);
+        c.t[l] = l < p.tail ? reinterpret_cast<CT*>(base + a_t[l]) : nullptr;
+    }
+    c.tl.n = p.levels - p.tail;
+    for (int q = 0; q < c.tl.n; ++q) {
+        c.tl.lv[q] = c.C[p.tail + q];
+        c.dv.inv[q] = (unsigned)(((1ull << 32) + p.nx[p.tail + q] - 1) / p.nx[p.tail + q]);
+    }
+    c.tl.nu1 = c.tl.nu2 = 1;
+    const int nyc = p.ny[p.levels - 1], cs = prm.pot_coarse_sweeps;
+    c.tl.coarse_sweeps = cs < 0 ? -cs : cs * std::max(1, nyc / 2);
+    c.tl.omega = CT(sor_omega_opt(nyc));
+    c.levels = p.levels;
+    c.tail = p.tail;
+    c.thr = prm.pot_tol * std::fabs(prm.H0);
+    return c;
+}
+
+template <typename T>
+fcd_status batch_upload_mg(fcd_batch* b) {
+    if (!b->L.mg_ok) return FCD_OK;
+    std::vector<fcd::MgChan<T, CT>> ch(b->n);
+    b->mg_lds = 0;
+    for (int k = 0; k < b->n; ++k) {
+        ch[k] = make_mgchan<T>(b, k);
+        b->mg_lds = std::max(b->mg_lds, fcd::mg_tail_lds_bytes<CT>(ch[k].tl));
+    }
+    return hip_check(hipMemcpy(b->scratch + b->L.off_mgchan, ch.data(), ch.size() * sizeof(ch[0]),
+                               hipMemcpyHostToDevice), "multigrid descriptor upload");
+}
+
 // Re-uploads the channel descriptors after a parameter change (after the batch's queued
 // work, which reads them, has finished).
 template <typename T>
@@ -1240,6 +1401,7 @@ fcd_status batch_upload_inst(fcd_batch* b) {
     if (!st)
         st = hip_check(hipMemcpy(b->scratch + b->L.off_inst, inst.data(), inst.size() * sizeof(inst[0]),
                                  hipMemcpyHostToDevice), "descriptor upload");
+    if (!st) st = batch_upload_mg<T>(b);
     return st;
 }
 
@@ -1283,8 +1445,20 @@ fcd_status batch_upload(fcd_batch* b) {
                    "active tile list");
     if (st) return st;
     // residual slots start (and are always left) at zero
-    return hip_check(hipMemset(b->scratch + b->L.off_res, 0, 6 * (size_t)b->n * sizeof(unsigned long long)),
-                     "residual slots");
+    st = hip_check(hipMemset(b->scratch + b->L.off_res, 0, 6 * (size_t)b->n * sizeof(unsigned long long)),
+                   "residual slots");
+    if (st || !b->L.mg_ok) return st;
+    st = batch_upload_mg<T>(b);
+    if (!st)
+        st = hip_check(hipMemcpy(b->scratch + b->L.off_jobs, b->L.jobs.data(), b->L.jobs.size() * sizeof(fcd::MgJob),
+                                 hipMemcpyHostToDevice), "multigrid job upload");
+    if (!st)
+        st = hip_check(hipMemset(b->scratch + b->L.off_mgres, 0, 2 * (size_t)b->n * sizeof(unsigned long long)),
+                       "multigrid residual slots");
+    if (!st)
+        st = hip_check(hipMemset(b->scratch + b->L.off_mgcycles, 0, (size_t)b->n * sizeof(int)),
+                       "multigrid cycle counts");
+    return st;
 }
 
 template <typename T>
@@ -1435,6 +1609,90 @@ fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
     return FCD_OK;
 }
 
+// Batched multigrid.  One V-cycle of every active channel (the single-channel cycle:
+// pot_smooth finest sweeps, of which the first also reduces its input's residual into
+// the channel's slot, restriction with pre-smoothing down the tiled levels, the tail,
+// prolongation with post-smoothing back up, pot_smooth finest sweeps), with the
+// convergence decision taken on the device after the first sweep: a channel whose input
+// already meets its threshold stops there (its psi' plane untouched, the sweep's output
+// in the second plane discarded), so every channel receives exactly the cycles its own
+// single-channel solve would, whatever the batch.
+constexpr int BMG_INNER = 2;            // tile sweeps per launch on the tiled coarse levels
+constexpr int BMG_BLOCK_CYCLES = 2;     // V-cycles per graph launch
+
+template <typename T>
+void bmg_cycle(fcd_batch* b) {
+    const BatchLayout& L = b->L;
+    const auto* ch = reinterpret_cast<const fcd::MgChan<T, CT>*>(b->scratch + L.off_mgchan);
+    const auto* jobs = reinterpret_cast<const fcd::MgJob*>(b->scratch + L.off_jobs);
+    int* active = bptr<int>(b->scratch, b->L.off_active);
+    unsigned long long* res = bptr<unsigned long long>(b->scratch, L.off_mgres);
+    int* cycles = bptr<int>(b->scratch, L.off_mgcycles);
+    int* counts = bptr<int>(b->scratch, L.off_counts);
+    hipStream_t st = b->stream;
+    const int nu = std::max(1, b->prm[0].pot_smooth);
+    const fcd::MgJob* fine = jobs + L.fine0;
+    // pre-smoothing: sweep q reads the plane the previous one wrote (q even: psi' -> second)
+    int cur = 0;  // plane holding the current finest iterate: 0 psi', 1 the second plane
+    for (int q = 0; q < nu; ++q) {
+        fcd::launch_bmg_smooth_fine<T, CT>(ch, fine, L.nfine, active, cur, false, q == 0 ? res : nullptr, st);
+        cur = 1 - cur;
+        if (q == 0) fcd::launch_bmg_decide<T, CT>(ch, b->n, res, active, cycles, counts, resid_floor_factor<T>(), st);
+    }
+    for (int l = 1; l < L.mg_lmax; ++l)
+        if (L.nrs[l]) fcd::launch_bmg_restrict_smooth<T, CT>(ch, jobs + L.rs0[l], L.nrs[l], active, l, cur, BMG_INNER, st);
+    if (L.nrt0) fcd::launch_bmg_restrict_tail<T, CT>(ch, jobs + L.rt00, L.nrt0, active, true, cur, st);
+    if (L.nrtC) fcd::launch_bmg_restrict_tail<T, CT>(ch, jobs + L.rtC0, L.nrtC, active, false, cur, st);
+    fcd::launch_bmg_tail<T, CT>(ch, b->n, b->mg_lds, active, st);
+    for (int l = L.mg_lmax - 1; l >= 1; --l)
+        if (L.npost[l]) fcd::launch_bmg_post_coarse<T, CT>(ch, jobs + L.post0[l], L.npost[l], active, BMG_INNER, st);
+    for (int q = 0; q < nu; ++q) {
+        fcd::launch_bmg_smooth_fine<T, CT>(ch, fine, L.nfine, active, cur, q == 0, nullptr, st);
+        cur = 1 - cur;
+    }
+    if (cur) fcd::launch_bmg_copy_fine<T, CT>(ch, fine, L.nfine, active, st);
+}
+
+// Potential solves of every channel by batched V-cycles: the coarse mu of every level,
+// then graph launches of BMG_BLOCK_CYCLES cycles until no channel is active; the host
+// reads the active count after each launch, except for the launches the previous solve
+// needed minus one.
+template <typename T>
+fcd_status batch_solve_mg(fcd_batch* b, int max_iters) {
+    const BatchLayout& L = b->L;
+    const auto* ch = reinterpret_cast<const fcd::MgChan<T, CT>*>(b->scratch + L.off_mgchan);
+    const auto* jobs = reinterpret_cast<const fcd::MgJob*>(b->scratch + L.off_jobs);
+    fcd::launch_bmg_mu4<T, CT>(ch, jobs + L.fine0, L.nfine, 0, b->stream);
+    for (int g = 1; g < 4; ++g)
+        if (L.nmu[g]) fcd::launch_bmg_mu4<T, CT>(ch, jobs + L.mu0[g], L.nmu[g], g, b->stream);
+    fcd::launch_fill<int>(bptr<int>(b->scratch, L.off_active), b->n, 1, b->stream);
+    fcd_status st = hip_check(hipGetLastError(), "batch multigrid launch");
+    if (st) return st;
+    const int G = BMG_BLOCK_CYCLES;
+    int blind = b->mg_last_cycles > G ? (b->mg_last_cycles + G - 1) / G - 1 : 0;
+    int left = 1, it = 0;
+    while (left > 0) {
+        if (it >= max_iters) break;
+        st = run_graph_on(b->graphs, b->stream, false, ch, jobs, (7 << 24) + std::max(1, b->prm[0].pot_smooth),
+                          [&]() {
+                              for (int c = 0; c < G; ++c) bmg_cycle<T>(b);
+                          });
+        if (st) return st;
+        it += G;
+        if (blind > 0) {
+            --blind;
+            continue;
+        }
+        st = batch_read_counts<T>(b, &left);
+        if (st) return st;
+    }
+    b->iters += it;
+    b->mg_last_cycles = it;
+    b->last_resid = 0.0;
+    if (left > 0) return fail(FCD_ERR_NOT_CONVERGED, "a channel's potential solve reached pot_max_iters");
+    return FCD_OK;
+}
+
 template <typename T>
 fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
     const fcd_params& p0 = b->prm[0];
@@ -1446,7 +1704,8 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
         if (b->qs % std::max(1, p0.pot_every) == 0) {  // quasi-static coupling, as fcd_step
             if (p0.pot_extrapolate)
                 fcd::launch_batch_psi_history<T>(binst<T>(b), t, b->hist >= 2 ? 1 : 0, b->stream);
-            st = batch_solve<T>(b, forward_problem<T>(b), p0.pot_max_iters);
+            st = b->mg ? batch_solve_mg<T>(b, p0.pot_max_iters)
+                       : batch_solve<T>(b, forward_problem<T>(b), p0.pot_max_iters);
             if (st) return st;
             ++b->hist;
         }
@@ -2485,6 +2744,9 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     b->last_resid = 0.0;
     b->shape = 2;  // 64 x 4 tiles
     b->init_fresh = 0;
+    b->mg = prms[0].pot_solver == FCD_SOLVER_MG && L.mg_ok;
+    b->mg_lds = 0;
+    b->mg_last_cycles = 0;
     b->adj_work = nullptr;
     b->adj_nsteps = b->adj_every = b->adj_from_init = 0;
     b->adj_final_iters = b->adj_final_hist = b->adj_solve_iters = 0;

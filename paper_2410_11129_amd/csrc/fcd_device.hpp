@@ -74,6 +74,35 @@ struct MgTail {
     T omega;  // SOR factor of the coarsest-level sweeps
 };
 
+// ceil(2^32 / nx) of every tail level (see fcd_potential.hip).
+struct TailDiv {
+    unsigned inv[MG_MAX_TAIL];
+};
+
+// Levels of a multigrid hierarchy at most.
+constexpr int MG_MAX_LEVELS = 16;
+
+// One channel's multigrid hierarchy as the batched multigrid kernels see it (device
+// memory): the finest level (u = psi', mu = mu_r, f = nullptr) and its ping-pong plane,
+// the FP32 coarse levels 1 .. levels-1 with the smoothers' second planes, and the tail
+// (levels tail .. levels-1) with its divisors.  Levels 1 .. tail-1 are smoothed by tiles.
+template <typename T, typename TC>
+struct MgChan {
+    PotLevel<T> L0;
+    T* t0;
+    PotLevel<TC> C[MG_MAX_LEVELS];
+    TC* t[MG_MAX_LEVELS];
+    MgTail<TC> tl;
+    TailDiv dv;
+    int levels, tail;
+    double thr;  // the channel stops when max |residual| <= max(thr, rounding floor)
+};
+
+// A block's work in a batched multigrid launch: channel k, level l, tile (bx, by).
+struct MgJob {
+    int k, l, bx, by;
+};
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ a, long long n, T v) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -91,13 +91,13 @@ __global__ void __launch_bounds__(RES_T) k_pot_residual(PotLevel<T> L, unsigned 
 constexpr int MU_TX = 64, MU_TY = 16;
 
 template <typename T, typename TC>
-__global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* __restrict__ muf, int pitchf, int nxf,
-                                                                        int nyf, MuLevels<TC> C) {
+__device__ __forceinline__ void mg_restrict_mu4_tile(const T* __restrict__ muf, int pitchf, int nxf, int nyf,
+                                                     const MuLevels<TC>& C, int bx, int by) {
     constexpr int NT = MU_TX * MU_TY / 4;
     __shared__ T s0[MU_TY][MU_TX];
     __shared__ TC sa[MU_TY / 2][MU_TX / 2];
     __shared__ TC sb[MU_TY / 4][MU_TX / 4];
-    const int i0 = blockIdx.x * MU_TX, j0 = blockIdx.y * MU_TY, tid = threadIdx.x;
+    const int i0 = bx * MU_TX, j0 = by * MU_TY, tid = threadIdx.x;
     T v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -143,6 +143,12 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* _
         dst = tmp;
         sx = cx;
     }
+}
+
+template <typename T, typename TC>
+__global__ void __launch_bounds__(MU_TX* MU_TY / 4) k_mg_restrict_mu4(const T* __restrict__ muf, int pitchf, int nxf,
+                                                                        int nyf, MuLevels<TC> C) {
+    mg_restrict_mu4_tile<T, TC>(muf, pitchf, nxf, nyf, C, blockIdx.x, blockIdx.y);
 }
 
 // Bilinear interpolation of the coarse correction at fine node (i, j): weights 9/16,
@@ -302,20 +308,19 @@ __device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int
 }
 
 template <typename T, typename G, bool PROLONG, int MODE, typename TC>
-__global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
-                                                          T* __restrict__ uout, PotLevel<TC> Cl,
-                                                          unsigned long long* __restrict__ res,
-                                                          unsigned long long* __restrict__ res_clear, int inner) {
+__device__ __forceinline__ void mg_smooth_tile(const PotLevel<T>& L, const T* __restrict__ uin, T* __restrict__ uout,
+                                               const PotLevel<TC>& Cl, unsigned long long* __restrict__ res,
+                                               unsigned long long* __restrict__ res_clear, int inner, int bx, int by) {
     constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT, CX = G::CX, CY = G::CY;
     // the next test's (other) residual slot, zeroed for it: the kernel boundary orders this
     // store before that test's atomics, and the host has read that slot before this launch
-    if (res_clear && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) res_clear[threadIdx.x] = 0ULL;
+    if (res_clear && bx == 0 && by == 0 && threadIdx.x < 2) res_clear[threadIdx.x] = 0ULL;
     __shared__ T su[HY][HX];
     __shared__ T sm[HY][HX];
     __shared__ T sf[MODE == 1 ? 1 : SY][SX];
     __shared__ T sc[PROLONG ? CY : 1][CX];
     __shared__ double wmax[2][NT / 64];
-    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * SY;
+    const int i0 = bx * SX, j0 = by * SY;
     const int tid = threadIdx.x;
     T uv[G::HPER], mv[G::HPER], fv[G::FPER], cv[G::CPER];
     load_tile<T, G>(L, uin, i0, j0, uv, mv);
@@ -418,6 +423,14 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
     }
 }
 
+template <typename T, typename G, bool PROLONG, int MODE, typename TC>
+__global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T* __restrict__ uin,
+                                                          T* __restrict__ uout, PotLevel<TC> Cl,
+                                                          unsigned long long* __restrict__ res,
+                                                          unsigned long long* __restrict__ res_clear, int inner) {
+    mg_smooth_tile<T, G, PROLONG, MODE, TC>(L, uin, uout, Cl, res, res_clear, inner, blockIdx.x, blockIdx.y);
+}
+
 // Residual restriction.  The coarse right-hand side at coarse node (I, J) is the
 // transpose of the bilinear prolongation applied to the fine residual: weights
 // (1, 3, 3, 1)/8 along each axis over fine columns 2I-1 .. 2I+2 (periodic) and rows
@@ -510,13 +523,13 @@ __device__ __forceinline__ T restrict16(const T (*sr)[RX], int cx, int cy) {
 // above the coarse grid enters the last coarse row with the weight of row 2J+2), and fine
 // columns wrap over the fine width.
 template <typename T, typename G, int MODE, typename TC>
-__global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
+__device__ __forceinline__ void mg_restrict_tile(const PotLevel<T>& F, const PotLevel<TC>& Cl, int bx, int by) {
     using R = RestrictGeom<G>;
     constexpr int SX = G::SX, NT = G::NT;
     __shared__ T fu[R::FY][R::FX];
     __shared__ T fm[R::FY][R::FX];
     __shared__ T sr[R::RY][R::RX];
-    const int i0 = blockIdx.x * SX, j0 = blockIdx.y * G::SY;
+    const int i0 = bx * SX, j0 = by * G::SY;
     const int tid = threadIdx.x;
     T uv[R::FPER], mv[R::FPER], fv[R::RPER];
     restrict_loads<T, G, MODE>(F, i0, j0, uv, mv, fv);
@@ -540,6 +553,11 @@ __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLe
     }
 }
 
+template <typename T, typename G, int MODE, typename TC>
+__global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
+    mg_restrict_tile<T, G, MODE, TC>(F, Cl, blockIdx.x, blockIdx.y);
+}
+
 // Residual restriction fused with the first pre-smoothing of the coarse level below it.
 // One block owns a 32 x 8 coarse tile: it stages the matching 64 x 16 tile of the
 // smoothed fine iterate and of the fine mu with a two-node halo, forms the fine
@@ -550,8 +568,8 @@ __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLe
 // arithmetic as k_mg_restrict_tile followed by k_mg_smooth_tile, one launch fewer.
 // Coarse sizes as in k_mg_restrict_tile.
 template <typename T, int FMODE, typename TC>
-__global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<TC> C,
-                                                                     TC* __restrict__ uout, int inner) {
+__device__ __forceinline__ void mg_restrict_smooth(const PotLevel<T>& F, const PotLevel<TC>& C, TC* __restrict__ uout,
+                                                   int inner, int bx, int by) {
     // fine part on the fine tile's 256 threads (loads staged in registers, issued
     // together); coarse smoothing by the first 64, one coarse node per colour each
     using G = CoarseTile;
@@ -565,7 +583,7 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
     __shared__ TC su[G::HY][G::HX];
     __shared__ TC sm[G::HY][G::HX];
     __shared__ TC sf[SY][SX];
-    const int I0 = blockIdx.x * SX, J0 = blockIdx.y * SY;  // coarse tile origin
+    const int I0 = bx * SX, J0 = by * SY;  // coarse tile origin
     const int i0 = 2 * I0, j0 = 2 * J0;                    // fine tile origin
     const int tid = threadIdx.x;
     const int cy = tid / SX, cx = tid - cy * SX;  // this thread's coarse node
@@ -625,6 +643,12 @@ __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T>
     if (I0 + cx < C.nx && J0 + cy < C.ny) uout[(long long)(J0 + cy) * C.pitch + I0 + cx] = su[cy + 1][cx + 1];
 }
 
+template <typename T, int FMODE, typename TC>
+__global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<TC> C,
+                                                                     TC* __restrict__ uout, int inner) {
+    mg_restrict_smooth<T, FMODE, TC>(F, C, uout, inner, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------------
 // Tail of the V-cycle: the coarsest levels, all in LDS, by one block.  Level 0 of the
 // tail takes its right-hand side from global memory (written by the restriction above
@@ -654,13 +678,10 @@ struct TailLevel {
     T *d, *rd;
 };
 
-// ceil(2^32 / nx) of every tail level (2 <= nx, as coarse levels have), from the host:
-// for t < TAIL_MAXN and nx < 2^20, t / nx is the high word of t * inv (the rounding up
-// adds less than t / 2^32 < 1 / nx to t / nx), one multiply in place of an integer
-// division in every node loop of the tail.
-struct TailDiv {
-    unsigned inv[MG_MAX_TAIL];
-};
+// TailDiv holds ceil(2^32 / nx) of every tail level (2 <= nx, as coarse levels have), from
+// the host: for t < TAIL_MAXN and nx < 2^20, t / nx is the high word of t * inv (the
+// rounding up adds less than t / 2^32 < 1 / nx to t / nx), one multiply in place of an
+// integer division in every node loop of the tail.
 
 __device__ __forceinline__ int tail_div(int t, unsigned inv) { return (int)__umulhi((unsigned)t, inv); }
 
@@ -774,7 +795,7 @@ constexpr int TAIL_MAXN = 4096;
 constexpr int TAIL_LPER = TAIL_MAXN / TAIL_T;
 
 template <typename T>
-__global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
+__device__ __forceinline__ void mg_tail(const MgTail<T>& tl, const TailDiv& dv) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* base = reinterpret_cast<T*>(lds_raw);
     const int tid = threadIdx.x;
@@ -900,6 +921,11 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
         const int j = tail_div(t, S.inv), i = t - j * S.nx;
         G.u[(long long)j * G.pitch + i] = S.u[t];
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
+    mg_tail<T>(tl, dv);
 }
 
 // Warm start from the recorded solutions: mode 0 keeps psi' and records it; mode 1
@@ -1036,6 +1062,275 @@ void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, in
     hipLaunchKernelGGL(k_psi_history<T>, pgrid(nx, ny), dim3(PX, PY), 0, s, psi, prev, prev2, nx, ny, pitch, mode);
 }
 
+// ---------------------------------------------------------------------------------
+// Batched multigrid: the tile kernels above, one launch for one level of every channel
+// of a batch.  Block b works on jobs[b] (channel k, level l, tile bx, by) with channel
+// k's descriptors; a channel whose flag in `active` is 0 has converged and its blocks
+// return at once (uniformly, before any barrier).  A channel's V-cycle is the
+// single-channel one (finest tiles 64 x 16).
+// ---------------------------------------------------------------------------------
+
+// Finest-level sweep: dir 0 reads L0.u and writes t0, dir 1 the reverse; PROLONG adds
+// level 1's correction to the input first; res != nullptr: max |residual| and max |C u|
+// of the input into res[2k], res[2k+1].
+template <typename T, bool PROLONG, typename TC>
+__global__ void __launch_bounds__(FineTile::NT) kbm_smooth_fine(const MgChan<T, TC>* __restrict__ ch,
+                                                                const MgJob* __restrict__ jobs,
+                                                                const int* __restrict__ active, int dir,
+                                                                unsigned long long* __restrict__ res) {
+    const MgJob J = jobs[blockIdx.x];
+    if (!active[J.k]) return;
+    const MgChan<T, TC>& c = ch[J.k];
+    const PotLevel<T> L = c.L0;
+    const PotLevel<TC> Cl = c.C[1];
+    const T* uin = dir ? c.t0 : L.u;
+    T* uout = dir ? L.u : c.t0;
+    mg_smooth_tile<T, FineTile, PROLONG, 1, TC>(L, uin, uout, Cl, res ? res + 2 * J.k : nullptr, nullptr, 1, J.bx,
+                                                J.by);
+}
+
+// Copy of t0 into L0.u (a finest-level iterate that ended in the ping-pong plane).
+template <typename T, typename TC>
+__global__ void __launch_bounds__(FineTile::NT) kbm_copy_fine(const MgChan<T, TC>* __restrict__ ch,
+                                                              const MgJob* __restrict__ jobs,
+                                                              const int* __restrict__ active) {
+    const MgJob J = jobs[blockIdx.x];
+    if (!active[J.k]) return;
+    const MgChan<T, TC>& c = ch[J.k];
+    const PotLevel<T> L = c.L0;
+    const T* src = c.t0;
+    for (int q = threadIdx.x; q < FineTile::SX * FineTile::SY; q += FineTile::NT) {
+        const int i = J.bx * FineTile::SX + q % FineTile::SX, j = J.by * FineTile::SY + q / FineTile::SX;
+        if (i < L.nx && j < L.ny) L.u[(long long)j * L.pitch + i] = src[(long long)j * L.pitch + i];
+    }
+}
+
+// Restriction of the finest level's residual (its pre-smoothed iterate in t0 when src,
+// else in L0.u) fused with level 1's pre-smoothing into t[1].
+template <typename T, typename TC>
+__global__ void __launch_bounds__(FineTile::NT) kbm_restrict_smooth0(const MgChan<T, TC>* __restrict__ ch,
+                                                                     const MgJob* __restrict__ jobs,
+                                                                     const int* __restrict__ active, int src,
+                                                                     int inner) {
+    const MgJob J = jobs[blockIdx.x];
+    if (!active[J.k]) return;
+    const MgChan<T, TC>& c = ch[J.k];
+    PotLevel<T> F = c.L0;
+    if (src) F.u = c.t0;
+    const PotLevel<TC> C = c.C[1];
+    mg_restrict_smooth<T, 1, TC>(F, C, c.t[1], inner, J.bx, J.by);
+}
+
+// The same from coarse level l - 1 (pre-smoothed iterate in t[l-1]) into level l (t[l]).
+template <typename TC, typename T>
+__global__ void __launch_bounds__(FineTile::NT) kbm_restrict_smoothC(const MgChan<T, TC>* __restrict__ ch,
+                                                                     const MgJob* __restrict__ jobs,
+                                                                     const int* __restrict__ active, int inner) {
+    const MgJob J = jobs[blockIdx.x];
+    if (!active[J.k]) return;
+    const MgChan<T, TC>& c = ch[J.k];
+    PotLevel<TC> F = c.C[J.l - 1];
+    F.u = c.t[J.l - 1];
+    const PotLevel<TC> C = c.C[J.l];
+    mg_restrict_smooth<TC, 0, TC>(F, C, c.t[J.l], inner, J.bx, J.by);
+}
+
+// Restriction into the first tail level: from the finest level (tail == 1; its iterate
+// in t0 when src) ...
+template <typename T, typename TC>
+__global__ void __launch_bounds__(FineTile::NT) kbm_restrict_tail0(const MgChan<T, TC>* __restrict__ ch,
+                                                                   const MgJob* __restrict__ jobs,
+                                                                   const int* __restrict__ active, int src) {
+    const MgJob J = jobs[blockIdx.x];
+    if (!active[J.k]) return;
+    const MgChan<T, TC>& c = ch[J.k];
+    PotLevel<T> F = c.L0;
+    if (src) F.u = c.t0;
+    const PotLevel<TC> C = c.C[1];
+    mg_restrict_tile<T, FineTile, 1, TC>(F, C, J.bx, J.by);
+}
+
+// ... or from coarse level l = tail - 1 (its iterate in t[l]).
+template <typename TC, typename T>
+__global__ void __launch_bounds__(CoarseTile::NT) kbm_restrict_tailC(const MgChan<T, TC>* __restrict__ ch,
+                                                                     const MgJob* __restrict__ jobs,
+                                                                     const int* __restrict__ active) {
+    const MgJob J = jobs[blockIdx.x];
+    if (!active[J.k]) return;
+    const MgChan<T, TC>& c = ch[J.k];
+    PotLevel<TC> F = c.C[J.l];
+    F.u = c.t[J.l];
+    const PotLevel<TC> C = c.C[J.l + 1];
+    mg_restrict_tile<TC, CoarseTile, 0, TC>(F, C, J.bx, J.by);
+}
+
+// The tail of channel blockIdx.x.
+template <typename TC, typename T>
+__global__ void __launch_bounds__(TAIL_T) kbm_tail(const MgChan<T, TC>* __restrict__ ch,
+                                                   const int* __restrict__ active) {
+    const int k = blockIdx.x;
+    if (!active[k]) return;
+    mg_tail<TC>(ch[k].tl, ch[k].dv);
+}
+
+// Prolongation from level l + 1 fused with level l's post-smoothing, t[l] into C[l].u.
+template <typename TC, typename T>
+__global__ void __launch_bounds__(CoarseTile::NT) kbm_post_coarse(const MgChan<T, TC>* __restrict__ ch,
+                                                                  const MgJob* __restrict__ jobs,
+                                                                  const int* __restrict__ active, int inner) {
+    const MgJob J = jobs[blockIdx.x];
+    if (!active[J.k]) return;
+    const MgChan<T, TC>& c = ch[J.k];
+    const PotLevel<TC> F = c.C[J.l], Cl = c.C[J.l + 1];
+    mg_smooth_tile<TC, CoarseTile, true, 0, TC>(F, c.t[J.l], F.u, Cl, nullptr, nullptr, inner, J.bx, J.by);
+}
+
+// Coarse mu of levels 4g+1 .. 4g+4 (those that exist) from level 4g: the finest level's mu
+// (g == 0, type T) ...
+template <typename T, typename TC>
+__global__ void __launch_bounds__(MU_TX* MU_TY / 4) kbm_mu4_0(const MgChan<T, TC>* __restrict__ ch,
+                                                              const MgJob* __restrict__ jobs) {
+    const MgJob J = jobs[blockIdx.x];
+    const MgChan<T, TC>& c = ch[J.k];
+    MuLevels<TC> M{};
+    M.n = min(4, c.levels - 1);
+    for (int q = 0; q < M.n; ++q) {
+        M.mu[q] = const_cast<TC*>(c.C[1 + q].mu);
+        M.nx[q] = c.C[1 + q].nx;
+        M.ny[q] = c.C[1 + q].ny;
+        M.pitch[q] = c.C[1 + q].pitch;
+    }
+    mg_restrict_mu4_tile<T, TC>(c.L0.mu, c.L0.pitch, c.L0.nx, c.L0.ny, M, J.bx, J.by);
+}
+
+// ... or coarse level 4g (g = J.l >= 1).
+template <typename TC, typename T>
+__global__ void __launch_bounds__(MU_TX* MU_TY / 4) kbm_mu4_C(const MgChan<T, TC>* __restrict__ ch,
+                                                              const MgJob* __restrict__ jobs) {
+    const MgJob J = jobs[blockIdx.x];
+    const MgChan<T, TC>& c = ch[J.k];
+    const int f = 4 * J.l;
+    MuLevels<TC> M{};
+    M.n = min(4, c.levels - 1 - f);
+    for (int q = 0; q < M.n; ++q) {
+        M.mu[q] = const_cast<TC*>(c.C[f + 1 + q].mu);
+        M.nx[q] = c.C[f + 1 + q].nx;
+        M.ny[q] = c.C[f + 1 + q].ny;
+        M.pitch[q] = c.C[f + 1 + q].pitch;
+    }
+    const PotLevel<TC> F = c.C[f];
+    mg_restrict_mu4_tile<TC, TC>(F.mu, F.pitch, F.nx, F.ny, M, J.bx, J.by);
+}
+
+// The convergence decision of every channel, one block: a channel active on entry stays
+// active while its residual (res[2k], the bit pattern of max |r|, and res[2k+1], that of
+// max |C u|) is above max(thr, floor * scale); a NaN residual stops it and is counted.
+// Both words are zeroed for the next test; cycles[k] counts the cycles a channel
+// receives; counts = {channels left active, NaN channels}.
+constexpr int BMG_DECIDE_T = 256;
+
+template <typename T, typename TC>
+__global__ void __launch_bounds__(BMG_DECIDE_T) kbm_decide(const MgChan<T, TC>* __restrict__ ch, int n,
+                                                           unsigned long long* __restrict__ res,
+                                                           int* __restrict__ active, int* __restrict__ cycles,
+                                                           int* __restrict__ counts, double floor_factor) {
+    __shared__ int cnt[2][BMG_DECIDE_T / 64];
+    int a_sum = 0, nan_sum = 0;
+    for (int k = threadIdx.x; k < n; k += BMG_DECIDE_T) {
+        if (!active[k]) continue;
+        const double r = __longlong_as_double((long long)res[2 * k]);
+        const double sc = __longlong_as_double((long long)res[2 * k + 1]);
+        res[2 * k] = 0ULL;
+        res[2 * k + 1] = 0ULL;
+        int a = 0;
+        if (r != r) {
+            ++nan_sum;
+        } else if (!(r <= fmax(ch[k].thr, floor_factor * sc))) {
+            a = 1;
+            ++cycles[k];
+        }
+        active[k] = a;
+        a_sum += a;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a_sum += __shfl_xor(a_sum, off, 64);
+        nan_sum += __shfl_xor(nan_sum, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        cnt[0][threadIdx.x >> 6] = a_sum;
+        cnt[1][threadIdx.x >> 6] = nan_sum;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        int t = 0;
+        for (int w = 0; w < BMG_DECIDE_T / 64; ++w) t += cnt[threadIdx.x][w];
+        counts[threadIdx.x] = t;
+    }
+}
+
+template <typename T, typename TC>
+void launch_bmg_smooth_fine(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, int dir,
+                            bool prolong, unsigned long long* res, hipStream_t s) {
+    if (prolong)
+        hipLaunchKernelGGL((kbm_smooth_fine<T, true, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, dir,
+                           res);
+    else
+        hipLaunchKernelGGL((kbm_smooth_fine<T, false, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active,
+                           dir, res);
+}
+
+template <typename T, typename TC>
+void launch_bmg_copy_fine(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, hipStream_t s) {
+    hipLaunchKernelGGL((kbm_copy_fine<T, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active);
+}
+
+template <typename T, typename TC>
+void launch_bmg_restrict_smooth(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, int level,
+                                int src, int inner, hipStream_t s) {
+    if (level == 1)
+        hipLaunchKernelGGL((kbm_restrict_smooth0<T, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, src,
+                           inner);
+    else
+        hipLaunchKernelGGL((kbm_restrict_smoothC<TC, T>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active,
+                           inner);
+}
+
+template <typename T, typename TC>
+void launch_bmg_restrict_tail(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, bool from0,
+                              int src, hipStream_t s) {
+    if (from0)
+        hipLaunchKernelGGL((kbm_restrict_tail0<T, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, src);
+    else
+        hipLaunchKernelGGL((kbm_restrict_tailC<TC, T>), dim3(njobs), dim3(CoarseTile::NT), 0, s, ch, jobs, active);
+}
+
+template <typename T, typename TC>
+void launch_bmg_tail(const MgChan<T, TC>* ch, int n, size_t lds_bytes, const int* active, hipStream_t s) {
+    hipLaunchKernelGGL((kbm_tail<TC, T>), dim3(n), dim3(TAIL_T), lds_bytes, s, ch, active);
+}
+
+template <typename T, typename TC>
+void launch_bmg_post_coarse(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, int inner,
+                            hipStream_t s) {
+    hipLaunchKernelGGL((kbm_post_coarse<TC, T>), dim3(njobs), dim3(CoarseTile::NT), 0, s, ch, jobs, active, inner);
+}
+
+template <typename T, typename TC>
+void launch_bmg_mu4(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, int group, hipStream_t s) {
+    if (group == 0)
+        hipLaunchKernelGGL((kbm_mu4_0<T, TC>), dim3(njobs), dim3(MU_TX * MU_TY / 4), 0, s, ch, jobs);
+    else
+        hipLaunchKernelGGL((kbm_mu4_C<TC, T>), dim3(njobs), dim3(MU_TX * MU_TY / 4), 0, s, ch, jobs);
+}
+
+template <typename T, typename TC>
+void launch_bmg_decide(const MgChan<T, TC>* ch, int n, unsigned long long* res, int* active, int* cycles, int* counts,
+                       double floor_factor, hipStream_t s) {
+    hipLaunchKernelGGL((kbm_decide<T, TC>), dim3(1), dim3(BMG_DECIDE_T), 0, s, ch, n, res, active, cycles, counts,
+                       floor_factor);
+}
+
 #define FCD_POT_INSTANTIATE(T)                                                                            \
     template void launch_pot_sweep<T>(const PotLevel<T>&, T, hipStream_t);                                \
     template void launch_pot_residual<T>(const PotLevel<T>&, unsigned long long*, hipStream_t);           \
@@ -1045,6 +1340,21 @@ void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, in
 
 // Multigrid transfer and smoothing kernels between a level of type T and coarse levels of
 // type TC (the coarse levels are FP32 under an FP64 finest level).
+#define FCD_BMG_INSTANTIATE(T, TC)                                                                            \
+    template void launch_bmg_smooth_fine<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, int, bool,  \
+                                                unsigned long long*, hipStream_t);                                \
+    template void launch_bmg_copy_fine<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, hipStream_t);  \
+    template void launch_bmg_restrict_smooth<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, int, int, \
+                                                    int, hipStream_t);                                            \
+    template void launch_bmg_restrict_tail<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, bool, int, \
+                                                  hipStream_t);                                                   \
+    template void launch_bmg_tail<T, TC>(const MgChan<T, TC>*, int, size_t, const int*, hipStream_t);            \
+    template void launch_bmg_post_coarse<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, int,        \
+                                                hipStream_t);                                                     \
+    template void launch_bmg_mu4<T, TC>(const MgChan<T, TC>*, const MgJob*, int, int, hipStream_t);              \
+    template void launch_bmg_decide<T, TC>(const MgChan<T, TC>*, int, unsigned long long*, int*, int*, int*,     \
+                                           double, hipStream_t);
+
 #define FCD_MG_INSTANTIATE(T, TC)                                                                             \
     template void launch_mg_restrict_mu4<T, TC>(const T*, int, int, int, const MuLevels<TC>&, hipStream_t);   \
     template void launch_mg_smooth_tile<T, TC>(const PotLevel<T>&, const T*, T*, const PotLevel<TC>*, int,    \
@@ -1057,5 +1367,7 @@ FCD_POT_INSTANTIATE(double)
 FCD_POT_INSTANTIATE(float)
 FCD_MG_INSTANTIATE(double, float)
 FCD_MG_INSTANTIATE(float, float)
+FCD_BMG_INSTANTIATE(double, float)
+FCD_BMG_INSTANTIATE(float, float)
 
 }  // namespace fcd

@@ -204,3 +204,94 @@ def test_many_channels_and_a_longer_test_interval():
             one.step(3)
             assert np.array_equal(one.state(0), st), (fused, tail, k)
             one.close()
+
+
+MG = dict(solver=fcd.FCD_SOLVER_MG, smooth=2)
+
+
+def test_batch_multigrid_matches_oracle_fp64():
+    """The batched multigrid (one launch per level for every channel; each channel's
+    convergence decided on the device after its cycle's first sweep) on the uneven channels
+    (one without field, odd ny, one narrower than a tile) against the oracle, to the SOR
+    batch's bar."""
+    ws = uneven_channels()
+    say("case batch multigrid fp64 uneven channels vs oracle")
+    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-12, **MG)
+    bt.init_droplets()
+    bt.step(30)
+    cycles = bt.stats()[1]
+    say(f"  {cycles:.0f} V-cycles launched over 30 steps")
+    # V-cycles, not SOR sweeps (an SOR batch needs hundreds of sweeps a step here)
+    assert cycles <= 30 * 40
+    dg = bt.deformation()
+    for k, w in enumerate(ws):
+        s = OracleSim(w)
+        s.init_droplet(solve=False)
+        assert s.step(30) == 0
+        ref = np.concatenate([s.f, s.g1, s.g2])
+        assert np.abs(bt.state(k) - ref).max() < 1e-11, w.name
+        m, om = bt.moments(k), s.moments()
+        for key in om:
+            assert np.abs(m[key] - om[key]).max() < 1e-11, (w.name, key)
+        od = s.diagnostics()
+        assert abs(dg[k][0] - od[0]) < 1e-11 and abs(dg[k][1] - od[1]) < 1e-11
+    bt.close()
+
+
+@pytest.mark.parametrize("precision", [fcd.FCD_FP64, fcd.FCD_FP32])
+def test_batch_multigrid_channel_equals_its_batch_of_one(precision):
+    """A channel's cycles are decided on the device from its own residual alone: in a batch
+    of 300 channels (more than the decision kernel's block) of differing size, field and
+    hierarchy depth, each sampled channel ends bit for bit as in a batch of its own."""
+    base = single_channel_small().replace(nx=48, ny=14, xc=16.0, yc=6.5, r_core=2.0, r_shell=4.5,
+                                          drive_G=channel_drive(0.01, 1.0, 0.8, 14))
+    ws = [base.replace(name=f"m{k}", H0=base.H0 * (0.5 + (k % 7) / 7.0), alpha=0.1 * (k % 5),
+                       ny=14 + (k % 5), nx=48 + 16 * (k % 3), drive_G=channel_drive(0.01, 1.0, 0.8, 14 + (k % 5)))
+          for k in range(300)] + uneven_channels()
+    tol = 1e-10 if precision == fcd.FCD_FP64 else 1e-5
+    say(f"case batch multigrid of {len(ws)} channels, precision {precision}")
+    bt = Batch(ws, precision=precision, tol=tol, **MG)
+    bt.init_droplets()
+    bt.step(6)
+    got = {k: bt.state(k) for k in (0, 1, 137, 299, 300, 302, 303)}
+    bt.close()
+    for k, st in got.items():
+        one = Batch([ws[k]], precision=precision, tol=tol, **MG)
+        one.init_droplets()
+        one.step(6)
+        assert np.array_equal(one.state(0), st), k
+        one.close()
+
+
+def test_batch_multigrid_fp32_regime_channels_track_fp64():
+    """The FP32 multigrid batch on the regime-sweep channels (odd ny among them) against
+    single-channel FP64 runs, to the bars of the FP32 SOR batch: max |d phi| <= 1e-4 after
+    20 steps; after 200, mean |d phi| <= 1e-4 and |dD| <= 1e-3."""
+    ws = [w.replace(steps=200) for w in regime_sweep_batch()[::11]]
+    say(f"case batch multigrid fp32 regime subset sizes {[(w.nx, w.ny) for w in ws]}")
+    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5, **MG)
+    bt.init_droplets()
+    gs = []
+    for w in ws:
+        g = Channel(w, tol=1e-10)
+        g.init_droplet()
+        gs.append(g)
+    for n_steps, final in ((20, False), (180, True)):
+        bt.step(n_steps)
+        dg = bt.deformation()
+        for k, (w, g) in enumerate(zip(ws, gs)):
+            g.step(n_steps)
+            m32, m64 = bt.moments(k), g.moments()
+            d64 = g.deformation()
+            e_mean = max(np.abs(m32[key] - m64[key]).mean() for key in ("phi1", "phi2", "phi3"))
+            e_max = max(np.abs(m32[key] - m64[key]).max() for key in ("phi1", "phi2", "phi3"))
+            say(f"  {w.name} Bo {w.bond:.2f} after {'200' if final else '20'} steps: mean|dphi| {e_mean:.2e} "
+                f"max|dphi| {e_max:.2e} dD {abs(dg[k][0] - d64[0]):.2e} {abs(dg[k][1] - d64[1]):.2e}")
+            if not final:
+                assert e_max < 1e-4, w.name
+            else:
+                assert e_mean < 1e-4, w.name
+                assert abs(dg[k][0] - d64[0]) < 1e-3 and abs(dg[k][1] - d64[1]) < 1e-3
+    for g in gs:
+        g.close()
+    bt.close()
