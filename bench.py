@@ -133,21 +133,43 @@ def cpu_baseline(steps: int, bond: float, tol: float) -> dict:
 
 
 def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
-    """The 64-channel regime sweep (ny ~ U{64..256}, nx = 4 ny) as one FP32 batch (and, for
-    the gain at equal precision, as one FP64 batch at the single channels' tolerance),
-    against the same channels run one after another as single FP64 channels on this GPU
-    (with the batch's tuned SOR factors where a channel's solve is SOR).  The rates are
-    extrapolated to the sweep's 10k steps per channel from timed windows.  The tuners run
-    before the timed windows and are not part of them."""
+    """The 64-channel regime sweep (ny ~ U{64..256}, nx = 4 ny) as one FP32 batch and, for
+    the gain at equal precision, as one FP64 batch at the single channels' tolerance, both
+    with the batched multigrid (one finest sweep each way), against the same channels run
+    one after another as single FP64 channels on this GPU (multigrid, two finest sweeps).
+    The FP32 batch with its tuned four-colour SOR is timed too (the batch's other solver).
+    The rates are extrapolated to the sweep's 10k steps per channel from timed windows.
+    Tuners run before the timed windows and are not part of them."""
     from fcd_inputs import regime_sweep_batch
     from paper_2410_11129_amd import fcd
     from paper_2410_11129_amd.sim import Batch, Channel
     ws = regime_sweep_batch()
     nsteps_target = ws[0].steps
+    sites = sum(w.sites for w in ws)
+
+    def timed(bt, n):
+        bt.init_droplets()
+        bt.step(8)  # past the start-up transient
+        torch.cuda.synchronize()
+        it0 = bt.stats()[1]
+        t0 = time.perf_counter()
+        bt.step(n)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        return dt, (bt.stats()[1] - it0) / n
+
+    mg = dict(solver=fcd.FCD_SOLVER_MG, smooth=1)
+    bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5, **mg)
+    dt_batch, cyc32 = timed(bt, steps)
+    bt.close()
+    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-10, **mg)
+    dt_batch64, cyc64 = timed(bt, max(1, steps // 4))
+    bt.close()
+    # the FP32 batch with its SOR solver, factors and launch schedule tuned first
     bt = Batch(ws, precision=fcd.FCD_FP32, tol=1e-5)
     bt.init_droplets()
-    bt.step(8)  # past the start-up transient
-    omegas = bt.tune_omega(4)
+    bt.step(8)
+    bt.tune_omega(4)
     bt.init_droplets()
     rows, block, fused, tail_fused, tail_after = bt.autotune(3)
     bt.step(4)
@@ -156,30 +178,13 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     t0 = time.perf_counter()
     bt.step(steps)
     torch.cuda.synchronize()
-    dt_batch = (time.perf_counter() - t0) / steps
+    dt_sor = (time.perf_counter() - t0) / steps
     sweeps = (bt.stats()[1] - it0) / steps
-    sites = sum(w.sites for w in ws)
-    bt.close()
-    del bt
-    # the same batch in FP64 at the single channels' tolerance (the batching gain at equal
-    # precision), same SOR factors, autotuned, a shorter timed window
-    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-10)
-    bt.init_droplets()
-    bt.step(8)
-    bt.tune_omega(4)
-    bt.init_droplets()
-    bt.autotune(1)
-    bt.step(4)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bt.step(max(1, steps // 10))
-    torch.cuda.synchronize()
-    dt_batch64 = (time.perf_counter() - t0) / max(1, steps // 10)
     bt.close()
     del bt
     seq = 0.0
-    for w, om in zip(ws, omegas if seq_steps > 0 else []):
-        ch = Channel(w, tol=1e-10, omega=om)
+    for w in (ws if seq_steps > 0 else []):
+        ch = Channel(w, tol=1e-10, smooth=2)
         ch.init_droplet()
         ch.step(5)
         torch.cuda.synchronize()
@@ -188,20 +193,25 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
         torch.cuda.synchronize()
         seq += (time.perf_counter() - t0) / seq_steps
         ch.close()
-    batch_iph = len(ws) / (nsteps_target * dt_batch) * 3600.0
+    iph = lambda dt: len(ws) / (nsteps_target * dt) * 3600.0  # noqa: E731
     seq_iph = len(ws) / (nsteps_target * seq) * 3600.0 if seq_steps > 0 else None
     return {"channels": len(ws), "sites": sites, "steps_per_channel": nsteps_target,
+            "solver": "batched multigrid",
             "batch_fp32_ms_per_step": round(dt_batch * 1e3, 4), "batch_MLUPS": round(sites / dt_batch / 1e6, 1),
-            "batch_sor_sweeps_per_step": round(sweeps, 2),
-            "schedule": {"tile_rows": rows, "block_sweeps": block, "fused_sweeps": fused,
-                         "tail_fused_sweeps": tail_fused, "tail_after_sweeps": tail_after},
-            "instances_per_hour_batch_fp32": round(batch_iph, 1),
+            "batch_fp32_vcycles_per_step": round(cyc32, 2),
+            "instances_per_hour_batch_fp32": round(iph(dt_batch), 1),
             "batch_fp64_ms_per_step": round(dt_batch64 * 1e3, 4),
-            "instances_per_hour_batch_fp64": round(len(ws) / (nsteps_target * dt_batch64) * 3600.0, 1),
+            "batch_fp64_vcycles_per_step": round(cyc64, 2),
+            "instances_per_hour_batch_fp64": round(iph(dt_batch64), 1),
             "instances_per_hour_sequential_fp64": round(seq_iph, 1) if seq_iph else None,
-            "speedup": round(batch_iph / seq_iph, 2) if seq_iph else None,
-            "speedup_fp64_batch": round(len(ws) / (nsteps_target * dt_batch64) * 3600.0 / seq_iph, 2) if seq_iph else None,
-            "sample": f"batch: {steps} timed steps; sequential: {seq_steps} timed steps per channel"}
+            "speedup": round(iph(dt_batch) / seq_iph, 2) if seq_iph else None,
+            "speedup_fp64_batch": round(iph(dt_batch64) / seq_iph, 2) if seq_iph else None,
+            "sor_fp32": {"ms_per_step": round(dt_sor * 1e3, 4), "sweeps_per_step": round(sweeps, 2),
+                         "instances_per_hour": round(iph(dt_sor), 1),
+                         "schedule": {"tile_rows": rows, "block_sweeps": block, "fused_sweeps": fused,
+                                      "tail_fused_sweeps": tail_fused, "tail_after_sweeps": tail_after}},
+            "sample": f"batch: {steps} timed steps (FP64 {max(1, steps // 4)}); sequential: {seq_steps} timed "
+                      f"steps per channel"}
 
 
 def regime_accuracy(torch, stride: int, steps: int) -> dict:

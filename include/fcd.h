@@ -91,7 +91,7 @@ typedef struct {
                                   a negative value -N: exactly N sweeps; 0 is rejected */
     int32_t pot_extrapolate; /* warm start of each step's solve: 0 the previous psi', 1 the linear
                                 extrapolation 2 psi'(t-1) - psi'(t-2), 2 the quadratic one
-                                3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3) (batches: 2 acts as 1) */
+                                3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3) (SOR batches: 2 acts as 1) */
     int32_t pot_every;       /* quasi-static coupling: the potential is solved on steps 0, K, 2K, ...
                                 after the last state change and held in between (K = pot_every;
                                 0 or 1: every step, the paper's coupling; the adjoints need <= 1;
@@ -313,13 +313,22 @@ fcd_status fcd_adjoint_backward(fcd_handle* h, const double dJ_dD[2], double gra
 /* ---------------------------------------------------------------------------------
  * Batches: n independent channels of uneven size (e.g. a regime-map sweep over Bo_m and
  * Ca) stepped together.  Every kernel of a step is launched once for the whole batch;
- * per-channel lattices and parameters are honoured.  The potential is solved by
- * four-colour SOR per channel (pot_solver is ignored), each channel to its own
- * pot_tol * H0, with channels that have converged left untouched; a batch step ends
- * when every channel has converged.  All lattices must share one precision.
+ * per-channel lattices and parameters are honoured.  The potential of every channel is
+ * solved to its own pot_tol * H0, with channels that have converged left untouched; a
+ * batch step ends when every channel has converged.  Solver (channel 0's pot_solver):
+ * FCD_SOLVER_MG gives batched multigrid V-cycles (each channel's single-channel
+ * hierarchy and V-cycle, finest tiles 64 x 16, channel 0's pot_smooth and its own
+ * pot_coarse_sweeps; one launch per level for all channels, each channel's convergence
+ * decided on the device, so a channel's result does not depend on the rest of the
+ * batch) when
+ * every channel's lattice has a coarse level and an LDS tail (nx, ny >= 4 and a small
+ * enough coarsest level), else, and for FCD_SOLVER_SOR, four-colour SOR per channel
+ * (the SOR factors, schedule and tuners below apply to it only).  The adjoint potential
+ * solves of the batched adjoint use the SOR.  All lattices must share one precision.
  * Caller-owned buffers, sizes from fcd_batch_sizes: `state` (both state buffers of every
  * channel), `aux` (phi1, phi2, mu_r, psi' and psi' history planes), `scratch`
- * (descriptors, tile tables, reductions); each at least 256-byte aligned.
+ * (descriptors, tile and job tables, reductions, the coarse multigrid levels); each at
+ * least 256-byte aligned.
  * --------------------------------------------------------------------------------- */
 typedef struct fcd_batch fcd_batch;
 

@@ -1007,7 +1007,7 @@ constexpr int BATCH_MAX_CHANNELS = 65536;
 
 struct BatchLayout {
     std::vector<int> pitch;
-    std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev, off_alt;  // into state / aux
+    std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev, off_prev2, off_alt;  // into state / aux
     std::vector<int> tile0[fcd::BATCH_SHAPES], tiles_x[fcd::BATCH_SHAPES];
     std::vector<int> ctile0[fcd::BATCH_SHAPES], ctiles_x[fcd::BATCH_SHAPES];
     std::vector<int> stile0, stiles_x;  // fused-sweep tiles
@@ -1081,6 +1081,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
         L->aux_bytes += plane;
         L->off_prev.push_back(L->aux_bytes);
         L->aux_bytes += plane;
+        L->off_prev2.push_back(L->aux_bytes);
+        L->aux_bytes += plane;
         L->off_alt.push_back(L->aux_bytes);
         L->aux_bytes += plane;
         {
@@ -1120,7 +1122,7 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
     L->off_active = off;  // two buffers of activity flags
     off = align256(off + 2 * (size_t)n * sizeof(int));
     L->off_counts = off;
-    off = align256(off + 2 * sizeof(int));
+    off = align256(off + 3 * sizeof(int));
     L->off_sweeps = off;
     off = align256(off + (size_t)n * sizeof(int));
     L->off_div = off;  // per-channel divergence flags
@@ -1220,7 +1222,7 @@ struct fcd_batch {
     long long steps;
     long long iters;
     double last_resid;
-    double* host;  // pinned: [0] active count and NaN count (two ints), [1..] n x 4 diagnostics
+    double* host;  // pinned: [0..1] the solve counts (three ints), [2..] n x 4 diagnostics or n flags
     // launch schedule: tile shape (rows 1, 2, 4, 8), sweeps per graph-launched block and
     // sweeps per fused SOR launch (0: one launch per colour)
     int shape;
@@ -1292,6 +1294,7 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
     I.dist[1] = bptr<T>(b->state, b->L.off_d1[k]);
     I.phi = bptr<T>(b->aux, b->L.off_phi[k]);
     I.prev = bptr<T>(b->aux, b->L.off_prev[k]);
+    I.prev2 = bptr<T>(b->aux, b->L.off_prev2[k]);
     I.alt = bptr<T>(b->aux, b->L.off_alt[k]);
     I.L0.u = bptr<T>(b->aux, b->L.off_psi[k]);
     I.L0.mu = I.phi + 2 * (long long)I.P.plane;
@@ -1322,14 +1325,14 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
 // Reads every channel's divergence flag (waits for the stream); FCD_ERR_DIVERGED names the
 // first channel whose flag is set.
 fcd_status batch_read_divergence(fcd_batch* b) {
-    fcd_status st = hip_check(hipMemcpyAsync(b->host + 1, b->scratch + b->L.off_div,
+    fcd_status st = hip_check(hipMemcpyAsync(b->host + 2, b->scratch + b->L.off_div,
                                              (size_t)b->n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                              b->stream), "divergence flag copy");
     if (!st) st = hip_check(hipStreamSynchronize(b->stream), "divergence flag sync");
     if (st) return st;
     for (int k = 0; k < b->n; ++k) {
         unsigned long long w;
-        std::memcpy(&w, b->host + 1 + k, sizeof(w));
+        std::memcpy(&w, b->host + 2 + k, sizeof(w));
         if (w) return divergence_status(w, u_limit_of(b->prm[k]), "divergence guard, channel " + std::to_string(k));
     }
     return FCD_OK;
@@ -1372,6 +1375,17 @@ fcd::MgChan<T, CT> make_mgchan(const fcd_batch* b, int k) {
     const int nyc = p.ny[p.levels - 1], cs = prm.pot_coarse_sweeps;
     c.tl.coarse_sweeps = cs < 0 ? -cs : cs * std::max(1, nyc / 2);
     c.tl.omega = CT(sor_omega_opt(nyc));
+    for (int g = 0; 4 * g + 1 < p.levels && g < 4; ++g) {
+        fcd::MuLevels<CT>& M = c.mu4[g];
+        M.n = std::min(4, p.levels - 1 - 4 * g);
+        for (int q = 0; q < M.n; ++q) {
+            const fcd::PotLevel<CT>& Lq = c.C[4 * g + 1 + q];
+            M.mu[q] = const_cast<CT*>(Lq.mu);
+            M.nx[q] = Lq.nx;
+            M.ny[q] = Lq.ny;
+            M.pitch[q] = Lq.pitch;
+        }
+    }
     c.levels = p.levels;
     c.tail = p.tail;
     c.thr = prm.pot_tol * std::fabs(prm.H0);
@@ -1553,16 +1567,17 @@ void batch_block(fcd_batch* b, const BatchProblem<T>& P, int fused) {
 }
 
 template <typename T>
-fcd_status batch_read_counts(fcd_batch* b, int* active_count) {
+fcd_status batch_read_counts(fcd_batch* b, int* active_count, int* needed = nullptr) {
     int* counts = bptr<int>(b->scratch, b->L.off_counts);
-    fcd_status st = hip_check(hipMemcpyAsync(b->host, counts, 2 * sizeof(int), hipMemcpyDeviceToHost, b->stream),
+    fcd_status st = hip_check(hipMemcpyAsync(b->host, counts, 3 * sizeof(int), hipMemcpyDeviceToHost, b->stream),
                               "batch count copy");
     if (!st) st = hip_check(hipStreamSynchronize(b->stream), "batch count sync");
     if (st) return st;
-    int c[2];
+    int c[3];
     std::memcpy(c, b->host, sizeof(c));
     if (c[1] > 0) return fail(FCD_ERR_DIVERGED, "a channel's potential residual is NaN");
     *active_count = c[0];
+    if (needed) *needed = c[2];
     return FCD_OK;
 }
 
@@ -1583,10 +1598,16 @@ fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
     if (st) return st;
     int left = 1, it = 0;
     const int G = b->block_sweeps;
-    int blind = *P.last_iters > G ? (*P.last_iters + G - 1) / G - 1 : 0;
+    // blocks launched without a read: as many as the previous solve took, less one; when the
+    // first read after them finds every channel converged, the solve may have needed fewer,
+    // so the next solve is given one block fewer (else the count could only ever grow)
+    const int blind0 = *P.last_iters > G ? (*P.last_iters + G - 1) / G - 1 : 0;
+    int blind = blind0;
+    bool first_read = true, overshoot = false;
     if (blind == 0) {
         st = batch_read_counts<T>(b, &left);
         if (st) return st;
+        first_read = false;
     }
     while (left > 0) {
         if (it >= max_iters) break;
@@ -1601,9 +1622,11 @@ fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
         }
         st = batch_read_counts<T>(b, &left);
         if (st) return st;
+        if (first_read) overshoot = blind0 > 0 && left == 0;
+        first_read = false;
     }
     b->iters += it;
-    *P.last_iters = it;
+    *P.last_iters = overshoot ? it - G : it;
     b->last_resid = 0.0;
     if (left > 0) return fail(FCD_ERR_NOT_CONVERGED, "a channel's potential solve reached pot_max_iters");
     return FCD_OK;
@@ -1665,12 +1688,16 @@ fcd_status batch_solve_mg(fcd_batch* b, int max_iters) {
     fcd::launch_bmg_mu4<T, CT>(ch, jobs + L.fine0, L.nfine, 0, b->stream);
     for (int g = 1; g < 4; ++g)
         if (L.nmu[g]) fcd::launch_bmg_mu4<T, CT>(ch, jobs + L.mu0[g], L.nmu[g], g, b->stream);
+    int* counts = bptr<int>(b->scratch, L.off_counts);
     fcd::launch_fill<int>(bptr<int>(b->scratch, L.off_active), b->n, 1, b->stream);
+    fcd::launch_fill<int>(counts + 2, 1, 0, b->stream);
     fcd_status st = hip_check(hipGetLastError(), "batch multigrid launch");
     if (st) return st;
+    // graph launches without a read: as many as the previous solve's cycles need, less one
+    // (the decision kernel counts the cycles a solve needs, however many were launched)
     const int G = BMG_BLOCK_CYCLES;
     int blind = b->mg_last_cycles > G ? (b->mg_last_cycles + G - 1) / G - 1 : 0;
-    int left = 1, it = 0;
+    int left = 1, it = 0, needed = 0;
     while (left > 0) {
         if (it >= max_iters) break;
         st = run_graph_on(b->graphs, b->stream, false, ch, jobs, (7 << 24) + std::max(1, b->prm[0].pot_smooth),
@@ -1683,11 +1710,11 @@ fcd_status batch_solve_mg(fcd_batch* b, int max_iters) {
             --blind;
             continue;
         }
-        st = batch_read_counts<T>(b, &left);
+        st = batch_read_counts<T>(b, &left, &needed);
         if (st) return st;
     }
     b->iters += it;
-    b->mg_last_cycles = it;
+    b->mg_last_cycles = needed;
     b->last_resid = 0.0;
     if (left > 0) return fail(FCD_ERR_NOT_CONVERGED, "a channel's potential solve reached pot_max_iters");
     return FCD_OK;
@@ -1702,8 +1729,13 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
         fcd_status st = hip_check(hipGetLastError(), "batch phase launch");
         if (st) return st;
         if (b->qs % std::max(1, p0.pot_every) == 0) {  // quasi-static coupling, as fcd_step
-            if (p0.pot_extrapolate)
-                fcd::launch_batch_psi_history<T>(binst<T>(b), t, b->hist >= 2 ? 1 : 0, b->stream);
+            if (p0.pot_extrapolate) {
+                // linear from the third solve; with the multigrid and pot_extrapolate == 2
+                // quadratic from the fourth (in SOR batches its coefficients amplify the FP32
+                // solve's rounding, so they start linearly whatever pot_extrapolate says)
+                const int mode = b->mg && p0.pot_extrapolate == 2 && b->hist >= 3 ? 2 : b->hist >= 2 ? 1 : 0;
+                fcd::launch_batch_psi_history<T>(binst<T>(b), t, mode, b->stream);
+            }
             st = b->mg ? batch_solve_mg<T>(b, p0.pot_max_iters)
                        : batch_solve<T>(b, forward_problem<T>(b), p0.pot_max_iters);
             if (st) return st;
@@ -1871,12 +1903,12 @@ fcd_status batch_diag_impl(fcd_batch* b, double* out) {
     }
     fcd_status st = hip_check(hipGetLastError(), "batch diagnostics launch");
     if (st) return st;
-    st = hip_check(hipMemcpyAsync(b->host + 1, results, (size_t)b->n * 4 * sizeof(double), hipMemcpyDeviceToHost,
+    st = hip_check(hipMemcpyAsync(b->host + 2, results, (size_t)b->n * 4 * sizeof(double), hipMemcpyDeviceToHost,
                                   b->stream), "batch diagnostics copy");
     if (st) return st;
     st = hip_check(hipStreamSynchronize(b->stream), "batch diagnostics sync");
     if (st) return st;
-    std::memcpy(out, b->host + 1, (size_t)b->n * 4 * sizeof(double));
+    std::memcpy(out, b->host + 2, (size_t)b->n * 4 * sizeof(double));
     return batch_read_divergence(b);
 }
 
@@ -2161,12 +2193,12 @@ BatchAdjLayout batch_adj_layout(const fcd_batch* b, int nsteps, int every) {
     for (int k = 0; k < b->n; ++k) {
         const size_t pl = align256((size_t)b->lat[k].ny * b->L.pitch[k] * esz);
         A.plane.push_back(pl);
-        A.crec.push_back(29 * pl);
+        A.crec.push_back(30 * pl);
         A.srec.push_back(28 * pl);
         A.off_ckpt.push_back(off);
-        off += (size_t)A.nseg * 29 * pl;
+        off += (size_t)A.nseg * 30 * pl;
         A.off_final.push_back(off);
-        off += 29 * pl;
+        off += 30 * pl;
         A.off_seg.push_back(off);
         off += (size_t)every * 28 * pl;
         A.off_lam0.push_back(off);
@@ -2212,6 +2244,7 @@ fcd_status batch_save_records(fcd_batch* b, const BatchAdjLayout& A, const std::
         st = dcopy(rec, bstate(b, k), 27 * pl, b->stream);
         if (!st) st = dcopy(rec + 27 * pl, b->aux + b->L.off_psi[k], pl, b->stream);
         if (!st) st = dcopy(rec + 28 * pl, b->aux + b->L.off_prev[k], pl, b->stream);
+        if (!st) st = dcopy(rec + 29 * pl, b->aux + b->L.off_prev2[k], pl, b->stream);
     }
     return st;
 }
@@ -2224,6 +2257,7 @@ fcd_status batch_load_records(fcd_batch* b, const BatchAdjLayout& A, const std::
         st = dcopy(bstate(b, k), rec, 27 * pl, b->stream);
         if (!st) st = dcopy(b->aux + b->L.off_psi[k], rec + 27 * pl, pl, b->stream);
         if (!st) st = dcopy(b->aux + b->L.off_prev[k], rec + 28 * pl, pl, b->stream);
+        if (!st) st = dcopy(b->aux + b->L.off_prev2[k], rec + 29 * pl, pl, b->stream);
     }
     return st;
 }
@@ -2241,6 +2275,7 @@ fcd_status batch_adj_forward_impl(fcd_batch* b, int nsteps, int every, char* wor
         I.L0.f = reinterpret_cast<T*>(work + A.off_rhs[k]);
         I.L0.H0x = I.L0.H0y = T(0);
         I.prev = reinterpret_cast<T*>(work + A.off_lprev[k]);
+        I.prev2 = nullptr;  // the adjoint solves start linearly
         fcd::BatchAdj<T>& D = adj[k];
         D.seg = reinterpret_cast<T*>(work + A.off_seg[k]);
         D.srec = (long long)(A.srec[k] / sizeof(T));
@@ -2757,7 +2792,7 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     // and four sweeps per launch after 16 tests
     b->tail_fused = fused_allowed(b, 4) ? 4 : 0;
     b->tail_after = 16 * check_interval(b);
-    if (hipHostMalloc(reinterpret_cast<void**>(&b->host), (1 + 4 * (size_t)n) * sizeof(double),
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->host), (2 + 4 * (size_t)n) * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         delete b;
         return fail(FCD_ERR_OOM, "pinned host allocation failed");

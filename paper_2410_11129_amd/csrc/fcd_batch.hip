@@ -469,7 +469,10 @@ __global__ void __launch_bounds__(TBX* TY) kb_psi_history(const BatchInst<T>* __
     if (i >= B.P.nx || j >= B.P.ny || !B.has_field) return;
     const long long q = (long long)j * B.L0.pitch + i;
     const T cur = B.L0.u[q];
-    if (mode == 1) B.L0.u[q] = T(2) * cur - B.prev[q];
+    const T p1 = B.prev[q];
+    if (mode == 1) B.L0.u[q] = T(2) * cur - p1;
+    if (mode == 2) B.L0.u[q] = T(3) * (cur - p1) + B.prev2[q];
+    if (B.prev2) B.prev2[q] = p1;
     B.prev[q] = cur;
 }
 

@@ -94,6 +94,7 @@ struct MgChan {
     TC* t[MG_MAX_LEVELS];
     MgTail<TC> tl;
     TailDiv dv;
+    MuLevels<TC> mu4[4];  // coarse mu written from level 4g: levels 4g+1 .. 4g+4 (those that exist)
     int levels, tail;
     double thr;  // the channel stops when max |residual| <= max(thr, rounding floor)
 };

@@ -1192,15 +1192,7 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) kbm_mu4_0(const MgChan<T, TC
                                                               const MgJob* __restrict__ jobs) {
     const MgJob J = jobs[blockIdx.x];
     const MgChan<T, TC>& c = ch[J.k];
-    MuLevels<TC> M{};
-    M.n = min(4, c.levels - 1);
-    for (int q = 0; q < M.n; ++q) {
-        M.mu[q] = const_cast<TC*>(c.C[1 + q].mu);
-        M.nx[q] = c.C[1 + q].nx;
-        M.ny[q] = c.C[1 + q].ny;
-        M.pitch[q] = c.C[1 + q].pitch;
-    }
-    mg_restrict_mu4_tile<T, TC>(c.L0.mu, c.L0.pitch, c.L0.nx, c.L0.ny, M, J.bx, J.by);
+    mg_restrict_mu4_tile<T, TC>(c.L0.mu, c.L0.pitch, c.L0.nx, c.L0.ny, c.mu4[0], J.bx, J.by);
 }
 
 // ... or coarse level 4g (g = J.l >= 1).
@@ -1209,24 +1201,16 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) kbm_mu4_C(const MgChan<T, TC
                                                               const MgJob* __restrict__ jobs) {
     const MgJob J = jobs[blockIdx.x];
     const MgChan<T, TC>& c = ch[J.k];
-    const int f = 4 * J.l;
-    MuLevels<TC> M{};
-    M.n = min(4, c.levels - 1 - f);
-    for (int q = 0; q < M.n; ++q) {
-        M.mu[q] = const_cast<TC*>(c.C[f + 1 + q].mu);
-        M.nx[q] = c.C[f + 1 + q].nx;
-        M.ny[q] = c.C[f + 1 + q].ny;
-        M.pitch[q] = c.C[f + 1 + q].pitch;
-    }
-    const PotLevel<TC> F = c.C[f];
-    mg_restrict_mu4_tile<TC, TC>(F.mu, F.pitch, F.nx, F.ny, M, J.bx, J.by);
+    const PotLevel<TC> F = c.C[4 * J.l];
+    mg_restrict_mu4_tile<TC, TC>(F.mu, F.pitch, F.nx, F.ny, c.mu4[J.l], J.bx, J.by);
 }
 
 // The convergence decision of every channel, one block: a channel active on entry stays
 // active while its residual (res[2k], the bit pattern of max |r|, and res[2k+1], that of
 // max |C u|) is above max(thr, floor * scale); a NaN residual stops it and is counted.
 // Both words are zeroed for the next test; cycles[k] counts the cycles a channel
-// receives; counts = {channels left active, NaN channels}.
+// receives; counts = {channels left active, NaN channels, decisions of this solve that
+// found a channel active} (the last: the cycles the solve needs, counted from zero).
 constexpr int BMG_DECIDE_T = 256;
 
 template <typename T, typename TC>
@@ -1234,10 +1218,11 @@ __global__ void __launch_bounds__(BMG_DECIDE_T) kbm_decide(const MgChan<T, TC>* 
                                                            unsigned long long* __restrict__ res,
                                                            int* __restrict__ active, int* __restrict__ cycles,
                                                            int* __restrict__ counts, double floor_factor) {
-    __shared__ int cnt[2][BMG_DECIDE_T / 64];
-    int a_sum = 0, nan_sum = 0;
+    __shared__ int cnt[3][BMG_DECIDE_T / 64];
+    int a_sum = 0, nan_sum = 0, e_sum = 0;
     for (int k = threadIdx.x; k < n; k += BMG_DECIDE_T) {
         if (!active[k]) continue;
+        ++e_sum;
         const double r = __longlong_as_double((long long)res[2 * k]);
         const double sc = __longlong_as_double((long long)res[2 * k + 1]);
         res[2 * k] = 0ULL;
@@ -1256,16 +1241,21 @@ __global__ void __launch_bounds__(BMG_DECIDE_T) kbm_decide(const MgChan<T, TC>* 
     for (int off = 32; off > 0; off >>= 1) {
         a_sum += __shfl_xor(a_sum, off, 64);
         nan_sum += __shfl_xor(nan_sum, off, 64);
+        e_sum += __shfl_xor(e_sum, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         cnt[0][threadIdx.x >> 6] = a_sum;
         cnt[1][threadIdx.x >> 6] = nan_sum;
+        cnt[2][threadIdx.x >> 6] = e_sum;
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
+    if (threadIdx.x < 3) {
         int t = 0;
         for (int w = 0; w < BMG_DECIDE_T / 64; ++w) t += cnt[threadIdx.x][w];
-        counts[threadIdx.x] = t;
+        if (threadIdx.x < 2)
+            counts[threadIdx.x] = t;
+        else if (t > 0)
+            ++counts[2];
     }
 }
 
