@@ -59,12 +59,13 @@ def values_per_site(solver: str) -> dict:
     return v
 
 
-def step_bytes_per_site(esz: int, cycles: float, solver: str, extrapolate: bool, smooth: int = 1) -> float:
+def step_bytes_per_site(esz: int, cycles: float, solver: str, extrapolate: int, smooth: int = 1) -> float:
     """Algorithmic HBM bytes per lattice site of one whole coupled step (every launch, each
     plane counted once per pass, tile halos and re-reads not counted).  Values are esz bytes;
     the multigrid's coarse levels are FP32 and level l holds 4^-l of the sites.
-    collide-and-stream 57 values; phase moments 18 read + 3 written; warm start (quadratic:
-    psi', two history planes read and written) 6; mu_r read once for the coarse mu of all
+    collide-and-stream 57 values; phase moments 18 read + 3 written; warm start (psi' and the
+    three history planes written, psi' and two of them read, the third too for the cubic
+    start) 7, or 8 when cubic; mu_r read once for the coarse mu of all
     levels (FP32 writes: sum 4 * 4^-l = 4/3 B).  A V-cycle on the finest level: `smooth`
     pre-smoothing launches of 3 (psi', mu_r read, result written), restriction fused with the
     level-1 smoothing 2 read + 2 B of FP32 writes (f and u of level 1), `smooth`
@@ -72,7 +73,7 @@ def step_bytes_per_site(esz: int, cycles: float, solver: str, extrapolate: bool,
     coarse level (one launch down, one up) repeats the single-launch pattern in FP32 on 4^-l
     of the sites: sum_l 8 * 4 * 4^-l = 32/3 B.  An SOR sweep: mu_r and psi' read, psi' written; a
     residual test every sweep adds two reads."""
-    b = (57 + 21) * esz + (6 * esz if extrapolate else 0)
+    b = (57 + 21) * esz + ((8 if extrapolate == 3 else 7) * esz if extrapolate else 0)
     if solver == "mg":
         b += esz + 4.0 / 3.0 + cycles * ((6 * smooth + 2) * esz + 3 + 32.0 / 3.0)
     else:
@@ -136,7 +137,8 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     """The 64-channel regime sweep (ny ~ U{64..256}, nx = 4 ny) as one FP32 batch and, for
     the gain at equal precision, as one FP64 batch at the single channels' tolerance, both
     with the batched multigrid (one finest sweep each way), against the same channels run
-    one after another as single FP64 channels on this GPU (multigrid, two finest sweeps).
+    one after another as single FP64 channels on this GPU (multigrid, two finest sweeps, cubic
+    warm start).
     The FP32 batch with its tuned four-colour SOR is timed too (the batch's other solver).
     The rates are extrapolated to the sweep's 10k steps per channel from timed windows.
     Tuners run before the timed windows and are not part of them."""
@@ -184,7 +186,7 @@ def batched_sweep(torch, steps: int, seq_steps: int) -> dict:
     del bt
     seq = 0.0
     for w in (ws if seq_steps > 0 else []):
-        ch = Channel(w, tol=1e-10, smooth=2)
+        ch = Channel(w, tol=1e-10, smooth=2, extrapolate=3)
         ch.init_droplet()
         ch.step(5)
         torch.cuda.synchronize()
@@ -370,7 +372,7 @@ def quasi_static(torch, steps: int) -> dict:
     ref = None
     out = {"workload": "channel_2048x512_fp64_bo2", "steps": steps}
     for K in (1, 4, 8):
-        ch = Channel(w, tol=1e-10, every=K)
+        ch = Channel(w, tol=1e-10, every=K, extrapolate=3)
         ch.init_droplet()
         ch.solve_potential(1e-10)
         ch.step(8)  # every K divides 8: the timed window starts on a solve step
@@ -405,7 +407,7 @@ def open_channel(torch, steps: int) -> dict:
     periodic = w.replace(u_inlet=None, drive_G=channel_drive(w.u_inlet, w.rho[2], w.tau[2], w.ny))
     out = {"workload": "open_channel_900x150_fp64_bo2", "steps": steps}
     for name, ww in (("open", w), ("periodic", periodic)):
-        ch = Channel(ww, tol=1e-10, smooth=2)
+        ch = Channel(ww, tol=1e-10, smooth=2, extrapolate=3)
         ch.init_droplet()
         ch.solve_potential(1e-10)
         ch.step(20)
@@ -458,7 +460,8 @@ def main() -> int:
     ap.add_argument("--smooth", type=int, default=3)
     ap.add_argument("--coarse-sweeps", type=int, default=2)
     ap.add_argument("--check-every", type=int, default=1)
-    ap.add_argument("--no-extrapolate", action="store_true")
+    ap.add_argument("--no-extrapolate", action="store_true")  # the same as --extrapolate 0
+    ap.add_argument("--extrapolate", type=int, choices=(0, 1, 2, 3), default=3)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -493,9 +496,10 @@ def main() -> int:
     w = single_channel_large(bond=args.bond)
     log(f"bench: {w.name} {w.nx}x{w.ny} {args.precision} Bo_m={args.bond} H0={w.H0:.5g} tol={tol:g}")
     solver = fcd.FCD_SOLVER_MG if args.solver == "mg" else fcd.FCD_SOLVER_SOR
+    extrap = 0 if args.no_extrapolate else args.extrapolate
     ch = Channel(w, precision=prec, solver=solver, tol=tol, check_every=args.check_every if args.solver == "mg" else 8,
                  max_iters=1 << 30, smooth=args.smooth, coarse_sweeps=args.coarse_sweeps,
-                 extrapolate=0 if args.no_extrapolate else 2)
+                 extrapolate=extrap)
     ch.init_droplet()
     t0 = time.perf_counter()
     st, sw0, res0 = ch.solve_potential(tol, 1 << 30)
@@ -558,7 +562,7 @@ def main() -> int:
             "frac": round(per_kind[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": VALUES_PER_SITE[dom] * esz * sites}
     cycles = sweeps / max(args.steps, 1)
-    step_b = step_bytes_per_site(esz, cycles, args.solver, not args.no_extrapolate, args.smooth)
+    step_b = step_bytes_per_site(esz, cycles, args.solver, extrap, args.smooth)
     step_gbps = step_b * sites / (dt / args.steps) / 1e9
     kernel_ms = sum(per_kind[k]["ms_per_step"] for k in ("collide_stream", "phase") if k in per_kind)
     ms_step = dt / args.steps * 1e3

@@ -88,7 +88,8 @@ struct MgPlan {
     double kappa_top[MAX_LEVELS];  // upper ghost rule of each level (fcd_potential.hip)
     size_t off_mu[MAX_LEVELS], off_u[MAX_LEVELS], off_f[MAX_LEVELS], off_t[MAX_LEVELS];
     size_t off_prev;  // psi' history planes: psi'(t-1) ...
-    size_t off_prev2; // ... and psi'(t-2) (quadratic extrapolation)
+    size_t off_prev2; // ... psi'(t-2) (quadratic extrapolation) ...
+    size_t off_prev3; // ... and psi'(t-3) (cubic extrapolation)
     size_t bytes;     // total scratch
 };
 
@@ -134,6 +135,8 @@ MgPlan make_plan(const fcd_lattice& l) {
     p.off_prev = off;
     off += align256((size_t)l.ny * l.pitch * esz);
     p.off_prev2 = off;
+    off += align256((size_t)l.ny * l.pitch * esz);
+    p.off_prev3 = off;
     off += align256((size_t)l.ny * l.pitch * esz);
     for (int L = 0; L < p.levels; ++L) {
         const size_t plane = align256((size_t)p.ny[L] * p.pitch[L] * (L == 0 ? esz : sizeof(CT)));
@@ -317,7 +320,8 @@ fcd_status check_params(const fcd_params* p) {
     if (p->pot_check_every < 1 || p->pot_max_iters < 0) return fail(FCD_ERR_ARG, "bad potential iteration counts");
     if (p->pot_solver == FCD_SOLVER_MG && (p->pot_smooth < 1 || p->pot_coarse_sweeps == 0))
         return fail(FCD_ERR_ARG, "multigrid needs pot_smooth >= 1 and pot_coarse_sweeps != 0");
-    if (p->pot_extrapolate < 0 || p->pot_extrapolate > 2) return fail(FCD_ERR_ARG, "pot_extrapolate must be 0, 1 or 2");
+    if (p->pot_extrapolate < 0 || p->pot_extrapolate > 3)
+        return fail(FCD_ERR_ARG, "pot_extrapolate must be 0, 1, 2 or 3");
     if (p->pot_every < 0) return fail(FCD_ERR_ARG, "pot_every must be >= 0");
     if (!(p->u_limit >= 0.0)) return fail(FCD_ERR_ARG, "u_limit must be >= 0 (0: default)");
     if (p->div_check_every < 0) return fail(FCD_ERR_ARG, "div_check_every must be >= 0 (0: default)");
@@ -818,6 +822,7 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
     T* phi = static_cast<T*>(h->buf.phi);
     T* prev = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev);
     T* prev2 = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev2);
+    T* prev3 = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev3);
     for (int n = 0; n < nsteps; ++n) {
         const T* src = static_cast<const T*>(h->buf.dist[h->cur]);
         T* dst = static_cast<T*>(h->buf.dist[1 - h->cur]);
@@ -833,9 +838,11 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
         if (h->qs % K == 0) {
             if (h->prm.pot_extrapolate && h->prm.H0 != 0.0) {
                 // the first solve's start (the initial solve) is not extrapolated from; linear
-                // from the third solve, quadratic from the fourth
-                const int mode = h->hist >= 3 && h->prm.pot_extrapolate == 2 ? 2 : h->hist >= 2 ? 1 : 0;
-                fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, h->lat.nx, h->lat.ny,
+                // from the third solve, quadratic from the fourth, cubic from the fifth (up to
+                // the order pot_extrapolate asks for)
+                const int ex = h->prm.pot_extrapolate;
+                const int mode = h->hist >= 4 && ex == 3 ? 3 : h->hist >= 3 && ex >= 2 ? 2 : h->hist >= 2 ? 1 : 0;
+                fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, prev3, h->lat.nx, h->lat.ny,
                                            h->lat.pitch, mode, h->stream);
             }
             st = solve_impl<T>(h, h->prm.pot_tol, h->prm.pot_max_iters, nullptr, nullptr);
@@ -1733,7 +1740,7 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
                 // linear from the third solve; with the multigrid and pot_extrapolate == 2
                 // quadratic from the fourth (in SOR batches its coefficients amplify the FP32
                 // solve's rounding, so they start linearly whatever pot_extrapolate says)
-                const int mode = b->mg && p0.pot_extrapolate == 2 && b->hist >= 3 ? 2 : b->hist >= 2 ? 1 : 0;
+                const int mode = b->mg && p0.pot_extrapolate >= 2 && b->hist >= 3 ? 2 : b->hist >= 2 ? 1 : 0;
                 fcd::launch_batch_psi_history<T>(binst<T>(b), t, mode, b->stream);
             }
             st = b->mg ? batch_solve_mg<T>(b, p0.pot_max_iters)
@@ -1934,7 +1941,7 @@ fcd_status batch_moments_impl(fcd_batch* b, int k, unsigned mask, double* out) {
 // ---------------------------------------------------------------------------------
 struct AdjLayout {
     size_t plane, state;
-    size_t crec;  // checkpoint record: state, psi' and the two psi' history planes (warm start)
+    size_t crec;  // checkpoint record: state, psi' and the three psi' history planes (warm start)
     size_t srec;  // segment record: state and the step's psi'
     int nseg, nblocks;
     size_t off_ckpt, off_final, off_seg, off_lam, off_sens, off_rhs, off_lpsi, off_lprev, off_lprev2, off_part, off_acc,
@@ -1945,7 +1952,7 @@ AdjLayout adj_layout(const fcd_lattice& l, int nsteps, int every) {
     AdjLayout L{};
     L.plane = (size_t)l.ny * l.pitch * elem_size(l.precision);
     L.state = 27 * L.plane;
-    L.crec = align256(L.state + 3 * L.plane);
+    L.crec = align256(L.state + 4 * L.plane);
     L.srec = align256(L.state + L.plane);
     L.nseg = (nsteps + every - 1) / every;
     L.nblocks = fcd::adj_blocks(l.nx, l.ny);
@@ -1987,7 +1994,8 @@ fcd_status dcopy(void* dst, const void* src, size_t bytes, hipStream_t s) {
 // iteration count are kept on the host beside them.
 template <typename T>
 T* psi_prev(fcd_handle* h, int k = 1) {
-    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + (k == 1 ? h->plan.off_prev : h->plan.off_prev2));
+    const size_t off = k == 1 ? h->plan.off_prev : k == 2 ? h->plan.off_prev2 : h->plan.off_prev3;
+    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + off);
 }
 
 template <typename T>
@@ -1996,6 +2004,7 @@ fcd_status save_record(fcd_handle* h, char* rec, const AdjLayout& L) {
     if (!st) st = dcopy(rec + L.state, h->buf.psi, L.plane, h->stream);
     if (!st) st = dcopy(rec + L.state + L.plane, psi_prev<T>(h), L.plane, h->stream);
     if (!st) st = dcopy(rec + L.state + 2 * L.plane, psi_prev<T>(h, 2), L.plane, h->stream);
+    if (!st) st = dcopy(rec + L.state + 3 * L.plane, psi_prev<T>(h, 3), L.plane, h->stream);
     return st;
 }
 
@@ -2005,6 +2014,7 @@ fcd_status load_record(fcd_handle* h, const char* rec, const AdjLayout& L) {
     if (!st) st = dcopy(h->buf.psi, rec + L.state, L.plane, h->stream);
     if (!st) st = dcopy(psi_prev<T>(h), rec + L.state + L.plane, L.plane, h->stream);
     if (!st) st = dcopy(psi_prev<T>(h, 2), rec + L.state + 2 * L.plane, L.plane, h->stream);
+    if (!st) st = dcopy(psi_prev<T>(h, 3), rec + L.state + 3 * L.plane, L.plane, h->stream);
     return st;
 }
 
@@ -2106,10 +2116,10 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
                     // warm start: linear extrapolation of the last two adjoint solutions
                     if (h->prm.pot_extrapolate) {
                         // the adjoint potentials of successive (reversed) steps, extrapolated
-                        // as in the forward
-                        const int mode = lhist >= 3 && h->prm.pot_extrapolate == 2 ? 2 : lhist >= 2 ? 1 : 0;
-                        fcd::launch_psi_history<T>(lpsi, lprev, lprev2, h->lat.nx, h->lat.ny, h->lat.pitch, mode,
-                                                   h->stream);
+                        // as in the forward, at most quadratically
+                        const int mode = lhist >= 3 && h->prm.pot_extrapolate >= 2 ? 2 : lhist >= 2 ? 1 : 0;
+                        fcd::launch_psi_history<T>(lpsi, lprev, lprev2, static_cast<T*>(nullptr), h->lat.nx,
+                                                   h->lat.ny, h->lat.pitch, mode, h->stream);
                     }
                     ++lhist;
                     fcd::PotLevel<T> La = pot_level<T>(h, 0);

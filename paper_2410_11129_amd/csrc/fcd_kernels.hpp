@@ -54,7 +54,7 @@ size_t mg_tail_lds_bytes(const MgTail<T>& tl);
 template <typename T>
 void launch_mg_tail(const MgTail<T>& tl, hipStream_t s);
 template <typename T>
-void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, int mode, hipStream_t s);
+void launch_psi_history(T* psi, T* prev, T* prev2, T* prev3, int nx, int ny, int pitch, int mode, hipStream_t s);
 
 // Batched multigrid (fcd_potential.hip): one launch per level for every channel of a
 // batch, jobs = (channel, level, tile), channels with active[k] == 0 skipped.

@@ -930,11 +930,13 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
 
 // Warm start from the recorded solutions: mode 0 keeps psi' and records it; mode 1
 // replaces psi' by the linear extrapolation 2 psi'(t-1) - psi'(t-2), mode 2 by the
-// quadratic one 3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3); prev records psi'(t-1) and, when
-// prev2 is given, prev2 the previous prev.
+// quadratic one 3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3), mode 3 by the cubic one
+// 4 psi'(t-1) - 6 psi'(t-2) + 4 psi'(t-3) - psi'(t-4); prev records psi'(t-1), and each
+// further plane given (prev2, prev3) the one before it.
 template <typename T>
 __global__ void __launch_bounds__(PX* PY) k_psi_history(T* __restrict__ psi, T* __restrict__ prev,
-                                                        T* __restrict__ prev2, int nx, int ny, int pitch, int mode) {
+                                                        T* __restrict__ prev2, T* __restrict__ prev3, int nx, int ny,
+                                                        int pitch, int mode) {
     const int i = blockIdx.x * PX + threadIdx.x, j = blockIdx.y * PY + threadIdx.y;
     if (i >= nx || j >= ny) return;
     const long long k = (long long)j * pitch + i;
@@ -942,6 +944,8 @@ __global__ void __launch_bounds__(PX* PY) k_psi_history(T* __restrict__ psi, T* 
     const T p1 = prev[k];
     if (mode == 1) psi[k] = T(2) * cur - p1;
     if (mode == 2) psi[k] = T(3) * (cur - p1) + prev2[k];
+    if (mode == 3) psi[k] = T(4) * (cur + prev2[k]) - T(6) * p1 - prev3[k];
+    if (prev3) prev3[k] = prev2[k];
     if (prev2) prev2[k] = p1;
     prev[k] = cur;
 }
@@ -1058,8 +1062,9 @@ void launch_mg_tail(const MgTail<T>& tl, hipStream_t s) {
 }
 
 template <typename T>
-void launch_psi_history(T* psi, T* prev, T* prev2, int nx, int ny, int pitch, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_psi_history<T>, pgrid(nx, ny), dim3(PX, PY), 0, s, psi, prev, prev2, nx, ny, pitch, mode);
+void launch_psi_history(T* psi, T* prev, T* prev2, T* prev3, int nx, int ny, int pitch, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_psi_history<T>, pgrid(nx, ny), dim3(PX, PY), 0, s, psi, prev, prev2, prev3, nx, ny, pitch,
+                       mode);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1326,7 +1331,7 @@ void launch_bmg_decide(const MgChan<T, TC>* ch, int n, unsigned long long* res, 
     template void launch_pot_residual<T>(const PotLevel<T>&, unsigned long long*, hipStream_t);           \
     template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
     template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \
-    template void launch_psi_history<T>(T*, T*, T*, int, int, int, int, hipStream_t);
+    template void launch_psi_history<T>(T*, T*, T*, T*, int, int, int, int, hipStream_t);
 
 // Multigrid transfer and smoothing kernels between a level of type T and coarse levels of
 // type TC (the coarse levels are FP32 under an FP64 finest level).

@@ -105,7 +105,7 @@ def test_batch_schedule_calls_and_warm_start_order_validated_on_host():
     st = L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h := C.c_void_p()))
     assert st == fcd.FCD_ERR_ARG and "pot_coarse_sweeps" in fcd.fcd_last_error()
     p = good_params()
-    p.pot_extrapolate = 3
+    p.pot_extrapolate = 4  # 0..3: none, linear, quadratic, cubic
     h = C.c_void_p()
     st = L.fcd_create(C.byref(lat), C.byref(p), C.byref(buf), None, C.byref(h))
     assert st == fcd.FCD_ERR_ARG and "pot_extrapolate" in fcd.fcd_last_error()

@@ -139,9 +139,9 @@ def test_adjoint_matches_oracle_central_differences():
     ch.close()
 
 
-def cs_check(w, nsteps, every, rel):
+def cs_check(w, nsteps, every, rel, extrapolate=2):
     theta = theta_of(w)
-    ch = Channel(w, tol=1e-13)
+    ch = Channel(w, tol=1e-13, extrapolate=extrapolate)
     run = AdjointRun(ch, nsteps, every)
     D = run.forward(theta)
     g = np.array(run.backward([A_O, A_I]))
@@ -175,6 +175,15 @@ def test_adjoint_matches_oracle_complex_step_gradient_over_300_steps():
     w = small_channel()
     say(f"case adjoint vs oracle complex step, {w.nx}x{w.ny}, 300 steps, ckpt 25")
     cs_check(w, 300, 25, 1e-10)
+
+
+def test_adjoint_with_cubic_warm_start_matches_oracle_complex_step_gradient():
+    """The forward's solves started from the cubic extrapolation in time (the checkpoints
+    record the third history plane, so recomputed segments repeat the forward exactly; the
+    adjoint solves start at most quadratically)."""
+    w = small_channel()
+    say(f"case adjoint cubic start vs oracle complex step, {w.nx}x{w.ny}, {NSTEPS} steps, ckpt 8")
+    cs_check(w, NSTEPS, 8, 1e-10, extrapolate=3)
 
 
 def test_checkpoint_interval_does_not_change_gradient():

@@ -96,6 +96,24 @@ def test_moments_parity():
         assert np.abs(gm[k] - om[k]).max() < 1e-11, k
 
 
+def test_channel_200x50_1000_steps_cubic_warm_start():
+    """The multigrid with the cubic warm start in time (pot_extrapolate = 3): every field
+    within 1e-10 of the oracle after 1000 steps, as with the quadratic start."""
+    w = single_channel_small(steps=1000)
+    say("case channel 200x50 fp64 1000 steps, cubic warm start")
+    g = Channel(w, extrapolate=3, **MG_TIGHT)
+    g.init_droplet()
+    g.step(w.steps)
+    s = OracleSim(w)
+    s.init_droplet(solve=False)
+    assert s.step(w.steps) == 0
+    assert np.abs(g.state() - oracle_state(s)).max() < 1e-10
+    gm, om = g.moments(), s.moments()
+    for k in om:
+        assert np.abs(gm[k] - om[k]).max() < 1e-10, k
+    g.close()
+
+
 @pytest.mark.parametrize("nx,ny", [(90, 15), (200, 75), (200, 97), (226, 37), (130, 19), (900, 150)])
 def test_potential_parity_odd_hierarchy(nx, ny):
     """Multigrid on lattices whose hierarchy passes odd sizes (coarse levels of
