@@ -457,7 +457,7 @@ def main() -> int:
     # finest-level smoothing sweeps (one launch each) before and after each coarse
     # correction: 3 needs 2.15 V-cycles per step against 4.0 with 1 (measured, 2048 x 512
     # FP64 Bo_m = 2, steps 501-540: 0.531 against 0.632 ms/step; 4, 5, 6: 0.556, 0.601, 0.649)
-    ap.add_argument("--smooth", type=int, default=3)
+    ap.add_argument("--smooth", type=int, default=2)
     ap.add_argument("--coarse-sweeps", type=int, default=2)
     ap.add_argument("--check-every", type=int, default=1)
     ap.add_argument("--no-extrapolate", action="store_true")  # the same as --extrapolate 0

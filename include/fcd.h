@@ -93,8 +93,8 @@ typedef struct {
                                 extrapolation 2 psi'(t-1) - psi'(t-2), 2 the quadratic one
                                 3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3), 3 the cubic one
                                 4 psi'(t-1) - 6 psi'(t-2) + 4 psi'(t-3) - psi'(t-4) (each order once
-                                that many solutions exist); batches: multigrid at most quadratic,
-                                SOR linear; the adjoint solves at most quadratic */
+                                that many solutions exist); SOR batches: linear at most; the
+                                adjoint solves: quadratic at most */
     int32_t pot_every;       /* quasi-static coupling: the potential is solved on steps 0, K, 2K, ...
                                 after the last state change and held in between (K = pot_every;
                                 0 or 1: every step, the paper's coupling; the adjoints need <= 1;

@@ -1014,7 +1014,7 @@ constexpr int BATCH_MAX_CHANNELS = 65536;
 
 struct BatchLayout {
     std::vector<int> pitch;
-    std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev, off_prev2, off_alt;  // into state / aux
+    std::vector<size_t> off_d0, off_d1, off_phi, off_psi, off_prev, off_prev2, off_prev3, off_alt;  // state / aux
     std::vector<int> tile0[fcd::BATCH_SHAPES], tiles_x[fcd::BATCH_SHAPES];
     std::vector<int> ctile0[fcd::BATCH_SHAPES], ctiles_x[fcd::BATCH_SHAPES];
     std::vector<int> stile0, stiles_x;  // fused-sweep tiles
@@ -1089,6 +1089,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
         L->off_prev.push_back(L->aux_bytes);
         L->aux_bytes += plane;
         L->off_prev2.push_back(L->aux_bytes);
+        L->aux_bytes += plane;
+        L->off_prev3.push_back(L->aux_bytes);
         L->aux_bytes += plane;
         L->off_alt.push_back(L->aux_bytes);
         L->aux_bytes += plane;
@@ -1302,6 +1304,7 @@ fcd::BatchInst<T> make_batch_inst(const fcd_batch* b, int k) {
     I.phi = bptr<T>(b->aux, b->L.off_phi[k]);
     I.prev = bptr<T>(b->aux, b->L.off_prev[k]);
     I.prev2 = bptr<T>(b->aux, b->L.off_prev2[k]);
+    I.prev3 = bptr<T>(b->aux, b->L.off_prev3[k]);
     I.alt = bptr<T>(b->aux, b->L.off_alt[k]);
     I.L0.u = bptr<T>(b->aux, b->L.off_psi[k]);
     I.L0.mu = I.phi + 2 * (long long)I.P.plane;
@@ -1737,10 +1740,11 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
         if (st) return st;
         if (b->qs % std::max(1, p0.pot_every) == 0) {  // quasi-static coupling, as fcd_step
             if (p0.pot_extrapolate) {
-                // linear from the third solve; with the multigrid and pot_extrapolate == 2
-                // quadratic from the fourth (in SOR batches its coefficients amplify the FP32
-                // solve's rounding, so they start linearly whatever pot_extrapolate says)
-                const int mode = b->mg && p0.pot_extrapolate >= 2 && b->hist >= 3 ? 2 : b->hist >= 2 ? 1 : 0;
+                // linear from the third solve; with the multigrid quadratic from the fourth and
+                // cubic from the fifth, up to pot_extrapolate (in SOR batches the higher orders'
+                // coefficients amplify the FP32 solve's rounding, so they start linearly)
+                const int ex = b->mg ? p0.pot_extrapolate : 1;
+                const int mode = ex >= 3 && b->hist >= 4 ? 3 : ex >= 2 && b->hist >= 3 ? 2 : b->hist >= 2 ? 1 : 0;
                 fcd::launch_batch_psi_history<T>(binst<T>(b), t, mode, b->stream);
             }
             st = b->mg ? batch_solve_mg<T>(b, p0.pot_max_iters)
@@ -2203,12 +2207,12 @@ BatchAdjLayout batch_adj_layout(const fcd_batch* b, int nsteps, int every) {
     for (int k = 0; k < b->n; ++k) {
         const size_t pl = align256((size_t)b->lat[k].ny * b->L.pitch[k] * esz);
         A.plane.push_back(pl);
-        A.crec.push_back(30 * pl);
+        A.crec.push_back(31 * pl);
         A.srec.push_back(28 * pl);
         A.off_ckpt.push_back(off);
-        off += (size_t)A.nseg * 30 * pl;
+        off += (size_t)A.nseg * 31 * pl;
         A.off_final.push_back(off);
-        off += 30 * pl;
+        off += 31 * pl;
         A.off_seg.push_back(off);
         off += (size_t)every * 28 * pl;
         A.off_lam0.push_back(off);
@@ -2255,6 +2259,7 @@ fcd_status batch_save_records(fcd_batch* b, const BatchAdjLayout& A, const std::
         if (!st) st = dcopy(rec + 27 * pl, b->aux + b->L.off_psi[k], pl, b->stream);
         if (!st) st = dcopy(rec + 28 * pl, b->aux + b->L.off_prev[k], pl, b->stream);
         if (!st) st = dcopy(rec + 29 * pl, b->aux + b->L.off_prev2[k], pl, b->stream);
+        if (!st) st = dcopy(rec + 30 * pl, b->aux + b->L.off_prev3[k], pl, b->stream);
     }
     return st;
 }
@@ -2268,6 +2273,7 @@ fcd_status batch_load_records(fcd_batch* b, const BatchAdjLayout& A, const std::
         if (!st) st = dcopy(b->aux + b->L.off_psi[k], rec + 27 * pl, pl, b->stream);
         if (!st) st = dcopy(b->aux + b->L.off_prev[k], rec + 28 * pl, pl, b->stream);
         if (!st) st = dcopy(b->aux + b->L.off_prev2[k], rec + 29 * pl, pl, b->stream);
+        if (!st) st = dcopy(b->aux + b->L.off_prev3[k], rec + 30 * pl, pl, b->stream);
     }
     return st;
 }
@@ -2286,6 +2292,7 @@ fcd_status batch_adj_forward_impl(fcd_batch* b, int nsteps, int every, char* wor
         I.L0.H0x = I.L0.H0y = T(0);
         I.prev = reinterpret_cast<T*>(work + A.off_lprev[k]);
         I.prev2 = nullptr;  // the adjoint solves start linearly
+        I.prev3 = nullptr;
         fcd::BatchAdj<T>& D = adj[k];
         D.seg = reinterpret_cast<T*>(work + A.off_seg[k]);
         D.srec = (long long)(A.srec[k] / sizeof(T));

@@ -472,6 +472,8 @@ __global__ void __launch_bounds__(TBX* TY) kb_psi_history(const BatchInst<T>* __
     const T p1 = B.prev[q];
     if (mode == 1) B.L0.u[q] = T(2) * cur - p1;
     if (mode == 2) B.L0.u[q] = T(3) * (cur - p1) + B.prev2[q];
+    if (mode == 3) B.L0.u[q] = T(4) * (cur + B.prev2[q]) - T(6) * p1 - B.prev3[q];
+    if (B.prev3) B.prev3[q] = B.prev2[q];
     if (B.prev2) B.prev2[q] = p1;
     B.prev[q] = cur;
 }

@@ -18,7 +18,8 @@ struct BatchInst {
     T* dist[2];       // the two state buffers (27 planes each)
     T* phi;           // phi1, phi2, mu_r planes
     T* prev;          // psi' history plane: psi'(t-1) ...
-    T* prev2;         // ... and psi'(t-2) (quadratic start of the multigrid batch; may be null)
+    T* prev2;         // ... psi'(t-2) (quadratic start of the multigrid batch; may be null) ...
+    T* prev3;         // ... and psi'(t-3) (its cubic start; may be null)
     T* alt;           // second potential plane of the fused sweeps (input and output alternate)
     T omega;          // SOR factor
     double thr;       // stop when max |residual| <= thr (= tol * H0)
