@@ -30,7 +30,7 @@ METRIC = "MLUPS + HBM GB/s of coupled step; batched instances/hr; adjoint/forwar
 # of the sources the kernel was built from; reported only while the sources are unchanged.
 TRAFFIC_BYTES = {"collide_stream": (2 * 129848 + 230388) * 1024}
 TRAFFIC_SOURCES = {"paper_2410_11129_amd/csrc/fcd_step.hpp": "0955c195fe226b4b",
-                   "paper_2410_11129_amd/csrc/fcd_device.hpp": "fedf834776d01323",
+                   "paper_2410_11129_amd/csrc/fcd_device.hpp": "a671d488bf7046bc",
                    "paper_2410_11129_amd/csrc/fcd_kernels.hip": "b646750e3bcf8da3"}
 
 
