@@ -293,8 +293,9 @@ def adjoint_ratio(torch, steps: int, every: int) -> dict:
 def batched_adjoint(torch, steps: int, every: int) -> dict:
     """The 32 adjoint channels (256 x 64, Bo_m ~ U(0, 6), Ca ~ U(0.05, 0.2), random field
     angle) as one batch: checkpointed forward + batched reverse sweep of `steps` steps, in
-    FP32 and in FP64, against the single-channel FP64 adjoint of the first two channels run
-    one after another (per-instance rates)."""
+    FP32 and in FP64, the forward and adjoint potentials by the batched multigrid, against the
+    single-channel FP64 adjoint of the first two channels run one after another
+    (per-instance rates)."""
     from fcd_inputs import adjoint_batch
     from paper_2410_11129_amd import fcd
     from paper_2410_11129_amd.adjoint import AdjointRun, BatchAdjointRun, theta_of
@@ -329,11 +330,8 @@ def batched_adjoint(torch, steps: int, every: int) -> dict:
     out = {"channels": len(ws), "steps": steps, "ckpt_every": every,
            "s_per_gradient_sequential_fp64": round(per_seq, 4),
            "fp64_gradient_change_under_6e-8_perturbation": float(f"{sens:.3e}")}
-    for name, prec, tol in (("fp32", fcd.FCD_FP32, 1e-5), ("fp64", fcd.FCD_FP64, 1e-10)):
-        bt = Batch(ws, precision=prec, tol=tol)
-        bt.init_droplets()
-        bt.step(8)
-        bt.tune_omega(4)  # not timed
+    for name, prec, tol, sm in (("fp32", fcd.FCD_FP32, 1e-5, 1), ("fp64", fcd.FCD_FP64, 1e-10, 2)):
+        bt = Batch(ws, precision=prec, tol=tol, solver=fcd.FCD_SOLVER_MG, smooth=sm)
         bt.init_droplets()
         run = BatchAdjointRun(bt, steps, every)
         torch.cuda.synchronize()

@@ -1031,7 +1031,7 @@ struct BatchLayout {
     int mg_lmax = 0;
     std::vector<MgPlan> mg;
     std::vector<size_t> off_mgc;
-    size_t off_mgchan = 0, off_jobs = 0, off_mgres = 0, off_mgcycles = 0;
+    size_t off_mgchan = 0, off_mgchan_adj = 0, off_jobs = 0, off_mgres = 0, off_mgcycles = 0;
     std::vector<fcd::MgJob> jobs;
     int fine0 = 0, nfine = 0;                                   // level-0 64 x 16 tiles
     int mu0[4] = {}, nmu[4] = {};                              // mu groups 1..3 (group 0: the fine list)
@@ -1161,6 +1161,8 @@ fcd_status batch_layout(int n, const fcd_lattice* lats, BatchLayout* L) {
         const size_t chan_sz = prec == FCD_FP64 ? sizeof(fcd::MgChan<double, CT>) : sizeof(fcd::MgChan<float, CT>);
         L->off_mgchan = off;
         off = align256(off + (size_t)n * chan_sz);
+        L->off_mgchan_adj = off;  // the batched adjoint's potential problems
+        off = align256(off + (size_t)n * chan_sz);
         // job lists, in launch order of a V-cycle
         auto tiles = [&](int k, int l, int sx, int sy) {
             const MgPlan& p = L->mg[k];
@@ -1252,7 +1254,8 @@ struct fcd_batch {
     // every channel has a hierarchy with a tail)
     bool mg;
     size_t mg_lds;       // dynamic LDS of the batched tail launch (largest channel's tail)
-    int mg_last_cycles;  // graph-launched cycles the previous solve needed
+    int mg_last_cycles;  // cycles the previous forward solve needed
+    int adj_mg_last_cycles;  // ... and the previous adjoint solve
 };
 
 namespace {
@@ -1653,10 +1656,29 @@ fcd_status batch_solve(fcd_batch* b, const BatchProblem<T>& P, int max_iters) {
 constexpr int BMG_INNER = 2;            // tile sweeps per launch on the tiled coarse levels
 constexpr int BMG_BLOCK_CYCLES = 2;     // V-cycles per graph launch
 
+// A batched potential problem: the descriptors (finest level's iterate, right-hand side from
+// the field or from a plane), the thresholds (the descriptors' absolute ones, or rel_tol times
+// per-channel scales on the device) and the cycle count of its previous solve.
 template <typename T>
-void bmg_cycle(fcd_batch* b) {
+struct BmgProblem {
+    const fcd::MgChan<T, CT>* ch;
+    bool rhs_plane;
+    const unsigned long long* scale;
+    double rel_tol;
+    int* last_cycles;
+};
+
+template <typename T>
+BmgProblem<T> bmg_forward(fcd_batch* b) {
+    return {reinterpret_cast<const fcd::MgChan<T, CT>*>(b->scratch + b->L.off_mgchan), false, nullptr, 0.0,
+            &b->mg_last_cycles};
+}
+
+template <typename T>
+void bmg_cycle(fcd_batch* b, const BmgProblem<T>& P) {
     const BatchLayout& L = b->L;
-    const auto* ch = reinterpret_cast<const fcd::MgChan<T, CT>*>(b->scratch + L.off_mgchan);
+    const fcd::MgChan<T, CT>* ch = P.ch;
+    const bool rp = P.rhs_plane;
     const auto* jobs = reinterpret_cast<const fcd::MgJob*>(b->scratch + L.off_jobs);
     int* active = bptr<int>(b->scratch, b->L.off_active);
     unsigned long long* res = bptr<unsigned long long>(b->scratch, L.off_mgres);
@@ -1668,19 +1690,22 @@ void bmg_cycle(fcd_batch* b) {
     // pre-smoothing: sweep q reads the plane the previous one wrote (q even: psi' -> second)
     int cur = 0;  // plane holding the current finest iterate: 0 psi', 1 the second plane
     for (int q = 0; q < nu; ++q) {
-        fcd::launch_bmg_smooth_fine<T, CT>(ch, fine, L.nfine, active, cur, false, q == 0 ? res : nullptr, st);
+        fcd::launch_bmg_smooth_fine<T, CT>(ch, fine, L.nfine, active, cur, false, rp, q == 0 ? res : nullptr, st);
         cur = 1 - cur;
-        if (q == 0) fcd::launch_bmg_decide<T, CT>(ch, b->n, res, active, cycles, counts, resid_floor_factor<T>(), st);
+        if (q == 0)
+            fcd::launch_bmg_decide<T, CT>(ch, b->n, res, active, cycles, counts, resid_floor_factor<T>(), P.scale,
+                                          P.rel_tol, st);
     }
     for (int l = 1; l < L.mg_lmax; ++l)
-        if (L.nrs[l]) fcd::launch_bmg_restrict_smooth<T, CT>(ch, jobs + L.rs0[l], L.nrs[l], active, l, cur, BMG_INNER, st);
-    if (L.nrt0) fcd::launch_bmg_restrict_tail<T, CT>(ch, jobs + L.rt00, L.nrt0, active, true, cur, st);
-    if (L.nrtC) fcd::launch_bmg_restrict_tail<T, CT>(ch, jobs + L.rtC0, L.nrtC, active, false, cur, st);
+        if (L.nrs[l])
+            fcd::launch_bmg_restrict_smooth<T, CT>(ch, jobs + L.rs0[l], L.nrs[l], active, l, cur, BMG_INNER, rp, st);
+    if (L.nrt0) fcd::launch_bmg_restrict_tail<T, CT>(ch, jobs + L.rt00, L.nrt0, active, true, cur, rp, st);
+    if (L.nrtC) fcd::launch_bmg_restrict_tail<T, CT>(ch, jobs + L.rtC0, L.nrtC, active, false, cur, rp, st);
     fcd::launch_bmg_tail<T, CT>(ch, b->n, b->mg_lds, active, st);
     for (int l = L.mg_lmax - 1; l >= 1; --l)
         if (L.npost[l]) fcd::launch_bmg_post_coarse<T, CT>(ch, jobs + L.post0[l], L.npost[l], active, BMG_INNER, st);
     for (int q = 0; q < nu; ++q) {
-        fcd::launch_bmg_smooth_fine<T, CT>(ch, fine, L.nfine, active, cur, q == 0, nullptr, st);
+        fcd::launch_bmg_smooth_fine<T, CT>(ch, fine, L.nfine, active, cur, q == 0, rp, nullptr, st);
         cur = 1 - cur;
     }
     if (cur) fcd::launch_bmg_copy_fine<T, CT>(ch, fine, L.nfine, active, st);
@@ -1691,9 +1716,9 @@ void bmg_cycle(fcd_batch* b) {
 // reads the active count after each launch, except for the launches the previous solve
 // needed minus one.
 template <typename T>
-fcd_status batch_solve_mg(fcd_batch* b, int max_iters) {
+fcd_status batch_solve_mg(fcd_batch* b, const BmgProblem<T>& P, int max_iters) {
     const BatchLayout& L = b->L;
-    const auto* ch = reinterpret_cast<const fcd::MgChan<T, CT>*>(b->scratch + L.off_mgchan);
+    const fcd::MgChan<T, CT>* ch = P.ch;
     const auto* jobs = reinterpret_cast<const fcd::MgJob*>(b->scratch + L.off_jobs);
     fcd::launch_bmg_mu4<T, CT>(ch, jobs + L.fine0, L.nfine, 0, b->stream);
     for (int g = 1; g < 4; ++g)
@@ -1706,13 +1731,13 @@ fcd_status batch_solve_mg(fcd_batch* b, int max_iters) {
     // graph launches without a read: as many as the previous solve's cycles need, less one
     // (the decision kernel counts the cycles a solve needs, however many were launched)
     const int G = BMG_BLOCK_CYCLES;
-    int blind = b->mg_last_cycles > G ? (b->mg_last_cycles + G - 1) / G - 1 : 0;
+    int blind = *P.last_cycles > G ? (*P.last_cycles + G - 1) / G - 1 : 0;
     int left = 1, it = 0, needed = 0;
     while (left > 0) {
         if (it >= max_iters) break;
         st = run_graph_on(b->graphs, b->stream, false, ch, jobs, (7 << 24) + std::max(1, b->prm[0].pot_smooth),
                           [&]() {
-                              for (int c = 0; c < G; ++c) bmg_cycle<T>(b);
+                              for (int c = 0; c < G; ++c) bmg_cycle<T>(b, P);
                           });
         if (st) return st;
         it += G;
@@ -1724,7 +1749,7 @@ fcd_status batch_solve_mg(fcd_batch* b, int max_iters) {
         if (st) return st;
     }
     b->iters += it;
-    b->mg_last_cycles = needed;
+    *P.last_cycles = needed;
     b->last_resid = 0.0;
     if (left > 0) return fail(FCD_ERR_NOT_CONVERGED, "a channel's potential solve reached pot_max_iters");
     return FCD_OK;
@@ -1747,7 +1772,7 @@ fcd_status batch_step_impl(fcd_batch* b, int nsteps) {
                 const int mode = ex >= 3 && b->hist >= 4 ? 3 : ex >= 2 && b->hist >= 3 ? 2 : b->hist >= 2 ? 1 : 0;
                 fcd::launch_batch_psi_history<T>(binst<T>(b), t, mode, b->stream);
             }
-            st = b->mg ? batch_solve_mg<T>(b, p0.pot_max_iters)
+            st = b->mg ? batch_solve_mg<T>(b, bmg_forward<T>(b), p0.pot_max_iters)
                        : batch_solve<T>(b, forward_problem<T>(b), p0.pot_max_iters);
             if (st) return st;
             ++b->hist;
@@ -2305,6 +2330,17 @@ fcd_status batch_adj_forward_impl(fcd_batch* b, int nsteps, int every, char* wor
     }
     fcd_status st = hip_check(hipMemcpy(work + A.off_ainst, ainst.data(), ainst.size() * sizeof(ainst[0]),
                                         hipMemcpyHostToDevice), "adjoint descriptor upload");
+    if (!st && b->mg) {
+        // the adjoint potential problems for the batched multigrid: each channel's hierarchy
+        // with the adjoint potential plane and its right-hand side on the finest level
+        std::vector<fcd::MgChan<T, CT>> mch(b->n);
+        for (int k = 0; k < b->n; ++k) {
+            mch[k] = make_mgchan<T>(b, k);
+            mch[k].L0 = ainst[k].L0;
+        }
+        st = hip_check(hipMemcpy(b->scratch + b->L.off_mgchan_adj, mch.data(), mch.size() * sizeof(mch[0]),
+                                 hipMemcpyHostToDevice), "adjoint multigrid descriptor upload");
+    }
     if (!st) st = hip_check(hipMemcpy(work + A.off_adj, adj.data(), adj.size() * sizeof(adj[0]),
                                       hipMemcpyHostToDevice), "adjoint descriptor upload");
     if (st) return st;
@@ -2376,6 +2412,9 @@ fcd_status batch_adj_backward_impl(fcd_batch* b, const double* dJ, double* grad)
     b->adj_solve_iters = 0;
     const fcd_params& p0 = b->prm[0];
     const BatchProblem<T> adjP{ainst, scale, p0.pot_tol, &b->adj_solve_iters, true};
+    b->adj_mg_last_cycles = 0;
+    const BmgProblem<T> adjM{reinterpret_cast<const fcd::MgChan<T, CT>*>(b->scratch + b->L.off_mgchan_adj), true, scale,
+                             p0.pot_tol, &b->adj_mg_last_cycles};
     for (int seg = A.nseg - 1; seg >= 0 && !st; --seg) {
         const int t0 = seg * every, t1 = std::min(nsteps, t0 + every);
         st = batch_load_records(b, A, A.off_ckpt, seg);
@@ -2397,7 +2436,7 @@ fcd_status batch_adj_backward_impl(fcd_batch* b, const double* dJ, double* grad)
             if (p0.pot_extrapolate) fcd::launch_batch_psi_history<T>(ainst, btiles(b), lhist >= 2 ? 1 : 0, b->stream);
             ++lhist;
             st = hip_check(hipGetLastError(), "batch adjoint launch");
-            if (!st) st = batch_solve<T>(b, adjP, p0.pot_max_iters);
+            if (!st) st = b->mg ? batch_solve_mg<T>(b, adjM, p0.pot_max_iters) : batch_solve<T>(b, adjP, p0.pot_max_iters);
             if (st) break;
             fcd::launch_batch_adj_finish<T>(inst, ainst, adj, t2, r, Aidx, part, b->stream);
             fcd::launch_batch_adj_reduce<T>(adj, b->n, part, 2, acc, 13, b->stream);
@@ -2798,7 +2837,7 @@ fcd_status fcd_batch_create(int32_t n, const fcd_lattice* lats, const fcd_params
     b->init_fresh = 0;
     b->mg = prms[0].pot_solver == FCD_SOLVER_MG && L.mg_ok;
     b->mg_lds = 0;
-    b->mg_last_cycles = 0;
+    b->mg_last_cycles = b->adj_mg_last_cycles = 0;
     b->adj_work = nullptr;
     b->adj_nsteps = b->adj_every = b->adj_from_init = 0;
     b->adj_final_iters = b->adj_final_hist = b->adj_solve_iters = 0;

@@ -60,15 +60,15 @@ void launch_psi_history(T* psi, T* prev, T* prev2, T* prev3, int nx, int ny, int
 // batch, jobs = (channel, level, tile), channels with active[k] == 0 skipped.
 template <typename T, typename TC>
 void launch_bmg_smooth_fine(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, int dir,
-                            bool prolong, unsigned long long* res, hipStream_t s);
+                            bool prolong, bool rhs_plane, unsigned long long* res, hipStream_t s);
 template <typename T, typename TC>
 void launch_bmg_copy_fine(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, hipStream_t s);
 template <typename T, typename TC>
 void launch_bmg_restrict_smooth(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, int level,
-                                int src, int inner, hipStream_t s);
+                                int src, int inner, bool rhs_plane, hipStream_t s);
 template <typename T, typename TC>
 void launch_bmg_restrict_tail(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, bool from0,
-                              int src, hipStream_t s);
+                              int src, bool rhs_plane, hipStream_t s);
 template <typename T, typename TC>
 void launch_bmg_tail(const MgChan<T, TC>* ch, int n, size_t lds_bytes, const int* active, hipStream_t s);
 template <typename T, typename TC>
@@ -78,7 +78,7 @@ template <typename T, typename TC>
 void launch_bmg_mu4(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, int group, hipStream_t s);
 template <typename T, typename TC>
 void launch_bmg_decide(const MgChan<T, TC>* ch, int n, unsigned long long* res, int* active, int* cycles, int* counts,
-                       double floor_factor, hipStream_t s);
+                       double floor_factor, const unsigned long long* rel_scale, double rel_tol, hipStream_t s);
 template <typename T>
 void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P,
                            unsigned long long* div, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);

@@ -1076,9 +1076,10 @@ void launch_psi_history(T* psi, T* prev, T* prev2, T* prev3, int nx, int ny, int
 // ---------------------------------------------------------------------------------
 
 // Finest-level sweep: dir 0 reads L0.u and writes t0, dir 1 the reverse; PROLONG adds
-// level 1's correction to the input first; res != nullptr: max |residual| and max |C u|
-// of the input into res[2k], res[2k+1].
-template <typename T, bool PROLONG, typename TC>
+// level 1's correction to the input first; MODE 1 forms the right-hand side from the field,
+// MODE 2 reads it from L0.f; res != nullptr: max |residual| and max |C u| of the input into
+// res[2k], res[2k+1].
+template <typename T, bool PROLONG, int MODE, typename TC>
 __global__ void __launch_bounds__(FineTile::NT) kbm_smooth_fine(const MgChan<T, TC>* __restrict__ ch,
                                                                 const MgJob* __restrict__ jobs,
                                                                 const int* __restrict__ active, int dir,
@@ -1090,8 +1091,8 @@ __global__ void __launch_bounds__(FineTile::NT) kbm_smooth_fine(const MgChan<T, 
     const PotLevel<TC> Cl = c.C[1];
     const T* uin = dir ? c.t0 : L.u;
     T* uout = dir ? L.u : c.t0;
-    mg_smooth_tile<T, FineTile, PROLONG, 1, TC>(L, uin, uout, Cl, res ? res + 2 * J.k : nullptr, nullptr, 1, J.bx,
-                                                J.by);
+    mg_smooth_tile<T, FineTile, PROLONG, MODE, TC>(L, uin, uout, Cl, res ? res + 2 * J.k : nullptr, nullptr, 1, J.bx,
+                                                   J.by);
 }
 
 // Copy of t0 into L0.u (a finest-level iterate that ended in the ping-pong plane).
@@ -1112,7 +1113,7 @@ __global__ void __launch_bounds__(FineTile::NT) kbm_copy_fine(const MgChan<T, TC
 
 // Restriction of the finest level's residual (its pre-smoothed iterate in t0 when src,
 // else in L0.u) fused with level 1's pre-smoothing into t[1].
-template <typename T, typename TC>
+template <typename T, int FMODE, typename TC>
 __global__ void __launch_bounds__(FineTile::NT) kbm_restrict_smooth0(const MgChan<T, TC>* __restrict__ ch,
                                                                      const MgJob* __restrict__ jobs,
                                                                      const int* __restrict__ active, int src,
@@ -1123,7 +1124,7 @@ __global__ void __launch_bounds__(FineTile::NT) kbm_restrict_smooth0(const MgCha
     PotLevel<T> F = c.L0;
     if (src) F.u = c.t0;
     const PotLevel<TC> C = c.C[1];
-    mg_restrict_smooth<T, 1, TC>(F, C, c.t[1], inner, J.bx, J.by);
+    mg_restrict_smooth<T, FMODE, TC>(F, C, c.t[1], inner, J.bx, J.by);
 }
 
 // The same from coarse level l - 1 (pre-smoothed iterate in t[l-1]) into level l (t[l]).
@@ -1142,7 +1143,7 @@ __global__ void __launch_bounds__(FineTile::NT) kbm_restrict_smoothC(const MgCha
 
 // Restriction into the first tail level: from the finest level (tail == 1; its iterate
 // in t0 when src) ...
-template <typename T, typename TC>
+template <typename T, int FMODE, typename TC>
 __global__ void __launch_bounds__(FineTile::NT) kbm_restrict_tail0(const MgChan<T, TC>* __restrict__ ch,
                                                                    const MgJob* __restrict__ jobs,
                                                                    const int* __restrict__ active, int src) {
@@ -1152,7 +1153,7 @@ __global__ void __launch_bounds__(FineTile::NT) kbm_restrict_tail0(const MgChan<
     PotLevel<T> F = c.L0;
     if (src) F.u = c.t0;
     const PotLevel<TC> C = c.C[1];
-    mg_restrict_tile<T, FineTile, 1, TC>(F, C, J.bx, J.by);
+    mg_restrict_tile<T, FineTile, FMODE, TC>(F, C, J.bx, J.by);
 }
 
 // ... or from coarse level l = tail - 1 (its iterate in t[l]).
@@ -1212,7 +1213,9 @@ __global__ void __launch_bounds__(MU_TX* MU_TY / 4) kbm_mu4_C(const MgChan<T, TC
 
 // The convergence decision of every channel, one block: a channel active on entry stays
 // active while its residual (res[2k], the bit pattern of max |r|, and res[2k+1], that of
-// max |C u|) is above max(thr, floor * scale); a NaN residual stops it and is counted.
+// max |C u|) is above max(thr, floor * scale), thr the descriptor's or, with rel_scale,
+// rel_tol times rel_scale[k] (the bit pattern of a non-negative double, set on the
+// device); a NaN residual stops it and is counted.
 // Both words are zeroed for the next test; cycles[k] counts the cycles a channel
 // receives; counts = {channels left active, NaN channels, decisions of this solve that
 // found a channel active} (the last: the cycles the solve needs, counted from zero).
@@ -1222,7 +1225,9 @@ template <typename T, typename TC>
 __global__ void __launch_bounds__(BMG_DECIDE_T) kbm_decide(const MgChan<T, TC>* __restrict__ ch, int n,
                                                            unsigned long long* __restrict__ res,
                                                            int* __restrict__ active, int* __restrict__ cycles,
-                                                           int* __restrict__ counts, double floor_factor) {
+                                                           int* __restrict__ counts, double floor_factor,
+                                                           const unsigned long long* __restrict__ rel_scale,
+                                                           double rel_tol) {
     __shared__ int cnt[3][BMG_DECIDE_T / 64];
     int a_sum = 0, nan_sum = 0, e_sum = 0;
     for (int k = threadIdx.x; k < n; k += BMG_DECIDE_T) {
@@ -1235,7 +1240,8 @@ __global__ void __launch_bounds__(BMG_DECIDE_T) kbm_decide(const MgChan<T, TC>* 
         int a = 0;
         if (r != r) {
             ++nan_sum;
-        } else if (!(r <= fmax(ch[k].thr, floor_factor * sc))) {
+        } else if (!(r <= fmax(rel_scale ? rel_tol * __longlong_as_double((long long)rel_scale[k]) : ch[k].thr,
+                                floor_factor * sc))) {
             a = 1;
             ++cycles[k];
         }
@@ -1266,13 +1272,15 @@ __global__ void __launch_bounds__(BMG_DECIDE_T) kbm_decide(const MgChan<T, TC>* 
 
 template <typename T, typename TC>
 void launch_bmg_smooth_fine(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, int dir,
-                            bool prolong, unsigned long long* res, hipStream_t s) {
-    if (prolong)
-        hipLaunchKernelGGL((kbm_smooth_fine<T, true, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, dir,
-                           res);
-    else
-        hipLaunchKernelGGL((kbm_smooth_fine<T, false, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active,
-                           dir, res);
+                            bool prolong, bool rhs_plane, unsigned long long* res, hipStream_t s) {
+#define FCD_BMG_FINE(P, M) \
+    hipLaunchKernelGGL((kbm_smooth_fine<T, P, M, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, dir, res)
+    if (prolong) {
+        if (rhs_plane) FCD_BMG_FINE(true, 2); else FCD_BMG_FINE(true, 1);
+    } else {
+        if (rhs_plane) FCD_BMG_FINE(false, 2); else FCD_BMG_FINE(false, 1);
+    }
+#undef FCD_BMG_FINE
 }
 
 template <typename T, typename TC>
@@ -1282,10 +1290,13 @@ void launch_bmg_copy_fine(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs,
 
 template <typename T, typename TC>
 void launch_bmg_restrict_smooth(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, int level,
-                                int src, int inner, hipStream_t s) {
-    if (level == 1)
-        hipLaunchKernelGGL((kbm_restrict_smooth0<T, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, src,
-                           inner);
+                                int src, int inner, bool rhs_plane, hipStream_t s) {
+    if (level == 1 && rhs_plane)
+        hipLaunchKernelGGL((kbm_restrict_smooth0<T, 2, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active,
+                           src, inner);
+    else if (level == 1)
+        hipLaunchKernelGGL((kbm_restrict_smooth0<T, 1, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active,
+                           src, inner);
     else
         hipLaunchKernelGGL((kbm_restrict_smoothC<TC, T>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active,
                            inner);
@@ -1293,9 +1304,11 @@ void launch_bmg_restrict_smooth(const MgChan<T, TC>* ch, const MgJob* jobs, int 
 
 template <typename T, typename TC>
 void launch_bmg_restrict_tail(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, const int* active, bool from0,
-                              int src, hipStream_t s) {
-    if (from0)
-        hipLaunchKernelGGL((kbm_restrict_tail0<T, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, src);
+                              int src, bool rhs_plane, hipStream_t s) {
+    if (from0 && rhs_plane)
+        hipLaunchKernelGGL((kbm_restrict_tail0<T, 2, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, src);
+    else if (from0)
+        hipLaunchKernelGGL((kbm_restrict_tail0<T, 1, TC>), dim3(njobs), dim3(FineTile::NT), 0, s, ch, jobs, active, src);
     else
         hipLaunchKernelGGL((kbm_restrict_tailC<TC, T>), dim3(njobs), dim3(CoarseTile::NT), 0, s, ch, jobs, active);
 }
@@ -1321,9 +1334,9 @@ void launch_bmg_mu4(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, int g
 
 template <typename T, typename TC>
 void launch_bmg_decide(const MgChan<T, TC>* ch, int n, unsigned long long* res, int* active, int* cycles, int* counts,
-                       double floor_factor, hipStream_t s) {
+                       double floor_factor, const unsigned long long* rel_scale, double rel_tol, hipStream_t s) {
     hipLaunchKernelGGL((kbm_decide<T, TC>), dim3(1), dim3(BMG_DECIDE_T), 0, s, ch, n, res, active, cycles, counts,
-                       floor_factor);
+                       floor_factor, rel_scale, rel_tol);
 }
 
 #define FCD_POT_INSTANTIATE(T)                                                                            \
@@ -1337,18 +1350,18 @@ void launch_bmg_decide(const MgChan<T, TC>* ch, int n, unsigned long long* res, 
 // type TC (the coarse levels are FP32 under an FP64 finest level).
 #define FCD_BMG_INSTANTIATE(T, TC)                                                                            \
     template void launch_bmg_smooth_fine<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, int, bool,  \
-                                                unsigned long long*, hipStream_t);                                \
+                                                bool, unsigned long long*, hipStream_t);                          \
     template void launch_bmg_copy_fine<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, hipStream_t);  \
     template void launch_bmg_restrict_smooth<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, int, int, \
-                                                    int, hipStream_t);                                            \
+                                                    int, bool, hipStream_t);                                      \
     template void launch_bmg_restrict_tail<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, bool, int, \
-                                                  hipStream_t);                                                   \
+                                                  bool, hipStream_t);                                             \
     template void launch_bmg_tail<T, TC>(const MgChan<T, TC>*, int, size_t, const int*, hipStream_t);            \
     template void launch_bmg_post_coarse<T, TC>(const MgChan<T, TC>*, const MgJob*, int, const int*, int,        \
                                                 hipStream_t);                                                     \
     template void launch_bmg_mu4<T, TC>(const MgChan<T, TC>*, const MgJob*, int, int, hipStream_t);              \
     template void launch_bmg_decide<T, TC>(const MgChan<T, TC>*, int, unsigned long long*, int*, int*, int*,     \
-                                           double, hipStream_t);
+                                           double, const unsigned long long*, double, hipStream_t);
 
 #define FCD_MG_INSTANTIATE(T, TC)                                                                             \
     template void launch_mg_restrict_mu4<T, TC>(const T*, int, int, int, const MuLevels<TC>&, hipStream_t);   \

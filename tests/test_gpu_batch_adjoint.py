@@ -52,11 +52,15 @@ def single_grad(w, nsteps, dJ, every=8, tol=1e-12):
     return D, g
 
 
-def test_batch_adjoint_equals_single_channel_adjoints_fp64():
+@pytest.mark.parametrize("solver", ["sor", "mg"])
+def test_batch_adjoint_equals_single_channel_adjoints_fp64(solver):
+    """The batch's potentials by SOR or by the batched multigrid (forward and adjoint solves):
+    every channel's gradient as its single-channel adjoint's."""
     ws = field_channels()
     nsteps = 20
-    say(f"case batch adjoint fp64 {[(w.nx, w.ny) for w in ws]} {nsteps} steps")
-    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-12)
+    say(f"case batch adjoint fp64 {[(w.nx, w.ny) for w in ws]} {nsteps} steps, solver {solver}")
+    kw = dict(solver=fcd.FCD_SOLVER_MG, smooth=2) if solver == "mg" else {}
+    bt = Batch(ws, precision=fcd.FCD_FP64, tol=1e-12, **kw)
     bt.init_droplets()
     run = BatchAdjointRun(bt, nsteps, 6)
     D = run.forward()
