@@ -326,8 +326,8 @@ fcd_status fcd_adjoint_backward(fcd_handle* h, const double dJ_dD[2], double gra
  * batch) when
  * every channel's lattice has a coarse level and an LDS tail (nx, ny >= 4 and a small
  * enough coarsest level), else, and for FCD_SOLVER_SOR, four-colour SOR per channel
- * (the SOR factors, schedule and tuners below apply to it only).  The adjoint potential
- * solves of the batched adjoint use the SOR.  All lattices must share one precision.
+ * (the SOR factors, schedule and tuners below apply to it only).  The batched adjoint's
+ * potential solves use the same solver.  All lattices must share one precision.
  * Caller-owned buffers, sizes from fcd_batch_sizes: `state` (both state buffers of every
  * channel), `aux` (phi1, phi2, mu_r, psi' and psi' history planes), `scratch`
  * (descriptors, tile and job tables, reductions, the coarse multigrid levels); each at
@@ -408,7 +408,7 @@ fcd_status fcd_batch_tune_omega(fcd_batch* b, int32_t steps, int32_t ncand, cons
 
 /* Batched adjoint: the adjoint of fcd_adjoint_forward / _backward for every channel of
  * the batch at once (one launch per kernel for all channels, the adjoint potential
- * solves by the batch's SOR with per-channel thresholds pot_tol * max |psi'-bar|).
+ * solves by the batch's solver with per-channel thresholds pot_tol * max |psi'-bar|).
  * fcd_batch_adjoint_bytes: device bytes of `work` (host only).
  * fcd_batch_adjoint_forward: nsteps steps from the current state, checkpoints every
  * ckpt_every steps in `work` (caller-owned, 256-byte aligned); D_out[2k..2k+1] =
