@@ -176,7 +176,14 @@ fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_iters,
 
 /* Advance nsteps coupled time steps: phases and mu_r, potential solve (pot_tol,
  * pot_max_iters), then the fused collide-and-stream of f, g1, g2 with all forces.
- * The potential solve synchronises the stream at each residual test.
+ * A multigrid solve whose hierarchy ends in the LDS tail is decided on the GPU: a
+ * residual test before every V-cycle, decided by the test kernel itself, with the next
+ * V-cycle and the collide-and-stream launched ahead of the decision and gated on it;
+ * the collision publishes the outcome to pinned host memory, which the host reads
+ * while that collision runs, and the host adds V-cycles only when the solve needs more
+ * than one.  Other solves (SOR, a hierarchy without the tail, per-kernel timing on)
+ * synchronise the stream at each residual test.  Both take the same decisions: the
+ * results are bitwise the same.
  * Divergence guard: the collide-and-stream kernel raises a device flag when a node's
  * velocity exceeds u_limit or its p*, phi1 or phi2 is not finite; the flag stays set
  * until the state is replaced (fcd_init_*, fcd_write_state).  It is read at every
@@ -268,9 +275,10 @@ fcd_status fcd_stats(fcd_handle* h, double out[3]);
 fcd_status fcd_timing(fcd_handle* h, int32_t enable);
 fcd_status fcd_timing_read(fcd_handle* h, double out[12]);
 
-/* Repeated launch sequences of the potential solve (a multigrid V-cycle and the part of
- * it after the convergence test) run as HIP graphs captured on first use and replayed
- * on the handle's stream (default: enabled).  enable = 0 launches every kernel
+/* Repeated launch sequences of a host-decided potential solve (a multigrid V-cycle and
+ * the part of it after the convergence test) run as HIP graphs captured on first use and
+ * replayed on the handle's stream (default: enabled); a time step's solve decided on
+ * the GPU (fcd_step) launches eagerly either way.  enable = 0 launches every kernel
  * eagerly; the results are bitwise the same.  Graphs are also bypassed while
  * fcd_timing is on.  Sync. */
 fcd_status fcd_use_graphs(fcd_handle* h, int32_t enable);

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -38,11 +39,13 @@ constexpr size_t OFF_RES = 0;      // slot A, 2 x uint64
 constexpr size_t OFF_DIV = 16;     // uint64: divergence flag (0, or the worst node's max |u| bits / NaN)
 constexpr size_t OFF_RES_B = 24;   // slot B, 2 x uint64
 constexpr size_t OFF_RES_SOR = 40; // 2 x uint64 (SOR and the explicit residual kernel)
+constexpr size_t OFF_SLOTS = 64;   // 3 x 2 x uint64: residual tests of solves decided on the device
 constexpr size_t OFF_CENT = 256;   // 8 doubles: centroids and masses
 constexpr size_t OFF_RESULT = 512; // 4 doubles: D_o, D_i, mass1, mass2
 constexpr size_t OFF_EXTENT = 768; // Eq. 42 extents: 2 x uint64 (l_y bit patterns), 2 doubles (l_x)
 constexpr size_t OFF_BREAKUP = 832; // breakup probe: 6 doubles of sums
 constexpr size_t OFF_ROWS = 1024;  // ny * 8 doubles: per-row partial sums
+static_assert(OFF_SLOTS >= OFF_RES_SOR + 16 && OFF_SLOTS + 48 <= OFF_CENT, "scratch words overlap");
 
 size_t elem_size(int precision) { return precision == FCD_FP64 ? sizeof(double) : sizeof(float); }
 
@@ -276,6 +279,12 @@ struct fcd_handle {
     int qs;    // steps since the last state change (the potential is solved when qs % pot_every == 0)
     int last_iters;  // iterations the previous solve needed (first residual test is deferred)
     int res_slot;    // multigrid residual slot of the next test (0: A, 1: B); that slot is zero
+    // time steps whose multigrid solve is decided on the device (step_solve_collide)
+    fcd::SolveMirror* mirror;      // pinned, coherent: the tests as published by the GPU
+    unsigned long long seq_want;   // publications launched so far (the mirror's seq catches up)
+    unsigned long long test_idx;   // index of the next such residual test (slot test_idx % 3)
+    fcd::ResGate gate;             // set while launching gated kernels: levels built carry it
+    int pipe_last;                 // V-cycles the previous such solve needed
     int init_fresh;  // the state is the compound-droplet initial state (no step since)
     int open_x;      // open channel: Eq. 37 inlet at x = 0, convective outlet at x = nx - 1
     double u_in;     // u_avg of Eq. 37 (centreline value of the inlet profile)
@@ -443,6 +452,7 @@ fcd::PotLevel<T> pot_level(const fcd_handle* h, int l) {
     L.u = static_cast<T*>(h->buf.psi);
     L.mu = plane_ptr<T>(h->buf.phi, h, 2);
     L.f = nullptr;
+    L.gate = h->gate;
     L.inv_h2 = T(1);
     L.kappa = T(0);
     L.kappa_top = T(0);
@@ -463,6 +473,7 @@ fcd::PotLevel<CT> coarse_level(const fcd_handle* h, int l) {
         L.u = reinterpret_cast<CT*>(s + h->plan.off_u[l]);
         L.mu = reinterpret_cast<const CT*>(s + h->plan.off_mu[l]);
         L.f = reinterpret_cast<CT*>(s + h->plan.off_f[l]);
+        L.gate = h->gate;
         L.inv_h2 = CT(1.0 / (hh * hh));
         L.kappa = CT((hh - 1.0) / (hh + 1.0));
         L.kappa_top = CT(h->plan.kappa_top[l]);
@@ -588,20 +599,16 @@ int fine_mode(const fcd::PotLevel<T>& L0) {
     return L0.f ? 2 : 1;
 }
 
-// nu1 pre-smoothing sweeps of the finest level starting from F.u; returns the buffer
-// holding the result.  The first sweep reduces the input's residual into res when
-// res != nullptr.
+// n pre-smoothing sweeps of the finest level from the buffer a (F.u or the temporary
+// plane), alternating between the two; returns the buffer holding the result.
 template <typename T>
-T* mg_presmooth(fcd_handle* h, const fcd::PotLevel<T>& F, int mode, unsigned long long* res,
-                unsigned long long* res_clear = nullptr) {
-    T* a = F.u;
-    T* b = mg_temp<T>(h, 0);
+T* mg_sweeps(fcd_handle* h, const fcd::PotLevel<T>& F, int mode, T* a, int n) {
+    T* b = a == F.u ? mg_temp<T>(h, 0) : F.u;
     const fcd::PotLevel<CT>* none = nullptr;
-    for (int s = 0; s < std::max(1, h->prm.pot_smooth); ++s) {
+    for (int s = 0; s < n; ++s) {
         hipEvent_t ev = nullptr;
         const bool timed = h->timer.begin(h->stream, &ev);
-        fcd::launch_mg_smooth_tile<T, CT>(F, a, b, none, mode, s == 0 ? res : nullptr, 1, h->stream,
-                                          s == 0 ? res_clear : nullptr);
+        fcd::launch_mg_smooth_tile<T, CT>(F, a, b, none, mode, nullptr, 1, h->stream);
         if (timed) h->timer.end(h->stream, TK_SMOOTH0, ev);
         std::swap(a, b);
     }
@@ -693,7 +700,7 @@ void vcycle(fcd_handle* h, const fcd::PotLevel<T>& L0) {
         coarse_solve<T>(h, L0, true);
         return;
     }
-    T* cur0 = mg_presmooth<T>(h, L0, fine_mode(L0), nullptr);
+    T* cur0 = mg_sweeps<T>(h, L0, fine_mode(L0), L0.u, std::max(1, h->prm.pot_smooth));
     vcycle_rest<T>(h, L0, cur0);
 }
 
@@ -719,14 +726,15 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
             fcd::launch_pot_sweep<T>(L0, omega, h->stream);
         if (timed) h->timer.end(h->stream, TK_ITER, ev);
     };
-    // The residual is tested before iterating and then every pot_check_every
+    // SOR: the residual is tested before iterating and then every pot_check_every
     // iterations, except that the first test is deferred past the iterations the
     // previous comparable solve needed minus one: consecutive steps need similar counts,
-    // and each test costs a host round trip.  With multigrid the test is the residual of
-    // the iterate entering a V-cycle, reduced by the cycle's first smoothing kernel; the
-    // host waits for it before launching the rest of the cycle.
+    // and each test costs a host round trip.  Multigrid: the residual of the iterate
+    // entering every V-cycle is tested, reduced by the cycle's first smoothing kernel; the
+    // host waits for it before launching the rest of the cycle (the same decisions as a
+    // time step's solve decided on the device, step_solve_collide).
     int it = 0;
-    const int defer = defer_from > 1 ? defer_from - 1 : 0;
+    const int defer = !mg && defer_from > 1 ? defer_from - 1 : 0;
     if (defer > 0 && defer <= max_iters) {
         for (int s = 0; s < defer; ++s) one();
         it = defer;
@@ -735,11 +743,17 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
     double r = 0.0, scale = 0.0;
     fcd_status st = FCD_OK;
     if (mg) {
+        const int mode = fine_mode(L0);
+        T* const t0 = mg_temp<T>(h, 0);
+        const fcd::PotLevel<CT>* none = nullptr;
         for (;;) {
+            // the test: the first pre-smoothing sweep (F.u into the temporary plane) reduces
+            // its input's residual; F.u is the accepted iterate when it passes
             hipEvent_t ev = nullptr;
             bool timed = h->timer.begin(h->stream, &ev);
             const int slot = h->res_slot;
-            T* cur0 = mg_presmooth<T>(h, L0, fine_mode(L0), res_slot_ptr(h, slot), res_slot_ptr(h, 1 - slot));
+            fcd::launch_mg_smooth_tile<T, CT>(L0, L0.u, t0, none, mode, res_slot_ptr(h, slot), 1, h->stream,
+                                              res_slot_ptr(h, 1 - slot));
             h->res_slot = 1 - slot;
             if (timed) h->timer.end(h->stream, TK_RESID, ev);
             // slot A: words 0-2 = (r, scale, flag); slot B: words 2-4 = (flag, r, scale)
@@ -764,7 +778,10 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
             }
             if (it >= max_iters) break;
             timed = h->timer.begin(h->stream, &ev);
-            st = run_graph(h, L0.u, L0.f, G_REST, [&]() { vcycle_rest<T>(h, L0, cur0); });
+            st = run_graph(h, L0.u, L0.f, G_REST, [&]() {
+                T* cur0 = mg_sweeps<T>(h, L0, mode, t0, std::max(1, h->prm.pot_smooth) - 1);
+                vcycle_rest<T>(h, L0, cur0);
+            });
             if (timed) h->timer.end(h->stream, TK_ITER, ev);
             if (st) return st;
             ++it;
@@ -816,6 +833,137 @@ fcd_status solve_impl(fcd_handle* h, double tol, int max_iters, int* iters_out, 
     return st;
 }
 
+// Wait until the GPU has published the outcome of every collide-and-stream enqueued so far
+// (the gated kernel's first lane stores the mirror's seq last); the stream is queried now
+// and then so that an asynchronous error ends the wait.
+fcd_status wait_decisions(fcd_handle* h) {
+    const volatile unsigned long long* seq = &h->mirror->seq;
+    for (unsigned it = 1; *seq < h->seq_want; ++it) {
+        if ((it & 4095u) == 0) {
+            const hipError_t e = hipStreamQuery(h->stream);
+            if (e == hipSuccess && *seq < h->seq_want) {
+                h->seq_want = *seq;
+                return fail(FCD_ERR_HIP, "a potential solve's outcome did not reach the host");
+            }
+            if (e != hipSuccess && e != hipErrorNotReady) return hip_check(e, "potential solve outcome wait");
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return FCD_OK;
+}
+
+// Whether a time step's multigrid solve is decided on the device: a hierarchy with an LDS
+// tail and a field; per-kernel timing keeps the host-decided loop, whose decisions are the
+// same (a test before every V-cycle), so the results are bitwise identical either way.
+bool step_decided_on_device(const fcd_handle* h) {
+    return h->prm.pot_solver == FCD_SOLVER_MG && h->plan.levels > 1 && h->plan.tail < h->plan.levels &&
+           h->prm.H0 != 0.0 && !h->timer.on;
+}
+
+// A time step's potential solve and its collide-and-stream without the host waiting inside
+// the step.  The residual tests (the finest level's first pre-smoothing sweep, reducing
+// its input's residual) write rotating slots; every kernel of a V-cycle, the pre-smoothing
+// sweeps after the test included, reads the preceding test's slot and does nothing when
+// that test passed, and the collide-and-stream runs only when the last test passed.  The
+// first test, one V-cycle and the next test, then the collision, are launched together;
+// the collision's first lane publishes both tests, which the host reads while the
+// collision runs, applying the same rule, before it launches the next time step.  Only
+// when the solve needs more V-cycles does the host add one cycle, its test and the
+// collision again at a time.  No V-cycle is launched ahead when the previous solve needed
+// none, or when max_iters is 0.  A test that did not run leaves its slot zero (a pass): a
+// test zeroes the slot after its own, and the collision the slot after the gating test.
+// Eager launches: the host runs ahead of the GPU here, and a launch after a replayed graph
+// waits several microseconds for the graph to retire.  *collided: the collide-and-stream
+// has run (src -> dst).
+template <typename T>
+fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T* src, T* dst, bool* collided) {
+    *collided = false;
+    restrict_mu_all<T>(h);
+    auto slot = [&](unsigned long long k) {
+        return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + OFF_SLOTS) + 2 * (k % 3);
+    };
+    const double thr0 = h->prm.pot_tol * std::fabs(h->prm.H0);
+    const double ff = resid_floor_factor<T>();
+    auto passes = [&](double r, double sc) { return r <= std::max(thr0, ff * sc); };
+    auto gate_of = [&](unsigned long long k) { return fcd::ResGate{slot(k), thr0, ff}; };
+    const fcd::PotLevel<T> L0 = pot_level<T>(h, 0);
+    const int mode = fine_mode(L0);
+    T* const t0 = mg_temp<T>(h, 0);
+    const int nu1 = std::max(1, h->prm.pot_smooth);
+    const int max_iters = h->prm.pot_max_iters;
+    T* const psi = static_cast<T*>(h->buf.psi);
+    const T* phi = static_cast<const T*>(h->buf.phi);
+    const fcd::PotLevel<CT>* none = nullptr;
+    // test k (gated on test k - 1 unless it is the solve's first) into slot k, zeroing slot k + 1
+    auto test = [&](unsigned long long k, const fcd::PotLevel<T>& L) {
+        fcd::launch_mg_smooth_tile<T, CT>(L, L.u, t0, none, mode, slot(k), 1, h->stream, slot(k + 1));
+    };
+    // the V-cycle after test k and test k + 1, both gated on test k
+    auto cycle = [&](unsigned long long k) {
+        h->gate = gate_of(k);  // the levels built while it is set carry the gate
+        const fcd::PotLevel<T> L0g = pot_level<T>(h, 0);
+        vcycle_rest<T>(h, L0g, mg_sweeps<T>(h, L0g, mode, t0, nu1 - 1));
+        test(k + 1, L0g);
+        h->gate = fcd::ResGate{};
+        return hip_check(hipGetLastError(), "potential launch");
+    };
+    // the collision gated on test k, publishing tests k - 1 and k
+    auto collide = [&](unsigned long long k) {
+        ++h->seq_want;
+        const fcd::StepGate sg{gate_of(k), slot(k - 1), slot(k + 1), h->mirror, div_word(h), h->seq_want};
+        fcd::launch_collide_stream<T>(src, dst, phi, psi, P, div_word(h), h->stream, nullptr, nullptr, sg);
+        if (h->open_x)
+            fcd::launch_open_boundaries<T>(src, dst, phi, psi, P, h->u_in, h->u_out, h->stream, gate_of(k));
+        return hip_check(hipGetLastError(), "collide-stream launch");
+    };
+    unsigned long long k = h->test_idx;
+    test(k, L0);
+    int cycles = 0;
+    bool ahead = h->pipe_last > 0 && max_iters > 0;
+    fcd_status st = hip_check(hipGetLastError(), "potential launch");
+    if (!st && ahead) st = cycle(k);
+    unsigned long long last = ahead ? k + 1 : k;
+    if (!st) st = collide(last);
+    if (!st) st = wait_decisions(h);
+    double r = 0.0;
+    bool done = false;
+    while (!st) {
+        const fcd::SolveMirror m = *h->mirror;
+        if (ahead && passes(m.r[0], m.scale[0])) {  // the first test passed: nothing after it ran
+            r = m.r[0];
+            done = true;
+        } else {
+            if (ahead) ++cycles;  // the cycle launched ahead ran (also after a NaN test)
+            r = m.r[1];
+            done = passes(m.r[1], m.scale[1]);
+        }
+        ahead = false;
+        st = divergence_status(m.div, u_limit_of(h->prm), "divergence guard");
+        if (st || done) break;
+        if (r != r) {
+            st = fail(FCD_ERR_DIVERGED, "potential residual is NaN");
+            break;
+        }
+        if (cycles >= max_iters) {
+            st = fail(FCD_ERR_NOT_CONVERGED, "potential solve reached max_iters");
+            break;
+        }
+        st = cycle(last);
+        ++cycles;
+        ++last;
+        if (!st) st = collide(last);
+        if (!st) st = wait_decisions(h);
+    }
+    h->test_idx = last + 1;
+    *collided = done;
+    h->sweeps += cycles;
+    h->last_iters = cycles;
+    h->pipe_last = cycles;
+    h->last_resid = r;
+    return st;
+}
+
 template <typename T>
 fcd_status step_impl(fcd_handle* h, int nsteps) {
     const fcd::StepConst<T> P = make_const<T>(h);
@@ -844,6 +992,22 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
                 const int mode = h->hist >= 4 && ex == 3 ? 3 : h->hist >= 3 && ex >= 2 ? 2 : h->hist >= 2 ? 1 : 0;
                 fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, prev3, h->lat.nx, h->lat.ny,
                                            h->lat.pitch, mode, h->stream);
+            }
+            if (step_decided_on_device(h)) {
+                bool collided = false;
+                st = step_solve_collide<T>(h, P, src, dst, &collided);
+                if (collided) {
+                    ++h->hist;
+                    ++h->qs;
+                    h->cur = 1 - h->cur;
+                    ++h->steps;
+                }
+                if (st) return st;
+                if (h->steps % div_every_of(h->prm) == 0) {
+                    st = read_divergence(h);
+                    if (st) return st;
+                }
+                continue;
             }
             st = solve_impl<T>(h, h->prm.pot_tol, h->prm.pot_max_iters, nullptr, nullptr);
             if (st) return st;
@@ -2539,12 +2703,26 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
         delete h;
         return fail(FCD_ERR_OOM, "pinned host allocation failed");
     }
-    // the scratch arrives with the caller's contents: zero both residual slots and the flag
+    // written by the GPU while the host polls it: coherent (fine-grained) host memory
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->mirror), sizeof(fcd::SolveMirror), hipHostMallocCoherent) !=
+        hipSuccess) {
+        (void)hipHostFree(h->host);
+        delete h;
+        return fail(FCD_ERR_OOM, "pinned host allocation failed");
+    }
+    std::memset(h->mirror, 0, sizeof(fcd::SolveMirror));
+    h->seq_want = 0;
+    h->test_idx = 0;
+    h->gate = fcd::ResGate{};
+    h->pipe_last = 1;
+    // the scratch arrives with the caller's contents: zero both residual slots, the flag,
+    // the SOR words and the device-decided solve's words
     h->res_slot = 0;
-    hipLaunchKernelGGL(fcd::k_fill<unsigned long long>, dim3(1), dim3(64), 0, h->stream, res_slot_ptr(h, 0), 5LL,
-                       0ULL);
+    hipLaunchKernelGGL(fcd::k_fill<unsigned long long>, dim3(1), dim3(64), 0, h->stream, res_slot_ptr(h, 0),
+                       (long long)((OFF_SLOTS + 48) / sizeof(unsigned long long)), 0ULL);
     st = hip_check(hipGetLastError(), "residual slot clear");
     if (st) {
+        (void)hipHostFree(h->mirror);
         (void)hipHostFree(h->host);
         delete h;
         return st;
@@ -2767,6 +2945,7 @@ fcd_status fcd_sync(fcd_handle* h) {
 fcd_status fcd_destroy(fcd_handle* h) {
     if (!h) return fail(FCD_ERR_ARG, "handle is null");
     fcd_status st = hip_check(hipStreamSynchronize(h->stream), "stream sync");
+    (void)hipHostFree(h->mirror);
     (void)hipHostFree(h->host);
     delete h;
     return st;

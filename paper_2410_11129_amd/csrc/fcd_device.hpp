@@ -42,6 +42,20 @@ struct StepConst {
     T u_limit;                // divergence guard: largest admissible max(|u_x|, |u_y|)
 };
 
+// The outcome of a residual test, read on the device from the test's two words (max
+// |residual| and max |C psi'| as bit patterns of non-negative doubles; both zero when the
+// test did not run): passed when r <= max(thr0, floor_factor * scale).  A NaN residual
+// does not pass.  res == nullptr: no test (nothing is gated).
+struct ResGate {
+    const unsigned long long* res;
+    double thr0, floor_factor;
+    __device__ __forceinline__ bool passed() const {
+        const double r = __longlong_as_double((long long)res[0]);
+        const double sc = __longlong_as_double((long long)res[1]);
+        return r <= fmax(thr0, floor_factor * sc);
+    }
+};
+
 // One level of the potential problem (see fcd_potential.hip).  f == nullptr marks the
 // finest level, whose right-hand side H0 sum_a c_a (e_a . h) is formed on the fly.
 template <typename T>
@@ -49,11 +63,35 @@ struct PotLevel {
     T* u;         // unknown: psi' on the finest level, the correction on coarse levels
     const T* mu;  // mu_r (finest) or its cell averages (coarse)
     T* f;         // right-hand side, nullptr on the finest level
+    // a kernel given this level does nothing when gate.res is set and that test passed
+    // (the V-cycle it belongs to is not needed)
+    ResGate gate;
     int nx, ny, pitch, pad;
     T inv_h2;     // 1 / h^2, h = 2^level
     T kappa;      // the ghost row below the first row carries -kappa times it: (h - 1) / (h + 1)
     T kappa_top;  // the ghost row above the last row carries -kappa_top times it (wall distance)
     T H0x, H0y;   // applied field (finest level only)
+};
+
+// The last two residual tests of a time step's solve and the divergence flag word, as the
+// step's collide-and-stream publishes them to pinned host memory; seq is stored last.
+struct SolveMirror {
+    unsigned long long seq;
+    double r[2], scale[2];  // [0]: the test before the gating one, [1]: the gating test
+    unsigned long long div;
+};
+
+// The collide-and-stream of a time step whose solve is decided on the device: with
+// gate.res set it runs only if that test passed, and its first lane first publishes the
+// previous test (prev) and the gating test with the divergence word to m under the
+// sequence number seq, and zeroes the two words at clear (the next test's).
+struct StepGate {
+    ResGate gate;
+    const unsigned long long* prev;
+    unsigned long long* clear;
+    SolveMirror* m;
+    const unsigned long long* div;
+    unsigned long long seq;
 };
 
 // The coarsest levels of a V-cycle, solved in LDS by one block (levels lv[0..n), finest

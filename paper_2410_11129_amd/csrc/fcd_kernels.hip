@@ -103,7 +103,22 @@ __device__ __forceinline__ Nb9<T> lds_nb(const T (*t)[BX + 2], int lx, int ly) {
 template <typename T>
 __global__ void __launch_bounds__(BX* CY)
     k_collide_stream(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ phi,
-                         const T* __restrict__ psi, StepConst<T> P, unsigned long long* __restrict__ div) {
+                         const T* __restrict__ psi, StepConst<T> P, unsigned long long* __restrict__ div,
+                         StepGate sg) {
+    if (sg.gate.res) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+            SolveMirror* m = sg.m;
+            m->r[0] = __longlong_as_double((long long)sg.prev[0]);
+            m->scale[0] = __longlong_as_double((long long)sg.prev[1]);
+            m->r[1] = __longlong_as_double((long long)sg.gate.res[0]);
+            m->scale[1] = __longlong_as_double((long long)sg.gate.res[1]);
+            m->div = *sg.div;
+            sg.clear[0] = 0ULL;
+            sg.clear[1] = 0ULL;
+            __hip_atomic_store(&m->seq, sg.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        if (!sg.gate.passed()) return;
+    }
     __shared__ T t1[CY + 2][BX + 2], t2[CY + 2][BX + 2], tp[CY + 2][BX + 2];
     const int i0 = blockIdx.x * BX, j0 = blockIdx.y * CY;
     const int tid = threadIdx.y * BX + threadIdx.x;
@@ -307,14 +322,21 @@ void launch_init_droplet(T* dist, int nx, int ny, int pitch, double xc, double y
 template <typename T>
 void launch_phase(const T* dist, T* phi, const StepConst<T>& P, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     // with events, the launch itself records the kernel's start and end (no host gap inside)
-    hipExtLaunchKernelGGL(k_phase<T>, grid2(P.nx, P.ny), dim3(BX, BY), 0, s, ev0, ev1, 0, dist, phi, P);
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(k_phase<T>, grid2(P.nx, P.ny), dim3(BX, BY), 0, s, ev0, ev1, 0, dist, phi, P);
+    else
+        hipLaunchKernelGGL(k_phase<T>, grid2(P.nx, P.ny), dim3(BX, BY), 0, s, dist, phi, P);
 }
 
 template <typename T>
 void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P,
-                           unsigned long long* div, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    hipExtLaunchKernelGGL(k_collide_stream<T>, dim3((P.nx + BX - 1) / BX, (P.ny + CY - 1) / CY), dim3(BX, CY), 0, s,
-                          ev0, ev1, 0, src, dst, phi, psi, P, div);
+                           unsigned long long* div, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, const StepGate& sg) {
+    const dim3 g((P.nx + BX - 1) / BX, (P.ny + CY - 1) / CY);
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL(k_collide_stream<T>, g, dim3(BX, CY), 0, s, ev0, ev1, 0, src, dst, phi, psi, P, div,
+                              sg);
+    else
+        hipLaunchKernelGGL(k_collide_stream<T>, g, dim3(BX, CY), 0, s, src, dst, phi, psi, P, div, sg);
 }
 
 template <typename T>
@@ -355,7 +377,8 @@ void launch_diagnostics(const T* phi, const StepConst<T>& P, double* rows, doubl
                                          hipStream_t);                                                           \
     template void launch_phase<T>(const T*, T*, const StepConst<T>&, hipStream_t, hipEvent_t, hipEvent_t);       \
     template void launch_collide_stream<T>(const T*, T*, const T*, const T*, const StepConst<T>&,                \
-                                           unsigned long long*, hipStream_t, hipEvent_t, hipEvent_t);            \
+                                           unsigned long long*, hipStream_t, hipEvent_t, hipEvent_t,              \
+                                           const StepGate&);                                                      \
     template void launch_moments<T>(const T*, const T*, const T*, const StepConst<T>&, unsigned, double*,        \
                                     hipStream_t);                                                                \
     template void launch_to_dense<T>(const T*, double*, int, int, int, int, hipStream_t);                        \

@@ -79,9 +79,11 @@ void launch_bmg_mu4(const MgChan<T, TC>* ch, const MgJob* jobs, int njobs, int g
 template <typename T, typename TC>
 void launch_bmg_decide(const MgChan<T, TC>* ch, int n, unsigned long long* res, int* active, int* cycles, int* counts,
                        double floor_factor, const unsigned long long* rel_scale, double rel_tol, hipStream_t s);
+// sg: see StepGate (sg.c == nullptr: ungated).
 template <typename T>
 void launch_collide_stream(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P,
-                           unsigned long long* div, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                           unsigned long long* div, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                           const StepGate& sg = StepGate{});
 template <typename T>
 void launch_moments(const T* src, const T* phi, const T* psi, const StepConst<T>& P, unsigned mask, double* out,
                     hipStream_t s);
@@ -106,9 +108,10 @@ void launch_breakup_probe(const T* phi, const StepConst<T>& P, double* rows, dou
 // Open channel (fcd_open.hip): after the periodic collide-and-stream of src into dst, the end
 // columns re-collided with zero-gradient phi stencils, then the Eq. 37 inlet and the
 // convective outlet (u_in: centreline inflow; U: outlet convective velocity).
+// gate: with gate.res set the kernels run only if that residual test passed.
 template <typename T>
 void launch_open_boundaries(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P, double u_in,
-                            double U, hipStream_t s);
+                            double U, hipStream_t s, const ResGate& gate = ResGate{});
 // Moments of the two end columns with the open-channel stencils (after launch_moments).
 template <typename T>
 void launch_open_edge_moments(const T* src, const T* phi, const T* psi, const StepConst<T>& P, unsigned mask,

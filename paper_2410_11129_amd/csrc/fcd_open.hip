@@ -51,7 +51,8 @@ __device__ __forceinline__ bool edge_node(int q, int nx, int ny, int& i, int& j)
 template <typename T>
 __global__ void __launch_bounds__(OPEN_T)
     k_open_edge_collide(const T* __restrict__ src, T* __restrict__ dst, const T* __restrict__ phi,
-                        const T* __restrict__ psi, StepConst<T> P) {
+                        const T* __restrict__ psi, StepConst<T> P, ResGate gate) {
+    if (gate.res && !gate.passed()) return;
     int i, j;
     if (!edge_node(blockIdx.x * OPEN_T + threadIdx.x, P.nx, P.ny, i, j)) return;
     const NbIdx c = nb_index_open(i, j, P.nx, P.ny, P.pitch);
@@ -69,7 +70,9 @@ __global__ void __launch_bounds__(OPEN_T)
 // the step started from.
 template <typename T>
 __global__ void __launch_bounds__(OPEN_T)
-    k_open_bc(const T* __restrict__ src, T* __restrict__ dst, StepConst<T> P, double u_in, double U) {
+    k_open_bc(const T* __restrict__ src, T* __restrict__ dst, StepConst<T> P, double u_in, double U,
+              ResGate gate) {
+    if (gate.res && !gate.passed()) return;
     const int j = blockIdx.x * OPEN_T + threadIdx.x;
     if (j >= P.ny) return;
     const long long pl = P.plane, k0 = (long long)j * P.pitch, kN = k0 + P.nx - 1, kB = kN - 1;
@@ -155,10 +158,10 @@ static inline unsigned open_grid(long long n) { return (unsigned)((n + OPEN_T - 
 
 template <typename T>
 void launch_open_boundaries(const T* src, T* dst, const T* phi, const T* psi, const StepConst<T>& P, double u_in,
-                            double U, hipStream_t s) {
+                            double U, hipStream_t s, const ResGate& gate) {
     hipLaunchKernelGGL(k_open_edge_collide<T>, dim3(open_grid(2LL * P.ny)), dim3(OPEN_T), 0, s, src, dst, phi, psi,
-                       P);
-    hipLaunchKernelGGL(k_open_bc<T>, dim3(open_grid(P.ny)), dim3(OPEN_T), 0, s, src, dst, P, u_in, U);
+                       P, gate);
+    hipLaunchKernelGGL(k_open_bc<T>, dim3(open_grid(P.ny)), dim3(OPEN_T), 0, s, src, dst, P, u_in, U, gate);
 }
 
 template <typename T>
@@ -177,7 +180,7 @@ void launch_open_init_droplet(T* dist, int nx, int ny, int pitch, double xc, dou
 
 #define FCD_OPEN_INST(T)                                                                                          \
     template void launch_open_boundaries<T>(const T*, T*, const T*, const T*, const StepConst<T>&, double, double, \
-                                            hipStream_t);                                                         \
+                                            hipStream_t, const ResGate&);                                         \
     template void launch_open_edge_moments<T>(const T*, const T*, const T*, const StepConst<T>&, unsigned,         \
                                               double*, hipStream_t);                                              \
     template void launch_open_init_droplet<T>(T*, int, int, int, double, double, double, double, double, double,   \

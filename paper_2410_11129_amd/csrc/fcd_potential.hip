@@ -36,6 +36,13 @@ namespace fcd {
 constexpr int PX = 64;  // one wavefront per row segment
 constexpr int PY = 4;
 
+// A kernel launched with a gated level does nothing when the gating residual test has
+// passed (every block reads the test's words first, before any barrier).
+template <typename T>
+__device__ __forceinline__ bool gated_off(const PotLevel<T>& L) {
+    return L.gate.res && L.gate.passed();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(PX* PY) k_pot_relax_colour(PotLevel<T> L, int colour, T omega) {
     const int i = 2 * (blockIdx.x * PX + threadIdx.x) + (colour & 1);
@@ -428,6 +435,7 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
                                                           T* __restrict__ uout, PotLevel<TC> Cl,
                                                           unsigned long long* __restrict__ res,
                                                           unsigned long long* __restrict__ res_clear, int inner) {
+    if (gated_off(L)) return;
     mg_smooth_tile<T, G, PROLONG, MODE, TC>(L, uin, uout, Cl, res, res_clear, inner, blockIdx.x, blockIdx.y);
 }
 
@@ -555,6 +563,7 @@ __device__ __forceinline__ void mg_restrict_tile(const PotLevel<T>& F, const Pot
 
 template <typename T, typename G, int MODE, typename TC>
 __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
+    if (gated_off(Cl)) return;
     mg_restrict_tile<T, G, MODE, TC>(F, Cl, blockIdx.x, blockIdx.y);
 }
 
@@ -646,6 +655,7 @@ __device__ __forceinline__ void mg_restrict_smooth(const PotLevel<T>& F, const P
 template <typename T, int FMODE, typename TC>
 __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<TC> C,
                                                                      TC* __restrict__ uout, int inner) {
+    if (gated_off(C)) return;
     mg_restrict_smooth<T, FMODE, TC>(F, C, uout, inner, blockIdx.x, blockIdx.y);
 }
 
@@ -925,6 +935,7 @@ __device__ __forceinline__ void mg_tail(const MgTail<T>& tl, const TailDiv& dv) 
 
 template <typename T>
 __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
+    if (gated_off(tl.lv[0])) return;
     mg_tail<T>(tl, dv);
 }
 

@@ -1,0 +1,119 @@
+"""Time steps whose multigrid solve is decided on the GPU against the host-decided loop.
+
+A channel whose hierarchy ends in an LDS tail decides each step's residual tests on the
+device: the next V-cycle and the collide-and-stream are enqueued ahead and gated on the
+decision.  Per-kernel timing selects the host-decided loop instead, which takes the same
+test before every V-cycle, so both must give the same cycle count and a bitwise identical
+state.  Covered: solves that need several cycles (the start from the initial state), solves
+that need none (a loose tolerance; such a step then enqueues no V-cycle ahead), an odd-size
+hierarchy with one finest sweep each way (the pre-smoothed iterate then sits in the
+temporary plane), the open channel's gated boundary kernels, FP32, the potential solved
+every fourth step, and the max_iters stop (the collision is then skipped).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from fcd_inputs import channel_drive, open_channel_paper, single_channel_small
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2410_11129_amd import fcd  # noqa: E402
+from paper_2410_11129_amd.sim import Channel  # noqa: E402
+
+MG = dict(solver=fcd.FCD_SOLVER_MG, check_every=1, max_iters=1000, smooth=2, extrapolate=3)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run(w, steps, host_decided, precision=fcd.FCD_FP64, **solver):
+    """(state, [steps, V-cycles, last residual], V-cycles of each step) after `steps` steps
+    from the initial droplet, stepped one at a time."""
+    ch = Channel(w, precision=precision, **{**MG, **solver})
+    if host_decided:
+        fcd.fcd_timing(ch.h, True)
+    ch.init_droplet()
+    per, done = [], 0.0
+    for _ in range(steps):
+        ch.step(1)
+        c = ch.stats()[1]
+        per.append(int(c - done))
+        done = c
+    out = ch.state(), ch.stats(), per
+    ch.close()
+    return out
+
+
+def odd_channel():
+    w = single_channel_small()
+    return w.replace(name="odd_200x75", ny=75, yc=37.0, drive_G=channel_drive(0.01, 1.0, 0.8, 75))
+
+
+CASES = {
+    "200x50_fp64": (single_channel_small, 60, fcd.FCD_FP64, dict(tol=1e-10)),
+    "200x50_loose": (single_channel_small, 60, fcd.FCD_FP64, dict(tol=1e-2)),
+    "200x75_odd": (odd_channel, 60, fcd.FCD_FP64, dict(tol=1e-10, smooth=1)),
+    "200x50_fp32": (single_channel_small, 60, fcd.FCD_FP32, dict(tol=1e-5)),
+    "open_900x150": (open_channel_paper, 30, fcd.FCD_FP64, dict(tol=1e-10)),
+    "200x50_every4": (single_channel_small, 60, fcd.FCD_FP64, dict(tol=1e-10, every=4)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_device_decided_steps_equal_host_decided(case):
+    make, steps, prec, solver = CASES[case]
+    w = make()
+    say(f"case device-decided {case} {w.nx}x{w.ny} steps={steps}")
+    s_dev, st_dev, per_dev = run(w, steps, False, prec, **solver)
+    s_host, st_host, per_host = run(w, steps, True, prec, **solver)
+    say(f"  V-cycles per step (device) {per_dev}")
+    assert st_dev[0] == st_host[0] == steps
+    assert per_dev == per_host
+    assert st_dev[2] == st_host[2]
+    assert np.array_equal(s_dev, s_host)
+    # steps needing more than the one V-cycle launched ahead (the host adds cycles)
+    assert max(per_dev) >= 2
+    if case == "200x50_loose":
+        # steps whose first test passes, and a step needing a cycle after one that needed
+        # none (no V-cycle was launched ahead of it)
+        assert 0 in per_dev
+        assert any(a == 0 and b > 0 for a, b in zip(per_dev, per_dev[1:]))
+
+
+def step_until_error(w, host_decided, max_steps, **solver):
+    ch = Channel(w, **{**MG, **solver})
+    if host_decided:
+        fcd.fcd_timing(ch.h, True)
+    ch.init_droplet()
+    err = None
+    for k in range(1, max_steps + 1):
+        try:
+            ch.step(1)
+        except fcd.FcdError as e:
+            err = (k, e.status)
+            break
+    out = err, ch.state(), ch.stats()
+    ch.close()
+    return out
+
+
+def test_max_iters_stop_skips_the_collision():
+    """One V-cycle allowed at a tolerance that needs more: NOT_CONVERGED at the same step
+    either way, the state left as it was before that step's collision."""
+    w = single_channel_small()
+    say("case device-decided max_iters stop")
+    e_dev, s_dev, st_dev = step_until_error(w, False, 20, tol=1e-12, max_iters=1)
+    e_host, s_host, st_host = step_until_error(w, True, 20, tol=1e-12, max_iters=1)
+    say(f"  device {e_dev} {st_dev}, host {e_host} {st_host}")
+    assert e_dev is not None and e_dev == e_host
+    assert e_dev[1] == fcd.FCD_ERR_NOT_CONVERGED
+    assert st_dev[0] == st_host[0] == e_dev[0] - 1
+    assert np.array_equal(s_dev, s_host)
