@@ -359,8 +359,9 @@ def batched_adjoint(torch, steps: int, every: int) -> dict:
 
 
 def quasi_static(torch, steps: int) -> dict:
-    """The 2048 x 512 FP64 channel (Bo_m = 2, multigrid to 1e-10) with the potential solved
-    every K steps and held in between (an option, not the paper's every-step coupling):
+    """The 2048 x 512 FP64 channel (Bo_m = 2, multigrid to 1e-10 with the headline's solver
+    settings) with the potential solved every K steps and held in between (an option, not
+    the paper's every-step coupling):
     throughput for K = 4 and 8, and how far phi1 and D_o drift from the every-step run over
     the same `steps` steps from the same state."""
     from fcd_inputs import single_channel_large
@@ -370,7 +371,7 @@ def quasi_static(torch, steps: int) -> dict:
     ref = None
     out = {"workload": "channel_2048x512_fp64_bo2", "steps": steps}
     for K in (1, 4, 8):
-        ch = Channel(w, tol=1e-10, every=K, extrapolate=3)
+        ch = Channel(w, tol=1e-10, every=K, extrapolate=3, smooth=2)
         ch.init_droplet()
         ch.solve_potential(1e-10)
         ch.step(8)  # every K divides 8: the timed window starts on a solve step

@@ -39,13 +39,15 @@ constexpr size_t OFF_RES = 0;      // slot A, 2 x uint64
 constexpr size_t OFF_DIV = 16;     // uint64: divergence flag (0, or the worst node's max |u| bits / NaN)
 constexpr size_t OFF_RES_B = 24;   // slot B, 2 x uint64
 constexpr size_t OFF_RES_SOR = 40; // 2 x uint64 (SOR and the explicit residual kernel)
-constexpr size_t OFF_SLOTS = 64;   // 3 x 2 x uint64: residual tests of solves decided on the device
+constexpr size_t OFF_SLOTS = 64;   // SOLVE_SLOTS x 2 x uint64: residual tests of solves decided on the device
+constexpr size_t OFF_TESTS = OFF_SLOTS + 16 * fcd::SOLVE_SLOTS;  // uint32: such tests run since the last publication
 constexpr size_t OFF_CENT = 256;   // 8 doubles: centroids and masses
 constexpr size_t OFF_RESULT = 512; // 4 doubles: D_o, D_i, mass1, mass2
 constexpr size_t OFF_EXTENT = 768; // Eq. 42 extents: 2 x uint64 (l_y bit patterns), 2 doubles (l_x)
 constexpr size_t OFF_BREAKUP = 832; // breakup probe: 6 doubles of sums
 constexpr size_t OFF_ROWS = 1024;  // ny * 8 doubles: per-row partial sums
-static_assert(OFF_SLOTS >= OFF_RES_SOR + 16 && OFF_SLOTS + 48 <= OFF_CENT, "scratch words overlap");
+static_assert(OFF_SLOTS >= OFF_RES_SOR + 16 && OFF_TESTS + 8 <= OFF_CENT && (OFF_TESTS + 8) / 8 <= 64,
+              "scratch words overlap");
 
 size_t elem_size(int precision) { return precision == FCD_FP64 ? sizeof(double) : sizeof(float); }
 
@@ -863,26 +865,31 @@ bool step_decided_on_device(const fcd_handle* h) {
 
 // A time step's potential solve and its collide-and-stream without the host waiting inside
 // the step.  The residual tests (the finest level's first pre-smoothing sweep, reducing
-// its input's residual) write rotating slots; every kernel of a V-cycle, the pre-smoothing
-// sweeps after the test included, reads the preceding test's slot and does nothing when
-// that test passed, and the collide-and-stream runs only when the last test passed.  The
-// first test, one V-cycle and the next test, then the collision, are launched together;
-// the collision's first lane publishes both tests, which the host reads while the
-// collision runs, applying the same rule, before it launches the next time step.  Only
-// when the solve needs more V-cycles does the host add one cycle, its test and the
-// collision again at a time.  No V-cycle is launched ahead when the previous solve needed
-// none, or when max_iters is 0.  A test that did not run leaves its slot zero (a pass): a
-// test zeroes the slot after its own, and the collision the slot after the gating test.
-// Eager launches: the host runs ahead of the GPU here, and a launch after a replayed graph
-// waits several microseconds for the graph to retire.  *collided: the collide-and-stream
-// has run (src -> dst).
+// its input's residual) write rotating slots and count themselves; every kernel of a
+// V-cycle, the pre-smoothing sweeps after the test included, reads the preceding test's
+// slot and does nothing when that test passed, and the collide-and-stream runs only when
+// the last test launched passed.  The first test, some V-cycles each followed by its test,
+// then the collision, are launched together: one cycle fewer than the previous solve
+// needed, at least one (none when the previous solve needed none; at most max_iters and
+// SOLVE_SLOTS - 2, so that no slot is reused before its test is published).
+// The collision's first lane publishes the slots and the count of tests that ran, which
+// the host reads while the collision runs; the last test that ran decides, by the same
+// rule as on the device, and the host goes on to the next time step.  Only when the solve
+// needs more V-cycles than were launched does the host add one cycle, its test and the
+// collision again at a time.  A test that did not run leaves its slot zero (a pass): a
+// test that runs zeroes the slot after its own, one that does not zeroes its own, and the
+// collision zeroes the slot after the last test launched.  Eager launches: the host runs ahead of the GPU here, and a launch after a
+// replayed graph waits several microseconds for the graph to retire.  *collided: the
+// collide-and-stream has run (src -> dst).
 template <typename T>
 fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T* src, T* dst, bool* collided) {
     *collided = false;
     restrict_mu_all<T>(h);
+    char* scr = static_cast<char*>(h->buf.scratch);
     auto slot = [&](unsigned long long k) {
-        return reinterpret_cast<unsigned long long*>(static_cast<char*>(h->buf.scratch) + OFF_SLOTS) + 2 * (k % 3);
+        return reinterpret_cast<unsigned long long*>(scr + OFF_SLOTS) + 2 * (k % fcd::SOLVE_SLOTS);
     };
+    unsigned* const tests = reinterpret_cast<unsigned*>(scr + OFF_TESTS);
     const double thr0 = h->prm.pot_tol * std::fabs(h->prm.H0);
     const double ff = resid_floor_factor<T>();
     auto passes = [&](double r, double sc) { return r <= std::max(thr0, ff * sc); };
@@ -897,7 +904,7 @@ fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T
     const fcd::PotLevel<CT>* none = nullptr;
     // test k (gated on test k - 1 unless it is the solve's first) into slot k, zeroing slot k + 1
     auto test = [&](unsigned long long k, const fcd::PotLevel<T>& L) {
-        fcd::launch_mg_smooth_tile<T, CT>(L, L.u, t0, none, mode, slot(k), 1, h->stream, slot(k + 1));
+        fcd::launch_mg_smooth_tile<T, CT>(L, L.u, t0, none, mode, slot(k), 1, h->stream, slot(k + 1), tests);
     };
     // the V-cycle after test k and test k + 1, both gated on test k
     auto cycle = [&](unsigned long long k) {
@@ -908,53 +915,57 @@ fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T
         h->gate = fcd::ResGate{};
         return hip_check(hipGetLastError(), "potential launch");
     };
-    // the collision gated on test k, publishing tests k - 1 and k
+    // the collision gated on test k, publishing the slots and the test count
     auto collide = [&](unsigned long long k) {
         ++h->seq_want;
-        const fcd::StepGate sg{gate_of(k), slot(k - 1), slot(k + 1), h->mirror, div_word(h), h->seq_want};
+        const fcd::StepGate sg{gate_of(k), slot(0), slot(k + 1), tests, h->mirror, div_word(h), h->seq_want};
         fcd::launch_collide_stream<T>(src, dst, phi, psi, P, div_word(h), h->stream, nullptr, nullptr, sg);
         if (h->open_x)
             fcd::launch_open_boundaries<T>(src, dst, phi, psi, P, h->u_in, h->u_out, h->stream, gate_of(k));
         return hip_check(hipGetLastError(), "collide-stream launch");
     };
-    unsigned long long k = h->test_idx;
-    test(k, L0);
-    int cycles = 0;
-    bool ahead = h->pipe_last > 0 && max_iters > 0;
+    const unsigned long long k0 = h->test_idx;
+    test(k0, L0);
     fcd_status st = hip_check(hipGetLastError(), "potential launch");
-    if (!st && ahead) st = cycle(k);
-    unsigned long long last = ahead ? k + 1 : k;
+    const int ahead =
+        std::min({max_iters, fcd::SOLVE_SLOTS - 2, h->pipe_last <= 1 ? h->pipe_last : h->pipe_last - 1});
+    unsigned long long first = k0, last = k0;  // the tests of the launches awaiting publication
+    for (int c = 0; c < ahead && !st; ++c) st = cycle(last++);
     if (!st) st = collide(last);
     if (!st) st = wait_decisions(h);
+    long long run = 0;  // tests of this solve that ran
     double r = 0.0;
     bool done = false;
     while (!st) {
         const fcd::SolveMirror m = *h->mirror;
-        if (ahead && passes(m.r[0], m.scale[0])) {  // the first test passed: nothing after it ran
-            r = m.r[0];
-            done = true;
-        } else {
-            if (ahead) ++cycles;  // the cycle launched ahead ran (also after a NaN test)
-            r = m.r[1];
-            done = passes(m.r[1], m.scale[1]);
+        if (m.tests < 1 || m.tests > last - first + 1) {
+            char msg[160];
+            std::snprintf(msg, sizeof(msg), "inconsistent count of potential residual tests: %u ran, %llu launched",
+                          m.tests, last - first + 1);
+            st = fail(FCD_ERR_HIP, msg);
+            break;
         }
-        ahead = false;
+        // tests first .. first + tests - 1 ran; the last of them decides
+        const unsigned long long k = first + m.tests - 1;
+        run += m.tests;
+        r = m.r[k % fcd::SOLVE_SLOTS];
+        done = passes(r, m.scale[k % fcd::SOLVE_SLOTS]);
         st = divergence_status(m.div, u_limit_of(h->prm), "divergence guard");
         if (st || done) break;
         if (r != r) {
             st = fail(FCD_ERR_DIVERGED, "potential residual is NaN");
             break;
         }
-        if (cycles >= max_iters) {
+        if (run - 1 >= max_iters) {
             st = fail(FCD_ERR_NOT_CONVERGED, "potential solve reached max_iters");
             break;
         }
-        st = cycle(last);
-        ++cycles;
-        ++last;
+        first = last + 1;
+        st = cycle(last++);
         if (!st) st = collide(last);
         if (!st) st = wait_decisions(h);
     }
+    const int cycles = (int)std::max(0LL, run - 1);
     h->test_idx = last + 1;
     *collided = done;
     h->sweeps += cycles;
@@ -2719,7 +2730,7 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     // the SOR words and the device-decided solve's words
     h->res_slot = 0;
     hipLaunchKernelGGL(fcd::k_fill<unsigned long long>, dim3(1), dim3(64), 0, h->stream, res_slot_ptr(h, 0),
-                       (long long)((OFF_SLOTS + 48) / sizeof(unsigned long long)), 0ULL);
+                       (long long)((OFF_TESTS + 8) / sizeof(unsigned long long)), 0ULL);
     st = hip_check(hipGetLastError(), "residual slot clear");
     if (st) {
         (void)hipHostFree(h->mirror);

@@ -45,7 +45,8 @@ struct StepConst {
 // The outcome of a residual test, read on the device from the test's two words (max
 // |residual| and max |C psi'| as bit patterns of non-negative doubles; both zero when the
 // test did not run): passed when r <= max(thr0, floor_factor * scale).  A NaN residual
-// does not pass.  res == nullptr: no test (nothing is gated).
+// does not pass.  res == nullptr: no test (nothing is gated).  The words are written and
+// cleared by earlier kernels on the same stream only.
 struct ResGate {
     const unsigned long long* res;
     double thr0, floor_factor;
@@ -73,22 +74,26 @@ struct PotLevel {
     T H0x, H0y;   // applied field (finest level only)
 };
 
-// The last two residual tests of a time step's solve and the divergence flag word, as the
-// step's collide-and-stream publishes them to pinned host memory; seq is stored last.
+// The residual tests of a time step's solve (the rotating slots), the number of tests that
+// ran since the last publication and the divergence flag word, as the step's
+// collide-and-stream publishes them to pinned host memory; seq is stored last.
+constexpr int SOLVE_SLOTS = 8;
 struct SolveMirror {
     unsigned long long seq;
-    double r[2], scale[2];  // [0]: the test before the gating one, [1]: the gating test
+    double r[SOLVE_SLOTS], scale[SOLVE_SLOTS];
+    unsigned tests, pad_;
     unsigned long long div;
 };
 
 // The collide-and-stream of a time step whose solve is decided on the device: with
 // gate.res set it runs only if that test passed, and its first lane first publishes the
-// previous test (prev) and the gating test with the divergence word to m under the
-// sequence number seq, and zeroes the two words at clear (the next test's).
+// slots, the test count (then zeroed) and the divergence word to m under the sequence
+// number seq, and zeroes the two words at clear (the next test's).
 struct StepGate {
     ResGate gate;
-    const unsigned long long* prev;
+    const unsigned long long* slots;
     unsigned long long* clear;
+    unsigned* tests;
     SolveMirror* m;
     const unsigned long long* div;
     unsigned long long seq;

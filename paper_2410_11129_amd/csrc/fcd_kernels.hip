@@ -108,11 +108,13 @@ __global__ void __launch_bounds__(BX* CY)
     if (sg.gate.res) {
         if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
             SolveMirror* m = sg.m;
-            m->r[0] = __longlong_as_double((long long)sg.prev[0]);
-            m->scale[0] = __longlong_as_double((long long)sg.prev[1]);
-            m->r[1] = __longlong_as_double((long long)sg.gate.res[0]);
-            m->scale[1] = __longlong_as_double((long long)sg.gate.res[1]);
+            for (int q = 0; q < SOLVE_SLOTS; ++q) {
+                m->r[q] = __longlong_as_double((long long)sg.slots[2 * q]);
+                m->scale[q] = __longlong_as_double((long long)sg.slots[2 * q + 1]);
+            }
+            m->tests = *sg.tests;
             m->div = *sg.div;
+            *sg.tests = 0u;
             sg.clear[0] = 0ULL;
             sg.clear[1] = 0ULL;
             __hip_atomic_store(&m->seq, sg.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);

@@ -32,10 +32,12 @@ void launch_mg_restrict_mu4(const T* muf, int pitchf, int nxf, int nyf, const Mu
 // with res_clear == nullptr a fill launch clears them first; otherwise the kernel itself
 // zeroes res_clear[0..1] (the next test's slot) and res must already be zero.
 // inner: sweeps on the tile before it is written back.  The coarse correction may be of
-// another type (TC) than the level's.
+// another type (TC) than the level's.  count != nullptr: the launch adds one to *count
+// when it runs (it does not when its level's gate has closed it).
 template <typename T, typename TC>
 void launch_mg_smooth_tile(const PotLevel<T>& L, const T* uin, T* uout, const PotLevel<TC>* prolong_from, int mode,
-                           unsigned long long* res, int inner, hipStream_t s, unsigned long long* res_clear = nullptr);
+                           unsigned long long* res, int inner, hipStream_t s, unsigned long long* res_clear = nullptr,
+                           unsigned* count = nullptr);
 // Residual restriction by tiles from F (u = the smoothed iterate) into C (f, u = 0);
 // mode as for the tile smoother.
 template <typename T, typename TC>
