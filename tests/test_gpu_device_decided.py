@@ -5,6 +5,7 @@ device: the next V-cycle and the collide-and-stream are enqueued ahead and gated
 decision.  Per-kernel timing selects the host-decided loop instead, which takes the same
 test before every V-cycle, so both must give the same cycle count and a bitwise identical
 state.  Covered: solves that need several cycles (the start from the initial state), solves
+that need fewer cycles than were launched ahead (several gated tests skipped in a row), solves
 that need none (a loose tolerance; such a step then enqueues no V-cycle ahead), an odd-size
 hierarchy with one finest sweep each way (the pre-smoothed iterate then sits in the
 temporary plane), the open channel's gated boundary kernels, FP32, the potential solved
@@ -81,6 +82,11 @@ def test_device_decided_steps_equal_host_decided(case):
     assert np.array_equal(s_dev, s_host)
     # steps needing more than the one V-cycle launched ahead (the host adds cycles)
     assert max(per_dev) >= 2
+    if case == "200x50_fp32":
+        # a step needing two or more cycles fewer than were launched ahead of it (one fewer
+        # than the previous step needed, at most six): several gated tests skipped in a row
+        ahead = [min(6, p - 1 if p > 1 else p) for p in per_dev[:-1]]
+        assert max(a - n for a, n in zip(ahead, per_dev[1:])) >= 2
     if case == "200x50_loose":
         # steps whose first test passes, and a step needing a cycle after one that needed
         # none (no V-cycle was launched ahead of it)
