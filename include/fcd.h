@@ -271,7 +271,10 @@ fcd_status fcd_stats(fcd_handle* h, double out[3]);
  * 2 convergence test (SOR: residual kernel; multigrid: the V-cycle's first smoothing
  * kernel, which reduces the residual of its input); 3 phase moments; 4 multigrid finest-level pre-smoothing kernel; 5 multigrid finest-level
  * prolongation + post-smoothing kernel.  Classes 4 and 5 are single kernels, also
- * counted inside classes 1 and 2.  out must hold 12 doubles. */
+ * counted inside classes 1 and 2.  out must hold 12 doubles.  While timing is on, time
+ * steps decide their multigrid tests on the host (one stream synchronisation per test, no
+ * launches ahead of a decision), with the same decisions and results as the
+ * device-decided steps. */
 fcd_status fcd_timing(fcd_handle* h, int32_t enable);
 fcd_status fcd_timing_read(fcd_handle* h, double out[12]);
 
