@@ -855,83 +855,67 @@ fcd_status wait_decisions(fcd_handle* h) {
     return FCD_OK;
 }
 
-// Whether a time step's multigrid solve is decided on the device: a hierarchy with an LDS
-// tail and a field; per-kernel timing keeps the host-decided loop, whose decisions are the
-// same (a test before every V-cycle), so the results are bitwise identical either way.
-bool step_decided_on_device(const fcd_handle* h) {
-    return h->prm.pot_solver == FCD_SOLVER_MG && h->plan.levels > 1 && h->plan.tail < h->plan.levels &&
-           h->prm.H0 != 0.0 && !h->timer.on;
-}
-
-// A time step's potential solve and its collide-and-stream without the host waiting inside
-// the step.  The residual tests (the finest level's first pre-smoothing sweep, reducing
-// its input's residual) write rotating slots and count themselves; every kernel of a
-// V-cycle, the pre-smoothing sweeps after the test included, reads the preceding test's
-// slot and does nothing when that test passed, and the collide-and-stream runs only when
-// the last test launched passed.  The first test, some V-cycles each followed by its test,
-// then the collision, are launched together: one cycle fewer than the previous solve
-// needed, at least one (none when the previous solve needed none; at most max_iters and
-// SOLVE_SLOTS - 2, so that no slot is reused before its test is published).
-// The collision's first lane publishes the slots and the count of tests that ran, which
-// the host reads while the collision runs; the last test that ran decides, by the same
-// rule as on the device, and the host goes on to the next time step.  Only when the solve
-// needs more V-cycles than were launched does the host add one cycle, its test and the
-// collision again at a time.  A test that did not run leaves its slot zero (a pass): a
-// test that runs zeroes the slot after its own, one that does not zeroes its own, and the
-// collision zeroes the slot after the last test launched.  Eager launches: the host runs ahead of the GPU here, and a launch after a
-// replayed graph waits several microseconds for the graph to retire.  *collided: the
-// collide-and-stream has run (src -> dst).
-template <typename T>
-fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T* src, T* dst, bool* collided) {
-    *collided = false;
-    restrict_mu_all<T>(h);
+// A multigrid solve of the finest-level problem L0 (ungated; its mu hierarchy restricted)
+// without the host waiting inside it.  The residual tests (the finest level's first
+// pre-smoothing sweep, reducing its input's residual) write rotating slots and count
+// themselves; every kernel of a V-cycle, the pre-smoothing sweeps after the test included,
+// reads the preceding test's slot and does nothing when that test passed.  The first test
+// and `ahead` V-cycles each followed by its test are launched together, then finish(sg),
+// which launches what ends the batch: a kernel that publishes sg (the slots, the count of
+// tests that ran, the divergence word) with one lane and, for a time step, the
+// collide-and-stream gated on the last test.  The host waits for the publication; the last
+// test that ran decides, by the same rule as on the device (converged when max |r| <=
+// max(thr0, 16 eps max |C psi'|)); when the solve needs more V-cycles the host adds one
+// cycle, its test and finish again at a time.  A test that did not run leaves its slot
+// zero (a pass): a test that runs zeroes the slot after its own, one that does not zeroes
+// its own, and the publication the slot after the last test launched; at most
+// SOLVE_SLOTS - 2 cycles are launched at once, so that no slot is reused before its test is
+// published.  The decisions are those of the host-decided loop (a test before every
+// V-cycle).  Eager launches: the host runs ahead of the GPU here, and a launch after a
+// replayed graph waits several microseconds for the graph to retire.  *done: the solve
+// converged (a time step's collision has then run); *cycles, *resid: V-cycles run, the
+// deciding test's residual.
+template <typename T, typename Finish>
+fcd_status solve_on_device(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0, int max_iters, int ahead,
+                           Finish&& finish, int* cycles_out, double* resid_out, bool* done_out) {
     char* scr = static_cast<char*>(h->buf.scratch);
     auto slot = [&](unsigned long long k) {
         return reinterpret_cast<unsigned long long*>(scr + OFF_SLOTS) + 2 * (k % fcd::SOLVE_SLOTS);
     };
     unsigned* const tests = reinterpret_cast<unsigned*>(scr + OFF_TESTS);
-    const double thr0 = h->prm.pot_tol * std::fabs(h->prm.H0);
     const double ff = resid_floor_factor<T>();
     auto passes = [&](double r, double sc) { return r <= std::max(thr0, ff * sc); };
     auto gate_of = [&](unsigned long long k) { return fcd::ResGate{slot(k), thr0, ff}; };
-    const fcd::PotLevel<T> L0 = pot_level<T>(h, 0);
     const int mode = fine_mode(L0);
     T* const t0 = mg_temp<T>(h, 0);
     const int nu1 = std::max(1, h->prm.pot_smooth);
-    const int max_iters = h->prm.pot_max_iters;
-    T* const psi = static_cast<T*>(h->buf.psi);
-    const T* phi = static_cast<const T*>(h->buf.phi);
     const fcd::PotLevel<CT>* none = nullptr;
+    ahead = std::max(0, std::min({ahead, max_iters, fcd::SOLVE_SLOTS - 2}));
     // test k (gated on test k - 1 unless it is the solve's first) into slot k, zeroing slot k + 1
     auto test = [&](unsigned long long k, const fcd::PotLevel<T>& L) {
         fcd::launch_mg_smooth_tile<T, CT>(L, L.u, t0, none, mode, slot(k), 1, h->stream, slot(k + 1), tests);
     };
     // the V-cycle after test k and test k + 1, both gated on test k
     auto cycle = [&](unsigned long long k) {
-        h->gate = gate_of(k);  // the levels built while it is set carry the gate
-        const fcd::PotLevel<T> L0g = pot_level<T>(h, 0);
+        h->gate = gate_of(k);  // the coarse levels built while it is set carry the gate
+        fcd::PotLevel<T> L0g = L0;
+        L0g.gate = h->gate;
         vcycle_rest<T>(h, L0g, mg_sweeps<T>(h, L0g, mode, t0, nu1 - 1));
         test(k + 1, L0g);
         h->gate = fcd::ResGate{};
         return hip_check(hipGetLastError(), "potential launch");
     };
-    // the collision gated on test k, publishing the slots and the test count
-    auto collide = [&](unsigned long long k) {
+    // what ends a batch whose last test is k
+    auto fin = [&](unsigned long long k) {
         ++h->seq_want;
-        const fcd::StepGate sg{gate_of(k), slot(0), slot(k + 1), tests, h->mirror, div_word(h), h->seq_want};
-        fcd::launch_collide_stream<T>(src, dst, phi, psi, P, div_word(h), h->stream, nullptr, nullptr, sg);
-        if (h->open_x)
-            fcd::launch_open_boundaries<T>(src, dst, phi, psi, P, h->u_in, h->u_out, h->stream, gate_of(k));
-        return hip_check(hipGetLastError(), "collide-stream launch");
+        return finish(fcd::StepGate{gate_of(k), slot(0), slot(k + 1), tests, h->mirror, div_word(h), h->seq_want});
     };
     const unsigned long long k0 = h->test_idx;
     test(k0, L0);
     fcd_status st = hip_check(hipGetLastError(), "potential launch");
-    const int ahead =
-        std::min({max_iters, fcd::SOLVE_SLOTS - 2, h->pipe_last <= 1 ? h->pipe_last : h->pipe_last - 1});
     unsigned long long first = k0, last = k0;  // the tests of the launches awaiting publication
     for (int c = 0; c < ahead && !st; ++c) st = cycle(last++);
-    if (!st) st = collide(last);
+    if (!st) st = fin(last);
     if (!st) st = wait_decisions(h);
     long long run = 0;  // tests of this solve that ran
     double r = 0.0;
@@ -962,12 +946,44 @@ fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T
         }
         first = last + 1;
         st = cycle(last++);
-        if (!st) st = collide(last);
+        if (!st) st = fin(last);
         if (!st) st = wait_decisions(h);
     }
-    const int cycles = (int)std::max(0LL, run - 1);
     h->test_idx = last + 1;
-    *collided = done;
+    *cycles_out = (int)std::max(0LL, run - 1);
+    *resid_out = r;
+    *done_out = done;
+    return st;
+}
+
+// Whether solves of this handle run on the device (solve_on_device): multigrid on a
+// hierarchy with the LDS tail; per-kernel timing keeps the host-decided loop, whose
+// decisions are the same, so the results are bitwise identical either way.
+bool solves_on_device(const fcd_handle* h) {
+    return h->prm.pot_solver == FCD_SOLVER_MG && h->plan.levels > 1 && h->plan.tail < h->plan.levels &&
+           !h->timer.on;
+}
+
+// A time step's potential solve and its collide-and-stream (solve_on_device, the
+// collision ending each batch): V-cycles launched ahead one fewer than the previous solve
+// needed, at least one (none when it needed none).  *collided: the collide-and-stream has
+// run (src -> dst).
+template <typename T>
+fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T* src, T* dst, bool* collided) {
+    restrict_mu_all<T>(h);
+    T* const psi = static_cast<T*>(h->buf.psi);
+    const T* phi = static_cast<const T*>(h->buf.phi);
+    auto collide = [&](const fcd::StepGate& sg) {
+        fcd::launch_collide_stream<T>(src, dst, phi, psi, P, div_word(h), h->stream, nullptr, nullptr, sg);
+        if (h->open_x)
+            fcd::launch_open_boundaries<T>(src, dst, phi, psi, P, h->u_in, h->u_out, h->stream, sg.gate);
+        return hip_check(hipGetLastError(), "collide-stream launch");
+    };
+    int cycles = 0;
+    double r = 0.0;
+    const int ahead = h->pipe_last <= 1 ? h->pipe_last : h->pipe_last - 1;
+    const fcd_status st = solve_on_device<T>(h, pot_level<T>(h, 0), h->prm.pot_tol * std::fabs(h->prm.H0),
+                                             h->prm.pot_max_iters, ahead, collide, &cycles, &r, collided);
     h->sweeps += cycles;
     h->last_iters = cycles;
     h->pipe_last = cycles;
@@ -1004,7 +1020,7 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
                 fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, prev3, h->lat.nx, h->lat.ny,
                                            h->lat.pitch, mode, h->stream);
             }
-            if (step_decided_on_device(h)) {
+            if (h->prm.H0 != 0.0 && solves_on_device(h)) {
                 bool collided = false;
                 st = step_solve_collide<T>(h, P, src, dst, &collided);
                 if (collided) {
@@ -2331,7 +2347,21 @@ fcd_status adj_backward_impl(fcd_handle* h, const double dJ[2], double grad[6]) 
                     La.f = rhs;
                     La.H0x = La.H0y = T(0);
                     int it = 0;
-                    st = iterate_level0<T>(h, La, h->prm.pot_tol * rm, h->prm.pot_max_iters, adj_iters, &it, nullptr);
+                    if (solves_on_device(h)) {
+                        auto publish = [&](const fcd::StepGate& sg) {
+                            fcd::launch_solve_publish(sg, h->stream);
+                            return hip_check(hipGetLastError(), "publication launch");
+                        };
+                        double r = 0.0;
+                        bool done = false;
+                        st = solve_on_device<T>(h, La, h->prm.pot_tol * rm, h->prm.pot_max_iters,
+                                                adj_iters <= 1 ? adj_iters : adj_iters - 1, publish, &it, &r, &done);
+                        h->sweeps += it;
+                        h->last_resid = r;
+                    } else {
+                        st = iterate_level0<T>(h, La, h->prm.pot_tol * rm, h->prm.pot_max_iters, adj_iters, &it,
+                                               nullptr);
+                    }
                     adj_iters = it;
                     if (st) break;
                 } else {

@@ -85,10 +85,11 @@ struct SolveMirror {
     unsigned long long div;
 };
 
-// The collide-and-stream of a time step whose solve is decided on the device: with
-// gate.res set it runs only if that test passed, and its first lane first publishes the
-// slots, the test count (then zeroed) and the divergence word to m under the sequence
-// number seq, and zeroes the two words at clear (the next test's).
+// The launch that ends a batch of a solve decided on the device (the collide-and-stream
+// of a time step, or a one-lane publication): with gate.res set, the collide-and-stream
+// runs only if that test passed; one lane first publishes the slots, the test count
+// (then zeroed) and the divergence word to m under the sequence number seq, and zeroes
+// the two words at clear (the next test's).
 struct StepGate {
     ResGate gate;
     const unsigned long long* slots;
@@ -98,6 +99,21 @@ struct StepGate {
     const unsigned long long* div;
     unsigned long long seq;
 };
+
+// The publication of a StepGate, by one lane; the host polls m->seq (stored last).
+__device__ __forceinline__ void publish_tests(const StepGate& sg) {
+    SolveMirror* m = sg.m;
+    for (int q = 0; q < SOLVE_SLOTS; ++q) {
+        m->r[q] = __longlong_as_double((long long)sg.slots[2 * q]);
+        m->scale[q] = __longlong_as_double((long long)sg.slots[2 * q + 1]);
+    }
+    m->tests = *sg.tests;
+    m->div = *sg.div;
+    *sg.tests = 0u;
+    sg.clear[0] = 0ULL;
+    sg.clear[1] = 0ULL;
+    __hip_atomic_store(&m->seq, sg.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // The coarsest levels of a V-cycle, solved in LDS by one block (levels lv[0..n), finest
 // first; lv[0].f holds the restricted residual, lv[0].u receives the correction).

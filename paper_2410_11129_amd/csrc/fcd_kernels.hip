@@ -106,19 +106,7 @@ __global__ void __launch_bounds__(BX* CY)
                          const T* __restrict__ psi, StepConst<T> P, unsigned long long* __restrict__ div,
                          StepGate sg) {
     if (sg.gate.res) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-            SolveMirror* m = sg.m;
-            for (int q = 0; q < SOLVE_SLOTS; ++q) {
-                m->r[q] = __longlong_as_double((long long)sg.slots[2 * q]);
-                m->scale[q] = __longlong_as_double((long long)sg.slots[2 * q + 1]);
-            }
-            m->tests = *sg.tests;
-            m->div = *sg.div;
-            *sg.tests = 0u;
-            sg.clear[0] = 0ULL;
-            sg.clear[1] = 0ULL;
-            __hip_atomic_store(&m->seq, sg.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) publish_tests(sg);
         if (!sg.gate.passed()) return;
     }
     __shared__ T t1[CY + 2][BX + 2], t2[CY + 2][BX + 2], tp[CY + 2][BX + 2];

@@ -57,6 +57,9 @@ template <typename T>
 void launch_mg_tail(const MgTail<T>& tl, hipStream_t s);
 template <typename T>
 void launch_psi_history(T* psi, T* prev, T* prev2, T* prev3, int nx, int ny, int pitch, int mode, hipStream_t s);
+// Publication of a solve decided on the device that no collide-and-stream ends
+// (fcd_potential.hip): one lane, as the collide-and-stream's first.
+void launch_solve_publish(const StepGate& sg, hipStream_t s);
 
 // Batched multigrid (fcd_potential.hip): one launch per level for every channel of a
 // batch, jobs = (channel, level, tile), channels with active[k] == 0 skipped.

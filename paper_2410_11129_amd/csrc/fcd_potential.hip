@@ -945,6 +945,11 @@ __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
     mg_tail<T>(tl, dv);
 }
 
+// Publication of a solve decided on the device when no collide-and-stream follows it.
+__global__ void __launch_bounds__(64) k_solve_publish(StepGate sg) {
+    if (threadIdx.x == 0) publish_tests(sg);
+}
+
 // Warm start from the recorded solutions: mode 0 keeps psi' and records it; mode 1
 // replaces psi' by the linear extrapolation 2 psi'(t-1) - psi'(t-2), mode 2 by the
 // quadratic one 3 psi'(t-1) - 3 psi'(t-2) + psi'(t-3), mode 3 by the cubic one
@@ -1078,6 +1083,10 @@ void launch_mg_tail(const MgTail<T>& tl, hipStream_t s) {
     TailDiv dv{};
     for (int k = 0; k < tl.n; ++k) dv.inv[k] = (unsigned)(((1ull << 32) + tl.lv[k].nx - 1) / tl.lv[k].nx);
     hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(TAIL_T), mg_tail_lds_bytes<T>(tl), s, tl, dv);
+}
+
+void launch_solve_publish(const StepGate& sg, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_publish, dim3(1), dim3(64), 0, s, sg);
 }
 
 template <typename T>
