@@ -168,7 +168,8 @@ fcd_status fcd_init_fields(fcd_handle* h, const double* phi1, const double* phi2
 
 /* Solve the potential for the current state (Eq. 6), warm-started from the stored psi',
  * with the configured solver (four-colour SOR or multigrid V-cycles), until
- * max |L(psi0 + psi')| <= tol * H0 or max_iters sweeps / cycles.  Sync.  iters_out /
+ * max |L(psi0 + psi')| <= tol * H0 or max_iters sweeps / cycles (multigrid with the LDS
+ * tail: tests decided on the GPU, as in fcd_step).  Sync.  iters_out /
  * resid_out (nullable) receive the iteration count and the final residual.  Returns
  * FCD_ERR_NOT_CONVERGED if the tolerance was not met. */
 fcd_status fcd_solve_potential(fcd_handle* h, double tol, int32_t max_iters,

@@ -816,24 +816,6 @@ fcd_status iterate_level0(fcd_handle* h, const fcd::PotLevel<T>& L0, double thr0
 }
 
 // Potential solve on the current mu_r plane, warm-started from the stored psi'.
-template <typename T>
-fcd_status solve_impl(fcd_handle* h, double tol, int max_iters, int* iters_out, double* resid_out) {
-    T* psi = static_cast<T*>(h->buf.psi);
-    if (iters_out) *iters_out = 0;
-    if (h->prm.H0 == 0.0) {  // no applied field: psi' = 0 exactly
-        fcd::launch_fill<T>(psi, (long long)h->lat.ny * h->lat.pitch, T(0), h->stream);
-        if (resid_out) *resid_out = 0.0;
-        h->last_resid = 0.0;
-        return hip_check(hipGetLastError(), "fill");
-    }
-    if (h->prm.pot_solver == FCD_SOLVER_MG) restrict_mu_all<T>(h);
-    int it = 0;
-    const fcd_status st = iterate_level0<T>(h, pot_level<T>(h, 0), tol * std::fabs(h->prm.H0), max_iters,
-                                            h->last_iters, &it, resid_out);
-    h->last_iters = it;
-    if (iters_out) *iters_out = it;
-    return st;
-}
 
 // Wait until the GPU has published the outcome of every collide-and-stream enqueued so far
 // (the gated kernel's first lane stores the mirror's seq last); the stream is queried now
@@ -988,6 +970,40 @@ fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T
     h->last_iters = cycles;
     h->pipe_last = cycles;
     h->last_resid = r;
+    return st;
+}
+
+template <typename T>
+fcd_status solve_impl(fcd_handle* h, double tol, int max_iters, int* iters_out, double* resid_out) {
+    T* psi = static_cast<T*>(h->buf.psi);
+    if (iters_out) *iters_out = 0;
+    if (h->prm.H0 == 0.0) {  // no applied field: psi' = 0 exactly
+        fcd::launch_fill<T>(psi, (long long)h->lat.ny * h->lat.pitch, T(0), h->stream);
+        if (resid_out) *resid_out = 0.0;
+        h->last_resid = 0.0;
+        return hip_check(hipGetLastError(), "fill");
+    }
+    if (h->prm.pot_solver == FCD_SOLVER_MG) restrict_mu_all<T>(h);
+    int it = 0;
+    fcd_status st = FCD_OK;
+    if (solves_on_device(h)) {
+        auto publish = [&](const fcd::StepGate& sg) {
+            fcd::launch_solve_publish(sg, h->stream);
+            return hip_check(hipGetLastError(), "publication launch");
+        };
+        double r = 0.0;
+        bool done = false;
+        st = solve_on_device<T>(h, pot_level<T>(h, 0), tol * std::fabs(h->prm.H0), max_iters,
+                                h->last_iters <= 1 ? h->last_iters : h->last_iters - 1, publish, &it, &r, &done);
+        h->sweeps += it;
+        h->last_resid = r;
+        if (resid_out) *resid_out = r;
+    } else {
+        st = iterate_level0<T>(h, pot_level<T>(h, 0), tol * std::fabs(h->prm.H0), max_iters, h->last_iters, &it,
+                               resid_out);
+    }
+    h->last_iters = it;
+    if (iters_out) *iters_out = it;
     return st;
 }
 
