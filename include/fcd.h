@@ -265,7 +265,9 @@ fcd_status fcd_stats(fcd_handle* h, double out[3]);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around every
  * launch of the step's kernels.  fcd_timing(h, 1) clears the totals and starts
- * recording; fcd_timing(h, 0) stops.  fcd_timing_read (sync) fills out[2*k] with the
+ * recording; fcd_timing(h, 0) stops; fcd_timing(h, 2) records only the launches of the
+ * collide-and-stream that ran (class 0; the kernel launch records its own start and end,
+ * and the steps keep their device-decided path).  Sync.  fcd_timing_read (sync) fills out[2*k] with the
  * total milliseconds and out[2*k+1] with the launch count of class k:
  * 0 fused collide-stream kernel; 1 one potential iteration (a four-colour SOR sweep,
  * or the part of a multigrid V-cycle that follows the convergence test);

@@ -174,6 +174,7 @@ struct Timer {
         hipEvent_t a, b;
     };
     bool on = false;
+    bool collide_only = false;  // only the collide-and-stream's launches are timed
     std::vector<Pair> pending;
     std::vector<hipEvent_t> pool;
     double ms[TK_KINDS] = {};
@@ -210,7 +211,20 @@ struct Timer {
         *b = take();
         return *a && *b;
     }
+    // The same for a collide-and-stream launch, which is also timed when only it is.
+    bool pair_collide(hipEvent_t* a, hipEvent_t* b) {
+        *a = *b = nullptr;
+        if (!on && !collide_only) return false;
+        *a = take();
+        *b = take();
+        return *a && *b;
+    }
     void add(int kind, hipEvent_t a, hipEvent_t b) { pending.push_back({kind, a, b}); }
+    // Events of a launch whose time is not wanted (a collision whose gate stayed closed).
+    void drop(hipEvent_t a, hipEvent_t b) {
+        if (a) pool.push_back(a);
+        if (b) pool.push_back(b);
+    }
     // Only after the stream has been synchronised.
     void resolve() {
         for (const Pair& p : pending) {
@@ -955,8 +969,13 @@ fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T
     restrict_mu_all<T>(h);
     T* const psi = static_cast<T*>(h->buf.psi);
     const T* phi = static_cast<const T*>(h->buf.phi);
+    // with collide-only timing, the events of the last collision launched (the earlier ones
+    // of the step found the solve unconverged and did nothing)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     auto collide = [&](const fcd::StepGate& sg) {
-        fcd::launch_collide_stream<T>(src, dst, phi, psi, P, div_word(h), h->stream, nullptr, nullptr, sg);
+        h->timer.drop(e0, e1);
+        if (!h->timer.pair_collide(&e0, &e1)) e0 = e1 = nullptr;
+        fcd::launch_collide_stream<T>(src, dst, phi, psi, P, div_word(h), h->stream, e0, e1, sg);
         if (h->open_x)
             fcd::launch_open_boundaries<T>(src, dst, phi, psi, P, h->u_in, h->u_out, h->stream, sg.gate);
         return hip_check(hipGetLastError(), "collide-stream launch");
@@ -966,6 +985,10 @@ fcd_status step_solve_collide(fcd_handle* h, const fcd::StepConst<T>& P, const T
     const int ahead = h->pipe_last <= 1 ? h->pipe_last : h->pipe_last - 1;
     const fcd_status st = solve_on_device<T>(h, pot_level<T>(h, 0), h->prm.pot_tol * std::fabs(h->prm.H0),
                                              h->prm.pot_max_iters, ahead, collide, &cycles, &r, collided);
+    if (e0 && *collided)
+        h->timer.add(TK_COLLIDE, e0, e1);
+    else
+        h->timer.drop(e0, e1);
     h->sweeps += cycles;
     h->last_iters = cycles;
     h->pipe_last = cycles;
@@ -1057,7 +1080,7 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
             ++h->hist;
         }
         ++h->qs;
-        timed = h->timer.pair(&e0, &e1);
+        timed = h->timer.pair_collide(&e0, &e1);
         fcd::launch_collide_stream<T>(src, dst, phi, static_cast<const T*>(h->buf.psi), P, div_word(h), h->stream,
                                       e0, e1);
         if (timed) h->timer.add(TK_COLLIDE, e0, e1);
@@ -2975,7 +2998,8 @@ fcd_status fcd_timing(fcd_handle* h, int32_t enable) {
     if (st) return st;
     h->timer.resolve();
     h->timer.clear();
-    h->timer.on = enable != 0;
+    h->timer.on = enable == 1;
+    h->timer.collide_only = enable == 2;
     return FCD_OK;
 }
 

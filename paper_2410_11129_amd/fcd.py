@@ -244,8 +244,9 @@ def fcd_stats(h):
     return list(out)
 
 
-def fcd_timing(h, enable: bool):
-    _check(lib().fcd_timing(h, 1 if enable else 0), "fcd_timing")
+def fcd_timing(h, enable):
+    """enable: False / 0 off, True / 1 every launch of the step, 2 the collide-and-stream only."""
+    _check(lib().fcd_timing(h, int(enable)), "fcd_timing")
 
 
 def fcd_use_graphs(h, enable: bool):

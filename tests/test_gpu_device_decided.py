@@ -123,3 +123,28 @@ def test_max_iters_stop_skips_the_collision():
     assert e_dev[1] == fcd.FCD_ERR_NOT_CONVERGED
     assert st_dev[0] == st_host[0] == e_dev[0] - 1
     assert np.array_equal(s_dev, s_host)
+
+
+def test_collide_only_timing_keeps_the_device_path():
+    """fcd_timing(h, 2) times the collide-and-stream launches that ran and nothing else;
+    the steps keep the device-decided solve (same cycles, same state as untimed)."""
+    w = single_channel_small()
+    say("case collide-only timing")
+    s_ref, st_ref, per_ref = run(w, 30, False, tol=1e-10)
+    ch = Channel(w, **{**MG, "tol": 1e-10})
+    ch.init_droplet()
+    fcd.fcd_timing(ch.h, 2)
+    per, done = [], 0.0
+    for _ in range(30):
+        ch.step(1)
+        c = ch.stats()[1]
+        per.append(int(c - done))
+        done = c
+    t = fcd.fcd_timing_read(ch.h)
+    fcd.fcd_timing(ch.h, 0)
+    s = ch.state()
+    ch.close()
+    assert per == per_ref
+    assert np.array_equal(s, s_ref)
+    assert t["collide_stream"][1] == 30 and t["collide_stream"][0] > 0.0
+    assert all(n == 0 for k, (ms, n) in t.items() if k != "collide_stream")
