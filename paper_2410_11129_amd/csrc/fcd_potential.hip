@@ -787,14 +787,23 @@ __device__ __forceinline__ void tail_sor(const TailLevel<T>& S, int sweeps, T om
         }
 }
 
-// Damped Jacobi, an even number of sweeps: u -> alt -> u -> ...
+// The first damped Jacobi sweep from u = 0 at node t (no neighbour enters it), as
+// tail_jacobi's arithmetic takes it: written by the phase that forms the level's f.
 template <typename T>
-__device__ __forceinline__ void tail_jacobi(const TailLevel<T>& S, int sweeps) {
+__device__ __forceinline__ T tail_first_sweep(const TailLevel<T>& S, int t) {
+    const T w = T(0.8), old = T(0);
+    return old + w * ((T(0) - S.f[t]) * S.rd[t] - old);
+}
+
+// Damped Jacobi, an even number of sweeps: u -> alt -> u -> ...; from_alt: the first sweep
+// from u = 0 is already in alt (tail_first_sweep), the others follow.
+template <typename T>
+__device__ __forceinline__ void tail_jacobi(const TailLevel<T>& S, int sweeps, bool from_alt = false) {
     const T w = T(0.8);
-    T* a = S.u;
-    T* b = S.alt;
+    T* a = from_alt ? S.alt : S.u;
+    T* b = from_alt ? S.u : S.alt;
     const int n = S.nx * S.ny;
-    for (int it = 0; it < sweeps; ++it) {
+    for (int it = from_alt ? 1 : 0; it < sweeps; ++it) {
         for (int t = threadIdx.x; t < n; t += TAIL_T) {
             const T old = a[t];
             b[t] = old + w * ((tail_acc(S, a, t) - S.f[t]) * S.rd[t] - old);
@@ -873,15 +882,20 @@ __device__ __forceinline__ void mg_tail(const MgTail<T>& tl, const TailDiv& dv) 
         }
     }
     __syncthreads();
+    // the couplings of every level; on the top level also the first Jacobi sweep from its
+    // zero correction (this thread stored that node's f above)
     for (int k = 0; k < tl.n; ++k) {
         const TailLevel<T> S = tail_view(tl, dv, base, k);
-        for (int t = tid; t < S.nx * S.ny; t += TAIL_T) tail_setup_node(S, tl.lv[k], t);
+        for (int t = tid; t < S.nx * S.ny; t += TAIL_T) {
+            tail_setup_node(S, tl.lv[k], t);
+            if (k == 0) S.alt[t] = tail_first_sweep(S, t);
+        }
     }
     __syncthreads();
     const int sw = 2 * ((tl.nu1 + 1) / 2);  // even
     for (int k = 0; k + 1 < tl.n; ++k) {
         const TailLevel<T> F = tail_view(tl, dv, base, k), Cc = tail_view(tl, dv, base, k + 1);
-        tail_jacobi(F, sw);
+        tail_jacobi(F, sw, sw > 0);
         // fine residuals f - L u into the (free) ping-pong array, then their
         // (1, 3, 3, 1)/8 x (1, 3, 3, 1)/8 weighted sums (as the tile restrictions)
         const int nf = F.nx * F.ny;
@@ -906,6 +920,7 @@ __device__ __forceinline__ void mg_tail(const MgTail<T>& tl, const TailDiv& dv) 
             }
             Cc.f[t] = (wa * rows[0] + wb * rows[1]) + (wb * rows[2] + wa * rows[3]);
             Cc.u[t] = T(0);
+            Cc.alt[t] = tail_first_sweep(Cc, t);  // the level's first Jacobi sweep from zero
         }
         __syncthreads();
     }
@@ -914,7 +929,7 @@ __device__ __forceinline__ void mg_tail(const MgTail<T>& tl, const TailDiv& dv) 
         // four colours need an even width: on an odd periodic row the first and last
         // nodes share a colour and neighbour each other
         if (S.ny <= 4 || (S.nx & 1))
-            tail_jacobi(S, 2 * tl.coarse_sweeps);
+            tail_jacobi(S, 2 * tl.coarse_sweeps, tl.coarse_sweeps > 0);
         else
             tail_sor(S, tl.coarse_sweeps, tl.omega);
     }
