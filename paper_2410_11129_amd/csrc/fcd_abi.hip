@@ -92,9 +92,11 @@ struct MgPlan {
     int nx[MAX_LEVELS], ny[MAX_LEVELS], pitch[MAX_LEVELS];
     double kappa_top[MAX_LEVELS];  // upper ghost rule of each level (fcd_potential.hip)
     size_t off_mu[MAX_LEVELS], off_u[MAX_LEVELS], off_f[MAX_LEVELS], off_t[MAX_LEVELS];
-    size_t off_prev;  // psi' history planes: psi'(t-1) ...
-    size_t off_prev2; // ... psi'(t-2) (quadratic extrapolation) ...
-    size_t off_prev3; // ... and psi'(t-3) (cubic extrapolation)
+    // psi' history: a ring of three planes holding psi'(t-1), psi'(t-2) (quadratic
+    // extrapolation) and psi'(t-3) (cubic), the newest at fcd_handle::ring
+    size_t off_prev;
+    size_t off_prev2;
+    size_t off_prev3;
     size_t bytes;     // total scratch
 };
 
@@ -301,6 +303,7 @@ struct fcd_handle {
     unsigned long long test_idx;   // index of the next such residual test (slot test_idx % 3)
     fcd::ResGate gate;             // set while launching gated kernels: levels built carry it
     int pipe_last;                 // V-cycles the previous such solve needed
+    int ring;  // the psi' history plane (0..2 of off_prev, off_prev2, off_prev3) holding psi'(t-1)
     int init_fresh;  // the state is the compound-droplet initial state (no step since)
     int open_x;      // open channel: Eq. 37 inlet at x = 0, convective outlet at x = nx - 1
     double u_in;     // u_avg of Eq. 37 (centreline value of the inlet profile)
@@ -456,6 +459,14 @@ fcd_status read_divergence(fcd_handle* h) {
 fcd_status clear_divergence(fcd_handle* h) {
     hipLaunchKernelGGL(fcd::k_fill<unsigned long long>, dim3(1), dim3(64), 0, h->stream, div_word(h), 1LL, 0ULL);
     return hip_check(hipGetLastError(), "divergence flag clear");
+}
+
+// The psi' history plane holding psi'(t-k), k = 1, 2, 3 (a ring of three planes).
+template <typename T>
+T* psi_prev(fcd_handle* h, int k = 1) {
+    const int q = (h->ring + k - 1) % 3;
+    const size_t off = q == 0 ? h->plan.off_prev : q == 1 ? h->plan.off_prev2 : h->plan.off_prev3;
+    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + off);
 }
 
 // Level 0 (the lattice's psi' and mu_r planes).
@@ -1034,9 +1045,6 @@ template <typename T>
 fcd_status step_impl(fcd_handle* h, int nsteps) {
     const fcd::StepConst<T> P = make_const<T>(h);
     T* phi = static_cast<T*>(h->buf.phi);
-    T* prev = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev);
-    T* prev2 = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev2);
-    T* prev3 = reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + h->plan.off_prev3);
     for (int n = 0; n < nsteps; ++n) {
         const T* src = static_cast<const T*>(h->buf.dist[h->cur]);
         T* dst = static_cast<T*>(h->buf.dist[1 - h->cur]);
@@ -1056,8 +1064,10 @@ fcd_status step_impl(fcd_handle* h, int nsteps) {
                 // the order pot_extrapolate asks for)
                 const int ex = h->prm.pot_extrapolate;
                 const int mode = h->hist >= 4 && ex == 3 ? 3 : h->hist >= 3 && ex >= 2 ? 2 : h->hist >= 2 ? 1 : 0;
-                fcd::launch_psi_history<T>(static_cast<T*>(h->buf.psi), prev, prev2, prev3, h->lat.nx, h->lat.ny,
-                                           h->lat.pitch, mode, h->stream);
+                T* const p3 = psi_prev<T>(h, 3);
+                fcd::launch_psi_history_ring<T>(static_cast<T*>(h->buf.psi), psi_prev<T>(h, 1), psi_prev<T>(h, 2), p3,
+                                                h->lat.nx, h->lat.ny, h->lat.pitch, mode, h->stream);
+                h->ring = (h->ring + 2) % 3;  // psi'(t-3)'s plane now holds the newest solution
             }
             if (h->prm.H0 != 0.0 && solves_on_device(h)) {
                 bool collided = false;
@@ -2249,13 +2259,8 @@ fcd_status dcopy(void* dst, const void* src, size_t bytes, hipStream_t s) {
 }
 
 // Checkpoint records hold everything a step reads: the state, psi' (the solver's warm
-// start) and the psi' history plane; the history count and the previous solve's
-// iteration count are kept on the host beside them.
-template <typename T>
-T* psi_prev(fcd_handle* h, int k = 1) {
-    const size_t off = k == 1 ? h->plan.off_prev : k == 2 ? h->plan.off_prev2 : h->plan.off_prev3;
-    return reinterpret_cast<T*>(static_cast<char*>(h->buf.scratch) + off);
-}
+// start) and the psi' history planes (in the order psi'(t-1), psi'(t-2), psi'(t-3)); the
+// history count and the previous solve's iteration count are kept on the host beside them.
 
 template <typename T>
 fcd_status save_record(fcd_handle* h, char* rec, const AdjLayout& L) {
@@ -2795,6 +2800,7 @@ fcd_status fcd_create(const fcd_lattice* lat, const fcd_params* prm, const fcd_b
     h->test_idx = 0;
     h->gate = fcd::ResGate{};
     h->pipe_last = 1;
+    h->ring = 0;
     // the scratch arrives with the caller's contents: zero both residual slots, the flag,
     // the SOR words and the device-decided solve's words
     h->res_slot = 0;

@@ -57,6 +57,10 @@ template <typename T>
 void launch_mg_tail(const MgTail<T>& tl, hipStream_t s);
 template <typename T>
 void launch_psi_history(T* psi, T* prev, T* prev2, T* prev3, int nx, int ny, int pitch, int mode, hipStream_t s);
+// The same with the recorded solutions in a ring: p1..p3 = psi'(t-1..t-3); psi' replaces p3.
+template <typename T>
+void launch_psi_history_ring(T* psi, const T* p1, const T* p2, T* p3, int nx, int ny, int pitch, int mode,
+                             hipStream_t s);
 // Publication of a solve decided on the device that no collide-and-stream ends
 // (fcd_potential.hip): one lane, as the collide-and-stream's first.
 void launch_solve_publish(const StepGate& sg, hipStream_t s);

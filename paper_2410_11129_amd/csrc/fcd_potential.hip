@@ -987,6 +987,24 @@ __global__ void __launch_bounds__(PX* PY) k_psi_history(T* __restrict__ psi, T* 
     prev[k] = cur;
 }
 
+// The same warm start with the recorded solutions in a ring of planes: p1, p2, p3 hold
+// psi'(t-1), psi'(t-2), psi'(t-3) (as far as mode reads them); the current psi' replaces
+// p3, which becomes the ring's newest plane (the caller rotates the ring).  Two writes per
+// node instead of the shift's four.
+template <typename T>
+__global__ void __launch_bounds__(PX* PY) k_psi_history_ring(T* __restrict__ psi, const T* __restrict__ p1,
+                                                             const T* __restrict__ p2, T* __restrict__ p3, int nx,
+                                                             int ny, int pitch, int mode) {
+    const int i = blockIdx.x * PX + threadIdx.x, j = blockIdx.y * PY + threadIdx.y;
+    if (i >= nx || j >= ny) return;
+    const long long k = (long long)j * pitch + i;
+    const T cur = psi[k];
+    if (mode == 1) psi[k] = T(2) * cur - p1[k];
+    if (mode == 2) psi[k] = T(3) * (cur - p1[k]) + p2[k];
+    if (mode == 3) psi[k] = T(4) * (cur + p2[k]) - T(6) * p1[k] - p3[k];
+    p3[k] = cur;
+}
+
 // ---------------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------------
@@ -1102,6 +1120,13 @@ void launch_mg_tail(const MgTail<T>& tl, hipStream_t s) {
 
 void launch_solve_publish(const StepGate& sg, hipStream_t s) {
     hipLaunchKernelGGL(k_solve_publish, dim3(1), dim3(64), 0, s, sg);
+}
+
+template <typename T>
+void launch_psi_history_ring(T* psi, const T* p1, const T* p2, T* p3, int nx, int ny, int pitch, int mode,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_psi_history_ring<T>, pgrid(nx, ny), dim3(PX, PY), 0, s, psi, p1, p2, p3, nx, ny, pitch,
+                       mode);
 }
 
 template <typename T>
@@ -1387,7 +1412,8 @@ void launch_bmg_decide(const MgChan<T, TC>* ch, int n, unsigned long long* res, 
     template void launch_pot_residual<T>(const PotLevel<T>&, unsigned long long*, hipStream_t);           \
     template size_t mg_tail_lds_bytes<T>(const MgTail<T>&);                                                \
     template void launch_mg_tail<T>(const MgTail<T>&, hipStream_t);                                        \
-    template void launch_psi_history<T>(T*, T*, T*, T*, int, int, int, int, hipStream_t);
+    template void launch_psi_history<T>(T*, T*, T*, T*, int, int, int, int, hipStream_t);                  \
+    template void launch_psi_history_ring<T>(T*, const T*, const T*, T*, int, int, int, int, hipStream_t);
 
 // Multigrid transfer and smoothing kernels between a level of type T and coarse levels of
 // type TC (the coarse levels are FP32 under an FP64 finest level).
