@@ -37,7 +37,9 @@ constexpr int PX = 64;  // one wavefront per row segment
 constexpr int PY = 4;
 
 // A kernel launched with a gated level does nothing when the gating residual test has
-// passed (every block reads the test's words first, before any barrier).
+// passed.  Every block reads the test's words after issuing its own loads and before any
+// barrier, so that the two memory latencies overlap (a gated-off block discards what it
+// loaded; every load stays in bounds either way).
 template <typename T>
 __device__ __forceinline__ bool gated_off(const PotLevel<T>& L) {
     return L.gate.res && L.gate.passed();
@@ -317,11 +319,9 @@ __device__ __forceinline__ T prolong_tile(const T (*sc)[CX], int i0, int j0, int
 template <typename T, typename G, bool PROLONG, int MODE, typename TC>
 __device__ __forceinline__ void mg_smooth_tile(const PotLevel<T>& L, const T* __restrict__ uin, T* __restrict__ uout,
                                                const PotLevel<TC>& Cl, unsigned long long* __restrict__ res,
-                                               unsigned long long* __restrict__ res_clear, int inner, int bx, int by) {
+                                               unsigned long long* __restrict__ res_clear, int inner, int bx, int by,
+                                               unsigned* __restrict__ count = nullptr) {
     constexpr int SX = G::SX, SY = G::SY, HX = G::HX, HY = G::HY, NT = G::NT, CX = G::CX, CY = G::CY;
-    // the next test's (other) residual slot, zeroed for it: the kernel boundary orders this
-    // store before that test's atomics, and the host has read that slot before this launch
-    if (res_clear && bx == 0 && by == 0 && threadIdx.x < 2) res_clear[threadIdx.x] = 0ULL;
     __shared__ T su[HY][HX];
     __shared__ T sm[HY][HX];
     __shared__ T sf[MODE == 1 ? 1 : SY][SX];
@@ -350,6 +350,17 @@ __device__ __forceinline__ void mg_smooth_tile(const PotLevel<T>& L, const T* __
                 cv[r] = T(Cl.u[(long long)J * Cl.pitch + I]);
             }
         }
+    }
+    if (gated_off(L)) {
+        // a residual test that does not run leaves its slot zero, which reads as a pass
+        if (res && bx == 0 && by == 0 && tid < 2) res[tid] = 0ULL;
+        return;
+    }
+    if (count && bx == 0 && by == 0 && tid == 0) atomicAdd(count, 1u);
+    // the next test's (other) residual slot, zeroed for it: the kernel boundary orders this
+    // store before that test's atomics, and the host has read that slot before this launch
+    if (res_clear && bx == 0 && by == 0 && tid < 2) res_clear[tid] = 0ULL;
+    if (PROLONG) {
 #pragma unroll
         for (int r = 0; r < G::CPER; ++r) {
             const int q = tid + r * NT;
@@ -436,13 +447,7 @@ __global__ void __launch_bounds__(G::NT) k_mg_smooth_tile(PotLevel<T> L, const T
                                                           unsigned long long* __restrict__ res,
                                                           unsigned long long* __restrict__ res_clear, int inner,
                                                           unsigned* __restrict__ count) {
-    if (gated_off(L)) {
-        // a residual test that does not run leaves its slot zero, which reads as a pass
-        if (res && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) res[threadIdx.x] = 0ULL;
-        return;
-    }
-    if (count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) atomicAdd(count, 1u);
-    mg_smooth_tile<T, G, PROLONG, MODE, TC>(L, uin, uout, Cl, res, res_clear, inner, blockIdx.x, blockIdx.y);
+    mg_smooth_tile<T, G, PROLONG, MODE, TC>(L, uin, uout, Cl, res, res_clear, inner, blockIdx.x, blockIdx.y, count);
 }
 
 // Residual restriction.  The coarse right-hand side at coarse node (I, J) is the
@@ -547,6 +552,7 @@ __device__ __forceinline__ void mg_restrict_tile(const PotLevel<T>& F, const Pot
     const int tid = threadIdx.x;
     T uv[R::FPER], mv[R::FPER], fv[R::RPER];
     restrict_loads<T, G, MODE>(F, i0, j0, uv, mv, fv);
+    if (gated_off(Cl)) return;
 #pragma unroll
     for (int r = 0; r < R::FPER; ++r) {
         const int q = tid + r * NT;
@@ -569,7 +575,6 @@ __device__ __forceinline__ void mg_restrict_tile(const PotLevel<T>& F, const Pot
 
 template <typename T, typename G, int MODE, typename TC>
 __global__ void __launch_bounds__(G::NT) k_mg_restrict_tile(PotLevel<T> F, PotLevel<TC> Cl) {
-    if (gated_off(Cl)) return;
     mg_restrict_tile<T, G, MODE, TC>(F, Cl, blockIdx.x, blockIdx.y);
 }
 
@@ -613,6 +618,7 @@ __device__ __forceinline__ void mg_restrict_smooth(const PotLevel<T>& F, const P
             cm[r] = C.mu[(long long)clamp_row(J0 + ly - 1, C.ny) * C.pitch + wrap_col(I0 + lx - 1, C.nx)];
         }
     }
+    if (gated_off(C)) return;
 #pragma unroll
     for (int r = 0; r < R::FPER; ++r) {
         const int q = tid + r * NT;
@@ -661,7 +667,6 @@ __device__ __forceinline__ void mg_restrict_smooth(const PotLevel<T>& F, const P
 template <typename T, int FMODE, typename TC>
 __global__ void __launch_bounds__(FineTile::NT) k_mg_restrict_smooth(PotLevel<T> F, PotLevel<TC> C,
                                                                      TC* __restrict__ uout, int inner) {
-    if (gated_off(C)) return;
     mg_restrict_smooth<T, FMODE, TC>(F, C, uout, inner, blockIdx.x, blockIdx.y);
 }
 
@@ -856,6 +861,7 @@ __device__ __forceinline__ void mg_tail(const MgTail<T>& tl, const TailDiv& dv) 
             }
         }
     }
+    if (gated_off(tl.lv[0])) return;
     {
         const TailLevel<T> S = tail_view(tl, dv, base, 0);
         const int n = S.nx * S.ny;
@@ -956,7 +962,6 @@ __device__ __forceinline__ void mg_tail(const MgTail<T>& tl, const TailDiv& dv) 
 
 template <typename T>
 __global__ void __launch_bounds__(TAIL_T) k_mg_tail(MgTail<T> tl, TailDiv dv) {
-    if (gated_off(tl.lv[0])) return;
     mg_tail<T>(tl, dv);
 }
 
