@@ -131,7 +131,9 @@ __device__ __forceinline__ void mg_restrict_mu4_tile(const T* __restrict__ muf, 
     {  // first level from the finer plane's type
         constexpr int cx = MU_TX / 2;
         const int y = tid / cx, x = tid - y * cx;  // NT = cx * (MU_TY / 2)
-        const TC m = TC(T(4) / ((T(1) / s0[2 * y][2 * x] + T(1) / s0[2 * y][2 * x + 1]) + (T(1) / s0[2 * y + 1][2 * x] + T(1) / s0[2 * y + 1][2 * x + 1])));
+        const T* r0 = s0[2 * y];
+        const T* r1 = s0[2 * y + 1];
+        const TC m = TC(T(4) / ((T(1) / r0[2 * x] + T(1) / r0[2 * x + 1]) + (T(1) / r1[2 * x] + T(1) / r1[2 * x + 1])));
         sa[y][x] = m;
         const int I = (i0 >> 1) + x, J = (j0 >> 1) + y;
         if (I < C.nx[0] && J < C.ny[0]) C.mu[0][(long long)J * C.pitch[0] + I] = m;
@@ -309,6 +311,7 @@ __device__ __forceinline__ T coarse_gs(const T (*su)[HX], const Cpl<T>& c, int l
     return (acc + cself * old - f) / (c.C + cself);
 }
 
+// HF: the coarse levels' harmonic face means (as coarse_cpl) in place of mu + mu'.
 template <typename T, int HX, bool HF = false>
 __device__ __forceinline__ MgEval<T> tile_eval(const T (*su)[HX], const T (*sm)[HX], int lx, int ly, bool bot,
                                                bool top, const PotLevel<T>& L, T fval, bool rhs_from_field) {
@@ -478,7 +481,8 @@ __device__ __forceinline__ void mg_smooth_tile(const PotLevel<T>& L, const T* __
         if (q < G::HN) {
             const int ly = q / HX, lx = q - ly * HX;
             T u = uv[r];
-            if (PROLONG) u += prolong_tile<T, CX, MODE == 0>(sc, scm, i0, j0, lx, ly, Cl.ny, T(Cl.kappa), T(Cl.kappa_top));
+            if (PROLONG)
+                u += prolong_tile<T, CX, MODE == 0>(sc, scm, i0, j0, lx, ly, Cl.ny, T(Cl.kappa), T(Cl.kappa_top));
             su[ly][lx] = u;
             sm[ly][lx] = mv[r];
         }
@@ -629,7 +633,8 @@ __device__ __forceinline__ void restrict_residuals(const PotLevel<T>& F, int i0,
             T v = T(0);
             if (j >= 0 && j < F.ny) {
                 const MgEval<T> e =
-                    tile_eval<T, R::FX, MODE == 0>(fu, fm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F, fv[r], MODE == 1);
+                    tile_eval<T, R::FX, MODE == 0>(fu, fm, lx + 1, ly + 1, j == 0, j == F.ny - 1, F, fv[r],
+                                                   MODE == 1);
                 v = e.rhs - (e.acc - e.C * fu[ly + 1][lx + 1]);
             }
             sr[ly][lx] = v;
@@ -857,7 +862,8 @@ __device__ __forceinline__ void tail_setup_node(const TailLevel<T>& S, const Pot
     const T a = G.inv_h2 * (T(1) / T(3)), q = G.inv_h2 * (T(1) / T(12)), k = G.kappa, kt = G.kappa_top;
     auto fc = [](T x, T y) { return T(4) * x * y * face_rcp(x + y); };
     T ce = a * fc(mc, m[e]), cw = a * fc(mc, m[w]), cn = a * fc(mc, m[t + dn]), cs = a * fc(mc, m[t + ds]);
-    T cne = q * fc(mc, m[e + dn]), cnw = q * fc(mc, m[w + dn]), csw = q * fc(mc, m[w + ds]), cse = q * fc(mc, m[e + ds]);
+    T cne = q * fc(mc, m[e + dn]), cnw = q * fc(mc, m[w + dn]);
+    T csw = q * fc(mc, m[w + ds]), cse = q * fc(mc, m[e + ds]);
     const T C = ((ce + cw) + (cn + cs)) + ((cne + csw) + (cnw + cse));
     T d = C;
     if (j == 0) {  // ghost row below: -k times row 0
